@@ -1,0 +1,330 @@
+"""Plain CPU FP64 oracle of the CWTHF single-scale hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this module: only the tests, the smoke check and the CPU-baseline leg
+of the benchmark use it.  It shares no code with the GPU library.
+
+It follows the paper's identification steps 1-6 (Sec. 2, enumerated list) for
+one scale:
+
+  step 1  k_w = w L / 1000                          -> ``scale_w``
+  step 2  CIC assignment, Eq. (1)                   -> ``deposit``
+  step 3  grid CWT, Eqs. (2)-(4)                    -> ``cwt``
+  step 4  local maxima of the grid CWT              -> ``maxima``
+  step 5  segmentation by the maxima (Sec. 2.3)     -> ``segment``
+  step 6  particles take their cell's label         -> ``label``
+
+Readings taken where the paper is silent are listed in the design notes and
+repeated at each function.  Everything here is deliberately unblocked and
+unfused; numpy's FFT is used as a library primitive for the periodic
+convolution, in FP64.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "scale_w", "fixed_point", "deposit", "total_mass", "mean_mass", "normalise",
+    "wavelet", "wavelet_hat", "sampled_kernel", "kernel_hat", "cwt_field", "cwt",
+    "neighbour_offsets", "maxima", "parents", "segment", "ngp_nodes", "label",
+    "find_halos", "DepositOverflow",
+]
+
+
+class DepositOverflow(ArithmeticError):
+    """A CIC cell sum does not fit a signed 64-bit integer."""
+
+
+# --------------------------------------------------------------------------
+# step 1: scale parameter
+# --------------------------------------------------------------------------
+def scale_w(kw: float, box_len: float) -> float:
+    """w (h/Mpc) from the dimensionless k_w = w L_box / 1000 (Sec. 2, step 1 footnote)."""
+    return 1000.0 * kw / box_len
+
+
+# --------------------------------------------------------------------------
+# step 2: cloud-in-cell deposit, Eq. (1)
+# --------------------------------------------------------------------------
+def fixed_point(pos: np.ndarray, box_len: float, n: int, frac_bits: int) -> np.ndarray:
+    """Per-axis fixed-point coordinate q in [0, n 2^B), in units of 2^-B cell.
+
+    Reading: the node g sits at g dx and the particle's CIC weights are taken
+    from its position in cell units with B fraction bits.  The scale factor
+    s = n 2^B / L is rounded once to the position dtype and t = x s is one
+    correctly rounded multiply in that dtype; q = floor(t) mod n 2^B, so
+    positions outside [0, L) wrap periodically.
+    """
+    pos = np.asarray(pos)
+    if pos.dtype not in (np.float32, np.float64):
+        raise TypeError("positions must be float32 or float64")
+    if pos.ndim != 2 or pos.shape[1] != 3:
+        raise ValueError("positions must have shape [np, 3]")
+    ft = pos.dtype.type
+    s = ft(float(n) * float(1 << frac_bits) / float(box_len))
+    t = pos * s  # elementwise, in the position dtype
+    if not np.all(np.isfinite(t)) or np.any(np.abs(t) >= 2.0 ** 62):
+        raise ValueError("non-finite or out-of-range particle position")
+    m = n << frac_bits
+    return np.mod(np.floor(t).astype(np.int64), m)
+
+
+def deposit(pos: np.ndarray, box_len: float, n: int, frac_bits: int = 15) -> np.ndarray:
+    """CIC mass on the periodic n^3 grid, int64 in units of 2^-3B particle.
+
+    Eq. (1): each particle becomes (at most) eight pseudo-particles on the grid
+    nodes around it, with the usual tri-linear cloud-in-cell weights.  A node's
+    weight along one axis is 2^B - f for the lower node and f for the upper,
+    f being the fractional part of q; the eight products are summed exactly.
+    Grid layout is [z][y][x].
+    """
+    if not 8 <= frac_bits <= 20:
+        raise ValueError("frac_bits must be in [8, 20]")
+    q = fixed_point(pos, box_len, n, frac_bits)
+    one = 1 << frac_bits
+    cell = q >> frac_bits
+    f = q & (one - 1)
+    w = (one - f, f)  # lower / upper node weight per axis
+    # Exact sums: split each product (< 2^61) into 32-bit halves so that no
+    # partial sum wraps, then recombine with Python integers for the check.
+    lo = np.zeros(n ** 3, dtype=np.int64)
+    hi = np.zeros(n ** 3, dtype=np.int64)
+    for cz in (0, 1):
+        for cy in (0, 1):
+            for cx in (0, 1):
+                iz = (cell[:, 2] + cz) % n
+                iy = (cell[:, 1] + cy) % n
+                ix = (cell[:, 0] + cx) % n
+                idx = (iz * n + iy) * n + ix
+                wt = w[cz][:, 2] * w[cy][:, 1] * w[cx][:, 0]
+                np.add.at(lo, idx, wt & 0xFFFFFFFF)
+                np.add.at(hi, idx, wt >> 32)
+    # true cell value = hi * 2^32 + lo; it must be <= 2^63 - 1
+    if np.any(hi + (lo >> 32) >= (1 << 31)):
+        raise DepositOverflow("a CIC cell exceeds 2^63 - 1")
+    rho = (hi << 32) + lo
+    return rho.reshape(n, n, n)
+
+
+def total_mass(rho: np.ndarray) -> int:
+    """Exact integer sum of a non-negative int64 grid (may exceed 2^63)."""
+    r = np.asarray(rho, dtype=np.int64).ravel()
+    if np.any(r < 0):
+        raise ValueError("negative cell mass")
+    lo = int(np.sum(r & 0xFFFFFFFF, dtype=np.uint64))
+    hi = int(np.sum(r >> 32, dtype=np.uint64))
+    return (hi << 32) + lo
+
+
+def mean_mass(rho: np.ndarray) -> float:
+    """Mean cell mass: exact integer total rounded once to FP64, then / n^3."""
+    return float(total_mass(rho)) / float(rho.size)
+
+
+def normalise(rho: np.ndarray) -> np.ndarray:
+    """f = rho / mean, so densities are in units of the mean density (step 7 unit)."""
+    mbar = mean_mass(rho)
+    if mbar == 0.0:
+        raise ValueError("empty grid: the mean density is zero")
+    return rho.astype(np.float64) / mbar
+
+
+# --------------------------------------------------------------------------
+# step 3: the grid CWT, Eqs. (2)-(4)
+# --------------------------------------------------------------------------
+def wavelet(w: float, r2) -> np.ndarray:
+    """Isotropic Mexican-hat wavelet of Eq. (4) as a function of r^2."""
+    u = (w * w) * np.asarray(r2, dtype=np.float64)
+    return w ** 1.5 * (6.0 - u) * np.exp(-u / 4.0)
+
+
+def wavelet_hat(w: float, k) -> np.ndarray:
+    """Continuum Fourier transform of Eq. (4): 32 pi^1.5 w^-1.5 (k/w)^2 exp(-(k/w)^2).
+
+    Derived from Eq. (4) with F(k) = int Psi(x) exp(-i k.x) d^3x.  It vanishes
+    at k = 0 (zero-mean wavelet) and peaks at k = w.
+    """
+    s = (np.asarray(k, dtype=np.float64) / w) ** 2
+    return 32.0 * math.pi ** 1.5 * w ** -1.5 * s * np.exp(-s)
+
+
+def _image_count(w: float, box_len: float) -> int:
+    # Images beyond |m| = I lie at distance >= (I + 1/2) L from every node;
+    # choose I so that w (I + 1/2) L >= 16, where |Psi| / Psi(0) < 1e-25.
+    return max(1, int(math.ceil(16.0 / (w * box_len) - 0.5)))
+
+
+def sampled_kernel(n: int, box_len: float, w: float) -> np.ndarray:
+    """dx^3 * sum over periodic images of Psi(w, x_j + m L), sampled on the grid.
+
+    This is the paper's discretised convolution (Eq. (2) last line, Sec. 2.1):
+    the wavelet sampled on the CIC grid spacing, here periodic and untruncated.
+    Offsets are minimum-image node offsets.
+    """
+    dx = box_len / n
+    j = np.arange(n)
+    off = ((j + n // 2) % n - n // 2) * dx
+    images = _image_count(w, box_len)
+    k = np.zeros((n, n, n), dtype=np.float64)
+    for mz in range(-images, images + 1):
+        z = (off + mz * box_len)[:, None, None]
+        for my in range(-images, images + 1):
+            y = (off + my * box_len)[None, :, None]
+            for mx in range(-images, images + 1):
+                x = (off + mx * box_len)[None, None, :]
+                k += wavelet(w, x * x + y * y + z * z)
+    return k * dx ** 3
+
+
+def kernel_hat(n: int, box_len: float, w: float, mode: str = "sampled") -> np.ndarray:
+    """DFT-domain multiplier on the rfftn half-spectrum [n][n][n/2+1].
+
+    ``sampled``: rfftn of the sampled kernel (real, since the kernel is even).
+    ``analytic``: the continuum transform at the DFT wavenumbers 2 pi m / L.
+    """
+    if mode == "sampled":
+        return np.fft.rfftn(sampled_kernel(n, box_len, w), axes=(0, 1, 2)).real
+    if mode == "analytic":
+        kf = 2.0 * math.pi * np.fft.fftfreq(n, d=box_len / n)
+        kh = 2.0 * math.pi * np.fft.rfftfreq(n, d=box_len / n)
+        k2 = kf[:, None, None] ** 2 + kf[None, :, None] ** 2 + kh[None, None, :] ** 2
+        return wavelet_hat(w, np.sqrt(k2))
+    raise ValueError("mode must be 'sampled' or 'analytic'")
+
+
+def cwt_field(f: np.ndarray, box_len: float, w: float, mode: str = "sampled") -> np.ndarray:
+    """C_j = sum_g f_g K(x_j - x_g): the periodic discrete convolution of Eq. (2)."""
+    f = np.asarray(f, dtype=np.float64)
+    n = f.shape[0]
+    spec = np.fft.rfftn(f, axes=(0, 1, 2))
+    spec *= kernel_hat(n, box_len, w, mode)
+    return np.fft.irfftn(spec, s=f.shape, axes=(0, 1, 2))
+
+
+def cwt(rho: np.ndarray, box_len: float, kw: float, mode: str = "sampled") -> np.ndarray:
+    """Step 3 on a CIC grid: normalise to the mean density, then Eq. (2)."""
+    return cwt_field(normalise(rho), box_len, scale_w(kw, box_len), mode)
+
+
+# --------------------------------------------------------------------------
+# step 4: local maxima
+# --------------------------------------------------------------------------
+def neighbour_offsets():
+    """The 26 (dz, dy, dx) offsets of the 3x3x3 neighbourhood without the centre."""
+    return [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+            if (dz, dy, dx) != (0, 0, 0)]
+
+
+def _check_field(c: np.ndarray) -> np.ndarray:
+    c = np.asarray(c)
+    if c.ndim != 3 or not (c.shape[0] == c.shape[1] == c.shape[2]):
+        raise ValueError("field must be n^3")
+    if np.any(np.isnan(c)):
+        raise ValueError("NaN in the CWT field")
+    return c
+
+
+def _beats(c_a, i_a, c_b, i_b):
+    """Strict total order on (value, linear index): a beats b.
+
+    Equal values (with -0 equal to +0) are broken by the larger linear index.
+    """
+    return (c_a > c_b) | ((c_a == c_b) & (i_a > i_b))
+
+
+def maxima(c: np.ndarray, tau: float = 0.0) -> np.ndarray:
+    """Sorted linear indices of cells that beat all 26 periodic neighbours and exceed tau.
+
+    Step 4 and Sec. 2.3: a halo is a positive CWT peak; tau = 0 by default.
+    Comparisons are made in the dtype of ``c``.
+    """
+    c = _check_field(c)
+    n = c.shape[0]
+    idx = np.arange(n ** 3, dtype=np.int64).reshape(n, n, n)
+    is_max = c > c.dtype.type(tau)
+    for (dz, dy, dx) in neighbour_offsets():
+        nb_c = np.roll(c, (-dz, -dy, -dx), axis=(0, 1, 2))
+        nb_i = np.roll(idx, (-dz, -dy, -dx), axis=(0, 1, 2))
+        is_max &= _beats(c, idx, nb_c, nb_i)
+    return np.flatnonzero(is_max.ravel()).astype(np.int64)
+
+
+# --------------------------------------------------------------------------
+# step 5: segmentation
+# --------------------------------------------------------------------------
+def parents(c: np.ndarray) -> np.ndarray:
+    """parent(j) = the cell of {j} + N26(j) that is largest in the (value, index) order."""
+    c = _check_field(c)
+    n = c.shape[0]
+    idx = np.arange(n ** 3, dtype=np.int64).reshape(n, n, n)
+    best_c = c.copy()
+    best_i = idx.copy()
+    for (dz, dy, dx) in neighbour_offsets():
+        nb_c = np.roll(c, (-dz, -dy, -dx), axis=(0, 1, 2))
+        nb_i = np.roll(idx, (-dz, -dy, -dx), axis=(0, 1, 2))
+        take = _beats(nb_c, nb_i, best_c, best_i)
+        best_c = np.where(take, nb_c, best_c)
+        best_i = np.where(take, nb_i, best_i)
+    return best_i.ravel()
+
+
+def segment(c: np.ndarray, tau: float = 0.0) -> np.ndarray:
+    """Cell labels: the root reached by steepest ascent, or -1.
+
+    Sec. 2.3 extends each halo from its positive peak out to the CWT valley
+    with no threshold.  Reading: every cell climbs to its largest neighbour
+    until it reaches a local maximum (its root); the basins meet at the
+    valleys.  Cells whose root is not above tau get -1.
+    """
+    c = _check_field(c)
+    par = parents(c)
+    root = par.copy()
+    active = np.flatnonzero(par[root] != root)
+    while active.size:  # follow the parent chain one step at a time
+        root[active] = par[root[active]]
+        active = active[par[root[active]] != root[active]]
+    flat = c.ravel()
+    return np.where(flat[root] > flat.dtype.type(tau), root, -1).astype(np.int64).reshape(c.shape)
+
+
+# --------------------------------------------------------------------------
+# step 6: particle labels
+# --------------------------------------------------------------------------
+def ngp_nodes(pos: np.ndarray, box_len: float, n: int, frac_bits: int = 15) -> np.ndarray:
+    """Linear index of each particle's nearest node (the largest CIC weight).
+
+    Reading: a particle belongs to the node carrying its largest CIC weight;
+    at exactly half a cell it goes to the upper node.
+    """
+    q = fixed_point(pos, box_len, n, frac_bits)
+    node = ((q + (1 << (frac_bits - 1))) >> frac_bits) % n
+    return (node[:, 2] * n + node[:, 1]) * n + node[:, 0]
+
+
+def label(pos: np.ndarray, box_len: float, n: int, cell_label: np.ndarray,
+          frac_bits: int = 15) -> np.ndarray:
+    """Step 6: a particle gets the label (temporary ID) of its segmented cell."""
+    return np.asarray(cell_label).ravel()[ngp_nodes(pos, box_len, n, frac_bits)]
+
+
+# --------------------------------------------------------------------------
+# the whole single-scale path
+# --------------------------------------------------------------------------
+def find_halos(pos, box_len: float, n: int, kw: float, frac_bits: int = 15,
+               tau: float = 0.0, mode: str = "sampled", decide_dtype=np.float64) -> dict:
+    """Steps 2-6 at one scale.  ``decide_dtype`` is the precision the maxima and
+    segmentation comparisons are made in (float64, or float32 to decide as an
+    FP32 pipeline would on the rounded field)."""
+    rho = deposit(pos, box_len, n, frac_bits)
+    c = cwt(rho, box_len, kw, mode)
+    cd = c.astype(decide_dtype)
+    cell = segment(cd, tau)
+    return {
+        "rho": rho,
+        "cwt": c,
+        "maxima": maxima(cd, tau),
+        "cell_label": cell,
+        "particle_label": label(pos, box_len, n, cell, frac_bits),
+    }

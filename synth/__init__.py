@@ -1,0 +1,186 @@
+"""Seeded synthetic inputs for the CWT halo-finder hot path.
+
+This module only draws random particle boxes and job streams.  It holds none of
+the halo finder's arithmetic (no deposit, transform, maxima or segmentation), so
+both the FP64 oracle and the GPU path can take their inputs from it.
+
+Recipe (a stand-in for the paper's SIMBA m50n512 dark-matter snapshot,
+Sec. 3, which is not available):
+
+* ``halo_frac`` (60%) of the particles sit in NFW spheres.  Halo masses follow
+  dN/dM ~ M^-1.9 on [50, 5000] particles (inverse CDF), then are scaled to the
+  60% budget with largest-remainder rounding so the counts are exact integers.
+* r_vir = (3 M / (4 pi 200 nbar))^(1/3) with nbar = N_p / L^3 (the r_200
+  radius the paper compares halo extents with, Sec. 2.3), concentration
+  c ~ U[4, 10], radii from the NFW enclosed-mass profile truncated at r_vir,
+  isotropic directions.
+* The remaining particles are uniform in the box.
+* Positions are wrapped into [0, L), cast to the configured dtype and put in a
+  seeded random order, so particle order carries no spatial locality.
+
+All draws go through one ``torch.Generator``; the stream is fixed by
+(seed, device).  CPU generation is used for everything the oracle checks at full
+size; very large boxes may be drawn on the GPU, whose stream differs from the
+CPU one for the same seed.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import torch
+
+HALO_FRAC = 0.6
+M_MIN, M_MAX, MASS_SLOPE = 50.0, 5000.0, -1.9
+C_LO, C_HI = 4.0, 10.0
+DELTA_VIR = 200.0
+
+
+@dataclass(frozen=True)
+class BoxConfig:
+    """One synthetic periodic box: side ``box_len`` (Mpc/h), grid ``n``^3."""
+
+    name: str
+    box_len: float
+    n: int
+    n_particles: int
+    n_halos: int
+    dtype: str  # "f32" or "f64"
+    seed: int
+    scales_cells: tuple = (2.0,)  # wavelet scale lengths 1/w, in grid cells
+
+    @property
+    def kw_list(self):
+        # k_w = w L / 1000 (Sec. 2, step 1); w = 1/(a dx) with dx = L/n.
+        return [self.n / (1000.0 * a) for a in self.scales_cells]
+
+
+CONFIGS = {
+    "M1": BoxConfig("M1", 100.0, 64, 64 ** 3, 200, "f64", 1, (2.0,)),
+    "M2": BoxConfig("M2", 250.0, 256, 256 ** 3, 20000, "f32", 2, (2.0,)),
+    "M3": BoxConfig("M3", 500.0, 512, 512 ** 3, 150000, "f32", 3, (1.0, 2.0, 4.0)),
+    "M4": BoxConfig("M4", 1000.0, 1024, 1024 ** 3, 1200000, "f32", 4, (2.0,)),
+}
+
+SERVE_SIZES = (64, 96, 128, 192, 256)
+
+
+def _torch_dtype(dtype: str):
+    return {"f32": torch.float32, "f64": torch.float64}[dtype]
+
+
+def halo_counts(gen: torch.Generator, n_halos: int, budget: int, device) -> torch.Tensor:
+    """Integer particle counts per halo: power-law draw scaled to ``budget``."""
+    if n_halos == 0 or budget == 0:
+        return torch.zeros(n_halos, dtype=torch.int64, device=device)
+    u = torch.rand(n_halos, generator=gen, dtype=torch.float64, device=device)
+    e = 1.0 + MASS_SLOPE
+    lo, hi = M_MIN ** e, M_MAX ** e
+    m = (lo + u * (hi - lo)) ** (1.0 / e)
+    raw = m * (budget / m.sum())
+    base = torch.floor(raw)
+    rem = int(budget - int(base.sum().item()))
+    frac = raw - base
+    order = torch.argsort(frac, descending=True, stable=True)
+    counts = base.to(torch.int64)
+    if rem > 0:
+        counts[order[:rem]] += 1
+    return counts
+
+
+def nfw_radius(gen: torch.Generator, conc: torch.Tensor) -> torch.Tensor:
+    """r / r_vir drawn from the NFW enclosed mass mu(x) = ln(1+x) - x/(1+x), x <= c."""
+    u = torch.rand(conc.shape, generator=gen, dtype=torch.float64, device=conc.device)
+    y = u * (torch.log1p(conc) - conc / (1.0 + conc))
+    lo = torch.zeros_like(conc)
+    hi = conc.clone()
+    for _ in range(56):  # bisection; mu is increasing in x
+        mid = 0.5 * (lo + hi)
+        below = (torch.log1p(mid) - mid / (1.0 + mid)) < y
+        lo = torch.where(below, mid, lo)
+        hi = torch.where(below, hi, mid)
+    return 0.5 * (lo + hi) / conc
+
+
+def make_box(box_len: float, n_particles: int, n_halos: int, dtype: str, seed: int,
+             device="cpu", halo_frac: float = HALO_FRAC) -> torch.Tensor:
+    """Particle positions ``[n_particles, 3]`` (x, y, z) in [0, box_len)."""
+    device = torch.device(device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    f64 = torch.float64
+    budget = int(round(halo_frac * n_particles)) if n_halos > 0 else 0
+    counts = halo_counts(gen, n_halos, budget, device)
+    n_in_halos = int(counts.sum().item()) if n_halos > 0 else 0
+    centres = torch.rand((n_halos, 3), generator=gen, dtype=f64, device=device) * box_len
+    conc = C_LO + (C_HI - C_LO) * torch.rand(n_halos, generator=gen, dtype=f64, device=device)
+    nbar = n_particles / box_len ** 3
+    r_vir = (3.0 * counts.to(f64) / (4.0 * math.pi * DELTA_VIR * nbar)) ** (1.0 / 3.0)
+
+    pos = torch.empty((n_particles, 3), dtype=f64, device=device)
+    if n_in_halos > 0:
+        owner = torch.repeat_interleave(torch.arange(n_halos, device=device), counts)
+        r = nfw_radius(gen, conc[owner]) * r_vir[owner]
+        d = torch.randn((n_in_halos, 3), generator=gen, dtype=f64, device=device)
+        d = d / torch.linalg.vector_norm(d, dim=1, keepdim=True).clamp_min(1e-300)
+        pos[:n_in_halos] = centres[owner] + r[:, None] * d
+        del owner, r, d
+    n_uniform = n_particles - n_in_halos
+    if n_uniform > 0:
+        pos[n_in_halos:] = torch.rand((n_uniform, 3), generator=gen, dtype=f64, device=device) * box_len
+    pos = torch.remainder(pos, box_len)
+    out = pos.to(_torch_dtype(dtype))
+    del pos
+    top = torch.tensor(box_len, dtype=out.dtype, device=device)
+    out = torch.where(out >= top, out - top, out)  # values rounded up to L wrap to 0
+    perm = torch.randperm(n_particles, generator=gen, device=device)
+    return out[perm].contiguous()
+
+
+def make_config_box(cfg: BoxConfig, device="cpu") -> torch.Tensor:
+    return make_box(cfg.box_len, cfg.n_particles, cfg.n_halos, cfg.dtype, cfg.seed, device)
+
+
+@dataclass(frozen=True)
+class JobSpec:
+    """One serving request: a periodic subvolume with its own grid and scale."""
+
+    job_id: int
+    n: int
+    box_len: float
+    n_particles: int
+    n_halos: int
+    kw: float
+    seed: int
+    dtype: str = "f32"
+
+    def positions(self, device="cpu") -> torch.Tensor:
+        return make_box(self.box_len, self.n_particles, self.n_halos, self.dtype, self.seed, device)
+
+
+def job_stream(n_jobs: int = 2000, seed: int = 5, sizes=SERVE_SIZES) -> list:
+    """Serving jobs: n uniform over ``sizes``, N_p = n^3 U[0.5,2], scale U[1,4] cells.
+
+    Each subvolume has dx = 1 Mpc/h (L = n) and the halo number density of the
+    1024^3 / 1000 Mpc/h box (1.2e-3 halos per (Mpc/h)^3).
+    """
+    gen = torch.Generator()
+    gen.manual_seed(int(seed))
+    jobs = []
+    for j in range(n_jobs):
+        n = sizes[int(torch.randint(len(sizes), (1,), generator=gen).item())]
+        frac = 0.5 + 1.5 * float(torch.rand(1, generator=gen, dtype=torch.float64).item())
+        a = 1.0 + 3.0 * float(torch.rand(1, generator=gen, dtype=torch.float64).item())
+        box_len = float(n)
+        jobs.append(JobSpec(j, n, box_len, int(round(n ** 3 * frac)),
+                            int(round(1.2e-3 * box_len ** 3)), n / (1000.0 * a),
+                            5_000_000 + j))
+    return jobs
+
+
+def poisson_arrivals(n_jobs: int, rate_per_s: float, seed: int = 5) -> list:
+    """Arrival times (s) of a Poisson process with the given rate."""
+    gen = torch.Generator()
+    gen.manual_seed(int(seed) + 1)
+    gaps = -torch.log1p(-torch.rand(n_jobs, generator=gen, dtype=torch.float64)) / rate_per_s
+    return torch.cumsum(gaps, 0).tolist()
