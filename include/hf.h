@@ -1,0 +1,145 @@
+/*
+ * hf.h - C ABI of the MI355X (gfx950) single-scale CWT halo-finding path.
+ *
+ * The path is the per-scale core of CWTHF (Li, Wang & He, arXiv:2501.10622),
+ * Sec. 2, identification steps 2-6:
+ *
+ *   hf_deposit  step 2  cloud-in-cell mass on a periodic n^3 grid, Eq. (1)
+ *   hf_cwt      step 3  grid CWT with the Mexican-hat wavelet, Eqs. (2)-(4)
+ *   hf_maxima   step 4  local maxima of the grid CWT
+ *   hf_segment  step 5  segmentation of the grid by the maxima (Sec. 2.3)
+ *   hf_label    step 6  particles take the label of their segmented cell
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every array argument is a DEVICE pointer on the context's device.  The
+ *    caller allocates and owns all of them; no call keeps a pointer after it
+ *    returns.  Calls are asynchronous: they enqueue kernels on the context's
+ *    stream and return.
+ *  - Grids are C-order [z][y][x]; cell (x, y, z) has linear index
+ *    (z*n + y)*n + x (int32, so n <= 1024).
+ *  - Positions are [np][3] rows (x, y, z) in the units of box_len, FP32 or
+ *    FP64 (hf_dtype).  Positions outside [0, box_len) wrap periodically.
+ *  - Supported n: n = 2^a 3^b with a >= 1, 8 <= n <= 1024.
+ *    frac_bits (B, CIC fraction bits per axis) in [8, 20].
+ *  - Workspaces are device buffers of at least hf_workspace_size() bytes,
+ *    256-byte aligned.  One workspace may be reused by every stage in turn.
+ *  - Argument errors are returned synchronously and nothing is enqueued.
+ *    Errors found by kernels (overflow, capacity, bad input values) set a
+ *    status word in the context; hf_sync() waits for the stream and returns
+ *    (then clears) them.
+ *  - One context per stream; a context must not be used from two host
+ *    threads at once.
+ */
+#ifndef HF_H
+#define HF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HF_OK = 0,
+    HF_ERR_ARG = 1,       /* null pointer, bad enum, non-finite scale, bad count */
+    HF_ERR_SIZE = 2,      /* n not supported (see above) or frac_bits out of range */
+    HF_ERR_WORKSPACE = 3, /* workspace smaller than hf_workspace_size or misaligned */
+    HF_ERR_OVERFLOW = 4,  /* device: a CIC cell exceeded 2^63 - 1 */
+    HF_ERR_CAPACITY = 5,  /* device: more maxima than the list capacity */
+    HF_ERR_DEVICE = 6,    /* HIP runtime failure */
+    HF_ERR_INPUT = 7      /* device: non-finite/out-of-range position, NaN in a field,
+                             negative or all-zero density grid */
+} hf_status;
+
+typedef enum { HF_F32 = 0, HF_F64 = 1 } hf_dtype;
+
+/* Discretisation of the wavelet convolution (Eq. (2)).
+ *  SAMPLED:  the wavelet of Eq. (4) sampled at the grid spacing and summed
+ *            over periodic images (the paper's discretised convolution,
+ *            Sec. 2.1), applied through its exact DFT.
+ *  ANALYTIC: the continuum Fourier transform of Eq. (4),
+ *            32 pi^1.5 w^-1.5 (k/w)^2 exp(-(k/w)^2), at the DFT wavenumbers. */
+typedef enum { HF_KERNEL_SAMPLED = 0, HF_KERNEL_ANALYTIC = 1 } hf_kernel;
+
+/* Periodic box: n^3 grid on a side of box_len (Mpc/h); node g sits at g*box_len/n. */
+typedef struct {
+    int32_t n;
+    int32_t frac_bits;
+    double box_len;
+} hf_box;
+
+/* Stage selectors for hf_workspace_size (bit mask: the result covers every
+ * selected stage, so one buffer can serve them in turn). */
+enum { HF_STAGE_DEPOSIT = 1, HF_STAGE_CWT = 2, HF_STAGE_MAXIMA = 4, HF_STAGE_SEGMENT = 8 };
+
+typedef struct hf_ctx hf_ctx;
+
+/* Create a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  Allocates a 256-byte device
+ * status block and a pinned host mirror, freed by hf_destroy. */
+hf_status hf_create(int device, void *hip_stream, hf_ctx **out);
+hf_status hf_destroy(hf_ctx *ctx);
+const char *hf_status_str(hf_status s);
+
+/* Wait for the context's stream, then return (and clear) the first
+ * device-detected error, highest code first: INPUT, OVERFLOW, CAPACITY. */
+hf_status hf_sync(hf_ctx *ctx);
+
+/* Bytes of workspace the selected stages need for this box and particle count. */
+hf_status hf_workspace_size(const hf_box *box, int64_t np, int stage_mask, size_t *bytes);
+
+/* Step 2, Eq. (1): cloud-in-cell deposit.
+ *  pos [np][3] (dtype), rho [n][n][n] int64 (overwritten).
+ *  Per axis, s = n 2^B / box_len is rounded once to the position dtype,
+ *  t = x*s is one correctly rounded multiply in that dtype, q = floor(t) mod
+ *  n 2^B, cell = q >> B, f = q & (2^B - 1); the lower node gets weight 2^B - f,
+ *  the upper node (periodic) f.  Each of the 8 corners gets the product of its
+ *  three weights (one particle = 2^3B).  Sums are exact int64 and independent
+ *  of particle order.  A cell above 2^63 - 1 -> HF_ERR_OVERFLOW; a position
+ *  with non-finite t or |t| >= 2^62 -> HF_ERR_INPUT (that particle is skipped).
+ *  np == 0 gives an all-zero grid.  Workspace: HF_STAGE_DEPOSIT. */
+hf_status hf_deposit(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype,
+                     int64_t np, int64_t *rho, void *ws, size_t ws_bytes);
+
+/* Step 3, Eqs. (2)-(4): grid CWT at scale k_w = w box_len / 1000 (step 1).
+ *  rho [n][n][n] int64 (>= 0, not all zero); cwt [n][n][n] FP32 (overwritten).
+ *  C_j = sum_g f_g K(x_j - x_g) with f = rho / mean(rho) (mean density units)
+ *  and K the kernel selected by `kernel` (dx^3 Psi sampled, or the analytic
+ *  transform), computed as a real 3D FFT, a multiply and an inverse FFT in FP32.
+ *  The mean is formed from the exact integer total in FP64.  Negative or
+ *  all-zero rho -> HF_ERR_INPUT.  Workspace: HF_STAGE_CWT. */
+hf_status hf_cwt(hf_ctx *ctx, const hf_box *box, const int64_t *rho, double kw, hf_kernel kernel,
+                 float *cwt, void *ws, size_t ws_bytes);
+
+/* Step 4: local maxima.  Cell j is a maximum iff (C_j, j) beats all 26
+ * periodic neighbours in the order "larger value, then larger index"
+ * (-0 equals +0) and C_j > tau.  max_idx receives the maxima's linear indices
+ * in increasing order (at most max_cap of them); *d_count (device int64)
+ * receives the total number found.  More than max_cap -> HF_ERR_CAPACITY.
+ * NaN in cwt -> HF_ERR_INPUT.  Workspace: HF_STAGE_MAXIMA. */
+hf_status hf_maxima(hf_ctx *ctx, const hf_box *box, const float *cwt, float tau,
+                    int32_t *max_idx, int64_t max_cap, int64_t *d_count, void *ws, size_t ws_bytes);
+
+/* Step 5, Sec. 2.3: segmentation by steepest ascent.  Each cell's parent is
+ * the largest of itself and its 26 neighbours in the order above; following
+ * parents ends at a local maximum (the root).  cell_label [n][n][n] int32
+ * receives the root's linear index if C_root > tau, else -1.  Roots above tau
+ * are exactly the hf_maxima list.  NaN -> HF_ERR_INPUT.
+ * Workspace: HF_STAGE_SEGMENT. */
+hf_status hf_segment(hf_ctx *ctx, const hf_box *box, const float *cwt, float tau,
+                     int32_t *cell_label, void *ws, size_t ws_bytes);
+
+/* Step 6: particle labels.  Each particle's node is the one with its largest
+ * CIC weight, ((q + 2^(B-1)) >> B) mod n per axis with q as in hf_deposit
+ * (half a cell goes up); particle_label[i] = cell_label[node].  Positions
+ * hf_deposit would reject get label -1 and set HF_ERR_INPUT. */
+hf_status hf_label(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np,
+                   const int32_t *cell_label, int32_t *particle_label);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HF_H */

@@ -1,0 +1,97 @@
+// Context management, status reporting and workspace sizing of libhf.
+#include "hf_internal.h"
+
+using namespace hf;
+
+namespace {
+
+__global__ void clear_status_kernel(uint32_t *st) {
+    if (threadIdx.x == 0) st[0] = 0u;
+}
+
+}  // namespace
+
+extern "C" hf_status hf_create(int device, void *hip_stream, hf_ctx **out) {
+    if (!out) return HF_ERR_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return HF_ERR_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return HF_ERR_DEVICE;
+    hf_ctx *c = new hf_ctx{};
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipMalloc(&c->d_status, 256) != hipSuccess) {
+        delete c;
+        return HF_ERR_DEVICE;
+    }
+    if (hipHostMalloc(&c->h_status, 256, hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(c->d_status);
+        delete c;
+        return HF_ERR_DEVICE;
+    }
+    c->h_status[0] = 0;
+    hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, c->stream, c->d_status);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipFree(c->d_status);
+        (void)hipHostFree(c->h_status);
+        delete c;
+        return HF_ERR_DEVICE;
+    }
+    *out = c;
+    return HF_OK;
+}
+
+extern "C" hf_status hf_destroy(hf_ctx *ctx) {
+    if (!ctx) return HF_ERR_ARG;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->d_status);
+    (void)hipHostFree(ctx->h_status);
+    delete ctx;
+    return HF_OK;
+}
+
+extern "C" const char *hf_status_str(hf_status s) {
+    switch (s) {
+        case HF_OK: return "ok";
+        case HF_ERR_ARG: return "invalid argument";
+        case HF_ERR_SIZE: return "unsupported grid size or fraction bits";
+        case HF_ERR_WORKSPACE: return "workspace too small or misaligned";
+        case HF_ERR_OVERFLOW: return "CIC cell overflow (cell mass above 2^63-1)";
+        case HF_ERR_CAPACITY: return "maxima list capacity exceeded";
+        case HF_ERR_DEVICE: return "HIP runtime error";
+        case HF_ERR_INPUT: return "invalid input values (non-finite position, NaN field, or empty/negative density)";
+    }
+    return "unknown status";
+}
+
+extern "C" hf_status hf_sync(hf_ctx *ctx) {
+    if (!ctx) return HF_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    if (hipMemcpyAsync(ctx->h_status, ctx->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream) !=
+        hipSuccess)
+        return HF_ERR_DEVICE;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return HF_ERR_DEVICE;
+    uint32_t st = ctx->h_status[0];
+    if (st == 0) return HF_OK;
+    hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->d_status);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return HF_ERR_DEVICE;
+    if (st & ST_INPUT) return HF_ERR_INPUT;
+    if (st & ST_OVERFLOW) return HF_ERR_OVERFLOW;
+    if (st & ST_CAPACITY) return HF_ERR_CAPACITY;
+    return HF_ERR_DEVICE;
+}
+
+extern "C" hf_status hf_workspace_size(const hf_box *box, int64_t np, int stage_mask, size_t *bytes) {
+    if (!bytes || np < 0) return HF_ERR_ARG;
+    hf_status s = check_box(box);
+    if (s != HF_OK) return s;
+    if (stage_mask & ~(HF_STAGE_DEPOSIT | HF_STAGE_CWT | HF_STAGE_MAXIMA | HF_STAGE_SEGMENT)) return HF_ERR_ARG;
+    size_t need = 0;
+    if (stage_mask & HF_STAGE_DEPOSIT) need = need > deposit_ws_bytes(*box, np) ? need : deposit_ws_bytes(*box, np);
+    if (stage_mask & HF_STAGE_CWT) need = need > cwt_ws_bytes(*box) ? need : cwt_ws_bytes(*box);
+    if (stage_mask & HF_STAGE_MAXIMA) need = need > maxima_ws_bytes(*box) ? need : maxima_ws_bytes(*box);
+    if (stage_mask & HF_STAGE_SEGMENT) need = need > segment_ws_bytes(*box) ? need : segment_ws_bytes(*box);
+    *bytes = need;
+    return HF_OK;
+}

@@ -1,0 +1,157 @@
+// Step 2 (Eq. (1)): cloud-in-cell deposit in 64-bit fixed point, and step 6:
+// particle labels from the nearest node.
+#include "hf_internal.h"
+
+using namespace hf;
+
+namespace {
+
+constexpr int DEP_BLOCK = 256;
+
+__global__ void fill_u64_kernel(unsigned long long *p, size_t count) {
+    size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x;
+    size_t stride = size_t(gridDim.x) * blockDim.x;
+    for (; i < count; i += stride) p[i] = 0ull;
+}
+
+// Adds w to a cell; reports the add that carries the cell past 2^63 - 1.
+__device__ __forceinline__ void cell_add(unsigned long long *rho, uint32_t idx, unsigned long long w,
+                                         bool &overflow) {
+    if (w == 0) return;
+    unsigned long long old = atomicAdd(rho + idx, w);
+    // every addend is below 2^61, so a sum crossing 2^63 is seen by exactly the
+    // add that crosses it
+    if (!(old >> 63) && ((old + w) >> 63)) overflow = true;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(DEP_BLOCK) deposit_atomic_kernel(const T *__restrict__ pos, int64_t np,
+                                                                   FixedPoint<T> fp, int n,
+                                                                   unsigned long long *rho, uint32_t *status) {
+    const int64_t one = int64_t(1) << fp.bits;
+    bool overflow = false, bad = false;
+    int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < np; i += stride) {
+        int64_t qx, qy, qz;
+        bool ok = fp.q(pos[3 * i + 0], qx);
+        ok = fp.q(pos[3 * i + 1], qy) && ok;
+        ok = fp.q(pos[3 * i + 2], qz) && ok;
+        if (!ok) {
+            bad = true;
+            continue;
+        }
+        const uint32_t cx = uint32_t(qx >> fp.bits), cy = uint32_t(qy >> fp.bits), cz = uint32_t(qz >> fp.bits);
+        const uint64_t fx = uint64_t(qx & (one - 1)), fy = uint64_t(qy & (one - 1)), fz = uint64_t(qz & (one - 1));
+        const uint64_t wx[2] = {uint64_t(one) - fx, fx};
+        const uint64_t wy[2] = {uint64_t(one) - fy, fy};
+        const uint64_t wz[2] = {uint64_t(one) - fz, fz};
+        const uint32_t xs[2] = {cx, cx + 1 == uint32_t(n) ? 0u : cx + 1};
+        const uint32_t ys[2] = {cy, cy + 1 == uint32_t(n) ? 0u : cy + 1};
+        const uint32_t zs[2] = {cz, cz + 1 == uint32_t(n) ? 0u : cz + 1};
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const uint64_t wzy = wz[a] * wy[b];
+                const uint32_t row = (zs[a] * uint32_t(n) + ys[b]) * uint32_t(n);
+                cell_add(rho, row + xs[0], wzy * wx[0], overflow);
+                cell_add(rho, row + xs[1], wzy * wx[1], overflow);
+            }
+    }
+    if (overflow) atomicOr(status, ST_OVERFLOW);
+    if (bad) atomicOr(status, ST_INPUT);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(DEP_BLOCK) label_kernel(const T *__restrict__ pos, int64_t np, FixedPoint<T> fp,
+                                                          int n, const int32_t *__restrict__ cell_label,
+                                                          int32_t *__restrict__ out, uint32_t *status) {
+    const int64_t half = int64_t(1) << (fp.bits - 1);
+    bool bad = false;
+    int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < np; i += stride) {
+        int64_t qx, qy, qz;
+        bool ok = fp.q(pos[3 * i + 0], qx);
+        ok = fp.q(pos[3 * i + 1], qy) && ok;
+        ok = fp.q(pos[3 * i + 2], qz) && ok;
+        if (!ok) {
+            bad = true;
+            out[i] = -1;
+            continue;
+        }
+        uint32_t x = uint32_t((qx + half) >> fp.bits), y = uint32_t((qy + half) >> fp.bits),
+                 z = uint32_t((qz + half) >> fp.bits);
+        if (x == uint32_t(n)) x = 0;
+        if (y == uint32_t(n)) y = 0;
+        if (z == uint32_t(n)) z = 0;
+        out[i] = cell_label[(z * uint32_t(n) + y) * uint32_t(n) + x];
+    }
+    if (bad) atomicOr(status, ST_INPUT);
+}
+
+template <typename T>
+FixedPoint<T> make_fixed_point(const hf_box &box) {
+    FixedPoint<T> fp;
+    fp.bits = box.frac_bits;
+    fp.period = int64_t(box.n) << box.frac_bits;
+    fp.scale = T(double(box.n) * double(int64_t(1) << box.frac_bits) / box.box_len);
+    return fp;
+}
+
+int grid_for(int64_t work, int block, int cap) {
+    int64_t g = (work + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return int(g);
+}
+
+}  // namespace
+
+size_t hf::deposit_ws_bytes(const hf_box &, int64_t) { return 0; }
+
+extern "C" hf_status hf_deposit(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np,
+                                int64_t *rho, void *ws, size_t ws_bytes) {
+    if (!ctx || !rho || np < 0 || (np > 0 && !pos)) return HF_ERR_ARG;
+    if (dtype != HF_F32 && dtype != HF_F64) return HF_ERR_ARG;
+    hf_status s = check_box(box);
+    if (s != HF_OK) return s;
+    s = check_ws(ws, ws_bytes, deposit_ws_bytes(*box, np));
+    if (s != HF_OK) return s;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    const size_t cells = size_t(box->n) * box->n * box->n;
+    auto *grid = reinterpret_cast<unsigned long long *>(rho);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(int64_t(cells), 256, 8192)), dim3(256), 0, ctx->stream, grid,
+                       cells);
+    if (np > 0) {
+        const int g = grid_for(np, DEP_BLOCK, 65536);
+        if (dtype == HF_F32)
+            hipLaunchKernelGGL(deposit_atomic_kernel<float>, dim3(g), dim3(DEP_BLOCK), 0, ctx->stream,
+                               static_cast<const float *>(pos), np, make_fixed_point<float>(*box), box->n, grid,
+                               ctx->d_status);
+        else
+            hipLaunchKernelGGL(deposit_atomic_kernel<double>, dim3(g), dim3(DEP_BLOCK), 0, ctx->stream,
+                               static_cast<const double *>(pos), np, make_fixed_point<double>(*box), box->n, grid,
+                               ctx->d_status);
+    }
+    return launch_status();
+}
+
+extern "C" hf_status hf_label(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np,
+                              const int32_t *cell_label, int32_t *particle_label) {
+    if (!ctx || !cell_label || np < 0 || (np > 0 && (!pos || !particle_label))) return HF_ERR_ARG;
+    if (dtype != HF_F32 && dtype != HF_F64) return HF_ERR_ARG;
+    hf_status s = check_box(box);
+    if (s != HF_OK) return s;
+    if (np == 0) return HF_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    const int g = grid_for(np, DEP_BLOCK, 65536);
+    if (dtype == HF_F32)
+        hipLaunchKernelGGL(label_kernel<float>, dim3(g), dim3(DEP_BLOCK), 0, ctx->stream,
+                           static_cast<const float *>(pos), np, make_fixed_point<float>(*box), box->n, cell_label,
+                           particle_label, ctx->d_status);
+    else
+        hipLaunchKernelGGL(label_kernel<double>, dim3(g), dim3(DEP_BLOCK), 0, ctx->stream,
+                           static_cast<const double *>(pos), np, make_fixed_point<double>(*box), box->n, cell_label,
+                           particle_label, ctx->d_status);
+    return launch_status();
+}

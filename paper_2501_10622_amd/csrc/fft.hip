@@ -1,0 +1,621 @@
+// Step 3 (Eqs. (2)-(4)): the grid CWT as a real 3D FFT, a multiply by the
+// wavelet's DFT-domain multiplier, and an inverse FFT, all in FP32 with
+// FP64 only for the mean density and for table generation.
+//
+// Data flow (n^3 grid, H = n/2 + 1, half spectrum S[z][y][kx] complex64):
+//   x_fwd   : rows of int64 rho -> float, two real rows packed as one complex
+//             row, complex FFT along x, split into two half-spectrum rows;
+//             also the exact 128-bit mass of the rows.
+//   mass    : sums the row masses, mean density in FP64 -> overall scale.
+//   y_pass  : complex FFT along y on 16-column tiles (forward).
+//   z_mul   : forward FFT along z, times the multiplier and the scale,
+//             inverse FFT along z, in LDS (one HBM round trip).
+//   y_pass  : inverse along y.
+//   x_inv   : two half-spectrum rows -> one complex row, inverse FFT, the
+//             real and imaginary parts are the two output rows.
+// Every 1D transform is a Stockham autosort FFT over radices 8/4/3/2 held in
+// LDS, element n of pencil p at buf[n * pitch + p].
+#include <cmath>
+
+#include "hf_internal.h"
+
+using namespace hf;
+
+namespace {
+
+constexpr int MAX_STAGES = 12;
+constexpr int MAX_ELEMS = 16;  // complex values per thread per stage
+constexpr int YZ_TILE = 16;    // pencils per workgroup in the y and z passes
+
+struct FftPlan {
+    int n;
+    int nst;
+    int radix[MAX_STAGES];
+};
+
+FftPlan make_plan(int n) {
+    FftPlan p{};
+    p.n = n;
+    int m = n;
+    while (m % 3 == 0) {
+        p.radix[p.nst++] = 3;
+        m /= 3;
+    }
+    while (m % 8 == 0) {
+        p.radix[p.nst++] = 8;
+        m /= 8;
+    }
+    while (m % 4 == 0) {
+        p.radix[p.nst++] = 4;
+        m /= 4;
+    }
+    while (m % 2 == 0) {
+        p.radix[p.nst++] = 2;
+        m /= 2;
+    }
+    return p;
+}
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 mul_mi(float2 a) {
+    return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(float2 &a, float2 &b) {
+    float2 t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2 &v0, float2 &v1, float2 &v2, float2 &v3) {
+    float2 t0 = cadd(v0, v2), t1 = csub(v0, v2);
+    float2 t2 = cadd(v1, v3), t3 = mul_mi<INV>(csub(v1, v3));
+    v0 = cadd(t0, t2);
+    v2 = csub(t0, t2);
+    v1 = cadd(t1, t3);
+    v3 = csub(t1, t3);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2 (&v)[R]) {
+    if constexpr (R == 2) {
+        dft2<INV>(v[0], v[1]);
+    } else if constexpr (R == 4) {
+        dft4<INV>(v[0], v[1], v[2], v[3]);
+    } else if constexpr (R == 8) {
+        // radix-8 as two radix-4 transforms of the even and odd inputs
+        float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+        float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+        dft4<INV>(e0, e1, e2, e3);
+        dft4<INV>(o0, o1, o2, o3);
+        const float r = 0.70710678118654752440f;
+        // o_s *= exp(-+ 2 pi i s / 8)
+        o1 = INV ? make_float2(r * (o1.x - o1.y), r * (o1.x + o1.y)) : make_float2(r * (o1.x + o1.y), r * (o1.y - o1.x));
+        o2 = mul_mi<INV>(o2);
+        o3 = INV ? make_float2(-r * (o3.x + o3.y), r * (o3.x - o3.y)) : make_float2(r * (o3.y - o3.x), -r * (o3.x + o3.y));
+        v[0] = cadd(e0, o0);
+        v[4] = csub(e0, o0);
+        v[1] = cadd(e1, o1);
+        v[5] = csub(e1, o1);
+        v[2] = cadd(e2, o2);
+        v[6] = csub(e2, o2);
+        v[3] = cadd(e3, o3);
+        v[7] = csub(e3, o3);
+    } else if constexpr (R == 3) {
+        const float c = -0.5f;
+        const float s = INV ? 0.86602540378443864676f : -0.86602540378443864676f;
+        float2 t = cadd(v[1], v[2]);
+        float2 d = csub(v[1], v[2]);
+        float2 m = make_float2(v[0].x + c * t.x, v[0].y + c * t.y);
+        float2 id = make_float2(-s * d.y, s * d.x);  // i s d
+        v[0] = cadd(v[0], t);
+        v[1] = cadd(m, id);
+        v[2] = csub(m, id);
+    }
+}
+
+// One Stockham stage of radix R on P pencils (P = 1 << lp) of length n in LDS.
+// tw[m] = exp(-2 pi i m / n).  Ns = product of the radices already applied.
+template <int R, bool INV>
+__device__ __forceinline__ void fft_stage(float2 *buf, int pitch, int lp, int n, int Ns, const float2 *tw, int tid,
+                                          int nthreads) {
+    constexpr int MAXB = (MAX_ELEMS + R - 1) / R;
+    const int nbf = n / R;
+    const int total = nbf << lp;
+    const int pmask = (1 << lp) - 1;
+    const int twstride = n / (Ns * R);
+    float2 v[MAXB][R];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = tid + i * nthreads;
+        if (b < total) {
+            const int p = b & pmask;
+            const int j = b >> lp;
+            const int k = j % Ns;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = buf[(j + r * nbf) * pitch + p];
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    float2 w = tw[r * k * twstride];
+                    if (INV) w.y = -w.y;
+                    v[i][r] = cmul(v[i][r], w);
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = tid + i * nthreads;
+        if (b < total) {
+            const int p = b & pmask;
+            const int j = b >> lp;
+            const int k = j % Ns;
+            dft<R, INV>(v[i]);
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[(base + r * Ns) * pitch + p] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <bool INV>
+__device__ void fft_lds(float2 *buf, int pitch, int lp, const FftPlan &pl, const float2 *tw, int tid,
+                        int nthreads) {
+    int Ns = 1;
+    for (int s = 0; s < pl.nst; ++s) {
+        const int R = pl.radix[s];
+        if (R == 8)
+            fft_stage<8, INV>(buf, pitch, lp, pl.n, Ns, tw, tid, nthreads);
+        else if (R == 4)
+            fft_stage<4, INV>(buf, pitch, lp, pl.n, Ns, tw, tid, nthreads);
+        else if (R == 2)
+            fft_stage<2, INV>(buf, pitch, lp, pl.n, Ns, tw, tid, nthreads);
+        else
+            fft_stage<3, INV>(buf, pitch, lp, pl.n, Ns, tw, tid, nthreads);
+        Ns *= R;
+    }
+}
+
+__device__ __forceinline__ void load_twiddles(float2 *tw_s, const float2 *tw_g, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tw_s[i] = tw_g[i];
+}
+
+// ---------------------------------------------------------------------------
+// Tables, generated in FP64 and stored as FP32.
+// ---------------------------------------------------------------------------
+struct TableArgs {
+    int n;
+    int mode;       // hf_kernel
+    int images;     // periodic images per side for the sampled kernel
+    double box_len;
+    double w;
+};
+
+// twiddles tw[m] = exp(-2 pi i m / n); periodised 1D Gaussian factors of the
+// sampled wavelet: G_j = sum_m g(x_j + m L), Hs_j = sum_m (x_j + m L)^2 g(...)
+// with g(t) = exp(-w^2 t^2 / 4) and x_j the minimum-image offset of node j.
+__global__ void tables_stage1(TableArgs a, float2 *tw, double *g_tab, double *h_tab) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.n) return;
+    double s, c;
+    sincospi(2.0 * double(j) / double(a.n), &s, &c);
+    tw[j] = make_float2(float(c), float(-s));
+    const double dx = a.box_len / a.n;
+    const int jc = (j + a.n / 2) % a.n - a.n / 2;
+    double G = 0.0, Hs = 0.0;
+    for (int m = -a.images; m <= a.images; ++m) {
+        const double x = jc * dx + m * a.box_len;
+        const double g = exp(-0.25 * a.w * a.w * x * x);
+        G += g;
+        Hs += x * x * g;
+    }
+    g_tab[j] = G;
+    h_tab[j] = Hs;
+}
+
+// Separable multiplier: M(kx,ky,kz) = P_x B_y B_z + B_x P_y B_z + B_x B_y P_z.
+//  sampled : B = DFT(G), A = DFT(Hs), P = (alpha/3) B + beta A with
+//            alpha = 6 dx^3 w^1.5, beta = -dx^3 w^3.5 (Eq. (4) split into
+//            6 g g g - w^2 (x^2 g g g + ...), periodised and transformed);
+//  analytic: B = exp(-k^2/w^2), P = 32 pi^1.5 w^-3.5 k^2 B (the transform of Eq. (4)).
+__global__ void tables_stage2(TableArgs a, const double *g_tab, const double *h_tab, float *b_out, float *p_out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const double w = a.w;
+    if (a.mode == HF_KERNEL_ANALYTIC) {
+        const int ks = k <= a.n / 2 ? k : k - a.n;
+        const double kk = 2.0 * M_PI * ks / a.box_len;
+        const double B = exp(-(kk * kk) / (w * w));
+        const double beta = 32.0 * pow(M_PI, 1.5) * pow(w, -3.5);
+        b_out[k] = float(B);
+        p_out[k] = float(beta * kk * kk * B);
+        return;
+    }
+    double B = 0.0, A = 0.0;
+    for (int j = 0; j < a.n; ++j) {
+        const long long ph = (static_cast<long long>(j) * k) % a.n;
+        const double c = cospi(2.0 * double(ph) / double(a.n));
+        B += g_tab[j] * c;
+        A += h_tab[j] * c;
+    }
+    const double dx = a.box_len / a.n;
+    const double dx3 = dx * dx * dx;
+    const double alpha = 6.0 * dx3 * pow(w, 1.5);
+    const double beta = -dx3 * pow(w, 3.5);
+    b_out[k] = float(B);
+    p_out[k] = float(alpha / 3.0 * B + beta * A);
+}
+
+// ---------------------------------------------------------------------------
+// x passes
+// ---------------------------------------------------------------------------
+struct Mass128 {
+    unsigned long long lo, hi;
+};
+
+__device__ __forceinline__ void add128(unsigned long long &lo, unsigned long long &hi, unsigned long long v) {
+    unsigned long long t = lo + v;
+    hi += (t < lo);
+    lo = t;
+}
+
+// One workgroup = xp row pairs (rows 2q, 2q+1 of the n*n rows of x).
+__global__ void fft_x_fwd_kernel(const int64_t *__restrict__ rho, float2 *__restrict__ spec, FftPlan pl, int lp,
+                                 const float2 *__restrict__ tw_g, Mass128 *__restrict__ mass, uint32_t *status) {
+    extern __shared__ float2 smem[];
+    const int n = pl.n, H = n / 2 + 1;
+    const int xp = 1 << lp, pitch = xp + 1;
+    float2 *tw = smem;
+    float2 *buf = smem + n;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int64_t pairs = int64_t(n) * n / 2;
+    const int64_t q0 = int64_t(blockIdx.x) * xp;
+    load_twiddles(tw, tw_g, n);
+    unsigned long long lo = 0, hi = 0;
+    bool neg = false;
+    for (int e = tid; e < xp * n; e += nt) {
+        const int p = e / n, x = e - p * n;
+        const int64_t q = q0 + p;
+        float2 v = make_float2(0.f, 0.f);
+        if (q < pairs) {
+            const int64_t a = rho[(2 * q) * n + x];
+            const int64_t b = rho[(2 * q + 1) * n + x];
+            neg |= (a < 0) | (b < 0);
+            add128(lo, hi, static_cast<unsigned long long>(a));
+            add128(lo, hi, static_cast<unsigned long long>(b));
+            v = make_float2(float(a), float(b));
+        }
+        buf[x * pitch + p] = v;
+    }
+    if (neg) atomicOr(status, ST_INPUT);
+    // workgroup sum of the 128-bit masses (fixed order: deterministic)
+    __shared__ unsigned long long red_lo[1024 / 64], red_hi[1024 / 64];
+    {
+        // wave reduction by shuffles
+        for (int off = 32; off > 0; off >>= 1) {
+            unsigned long long olo = __shfl_down(lo, off, 64);
+            unsigned long long ohi = __shfl_down(hi, off, 64);
+            add128(lo, hi, olo);
+            hi += ohi;
+        }
+        const int wave = tid >> 6;
+        if ((tid & 63) == 0) {
+            red_lo[wave] = lo;
+            red_hi[wave] = hi;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long L = 0, Hh = 0;
+        for (int w = 0; w < (nt + 63) / 64; ++w) {
+            add128(L, Hh, red_lo[w]);
+            Hh += red_hi[w];
+        }
+        mass[blockIdx.x].lo = L;
+        mass[blockIdx.x].hi = Hh;
+    }
+    fft_lds<false>(buf, pitch, lp, pl, tw, tid, nt);
+    // split Z = A + iB into the two real rows' spectra
+    for (int e = tid; e < xp * H; e += nt) {
+        const int p = e / H, k = e - p * H;
+        const int64_t q = q0 + p;
+        if (q >= pairs) continue;
+        const float2 zk = buf[k * pitch + p];
+        const float2 zm = buf[((n - k) % n) * pitch + p];
+        const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+        const float2 B = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+        spec[(2 * q) * H + k] = A;
+        spec[(2 * q + 1) * H + k] = B;
+    }
+}
+
+__global__ void fft_x_inv_kernel(const float2 *__restrict__ spec, float *__restrict__ out, FftPlan pl, int lp,
+                                 const float2 *__restrict__ tw_g) {
+    extern __shared__ float2 smem[];
+    const int n = pl.n, H = n / 2 + 1;
+    const int xp = 1 << lp, pitch = xp + 1;
+    float2 *tw = smem;
+    float2 *buf = smem + n;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int64_t pairs = int64_t(n) * n / 2;
+    const int64_t q0 = int64_t(blockIdx.x) * xp;
+    load_twiddles(tw, tw_g, n);
+    for (int e = tid; e < xp * H; e += nt) {
+        const int p = e / H, k = e - p * H;
+        const int64_t q = q0 + p;
+        float2 A = make_float2(0.f, 0.f), B = A;
+        if (q < pairs) {
+            A = spec[(2 * q) * H + k];
+            B = spec[(2 * q + 1) * H + k];
+        }
+        if (k == 0 || 2 * k == n) {
+            // DC and Nyquist of a real row are real
+            buf[k * pitch + p] = make_float2(A.x, B.x);
+        } else {
+            buf[k * pitch + p] = make_float2(A.x - B.y, A.y + B.x);
+            buf[(n - k) * pitch + p] = make_float2(A.x + B.y, B.x - A.y);
+        }
+    }
+    __syncthreads();
+    fft_lds<true>(buf, pitch, lp, pl, tw, tid, nt);
+    for (int e = tid; e < xp * n; e += nt) {
+        const int p = e / n, x = e - p * n;
+        const int64_t q = q0 + p;
+        if (q >= pairs) continue;
+        const float2 v = buf[x * pitch + p];
+        out[(2 * q) * n + x] = v.x;
+        out[(2 * q + 1) * n + x] = v.y;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// mean density and overall scale
+// ---------------------------------------------------------------------------
+// Correctly rounded conversion of a 128-bit unsigned integer to double.
+__device__ double u128_to_double(unsigned long long lo, unsigned long long hi) {
+    if (hi == 0) {
+        // split into 32-bit halves: both converts are exact, one rounding in the add
+        return double(uint32_t(lo >> 32)) * 4294967296.0 + double(uint32_t(lo));
+    }
+    const int lz = __clzll(hi);
+    const int sh = 64 - lz;  // bits to drop so the value fits 64 bits
+    unsigned long long top = (hi << lz) | (lo >> sh);
+    const unsigned long long dropped = lo & ((1ull << sh) - 1ull);
+    top |= (dropped != 0);  // sticky bit keeps round-to-nearest correct
+    const double t = double(uint32_t(top >> 32)) * 4294967296.0 + double(uint32_t(top));
+    return ldexp(t, sh);
+}
+
+__global__ void mass_kernel(const Mass128 *__restrict__ mass, int64_t nparts, int n, double *scalars,
+                            uint32_t *status) {
+    __shared__ unsigned long long red_lo[16], red_hi[16];
+    unsigned long long lo = 0, hi = 0;
+    for (int64_t i = threadIdx.x; i < nparts; i += blockDim.x) {
+        add128(lo, hi, mass[i].lo);
+        hi += mass[i].hi;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long olo = __shfl_down(lo, off, 64);
+        unsigned long long ohi = __shfl_down(hi, off, 64);
+        add128(lo, hi, olo);
+        hi += ohi;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red_lo[threadIdx.x >> 6] = lo;
+        red_hi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long L = 0, Hh = 0;
+        for (int w = 0; w < int(blockDim.x >> 6); ++w) {
+            add128(L, Hh, red_lo[w]);
+            Hh += red_hi[w];
+        }
+        const double total = u128_to_double(L, Hh);
+        const double cells = double(n) * double(n) * double(n);
+        const double mbar = total / cells;  // mean cell mass, FP64
+        if (!(mbar > 0.0)) {
+            atomicOr(status, ST_INPUT);
+            scalars[0] = 0.0;
+        } else {
+            // C = IDFT(DFT(rho) M) / (mbar n^3): the mean normalisation and the
+            // inverse-transform 1/n^3 folded into one factor
+            scalars[0] = 1.0 / (mbar * cells);
+        }
+        scalars[1] = mbar;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// y and z passes on 16-column tiles of the half spectrum
+// ---------------------------------------------------------------------------
+template <bool INV>
+__global__ void fft_y_kernel(float2 *__restrict__ spec, FftPlan pl, const float2 *__restrict__ tw_g) {
+    extern __shared__ float2 smem[];
+    const int n = pl.n, H = n / 2 + 1;
+    float2 *tw = smem;
+    float2 *buf = smem + n;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int kx0 = blockIdx.x * YZ_TILE;
+    const int valid = min(YZ_TILE, H - kx0);
+    const size_t zbase = size_t(blockIdx.y) * n * H;
+    load_twiddles(tw, tw_g, n);
+    for (int e = tid; e < n * YZ_TILE; e += nt) {
+        const int p = e & (YZ_TILE - 1), y = e >> 4;
+        buf[e] = p < valid ? spec[zbase + size_t(y) * H + kx0 + p] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    fft_lds<INV>(buf, YZ_TILE, 4, pl, tw, tid, nt);
+    for (int e = tid; e < n * YZ_TILE; e += nt) {
+        const int p = e & (YZ_TILE - 1), y = e >> 4;
+        if (p < valid) spec[zbase + size_t(y) * H + kx0 + p] = buf[e];
+    }
+}
+
+__global__ void fft_z_mul_kernel(float2 *__restrict__ spec, FftPlan pl, const float2 *__restrict__ tw_g,
+                                 const float *__restrict__ tab_b, const float *__restrict__ tab_p,
+                                 const double *__restrict__ scalars) {
+    extern __shared__ float2 smem[];
+    const int n = pl.n, H = n / 2 + 1;
+    float2 *tw = smem;
+    float2 *buf = smem + n;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int kx0 = blockIdx.x * YZ_TILE;
+    const int ky = blockIdx.y;
+    const int valid = min(YZ_TILE, H - kx0);
+    const size_t zstride = size_t(n) * H;
+    const size_t base = size_t(ky) * H + kx0;
+    load_twiddles(tw, tw_g, n);
+    for (int e = tid; e < n * YZ_TILE; e += nt) {
+        const int p = e & (YZ_TILE - 1), z = e >> 4;
+        buf[e] = p < valid ? spec[size_t(z) * zstride + base + p] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    fft_lds<false>(buf, YZ_TILE, 4, pl, tw, tid, nt);
+    const float scale = float(scalars[0]);
+    const float by = tab_b[ky], py = tab_p[ky];
+    for (int e = tid; e < n * YZ_TILE; e += nt) {
+        const int p = e & (YZ_TILE - 1), z = e >> 4;
+        const int kx = min(kx0 + p, H - 1);
+        const float bx = tab_b[kx], px = tab_p[kx];
+        const float bz = tab_b[z], pz = tab_p[z];
+        const float m = ((px * by + bx * py) * bz + bx * by * pz) * scale;
+        const float2 v = buf[e];
+        buf[e] = make_float2(v.x * m, v.y * m);
+    }
+    __syncthreads();
+    fft_lds<true>(buf, YZ_TILE, 4, pl, tw, tid, nt);
+    for (int e = tid; e < n * YZ_TILE; e += nt) {
+        const int p = e & (YZ_TILE - 1), z = e >> 4;
+        if (p < valid) spec[size_t(z) * zstride + base + p] = buf[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+struct CwtLayout {
+    size_t scalars, tw, gtab, htab, btab, ptab, mass, spec, total;
+    int lp_x;       // log2 of row pairs per x-pass workgroup
+    int64_t xblocks;
+};
+
+int x_log_pairs(int n) {
+    // about 4096 complex values per x-pass workgroup, between 4 and 16 row pairs
+    int lp = 4;
+    while (lp > 2 && (n << lp) > 4096) --lp;
+    return lp;
+}
+
+CwtLayout cwt_layout(int n) {
+    CwtLayout L{};
+    const size_t H = size_t(n) / 2 + 1;
+    L.lp_x = x_log_pairs(n);
+    const int64_t pairs = int64_t(n) * n / 2;
+    L.xblocks = (pairs + (1 << L.lp_x) - 1) >> L.lp_x;
+    size_t off = 0;
+    L.scalars = off;
+    off = align_up(off + 64);
+    L.tw = off;
+    off = align_up(off + sizeof(float2) * n);
+    L.gtab = off;
+    off = align_up(off + sizeof(double) * n);
+    L.htab = off;
+    off = align_up(off + sizeof(double) * n);
+    L.btab = off;
+    off = align_up(off + sizeof(float) * n);
+    L.ptab = off;
+    off = align_up(off + sizeof(float) * n);
+    L.mass = off;
+    off = align_up(off + sizeof(Mass128) * size_t(L.xblocks));
+    L.spec = off;
+    off = align_up(off + sizeof(float2) * size_t(n) * n * H);
+    L.total = off;
+    return L;
+}
+
+int threads_for(int elems) {
+    int t = (elems + MAX_ELEMS - 1) / MAX_ELEMS;
+    t = (t + 63) / 64 * 64;
+    if (t < 64) t = 64;
+    if (t > 1024) t = 1024;
+    return t;
+}
+
+}  // namespace
+
+size_t hf::cwt_ws_bytes(const hf_box &box) { return cwt_layout(box.n).total; }
+
+extern "C" hf_status hf_cwt(hf_ctx *ctx, const hf_box *box, const int64_t *rho, double kw, hf_kernel kernel,
+                            float *cwt, void *ws, size_t ws_bytes) {
+    if (!ctx || !rho || !cwt) return HF_ERR_ARG;
+    if (kernel != HF_KERNEL_SAMPLED && kernel != HF_KERNEL_ANALYTIC) return HF_ERR_ARG;
+    if (!(kw > 0.0) || !std::isfinite(kw)) return HF_ERR_ARG;
+    hf_status s = check_box(box);
+    if (s != HF_OK) return s;
+    const int n = box->n;
+    const CwtLayout L = cwt_layout(n);
+    s = check_ws(ws, ws_bytes, L.total);
+    if (s != HF_OK) return s;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    char *w8 = static_cast<char *>(ws);
+    double *scalars = reinterpret_cast<double *>(w8 + L.scalars);
+    float2 *tw = reinterpret_cast<float2 *>(w8 + L.tw);
+    double *gtab = reinterpret_cast<double *>(w8 + L.gtab);
+    double *htab = reinterpret_cast<double *>(w8 + L.htab);
+    float *btab = reinterpret_cast<float *>(w8 + L.btab);
+    float *ptab = reinterpret_cast<float *>(w8 + L.ptab);
+    Mass128 *mass = reinterpret_cast<Mass128 *>(w8 + L.mass);
+    float2 *spec = reinterpret_cast<float2 *>(w8 + L.spec);
+    hipStream_t st = ctx->stream;
+
+    TableArgs ta{};
+    ta.n = n;
+    ta.mode = kernel;
+    ta.box_len = box->box_len;
+    ta.w = 1000.0 * kw / box->box_len;  // step 1: k_w = w L / 1000
+    // periodic images within w (I + 1/2) L >= 16, where the wavelet is < 1e-25 of its peak
+    ta.images = std::max(1, int(std::ceil(16.0 / (ta.w * box->box_len) - 0.5)));
+    const int tb = 256, tg = (n + tb - 1) / tb;
+    hipLaunchKernelGGL(tables_stage1, dim3(tg), dim3(tb), 0, st, ta, tw, gtab, htab);
+    hipLaunchKernelGGL(tables_stage2, dim3(tg), dim3(tb), 0, st, ta, gtab, htab, btab, ptab);
+
+    const FftPlan pl = make_plan(n);
+    const int H = n / 2 + 1;
+    const int tiles = (H + YZ_TILE - 1) / YZ_TILE;
+    const int yz_threads = threads_for(n * YZ_TILE);
+    const size_t yz_shm = sizeof(float2) * (size_t(n) + size_t(n) * YZ_TILE);
+    const int x_threads = threads_for((1 << L.lp_x) * n);
+    const size_t x_shm = sizeof(float2) * (size_t(n) + size_t(n) * ((1 << L.lp_x) + 1));
+    if (yz_shm > 65536) {
+        // tiles of 16 pencils of length n need more than the default 64 KiB of LDS
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_y_kernel<false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(yz_shm)) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_y_kernel<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(yz_shm)) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_z_mul_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(yz_shm)) != hipSuccess)
+            return HF_ERR_DEVICE;
+    }
+    hipLaunchKernelGGL(fft_x_fwd_kernel, dim3(unsigned(L.xblocks)), dim3(x_threads), x_shm, st, rho, spec, pl,
+                       L.lp_x, tw, mass, ctx->d_status);
+    hipLaunchKernelGGL(mass_kernel, dim3(1), dim3(1024), 0, st, mass, L.xblocks, n, scalars, ctx->d_status);
+    hipLaunchKernelGGL(fft_y_kernel<false>, dim3(tiles, n), dim3(yz_threads), yz_shm, st, spec, pl, tw);
+    hipLaunchKernelGGL(fft_z_mul_kernel, dim3(tiles, n), dim3(yz_threads), yz_shm, st, spec, pl, tw, btab, ptab,
+                       scalars);
+    hipLaunchKernelGGL(fft_y_kernel<true>, dim3(tiles, n), dim3(yz_threads), yz_shm, st, spec, pl, tw);
+    hipLaunchKernelGGL(fft_x_inv_kernel, dim3(unsigned(L.xblocks)), dim3(x_threads), x_shm, st, spec, cwt, pl,
+                       L.lp_x, tw);
+    return launch_status();
+}

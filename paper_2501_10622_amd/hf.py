@@ -1,0 +1,278 @@
+"""ctypes binding of libhf (include/hf.h): argument marshalling only.
+
+Every stage runs in the HIP kernels of libhf.so.  There is no CPU fallback:
+if the library is missing or no GPU is visible, the calls raise.
+PyTorch provides device memory and the stream the kernels are enqueued on.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhf.so")
+
+HF_OK, HF_ERR_ARG, HF_ERR_SIZE, HF_ERR_WORKSPACE = 0, 1, 2, 3
+HF_ERR_OVERFLOW, HF_ERR_CAPACITY, HF_ERR_DEVICE, HF_ERR_INPUT = 4, 5, 6, 7
+HF_F32, HF_F64 = 0, 1
+KERNELS = {"sampled": 0, "analytic": 1}
+STAGE_DEPOSIT, STAGE_CWT, STAGE_MAXIMA, STAGE_SEGMENT = 1, 2, 4, 8
+
+EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_size",
+           "hf_deposit", "hf_cwt", "hf_maxima", "hf_segment", "hf_label")
+
+
+class HFError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {status_str(code)} (hf_status {code})")
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("frac_bits", ctypes.c_int32), ("box_len", ctypes.c_double)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libhf.so and declare its signatures (no GPU needed to load)."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built: run __graft_entry__.build() "
+                               "(python -m paper_2501_10622_amd.build)")
+        lib = ctypes.CDLL(path)
+        vp, i32, i64, sz, dbl, flt = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t,
+                                      ctypes.c_double, ctypes.c_float)
+        bp = ctypes.POINTER(Box)
+        sig = {
+            "hf_create": (ctypes.c_int, [ctypes.c_int, vp, ctypes.POINTER(vp)]),
+            "hf_destroy": (ctypes.c_int, [vp]),
+            "hf_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+            "hf_sync": (ctypes.c_int, [vp]),
+            "hf_workspace_size": (ctypes.c_int, [bp, i64, ctypes.c_int, ctypes.POINTER(sz)]),
+            "hf_deposit": (ctypes.c_int, [vp, bp, vp, ctypes.c_int, i64, vp, vp, sz]),
+            "hf_cwt": (ctypes.c_int, [vp, bp, vp, dbl, ctypes.c_int, vp, vp, sz]),
+            "hf_maxima": (ctypes.c_int, [vp, bp, vp, flt, vp, i64, vp, vp, sz]),
+            "hf_segment": (ctypes.c_int, [vp, bp, vp, flt, vp, vp, sz]),
+            "hf_label": (ctypes.c_int, [vp, bp, vp, ctypes.c_int, i64, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+        return lib
+
+
+def status_str(code: int) -> str:
+    try:
+        return load_library().hf_status_str(int(code)).decode()
+    except RuntimeError:
+        return f"status {code}"
+
+
+def _check(code: int, where: str):
+    if code != HF_OK:
+        raise HFError(code, where)
+
+
+# ---------------------------------------------------------------------------
+# contexts and workspaces
+# ---------------------------------------------------------------------------
+class Context:
+    """An hf_ctx bound to one device and one HIP stream."""
+
+    def __init__(self, device: int, stream: torch.cuda.Stream):
+        lib = load_library()
+        self.device = int(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib.hf_create(self.device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)), "hf_create")
+        self.handle = h
+
+    def sync(self):
+        _check(load_library().hf_sync(self.handle), "hf_sync")
+
+    def close(self):
+        if self.handle:
+            load_library().hf_destroy(self.handle)
+            self.handle = None
+
+
+_ctxs: dict = {}
+_ws: dict = {}
+
+
+def _require_cuda(t: torch.Tensor, name: str):
+    if not torch.cuda.is_available():
+        raise RuntimeError("libhf needs a ROCm GPU; none is visible")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def context(device=None, stream=None) -> Context:
+    dev = torch.cuda.current_device() if device is None else torch.device("cuda", device).index
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    key = (dev, st.cuda_stream)
+    ctx = _ctxs.get(key)
+    if ctx is None:
+        with torch.cuda.device(dev):
+            ctx = Context(dev, st)
+        _ctxs[key] = ctx
+    return ctx
+
+
+def workspace(nbytes: int, device: int) -> torch.Tensor:
+    """A reusable device workspace of at least nbytes (one per device)."""
+    cur = _ws.get(device)
+    if cur is None or cur.numel() < nbytes:
+        cur = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=torch.device("cuda", device))
+        _ws[device] = cur
+    return cur
+
+
+def box(n: int, box_len: float, frac_bits: int = 15) -> Box:
+    return Box(int(n), int(frac_bits), float(box_len))
+
+
+def workspace_size(n: int, box_len: float, np_: int, stages: int, frac_bits: int = 15) -> int:
+    out = ctypes.c_size_t()
+    b = box(n, box_len, frac_bits)
+    _check(load_library().hf_workspace_size(ctypes.byref(b), int(np_), int(stages), ctypes.byref(out)),
+           "hf_workspace_size")
+    return out.value
+
+
+def _dtype_code(pos: torch.Tensor) -> int:
+    if pos.dtype == torch.float32:
+        return HF_F32
+    if pos.dtype == torch.float64:
+        return HF_F64
+    raise ValueError("positions must be float32 or float64")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+# ---------------------------------------------------------------------------
+# stages
+# ---------------------------------------------------------------------------
+def deposit(pos: torch.Tensor, box_len: float, n: int, frac_bits: int = 15, out=None, ctx=None) -> torch.Tensor:
+    """Step 2: CIC deposit -> int64 grid [n, n, n] (units of 2^-3B particle)."""
+    _require_cuda(pos, "pos")
+    if pos.ndim != 2 or pos.shape[1] != 3:
+        raise ValueError("pos must be [np, 3]")
+    ctx = ctx or context(pos.device.index)
+    if out is None:
+        out = torch.empty((n, n, n), dtype=torch.int64, device=pos.device)
+    b = box(n, box_len, frac_bits)
+    need = workspace_size(n, box_len, pos.shape[0], STAGE_DEPOSIT, frac_bits)
+    ws = workspace(need, pos.device.index) if need else None
+    _check(load_library().hf_deposit(ctx.handle, ctypes.byref(b), _ptr(pos), _dtype_code(pos), pos.shape[0],
+                                     _ptr(out), _ptr(ws), need), "hf_deposit")
+    return out
+
+
+def cwt(rho: torch.Tensor, box_len: float, kw: float, kernel: str = "sampled", out=None, ctx=None,
+        frac_bits: int = 15) -> torch.Tensor:
+    """Step 3: grid CWT (FP32) of an int64 CIC grid at scale k_w."""
+    _require_cuda(rho, "rho")
+    if rho.dtype != torch.int64 or rho.ndim != 3:
+        raise ValueError("rho must be an int64 [n, n, n] grid")
+    n = rho.shape[0]
+    ctx = ctx or context(rho.device.index)
+    if out is None:
+        out = torch.empty((n, n, n), dtype=torch.float32, device=rho.device)
+    b = box(n, box_len, frac_bits)
+    need = workspace_size(n, box_len, 0, STAGE_CWT, frac_bits)
+    ws = workspace(need, rho.device.index)
+    _check(load_library().hf_cwt(ctx.handle, ctypes.byref(b), _ptr(rho), float(kw), KERNELS[kernel], _ptr(out),
+                                 _ptr(ws), need), "hf_cwt")
+    return out
+
+
+def maxima(c: torch.Tensor, tau: float = 0.0, capacity: int | None = None, ctx=None, sync: bool = True):
+    """Step 4: sorted int32 linear indices of the local maxima above tau.
+
+    With sync=True the list is trimmed to the count (one stream sync);
+    otherwise (buffer, device_count) is returned."""
+    _require_cuda(c, "cwt")
+    if c.dtype != torch.float32 or c.ndim != 3:
+        raise ValueError("cwt must be a float32 [n, n, n] grid")
+    n = c.shape[0]
+    ctx = ctx or context(c.device.index)
+    if capacity is None:
+        capacity = ((n + 1) // 2) ** 3  # two maxima are never neighbours
+    buf = torch.empty(max(int(capacity), 1), dtype=torch.int32, device=c.device)
+    cnt = torch.empty(1, dtype=torch.int64, device=c.device)
+    b = box(n, 1.0)
+    need = workspace_size(n, 1.0, 0, STAGE_MAXIMA)
+    ws = workspace(need, c.device.index)
+    _check(load_library().hf_maxima(ctx.handle, ctypes.byref(b), _ptr(c), float(tau), _ptr(buf), int(capacity),
+                                    _ptr(cnt), _ptr(ws), need), "hf_maxima")
+    if not sync:
+        return buf, cnt
+    ctx.sync()
+    return buf[: int(cnt.item())]
+
+
+def segment(c: torch.Tensor, tau: float = 0.0, out=None, ctx=None) -> torch.Tensor:
+    """Step 5: int32 cell labels (root index or -1)."""
+    _require_cuda(c, "cwt")
+    if c.dtype != torch.float32 or c.ndim != 3:
+        raise ValueError("cwt must be a float32 [n, n, n] grid")
+    n = c.shape[0]
+    ctx = ctx or context(c.device.index)
+    if out is None:
+        out = torch.empty((n, n, n), dtype=torch.int32, device=c.device)
+    b = box(n, 1.0)
+    need = workspace_size(n, 1.0, 0, STAGE_SEGMENT)
+    ws = workspace(need, c.device.index)
+    _check(load_library().hf_segment(ctx.handle, ctypes.byref(b), _ptr(c), float(tau), _ptr(out), _ptr(ws), need),
+           "hf_segment")
+    return out
+
+
+def label(pos: torch.Tensor, box_len: float, n: int, cell_label: torch.Tensor, frac_bits: int = 15, out=None,
+          ctx=None) -> torch.Tensor:
+    """Step 6: int32 particle labels from the nearest node's cell label."""
+    _require_cuda(pos, "pos")
+    _require_cuda(cell_label, "cell_label")
+    if cell_label.dtype != torch.int32 or cell_label.numel() != n ** 3:
+        raise ValueError("cell_label must be int32 with n^3 cells")
+    ctx = ctx or context(pos.device.index)
+    if out is None:
+        out = torch.empty(pos.shape[0], dtype=torch.int32, device=pos.device)
+    b = box(n, box_len, frac_bits)
+    _check(load_library().hf_label(ctx.handle, ctypes.byref(b), _ptr(pos), _dtype_code(pos), pos.shape[0],
+                                   _ptr(cell_label), _ptr(out)), "hf_label")
+    return out
+
+
+def sync(device=None):
+    """Wait for the current stream and raise on a device-detected error."""
+    context(device).sync()
+
+
+def find_halos(pos: torch.Tensor, box_len: float, n: int, kw: float, frac_bits: int = 15, tau: float = 0.0,
+               kernel: str = "sampled") -> dict:
+    """Steps 2-6 at one scale, all on the GPU; one sync at the end."""
+    ctx = context(pos.device.index)
+    rho = deposit(pos, box_len, n, frac_bits, ctx=ctx)
+    c = cwt(rho, box_len, kw, kernel, ctx=ctx, frac_bits=frac_bits)
+    mx, cnt = maxima(c, tau, ctx=ctx, sync=False)
+    cell = segment(c, tau, ctx=ctx)
+    part = label(pos, box_len, n, cell, frac_bits, ctx=ctx)
+    ctx.sync()
+    return {"rho": rho, "cwt": c, "maxima": mx[: int(cnt.item())], "cell_label": cell, "particle_label": part}

@@ -1,0 +1,86 @@
+"""Host-only checks of the C ABI: the library loads, exports every function that
+include/hf.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2501_10622_amd as hfm
+from paper_2501_10622_amd import hf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(hf.LIB_PATH):
+        from paper_2501_10622_amd import build
+        build.build(verbose=False)
+    return hf.load_library()
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "hf.h")).read()
+    return sorted(set(re.findall(r"\b(hf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = _declared()
+    assert set(declared) == set(hf.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code in range(8):
+        assert lib.hf_status_str(code)
+    assert b"overflow" in lib.hf_status_str(hf.HF_ERR_OVERFLOW).lower()
+
+
+@pytest.mark.parametrize("n,ok", [(8, True), (12, True), (96, True), (1024, True), (6, False), (10, False),
+                                  (9, False), (2048, False), (100, False), (1536, False)])
+def test_supported_sizes(lib, n, ok):
+    out = ctypes.c_size_t()
+    b = hf.Box(n, 15, 10.0)
+    code = lib.hf_workspace_size(ctypes.byref(b), 0, hf.STAGE_CWT, ctypes.byref(out))
+    assert (code == hf.HF_OK) == ok
+    if not ok:
+        assert code == hf.HF_ERR_SIZE
+
+
+def test_frac_bits_and_box_checks(lib):
+    out = ctypes.c_size_t()
+    for bits, code in ((7, hf.HF_ERR_SIZE), (8, hf.HF_OK), (20, hf.HF_OK), (21, hf.HF_ERR_SIZE)):
+        b = hf.Box(16, bits, 10.0)
+        assert lib.hf_workspace_size(ctypes.byref(b), 0, hf.STAGE_DEPOSIT, ctypes.byref(out)) == code
+    for L in (0.0, -1.0, float("nan"), float("inf")):
+        b = hf.Box(16, 15, L)
+        assert lib.hf_workspace_size(ctypes.byref(b), 0, hf.STAGE_DEPOSIT, ctypes.byref(out)) == hf.HF_ERR_ARG
+    b = hf.Box(16, 15, 10.0)
+    assert lib.hf_workspace_size(ctypes.byref(b), -1, hf.STAGE_DEPOSIT, ctypes.byref(out)) == hf.HF_ERR_ARG
+    assert lib.hf_workspace_size(ctypes.byref(b), 0, 64, ctypes.byref(out)) == hf.HF_ERR_ARG
+
+
+def test_workspace_grows_with_n(lib):
+    sizes = [hfm.workspace_size(n, 10.0, 0, hf.STAGE_CWT | hf.STAGE_MAXIMA | hf.STAGE_SEGMENT)
+             for n in (8, 64, 256)]
+    assert sizes == sorted(sizes) and sizes[0] > 0
+    # the half spectrum dominates: n * n * (n/2 + 1) complex64
+    assert sizes[-1] >= 256 * 256 * 129 * 8
+
+
+def test_null_context_rejected_before_any_device_call(lib):
+    b = hf.Box(16, 15, 10.0)
+    vp = ctypes.c_void_p
+    assert lib.hf_deposit(None, ctypes.byref(b), vp(0), 0, 0, vp(0), vp(0), 0) == hf.HF_ERR_ARG
+    assert lib.hf_cwt(None, ctypes.byref(b), vp(0), 0.1, 0, vp(0), vp(0), 0) == hf.HF_ERR_ARG
+    assert lib.hf_maxima(None, ctypes.byref(b), vp(0), 0.0, vp(0), 0, vp(0), vp(0), 0) == hf.HF_ERR_ARG
+    assert lib.hf_segment(None, ctypes.byref(b), vp(0), 0.0, vp(0), vp(0), 0) == hf.HF_ERR_ARG
+    assert lib.hf_label(None, ctypes.byref(b), vp(0), 0, 0, vp(0), vp(0)) == hf.HF_ERR_ARG
+    assert lib.hf_sync(None) == hf.HF_ERR_ARG
+    assert lib.hf_destroy(None) == hf.HF_ERR_ARG
+
+
+def test_create_out_pointer_checked(lib):
+    assert lib.hf_create(0, None, None) == hf.HF_ERR_ARG
