@@ -1,0 +1,244 @@
+#!/usr/bin/env python
+"""Benchmark: the single-scale CWT halo path (deposit -> CWT -> maxima ->
+segmentation -> labels) on one MI355X.
+
+One step is one pass of the whole path over one synthetic box that is already
+resident in HBM.  Default workload: L = 1000 Mpc/h, 1024^3 grid, 1024^3 FP32
+particles (60% in 1.2M NFW halos, 40% uniform, random order), wavelet scale
+a = 2 cells (k_w = 0.512), sampled kernel.
+
+Prints ONE JSON line with particles/s, the end-to-end fraction of the HBM
+roofline for the model bytes, the dominant kernel's roofline (live HIP-event
+timing from the library's kernel timer), and the FP64 oracle timed on a bounded
+sample of the same recipe on the host cores.
+
+  python bench.py [--steps K] [--warmup W] [--config M4] [--no-cpu-baseline]
+  python bench.py --copy-calibration    # plain copy kernel for HBM counter scaling
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_bytes(n: int, np_: int, pos_bytes: int) -> dict:
+    """Algorithmic (compulsory) HBM bytes per launch of each kernel.
+
+    Stage totals: deposit 12 B/particle (FP32) + 8 B/cell; CWT 8 + 4.01 (x fwd)
+    + 3 x 8.02 (y, z*mul*z^-1, y^-1) + 4.01 + 4 (x inv) = 44.06 B/cell; maxima
+    4 B/cell; segmentation 8 B/cell; labels 20 B/particle.  Launches that only
+    exist because of how a stage is implemented (tables, reductions, scans,
+    pointer-jumping rounds) carry no algorithmic bytes.
+    """
+    cells = n ** 3
+    half = n * n * (n // 2 + 1) * 8  # complex64 half spectrum
+    return {
+        "zero_grid": 8 * cells,
+        "deposit": pos_bytes * 3 * np_,
+        "fft_x_fwd": 8 * cells + half,
+        "fft_y_fwd": 2 * half,
+        "fft_z_mul": 2 * half,
+        "fft_y_inv": 2 * half,
+        "fft_x_inv": half + 4 * cells,
+        "maxima_mark": 4 * cells,
+        "parent": 8 * cells,
+        "label": (pos_bytes * 3 + 4 + 4) * np_,
+    }
+
+
+def copy_calibration():
+    """A plain device copy of 4 GiB, for scaling FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    nbytes = 4 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(5):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / 5
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "ms": ms,
+                      "GBps": 2 * nbytes / ms / 1e6}))
+
+
+def cpu_baseline(seed: int) -> dict:
+    """The FP64 oracle on a bounded sample of the same recipe: a 192^3 grid box
+    with the same cell size, particle density, halo density and scale in cells."""
+    import numpy as np
+    from oracle import cwthf as O
+    import synth
+    n, L = 192, 187.5
+    np_ = n ** 3
+    halos = int(round(1.2e-3 * L ** 3))
+    kw = n / (1000.0 * 2.0)
+    pos = synth.make_box(L, np_, halos, "f32", seed).numpy()
+    t = {}
+    t0 = time.perf_counter()
+    rho = O.deposit(pos, L, n)
+    t["deposit"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    c = O.cwt(rho, L, kw).astype(np.float32)
+    t["cwt"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.maxima(c)
+    t["maxima"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    cell = O.segment(c)
+    t["segment"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.label(pos, L, n, cell)
+    t["label"] = time.perf_counter() - t0
+    total = sum(t.values())
+    return {"value": np_ / total, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": f"same recipe at n=192, L=187.5 Mpc/h, {np_} FP32 particles, {halos} halos, a=2 cells; "
+                      f"numpy single-threaded; host os.cpu_count()={os.cpu_count()}",
+            "stage_s": {k: round(v, 3) for k, v in t.items()}, "total_s": round(total, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="M4", choices=["M1", "M2", "M3", "M4"])
+    ap.add_argument("--kernel", default="sampled", choices=["sampled", "analytic"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(jobs and boxes are sharded one per GPU by the caller).", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import torch
+    import paper_2501_10622_amd as hfm
+    import synth
+
+    if not os.path.exists(hfm.LIB_PATH):
+        from paper_2501_10622_amd import build as _b
+        _b.build(verbose=False)
+    cfg = synth.CONFIGS[args.config]
+    n, L = cfg.n, cfg.box_len
+    kw = cfg.kw_list[0]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log(f"generating {args.config}: n={n} np={cfg.n_particles} on the GPU")
+    t0 = time.perf_counter()
+    pos = synth.make_config_box(cfg, device=dev)
+    torch.cuda.synchronize()
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+
+    ctx = hfm.context(0)
+    rho = torch.empty((n, n, n), dtype=torch.int64, device=dev)
+    cwt = torch.empty((n, n, n), dtype=torch.float32, device=dev)
+    cell = torch.empty((n, n, n), dtype=torch.int32, device=dev)
+    part = torch.empty(cfg.n_particles, dtype=torch.int32, device=dev)
+
+    def step():
+        hfm.deposit(pos, L, n, out=rho, ctx=ctx)
+        hfm.cwt(rho, L, kw, args.kernel, out=cwt, ctx=ctx)
+        mx = hfm.maxima(cwt, 0.0, ctx=ctx, sync=False)
+        hfm.segment(cwt, 0.0, out=cell, ctx=ctx)
+        hfm.label(pos, L, n, cell, out=part, ctx=ctx)
+        return mx
+
+    for i in range(args.warmup):
+        step()
+        ctx.sync()
+        log(f"warmup {i + 1}/{args.warmup} done")
+
+    ctx.profile(True)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    start.record()
+    for i in range(args.steps):
+        mx = step()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ctx.sync()
+    ms_step = start.elapsed_time(stop) / args.steps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f})")
+
+    # properties that hold at any size: exact mass, labelled roots are the maxima
+    lo = int((rho & 0xFFFFFFFF).sum().item())
+    hi = int((rho >> 32).sum().item())
+    mass_ok = (hi << 32) + lo == cfg.n_particles << (3 * 15)
+    buf, cnt = mx
+    nmax = int(cnt.item())
+    roots_ok = bool((cell.view(-1)[buf[:nmax].long()] == buf[:nmax]).all().item()) if nmax else True
+
+    pos_bytes = 4 if cfg.dtype == "f32" else 8
+    kb = kernel_bytes(n, cfg.n_particles, pos_bytes)
+    kernels = {}
+    for name, (ms, launches) in prof.items():
+        if launches == 0:
+            continue
+        per_launch = ms / launches
+        ab = kb.get(name, 0)
+        kernels[name] = {"ms_per_step": round(ms / args.steps, 4), "launches_per_step": launches // args.steps,
+                         "avg_ms": round(per_launch, 4),
+                         "GBps": round(ab / per_launch / 1e6, 1) if ab else None}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    dom_avg = kernels[dom]["avg_ms"]
+    dom_bytes = kb.get(dom, 0)
+    achieved = dom_bytes / dom_avg / 1e6 if dom_bytes else 0.0
+    model_bytes = sum(kb.values())
+    e2e_gbs = model_bytes / ms_step / 1e6
+    cells = n ** 3
+    out = {
+        "metric": "particles/s end-to-end (deposit+CWT+maxima+segmentation+labels) and % of HBM roofline",
+        "value": cfg.n_particles / (ms_step / 1e3),
+        "unit": "particles/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.config}: periodic box L={L:g} Mpc/h, {n}^3 grid, {cfg.n_particles} "
+                               f"{'FP32' if pos_bytes == 4 else 'FP64'} particles, {cfg.n_halos} NFW halos (60%) + "
+                               f"uniform, random order, one scale a=2 cells (k_w={kw:g}), {args.kernel} kernel",
+                   "grid": n, "particles": cfg.n_particles, "kw": kw, "kernel": args.kernel, "seed": cfg.seed},
+        "cells_per_s": cells / (ms_step / 1e3),
+        "e2e_model_bytes": model_bytes,
+        "e2e_hbm_roofline_frac": round(e2e_gbs / HBM_PEAK_GBS, 4),
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "bytes_per_launch": dom_bytes, "avg_ms": dom_avg, "traffic": None},
+        "kernels": kernels,
+        "checks": {"mass_exact": mass_ok, "labelled_roots_are_maxima": roots_ok, "maxima": nmax},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(cfg.seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

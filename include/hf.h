@@ -138,6 +138,16 @@ hf_status hf_segment(hf_ctx *ctx, const hf_box *box, const float *cwt, float tau
 hf_status hf_label(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np,
                    const int32_t *cell_label, int32_t *particle_label);
 
+/* Kernel timer (a tracing aid, not part of the method).  When enabled, every
+ * kernel launch made through this context is bracketed by HIP events on its
+ * stream.  hf_profile_read(ctx, i, ...) waits for the stream and returns the
+ * name, accumulated milliseconds and launch count of kernel i, for
+ * i in [0, count); an index past the end returns HF_ERR_ARG.  The name string
+ * is static.  hf_profile_reset zeroes the totals. */
+hf_status hf_profile_enable(hf_ctx *ctx, int enable);
+hf_status hf_profile_reset(hf_ctx *ctx);
+hf_status hf_profile_read(hf_ctx *ctx, int index, const char **name, double *ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,74 @@ __global__ void clear_status_kernel(uint32_t *st) {
 
 }  // namespace
 
+const char *hf::kernel_name(int id) {
+    static const char *names[K_COUNT] = {
+        "zero_grid", "deposit", "label",
+        "deposit_atomic", "deposit_prep", "deposit_l1_hist", "deposit_l1_scatter", "deposit_l2_hist",
+        "deposit_l2_scatter", "deposit_fold",
+        "tables_1", "tables_2", "fft_x_fwd", "mass", "fft_y_fwd", "fft_z_mul", "fft_y_inv", "fft_x_inv",
+        "maxima_mark", "maxima_count", "maxima_scan", "maxima_write",
+        "parent", "jump_flags", "jump", "finalize",
+    };
+    return (id >= 0 && id < K_COUNT) ? names[id] : "?";
+}
+
+hipEvent_t hf::take_event(hf_ctx *c) {
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Resolves recorded event pairs into the per-kernel totals.
+static hf_status flush_profile(hf_ctx *c) {
+    if (c->pending.empty()) return HF_OK;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return HF_ERR_DEVICE;
+    for (const ProfRecord &r : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+            c->ms[r.kid] += ms;
+            c->launches[r.kid] += 1;
+        }
+        c->pool.push_back(r.start);
+        c->pool.push_back(r.stop);
+    }
+    c->pending.clear();
+    return HF_OK;
+}
+
+extern "C" hf_status hf_profile_enable(hf_ctx *ctx, int enable) {
+    if (!ctx) return HF_ERR_ARG;
+    ctx->prof = enable != 0;
+    return HF_OK;
+}
+
+extern "C" hf_status hf_profile_reset(hf_ctx *ctx) {
+    if (!ctx) return HF_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    hf_status s = flush_profile(ctx);
+    for (int i = 0; i < K_COUNT; ++i) {
+        ctx->ms[i] = 0.0;
+        ctx->launches[i] = 0;
+    }
+    return s;
+}
+
+extern "C" hf_status hf_profile_read(hf_ctx *ctx, int index, const char **name, double *ms, int64_t *launches) {
+    if (!ctx || !name || !ms || !launches) return HF_ERR_ARG;
+    if (index < 0 || index >= K_COUNT) return HF_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    hf_status s = flush_profile(ctx);
+    *name = kernel_name(index);
+    *ms = ctx->ms[index];
+    *launches = ctx->launches[index];
+    return s;
+}
+
 extern "C" hf_status hf_create(int device, void *hip_stream, hf_ctx **out) {
     if (!out) return HF_ERR_ARG;
     *out = nullptr;
@@ -45,6 +113,11 @@ extern "C" hf_status hf_destroy(hf_ctx *ctx) {
     if (!ctx) return HF_ERR_ARG;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    for (const ProfRecord &r : ctx->pending) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     (void)hipFree(ctx->d_status);
     (void)hipHostFree(ctx->h_status);
     delete ctx;

@@ -107,7 +107,9 @@ int grid_for(int64_t work, int block, int cap) {
 
 }  // namespace
 
-size_t hf::deposit_ws_bytes(const hf_box &, int64_t) { return 0; }
+size_t hf::deposit_ws_bytes(const hf_box &box, int64_t np) {
+    return deposit_tiled_supported(box, np) ? deposit_tiled_ws_bytes(box, np) : 0;
+}
 
 extern "C" hf_status hf_deposit(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np,
                                 int64_t *rho, void *ws, size_t ws_bytes) {
@@ -118,18 +120,20 @@ extern "C" hf_status hf_deposit(hf_ctx *ctx, const hf_box *box, const void *pos,
     s = check_ws(ws, ws_bytes, deposit_ws_bytes(*box, np));
     if (s != HF_OK) return s;
     if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    if (deposit_tiled_supported(*box, np)) return deposit_tiled(ctx, *box, pos, dtype, np, rho, ws);
+    // direct form for grids the binned path does not cover: zero, then global atomics
     const size_t cells = size_t(box->n) * box->n * box->n;
     auto *grid = reinterpret_cast<unsigned long long *>(rho);
-    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(int64_t(cells), 256, 8192)), dim3(256), 0, ctx->stream, grid,
+    HF_LAUNCH(ctx, K_ZERO_GRID, fill_u64_kernel, dim3(grid_for(int64_t(cells), 256, 8192)), dim3(256), 0, ctx->stream, grid,
                        cells);
     if (np > 0) {
         const int g = grid_for(np, DEP_BLOCK, 65536);
         if (dtype == HF_F32)
-            hipLaunchKernelGGL(deposit_atomic_kernel<float>, dim3(g), dim3(DEP_BLOCK), 0, ctx->stream,
+            HF_LAUNCH(ctx, K_DEP_ATOMIC, deposit_atomic_kernel<float>, dim3(g), dim3(DEP_BLOCK), 0, ctx->stream,
                                static_cast<const float *>(pos), np, make_fixed_point<float>(*box), box->n, grid,
                                ctx->d_status);
         else
-            hipLaunchKernelGGL(deposit_atomic_kernel<double>, dim3(g), dim3(DEP_BLOCK), 0, ctx->stream,
+            HF_LAUNCH(ctx, K_DEP_ATOMIC, deposit_atomic_kernel<double>, dim3(g), dim3(DEP_BLOCK), 0, ctx->stream,
                                static_cast<const double *>(pos), np, make_fixed_point<double>(*box), box->n, grid,
                                ctx->d_status);
     }
@@ -146,11 +150,11 @@ extern "C" hf_status hf_label(hf_ctx *ctx, const hf_box *box, const void *pos, h
     if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
     const int g = grid_for(np, DEP_BLOCK, 65536);
     if (dtype == HF_F32)
-        hipLaunchKernelGGL(label_kernel<float>, dim3(g), dim3(DEP_BLOCK), 0, ctx->stream,
+        HF_LAUNCH(ctx, K_LABEL, label_kernel<float>, dim3(g), dim3(DEP_BLOCK), 0, ctx->stream,
                            static_cast<const float *>(pos), np, make_fixed_point<float>(*box), box->n, cell_label,
                            particle_label, ctx->d_status);
     else
-        hipLaunchKernelGGL(label_kernel<double>, dim3(g), dim3(DEP_BLOCK), 0, ctx->stream,
+        HF_LAUNCH(ctx, K_LABEL, label_kernel<double>, dim3(g), dim3(DEP_BLOCK), 0, ctx->stream,
                            static_cast<const double *>(pos), np, make_fixed_point<double>(*box), box->n, cell_label,
                            particle_label, ctx->d_status);
     return launch_status();

@@ -588,8 +588,8 @@ extern "C" hf_status hf_cwt(hf_ctx *ctx, const hf_box *box, const int64_t *rho, 
     // periodic images within w (I + 1/2) L >= 16, where the wavelet is < 1e-25 of its peak
     ta.images = std::max(1, int(std::ceil(16.0 / (ta.w * box->box_len) - 0.5)));
     const int tb = 256, tg = (n + tb - 1) / tb;
-    hipLaunchKernelGGL(tables_stage1, dim3(tg), dim3(tb), 0, st, ta, tw, gtab, htab);
-    hipLaunchKernelGGL(tables_stage2, dim3(tg), dim3(tb), 0, st, ta, gtab, htab, btab, ptab);
+    HF_LAUNCH(ctx, K_TABLES_1, tables_stage1, dim3(tg), dim3(tb), 0, st, ta, tw, gtab, htab);
+    HF_LAUNCH(ctx, K_TABLES_2, tables_stage2, dim3(tg), dim3(tb), 0, st, ta, gtab, htab, btab, ptab);
 
     const FftPlan pl = make_plan(n);
     const int H = n / 2 + 1;
@@ -608,14 +608,14 @@ extern "C" hf_status hf_cwt(hf_ctx *ctx, const hf_box *box, const int64_t *rho, 
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(yz_shm)) != hipSuccess)
             return HF_ERR_DEVICE;
     }
-    hipLaunchKernelGGL(fft_x_fwd_kernel, dim3(unsigned(L.xblocks)), dim3(x_threads), x_shm, st, rho, spec, pl,
+    HF_LAUNCH(ctx, K_X_FWD, fft_x_fwd_kernel, dim3(unsigned(L.xblocks)), dim3(x_threads), x_shm, st, rho, spec, pl,
                        L.lp_x, tw, mass, ctx->d_status);
-    hipLaunchKernelGGL(mass_kernel, dim3(1), dim3(1024), 0, st, mass, L.xblocks, n, scalars, ctx->d_status);
-    hipLaunchKernelGGL(fft_y_kernel<false>, dim3(tiles, n), dim3(yz_threads), yz_shm, st, spec, pl, tw);
-    hipLaunchKernelGGL(fft_z_mul_kernel, dim3(tiles, n), dim3(yz_threads), yz_shm, st, spec, pl, tw, btab, ptab,
+    HF_LAUNCH(ctx, K_MASS, mass_kernel, dim3(1), dim3(1024), 0, st, mass, L.xblocks, n, scalars, ctx->d_status);
+    HF_LAUNCH(ctx, K_Y_FWD, fft_y_kernel<false>, dim3(tiles, n), dim3(yz_threads), yz_shm, st, spec, pl, tw);
+    HF_LAUNCH(ctx, K_Z_MUL, fft_z_mul_kernel, dim3(tiles, n), dim3(yz_threads), yz_shm, st, spec, pl, tw, btab, ptab,
                        scalars);
-    hipLaunchKernelGGL(fft_y_kernel<true>, dim3(tiles, n), dim3(yz_threads), yz_shm, st, spec, pl, tw);
-    hipLaunchKernelGGL(fft_x_inv_kernel, dim3(unsigned(L.xblocks)), dim3(x_threads), x_shm, st, spec, cwt, pl,
+    HF_LAUNCH(ctx, K_Y_INV, fft_y_kernel<true>, dim3(tiles, n), dim3(yz_threads), yz_shm, st, spec, pl, tw);
+    HF_LAUNCH(ctx, K_X_INV, fft_x_inv_kernel, dim3(unsigned(L.xblocks)), dim3(x_threads), x_shm, st, spec, cwt, pl,
                        L.lp_x, tw);
     return launch_status();
 }

@@ -5,17 +5,76 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "hf.h"
+
+namespace hf {
+
+// Kernels whose launches the optional per-context timer tracks.
+enum KernelId {
+    K_ZERO_GRID, K_DEPOSIT, K_LABEL,
+    K_DEP_ATOMIC, K_DEP_PREP, K_DEP_L1_HIST, K_DEP_L1_SCATTER, K_DEP_L2_HIST, K_DEP_L2_SCATTER, K_DEP_FOLD,
+    K_TABLES_1, K_TABLES_2, K_X_FWD, K_MASS, K_Y_FWD, K_Z_MUL, K_Y_INV, K_X_INV,
+    K_MAX_MARK, K_MAX_COUNT, K_MAX_SCAN, K_MAX_WRITE,
+    K_PARENT, K_FLAGS, K_JUMP, K_FINALIZE,
+    K_COUNT
+};
+const char *kernel_name(int id);
+
+struct ProfRecord {
+    int kid;
+    hipEvent_t start, stop;
+};
+
+}  // namespace hf
 
 struct hf_ctx {
     int device;
     hipStream_t stream;
     uint32_t *d_status;  // device status block: [0] error bit mask
     uint32_t *h_status;  // pinned host mirror
+    // kernel timer (off unless hf_profile_enable): events around every launch
+    bool prof = false;
+    std::vector<hf::ProfRecord> pending;
+    std::vector<hipEvent_t> pool;
+    double ms[hf::K_COUNT] = {};
+    int64_t launches[hf::K_COUNT] = {};
 };
 
 namespace hf {
+
+hipEvent_t take_event(hf_ctx *c);
+
+// Brackets the launches issued in its scope with timing events when the
+// context's timer is on.
+struct ProfScope {
+    hf_ctx *c;
+    int kid;
+    hipEvent_t start = nullptr;
+    ProfScope(hf_ctx *ctx, int id) : c(ctx), kid(id) {
+        if (c->prof) {
+            start = take_event(c);
+            if (start) (void)hipEventRecord(start, c->stream);
+        }
+    }
+    ~ProfScope() {
+        if (c->prof && start) {
+            hipEvent_t stop = take_event(c);
+            if (stop) {
+                (void)hipEventRecord(stop, c->stream);
+                c->pending.push_back({kid, start, stop});
+            }
+        }
+    }
+};
+
+// Launches a kernel on ctx->stream under the context's kernel timer.
+#define HF_LAUNCH(ctx, kid, ...)                 \
+    do {                                         \
+        ::hf::ProfScope hf_prof_scope_(ctx, kid); \
+        hipLaunchKernelGGL(__VA_ARGS__);         \
+    } while (0)
 
 // Device status bits (one per device-detected hf_status code).
 constexpr uint32_t ST_OVERFLOW = 1u << HF_ERR_OVERFLOW;
@@ -53,6 +112,12 @@ inline hf_status check_ws(void *ws, size_t ws_bytes, size_t need) {
 inline hf_status launch_status() {
     return hipGetLastError() == hipSuccess ? HF_OK : HF_ERR_DEVICE;
 }
+
+// Binned deposit (n % 16 == 0, B <= 17, np < 2^32).
+bool deposit_tiled_supported(const hf_box &box, int64_t np);
+size_t deposit_tiled_ws_bytes(const hf_box &box, int64_t np);
+hf_status deposit_tiled(hf_ctx *ctx, const hf_box &box, const void *pos, hf_dtype dtype, int64_t np, int64_t *rho,
+                        void *ws);
 
 // Workspace requirements of each stage (defined next to each stage).
 size_t deposit_ws_bytes(const hf_box &box, int64_t np);

@@ -4,28 +4,250 @@
 // Order on cells: (value, linear index), larger value first, equal values by
 // larger index, -0 equal to +0.  It is encoded as a 64-bit key whose integer
 // order is that order: high word = order-preserving bits of the float, low
-// word = index.
+// word = index.  A cell's parent is the largest key of its 3x3x3 periodic
+// neighbourhood (itself included); a cell is a maximum iff it is its own
+// parent and its value exceeds tau.
+//
+// Tiled path (n % 32 == 0): one workgroup per 32x8x8 tile holds the tile and a
+// one-cell halo of keys in LDS and forms the 3x3x3 maximum separably (x, y, z).
+//  - maxima: a wavefront covers two 32-cell rows, so its ballot is two aligned
+//    32-bit words of a linear-order bit mask; count / scan / write passes turn
+//    the mask into the sorted index list.
+//  - segmentation: parent chains are followed inside the tile by pointer
+//    doubling in LDS, so every cell ends at a root or at the first cell its
+//    chain reaches outside the tile.  Such exit targets are always on a tile
+//    boundary, so only the 968 boundary cells of each tile (kept in a compact
+//    array) take part in the global pointer-jumping rounds; a last pass maps
+//    every cell through them to its root and applies tau.
+// Other sizes use direct per-cell kernels with the same results.
 #include "hf_internal.h"
 
 using namespace hf;
 
 namespace {
 
-constexpr int MAX_BLOCK = 256;
-constexpr int MAX_PER_THREAD = 16;
-constexpr int MAX_CHUNK = MAX_BLOCK * MAX_PER_THREAD;  // cells per maxima workgroup
-
-__device__ __forceinline__ uint64_t cell_key(float c, uint32_t idx, bool &nan) {
+// ------------------------------------------------------------------ keys
+__device__ __forceinline__ uint32_t ordered_bits(float c, bool &nan) {
     uint32_t u = __float_as_uint(c);
     if ((u & 0x7fffffffu) > 0x7f800000u) nan = true;
     if (u == 0x80000000u) u = 0u;  // -0 -> +0
-    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-    return (uint64_t(u) << 32) | idx;
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ uint64_t cell_key(float c, uint32_t idx, bool &nan) {
+    return (uint64_t(ordered_bits(c, nan)) << 32) | idx;
 }
 
 __device__ __forceinline__ uint32_t wrap(int v, int n) { return uint32_t(v < 0 ? v + n : (v >= n ? v - n : v)); }
 
-// Largest key among the 26 neighbours of (x, y, z).
+__device__ __forceinline__ uint64_t kmax(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+uint32_t host_ordered_bits(float c) {
+    uint32_t u;
+    static_assert(sizeof(u) == sizeof(c), "float is 32-bit");
+    __builtin_memcpy(&u, &c, sizeof(u));
+    if (u == 0x80000000u) u = 0u;
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// ------------------------------------------------------------------ tile geometry
+constexpr int TX = 32, TY = 8, TZ = 8;
+constexpr int TCELLS = TX * TY * TZ;                          // 2048
+constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+constexpr int HCELLS = HX * HY * HZ;                          // 3400
+constexpr int NBND = 2 * TX * TY + (TZ - 2) * (2 * TX + 2 * (TY - 2));  // 968 boundary cells per tile
+constexpr int SEG_THREADS = 256;
+constexpr int PER_THREAD = TCELLS / SEG_THREADS;              // 8
+
+struct TileGrid {
+    int n;
+    int ntx, nty, ntz;  // tiles per axis
+};
+
+// Rank of local cell (x, y, z) among its tile's boundary cells, or -1.
+// Order: plane z = 0, planes 1..6 (row y = 0, then x = 0 / x = 31 of rows
+// 1..6, then row y = 7), plane z = 7.
+__device__ __forceinline__ int bnd_rank(int x, int y, int z) {
+    if (z == 0) return y * TX + x;
+    constexpr int MID = 2 * TX + 2 * (TY - 2);  // 76
+    if (z == TZ - 1) return TX * TY + (TZ - 2) * MID + y * TX + x;
+    const int base = TX * TY + (z - 1) * MID;
+    if (y == 0) return base + x;
+    if (y == TY - 1) return base + TX + 2 * (TY - 2) + x;
+    if (x == 0) return base + TX + 2 * (y - 1);
+    if (x == TX - 1) return base + TX + 2 * (y - 1) + 1;
+    return -1;
+}
+
+// Where the compact boundary array keeps cell g, or -1 if g is interior.
+__device__ __forceinline__ int64_t bnd_slot(const TileGrid &tg, int32_t g) {
+    const uint32_t n = uint32_t(tg.n);
+    const uint32_t x = uint32_t(g) % n, y = (uint32_t(g) / n) % n, z = uint32_t(g) / (n * n);
+    const int r = bnd_rank(int(x % TX), int(y % TY), int(z % TZ));
+    if (r < 0) return -1;
+    const int64_t tile = (int64_t(z / TZ) * tg.nty + y / TY) * tg.ntx + x / TX;
+    return tile * NBND + r;
+}
+
+// Loads the keys of the tile at (x0, y0, z0) plus a one-cell periodic halo and
+// leaves the parent key of local cell e = x + TX (y + TY z) in M[e].
+__device__ void tile_parent_keys(const float *__restrict__ c, int n, int x0, int y0, int z0, uint64_t *K,
+                                 uint64_t *M, bool &nan) {
+    for (int e = threadIdx.x; e < HCELLS; e += SEG_THREADS) {
+        const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
+        const uint32_t gx = wrap(x0 + hx - 1, n), gy = wrap(y0 + hy - 1, n), gz = wrap(z0 + hz - 1, n);
+        const uint32_t j = (gz * uint32_t(n) + gy) * uint32_t(n) + gx;
+        K[e] = cell_key(c[j], j, nan);
+    }
+    __syncthreads();
+    // x: M[hz][hy][x] over HZ x HY x TX
+    for (int e = threadIdx.x; e < TX * HY * HZ; e += SEG_THREADS) {
+        const int x = e % TX, r = e / TX;  // r = hz * HY + hy
+        const uint64_t *k = K + r * HX + x;
+        M[e] = kmax(kmax(k[0], k[1]), k[2]);
+    }
+    __syncthreads();
+    // y: K[hz][y][x] over HZ x TY x TX
+    for (int e = threadIdx.x; e < TX * TY * HZ; e += SEG_THREADS) {
+        const int x = e % TX, y = (e / TX) % TY, hz = e / (TX * TY);
+        const uint64_t *m = M + (hz * HY + y) * TX + x;
+        K[e] = kmax(kmax(m[0], m[TX]), m[2 * TX]);
+    }
+    __syncthreads();
+    // z: M[z][y][x] over TZ x TY x TX
+    for (int e = threadIdx.x; e < TCELLS; e += SEG_THREADS) {
+        const uint64_t *k = K + e;
+        M[e] = kmax(kmax(k[0], k[TX * TY]), k[2 * TX * TY]);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void tile_origin(const TileGrid &tg, int t, int &x0, int &y0, int &z0) {
+    x0 = (t % tg.ntx) * TX;
+    y0 = ((t / tg.ntx) % tg.nty) * TY;
+    z0 = (t / (tg.ntx * tg.nty)) * TZ;
+}
+
+// Maxima bit mask: bit (j % 32) of word j / 32 is set iff cell j is a maximum.
+__global__ void __launch_bounds__(SEG_THREADS) max_tile_kernel(const float *__restrict__ c, TileGrid tg,
+                                                               uint32_t tau_ord, uint32_t *__restrict__ mask,
+                                                               uint32_t *status) {
+    __shared__ uint64_t K[HCELLS];
+    __shared__ uint64_t M[TX * HY * HZ];
+    int x0, y0, z0;
+    tile_origin(tg, blockIdx.x, x0, y0, z0);
+    bool nan = false;
+    tile_parent_keys(c, tg.n, x0, y0, z0, K, M, nan);
+    const uint32_t n = uint32_t(tg.n);
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; ++i) {
+        const int e = i * SEG_THREADS + threadIdx.x;  // a wavefront covers rows (y, z) and (y + 1, z)
+        const int x = e % TX, y = (e / TX) % TY, z = e / (TX * TY);
+        const uint32_t g = ((uint32_t(z0 + z) * n) + uint32_t(y0 + y)) * n + uint32_t(x0 + x);
+        const uint64_t p = M[e];
+        const bool is_max = uint32_t(p) == g && uint32_t(p >> 32) > tau_ord;
+        const unsigned long long bits = __ballot(is_max);
+        if ((threadIdx.x & 63) == 0) {
+            mask[g >> 5] = uint32_t(bits);
+            mask[(g + n) >> 5] = uint32_t(bits >> 32);  // next row of the tile
+        }
+    }
+    if (nan) atomicOr(status, ST_INPUT);
+}
+
+// Parents resolved inside the tile.  ptr[g] = the root or the exit target of
+// cell g's chain; bnd[] holds the same for the tile's boundary cells.
+__global__ void __launch_bounds__(SEG_THREADS) seg_tile_kernel(const float *__restrict__ c, TileGrid tg,
+                                                               int32_t *__restrict__ ptr, int32_t *__restrict__ bnd,
+                                                               uint32_t *status) {
+    __shared__ uint64_t K[HCELLS];
+    __shared__ uint64_t M[TX * HY * HZ];
+    int x0, y0, z0;
+    tile_origin(tg, blockIdx.x, x0, y0, z0);
+    bool nan = false;
+    tile_parent_keys(c, tg.n, x0, y0, z0, K, M, nan);
+    const uint32_t n = uint32_t(tg.n);
+    // loc[e] >= 0: pointer to local cell loc[e];  loc[e] < 0: resolved to global -loc[e] - 1
+    int32_t *loc = reinterpret_cast<int32_t *>(K);
+    for (int e = threadIdx.x; e < TCELLS; e += SEG_THREADS) {
+        const int x = e % TX, y = (e / TX) % TY, z = e / (TX * TY);
+        const uint32_t g = ((uint32_t(z0 + z) * n) + uint32_t(y0 + y)) * n + uint32_t(x0 + x);
+        const uint32_t p = uint32_t(M[e]);
+        int32_t v = -int32_t(p) - 1;
+        if (p != g) {
+            const int px = int(p % n), py = int((p / n) % n), pz = int(p / (n * n));
+            const int lx = px - x0, ly = py - y0, lz = pz - z0;
+            if (lx >= 0 && lx < TX && ly >= 0 && ly < TY && lz >= 0 && lz < TZ) v = lx + TX * (ly + TY * lz);
+        }
+        loc[e] = v;
+    }
+    __syncthreads();
+    // pointer doubling inside the tile (chains are at most TCELLS - 1 long)
+    bool open = true;
+    while (open) {
+        int32_t nv[PER_THREAD];
+        bool any = false;
+#pragma unroll
+        for (int i = 0; i < PER_THREAD; ++i) {
+            const int32_t v = loc[i * SEG_THREADS + threadIdx.x];
+            nv[i] = v >= 0 ? loc[v] : v;
+            any |= nv[i] >= 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PER_THREAD; ++i) loc[i * SEG_THREADS + threadIdx.x] = nv[i];
+        open = __syncthreads_or(any);
+    }
+    const int64_t tile = blockIdx.x;
+    for (int e = threadIdx.x; e < TCELLS; e += SEG_THREADS) {
+        const int x = e % TX, y = (e / TX) % TY, z = e / (TX * TY);
+        const uint32_t g = ((uint32_t(z0 + z) * n) + uint32_t(y0 + y)) * n + uint32_t(x0 + x);
+        const int32_t t = -loc[e] - 1;
+        ptr[g] = t;
+        const int r = bnd_rank(x, y, z);
+        if (r >= 0) bnd[tile * NBND + r] = t;
+    }
+    if (nan) atomicOr(status, ST_INPUT);
+}
+
+__global__ void fill_flags_kernel(uint32_t *flags, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) flags[i] = (i == 0) ? 1u : 0u;
+}
+
+// One pointer-jumping round over the boundary cells, in place.  Round r runs
+// only if round r - 1 changed something, so a fixed number of launches is enough.
+__global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd, int64_t count, TileGrid tg,
+                                                       uint32_t *flags, int round) {
+    if (flags[round] == 0u) return;
+    bool changed = false;
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < count; k += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t p = bnd[k];
+        const int64_t s = bnd_slot(tg, p);
+        if (s < 0) continue;  // an interior target is a root
+        const int32_t q = bnd[s];
+        if (q != p) {
+            bnd[k] = q;
+            changed = true;
+        }
+    }
+    if (__any(changed) && (threadIdx.x & 63) == 0) flags[round + 1] = 1u;
+}
+
+__global__ void __launch_bounds__(256) seg_finalize_kernel(const int32_t *__restrict__ ptr,
+                                                           const int32_t *__restrict__ bnd,
+                                                           const float *__restrict__ c, TileGrid tg, float tau,
+                                                           int32_t *__restrict__ label) {
+    const int64_t cells = int64_t(tg.n) * tg.n * tg.n;
+    for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < cells; j += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t t = ptr[j];
+        const int64_t s = bnd_slot(tg, t);
+        const int32_t r = s < 0 ? t : bnd[s];
+        label[j] = c[r] > tau ? r : -1;
+    }
+}
+
+// ------------------------------------------------------------------ direct path (n % 32 != 0)
 __device__ __forceinline__ uint64_t neighbour_max(const float *__restrict__ c, int n, int x, int y, int z,
                                                   bool &nan) {
     uint64_t best = 0;
@@ -40,52 +262,92 @@ __device__ __forceinline__ uint64_t neighbour_max(const float *__restrict__ c, i
             for (int dx = -1; dx <= 1; ++dx) {
                 if (dz == 0 && dy == 0 && dx == 0) continue;
                 const uint32_t j = row + wrap(x + dx, n);
-                const uint64_t k = cell_key(c[j], j, nan);
-                best = k > best ? k : best;
+                best = kmax(best, cell_key(c[j], j, nan));
             }
         }
     }
     return best;
 }
 
-// Pass 1: is-maximum bit mask (one 64-bit word per 64 consecutive cells) and
-// the number of maxima in each workgroup's chunk of MAX_CHUNK cells.
-__global__ void __launch_bounds__(MAX_BLOCK) maxima_mark_kernel(const float *__restrict__ c, int n, float tau,
-                                                                unsigned long long *__restrict__ mask,
-                                                                uint32_t *__restrict__ counts, uint32_t *status) {
+__global__ void __launch_bounds__(256) max_direct_kernel(const float *__restrict__ c, int n, float tau,
+                                                         uint32_t *__restrict__ mask, uint32_t *status) {
     const uint32_t cells = uint32_t(n) * n * n;
-    const uint32_t base = blockIdx.x * MAX_CHUNK;
+    const uint32_t words = (cells + 31) / 32;
     bool nan = false;
-    uint32_t cnt = 0;
-#pragma unroll 1
-    for (int i = 0; i < MAX_PER_THREAD; ++i) {
-        const uint32_t j = base + i * MAX_BLOCK + threadIdx.x;
+    // one wavefront per 64 consecutive cells: two mask words
+    for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < cells;
+         base += gridDim.x * blockDim.x) {
+        const uint32_t j = base + (threadIdx.x & 63u);
         bool is_max = false;
         if (j < cells) {
-            const int x = int(j % uint32_t(n)), y = int((j / uint32_t(n)) % uint32_t(n)), z = int(j / (uint32_t(n) * n));
+            const int x = int(j % uint32_t(n)), y = int((j / uint32_t(n)) % uint32_t(n)),
+                      z = int(j / (uint32_t(n) * n));
             const float v = c[j];
-            const uint64_t me = cell_key(v, j, nan);
-            is_max = (v > tau) && me > neighbour_max(c, n, x, y, z, nan);
+            is_max = (v > tau) && cell_key(v, j, nan) > neighbour_max(c, n, x, y, z, nan);
         }
         const unsigned long long bits = __ballot(is_max);
-        if ((threadIdx.x & 63) == 0 && base + i * MAX_BLOCK + threadIdx.x < cells) mask[(j >> 6)] = bits;
-        cnt += __popcll(bits);
-    }
-    __shared__ uint32_t red[MAX_BLOCK / 64];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = 0;
-        for (int w = 0; w < MAX_BLOCK / 64; ++w) t += red[w];
-        counts[blockIdx.x] = t;
+        if ((threadIdx.x & 63) == 0) {
+            mask[base >> 5] = uint32_t(bits);
+            if ((base >> 5) + 1 < words) mask[(base >> 5) + 1] = uint32_t(bits >> 32);
+        }
     }
     if (nan) atomicOr(status, ST_INPUT);
 }
 
-// Pass 2: exclusive scan of the chunk counts (one workgroup, fixed order).
-__global__ void __launch_bounds__(1024) maxima_scan_kernel(const uint32_t *__restrict__ counts, int nchunks,
-                                                           uint32_t *__restrict__ offsets, int64_t cap,
-                                                           int64_t *d_count, uint32_t *status) {
+__global__ void __launch_bounds__(256) parent_direct_kernel(const float *__restrict__ c, int n,
+                                                            int32_t *__restrict__ parent, uint32_t *status) {
+    const uint32_t cells = uint32_t(n) * n * n;
+    bool nan = false;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cells; j += gridDim.x * blockDim.x) {
+        const int x = int(j % uint32_t(n)), y = int((j / uint32_t(n)) % uint32_t(n)), z = int(j / (uint32_t(n) * n));
+        const uint64_t me = cell_key(c[j], j, nan);
+        const uint64_t nb = neighbour_max(c, n, x, y, z, nan);
+        parent[j] = int32_t(uint32_t(kmax(nb, me)));
+    }
+    if (nan) atomicOr(status, ST_INPUT);
+}
+
+__global__ void __launch_bounds__(256) jump_direct_kernel(int32_t *__restrict__ ptr, uint32_t cells, uint32_t *flags,
+                                                          int round) {
+    if (flags[round] == 0u) return;
+    bool changed = false;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cells; j += gridDim.x * blockDim.x) {
+        const int32_t p = ptr[j];
+        const int32_t pp = ptr[p];
+        if (pp != p) {
+            ptr[j] = pp;
+            changed = true;
+        }
+    }
+    if (__any(changed) && (threadIdx.x & 63) == 0) flags[round + 1] = 1u;
+}
+
+__global__ void __launch_bounds__(256) finalize_direct_kernel(int32_t *__restrict__ ptr, const float *__restrict__ c,
+                                                              uint32_t cells, float tau) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cells; j += gridDim.x * blockDim.x) {
+        const int32_t r = ptr[j];
+        ptr[j] = c[r] > tau ? r : -1;
+    }
+}
+
+// ------------------------------------------------------------------ mask -> sorted list
+constexpr int LIST_CHUNK_WORDS = 128;  // 4096 cells per chunk
+
+__global__ void __launch_bounds__(LIST_CHUNK_WORDS) mask_count_kernel(const uint32_t *__restrict__ mask,
+                                                                      int64_t words, uint32_t *__restrict__ counts) {
+    const int64_t w = int64_t(blockIdx.x) * LIST_CHUNK_WORDS + threadIdx.x;
+    uint32_t v = w < words ? uint32_t(__popc(mask[w])) : 0u;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    __shared__ uint32_t red[LIST_CHUNK_WORDS / 64];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) counts[blockIdx.x] = red[0] + red[1];
+}
+
+// Exclusive scan of the chunk counts (one workgroup, fixed order).
+__global__ void __launch_bounds__(1024) list_scan_kernel(const uint32_t *__restrict__ counts, int nchunks,
+                                                         uint32_t *__restrict__ offsets, int64_t cap,
+                                                         int64_t *d_count, uint32_t *status) {
     __shared__ uint64_t part[1024];
     const int t = threadIdx.x;
     const int per = (nchunks + 1023) / 1024;
@@ -112,97 +374,59 @@ __global__ void __launch_bounds__(1024) maxima_scan_kernel(const uint32_t *__res
     }
 }
 
-// Pass 3: write each chunk's maxima at its offset, in index order.
-__global__ void __launch_bounds__(MAX_BLOCK) maxima_write_kernel(int n, const unsigned long long *__restrict__ mask,
-                                                                 const uint32_t *__restrict__ offsets, int64_t cap,
-                                                                 int32_t *__restrict__ out) {
-    const uint32_t cells = uint32_t(n) * n * n;
-    const uint32_t base = blockIdx.x * MAX_CHUNK;
-    const uint32_t words = (min(cells - base, uint32_t(MAX_CHUNK)) + 63) / 64;
-    __shared__ uint32_t pre[MAX_CHUNK / 64 + 1];
+__global__ void __launch_bounds__(LIST_CHUNK_WORDS) list_write_kernel(const uint32_t *__restrict__ mask,
+                                                                      int64_t words,
+                                                                      const uint32_t *__restrict__ offsets,
+                                                                      int64_t cap, int32_t *__restrict__ out) {
+    __shared__ uint32_t pre[LIST_CHUNK_WORDS];
+    const int64_t w = int64_t(blockIdx.x) * LIST_CHUNK_WORDS + threadIdx.x;
+    const uint32_t bits0 = w < words ? mask[w] : 0u;
+    pre[threadIdx.x] = uint32_t(__popc(bits0));
+    __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t r = 0;
-        for (uint32_t w = 0; w < words; ++w) {
-            pre[w] = r;
-            r += __popcll(mask[(base >> 6) + w]);
+        for (int i = 0; i < LIST_CHUNK_WORDS; ++i) {
+            const uint32_t v = pre[i];
+            pre[i] = r;
+            r += v;
         }
     }
     __syncthreads();
-    const uint32_t off0 = offsets[blockIdx.x];
-    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) {
-        unsigned long long bits = mask[(base >> 6) + w];
-        uint32_t r = off0 + pre[w];
-        while (bits) {
-            const int b = __ffsll(bits) - 1;
-            bits &= bits - 1;
-            if (int64_t(r) < cap) out[r] = int32_t(base + w * 64 + b);
-            ++r;
-        }
+    uint32_t bits = bits0;
+    uint32_t r = offsets[blockIdx.x] + pre[threadIdx.x];
+    while (bits) {
+        const int b = __ffs(bits) - 1;
+        bits &= bits - 1;
+        if (int64_t(r) < cap) out[r] = int32_t(w * 32 + b);
+        ++r;
     }
 }
 
-// Segmentation pass 1: parent = largest of self and the 26 neighbours.
-__global__ void __launch_bounds__(256) parent_kernel(const float *__restrict__ c, int n,
-                                                     int32_t *__restrict__ parent, uint32_t *status) {
-    const uint32_t cells = uint32_t(n) * n * n;
-    bool nan = false;
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cells; j += gridDim.x * blockDim.x) {
-        const int x = int(j % uint32_t(n)), y = int((j / uint32_t(n)) % uint32_t(n)), z = int(j / (uint32_t(n) * n));
-        const uint64_t me = cell_key(c[j], j, nan);
-        const uint64_t nb = neighbour_max(c, n, x, y, z, nan);
-        parent[j] = int32_t(uint32_t((nb > me ? nb : me) & 0xffffffffu));
-    }
-    if (nan) atomicOr(status, ST_INPUT);
-}
+// ------------------------------------------------------------------ host side
+bool tiled(int n) { return n % TX == 0; }  // TY = TZ = 8 divide every multiple of 32
 
-__global__ void fill_flags_kernel(uint32_t *flags, int count) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) flags[i] = (i == 0) ? 1u : 0u;
-}
+TileGrid tile_grid(int n) { return TileGrid{n, n / TX, n / TY, n / TZ}; }
 
-// One pointer-jumping round, in place: p <- p[p].  Round r runs only if round
-// r-1 changed something (flags[r] set), so a fixed number of launches suffices.
-__global__ void __launch_bounds__(256) jump_kernel(int32_t *__restrict__ ptr, uint32_t cells, uint32_t *flags,
-                                                   int round) {
-    if (flags[round] == 0u) return;
-    bool changed = false;
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cells; j += gridDim.x * blockDim.x) {
-        const int32_t p = ptr[j];
-        const int32_t pp = ptr[p];
-        if (pp != p) {
-            ptr[j] = pp;
-            changed = true;
-        }
-    }
-    if (__any(changed) && (threadIdx.x & 63) == 0) flags[round + 1] = 1u;
-}
-
-__global__ void __launch_bounds__(256) finalize_kernel(int32_t *__restrict__ ptr, const float *__restrict__ c,
-                                                       uint32_t cells, float tau) {
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cells; j += gridDim.x * blockDim.x) {
-        const int32_t r = ptr[j];
-        ptr[j] = c[r] > tau ? r : -1;
-    }
-}
-
-int rounds_for(uint32_t cells) {
+int rounds_for(uint64_t count) {
     int k = 0;
-    while ((uint64_t(1) << k) < cells) ++k;
-    return k + 1;  // ceil(log2(longest path)) rounds, plus one that sees no change
+    while ((uint64_t(1) << k) < count) ++k;
+    return k + 1;  // ceil(log2(longest chain)) rounds, plus one that sees no change
 }
 
 struct MaximaLayout {
     size_t mask, counts, offsets, total;
+    int64_t words;
     int nchunks;
 };
 
 MaximaLayout maxima_layout(int n) {
     MaximaLayout L{};
     const size_t cells = size_t(n) * n * n;
-    L.nchunks = int((cells + MAX_CHUNK - 1) / MAX_CHUNK);
+    L.words = int64_t((cells + 31) / 32);
+    L.nchunks = int((L.words + LIST_CHUNK_WORDS - 1) / LIST_CHUNK_WORDS);
     size_t off = 0;
     L.mask = off;
-    off = align_up(off + sizeof(unsigned long long) * ((cells + 63) / 64 + MAX_CHUNK / 64));
+    off = align_up(off + sizeof(uint32_t) * size_t(L.words + 2));
     L.counts = off;
     off = align_up(off + sizeof(uint32_t) * L.nchunks);
     L.offsets = off;
@@ -211,8 +435,36 @@ MaximaLayout maxima_layout(int n) {
     return L;
 }
 
-int stride_grid(uint32_t cells) {
-    uint32_t g = (cells + 255) / 256;
+struct SegmentLayout {
+    size_t flags, ptr, bnd, total;
+    int rounds;
+    int64_t nbnd;
+};
+
+SegmentLayout segment_layout(int n) {
+    SegmentLayout L{};
+    const uint64_t cells = uint64_t(n) * n * n;
+    size_t off = 0;
+    L.flags = off;
+    if (tiled(n)) {
+        const TileGrid tg = tile_grid(n);
+        L.nbnd = int64_t(tg.ntx) * tg.nty * tg.ntz * NBND;
+        L.rounds = rounds_for(uint64_t(L.nbnd));
+        off = align_up(off + sizeof(uint32_t) * (L.rounds + 2));
+        L.ptr = off;
+        off = align_up(off + sizeof(int32_t) * cells);
+        L.bnd = off;
+        off = align_up(off + sizeof(int32_t) * size_t(L.nbnd));
+    } else {
+        L.rounds = rounds_for(cells);
+        off = align_up(off + sizeof(uint32_t) * (L.rounds + 2));
+    }
+    L.total = off;
+    return L;
+}
+
+int stride_grid(int64_t work) {
+    int64_t g = (work + 255) / 256;
     return int(g > 4096 ? 4096 : (g < 1 ? 1 : g));
 }
 
@@ -220,10 +472,7 @@ int stride_grid(uint32_t cells) {
 
 size_t hf::maxima_ws_bytes(const hf_box &box) { return maxima_layout(box.n).total; }
 
-size_t hf::segment_ws_bytes(const hf_box &box) {
-    const uint32_t cells = uint32_t(box.n) * box.n * box.n;
-    return align_up(sizeof(uint32_t) * (rounds_for(cells) + 2));
-}
+size_t hf::segment_ws_bytes(const hf_box &box) { return segment_layout(box.n).total; }
 
 extern "C" hf_status hf_maxima(hf_ctx *ctx, const hf_box *box, const float *cwt, float tau, int32_t *max_idx,
                                int64_t max_cap, int64_t *d_count, void *ws, size_t ws_bytes) {
@@ -236,15 +485,25 @@ extern "C" hf_status hf_maxima(hf_ctx *ctx, const hf_box *box, const float *cwt,
     if (s != HF_OK) return s;
     if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
     char *w8 = static_cast<char *>(ws);
-    auto *mask = reinterpret_cast<unsigned long long *>(w8 + L.mask);
+    auto *mask = reinterpret_cast<uint32_t *>(w8 + L.mask);
     auto *counts = reinterpret_cast<uint32_t *>(w8 + L.counts);
     auto *offsets = reinterpret_cast<uint32_t *>(w8 + L.offsets);
-    hipLaunchKernelGGL(maxima_mark_kernel, dim3(L.nchunks), dim3(MAX_BLOCK), 0, ctx->stream, cwt, box->n, tau, mask,
-                       counts, ctx->d_status);
-    hipLaunchKernelGGL(maxima_scan_kernel, dim3(1), dim3(1024), 0, ctx->stream, counts, L.nchunks, offsets, max_cap,
-                       d_count, ctx->d_status);
-    hipLaunchKernelGGL(maxima_write_kernel, dim3(L.nchunks), dim3(MAX_BLOCK), 0, ctx->stream, box->n, mask, offsets,
-                       max_cap, max_idx);
+    const int n = box->n;
+    if (tiled(n)) {
+        const TileGrid tg = tile_grid(n);
+        HF_LAUNCH(ctx, K_MAX_MARK, max_tile_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(SEG_THREADS), 0,
+                  ctx->stream, cwt, tg, host_ordered_bits(tau), mask, ctx->d_status);
+    } else {
+        const int64_t cells = int64_t(n) * n * n;
+        HF_LAUNCH(ctx, K_MAX_MARK, max_direct_kernel, dim3(stride_grid(cells)), dim3(256), 0, ctx->stream, cwt, n,
+                  tau, mask, ctx->d_status);
+    }
+    HF_LAUNCH(ctx, K_MAX_COUNT, mask_count_kernel, dim3(L.nchunks), dim3(LIST_CHUNK_WORDS), 0, ctx->stream, mask,
+              L.words, counts);
+    HF_LAUNCH(ctx, K_MAX_SCAN, list_scan_kernel, dim3(1), dim3(1024), 0, ctx->stream, counts, L.nchunks, offsets,
+              max_cap, d_count, ctx->d_status);
+    HF_LAUNCH(ctx, K_MAX_WRITE, list_write_kernel, dim3(L.nchunks), dim3(LIST_CHUNK_WORDS), 0, ctx->stream, mask,
+              L.words, offsets, max_cap, max_idx);
     return launch_status();
 }
 
@@ -254,18 +513,36 @@ extern "C" hf_status hf_segment(hf_ctx *ctx, const hf_box *box, const float *cwt
     if (tau != tau) return HF_ERR_ARG;
     hf_status s = check_box(box);
     if (s != HF_OK) return s;
-    s = check_ws(ws, ws_bytes, segment_ws_bytes(*box));
+    const SegmentLayout L = segment_layout(box->n);
+    s = check_ws(ws, ws_bytes, L.total);
     if (s != HF_OK) return s;
     if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
-    const uint32_t cells = uint32_t(box->n) * box->n * box->n;
-    const int rounds = rounds_for(cells);
-    auto *flags = static_cast<uint32_t *>(ws);
-    const int g = stride_grid(cells);
-    hipLaunchKernelGGL(fill_flags_kernel, dim3((rounds + 2 + 255) / 256), dim3(256), 0, ctx->stream, flags,
-                       rounds + 2);
-    hipLaunchKernelGGL(parent_kernel, dim3(g), dim3(256), 0, ctx->stream, cwt, box->n, cell_label, ctx->d_status);
-    for (int r = 0; r < rounds; ++r)
-        hipLaunchKernelGGL(jump_kernel, dim3(g), dim3(256), 0, ctx->stream, cell_label, cells, flags, r);
-    hipLaunchKernelGGL(finalize_kernel, dim3(g), dim3(256), 0, ctx->stream, cell_label, cwt, cells, tau);
+    char *w8 = static_cast<char *>(ws);
+    auto *flags = reinterpret_cast<uint32_t *>(w8 + L.flags);
+    const int n = box->n;
+    HF_LAUNCH(ctx, K_FLAGS, fill_flags_kernel, dim3((L.rounds + 2 + 255) / 256), dim3(256), 0, ctx->stream, flags,
+              L.rounds + 2);
+    if (tiled(n)) {
+        const TileGrid tg = tile_grid(n);
+        auto *ptr = reinterpret_cast<int32_t *>(w8 + L.ptr);
+        auto *bnd = reinterpret_cast<int32_t *>(w8 + L.bnd);
+        HF_LAUNCH(ctx, K_PARENT, seg_tile_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(SEG_THREADS), 0, ctx->stream,
+                  cwt, tg, ptr, bnd, ctx->d_status);
+        const int g = stride_grid(L.nbnd);
+        for (int r = 0; r < L.rounds; ++r)
+            HF_LAUNCH(ctx, K_JUMP, bnd_jump_kernel, dim3(g), dim3(256), 0, ctx->stream, bnd, L.nbnd, tg, flags, r);
+        const int64_t cells = int64_t(n) * n * n;
+        HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel, dim3(stride_grid(cells)), dim3(256), 0, ctx->stream, ptr, bnd,
+                  cwt, tg, tau, cell_label);
+    } else {
+        const uint32_t cells = uint32_t(n) * n * n;
+        const int g = stride_grid(cells);
+        HF_LAUNCH(ctx, K_PARENT, parent_direct_kernel, dim3(g), dim3(256), 0, ctx->stream, cwt, n, cell_label,
+                  ctx->d_status);
+        for (int r = 0; r < L.rounds; ++r)
+            HF_LAUNCH(ctx, K_JUMP, jump_direct_kernel, dim3(g), dim3(256), 0, ctx->stream, cell_label, cells, flags, r);
+        HF_LAUNCH(ctx, K_FINALIZE, finalize_direct_kernel, dim3(g), dim3(256), 0, ctx->stream, cell_label, cwt, cells,
+                  tau);
+    }
     return launch_status();
 }

@@ -22,7 +22,8 @@ KERNELS = {"sampled": 0, "analytic": 1}
 STAGE_DEPOSIT, STAGE_CWT, STAGE_MAXIMA, STAGE_SEGMENT = 1, 2, 4, 8
 
 EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_size",
-           "hf_deposit", "hf_cwt", "hf_maxima", "hf_segment", "hf_label")
+           "hf_deposit", "hf_cwt", "hf_maxima", "hf_segment", "hf_label",
+           "hf_profile_enable", "hf_profile_reset", "hf_profile_read")
 
 
 class HFError(RuntimeError):
@@ -63,6 +64,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "hf_maxima": (ctypes.c_int, [vp, bp, vp, flt, vp, i64, vp, vp, sz]),
             "hf_segment": (ctypes.c_int, [vp, bp, vp, flt, vp, vp, sz]),
             "hf_label": (ctypes.c_int, [vp, bp, vp, ctypes.c_int, i64, vp, vp]),
+            "hf_profile_enable": (ctypes.c_int, [vp, ctypes.c_int]),
+            "hf_profile_reset": (ctypes.c_int, [vp]),
+            "hf_profile_read": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -100,6 +105,28 @@ class Context:
 
     def sync(self):
         _check(load_library().hf_sync(self.handle), "hf_sync")
+
+    def profile(self, enable: bool = True):
+        """Turn the library's per-kernel event timer on or off."""
+        _check(load_library().hf_profile_enable(self.handle, int(bool(enable))), "hf_profile_enable")
+
+    def profile_reset(self):
+        _check(load_library().hf_profile_reset(self.handle), "hf_profile_reset")
+
+    def profile_read(self) -> dict:
+        """{kernel name: (total ms, launches)} accumulated since the last reset."""
+        lib = load_library()
+        out = {}
+        i = 0
+        while True:
+            name, ms, cnt = ctypes.c_char_p(), ctypes.c_double(), ctypes.c_int64()
+            code = lib.hf_profile_read(self.handle, i, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(cnt))
+            if code == HF_ERR_ARG:
+                break
+            _check(code, "hf_profile_read")
+            out[name.value.decode()] = (ms.value, cnt.value)
+            i += 1
+        return out
 
     def close(self):
         if self.handle:

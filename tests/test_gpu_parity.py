@@ -35,6 +35,12 @@ def hfm():
     (64, 100.0, 64 ** 3, 200, "f64", 15, 1),   # the 64^3 FP64 configuration
     (96, 96.0, 300000, 100, "f32", 16, 4),
     (128, 50.0, 500000, 300, "f32", 8, 5),
+    # two-level binned path (more than one coarse bucket)
+    (144, 144.0, 300000, 200, "f64", 15, 6),      # 27 buckets of 3^3 tiles
+    (192, 190.0, 2000000, 3000, "f32", 17, 7),
+    (256, 250.0, 256 ** 3, 20000, "f32", 15, 2),   # the 256^3 FP32 configuration
+    (512, 500.0, 3000000, 5000, "f32", 15, 8),
+    (432, 432.0, 400000, 100, "f32", 15, 9),        # 729 coarse buckets: direct atomic path
 ])
 def test_deposit_bit_exact(n, L, np_, halos, dtype, bits, seed):
     pos = small_box(n, L, np_, halos, dtype, seed)
@@ -255,3 +261,18 @@ def test_end_to_end_deterministic():
     b = hfm().find_halos(pos, 60.0, 48, 0.024)
     for k in ("rho", "cwt", "maxima", "cell_label", "particle_label"):
         assert torch.equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("n", [32, 64, 96, 160 // 5 * 3])
+def test_segment_long_chains_single_basin(n):
+    # one periodic bowl: every cell climbs to a single root across many tiles
+    g = np.arange(n)
+    d = lambda c0: ((g - c0 + n // 2) % n - n // 2).astype(np.float64)
+    r2 = d(5)[:, None, None] ** 2 + d(n - 3)[None, :, None] ** 2 + d(n // 2)[None, None, :] ** 2
+    c32 = (1000.0 - r2).astype(np.float32)
+    print(f"bowl n={n}", flush=True)
+    cell = hfm().segment(cuda(c32), 0.0)
+    mx = hfm().maxima(cuda(c32), 0.0)
+    hfm().sync()
+    np.testing.assert_array_equal(mx.cpu().numpy(), O.maxima(c32, 0.0))
+    np.testing.assert_array_equal(cell.cpu().numpy(), O.segment(c32, 0.0))
