@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(DEP_BLOCK) deposit_atomic_kernel(const T *__re
     bool overflow = false, bad = false;
     int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < np; i += stride) {
-        int64_t qx, qy, qz;
+        uint32_t qx, qy, qz;
         bool ok = fp.q(pos[3 * i + 0], qx);
         ok = fp.q(pos[3 * i + 1], qy) && ok;
         ok = fp.q(pos[3 * i + 2], qz) && ok;
@@ -40,8 +40,9 @@ __global__ void __launch_bounds__(DEP_BLOCK) deposit_atomic_kernel(const T *__re
             bad = true;
             continue;
         }
-        const uint32_t cx = uint32_t(qx >> fp.bits), cy = uint32_t(qy >> fp.bits), cz = uint32_t(qz >> fp.bits);
-        const uint64_t fx = uint64_t(qx & (one - 1)), fy = uint64_t(qy & (one - 1)), fz = uint64_t(qz & (one - 1));
+        const uint32_t cx = qx >> fp.bits, cy = qy >> fp.bits, cz = qz >> fp.bits;
+        const uint64_t fx = uint64_t(qx) & uint64_t(one - 1), fy = uint64_t(qy) & uint64_t(one - 1),
+                       fz = uint64_t(qz) & uint64_t(one - 1);
         const uint64_t wx[2] = {uint64_t(one) - fx, fx};
         const uint64_t wy[2] = {uint64_t(one) - fy, fy};
         const uint64_t wz[2] = {uint64_t(one) - fz, fz};
@@ -66,36 +67,50 @@ template <typename T>
 __global__ void __launch_bounds__(DEP_BLOCK) label_kernel(const T *__restrict__ pos, int64_t np, FixedPoint<T> fp,
                                                           int n, const int32_t *__restrict__ cell_label,
                                                           int32_t *__restrict__ out, uint32_t *status) {
-    const int64_t half = int64_t(1) << (fp.bits - 1);
+    const uint32_t half = 1u << (fp.bits - 1);
     bool bad = false;
-    int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < np; i += stride) {
-        int64_t qx, qy, qz;
-        bool ok = fp.q(pos[3 * i + 0], qx);
-        ok = fp.q(pos[3 * i + 1], qy) && ok;
-        ok = fp.q(pos[3 * i + 2], qz) && ok;
-        if (!ok) {
-            bad = true;
-            out[i] = -1;
-            continue;
+    constexpr int B = 4;  // particles per thread whose loads are issued together
+    const int64_t step = int64_t(gridDim.x) * blockDim.x * B;
+    for (int64_t i0 = blockIdx.x * int64_t(blockDim.x) * B + threadIdx.x; i0 < np; i0 += step) {
+        T px[B], py[B], pz[B];
+        int32_t lab[B];
+        uint32_t cell[B];
+        bool ok[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int64_t i = i0 + k * int64_t(blockDim.x);
+            if (i < np) {
+                px[k] = pos[3 * i + 0];
+                py[k] = pos[3 * i + 1];
+                pz[k] = pos[3 * i + 2];
+            }
         }
-        uint32_t x = uint32_t((qx + half) >> fp.bits), y = uint32_t((qy + half) >> fp.bits),
-                 z = uint32_t((qz + half) >> fp.bits);
-        if (x == uint32_t(n)) x = 0;
-        if (y == uint32_t(n)) y = 0;
-        if (z == uint32_t(n)) z = 0;
-        out[i] = cell_label[(z * uint32_t(n) + y) * uint32_t(n) + x];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int64_t i = i0 + k * int64_t(blockDim.x);
+            uint32_t qx = 0, qy = 0, qz = 0;
+            ok[k] = false;
+            if (i < np) {
+                ok[k] = fp.q(px[k], qx);
+                ok[k] = fp.q(py[k], qy) && ok[k];
+                ok[k] = fp.q(pz[k], qz) && ok[k];
+                bad |= !ok[k];
+            }
+            uint32_t x = (qx + half) >> fp.bits, y = (qy + half) >> fp.bits, z = (qz + half) >> fp.bits;
+            if (x == uint32_t(n)) x = 0;
+            if (y == uint32_t(n)) y = 0;
+            if (z == uint32_t(n)) z = 0;
+            cell[k] = (z * uint32_t(n) + y) * uint32_t(n) + x;
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) lab[k] = ok[k] ? cell_label[cell[k]] : -1;
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int64_t i = i0 + k * int64_t(blockDim.x);
+            if (i < np) out[i] = lab[k];
+        }
     }
     if (bad) atomicOr(status, ST_INPUT);
-}
-
-template <typename T>
-FixedPoint<T> make_fixed_point(const hf_box &box) {
-    FixedPoint<T> fp;
-    fp.bits = box.frac_bits;
-    fp.period = int64_t(box.n) << box.frac_bits;
-    fp.scale = T(double(box.n) * double(int64_t(1) << box.frac_bits) / box.box_len);
-    return fp;
 }
 
 int grid_for(int64_t work, int block, int cap) {
@@ -148,7 +163,7 @@ extern "C" hf_status hf_label(hf_ctx *ctx, const hf_box *box, const void *pos, h
     if (s != HF_OK) return s;
     if (np == 0) return HF_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
-    const int g = grid_for(np, DEP_BLOCK, 65536);
+    const int g = grid_for((np + 3) / 4, DEP_BLOCK, 65536);
     if (dtype == HF_F32)
         HF_LAUNCH(ctx, K_LABEL, label_kernel<float>, dim3(g), dim3(DEP_BLOCK), 0, ctx->stream,
                            static_cast<const float *>(pos), np, make_fixed_point<float>(*box), box->n, cell_label,

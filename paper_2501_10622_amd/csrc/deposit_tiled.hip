@@ -1,17 +1,18 @@
-// Step 2 (Eq. (1)), binned form of the CIC deposit for grids with n % 16 == 0.
+// Step 2 (Eq. (1)), binned form of the CIC deposit.
 //
 // Particles arrive in arbitrary order, so depositing straight into an n^3 grid
 // of int64 means random read-modify-writes of whole HBM lines.  Instead:
 //
-//   L1  partition the particles by coarse bucket (<= 512 buckets of bt^3
-//       tiles), records = the three fixed-point coordinates q (12 bytes);
-//   L2  partition each bucket by 16^3-cell tile, records = cell-in-tile and
-//       fraction bits packed into 8 bytes;
+//   L1  partition the particles by coarse bucket (<= 512 buckets of tiles),
+//       records = the three fixed-point coordinates q (12 bytes);
+//   L2  partition each bucket by tile (TX x 8 x 8 cells, TX = 64, 32 or 16),
+//       records = cell-in-tile and fraction bits packed into 8 bytes;
 //   ACC one workgroup per tile accumulates its particles' eight CIC weights in
-//       LDS int64 over the tile plus its +x/+y/+z skirt (17^3 cells), writes
-//       the 16^3 owned cells once and the 817 skirt sums to a side buffer;
+//       LDS int64 over the tile plus its +x/+y/+z skirt ((TX+1) x 9 x 9 cells),
+//       writes the owned cells once and the skirt sums to a side buffer;
 //   FOLD each tile adds the skirt sums of its lower neighbours to its low faces.
 //
+// Tiles are long in x so that the fold's face accesses are mostly whole rows.
 // Each partition pass is a histogram pass plus a scatter pass whose writes are
 // staged in LDS so that each workgroup writes one contiguous run per bucket.
 // Every sum is an exact integer sum, so the grid does not depend on particle
@@ -22,29 +23,33 @@ using namespace hf;
 
 namespace {
 
-constexpr int TILE = 16;
-constexpr int ACC_EDGE = TILE + 1;
-constexpr int ACC_CELLS = ACC_EDGE * ACC_EDGE * ACC_EDGE;              // 4913
-constexpr int FACE_X = ACC_EDGE * ACC_EDGE;                             // cells (16, y, z), y,z <= 16
-constexpr int FACE_Y = TILE * ACC_EDGE;                                 // cells (x, 16, z), x < 16, z <= 16
-constexpr int FACE_Z = TILE * TILE;                                     // cells (x, y, 16), x, y < 16
-constexpr int SKIRT = FACE_X + FACE_Y + FACE_Z;                         // 817
-constexpr int PART_THREADS = 1024;
+constexpr int TYZ = 8;               // tile extent in y and z
+constexpr int AYZ = TYZ + 1;          // accumulator extent in y and z (tile + skirt)
+constexpr int MAX_TX = 64;            // tile extent in x: 64, 32 or 16
+constexpr int MAX_ACC_CELLS = (MAX_TX + 1) * AYZ * AYZ;
+constexpr int PART_THREADS = 512;
 constexpr int PART_PER = 8;
-constexpr int CHUNK = PART_THREADS * PART_PER;                          // particles per partition workgroup
+constexpr int CHUNK = PART_THREADS * PART_PER;                          // particles per scatter workgroup
+constexpr int HIST_CHUNKS = 16;                                         // scatter chunks per histogram workgroup
+constexpr int HCHUNK = CHUNK * HIST_CHUNKS;
+constexpr int REPLICAS = 64;   // level-1 counters are replicated to spread atomic traffic
 constexpr int MAX_DIGITS = 512;
 constexpr int ACC_THREADS = 256;
 
 struct Geom {
-    int n;        // grid cells per axis
-    int nt;       // tiles per axis
-    int bt;       // tiles per bucket edge
-    int nb;       // buckets per axis
-    int bcell;    // cells per bucket edge
-    int nbuckets; // nb^3
-    int digits;   // bt^3 tiles per bucket
-    int ntiles;   // nt^3
-    int bits;     // fraction bits B
+    int n;              // grid cells per axis
+    int tx;             // tile extent in x (y and z: TYZ); a power of two
+    int ltx;            // log2(tx)
+    int ntx, nty, ntz;  // tiles per axis
+    int btx, bty, btz;  // tiles per bucket along each axis
+    int nbx, nby, nbz;  // buckets per axis
+    int nbuckets;       // nbx * nby * nbz
+    int digits;         // btx * bty * btz tiles per bucket
+    int ntiles;         // ntx * nty * ntz
+    int skirt;          // skirt cells per tile: 81 + 17 tx
+    int bits;           // fraction bits B
+    FastDiv cbx, cby, cbz;  // cells per bucket along x, y, z
+    FastDiv tbx, tby, tbz;  // tiles per bucket along x, y, z
 };
 
 struct Q3 {
@@ -52,52 +57,87 @@ struct Q3 {
 };
 
 __device__ __forceinline__ int bucket_of(const Geom &g, uint32_t cx, uint32_t cy, uint32_t cz) {
-    const uint32_t bc = uint32_t(g.bcell);
-    return int(((cz / bc) * g.nb + cy / bc) * g.nb + cx / bc);
+    return int((g.cbz.div(cz) * g.nby + g.cby.div(cy)) * g.nbx + g.cbx.div(cx));
 }
 
 __device__ __forceinline__ int tile_in_bucket(const Geom &g, uint32_t cx, uint32_t cy, uint32_t cz) {
-    const uint32_t bt = uint32_t(g.bt);
-    return int((((cz / TILE) % bt) * bt + (cy / TILE) % bt) * bt + (cx / TILE) % bt);
+    const uint32_t ux = g.tbx.mod(cx >> g.ltx), uy = g.tby.mod(cy >> 3), uz = g.tbz.mod(cz >> 3);
+    return int((uz * g.bty + uy) * g.btx + ux);
 }
 
-// Packed tile-local record: per axis ((cell % 16) << B) | fraction, 4 + B bits.
+// Packed tile-local record: x field ((cell_x % tx) << B) | frac (6 + B bits),
+// y and z fields ((cell % 8) << B) | frac (3 + B bits); 12 + 3B <= 63 bits.
 __device__ __forceinline__ uint64_t pack_local(const Geom &g, const Q3 &q) {
     const uint32_t fm = (1u << g.bits) - 1u;
-    const int s = 4 + g.bits;
-    const uint64_t lx = (uint64_t(((q.x >> g.bits) & 15u)) << g.bits) | (q.x & fm);
-    const uint64_t ly = (uint64_t(((q.y >> g.bits) & 15u)) << g.bits) | (q.y & fm);
-    const uint64_t lz = (uint64_t(((q.z >> g.bits) & 15u)) << g.bits) | (q.z & fm);
-    return lx | (ly << s) | (lz << (2 * s));
+    const int sx = 6 + g.bits, sy = 3 + g.bits;
+    const uint64_t lx = (uint64_t((q.x >> g.bits) & uint32_t(g.tx - 1)) << g.bits) | (q.x & fm);
+    const uint64_t ly = (uint64_t((q.y >> g.bits) & (TYZ - 1)) << g.bits) | (q.y & fm);
+    const uint64_t lz = (uint64_t((q.z >> g.bits) & (TYZ - 1)) << g.bits) | (q.z & fm);
+    return lx | (ly << sx) | (lz << (sx + sy));
+}
+
+constexpr int LBATCH = 8;  // loads per thread issued together in the streaming passes
+
+// q of particles i0 + k * stride (k < LBATCH) below end; all loads are issued
+// before any conversion so they are in flight together.  valid[k] is false for
+// indices past the end and for positions the deposit rejects (bad set).
+template <typename T>
+__device__ __forceinline__ void load_q_batch(const T *__restrict__ pos, int64_t i0, int64_t stride, int64_t end,
+                                             const FixedPoint<T> &fp, Q3 (&q)[LBATCH], bool (&valid)[LBATCH],
+                                             bool &bad) {
+    T x[LBATCH], y[LBATCH], z[LBATCH];
+#pragma unroll
+    for (int k = 0; k < LBATCH; ++k) {
+        const int64_t i = i0 + k * stride;
+        if (i < end) {
+            x[k] = pos[3 * i + 0];
+            y[k] = pos[3 * i + 1];
+            z[k] = pos[3 * i + 2];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < LBATCH; ++k) {
+        valid[k] = false;
+        if (i0 + k * stride < end) {
+            bool ok = fp.q(x[k], q[k].x);
+            ok = fp.q(y[k], q[k].y) && ok;
+            ok = fp.q(z[k], q[k].z) && ok;
+            valid[k] = ok;
+            bad |= !ok;
+        }
+    }
 }
 
 template <typename T>
 __device__ __forceinline__ bool load_q(const T *__restrict__ pos, int64_t i, const FixedPoint<T> &fp, Q3 &q) {
-    int64_t a, b, c;
-    bool ok = fp.q(pos[3 * i + 0], a);
-    ok = fp.q(pos[3 * i + 1], b) && ok;
-    ok = fp.q(pos[3 * i + 2], c) && ok;
-    q.x = uint32_t(a);
-    q.y = uint32_t(b);
-    q.z = uint32_t(c);
+    bool ok = fp.q(pos[3 * i + 0], q.x);
+    ok = fp.q(pos[3 * i + 1], q.y) && ok;
+    ok = fp.q(pos[3 * i + 2], q.z) && ok;
     return ok;
 }
 
-// In-place exclusive scan of s[0..count) (count <= 512) by the whole workgroup;
-// returns the total.  Hillis-Steele on a copy in `tmp`.
+// In-place exclusive scan of s[0..count) (count <= 512) by the whole workgroup
+// (at least 512 threads); returns the total.  Each wavefront scans 64 entries
+// with shuffles, then the wavefront totals are scanned; tmp holds 8 partials.
 __device__ uint32_t block_exclusive_scan(uint32_t *s, uint32_t *tmp, int count) {
-    const int t = threadIdx.x;
-    if (t < MAX_DIGITS) tmp[t] = t < count ? s[t] : 0u;
-    __syncthreads();
-    for (int off = 1; off < MAX_DIGITS; off <<= 1) {
-        uint32_t v = 0;
-        if (t < MAX_DIGITS && t >= off) v = tmp[t - off];
-        __syncthreads();
-        if (t < MAX_DIGITS) tmp[t] += v;
-        __syncthreads();
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t x = (t < count) ? s[t] : 0u;
+    uint32_t inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
     }
-    const uint32_t total = tmp[MAX_DIGITS - 1];
-    if (t < count) s[t] = tmp[t] - s[t];
+    if (t < MAX_DIGITS && lane == 63) tmp[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < MAX_DIGITS / 64; ++w) {
+        const uint32_t v = tmp[w];
+        before += w < wave ? v : 0u;
+        total += v;
+    }
+    if (t < count) s[t] = before + inc - x;
     __syncthreads();
     return total;
 }
@@ -116,45 +156,55 @@ __global__ void __launch_bounds__(PART_THREADS) l1_hist_kernel(const T *__restri
     for (int b = threadIdx.x; b < MAX_DIGITS; b += blockDim.x) h[b] = 0u;
     __syncthreads();
     bool bad = false;
-    const int64_t base = int64_t(blockIdx.x) * CHUNK;
+    const int64_t base = int64_t(blockIdx.x) * HCHUNK;
+    const int64_t end = base + HCHUNK < np ? base + HCHUNK : np;
+    for (int64_t i0 = base + threadIdx.x; i0 < end; i0 += PART_THREADS * LBATCH) {
+        Q3 q[LBATCH];
+        bool ok[LBATCH];
+        load_q_batch(pos, i0, PART_THREADS, end, fp, q, ok, bad);
 #pragma unroll
-    for (int k = 0; k < PART_PER; ++k) {
-        const int64_t i = base + k * PART_THREADS + threadIdx.x;
-        if (i < np) {
-            Q3 q;
-            if (load_q(pos, i, fp, q))
-                atomicAdd(&h[bucket_of(g, q.x >> g.bits, q.y >> g.bits, q.z >> g.bits)], 1u);
-            else
-                bad = true;
-        }
+        for (int k = 0; k < LBATCH; ++k)
+            if (ok[k]) atomicAdd(&h[bucket_of(g, q[k].x >> g.bits, q[k].y >> g.bits, q[k].z >> g.bits)], 1u);
     }
     __syncthreads();
+    uint32_t *mine = count1 + (blockIdx.x % REPLICAS) * MAX_DIGITS;
     for (int b = threadIdx.x; b < g.nbuckets; b += blockDim.x)
-        if (h[b]) atomicAdd(&count1[b], h[b]);
+        if (h[b]) atomicAdd(&mine[b], h[b]);
     if (bad) atomicOr(status, ST_INPUT);
 }
 
-// start1 / cursor1 = exclusive scan of the bucket counts; chunk_first = exclusive
-// scan of the number of CHUNK-sized level-2 chunks per bucket.
+// start1 = exclusive scan of the bucket totals; cursor1[r][b] = where replica r's
+// share of bucket b starts; chunk_first / hchunk_first = exclusive scans of the
+// number of level-2 scatter / histogram chunks per bucket.
 __global__ void __launch_bounds__(MAX_DIGITS) l1_scan_kernel(const uint32_t *__restrict__ count1, int nbuckets,
                                                              uint32_t *start1, uint32_t *cursor1,
-                                                             uint32_t *chunk_first) {
-    __shared__ uint32_t s[MAX_DIGITS], c[MAX_DIGITS], tmp[MAX_DIGITS];
+                                                             uint32_t *chunk_first, uint32_t *hchunk_first) {
+    __shared__ uint32_t s[MAX_DIGITS], c[MAX_DIGITS], hc[MAX_DIGITS], tmp[MAX_DIGITS];
     const int t = threadIdx.x;
-    const uint32_t cnt = t < nbuckets ? count1[t] : 0u;
+    uint32_t cnt = 0;
+    if (t < nbuckets)
+        for (int r = 0; r < REPLICAS; ++r) cnt += count1[r * MAX_DIGITS + t];
     s[t] = cnt;
     c[t] = (cnt + CHUNK - 1) / CHUNK;
+    hc[t] = (cnt + HCHUNK - 1) / HCHUNK;
     __syncthreads();
     const uint32_t total = block_exclusive_scan(s, tmp, nbuckets);
     const uint32_t chunks = block_exclusive_scan(c, tmp, nbuckets);
+    const uint32_t hchunks = block_exclusive_scan(hc, tmp, nbuckets);
     if (t < nbuckets) {
         start1[t] = s[t];
-        cursor1[t] = s[t];
+        uint32_t run = s[t];
+        for (int r = 0; r < REPLICAS; ++r) {
+            cursor1[r * MAX_DIGITS + t] = run;
+            run += count1[r * MAX_DIGITS + t];
+        }
         chunk_first[t] = c[t];
+        hchunk_first[t] = hc[t];
     }
     if (t == 0) {
         start1[nbuckets] = total;
         chunk_first[nbuckets] = chunks;
+        hchunk_first[nbuckets] = hchunks;
     }
 }
 
@@ -163,18 +213,22 @@ __global__ void __launch_bounds__(PART_THREADS) l1_scatter_kernel(const T *__res
                                                                   FixedPoint<T> fp, Geom g, uint32_t *cursor1,
                                                                   Q3 *__restrict__ rec1) {
     __shared__ Q3 stage[CHUNK];
+    __shared__ uint16_t sbk[CHUNK];
     __shared__ uint32_t h[MAX_DIGITS], off[MAX_DIGITS], gbase[MAX_DIGITS], tmp[MAX_DIGITS];
     for (int b = threadIdx.x; b < MAX_DIGITS; b += blockDim.x) h[b] = 0u;
     __syncthreads();
     const int64_t base = int64_t(blockIdx.x) * CHUNK;
+    static_assert(PART_PER == LBATCH, "one batch per scatter chunk");
     Q3 q[PART_PER];
+    bool ok[PART_PER];
     int bk[PART_PER];
     uint32_t rank[PART_PER];
+    bool bad = false;
+    load_q_batch(pos, base + threadIdx.x, PART_THREADS, np, fp, q, ok, bad);
 #pragma unroll
     for (int k = 0; k < PART_PER; ++k) {
-        const int64_t i = base + k * PART_THREADS + threadIdx.x;
         bk[k] = -1;
-        if (i < np && load_q(pos, i, fp, q[k])) {
+        if (ok[k]) {
             bk[k] = bucket_of(g, q[k].x >> g.bits, q[k].y >> g.bits, q[k].z >> g.bits);
             rank[k] = atomicAdd(&h[bk[k]], 1u);
         }
@@ -183,16 +237,21 @@ __global__ void __launch_bounds__(PART_THREADS) l1_scatter_kernel(const T *__res
     for (int b = threadIdx.x; b < g.nbuckets; b += blockDim.x) off[b] = h[b];
     __syncthreads();
     const uint32_t total = block_exclusive_scan(off, tmp, g.nbuckets);
+    // the histogram pass counted this chunk under replica (chunk / HIST_CHUNKS) % REPLICAS
+    uint32_t *mine = cursor1 + ((blockIdx.x / HIST_CHUNKS) % REPLICAS) * MAX_DIGITS;
     for (int b = threadIdx.x; b < g.nbuckets; b += blockDim.x)
-        if (h[b]) gbase[b] = atomicAdd(&cursor1[b], h[b]);
+        if (h[b]) gbase[b] = atomicAdd(&mine[b], h[b]);
 #pragma unroll
     for (int k = 0; k < PART_PER; ++k)
-        if (bk[k] >= 0) stage[off[bk[k]] + rank[k]] = q[k];
+        if (bk[k] >= 0) {
+            const uint32_t s = off[bk[k]] + rank[k];
+            stage[s] = q[k];
+            sbk[s] = uint16_t(bk[k]);
+        }
     __syncthreads();
     for (uint32_t s = threadIdx.x; s < total; s += PART_THREADS) {
-        const Q3 r = stage[s];
-        const int b = bucket_of(g, r.x >> g.bits, r.y >> g.bits, r.z >> g.bits);
-        rec1[gbase[b] + (s - off[b])] = r;
+        const int b = sbk[s];
+        rec1[gbase[b] + (s - off[b])] = stage[s];
     }
 }
 
@@ -206,8 +265,9 @@ struct L2Input {
     FixedPoint<T> fp;
     const Q3 *rec1;
     const uint32_t *start1;
-    const uint32_t *chunk_first;
+    const uint32_t *chunk_first;  // per-bucket chunk prefix for this kernel's chunk size
     int nbuckets;
+    int chunk;                    // records per workgroup
 };
 
 // Locates this workgroup's chunk: bucket b and the index range [lo, hi).
@@ -216,8 +276,8 @@ __device__ __forceinline__ bool l2_chunk(const L2Input<T, FROM_REC> &in, int &b,
     const uint32_t w = blockIdx.x;
     if (!FROM_REC) {
         b = 0;
-        lo = int64_t(w) * CHUNK;
-        hi = lo + CHUNK < in.np ? lo + CHUNK : in.np;
+        lo = int64_t(w) * in.chunk;
+        hi = lo + in.chunk < in.np ? lo + in.chunk : in.np;
         return lo < in.np;
     }
     if (w >= in.chunk_first[in.nbuckets]) return false;
@@ -228,9 +288,9 @@ __device__ __forceinline__ bool l2_chunk(const L2Input<T, FROM_REC> &in, int &b,
         else R = m - 1;
     }
     b = L;
-    lo = int64_t(in.start1[b]) + int64_t(w - in.chunk_first[b]) * CHUNK;
+    lo = int64_t(in.start1[b]) + int64_t(w - in.chunk_first[b]) * in.chunk;
     const int64_t end = in.start1[b + 1];
-    hi = lo + CHUNK < end ? lo + CHUNK : end;
+    hi = lo + in.chunk < end ? lo + in.chunk : end;
     return true;
 }
 
@@ -253,16 +313,22 @@ __global__ void __launch_bounds__(PART_THREADS) l2_hist_kernel(L2Input<T, FROM_R
     for (int d = threadIdx.x; d < MAX_DIGITS; d += blockDim.x) h[d] = 0u;
     __syncthreads();
     bool bad = false;
+    for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += PART_THREADS * LBATCH) {
+        Q3 q[LBATCH];
+        bool ok[LBATCH];
+        if (FROM_REC) {
 #pragma unroll
-    for (int k = 0; k < PART_PER; ++k) {
-        const int64_t i = lo + k * PART_THREADS + threadIdx.x;
-        if (i < hi) {
-            Q3 q;
-            if (l2_load(in, i, q))
-                atomicAdd(&h[tile_in_bucket(g, q.x >> g.bits, q.y >> g.bits, q.z >> g.bits)], 1u);
-            else
-                bad = true;
+            for (int k = 0; k < LBATCH; ++k) {
+                const int64_t i = i0 + k * PART_THREADS;
+                ok[k] = i < hi;
+                if (ok[k]) q[k] = in.rec1[i];
+            }
+        } else {
+            load_q_batch(in.pos, i0, PART_THREADS, hi, in.fp, q, ok, bad);
         }
+#pragma unroll
+        for (int k = 0; k < LBATCH; ++k)
+            if (ok[k]) atomicAdd(&h[tile_in_bucket(g, q[k].x >> g.bits, q[k].y >> g.bits, q[k].z >> g.bits)], 1u);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < g.digits; d += blockDim.x)
@@ -310,14 +376,25 @@ __global__ void __launch_bounds__(PART_THREADS) l2_scatter_kernel(L2Input<T, FRO
     uint64_t r[PART_PER];
     int dg[PART_PER];
     uint32_t rank[PART_PER];
+    Q3 q[PART_PER];
+    bool ok[PART_PER];
+    if (FROM_REC) {
+#pragma unroll
+        for (int k = 0; k < PART_PER; ++k) {
+            const int64_t i = lo + k * PART_THREADS + threadIdx.x;
+            ok[k] = i < hi;
+            if (ok[k]) q[k] = in.rec1[i];
+        }
+    } else {
+        bool bad = false;  // reported by the histogram pass
+        load_q_batch(in.pos, lo + threadIdx.x, PART_THREADS, hi, in.fp, q, ok, bad);
+    }
 #pragma unroll
     for (int k = 0; k < PART_PER; ++k) {
-        const int64_t i = lo + k * PART_THREADS + threadIdx.x;
         dg[k] = -1;
-        Q3 q;
-        if (i < hi && l2_load(in, i, q)) {
-            dg[k] = tile_in_bucket(g, q.x >> g.bits, q.y >> g.bits, q.z >> g.bits);
-            r[k] = pack_local(g, q);
+        if (ok[k]) {
+            dg[k] = tile_in_bucket(g, q[k].x >> g.bits, q[k].y >> g.bits, q[k].z >> g.bits);
+            r[k] = pack_local(g, q[k]);
             rank[k] = atomicAdd(&h[dg[k]], 1u);
         }
     }
@@ -343,41 +420,89 @@ __global__ void __launch_bounds__(PART_THREADS) l2_scatter_kernel(L2Input<T, FRO
 
 // ---------------------------------------------------------------- accumulate and fold
 __device__ __forceinline__ void tile_coords(const Geom &g, int b, int d, int &tx, int &ty, int &tz) {
-    const int bx = b % g.nb, by = (b / g.nb) % g.nb, bz = b / (g.nb * g.nb);
-    const int ux = d % g.bt, uy = (d / g.bt) % g.bt, uz = d / (g.bt * g.bt);
-    tx = bx * g.bt + ux;
-    ty = by * g.bt + uy;
-    tz = bz * g.bt + uz;
+    const int bx = b % g.nbx, by = (b / g.nbx) % g.nby, bz = b / (g.nbx * g.nby);
+    const int ux = d % g.btx, uy = (d / g.btx) % g.bty, uz = d / (g.btx * g.bty);
+    tx = bx * g.btx + ux;
+    ty = by * g.bty + uy;
+    tz = bz * g.btz + uz;
 }
 
+// CHECKED: returning atomic that reports the add carrying a cell past 2^63 - 1.
+template <bool CHECKED>
 __device__ __forceinline__ void lds_add(unsigned long long *acc, int c, unsigned long long w, bool &overflow) {
-    if (w == 0) return;
-    const unsigned long long old = atomicAdd(acc + c, w);
-    if (!(old >> 63) && ((old + w) >> 63)) overflow = true;
-}
-
-__device__ __forceinline__ void skirt_cell(int s, int &x, int &y, int &z) {
-    if (s < FACE_X) {
-        x = TILE;
-        y = s % ACC_EDGE;
-        z = s / ACC_EDGE;
-    } else if (s < FACE_X + FACE_Y) {
-        const int j = s - FACE_X;
-        x = j % TILE;
-        y = TILE;
-        z = j / TILE;
+    if (CHECKED) {
+        if (w == 0) return;
+        const unsigned long long old = atomicAdd(acc + c, w);
+        if (!(old >> 63) && ((old + w) >> 63)) overflow = true;
     } else {
-        const int j = s - FACE_X - FACE_Y;
-        x = j % TILE;
-        y = j / TILE;
-        z = TILE;
+        atomicAdd(acc + c, w);
     }
 }
 
-__device__ __forceinline__ int skirt_index(int x, int y, int z) {
-    if (x == TILE) return z * ACC_EDGE + y;
-    if (y == TILE) return FACE_X + z * TILE + x;
-    return FACE_X + FACE_Y + y * TILE + x;
+template <bool CHECKED>
+__device__ __forceinline__ void accumulate(const uint64_t *__restrict__ rec2, uint32_t lo, uint32_t hi, int bits,
+                                           int ax, unsigned long long *acc, bool &overflow) {
+    const int sx = 6 + bits, sy = 3 + bits;
+    const uint64_t fmask = (1ull << bits) - 1ull;
+    const uint64_t mx = (1ull << sx) - 1ull, my = (1ull << sy) - 1ull;
+    const uint64_t one = 1ull << bits;
+    const int plane = ax * AYZ;
+    constexpr int RB = 4;  // records per thread loaded together
+    for (uint32_t i0 = lo + threadIdx.x; i0 < hi; i0 += ACC_THREADS * RB) {
+        uint64_t rr[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const uint32_t i = i0 + k * ACC_THREADS;
+            rr[k] = i < hi ? rec2[i] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+        if (i0 + k * ACC_THREADS >= hi) break;
+        const uint64_t r = rr[k];
+        const uint64_t qx = r & mx, qy = (r >> sx) & my, qz = (r >> (sx + sy)) & my;
+        const int cx = int(qx >> bits), cy = int(qy >> bits), cz = int(qz >> bits);
+        const uint64_t fx = qx & fmask, fy = qy & fmask, fz = qz & fmask;
+        const uint64_t wx0 = one - fx, wy0 = one - fy, wz0 = one - fz;
+        const int c0 = (cz * AYZ + cy) * ax + cx;
+        const uint64_t w00 = wz0 * wy0, w01 = wz0 * fy, w10 = fz * wy0, w11 = fz * fy;
+        lds_add<CHECKED>(acc, c0, w00 * wx0, overflow);
+        lds_add<CHECKED>(acc, c0 + 1, w00 * fx, overflow);
+        lds_add<CHECKED>(acc, c0 + ax, w01 * wx0, overflow);
+        lds_add<CHECKED>(acc, c0 + ax + 1, w01 * fx, overflow);
+        lds_add<CHECKED>(acc, c0 + plane, w10 * wx0, overflow);
+        lds_add<CHECKED>(acc, c0 + plane + 1, w10 * fx, overflow);
+        lds_add<CHECKED>(acc, c0 + plane + ax, w11 * wx0, overflow);
+        lds_add<CHECKED>(acc, c0 + plane + ax + 1, w11 * fx, overflow);
+        }
+    }
+}
+
+// Skirt cells of a tile, in side-buffer order: the x face (x = tx, y and z in
+// [0, 8]), the y face (y = 8, x < tx, z in [0, 8]), the z face (z = 8, x < tx, y < 8).
+__device__ __forceinline__ void skirt_cell(int tx, int s, int &x, int &y, int &z) {
+    const int fx = AYZ * AYZ, fy = tx * AYZ;
+    if (s < fx) {
+        x = tx;
+        y = s % AYZ;
+        z = s / AYZ;
+    } else if (s < fx + fy) {
+        const int j = s - fx;
+        x = j % tx;
+        y = TYZ;
+        z = j / tx;
+    } else {
+        const int j = s - fx - fy;
+        x = j % tx;
+        y = j / tx;
+        z = TYZ;
+    }
+}
+
+__device__ __forceinline__ int skirt_index(int tx, int x, int y, int z) {
+    const int fx = AYZ * AYZ, fy = tx * AYZ;
+    if (x == tx) return z * AYZ + y;
+    if (y == TYZ) return fx + z * tx + x;
+    return fx + fy + y * tx + x;
 }
 
 // One workgroup per tile, in level-2 (bucket, tile-in-bucket) order.
@@ -386,47 +511,35 @@ __global__ void __launch_bounds__(ACC_THREADS) tile_accum_kernel(const uint64_t 
                                                                  unsigned long long *__restrict__ rho,
                                                                  unsigned long long *__restrict__ skirt,
                                                                  uint32_t *status) {
-    __shared__ unsigned long long acc[ACC_CELLS];
+    __shared__ unsigned long long acc[MAX_ACC_CELLS];
     const int slot = blockIdx.x;
     const int b = slot / g.digits, d = slot % g.digits;
     int tx, ty, tz;
     tile_coords(g, b, d, tx, ty, tz);
-    for (int c = threadIdx.x; c < ACC_CELLS; c += ACC_THREADS) acc[c] = 0ull;
+    const int ax = g.tx + 1;
+    const int ncells = ax * AYZ * AYZ;
+    for (int c = threadIdx.x; c < ncells; c += ACC_THREADS) acc[c] = 0ull;
     __syncthreads();
     const uint32_t lo = start2[slot], hi = start2[slot + 1];
-    const int s = 4 + g.bits;
-    const uint64_t fmask = (1ull << g.bits) - 1ull, lmask = (1ull << s) - 1ull;
-    const uint64_t one = 1ull << g.bits;
     bool overflow = false;
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += ACC_THREADS) {
-        const uint64_t r = rec2[i];
-        const uint64_t ax = r & lmask, ay = (r >> s) & lmask, az = (r >> (2 * s)) & lmask;
-        const int cx = int(ax >> g.bits), cy = int(ay >> g.bits), cz = int(az >> g.bits);
-        const uint64_t fx = ax & fmask, fy = ay & fmask, fz = az & fmask;
-        const uint64_t wx0 = one - fx, wy0 = one - fy, wz0 = one - fz;
-        const int c0 = (cz * ACC_EDGE + cy) * ACC_EDGE + cx;
-        const uint64_t w00 = wz0 * wy0, w01 = wz0 * fy, w10 = fz * wy0, w11 = fz * fy;
-        lds_add(acc, c0, w00 * wx0, overflow);
-        lds_add(acc, c0 + 1, w00 * fx, overflow);
-        lds_add(acc, c0 + ACC_EDGE, w01 * wx0, overflow);
-        lds_add(acc, c0 + ACC_EDGE + 1, w01 * fx, overflow);
-        lds_add(acc, c0 + ACC_EDGE * ACC_EDGE, w10 * wx0, overflow);
-        lds_add(acc, c0 + ACC_EDGE * ACC_EDGE + 1, w10 * fx, overflow);
-        lds_add(acc, c0 + ACC_EDGE * ACC_EDGE + ACC_EDGE, w11 * wx0, overflow);
-        lds_add(acc, c0 + ACC_EDGE * ACC_EDGE + ACC_EDGE + 1, w11 * fx, overflow);
-    }
+    // fewer than 2^(63 - 3B) particles cannot carry any cell of this tile past 2^63 - 1
+    if (uint64_t(hi - lo) < (1ull << (63 - 3 * g.bits)))
+        accumulate<false>(rec2, lo, hi, g.bits, ax, acc, overflow);
+    else
+        accumulate<true>(rec2, lo, hi, g.bits, ax, acc, overflow);
     __syncthreads();
     const size_t n = size_t(g.n);
-    for (int c = threadIdx.x; c < TILE * TILE * TILE; c += ACC_THREADS) {
-        const int x = c % TILE, y = (c / TILE) % TILE, z = c / (TILE * TILE);
-        rho[((size_t(tz) * TILE + z) * n + size_t(ty) * TILE + y) * n + size_t(tx) * TILE + x] =
-            acc[(z * ACC_EDGE + y) * ACC_EDGE + x];
+    const size_t gx0 = size_t(tx) * g.tx, gy0 = size_t(ty) * TYZ, gz0 = size_t(tz) * TYZ;
+    const int owned = g.tx * TYZ * TYZ;
+    for (int c = threadIdx.x; c < owned; c += ACC_THREADS) {
+        const int x = c & (g.tx - 1), y = (c >> g.ltx) & (TYZ - 1), z = c >> (g.ltx + 3);
+        rho[((gz0 + z) * n + gy0 + y) * n + gx0 + x] = acc[(z * AYZ + y) * ax + x];
     }
-    const size_t tglob = (size_t(tz) * g.nt + ty) * g.nt + tx;
-    for (int k = threadIdx.x; k < SKIRT; k += ACC_THREADS) {
+    const size_t tglob = (size_t(tz) * g.nty + ty) * g.ntx + tx;
+    for (int k = threadIdx.x; k < g.skirt; k += ACC_THREADS) {
         int x, y, z;
-        skirt_cell(k, x, y, z);
-        skirt[tglob * SKIRT + k] = acc[(z * ACC_EDGE + y) * ACC_EDGE + x];
+        skirt_cell(g.tx, k, x, y, z);
+        skirt[tglob * g.skirt + k] = acc[(z * AYZ + y) * ax + x];
     }
     if (overflow) atomicOr(status, ST_OVERFLOW);
 }
@@ -437,52 +550,126 @@ __global__ void __launch_bounds__(ACC_THREADS) skirt_fold_kernel(const unsigned 
                                                                  unsigned long long *__restrict__ rho,
                                                                  uint32_t *status) {
     const int t = blockIdx.x;
-    const int tx = t % g.nt, ty = (t / g.nt) % g.nt, tz = t / (g.nt * g.nt);
+    const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
     const size_t n = size_t(g.n);
+    const size_t gx0 = size_t(tx) * g.tx, gy0 = size_t(ty) * TYZ, gz0 = size_t(tz) * TYZ;
     bool overflow = false;
-    // the 16^3 - 15^3 = 721 cells with at least one local coordinate 0
-    for (int c = threadIdx.x; c < TILE * TILE * TILE; c += ACC_THREADS) {
-        const int x = c % TILE, y = (c / TILE) % TILE, z = c / (TILE * TILE);
+    // Face cells of a tx x 8 x 8 tile, enumerated directly: the z = 0 plane
+    // (8 tx cells), then for z = 1..7 the y = 0 row (tx cells) and the x = 0
+    // cells of rows y = 1..7 -- 15 tx + 49 cells in all.
+    const int nface = 15 * g.tx + 49;
+    constexpr int FB = (15 * MAX_TX + 49 + ACC_THREADS - 1) / ACC_THREADS;
+    unsigned long long v[FB], add_lo[FB], add_hi[FB];
+    size_t at[FB];
+#pragma unroll
+    for (int i = 0; i < FB; ++i) {
+        const int k = threadIdx.x + i * ACC_THREADS;
+        add_lo[i] = add_hi[i] = 0ull;
+        at[i] = 0;
+        if (k >= nface) continue;
+        int x, y, z;
+        if (k < 8 * g.tx) {
+            z = 0;
+            y = k >> g.ltx;
+            x = k & (g.tx - 1);
+        } else {
+            const int j = k - 8 * g.tx, row = g.tx + 7;
+            z = 1 + j / row;
+            const int r = j - (z - 1) * row;
+            if (r < g.tx) {
+                y = 0;
+                x = r;
+            } else {
+                y = r - g.tx + 1;
+                x = 0;
+            }
+        }
         const int zmask = (x == 0 ? 1 : 0) | (y == 0 ? 2 : 0) | (z == 0 ? 4 : 0);
-        if (!zmask) continue;
-        const size_t idx = ((size_t(tz) * TILE + z) * n + size_t(ty) * TILE + y) * n + size_t(tx) * TILE + x;
-        unsigned long long v = rho[idx];
+        at[i] = ((gz0 + z) * n + gy0 + y) * n + gx0 + x;
+        v[i] = rho[at[i]];
         for (int dm = zmask; dm; dm = (dm - 1) & zmask) {  // nonzero subsets of the zero axes
             const int dx = dm & 1, dy = (dm >> 1) & 1, dz = (dm >> 2) & 1;
-            const int sx = (tx - dx + g.nt) % g.nt, sy = (ty - dy + g.nt) % g.nt, sz = (tz - dz + g.nt) % g.nt;
-            const size_t src = (size_t(sz) * g.nt + sy) * g.nt + sx;
-            const unsigned long long w = skirt[src * SKIRT + skirt_index(x + TILE * dx, y + TILE * dy, z + TILE * dz)];
-            const unsigned long long old = v;
-            v += w;
-            if (!(old >> 63) && (v >> 63)) overflow = true;
+            const int sx = tx - dx < 0 ? g.ntx - 1 : tx - dx;
+            const int sy = ty - dy < 0 ? g.nty - 1 : ty - dy;
+            const int sz = tz - dz < 0 ? g.ntz - 1 : tz - dz;
+            const size_t src = (size_t(sz) * g.nty + sy) * g.ntx + sx;
+            const unsigned long long w =
+                skirt[src * g.skirt + skirt_index(g.tx, x + g.tx * dx, y + TYZ * dy, z + TYZ * dz)];
+            const unsigned long long t = add_lo[i] + w;
+            add_hi[i] += t < w;
+            add_lo[i] = t;
         }
-        rho[idx] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < FB; ++i) {
+        const int k = threadIdx.x + i * ACC_THREADS;
+        if (k >= nface) continue;
+        // every part is below 2^63 unless already reported; the total must be too
+        const unsigned long long t = add_lo[i] + v[i];
+        const unsigned long long hi = add_hi[i] + (t < v[i]);
+        if (hi != 0 || (t >> 63)) overflow = true;
+        rho[at[i]] = t;
     }
     if (overflow) atomicOr(status, ST_OVERFLOW);
 }
 
 // ---------------------------------------------------------------- host side
-Geom make_geom(const hf_box &box) {
+// Tile and bucket shape for an n^3 grid; false if the binned form cannot hold it
+// (at most MAX_DIGITS tiles per bucket and MAX_DIGITS buckets).
+bool make_geom(const hf_box &box, Geom &out) {
     Geom g{};
     g.n = box.n;
-    g.nt = box.n / TILE;
-    g.bt = 1;
-    for (int d = 8; d >= 1; --d)
-        if (g.nt % d == 0) {
-            g.bt = d;
-            break;
-        }
-    g.nb = g.nt / g.bt;
-    g.bcell = g.bt * TILE;
-    g.nbuckets = g.nb * g.nb * g.nb;
-    g.digits = g.bt * g.bt * g.bt;
-    g.ntiles = g.nt * g.nt * g.nt;
     g.bits = box.frac_bits;
-    return g;
+    g.tx = box.n % 64 == 0 ? 64 : (box.n % 32 == 0 ? 32 : 16);
+    g.ltx = g.tx == 64 ? 6 : (g.tx == 32 ? 5 : 4);
+    if (box.n % g.tx != 0 || box.n % TYZ != 0) return false;
+    g.ntx = box.n / g.tx;
+    g.nty = g.ntz = box.n / TYZ;
+    g.ntiles = g.ntx * g.nty * g.ntz;
+    g.skirt = AYZ * AYZ + g.tx * AYZ + g.tx * TYZ;
+    // fewest buckets, then the most cube-like bucket
+    long best_nb = -1;
+    double best_shape = 0.0;
+    for (int bx = 1; bx <= g.ntx; ++bx) {
+        if (g.ntx % bx) continue;
+        for (int by = 1; by <= g.nty; ++by) {
+            if (g.nty % by) continue;
+            for (int bz = 1; bz <= g.ntz; ++bz) {
+                if (g.ntz % bz || long(bx) * by * bz > MAX_DIGITS) continue;
+                const long nb = long(g.ntx / bx) * (g.nty / by) * (g.ntz / bz);
+                if (nb > MAX_DIGITS) continue;
+                const double ex = double(bx) * g.tx, ey = double(by) * TYZ, ez = double(bz) * TYZ;
+                const double hi = ex > ey ? (ex > ez ? ex : ez) : (ey > ez ? ey : ez);
+                const double lo = ex < ey ? (ex < ez ? ex : ez) : (ey < ez ? ey : ez);
+                const double shape = hi / lo;
+                if (best_nb < 0 || nb < best_nb || (nb == best_nb && shape < best_shape)) {
+                    best_nb = nb;
+                    best_shape = shape;
+                    g.btx = bx;
+                    g.bty = by;
+                    g.btz = bz;
+                }
+            }
+        }
+    }
+    if (best_nb < 0) return false;
+    g.nbx = g.ntx / g.btx;
+    g.nby = g.nty / g.bty;
+    g.nbz = g.ntz / g.btz;
+    g.nbuckets = g.nbx * g.nby * g.nbz;
+    g.digits = g.btx * g.bty * g.btz;
+    g.cbx = FastDiv(uint32_t(g.btx * g.tx));
+    g.cby = FastDiv(uint32_t(g.bty * TYZ));
+    g.cbz = FastDiv(uint32_t(g.btz * TYZ));
+    g.tbx = FastDiv(uint32_t(g.btx));
+    g.tby = FastDiv(uint32_t(g.bty));
+    g.tbz = FastDiv(uint32_t(g.btz));
+    out = g;
+    return true;
 }
 
 struct DepLayout {
-    size_t count1, start1, cursor1, chunk_first, count2, start2, cursor2, rec1, rec2, skirt, total;
+    size_t count1, start1, cursor1, chunk_first, hchunk_first, count2, start2, cursor2, rec1, rec2, skirt, total;
 };
 
 DepLayout dep_layout(const Geom &g, int64_t np) {
@@ -493,74 +680,70 @@ DepLayout dep_layout(const Geom &g, int64_t np) {
         off = align_up(off + bytes);
         return at;
     };
-    L.count1 = take(sizeof(uint32_t) * MAX_DIGITS);
+    L.count1 = take(sizeof(uint32_t) * MAX_DIGITS * REPLICAS);
     L.count2 = take(sizeof(uint32_t) * size_t(g.ntiles));  // count1 and count2 are zeroed together
     L.start1 = take(sizeof(uint32_t) * (MAX_DIGITS + 1));
-    L.cursor1 = take(sizeof(uint32_t) * MAX_DIGITS);
+    L.cursor1 = take(sizeof(uint32_t) * MAX_DIGITS * REPLICAS);
     L.chunk_first = take(sizeof(uint32_t) * (MAX_DIGITS + 1));
+    L.hchunk_first = take(sizeof(uint32_t) * (MAX_DIGITS + 1));
     L.start2 = take(sizeof(uint32_t) * (size_t(g.ntiles) + 1));
     L.cursor2 = take(sizeof(uint32_t) * size_t(g.ntiles));
     L.rec1 = take(g.nbuckets > 1 ? sizeof(Q3) * size_t(np) : 0);
     L.rec2 = take(sizeof(uint64_t) * size_t(np));
-    L.skirt = take(sizeof(unsigned long long) * SKIRT * size_t(g.ntiles));
+    L.skirt = take(sizeof(unsigned long long) * size_t(g.skirt) * size_t(g.ntiles));
     L.total = off;
     return L;
 }
 
 template <typename T>
-FixedPoint<T> fixed_point_of(const hf_box &box) {
-    FixedPoint<T> fp;
-    fp.bits = box.frac_bits;
-    fp.period = int64_t(box.n) << box.frac_bits;
-    fp.scale = T(double(box.n) * double(int64_t(1) << box.frac_bits) / box.box_len);
-    return fp;
-}
-
-template <typename T>
 hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, unsigned long long *rho,
                     char *ws) {
-    const Geom g = make_geom(box);
+    Geom g;
+    if (!make_geom(box, g)) return HF_ERR_SIZE;
     const DepLayout L = dep_layout(g, np);
     auto *count1 = reinterpret_cast<uint32_t *>(ws + L.count1);
     auto *count2 = reinterpret_cast<uint32_t *>(ws + L.count2);
     auto *start1 = reinterpret_cast<uint32_t *>(ws + L.start1);
     auto *cursor1 = reinterpret_cast<uint32_t *>(ws + L.cursor1);
     auto *chunk_first = reinterpret_cast<uint32_t *>(ws + L.chunk_first);
+    auto *hchunk_first = reinterpret_cast<uint32_t *>(ws + L.hchunk_first);
     auto *start2 = reinterpret_cast<uint32_t *>(ws + L.start2);
     auto *cursor2 = reinterpret_cast<uint32_t *>(ws + L.cursor2);
     auto *rec1 = reinterpret_cast<Q3 *>(ws + L.rec1);
     auto *rec2 = reinterpret_cast<uint64_t *>(ws + L.rec2);
     auto *skirt = reinterpret_cast<unsigned long long *>(ws + L.skirt);
     hipStream_t st = ctx->stream;
-    const FixedPoint<T> fp = fixed_point_of<T>(box);
+    const FixedPoint<T> fp = make_fixed_point<T>(box);
     const int64_t zero_count = int64_t((L.start1 - L.count1) / sizeof(uint32_t));
     HF_LAUNCH(ctx, K_DEP_PREP, zero_u32_kernel, dim3(64), dim3(256), 0, st, count1, zero_count);
     const unsigned part_blocks = unsigned((np + CHUNK - 1) / CHUNK);
+    const unsigned hist_blocks = unsigned((np + HCHUNK - 1) / HCHUNK);
     if (g.nbuckets > 1) {
-        if (part_blocks)
-            HF_LAUNCH(ctx, K_DEP_L1_HIST, l1_hist_kernel<T>, dim3(part_blocks), dim3(PART_THREADS), 0, st, pos, np,
+        if (hist_blocks)
+            HF_LAUNCH(ctx, K_DEP_L1_HIST, l1_hist_kernel<T>, dim3(hist_blocks), dim3(PART_THREADS), 0, st, pos, np,
                       fp, g, count1, ctx->d_status);
         HF_LAUNCH(ctx, K_DEP_PREP, l1_scan_kernel, dim3(1), dim3(MAX_DIGITS), 0, st, count1, g.nbuckets, start1,
-                  cursor1, chunk_first);
+                  cursor1, chunk_first, hchunk_first);
         if (part_blocks)
             HF_LAUNCH(ctx, K_DEP_L1_SCATTER, l1_scatter_kernel<T>, dim3(part_blocks), dim3(PART_THREADS), 0, st, pos,
                       np, fp, g, cursor1, rec1);
-        L2Input<T, true> in{pos, np, fp, rec1, start1, chunk_first, g.nbuckets};
-        const unsigned l2_blocks = part_blocks + unsigned(g.nbuckets);
-        HF_LAUNCH(ctx, K_DEP_L2_HIST, (l2_hist_kernel<T, true>), dim3(l2_blocks), dim3(PART_THREADS), 0, st, in, g,
-                  count2, ctx->d_status);
+        const L2Input<T, true> hin{pos, np, fp, rec1, start1, hchunk_first, g.nbuckets, HCHUNK};
+        const L2Input<T, true> sin{pos, np, fp, rec1, start1, chunk_first, g.nbuckets, CHUNK};
+        HF_LAUNCH(ctx, K_DEP_L2_HIST, (l2_hist_kernel<T, true>), dim3(hist_blocks + unsigned(g.nbuckets)),
+                  dim3(PART_THREADS), 0, st, hin, g, count2, ctx->d_status);
         HF_LAUNCH(ctx, K_DEP_PREP, l2_scan_kernel, dim3(1), dim3(1024), 0, st, count2, g.ntiles, start2, cursor2);
-        HF_LAUNCH(ctx, K_DEP_L2_SCATTER, (l2_scatter_kernel<T, true>), dim3(l2_blocks), dim3(PART_THREADS), 0, st,
-                  in, g, cursor2, rec2);
+        HF_LAUNCH(ctx, K_DEP_L2_SCATTER, (l2_scatter_kernel<T, true>), dim3(part_blocks + unsigned(g.nbuckets)),
+                  dim3(PART_THREADS), 0, st, sin, g, cursor2, rec2);
     } else {
-        L2Input<T, false> in{pos, np, fp, nullptr, nullptr, nullptr, 1};
-        if (part_blocks)
-            HF_LAUNCH(ctx, K_DEP_L2_HIST, (l2_hist_kernel<T, false>), dim3(part_blocks), dim3(PART_THREADS), 0, st,
-                      in, g, count2, ctx->d_status);
+        const L2Input<T, false> hin{pos, np, fp, nullptr, nullptr, nullptr, 1, HCHUNK};
+        const L2Input<T, false> sin{pos, np, fp, nullptr, nullptr, nullptr, 1, CHUNK};
+        if (hist_blocks)
+            HF_LAUNCH(ctx, K_DEP_L2_HIST, (l2_hist_kernel<T, false>), dim3(hist_blocks), dim3(PART_THREADS), 0, st,
+                      hin, g, count2, ctx->d_status);
         HF_LAUNCH(ctx, K_DEP_PREP, l2_scan_kernel, dim3(1), dim3(1024), 0, st, count2, g.ntiles, start2, cursor2);
         if (part_blocks)
             HF_LAUNCH(ctx, K_DEP_L2_SCATTER, (l2_scatter_kernel<T, false>), dim3(part_blocks), dim3(PART_THREADS),
-                      0, st, in, g, cursor2, rec2);
+                      0, st, sin, g, cursor2, rec2);
     }
     HF_LAUNCH(ctx, K_DEPOSIT, tile_accum_kernel, dim3(g.ntiles), dim3(ACC_THREADS), 0, st, rec2, start2, g, rho,
               skirt, ctx->d_status);
@@ -572,14 +755,15 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
 }  // namespace
 
 bool hf::deposit_tiled_supported(const hf_box &box, int64_t np) {
-    // packed tile records hold 3 x (4 + B) <= 63 bits; counts are uint32; the
-    // partition kernels hold at most MAX_DIGITS buckets (n = 432 and 864 would need 729)
-    if (box.n % TILE != 0 || box.frac_bits > 17 || np >= (int64_t(1) << 32)) return false;
-    return make_geom(box).nbuckets <= MAX_DIGITS;
+    // packed tile records hold 12 + 3B <= 63 bits; counts are uint32
+    if (box.frac_bits > 17 || np >= (int64_t(1) << 32)) return false;
+    Geom g;
+    return make_geom(box, g);
 }
 
 size_t hf::deposit_tiled_ws_bytes(const hf_box &box, int64_t np) {
-    return dep_layout(make_geom(box), np).total;
+    Geom g;
+    return make_geom(box, g) ? dep_layout(g, np).total : 0;
 }
 
 hf_status hf::deposit_tiled(hf_ctx *ctx, const hf_box &box, const void *pos, hf_dtype dtype, int64_t np,

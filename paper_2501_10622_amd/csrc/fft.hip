@@ -31,11 +31,15 @@ struct FftPlan {
     int n;
     int nst;
     int radix[MAX_STAGES];
+    FastDiv ns[MAX_STAGES];  // product of the radices before each stage
+    FastDiv dn, dh;          // division by n and by n/2 + 1
 };
 
 FftPlan make_plan(int n) {
     FftPlan p{};
     p.n = n;
+    p.dn = FastDiv(uint32_t(n));
+    p.dh = FastDiv(uint32_t(n / 2 + 1));
     int m = n;
     while (m % 3 == 0) {
         p.radix[p.nst++] = 3;
@@ -52,6 +56,11 @@ FftPlan make_plan(int n) {
     while (m % 2 == 0) {
         p.radix[p.nst++] = 2;
         m /= 2;
+    }
+    int ns = 1;
+    for (int s = 0; s < p.nst; ++s) {
+        p.ns[s] = FastDiv(uint32_t(ns));
+        ns *= p.radix[s];
     }
     return p;
 }
@@ -125,8 +134,8 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
 // One Stockham stage of radix R on P pencils (P = 1 << lp) of length n in LDS.
 // tw[m] = exp(-2 pi i m / n).  Ns = product of the radices already applied.
 template <int R, bool INV>
-__device__ __forceinline__ void fft_stage(float2 *buf, int pitch, int lp, int n, int Ns, const float2 *tw, int tid,
-                                          int nthreads) {
+__device__ __forceinline__ void fft_stage(float2 *buf, int pitch, int lp, int n, int Ns, const FastDiv &dns,
+                                          const float2 *tw, int tid, int nthreads) {
     constexpr int MAXB = (MAX_ELEMS + R - 1) / R;
     const int nbf = n / R;
     const int total = nbf << lp;
@@ -139,7 +148,7 @@ __device__ __forceinline__ void fft_stage(float2 *buf, int pitch, int lp, int n,
         if (b < total) {
             const int p = b & pmask;
             const int j = b >> lp;
-            const int k = j % Ns;
+            const int k = int(dns.mod(uint32_t(j)));
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i][r] = buf[(j + r * nbf) * pitch + p];
             if (Ns > 1) {
@@ -159,7 +168,7 @@ __device__ __forceinline__ void fft_stage(float2 *buf, int pitch, int lp, int n,
         if (b < total) {
             const int p = b & pmask;
             const int j = b >> lp;
-            const int k = j % Ns;
+            const int k = int(dns.mod(uint32_t(j)));
             dft<R, INV>(v[i]);
             const int base = (j - k) * R + k;
 #pragma unroll
@@ -176,19 +185,33 @@ __device__ void fft_lds(float2 *buf, int pitch, int lp, const FftPlan &pl, const
     for (int s = 0; s < pl.nst; ++s) {
         const int R = pl.radix[s];
         if (R == 8)
-            fft_stage<8, INV>(buf, pitch, lp, pl.n, Ns, tw, tid, nthreads);
+            fft_stage<8, INV>(buf, pitch, lp, pl.n, Ns, pl.ns[s], tw, tid, nthreads);
         else if (R == 4)
-            fft_stage<4, INV>(buf, pitch, lp, pl.n, Ns, tw, tid, nthreads);
+            fft_stage<4, INV>(buf, pitch, lp, pl.n, Ns, pl.ns[s], tw, tid, nthreads);
         else if (R == 2)
-            fft_stage<2, INV>(buf, pitch, lp, pl.n, Ns, tw, tid, nthreads);
+            fft_stage<2, INV>(buf, pitch, lp, pl.n, Ns, pl.ns[s], tw, tid, nthreads);
         else
-            fft_stage<3, INV>(buf, pitch, lp, pl.n, Ns, tw, tid, nthreads);
+            fft_stage<3, INV>(buf, pitch, lp, pl.n, Ns, pl.ns[s], tw, tid, nthreads);
         Ns *= R;
     }
 }
 
+// Loads of a workgroup's tile are issued as one batch into registers before
+// any is written to LDS, so each thread keeps all of its loads in flight
+// (a load-store loop would wait for every load in turn).  Every launch keeps
+// the elements per thread at or below MAX_ELEMS.
 __device__ __forceinline__ void load_twiddles(float2 *tw_s, const float2 *tw_g, int n) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) tw_s[i] = tw_g[i];
+    float2 t[MAX_ELEMS];
+#pragma unroll
+    for (int i = 0; i < MAX_ELEMS; ++i) {
+        const int e = threadIdx.x + i * blockDim.x;
+        if (e < n) t[i] = tw_g[e];
+    }
+#pragma unroll
+    for (int i = 0; i < MAX_ELEMS; ++i) {
+        const int e = threadIdx.x + i * blockDim.x;
+        if (e < n) tw_s[e] = t[i];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -284,19 +307,34 @@ __global__ void fft_x_fwd_kernel(const int64_t *__restrict__ rho, float2 *__rest
     load_twiddles(tw, tw_g, n);
     unsigned long long lo = 0, hi = 0;
     bool neg = false;
-    for (int e = tid; e < xp * n; e += nt) {
-        const int p = e / n, x = e - p * n;
-        const int64_t q = q0 + p;
-        float2 v = make_float2(0.f, 0.f);
-        if (q < pairs) {
-            const int64_t a = rho[(2 * q) * n + x];
-            const int64_t b = rho[(2 * q + 1) * n + x];
-            neg |= (a < 0) | (b < 0);
-            add128(lo, hi, static_cast<unsigned long long>(a));
-            add128(lo, hi, static_cast<unsigned long long>(b));
-            v = make_float2(float(a), float(b));
+    {
+        int64_t va[MAX_ELEMS], vb[MAX_ELEMS];
+#pragma unroll
+        for (int i = 0; i < MAX_ELEMS; ++i) {
+            const int e = tid + i * nt;
+            va[i] = 0;
+            vb[i] = 0;
+            if (e < xp * n) {
+                const int p = int(pl.dn.div(uint32_t(e))), x = e - p * n;
+                const int64_t q = q0 + p;
+                if (q < pairs) {
+                    va[i] = rho[(2 * q) * n + x];
+                    vb[i] = rho[(2 * q + 1) * n + x];
+                }
+            }
         }
-        buf[x * pitch + p] = v;
+#pragma unroll
+        for (int i = 0; i < MAX_ELEMS; ++i) {
+            const int e = tid + i * nt;
+            if (e < xp * n) {
+                const int p = int(pl.dn.div(uint32_t(e))), x = e - p * n;
+                const int64_t a = va[i], b = vb[i];
+                neg |= (a < 0) | (b < 0);
+                add128(lo, hi, static_cast<unsigned long long>(a));
+                add128(lo, hi, static_cast<unsigned long long>(b));
+                buf[x * pitch + p] = make_float2(float(a), float(b));
+            }
+        }
     }
     if (neg) atomicOr(status, ST_INPUT);
     // workgroup sum of the 128-bit masses (fixed order: deterministic)
@@ -328,7 +366,7 @@ __global__ void fft_x_fwd_kernel(const int64_t *__restrict__ rho, float2 *__rest
     fft_lds<false>(buf, pitch, lp, pl, tw, tid, nt);
     // split Z = A + iB into the two real rows' spectra
     for (int e = tid; e < xp * H; e += nt) {
-        const int p = e / H, k = e - p * H;
+        const int p = int(pl.dh.div(uint32_t(e))), k = e - p * H;
         const int64_t q = q0 + p;
         if (q >= pairs) continue;
         const float2 zk = buf[k * pitch + p];
@@ -351,14 +389,27 @@ __global__ void fft_x_inv_kernel(const float2 *__restrict__ spec, float *__restr
     const int64_t pairs = int64_t(n) * n / 2;
     const int64_t q0 = int64_t(blockIdx.x) * xp;
     load_twiddles(tw, tw_g, n);
-    for (int e = tid; e < xp * H; e += nt) {
-        const int p = e / H, k = e - p * H;
-        const int64_t q = q0 + p;
-        float2 A = make_float2(0.f, 0.f), B = A;
-        if (q < pairs) {
-            A = spec[(2 * q) * H + k];
-            B = spec[(2 * q + 1) * H + k];
+    float2 va[MAX_ELEMS], vb[MAX_ELEMS];
+#pragma unroll
+    for (int i = 0; i < MAX_ELEMS; ++i) {
+        const int e = tid + i * nt;
+        va[i] = make_float2(0.f, 0.f);
+        vb[i] = va[i];
+        if (e < xp * H) {
+            const int p = int(pl.dh.div(uint32_t(e))), k = e - p * H;
+            const int64_t q = q0 + p;
+            if (q < pairs) {
+                va[i] = spec[(2 * q) * H + k];
+                vb[i] = spec[(2 * q + 1) * H + k];
+            }
         }
+    }
+#pragma unroll
+    for (int i = 0; i < MAX_ELEMS; ++i) {
+        const int e = tid + i * nt;
+        if (e >= xp * H) continue;
+        const int p = int(pl.dh.div(uint32_t(e))), k = e - p * H;
+        const float2 A = va[i], B = vb[i];
         if (k == 0 || 2 * k == n) {
             // DC and Nyquist of a real row are real
             buf[k * pitch + p] = make_float2(A.x, B.x);
@@ -370,7 +421,7 @@ __global__ void fft_x_inv_kernel(const float2 *__restrict__ spec, float *__restr
     __syncthreads();
     fft_lds<true>(buf, pitch, lp, pl, tw, tid, nt);
     for (int e = tid; e < xp * n; e += nt) {
-        const int p = e / n, x = e - p * n;
+        const int p = int(pl.dn.div(uint32_t(e))), x = e - p * n;
         const int64_t q = q0 + p;
         if (q >= pairs) continue;
         const float2 v = buf[x * pitch + p];
@@ -447,13 +498,25 @@ __global__ void fft_y_kernel(float2 *__restrict__ spec, FftPlan pl, const float2
     float2 *tw = smem;
     float2 *buf = smem + n;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int kx0 = blockIdx.x * YZ_TILE;
+    // one dimension of logical tiles: kx-tile fastest, then z; XCD-contiguous
+    const uint32_t lt = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int kx0 = int(lt % gridDim.x) * YZ_TILE;
     const int valid = min(YZ_TILE, H - kx0);
-    const size_t zbase = size_t(blockIdx.y) * n * H;
+    const size_t zbase = size_t(lt / gridDim.x) * n * H;
     load_twiddles(tw, tw_g, n);
-    for (int e = tid; e < n * YZ_TILE; e += nt) {
-        const int p = e & (YZ_TILE - 1), y = e >> 4;
-        buf[e] = p < valid ? spec[zbase + size_t(y) * H + kx0 + p] : make_float2(0.f, 0.f);
+    {
+        float2 v[MAX_ELEMS];
+#pragma unroll
+        for (int i = 0; i < MAX_ELEMS; ++i) {
+            const int e = tid + i * nt;
+            const int p = e & (YZ_TILE - 1), y = e >> 4;
+            v[i] = (e < n * YZ_TILE && p < valid) ? spec[zbase + size_t(y) * H + kx0 + p] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < MAX_ELEMS; ++i) {
+            const int e = tid + i * nt;
+            if (e < n * YZ_TILE) buf[e] = v[i];
+        }
     }
     __syncthreads();
     fft_lds<INV>(buf, YZ_TILE, 4, pl, tw, tid, nt);
@@ -471,15 +534,26 @@ __global__ void fft_z_mul_kernel(float2 *__restrict__ spec, FftPlan pl, const fl
     float2 *tw = smem;
     float2 *buf = smem + n;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int kx0 = blockIdx.x * YZ_TILE;
-    const int ky = blockIdx.y;
+    const uint32_t lt = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int kx0 = int(lt % gridDim.x) * YZ_TILE;
+    const int ky = int(lt / gridDim.x);
     const int valid = min(YZ_TILE, H - kx0);
     const size_t zstride = size_t(n) * H;
     const size_t base = size_t(ky) * H + kx0;
     load_twiddles(tw, tw_g, n);
-    for (int e = tid; e < n * YZ_TILE; e += nt) {
-        const int p = e & (YZ_TILE - 1), z = e >> 4;
-        buf[e] = p < valid ? spec[size_t(z) * zstride + base + p] : make_float2(0.f, 0.f);
+    {
+        float2 v[MAX_ELEMS];
+#pragma unroll
+        for (int i = 0; i < MAX_ELEMS; ++i) {
+            const int e = tid + i * nt;
+            const int p = e & (YZ_TILE - 1), z = e >> 4;
+            v[i] = (e < n * YZ_TILE && p < valid) ? spec[size_t(z) * zstride + base + p] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < MAX_ELEMS; ++i) {
+            const int e = tid + i * nt;
+            if (e < n * YZ_TILE) buf[e] = v[i];
+        }
     }
     __syncthreads();
     fft_lds<false>(buf, YZ_TILE, 4, pl, tw, tid, nt);

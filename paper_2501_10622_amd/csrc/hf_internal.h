@@ -126,27 +126,79 @@ size_t maxima_ws_bytes(const hf_box &box);
 size_t segment_ws_bytes(const hf_box &box);
 
 // ---------------------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// xcd_remap turns the hardware block index into a logical one such that every
+// XCD walks one contiguous range of logical blocks, so neighbouring tiles (which
+// share halo and partial lines) are handled by the same L2.  Bijective on [0, G).
+// ---------------------------------------------------------------------------
+constexpr uint32_t NUM_XCD = 8;
+
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
+    const uint32_t q = G / NUM_XCD, r = G % NUM_XCD;
+    const uint32_t x = b % NUM_XCD, k = b / NUM_XCD;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// ---------------------------------------------------------------------------
+// Division of 32-bit unsigned integers by an invariant divisor d >= 1 with a
+// multiply-high and shifts (Granlund & Montgomery, "Division by invariant
+// integers using multiplication", 1994): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1, x / d = (t + ((x - t) >> min(l,1))) >> max(l-1,0)
+// where t = mulhi(m, x).  Exact for every 32-bit x.
+// ---------------------------------------------------------------------------
+struct FastDiv {
+    uint32_t d = 1, m = 1;
+    int s1 = 0, s2 = 0;
+    FastDiv() = default;
+    explicit FastDiv(uint32_t dd) : d(dd) {
+        int l = 0;
+        while ((uint64_t(1) << l) < d) ++l;
+        m = uint32_t((((uint64_t(1) << l) - d) << 32) / d + 1);
+        s1 = l < 1 ? l : 1;
+        s2 = l > 1 ? l - 1 : 0;
+    }
+    __device__ __forceinline__ uint32_t div(uint32_t x) const {
+        const uint32_t t = __umulhi(m, x);
+        return (t + ((x - t) >> s1)) >> s2;
+    }
+    __device__ __forceinline__ uint32_t mod(uint32_t x) const { return x - div(x) * d; }
+};
+
+// ---------------------------------------------------------------------------
 // Fixed-point particle coordinates, shared by the deposit and the labels so
 // both stages see exactly the same q for a particle.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct FixedPoint {
     T scale;        // n 2^B / L rounded to T
+    T period_t;     // n 2^B as T (exact: at most 10 significant bits)
     int64_t period; // n 2^B
     int bits;
 
-    // Returns false for a position the deposit rejects (non-finite t or |t| >= 2^62).
-    __device__ __forceinline__ bool q(T x, int64_t &out) const {
-        T t = x * scale;  // single correctly rounded multiply in T
-        if (!(t > T(-4.611686018427388e18) && t < T(4.611686018427388e18))) return false;
-        int64_t fl = static_cast<int64_t>(floor(t));
-        if (fl < 0 || fl >= period) {
-            fl %= period;
-            if (fl < 0) fl += period;
+    // q = floor(x * scale) mod n 2^B.  Returns false for a position the
+    // deposit rejects (non-finite t or |t| >= 2^62).
+    __device__ __forceinline__ bool q(T x, uint32_t &out) const {
+        const T t = x * scale;  // single correctly rounded multiply in T
+        if (t >= T(0) && t < period_t) {  // in the box: truncation is the floor
+            out = static_cast<uint32_t>(t);
+            return true;
         }
-        out = fl;
+        if (!(t > T(-4.611686018427388e18) && t < T(4.611686018427388e18))) return false;
+        int64_t fl = static_cast<int64_t>(floor(t)) % period;
+        if (fl < 0) fl += period;
+        out = uint32_t(fl);
         return true;
     }
 };
+
+template <typename T>
+inline FixedPoint<T> make_fixed_point(const hf_box &box) {
+    FixedPoint<T> fp;
+    fp.bits = box.frac_bits;
+    fp.period = int64_t(box.n) << box.frac_bits;
+    fp.period_t = T(fp.period);
+    fp.scale = T(double(box.n) * double(int64_t(1) << box.frac_bits) / box.box_len);
+    return fp;
+}
 
 }  // namespace hf

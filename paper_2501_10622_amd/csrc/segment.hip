@@ -62,7 +62,15 @@ constexpr int PER_THREAD = TCELLS / SEG_THREADS;              // 8
 struct TileGrid {
     int n;
     int ntx, nty, ntz;  // tiles per axis
+    FastDiv dn;         // division by n
 };
+
+__device__ __forceinline__ void cell_coords(const TileGrid &tg, uint32_t g, uint32_t &x, uint32_t &y, uint32_t &z) {
+    const uint32_t q = tg.dn.div(g);
+    x = g - q * uint32_t(tg.n);
+    z = tg.dn.div(q);
+    y = q - z * uint32_t(tg.n);
+}
 
 // Rank of local cell (x, y, z) among its tile's boundary cells, or -1.
 // Order: plane z = 0, planes 1..6 (row y = 0, then x = 0 / x = 31 of rows
@@ -81,8 +89,8 @@ __device__ __forceinline__ int bnd_rank(int x, int y, int z) {
 
 // Where the compact boundary array keeps cell g, or -1 if g is interior.
 __device__ __forceinline__ int64_t bnd_slot(const TileGrid &tg, int32_t g) {
-    const uint32_t n = uint32_t(tg.n);
-    const uint32_t x = uint32_t(g) % n, y = (uint32_t(g) / n) % n, z = uint32_t(g) / (n * n);
+    uint32_t x, y, z;
+    cell_coords(tg, uint32_t(g), x, y, z);
     const int r = bnd_rank(int(x % TX), int(y % TY), int(z % TZ));
     if (r < 0) return -1;
     const int64_t tile = (int64_t(z / TZ) * tg.nty + y / TY) * tg.ntx + x / TX;
@@ -93,11 +101,22 @@ __device__ __forceinline__ int64_t bnd_slot(const TileGrid &tg, int32_t g) {
 // leaves the parent key of local cell e = x + TX (y + TY z) in M[e].
 __device__ void tile_parent_keys(const float *__restrict__ c, int n, int x0, int y0, int z0, uint64_t *K,
                                  uint64_t *M, bool &nan) {
-    for (int e = threadIdx.x; e < HCELLS; e += SEG_THREADS) {
+    // all loads of the tile are issued before any is used (one batch per thread)
+    constexpr int LOADS = (HCELLS + SEG_THREADS - 1) / SEG_THREADS;
+    float v[LOADS];
+    uint32_t jj[LOADS];
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) {
+        const int e = threadIdx.x + i * SEG_THREADS;
         const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
         const uint32_t gx = wrap(x0 + hx - 1, n), gy = wrap(y0 + hy - 1, n), gz = wrap(z0 + hz - 1, n);
-        const uint32_t j = (gz * uint32_t(n) + gy) * uint32_t(n) + gx;
-        K[e] = cell_key(c[j], j, nan);
+        jj[i] = (gz * uint32_t(n) + gy) * uint32_t(n) + gx;
+        if (e < HCELLS) v[i] = c[jj[i]];
+    }
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) {
+        const int e = threadIdx.x + i * SEG_THREADS;
+        if (e < HCELLS) K[e] = cell_key(v[i], jj[i], nan);
     }
     __syncthreads();
     // x: M[hz][hy][x] over HZ x HY x TX
@@ -135,7 +154,8 @@ __global__ void __launch_bounds__(SEG_THREADS) max_tile_kernel(const float *__re
     __shared__ uint64_t K[HCELLS];
     __shared__ uint64_t M[TX * HY * HZ];
     int x0, y0, z0;
-    tile_origin(tg, blockIdx.x, x0, y0, z0);
+    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    tile_origin(tg, int(tile), x0, y0, z0);
     bool nan = false;
     tile_parent_keys(c, tg.n, x0, y0, z0, K, M, nan);
     const uint32_t n = uint32_t(tg.n);
@@ -163,7 +183,8 @@ __global__ void __launch_bounds__(SEG_THREADS) seg_tile_kernel(const float *__re
     __shared__ uint64_t K[HCELLS];
     __shared__ uint64_t M[TX * HY * HZ];
     int x0, y0, z0;
-    tile_origin(tg, blockIdx.x, x0, y0, z0);
+    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    tile_origin(tg, int(tile), x0, y0, z0);
     bool nan = false;
     tile_parent_keys(c, tg.n, x0, y0, z0, K, M, nan);
     const uint32_t n = uint32_t(tg.n);
@@ -175,8 +196,9 @@ __global__ void __launch_bounds__(SEG_THREADS) seg_tile_kernel(const float *__re
         const uint32_t p = uint32_t(M[e]);
         int32_t v = -int32_t(p) - 1;
         if (p != g) {
-            const int px = int(p % n), py = int((p / n) % n), pz = int(p / (n * n));
-            const int lx = px - x0, ly = py - y0, lz = pz - z0;
+            uint32_t px, py, pz;
+            cell_coords(tg, p, px, py, pz);
+            const int lx = int(px) - x0, ly = int(py) - y0, lz = int(pz) - z0;
             if (lx >= 0 && lx < TX && ly >= 0 && ly < TY && lz >= 0 && lz < TZ) v = lx + TX * (ly + TY * lz);
         }
         loc[e] = v;
@@ -198,14 +220,13 @@ __global__ void __launch_bounds__(SEG_THREADS) seg_tile_kernel(const float *__re
         for (int i = 0; i < PER_THREAD; ++i) loc[i * SEG_THREADS + threadIdx.x] = nv[i];
         open = __syncthreads_or(any);
     }
-    const int64_t tile = blockIdx.x;
     for (int e = threadIdx.x; e < TCELLS; e += SEG_THREADS) {
         const int x = e % TX, y = (e / TX) % TY, z = e / (TX * TY);
         const uint32_t g = ((uint32_t(z0 + z) * n) + uint32_t(y0 + y)) * n + uint32_t(x0 + x);
         const int32_t t = -loc[e] - 1;
         ptr[g] = t;
         const int r = bnd_rank(x, y, z);
-        if (r >= 0) bnd[tile * NBND + r] = t;
+        if (r >= 0) bnd[int64_t(tile) * NBND + r] = t;
     }
     if (nan) atomicOr(status, ST_INPUT);
 }
@@ -217,18 +238,34 @@ __global__ void fill_flags_kernel(uint32_t *flags, int count) {
 
 // One pointer-jumping round over the boundary cells, in place.  Round r runs
 // only if round r - 1 changed something, so a fixed number of launches is enough.
+constexpr int BATCH = 8;  // independent iterations per thread and pass, so their loads overlap
+
 __global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd, int64_t count, TileGrid tg,
                                                        uint32_t *flags, int round) {
     if (flags[round] == 0u) return;
     bool changed = false;
-    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < count; k += int64_t(gridDim.x) * blockDim.x) {
-        const int32_t p = bnd[k];
-        const int64_t s = bnd_slot(tg, p);
-        if (s < 0) continue;  // an interior target is a root
-        const int32_t q = bnd[s];
-        if (q != p) {
-            bnd[k] = q;
-            changed = true;
+    const int64_t step = int64_t(gridDim.x) * blockDim.x * BATCH;
+    for (int64_t k0 = blockIdx.x * int64_t(blockDim.x) * BATCH + threadIdx.x; k0 < count; k0 += step) {
+        int32_t p[BATCH], q[BATCH];
+        int64_t s[BATCH];
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i) {
+            const int64_t k = k0 + int64_t(i) * blockDim.x;
+            p[i] = k < count ? bnd[k] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i) {
+            const int64_t k = k0 + int64_t(i) * blockDim.x;
+            s[i] = k < count ? bnd_slot(tg, p[i]) : -1;  // an interior target is a root
+            q[i] = s[i] >= 0 ? bnd[s[i]] : p[i];
+        }
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i) {
+            const int64_t k = k0 + int64_t(i) * blockDim.x;
+            if (k < count && q[i] != p[i]) {
+                bnd[k] = q[i];
+                changed = true;
+            }
         }
     }
     if (__any(changed) && (threadIdx.x & 63) == 0) flags[round + 1] = 1u;
@@ -239,11 +276,27 @@ __global__ void __launch_bounds__(256) seg_finalize_kernel(const int32_t *__rest
                                                            const float *__restrict__ c, TileGrid tg, float tau,
                                                            int32_t *__restrict__ label) {
     const int64_t cells = int64_t(tg.n) * tg.n * tg.n;
-    for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < cells; j += int64_t(gridDim.x) * blockDim.x) {
-        const int32_t t = ptr[j];
-        const int64_t s = bnd_slot(tg, t);
-        const int32_t r = s < 0 ? t : bnd[s];
-        label[j] = c[r] > tau ? r : -1;
+    const int64_t step = int64_t(gridDim.x) * blockDim.x * BATCH;
+    for (int64_t j0 = blockIdx.x * int64_t(blockDim.x) * BATCH + threadIdx.x; j0 < cells; j0 += step) {
+        int32_t t[BATCH], r[BATCH];
+        float v[BATCH];
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i) {
+            const int64_t j = j0 + int64_t(i) * blockDim.x;
+            t[i] = j < cells ? ptr[j] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i) {
+            const int64_t s = bnd_slot(tg, t[i]);
+            r[i] = s < 0 ? t[i] : bnd[s];
+        }
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i) v[i] = c[r[i]];
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i) {
+            const int64_t j = j0 + int64_t(i) * blockDim.x;
+            if (j < cells) label[j] = v[i] > tau ? r[i] : -1;
+        }
     }
 }
 
@@ -405,7 +458,7 @@ __global__ void __launch_bounds__(LIST_CHUNK_WORDS) list_write_kernel(const uint
 // ------------------------------------------------------------------ host side
 bool tiled(int n) { return n % TX == 0; }  // TY = TZ = 8 divide every multiple of 32
 
-TileGrid tile_grid(int n) { return TileGrid{n, n / TX, n / TY, n / TZ}; }
+TileGrid tile_grid(int n) { return TileGrid{n, n / TX, n / TY, n / TZ, FastDiv(uint32_t(n))}; }
 
 int rounds_for(uint64_t count) {
     int k = 0;
@@ -468,6 +521,8 @@ int stride_grid(int64_t work) {
     return int(g > 4096 ? 4096 : (g < 1 ? 1 : g));
 }
 
+int batched_grid(int64_t work) { return stride_grid((work + BATCH - 1) / BATCH); }
+
 }  // namespace
 
 size_t hf::maxima_ws_bytes(const hf_box &box) { return maxima_layout(box.n).total; }
@@ -528,12 +583,12 @@ extern "C" hf_status hf_segment(hf_ctx *ctx, const hf_box *box, const float *cwt
         auto *bnd = reinterpret_cast<int32_t *>(w8 + L.bnd);
         HF_LAUNCH(ctx, K_PARENT, seg_tile_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(SEG_THREADS), 0, ctx->stream,
                   cwt, tg, ptr, bnd, ctx->d_status);
-        const int g = stride_grid(L.nbnd);
+        const int g = batched_grid(L.nbnd);
         for (int r = 0; r < L.rounds; ++r)
             HF_LAUNCH(ctx, K_JUMP, bnd_jump_kernel, dim3(g), dim3(256), 0, ctx->stream, bnd, L.nbnd, tg, flags, r);
         const int64_t cells = int64_t(n) * n * n;
-        HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel, dim3(stride_grid(cells)), dim3(256), 0, ctx->stream, ptr, bnd,
-                  cwt, tg, tau, cell_label);
+        HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel, dim3(batched_grid(cells)), dim3(256), 0, ctx->stream, ptr,
+                  bnd, cwt, tg, tau, cell_label);
     } else {
         const uint32_t cells = uint32_t(n) * n * n;
         const int g = stride_grid(cells);

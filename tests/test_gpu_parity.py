@@ -40,7 +40,7 @@ def hfm():
     (192, 190.0, 2000000, 3000, "f32", 17, 7),
     (256, 250.0, 256 ** 3, 20000, "f32", 15, 2),   # the 256^3 FP32 configuration
     (512, 500.0, 3000000, 5000, "f32", 15, 8),
-    (432, 432.0, 400000, 100, "f32", 15, 9),        # 729 coarse buckets: direct atomic path
+    (432, 432.0, 400000, 100, "f32", 15, 9),        # 16-wide tiles, 162 buckets
 ])
 def test_deposit_bit_exact(n, L, np_, halos, dtype, bits, seed):
     pos = small_box(n, L, np_, halos, dtype, seed)
