@@ -113,6 +113,49 @@ def cpu_baseline(seed: int) -> dict:
             "stage_s": {k: round(v, 3) for k, v in t.items()}, "total_s": round(total, 3)}
 
 
+def serving_bench(n_jobs: int, budget_gb: float, n_streams: int, max_batch: int, load: float) -> dict:
+    """Served (continuous batching) against the plain per-request loop on the
+    serving workload: grid sizes 64..256, N_p = n^3 U[0.5, 2], scale U[1, 4]
+    cells; particles resident (8 pool boxes per size)."""
+    import torch
+    import synth
+    from paper_2501_10622_amd.serve import Request, Server, plain_loop, summarize
+    jobs = synth.job_stream(n_jobs, seed=5)
+    pool = {}
+    for jb in jobs:
+        if jb.box_seed not in pool:
+            pool[jb.box_seed] = jb.positions("cuda")
+    torch.cuda.synchronize()
+
+    def requests(arrivals):
+        return [Request(jb.job_id, jb.n, jb.box_len, jb.kw, pool[jb.box_seed], t) for jb, t in zip(jobs, arrivals)]
+
+    warm = requests([0.0] * min(len(jobs), 60))
+    plain_loop(warm)
+    Server(budget_bytes=int(budget_gb * (1 << 30)), n_streams=n_streams, max_batch=max_batch).run(warm)
+    # capacity: every request waiting at t = 0
+    cap_plain = summarize(plain_loop(requests([0.0] * len(jobs))))
+    srv = Server(budget_bytes=int(budget_gb * (1 << 30)), n_streams=n_streams, max_batch=max_batch)
+    cap_served = summarize(srv.run(requests([0.0] * len(jobs))))
+    groups = dict(srv.stats)
+    log(f"serving capacity: plain {cap_plain['jobs_per_s']:.1f} jobs/s, served {cap_served['jobs_per_s']:.1f} jobs/s")
+    # latency under Poisson arrivals at `load` x the plain loop's capacity
+    rate = load * cap_plain["jobs_per_s"]
+    arr = synth.poisson_arrivals(len(jobs), rate, seed=5)
+    lat_plain = summarize(plain_loop(requests(arr)))
+    lat_served = summarize(Server(budget_bytes=int(budget_gb * (1 << 30)), n_streams=n_streams,
+                                  max_batch=max_batch).run(requests(arr)))
+    log(f"serving at {rate:.1f} jobs/s: p50/p99 plain {lat_plain['p50_ms']:.2f}/{lat_plain['p99_ms']:.2f} ms, "
+        f"served {lat_served['p50_ms']:.2f}/{lat_served['p99_ms']:.2f} ms")
+    r = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+    return {"jobs": len(jobs), "pool_boxes": len(pool), "budget_gb": budget_gb, "streams": n_streams,
+            "max_batch": max_batch, "capacity": {"plain": r(cap_plain), "served": r(cap_served),
+                                                 "served_groups": groups},
+            "throughput_ratio": round(cap_served["jobs_per_s"] / cap_plain["jobs_per_s"], 3),
+            "poisson_rate_per_s": round(rate, 2), "load": load,
+            "latency": {"plain": r(lat_plain), "served": r(lat_served)}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +165,11 @@ def main():
     ap.add_argument("--kernel", default="sampled", choices=["sampled", "analytic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=2000, help="serving requests (0 skips serving)")
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-batch", type=int, default=16)
+    ap.add_argument("--serve-load", type=float, default=0.8)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -234,6 +282,12 @@ def main():
         "kernels": kernels,
         "checks": {"mass_exact": mass_ok, "labelled_roots_are_maxima": roots_ok, "maxima": nmax},
     }
+    del pos, rho, cwt, cell, part
+    torch.cuda.empty_cache()
+    if args.serve_jobs > 0:
+        log(f"serving: {args.serve_jobs} requests")
+        out["serving"] = serving_bench(args.serve_jobs, args.serve_budget_gb, args.serve_streams, args.serve_batch,
+                                       args.serve_load)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(cfg.seed)

@@ -138,6 +138,63 @@ hf_status hf_segment(hf_ctx *ctx, const hf_box *box, const float *cwt, float tau
 hf_status hf_label(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np,
                    const int32_t *cell_label, int32_t *particle_label);
 
+/* Batched step 3 for serving: `count` (1..HF_CWT_BATCH_MAX) transforms of the
+ * same grid size n, each with its own box length and scale, enqueued as one
+ * launch per pass (the job is a grid dimension).  items[] is a HOST array read
+ * during the call; rho/cwt in each item are device pointers as in hf_cwt, and
+ * each job gets exactly the result hf_cwt would give it alone.  The workspace
+ * holds count per-job workspaces: hf_cwt_batch_ws_size(n, count, &bytes). */
+#define HF_CWT_BATCH_MAX 32
+typedef struct {
+    const int64_t *rho;
+    float *cwt;
+    double box_len;
+    double kw;
+} hf_cwt_item;
+hf_status hf_cwt_batch_ws_size(int32_t n, int32_t count, size_t *bytes);
+hf_status hf_cwt_batch(hf_ctx *ctx, int32_t n, int32_t count, const hf_cwt_item *items, hf_kernel kernel,
+                       void *ws, size_t ws_bytes);
+
+/* Steps 2-6 for one box in a single call (no host synchronisation inside):
+ * hf_deposit, hf_cwt, hf_maxima, hf_segment and hf_label in order on the
+ * context's stream, all sharing one workspace of
+ * hf_workspace_size(box, np, HF_STAGE_ALL) bytes.  Device-detected errors are
+ * reported by hf_sync as for the separate calls. */
+enum { HF_STAGE_ALL = 15 };
+typedef struct {
+    const void *pos;         /* [np][3] positions */
+    int64_t np;
+    hf_dtype dtype;
+    double kw;               /* scale k_w = w box_len / 1000 */
+    hf_kernel kernel;
+    float tau;               /* peak threshold (0 in the paper's reading) */
+    int64_t *rho;            /* [n^3] int64 density */
+    float *cwt;              /* [n^3] FP32 CWT */
+    int32_t *max_idx;        /* [max_cap] sorted maxima */
+    int64_t max_cap;
+    int64_t *d_count;        /* device int64: number of maxima */
+    int32_t *cell_label;     /* [n^3] */
+    int32_t *particle_label; /* [np] */
+} hf_job;
+hf_status hf_find_halos(hf_ctx *ctx, const hf_box *box, const hf_job *job, void *ws, size_t ws_bytes);
+
+/* Serving form of steps 2-6 for `count` (1..HF_CWT_BATCH_MAX) boxes of the same
+ * grid size n: per-box deposits, ONE batched transform (hf_cwt_batch) for the
+ * group, then per-box maxima, segmentation and labels, all on the context's
+ * stream.  items[] is a host array read during the call.  Each item carries its
+ * box length and its own workspace of hf_workspace_size(box, np,
+ * HF_STAGE_DEPOSIT | HF_STAGE_MAXIMA | HF_STAGE_SEGMENT) bytes; cwt_ws holds
+ * hf_cwt_batch_ws_size(n, count) bytes.  All jobs must use `kernel`.  Every box
+ * gets exactly the results hf_find_halos would give it alone. */
+typedef struct {
+    hf_job job;
+    double box_len;
+    void *ws;
+    size_t ws_bytes;
+} hf_group_item;
+hf_status hf_find_halos_group(hf_ctx *ctx, int32_t n, int32_t frac_bits, int32_t count,
+                              const hf_group_item *items, hf_kernel kernel, void *cwt_ws, size_t cwt_ws_bytes);
+
 /* Kernel timer (a tracing aid, not part of the method).  When enabled, every
  * kernel launch made through this context is bracketed by HIP events on its
  * stream.  hf_profile_read(ctx, i, ...) waits for the stream and returns the

@@ -4,6 +4,6 @@ Stages (HIP kernels in libhf.so, C ABI in include/hf.h): CIC deposit, grid CWT
 by FFT, 26-neighbour maxima, steepest-ascent segmentation, particle labels.
 """
 from .hf import (  # noqa: F401
-    EXPORTS, HFError, LIB_PATH, Context, context, cwt, deposit, find_halos, label, load_library, maxima,
-    segment, status_str, sync, workspace_size,
+    CWT_BATCH_MAX, EXPORTS, HFError, LIB_PATH, Context, context, cwt, cwt_batch, cwt_batch_ws_bytes, deposit,
+    find_halos, find_halos_async, find_halos_group_async, job_buffers, label, load_library, maxima, segment, status_str, sync, workspace_size,
 )

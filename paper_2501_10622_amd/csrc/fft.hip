@@ -217,34 +217,79 @@ __device__ __forceinline__ void load_twiddles(float2 *tw_s, const float2 *tw_g, 
 // ---------------------------------------------------------------------------
 // Tables, generated in FP64 and stored as FP32.
 // ---------------------------------------------------------------------------
-struct TableArgs {
-    int n;
-    int mode;       // hf_kernel
-    int images;     // periodic images per side for the sampled kernel
-    double box_len;
-    double w;
+struct Mass128 {
+    unsigned long long lo, hi;
 };
+
+// Per-job workspace layout (offsets from the job's workspace base).
+struct CwtLayout {
+    size_t scalars, tw, gtab, htab, btab, ptab, mass, spec, total;
+    int lp_x;       // log2 of row pairs per x-pass workgroup
+    int64_t xblocks;
+};
+
+// Up to MAX_BATCH same-n transforms in one launch per pass; the job index is a
+// grid dimension and job j's workspace starts at ws + j * stride.
+constexpr int MAX_BATCH = HF_CWT_BATCH_MAX;
+struct CwtJobs {
+    const int64_t *rho[MAX_BATCH];
+    float *cwt[MAX_BATCH];
+    double box_len[MAX_BATCH];
+    double w[MAX_BATCH];
+    int images[MAX_BATCH];
+    char *ws;
+    size_t stride;
+    int mode;  // hf_kernel
+    int count;
+};
+
+struct JobView {
+    double *scalars;
+    float2 *tw;
+    double *gtab, *htab;
+    float *btab, *ptab;
+    Mass128 *mass;
+    float2 *spec;
+};
+
+__device__ __forceinline__ JobView job_view(const CwtJobs &J, const CwtLayout &L, int j) {
+    char *b = J.ws + size_t(j) * J.stride;
+    JobView v;
+    v.scalars = reinterpret_cast<double *>(b + L.scalars);
+    v.tw = reinterpret_cast<float2 *>(b + L.tw);
+    v.gtab = reinterpret_cast<double *>(b + L.gtab);
+    v.htab = reinterpret_cast<double *>(b + L.htab);
+    v.btab = reinterpret_cast<float *>(b + L.btab);
+    v.ptab = reinterpret_cast<float *>(b + L.ptab);
+    v.mass = reinterpret_cast<Mass128 *>(b + L.mass);
+    v.spec = reinterpret_cast<float2 *>(b + L.spec);
+    return v;
+}
 
 // twiddles tw[m] = exp(-2 pi i m / n); periodised 1D Gaussian factors of the
 // sampled wavelet: G_j = sum_m g(x_j + m L), Hs_j = sum_m (x_j + m L)^2 g(...)
 // with g(t) = exp(-w^2 t^2 / 4) and x_j the minimum-image offset of node j.
-__global__ void tables_stage1(TableArgs a, float2 *tw, double *g_tab, double *h_tab) {
+// Job = blockIdx.y.
+__global__ void tables_stage1(CwtJobs J, CwtLayout L, int n) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= a.n) return;
+    if (j >= n) return;
+    const int job = blockIdx.y;
+    const JobView v = job_view(J, L, job);
+    const double box_len = J.box_len[job], w = J.w[job];
     double s, c;
-    sincospi(2.0 * double(j) / double(a.n), &s, &c);
-    tw[j] = make_float2(float(c), float(-s));
-    const double dx = a.box_len / a.n;
-    const int jc = (j + a.n / 2) % a.n - a.n / 2;
+    sincospi(2.0 * double(j) / double(n), &s, &c);
+    v.tw[j] = make_float2(float(c), float(-s));
+    const double dx = box_len / n;
+    const int jc = (j + n / 2) % n - n / 2;
     double G = 0.0, Hs = 0.0;
-    for (int m = -a.images; m <= a.images; ++m) {
-        const double x = jc * dx + m * a.box_len;
-        const double g = exp(-0.25 * a.w * a.w * x * x);
+    for (int m = -J.images[job]; m <= J.images[job]; ++m) {
+        const double x = jc * dx + m * box_len;
+        const double g = exp(-0.25 * w * w * x * x);
         G += g;
         Hs += x * x * g;
     }
-    g_tab[j] = G;
-    h_tab[j] = Hs;
+    v.gtab[j] = G;
+    v.htab[j] = Hs;
 }
 
 // Separable multiplier: M(kx,ky,kz) = P_x B_y B_z + B_x P_y B_z + B_x B_y P_z.
@@ -252,40 +297,39 @@ __global__ void tables_stage1(TableArgs a, float2 *tw, double *g_tab, double *h_
 //            alpha = 6 dx^3 w^1.5, beta = -dx^3 w^3.5 (Eq. (4) split into
 //            6 g g g - w^2 (x^2 g g g + ...), periodised and transformed);
 //  analytic: B = exp(-k^2/w^2), P = 32 pi^1.5 w^-3.5 k^2 B (the transform of Eq. (4)).
-__global__ void tables_stage2(TableArgs a, const double *g_tab, const double *h_tab, float *b_out, float *p_out) {
+__global__ void tables_stage2(CwtJobs J, CwtLayout L, int n) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.n) return;
-    const double w = a.w;
-    if (a.mode == HF_KERNEL_ANALYTIC) {
-        const int ks = k <= a.n / 2 ? k : k - a.n;
-        const double kk = 2.0 * M_PI * ks / a.box_len;
+    if (k >= n) return;
+    const int job = blockIdx.y;
+    const JobView v = job_view(J, L, job);
+    const double w = J.w[job], box_len = J.box_len[job];
+    if (J.mode == HF_KERNEL_ANALYTIC) {
+        const int ks = k <= n / 2 ? k : k - n;
+        const double kk = 2.0 * M_PI * ks / box_len;
         const double B = exp(-(kk * kk) / (w * w));
         const double beta = 32.0 * pow(M_PI, 1.5) * pow(w, -3.5);
-        b_out[k] = float(B);
-        p_out[k] = float(beta * kk * kk * B);
+        v.btab[k] = float(B);
+        v.ptab[k] = float(beta * kk * kk * B);
         return;
     }
     double B = 0.0, A = 0.0;
-    for (int j = 0; j < a.n; ++j) {
-        const long long ph = (static_cast<long long>(j) * k) % a.n;
-        const double c = cospi(2.0 * double(ph) / double(a.n));
-        B += g_tab[j] * c;
-        A += h_tab[j] * c;
+    for (int j = 0; j < n; ++j) {
+        const long long ph = (static_cast<long long>(j) * k) % n;
+        const double c = cospi(2.0 * double(ph) / double(n));
+        B += v.gtab[j] * c;
+        A += v.htab[j] * c;
     }
-    const double dx = a.box_len / a.n;
+    const double dx = box_len / n;
     const double dx3 = dx * dx * dx;
     const double alpha = 6.0 * dx3 * pow(w, 1.5);
     const double beta = -dx3 * pow(w, 3.5);
-    b_out[k] = float(B);
-    p_out[k] = float(alpha / 3.0 * B + beta * A);
+    v.btab[k] = float(B);
+    v.ptab[k] = float(alpha / 3.0 * B + beta * A);
 }
 
 // ---------------------------------------------------------------------------
 // x passes
 // ---------------------------------------------------------------------------
-struct Mass128 {
-    unsigned long long lo, hi;
-};
 
 __device__ __forceinline__ void add128(unsigned long long &lo, unsigned long long &hi, unsigned long long v) {
     unsigned long long t = lo + v;
@@ -294,9 +338,15 @@ __device__ __forceinline__ void add128(unsigned long long &lo, unsigned long lon
 }
 
 // One workgroup = xp row pairs (rows 2q, 2q+1 of the n*n rows of x).
-__global__ void fft_x_fwd_kernel(const int64_t *__restrict__ rho, float2 *__restrict__ spec, FftPlan pl, int lp,
-                                 const float2 *__restrict__ tw_g, Mass128 *__restrict__ mass, uint32_t *status) {
+__global__ void fft_x_fwd_kernel(CwtJobs J, CwtLayout L, FftPlan pl, uint32_t *status) {
     extern __shared__ float2 smem[];
+    const int job = blockIdx.y;
+    const JobView jv = job_view(J, L, job);
+    const int64_t *__restrict__ rho = J.rho[job];
+    float2 *__restrict__ spec = jv.spec;
+    const float2 *__restrict__ tw_g = jv.tw;
+    Mass128 *__restrict__ mass = jv.mass;
+    const int lp = L.lp_x;
     const int n = pl.n, H = n / 2 + 1;
     const int xp = 1 << lp, pitch = xp + 1;
     float2 *tw = smem;
@@ -378,9 +428,14 @@ __global__ void fft_x_fwd_kernel(const int64_t *__restrict__ rho, float2 *__rest
     }
 }
 
-__global__ void fft_x_inv_kernel(const float2 *__restrict__ spec, float *__restrict__ out, FftPlan pl, int lp,
-                                 const float2 *__restrict__ tw_g) {
+__global__ void fft_x_inv_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
     extern __shared__ float2 smem[];
+    const int job = blockIdx.y;
+    const JobView jv = job_view(J, L, job);
+    const float2 *__restrict__ spec = jv.spec;
+    float *__restrict__ out = J.cwt[job];
+    const float2 *__restrict__ tw_g = jv.tw;
+    const int lp = L.lp_x;
     const int n = pl.n, H = n / 2 + 1;
     const int xp = 1 << lp, pitch = xp + 1;
     float2 *tw = smem;
@@ -448,8 +503,11 @@ __device__ double u128_to_double(unsigned long long lo, unsigned long long hi) {
     return ldexp(t, sh);
 }
 
-__global__ void mass_kernel(const Mass128 *__restrict__ mass, int64_t nparts, int n, double *scalars,
-                            uint32_t *status) {
+__global__ void mass_kernel(CwtJobs J, CwtLayout L, int n, uint32_t *status) {
+    const JobView jv = job_view(J, L, blockIdx.x);
+    const Mass128 *__restrict__ mass = jv.mass;
+    const int64_t nparts = L.xblocks;
+    double *scalars = jv.scalars;
     __shared__ unsigned long long red_lo[16], red_hi[16];
     unsigned long long lo = 0, hi = 0;
     for (int64_t i = threadIdx.x; i < nparts; i += blockDim.x) {
@@ -491,18 +549,30 @@ __global__ void mass_kernel(const Mass128 *__restrict__ mass, int64_t nparts, in
 // ---------------------------------------------------------------------------
 // y and z passes on 16-column tiles of the half spectrum
 // ---------------------------------------------------------------------------
+// Logical tile of a (tiles, rows, jobs) grid, XCD-contiguous over the whole launch.
+__device__ __forceinline__ void yz_tile(int &tile, int &row, int &job) {
+    const uint32_t X = gridDim.x, Y = gridDim.y;
+    const uint32_t lt = xcd_remap(blockIdx.x + X * (blockIdx.y + Y * blockIdx.z), X * Y * gridDim.z);
+    tile = int(lt % X);
+    row = int((lt / X) % Y);
+    job = int(lt / (X * Y));
+}
+
 template <bool INV>
-__global__ void fft_y_kernel(float2 *__restrict__ spec, FftPlan pl, const float2 *__restrict__ tw_g) {
+__global__ void fft_y_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
     extern __shared__ float2 smem[];
+    int tile, zrow, job;
+    yz_tile(tile, zrow, job);
+    const JobView jv = job_view(J, L, job);
+    float2 *__restrict__ spec = jv.spec;
+    const float2 *__restrict__ tw_g = jv.tw;
     const int n = pl.n, H = n / 2 + 1;
     float2 *tw = smem;
     float2 *buf = smem + n;
     const int tid = threadIdx.x, nt = blockDim.x;
-    // one dimension of logical tiles: kx-tile fastest, then z; XCD-contiguous
-    const uint32_t lt = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    const int kx0 = int(lt % gridDim.x) * YZ_TILE;
+    const int kx0 = tile * YZ_TILE;
     const int valid = min(YZ_TILE, H - kx0);
-    const size_t zbase = size_t(lt / gridDim.x) * n * H;
+    const size_t zbase = size_t(zrow) * n * H;
     load_twiddles(tw, tw_g, n);
     {
         float2 v[MAX_ELEMS];
@@ -526,17 +596,22 @@ __global__ void fft_y_kernel(float2 *__restrict__ spec, FftPlan pl, const float2
     }
 }
 
-__global__ void fft_z_mul_kernel(float2 *__restrict__ spec, FftPlan pl, const float2 *__restrict__ tw_g,
-                                 const float *__restrict__ tab_b, const float *__restrict__ tab_p,
-                                 const double *__restrict__ scalars) {
+__global__ void fft_z_mul_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
     extern __shared__ float2 smem[];
+    int tile, yrow, job;
+    yz_tile(tile, yrow, job);
+    const JobView jv = job_view(J, L, job);
+    float2 *__restrict__ spec = jv.spec;
+    const float2 *__restrict__ tw_g = jv.tw;
+    const float *__restrict__ tab_b = jv.btab;
+    const float *__restrict__ tab_p = jv.ptab;
+    const double *__restrict__ scalars = jv.scalars;
     const int n = pl.n, H = n / 2 + 1;
     float2 *tw = smem;
     float2 *buf = smem + n;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const uint32_t lt = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    const int kx0 = int(lt % gridDim.x) * YZ_TILE;
-    const int ky = int(lt / gridDim.x);
+    const int kx0 = tile * YZ_TILE;
+    const int ky = yrow;
     const int valid = min(YZ_TILE, H - kx0);
     const size_t zstride = size_t(n) * H;
     const size_t base = size_t(ky) * H + kx0;
@@ -579,12 +654,6 @@ __global__ void fft_z_mul_kernel(float2 *__restrict__ spec, FftPlan pl, const fl
 // ---------------------------------------------------------------------------
 // workspace layout
 // ---------------------------------------------------------------------------
-struct CwtLayout {
-    size_t scalars, tw, gtab, htab, btab, ptab, mass, spec, total;
-    int lp_x;       // log2 of row pairs per x-pass workgroup
-    int64_t xblocks;
-};
-
 int x_log_pairs(int n) {
     // about 4096 complex values per x-pass workgroup, between 4 and 16 row pairs
     int lp = 4;
@@ -627,43 +696,14 @@ int threads_for(int elems) {
     return t;
 }
 
-}  // namespace
-
-size_t hf::cwt_ws_bytes(const hf_box &box) { return cwt_layout(box.n).total; }
-
-extern "C" hf_status hf_cwt(hf_ctx *ctx, const hf_box *box, const int64_t *rho, double kw, hf_kernel kernel,
-                            float *cwt, void *ws, size_t ws_bytes) {
-    if (!ctx || !rho || !cwt) return HF_ERR_ARG;
-    if (kernel != HF_KERNEL_SAMPLED && kernel != HF_KERNEL_ANALYTIC) return HF_ERR_ARG;
-    if (!(kw > 0.0) || !std::isfinite(kw)) return HF_ERR_ARG;
-    hf_status s = check_box(box);
-    if (s != HF_OK) return s;
-    const int n = box->n;
+// Enqueues the whole transform for J.count same-n jobs (one launch per pass).
+hf_status run_cwt(hf_ctx *ctx, int n, const CwtJobs &J) {
     const CwtLayout L = cwt_layout(n);
-    s = check_ws(ws, ws_bytes, L.total);
-    if (s != HF_OK) return s;
-    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
-    char *w8 = static_cast<char *>(ws);
-    double *scalars = reinterpret_cast<double *>(w8 + L.scalars);
-    float2 *tw = reinterpret_cast<float2 *>(w8 + L.tw);
-    double *gtab = reinterpret_cast<double *>(w8 + L.gtab);
-    double *htab = reinterpret_cast<double *>(w8 + L.htab);
-    float *btab = reinterpret_cast<float *>(w8 + L.btab);
-    float *ptab = reinterpret_cast<float *>(w8 + L.ptab);
-    Mass128 *mass = reinterpret_cast<Mass128 *>(w8 + L.mass);
-    float2 *spec = reinterpret_cast<float2 *>(w8 + L.spec);
     hipStream_t st = ctx->stream;
-
-    TableArgs ta{};
-    ta.n = n;
-    ta.mode = kernel;
-    ta.box_len = box->box_len;
-    ta.w = 1000.0 * kw / box->box_len;  // step 1: k_w = w L / 1000
-    // periodic images within w (I + 1/2) L >= 16, where the wavelet is < 1e-25 of its peak
-    ta.images = std::max(1, int(std::ceil(16.0 / (ta.w * box->box_len) - 0.5)));
+    const unsigned jobs = unsigned(J.count);
     const int tb = 256, tg = (n + tb - 1) / tb;
-    HF_LAUNCH(ctx, K_TABLES_1, tables_stage1, dim3(tg), dim3(tb), 0, st, ta, tw, gtab, htab);
-    HF_LAUNCH(ctx, K_TABLES_2, tables_stage2, dim3(tg), dim3(tb), 0, st, ta, gtab, htab, btab, ptab);
+    HF_LAUNCH(ctx, K_TABLES_1, tables_stage1, dim3(tg, jobs), dim3(tb), 0, st, J, L, n);
+    HF_LAUNCH(ctx, K_TABLES_2, tables_stage2, dim3(tg, jobs), dim3(tb), 0, st, J, L, n);
 
     const FftPlan pl = make_plan(n);
     const int H = n / 2 + 1;
@@ -682,14 +722,74 @@ extern "C" hf_status hf_cwt(hf_ctx *ctx, const hf_box *box, const int64_t *rho, 
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(yz_shm)) != hipSuccess)
             return HF_ERR_DEVICE;
     }
-    HF_LAUNCH(ctx, K_X_FWD, fft_x_fwd_kernel, dim3(unsigned(L.xblocks)), dim3(x_threads), x_shm, st, rho, spec, pl,
-                       L.lp_x, tw, mass, ctx->d_status);
-    HF_LAUNCH(ctx, K_MASS, mass_kernel, dim3(1), dim3(1024), 0, st, mass, L.xblocks, n, scalars, ctx->d_status);
-    HF_LAUNCH(ctx, K_Y_FWD, fft_y_kernel<false>, dim3(tiles, n), dim3(yz_threads), yz_shm, st, spec, pl, tw);
-    HF_LAUNCH(ctx, K_Z_MUL, fft_z_mul_kernel, dim3(tiles, n), dim3(yz_threads), yz_shm, st, spec, pl, tw, btab, ptab,
-                       scalars);
-    HF_LAUNCH(ctx, K_Y_INV, fft_y_kernel<true>, dim3(tiles, n), dim3(yz_threads), yz_shm, st, spec, pl, tw);
-    HF_LAUNCH(ctx, K_X_INV, fft_x_inv_kernel, dim3(unsigned(L.xblocks)), dim3(x_threads), x_shm, st, spec, cwt, pl,
-                       L.lp_x, tw);
+    HF_LAUNCH(ctx, K_X_FWD, fft_x_fwd_kernel, dim3(unsigned(L.xblocks), jobs), dim3(x_threads), x_shm, st, J, L, pl,
+              ctx->d_status);
+    HF_LAUNCH(ctx, K_MASS, mass_kernel, dim3(jobs), dim3(1024), 0, st, J, L, n, ctx->d_status);
+    HF_LAUNCH(ctx, K_Y_FWD, fft_y_kernel<false>, dim3(tiles, n, jobs), dim3(yz_threads), yz_shm, st, J, L, pl);
+    HF_LAUNCH(ctx, K_Z_MUL, fft_z_mul_kernel, dim3(tiles, n, jobs), dim3(yz_threads), yz_shm, st, J, L, pl);
+    HF_LAUNCH(ctx, K_Y_INV, fft_y_kernel<true>, dim3(tiles, n, jobs), dim3(yz_threads), yz_shm, st, J, L, pl);
+    HF_LAUNCH(ctx, K_X_INV, fft_x_inv_kernel, dim3(unsigned(L.xblocks), jobs), dim3(x_threads), x_shm, st, J, L,
+              pl);
     return launch_status();
+}
+
+bool fill_job(CwtJobs &J, int j, const int64_t *rho, float *cwt, double box_len, double kw) {
+    if (!rho || !cwt || !(kw > 0.0) || !std::isfinite(kw) || !(box_len > 0.0) || !(box_len < 1e300)) return false;
+    J.rho[j] = rho;
+    J.cwt[j] = cwt;
+    J.box_len[j] = box_len;
+    J.w[j] = 1000.0 * kw / box_len;  // step 1: k_w = w L / 1000
+    // periodic images within w (I + 1/2) L >= 16, where the wavelet is < 1e-25 of its peak
+    J.images[j] = std::max(1, int(std::ceil(16.0 / (J.w[j] * box_len) - 0.5)));
+    return true;
+}
+
+}  // namespace
+
+size_t hf::cwt_ws_bytes(const hf_box &box) { return cwt_layout(box.n).total; }
+
+extern "C" hf_status hf_cwt(hf_ctx *ctx, const hf_box *box, const int64_t *rho, double kw, hf_kernel kernel,
+                            float *cwt, void *ws, size_t ws_bytes) {
+    if (!ctx || !rho || !cwt) return HF_ERR_ARG;
+    if (kernel != HF_KERNEL_SAMPLED && kernel != HF_KERNEL_ANALYTIC) return HF_ERR_ARG;
+    if (!(kw > 0.0) || !std::isfinite(kw)) return HF_ERR_ARG;
+    hf_status s = check_box(box);
+    if (s != HF_OK) return s;
+    const size_t need = cwt_layout(box->n).total;
+    s = check_ws(ws, ws_bytes, need);
+    if (s != HF_OK) return s;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    CwtJobs J{};
+    if (!fill_job(J, 0, rho, cwt, box->box_len, kw)) return HF_ERR_ARG;
+    J.ws = static_cast<char *>(ws);
+    J.stride = need;
+    J.mode = kernel;
+    J.count = 1;
+    return run_cwt(ctx, box->n, J);
+}
+
+extern "C" hf_status hf_cwt_batch_ws_size(int32_t n, int32_t count, size_t *bytes) {
+    if (!bytes || count < 1 || count > HF_CWT_BATCH_MAX) return HF_ERR_ARG;
+    if (!supported_n(n)) return HF_ERR_SIZE;
+    *bytes = cwt_layout(n).total * size_t(count);
+    return HF_OK;
+}
+
+extern "C" hf_status hf_cwt_batch(hf_ctx *ctx, int32_t n, int32_t count, const hf_cwt_item *items, hf_kernel kernel,
+                                  void *ws, size_t ws_bytes) {
+    if (!ctx || !items || count < 1 || count > HF_CWT_BATCH_MAX) return HF_ERR_ARG;
+    if (kernel != HF_KERNEL_SAMPLED && kernel != HF_KERNEL_ANALYTIC) return HF_ERR_ARG;
+    if (!supported_n(n)) return HF_ERR_SIZE;
+    const size_t per = cwt_layout(n).total;
+    hf_status s = check_ws(ws, ws_bytes, per * size_t(count));
+    if (s != HF_OK) return s;
+    CwtJobs J{};
+    for (int j = 0; j < count; ++j)
+        if (!fill_job(J, j, items[j].rho, items[j].cwt, items[j].box_len, items[j].kw)) return HF_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    J.ws = static_cast<char *>(ws);
+    J.stride = per;
+    J.mode = kernel;
+    J.count = count;
+    return run_cwt(ctx, n, J);
 }

@@ -1,0 +1,84 @@
+// Steps 2-6 of one box in a single native call (Sec. 2, identification steps).
+#include "hf_internal.h"
+
+using namespace hf;
+
+extern "C" hf_status hf_find_halos(hf_ctx *ctx, const hf_box *box, const hf_job *job, void *ws, size_t ws_bytes) {
+    if (!ctx || !job) return HF_ERR_ARG;
+    hf_status s = check_box(box);
+    if (s != HF_OK) return s;
+    size_t need = 0;
+    s = hf_workspace_size(box, job->np, HF_STAGE_ALL, &need);
+    if (s != HF_OK) return s;
+    s = check_ws(ws, ws_bytes, need);
+    if (s != HF_OK) return s;
+    // argument checks of every stage run before anything is enqueued
+    if (!job->rho || !job->cwt || !job->d_count || !job->cell_label || job->np < 0 || job->max_cap < 0 ||
+        (job->max_cap > 0 && !job->max_idx) || (job->np > 0 && (!job->pos || !job->particle_label)) ||
+        (job->dtype != HF_F32 && job->dtype != HF_F64) ||
+        (job->kernel != HF_KERNEL_SAMPLED && job->kernel != HF_KERNEL_ANALYTIC) || !(job->kw > 0.0) ||
+        job->tau != job->tau)
+        return HF_ERR_ARG;
+    s = hf_deposit(ctx, box, job->pos, job->dtype, job->np, job->rho, ws, ws_bytes);
+    if (s != HF_OK) return s;
+    s = hf_cwt(ctx, box, job->rho, job->kw, job->kernel, job->cwt, ws, ws_bytes);
+    if (s != HF_OK) return s;
+    s = hf_maxima(ctx, box, job->cwt, job->tau, job->max_idx, job->max_cap, job->d_count, ws, ws_bytes);
+    if (s != HF_OK) return s;
+    s = hf_segment(ctx, box, job->cwt, job->tau, job->cell_label, ws, ws_bytes);
+    if (s != HF_OK) return s;
+    return hf_label(ctx, box, job->pos, job->dtype, job->np, job->cell_label, job->particle_label);
+}
+
+// A group of same-n boxes: per-box deposits, one batched transform for all of
+// them, then per-box maxima, segmentation and labels, in that order on the
+// context's stream.
+extern "C" hf_status hf_find_halos_group(hf_ctx *ctx, int32_t n, int32_t frac_bits, int32_t count,
+                                         const hf_group_item *items, hf_kernel kernel, void *cwt_ws,
+                                         size_t cwt_ws_bytes) {
+    if (!ctx || !items || count < 1 || count > HF_CWT_BATCH_MAX) return HF_ERR_ARG;
+    if (kernel != HF_KERNEL_SAMPLED && kernel != HF_KERNEL_ANALYTIC) return HF_ERR_ARG;
+    hf_cwt_item cw[HF_CWT_BATCH_MAX];
+    for (int j = 0; j < count; ++j) {
+        const hf_job &job = items[j].job;
+        const hf_box box{n, frac_bits, items[j].box_len};
+        hf_status s = check_box(&box);
+        if (s != HF_OK) return s;
+        size_t need = 0;
+        s = hf_workspace_size(&box, job.np, HF_STAGE_DEPOSIT | HF_STAGE_MAXIMA | HF_STAGE_SEGMENT, &need);
+        if (s != HF_OK) return s;
+        s = check_ws(items[j].ws, items[j].ws_bytes, need);
+        if (s != HF_OK) return s;
+        if (!job.rho || !job.cwt || !job.d_count || !job.cell_label || job.np < 0 || job.max_cap < 0 ||
+            (job.max_cap > 0 && !job.max_idx) || (job.np > 0 && (!job.pos || !job.particle_label)) ||
+            (job.dtype != HF_F32 && job.dtype != HF_F64) || job.kernel != kernel || !(job.kw > 0.0) ||
+            job.tau != job.tau)
+            return HF_ERR_ARG;
+        cw[j] = hf_cwt_item{job.rho, job.cwt, items[j].box_len, job.kw};
+    }
+    size_t need = 0;
+    hf_status s = hf_cwt_batch_ws_size(n, count, &need);
+    if (s != HF_OK) return s;
+    s = check_ws(cwt_ws, cwt_ws_bytes, need);
+    if (s != HF_OK) return s;
+    for (int j = 0; j < count; ++j) {
+        const hf_job &job = items[j].job;
+        const hf_box box{n, frac_bits, items[j].box_len};
+        s = hf_deposit(ctx, &box, job.pos, job.dtype, job.np, job.rho, items[j].ws, items[j].ws_bytes);
+        if (s != HF_OK) return s;
+    }
+    s = hf_cwt_batch(ctx, n, count, cw, kernel, cwt_ws, cwt_ws_bytes);
+    if (s != HF_OK) return s;
+    for (int j = 0; j < count; ++j) {
+        const hf_job &job = items[j].job;
+        const hf_box box{n, frac_bits, items[j].box_len};
+        s = hf_maxima(ctx, &box, job.cwt, job.tau, job.max_idx, job.max_cap, job.d_count, items[j].ws,
+                      items[j].ws_bytes);
+        if (s != HF_OK) return s;
+        s = hf_segment(ctx, &box, job.cwt, job.tau, job.cell_label, items[j].ws, items[j].ws_bytes);
+        if (s != HF_OK) return s;
+        s = hf_label(ctx, &box, job.pos, job.dtype, job.np, job.cell_label, job.particle_label);
+        if (s != HF_OK) return s;
+    }
+    return HF_OK;
+}

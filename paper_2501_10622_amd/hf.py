@@ -23,7 +23,10 @@ STAGE_DEPOSIT, STAGE_CWT, STAGE_MAXIMA, STAGE_SEGMENT = 1, 2, 4, 8
 
 EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_size",
            "hf_deposit", "hf_cwt", "hf_maxima", "hf_segment", "hf_label",
-           "hf_profile_enable", "hf_profile_reset", "hf_profile_read")
+           "hf_profile_enable", "hf_profile_reset", "hf_profile_read",
+           "hf_cwt_batch_ws_size", "hf_cwt_batch", "hf_find_halos", "hf_find_halos_group")
+CWT_BATCH_MAX = 32
+STAGE_ALL = 15
 
 
 class HFError(RuntimeError):
@@ -34,6 +37,23 @@ class HFError(RuntimeError):
 
 class Box(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("frac_bits", ctypes.c_int32), ("box_len", ctypes.c_double)]
+
+
+class CwtItem(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_void_p), ("cwt", ctypes.c_void_p), ("box_len", ctypes.c_double),
+                ("kw", ctypes.c_double)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("np", ctypes.c_int64), ("dtype", ctypes.c_int),
+                ("kw", ctypes.c_double), ("kernel", ctypes.c_int), ("tau", ctypes.c_float),
+                ("rho", ctypes.c_void_p), ("cwt", ctypes.c_void_p), ("max_idx", ctypes.c_void_p),
+                ("max_cap", ctypes.c_int64), ("d_count", ctypes.c_void_p), ("cell_label", ctypes.c_void_p),
+                ("particle_label", ctypes.c_void_p)]
+
+
+class GroupItem(ctypes.Structure):
+    _fields_ = [("job", Job), ("box_len", ctypes.c_double), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -68,6 +88,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "hf_profile_reset": (ctypes.c_int, [vp]),
             "hf_profile_read": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
+            "hf_cwt_batch_ws_size": (ctypes.c_int, [i32, i32, ctypes.POINTER(sz)]),
+            "hf_cwt_batch": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(CwtItem), ctypes.c_int, vp, sz]),
+            "hf_find_halos": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job), vp, sz]),
+            "hf_find_halos_group": (ctypes.c_int, [vp, i32, i32, i32, ctypes.POINTER(GroupItem), ctypes.c_int,
+                                                   vp, sz]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -292,14 +317,92 @@ def sync(device=None):
     context(device).sync()
 
 
+def cwt_batch(rhos, box_lens, kws, kernel: str = "sampled", outs=None, ws=None, ctx=None) -> list:
+    """Step 3 for several same-n grids in one launch per FFT pass (at most CWT_BATCH_MAX)."""
+    count = len(rhos)
+    if count < 1 or count > CWT_BATCH_MAX:
+        raise ValueError(f"batch size must be 1..{CWT_BATCH_MAX}")
+    n = rhos[0].shape[0]
+    for r in rhos:
+        _require_cuda(r, "rho")
+        if r.dtype != torch.int64 or r.shape != (n, n, n):
+            raise ValueError("all grids must be int64 [n, n, n] of the same n")
+    ctx = ctx or context(rhos[0].device.index)
+    if outs is None:
+        outs = [torch.empty((n, n, n), dtype=torch.float32, device=r.device) for r in rhos]
+    need = ctypes.c_size_t()
+    lib = load_library()
+    _check(lib.hf_cwt_batch_ws_size(n, count, ctypes.byref(need)), "hf_cwt_batch_ws_size")
+    if ws is None:
+        ws = torch.empty(need.value, dtype=torch.uint8, device=rhos[0].device)
+    items = (CwtItem * count)(*[CwtItem(r.data_ptr(), o.data_ptr(), float(L), float(k))
+                                 for r, o, L, k in zip(rhos, outs, box_lens, kws)])
+    _check(lib.hf_cwt_batch(ctx.handle, n, count, items, KERNELS[kernel], _ptr(ws), ws.numel()), "hf_cwt_batch")
+    return outs
+
+
+def job_buffers(n: int, np_: int, device, with_cwt_ws: bool = True, frac_bits: int = 15) -> dict:
+    """Output and workspace tensors for one box (allocated on the current stream)."""
+    stages = STAGE_ALL if with_cwt_ws else (STAGE_DEPOSIT | STAGE_MAXIMA | STAGE_SEGMENT)
+    need = workspace_size(n, 1.0, np_, stages, frac_bits)
+    cap = ((n + 1) // 2) ** 3
+    return {
+        "rho": torch.empty((n, n, n), dtype=torch.int64, device=device),
+        "cwt": torch.empty((n, n, n), dtype=torch.float32, device=device),
+        "maxima": torch.empty(cap, dtype=torch.int32, device=device),
+        "count": torch.empty(1, dtype=torch.int64, device=device),
+        "cell_label": torch.empty((n, n, n), dtype=torch.int32, device=device),
+        "particle_label": torch.empty(max(np_, 1), dtype=torch.int32, device=device),
+        "ws": torch.empty(max(need, 256), dtype=torch.uint8, device=device),
+    }
+
+
+def find_halos_async(pos: torch.Tensor, box_len: float, n: int, kw: float, bufs: dict, frac_bits: int = 15,
+                     tau: float = 0.0, kernel: str = "sampled", ctx=None):
+    """Enqueue steps 2-6 with the native single-call driver (no synchronisation)."""
+    _require_cuda(pos, "pos")
+    ctx = ctx or context(pos.device.index)
+    b = box(n, box_len, frac_bits)
+    job = _job_struct(pos, kw, bufs, tau, kernel)
+    _check(load_library().hf_find_halos(ctx.handle, ctypes.byref(b), ctypes.byref(job), _ptr(bufs["ws"]),
+                                        bufs["ws"].numel()), "hf_find_halos")
+
+
+def cwt_batch_ws_bytes(n: int, count: int) -> int:
+    out = ctypes.c_size_t()
+    _check(load_library().hf_cwt_batch_ws_size(int(n), int(count), ctypes.byref(out)), "hf_cwt_batch_ws_size")
+    return out.value
+
+
+def _job_struct(pos, kw, bufs, tau, kernel):
+    return Job(pos.data_ptr(), pos.shape[0], _dtype_code(pos), float(kw), KERNELS[kernel], float(tau),
+               bufs["rho"].data_ptr(), bufs["cwt"].data_ptr(), bufs["maxima"].data_ptr(), bufs["maxima"].numel(),
+               bufs["count"].data_ptr(), bufs["cell_label"].data_ptr(), bufs["particle_label"].data_ptr())
+
+
+def find_halos_group_async(n: int, entries, cwt_ws: torch.Tensor, frac_bits: int = 15, tau: float = 0.0,
+                           kernel: str = "sampled", ctx=None):
+    """Enqueue steps 2-6 for same-n boxes with one batched transform.
+
+    entries: list of (pos, box_len, kw, bufs) with bufs from job_buffers(..., with_cwt_ws=False)."""
+    count = len(entries)
+    if count < 1 or count > CWT_BATCH_MAX:
+        raise ValueError(f"group size must be 1..{CWT_BATCH_MAX}")
+    ctx = ctx or context(entries[0][0].device.index)
+    items = (GroupItem * count)(*[
+        GroupItem(_job_struct(pos, kw, bufs, tau, kernel), float(L), bufs["ws"].data_ptr(), bufs["ws"].numel())
+        for pos, L, kw, bufs in entries])
+    _check(load_library().hf_find_halos_group(ctx.handle, int(n), int(frac_bits), count, items, KERNELS[kernel],
+                                              _ptr(cwt_ws), cwt_ws.numel()), "hf_find_halos_group")
+
+
 def find_halos(pos: torch.Tensor, box_len: float, n: int, kw: float, frac_bits: int = 15, tau: float = 0.0,
                kernel: str = "sampled") -> dict:
-    """Steps 2-6 at one scale, all on the GPU; one sync at the end."""
+    """Steps 2-6 at one scale, all on the GPU through one native call; one sync at the end."""
     ctx = context(pos.device.index)
-    rho = deposit(pos, box_len, n, frac_bits, ctx=ctx)
-    c = cwt(rho, box_len, kw, kernel, ctx=ctx, frac_bits=frac_bits)
-    mx, cnt = maxima(c, tau, ctx=ctx, sync=False)
-    cell = segment(c, tau, ctx=ctx)
-    part = label(pos, box_len, n, cell, frac_bits, ctx=ctx)
+    bufs = job_buffers(n, pos.shape[0], pos.device, True, frac_bits)
+    find_halos_async(pos, box_len, n, kw, bufs, frac_bits, tau, kernel, ctx)
     ctx.sync()
-    return {"rho": rho, "cwt": c, "maxima": mx[: int(cnt.item())], "cell_label": cell, "particle_label": part}
+    cnt = int(bufs["count"].item())
+    return {"rho": bufs["rho"], "cwt": bufs["cwt"], "maxima": bufs["maxima"][:cnt], "cell_label": bufs["cell_label"],
+            "particle_label": bufs["particle_label"][: pos.shape[0]]}

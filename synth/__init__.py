@@ -143,7 +143,11 @@ def make_config_box(cfg: BoxConfig, device="cpu") -> torch.Tensor:
 
 @dataclass(frozen=True)
 class JobSpec:
-    """One serving request: a periodic subvolume with its own grid and scale."""
+    """One serving request: a periodic subvolume (grid n, side L = n Mpc/h) and a scale.
+
+    The particles of a request come from a resident pool of boxes: ``box_seed``
+    names the pool box; several requests may share one box with different scales.
+    """
 
     job_id: int
     n: int
@@ -151,30 +155,36 @@ class JobSpec:
     n_particles: int
     n_halos: int
     kw: float
-    seed: int
+    box_seed: int
     dtype: str = "f32"
 
     def positions(self, device="cpu") -> torch.Tensor:
-        return make_box(self.box_len, self.n_particles, self.n_halos, self.dtype, self.seed, device)
+        return make_box(self.box_len, self.n_particles, self.n_halos, self.dtype, self.box_seed, device)
 
 
-def job_stream(n_jobs: int = 2000, seed: int = 5, sizes=SERVE_SIZES) -> list:
+def job_stream(n_jobs: int = 2000, seed: int = 5, sizes=SERVE_SIZES, boxes_per_size: int = 8) -> list:
     """Serving jobs: n uniform over ``sizes``, N_p = n^3 U[0.5,2], scale U[1,4] cells.
 
     Each subvolume has dx = 1 Mpc/h (L = n) and the halo number density of the
-    1024^3 / 1000 Mpc/h box (1.2e-3 halos per (Mpc/h)^3).
+    1024^3 / 1000 Mpc/h box (1.2e-3 halos per (Mpc/h)^3).  Particle sets come
+    from ``boxes_per_size`` pool boxes per grid size (N_p drawn once per box);
+    every job draws its own scale.
     """
     gen = torch.Generator()
     gen.manual_seed(int(seed))
+    pool = {}
+    for n in sizes:
+        for k in range(boxes_per_size):
+            frac = 0.5 + 1.5 * float(torch.rand(1, generator=gen, dtype=torch.float64).item())
+            pool[(n, k)] = (int(round(n ** 3 * frac)), 5_000_000 + 1000 * n + k)
     jobs = []
     for j in range(n_jobs):
         n = sizes[int(torch.randint(len(sizes), (1,), generator=gen).item())]
-        frac = 0.5 + 1.5 * float(torch.rand(1, generator=gen, dtype=torch.float64).item())
+        k = int(torch.randint(boxes_per_size, (1,), generator=gen).item())
         a = 1.0 + 3.0 * float(torch.rand(1, generator=gen, dtype=torch.float64).item())
+        np_, box_seed = pool[(n, k)]
         box_len = float(n)
-        jobs.append(JobSpec(j, n, box_len, int(round(n ** 3 * frac)),
-                            int(round(1.2e-3 * box_len ** 3)), n / (1000.0 * a),
-                            5_000_000 + j))
+        jobs.append(JobSpec(j, n, box_len, np_, int(round(1.2e-3 * box_len ** 3)), n / (1000.0 * a), box_seed))
     return jobs
 
 

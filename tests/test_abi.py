@@ -84,3 +84,15 @@ def test_null_context_rejected_before_any_device_call(lib):
 
 def test_create_out_pointer_checked(lib):
     assert lib.hf_create(0, None, None) == hf.HF_ERR_ARG
+
+
+def test_serving_footprint_and_summary(lib):
+    from paper_2501_10622_amd.serve import Completion, job_footprint, summarize
+    small, big = job_footprint(64, 200000), job_footprint(256, 30_000_000)
+    assert 0 < small < big
+    # outputs alone: 16 B per cell + 4 B per particle, plus workspaces
+    assert big > 256 ** 3 * 16 + 30_000_000 * 4
+    done = [Completion(i, 64, 1000, 0.01 * i, 0.01 * i + 0.001 * (1 + i % 5)) for i in range(100)]
+    s = summarize(done)
+    assert s["jobs"] == 100 and s["p50_ms"] <= s["p99_ms"] <= 5.0 + 1e-9
+    assert abs(s["particles_per_s"] - 100 * 1000 / s["makespan_s"]) < 1e-6
