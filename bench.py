@@ -28,6 +28,25 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_2501_10622_amd", "csrc")
+
+# kernel-timer names of the library -> kernel symbols as rocprofv3 reports them
+TIMER_SYMBOLS = {
+    "zero_grid": ("fill_u64_kernel",), "deposit": ("tile_accum_kernel",), "label": ("label_kernel",),
+    "deposit_atomic": ("deposit_atomic_kernel",),
+    "deposit_prep": ("zero_u32_kernel", "l1_scan_kernel", "l2_scan_kernel"),
+    "deposit_l1_hist": ("l1_hist_kernel",), "deposit_l1_scatter": ("l1_scatter_kernel",),
+    "deposit_l2_hist": ("l2_hist_kernel",), "deposit_l2_scatter": ("l2_scatter_kernel",),
+    "deposit_fold": ("skirt_fold_kernel",),
+    "tables_1": ("tables_stage1",), "tables_2": ("tables_stage2",), "fft_x_fwd": ("fft_x_fwd_kernel",),
+    "mass": ("mass_kernel",), "fft_y_fwd": ("fft_y_kernel<false>",), "fft_z_mul": ("fft_z_mul_kernel",),
+    "fft_y_inv": ("fft_y_kernel<true>",), "fft_x_inv": ("fft_x_inv_kernel",),
+    "maxima_mark": ("max_tile_kernel", "max_direct_kernel"), "maxima_count": ("mask_count_kernel",),
+    "maxima_scan": ("list_scan_kernel",), "maxima_write": ("list_write_kernel",),
+    "parent": ("seg_tile_kernel", "parent_direct_kernel"), "jump_flags": ("fill_flags_kernel",),
+    "jump": ("bnd_jump_kernel", "jump_direct_kernel"), "finalize": ("seg_finalize_kernel", "finalize_direct_kernel"),
+}
 
 
 def log(msg: str):
@@ -57,6 +76,142 @@ def kernel_bytes(n: int, np_: int, pos_bytes: int) -> dict:
         "parent": 8 * cells,
         "label": (pos_bytes * 3 + 4 + 4) * np_,
     }
+
+
+def source_digest() -> str:
+    """sha256 over the library's HIP sources and its C header: counters taken
+    with other sources no longer describe the kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".h")))
+    for f in files + ["../../include/hf.h"]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_symbol(name: str) -> str:
+    """'void (anonymous namespace)::fft_y_kernel<true>(args...)' -> 'fft_y_kernel<true>'."""
+    import re
+    m = re.search(r"(?:::|^|\s)([A-Za-z_]\w*)(<[^()]*>)?\(", name)
+    if not m:
+        return name
+    tmpl = m.group(2) or ""
+    # keep a template argument only where it names a different pass (fft_y_kernel<INV>)
+    return m.group(1) + (tmpl if m.group(1) == "fft_y_kernel" else "")
+
+
+def timer_name(symbol: str):
+    for t, syms in TIMER_SYMBOLS.items():
+        if symbol in syms:
+            return t
+    return None
+
+
+def traffic_file(workload: str) -> str:
+    return os.path.join(PROFILES, f"hbm_traffic_{workload}.txt")
+
+
+def load_traffic(workload: str, digest: str) -> dict:
+    """{timer name: (fetch bytes, write bytes) per launch, copy-scaled} from the
+    committed counter summary, or {} if it is missing or was taken on other sources."""
+    path = traffic_file(workload)
+    if not os.path.exists(path):
+        return {}
+    out, ok = {}, False
+    for line in open(path):
+        if line.startswith("# sources"):
+            ok = line.split()[-1] == digest
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if f[0] == "kernel":
+            continue
+        out.setdefault(f[0], []).append((float(f[3]), float(f[4])))
+    # a timer name that covers several kernels has no single per-launch figure
+    return {k: v[0] for k, v in out.items() if len(v) == 1} if ok else {}
+
+
+def summarize_profiles(trace_dir: str, pmc_dir: str, workload: str, trace_cmd: str, pmc_cmd: str):
+    """Writes the short, committed summaries of a rocprofv3 kernel trace and of
+    the FETCH_SIZE / WRITE_SIZE counter runs (copy calibration + one step)."""
+    import csv
+    import collections
+    import glob
+    # ---- kernel trace: per-kernel stats of the libhf kernels
+    stats = glob.glob(os.path.join(trace_dir, "*_kernel_stats.csv"))[0]
+    bench_line = None
+    log = os.path.join(os.path.dirname(trace_dir.rstrip("/")), "trace.log")
+    if os.path.exists(log):
+        for line in open(log):
+            if line.startswith("{"):
+                bench_line = json.loads(line)
+    rows = []
+    for r in csv.DictReader(open(stats)):
+        sym = short_symbol(r["Name"])
+        t = timer_name(sym)
+        if t is None:
+            continue
+        rows.append((t, sym, int(r["Calls"]), float(r["AverageNs"]) / 1e6, float(r["TotalDurationNs"]) / 1e6))
+    rows.sort(key=lambda x: -x[4])
+    steps = (bench_line["steps"] + bench_line["warmup"]) if bench_line else None
+    lines = [f"# rocprofv3 kernel trace, libhf kernels, workload {workload}",
+             f"# command: {trace_cmd}",
+             f"# bench line of the traced run: ms_per_step={bench_line['ms_per_step'] if bench_line else '?'} "
+             f"(steps={bench_line['steps'] if bench_line else '?'}, warmup={bench_line['warmup'] if bench_line else '?'})",
+             "# avg_ms = rocprofv3 average duration per dispatch; timer_avg_ms = the library's HIP-event timer in",
+             "# the same run (timed steps only)",
+             f"{'timer':<20}{'symbol':<26}{'calls':>7}{'avg_ms':>11}{'timer_avg_ms':>14}{'ms/step':>10}"]
+    for t, sym, calls, avg, tot in rows:
+        tk = (bench_line or {}).get("kernels", {}).get(t)
+        tavg = f"{tk['avg_ms']:.4f}" if tk and len(TIMER_SYMBOLS[t]) == 1 else "-"
+        per_step = tot / steps if steps else float("nan")
+        lines.append(f"{t:<20}{sym:<26}{calls:>7}{avg:>11.4f}{tavg:>14}{per_step:>10.4f}")
+    total = sum(x[4] for x in rows) / steps if steps else float("nan")
+    lines.append(f"# sum of libhf kernels per step (warmup included in the average): {total:.3f} ms")
+    out1 = os.path.join(PROFILES, f"kernel_trace_{workload}.txt")
+    with open(out1, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    # ---- counters
+    def per_kernel(path):
+        agg = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            agg[short_symbol(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+        return agg
+
+    cf = per_kernel(glob.glob(os.path.join(pmc_dir, "copy_FETCH_SIZE_counter_collection.csv"))[0])
+    cw = per_kernel(glob.glob(os.path.join(pmc_dir, "copy_WRITE_SIZE_counter_collection.csv"))[0])
+    copy_sym = [k for k in cf if "copyBuffer" in k or "copy" in k.lower()][0]
+    copy_bytes = 4 << 30
+    kib_f = sum(cf[copy_sym]) / len(cf[copy_sym])
+    kib_w = sum(cw[copy_sym]) / len(cw[copy_sym])
+    ff, fw = copy_bytes / (kib_f * 1024), copy_bytes / (kib_w * 1024)
+    mf = per_kernel(glob.glob(os.path.join(pmc_dir, "m4_FETCH_SIZE_counter_collection.csv"))[0])
+    mw = per_kernel(glob.glob(os.path.join(pmc_dir, "m4_WRITE_SIZE_counter_collection.csv"))[0])
+    digest = None
+    plog = os.path.join(os.path.dirname(pmc_dir.rstrip("/")), "pmc_m4_FETCH_SIZE.log")
+    if os.path.exists(plog):
+        for line in open(plog):
+            if "libhf sources" in line:
+                digest = line.split()[-1]
+    lines = [f"# HBM traffic per dispatch from rocprofv3 counters, libhf kernels, workload {workload}",
+             f"# commands: {pmc_cmd}",
+             f"# copy calibration: {copy_sym} of {copy_bytes} B reads FETCH_SIZE {kib_f:.1f} KiB and "
+             f"WRITE_SIZE {kib_w:.1f} KiB per dispatch",
+             f"# scale factors: fetch x{ff:.4f}, write x{fw:.4f} (bytes = KiB * 1024 * factor)",
+             f"# sources {digest or source_digest()}",
+             f"{'kernel':<20}{'fetch_KiB':>16}{'write_KiB':>16}{'fetch_B':>18}{'write_B':>18}  symbol"]
+    for sym in mf:
+        t = timer_name(sym)
+        if t is None or sym not in mw:
+            continue
+        f_kib = sum(mf[sym]) / len(mf[sym])
+        w_kib = sum(mw[sym]) / len(mw[sym])
+        lines.append(f"{t:<20}{f_kib:>16.1f}{w_kib:>16.1f}{f_kib * 1024 * ff:>18.4e}{w_kib * 1024 * fw:>18.4e}  {sym}")
+    with open(traffic_file(workload), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(out1)
+    print(traffic_file(workload))
 
 
 def copy_calibration():
@@ -156,6 +311,11 @@ def serving_bench(n_jobs: int, budget_gb: float, n_streams: int, max_batch: int,
             "latency": {"plain": r(lat_plain), "served": r(lat_served)}}
 
 
+def synth_n(config: str) -> int:
+    import synth
+    return synth.CONFIGS[config].n
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +325,10 @@ def main():
     ap.add_argument("--kernel", default="sampled", choices=["sampled", "analytic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--summarize-profiles", nargs=2, metavar=("TRACE_DIR", "PMC_DIR"),
+                    help="write the committed summaries of a kernel trace and of the counter runs")
+    ap.add_argument("--trace-cmd", default="")
+    ap.add_argument("--pmc-cmd", default="")
     ap.add_argument("--serve-jobs", type=int, default=2000, help="serving requests (0 skips serving)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-streams", type=int, default=4)
@@ -180,6 +344,13 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    tag = f"{args.config.lower()}_{synth_n(args.config)}"
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles[0], args.summarize_profiles[1], tag, args.trace_cmd,
+                           args.pmc_cmd)
+        return
+    digest = source_digest()
+    log(f"libhf sources {digest}")
 
     import torch
     import paper_2501_10622_amd as hfm
@@ -258,6 +429,9 @@ def main():
     dom_avg = kernels[dom]["avg_ms"]
     dom_bytes = kb.get(dom, 0)
     achieved = dom_bytes / dom_avg / 1e6 if dom_bytes else 0.0
+    counted = load_traffic(tag, digest).get(dom)
+    traffic = ({"fetch_bytes": counted[0], "write_bytes": counted[1], "bytes": counted[0] + counted[1],
+                "source": os.path.relpath(traffic_file(tag), ROOT)} if counted else None)
     model_bytes = sum(kb.values())
     e2e_gbs = model_bytes / ms_step / 1e6
     cells = n ** 3
@@ -278,7 +452,8 @@ def main():
         "e2e_hbm_roofline_frac": round(e2e_gbs / HBM_PEAK_GBS, 4),
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "bytes_per_launch": dom_bytes, "avg_ms": dom_avg, "traffic": None},
+                     "bytes_per_launch": dom_bytes, "avg_ms": dom_avg,
+                     "traffic": traffic["bytes"] if traffic else None, "traffic_detail": traffic},
         "kernels": kernels,
         "checks": {"mass_exact": mass_ok, "labelled_roots_are_maxima": roots_ok, "maxima": nmax},
     }
