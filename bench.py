@@ -35,7 +35,7 @@ CSRC = os.path.join(ROOT, "paper_2501_10622_amd", "csrc")
 TIMER_SYMBOLS = {
     "zero_grid": ("fill_u64_kernel",), "deposit": ("tile_accum_kernel",), "label": ("label_kernel",),
     "deposit_atomic": ("deposit_atomic_kernel",),
-    "deposit_prep": ("zero_u32_kernel", "l1_scan_kernel", "l2_scan_kernel"),
+    "deposit_prep": ("l1_colscan_kernel", "l1_scan_kernel", "l2_colscan_kernel", "l2_scan_kernel"),
     "deposit_l1_hist": ("l1_hist_kernel",), "deposit_l1_scatter": ("l1_scatter_kernel",),
     "deposit_l2_hist": ("l2_hist_kernel",), "deposit_l2_scatter": ("l2_scatter_kernel",),
     "deposit_fold": ("skirt_fold_kernel",),
@@ -46,6 +46,7 @@ TIMER_SYMBOLS = {
     "maxima_scan": ("list_scan_kernel",), "maxima_write": ("list_write_kernel",),
     "parent": ("seg_tile_kernel", "parent_direct_kernel"), "jump_flags": ("fill_flags_kernel",),
     "jump": ("bnd_jump_kernel", "jump_direct_kernel"), "finalize": ("seg_finalize_kernel", "finalize_direct_kernel"),
+    "label_tiles": ("tile_label_kernel",), "label_level1": ("to_level1_kernel",), "label_input": ("to_input_kernel",),
 }
 
 
@@ -53,27 +54,42 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(n: int, np_: int, pos_bytes: int) -> dict:
-    """Algorithmic (compulsory) HBM bytes per launch of each kernel.
+# Stages of one step and the timer names of the launches that make them up.
+STAGES = {
+    "deposit": ("zero_grid", "deposit_atomic", "deposit_prep", "deposit_l1_hist", "deposit_l1_scatter",
+                "deposit_l2_hist", "deposit_l2_scatter", "deposit", "deposit_fold"),
+    "cwt_x_fwd": ("tables_1", "tables_2", "fft_x_fwd", "mass"),
+    "cwt_y_fwd": ("fft_y_fwd",),
+    "cwt_z_mul": ("fft_z_mul",),
+    "cwt_y_inv": ("fft_y_inv",),
+    "cwt_x_inv": ("fft_x_inv",),
+    "maxima": ("maxima_mark", "maxima_count", "maxima_scan", "maxima_write"),
+    "segment": ("parent", "jump_flags", "jump", "finalize"),
+    "label": ("label", "label_tiles", "label_level1", "label_input"),
+}
 
-    Stage totals: deposit 12 B/particle (FP32) + 8 B/cell; CWT 8 + 4.01 (x fwd)
-    + 3 x 8.02 (y, z*mul*z^-1, y^-1) + 4.01 + 4 (x inv) = 44.06 B/cell; maxima
-    4 B/cell; segmentation 8 B/cell; labels 20 B/particle.  Launches that only
-    exist because of how a stage is implemented (tables, reductions, scans,
-    pointer-jumping rounds) carry no algorithmic bytes.
+
+def stage_bytes(n: int, np_: int, pos_bytes: int) -> dict:
+    """Algorithmic (compulsory) HBM bytes of each stage for one box.
+
+    deposit 12 B/particle (FP32 positions) + 8 B/cell; the transform as five
+    pencil sweeps: x forward 8 + 4.01, y 8.02, z*mul*z^-1 8.02, y^-1 8.02, x^-1
+    4.01 + 4 (44.06 B/cell); maxima 4 B/cell; segmentation 4 + 4 B/cell; labels
+    3 * pos + 4 (cell label) + 4 (label) B/particle.  Launches that exist only
+    because of how a stage is built (histograms, scans, tables, pointer rounds,
+    the kept particle order) add no algorithmic bytes.
     """
     cells = n ** 3
     half = n * n * (n // 2 + 1) * 8  # complex64 half spectrum
     return {
-        "zero_grid": 8 * cells,
-        "deposit": pos_bytes * 3 * np_,
-        "fft_x_fwd": 8 * cells + half,
-        "fft_y_fwd": 2 * half,
-        "fft_z_mul": 2 * half,
-        "fft_y_inv": 2 * half,
-        "fft_x_inv": half + 4 * cells,
-        "maxima_mark": 4 * cells,
-        "parent": 8 * cells,
+        "deposit": pos_bytes * 3 * np_ + 8 * cells,
+        "cwt_x_fwd": 8 * cells + half,
+        "cwt_y_fwd": 2 * half,
+        "cwt_z_mul": 2 * half,
+        "cwt_y_inv": 2 * half,
+        "cwt_x_inv": half + 4 * cells,
+        "maxima": 4 * cells,
+        "segment": 8 * cells,
         "label": (pos_bytes * 3 + 4 + 4) * np_,
     }
 
@@ -113,8 +129,9 @@ def traffic_file(workload: str) -> str:
 
 
 def load_traffic(workload: str, digest: str) -> dict:
-    """{timer name: (fetch bytes, write bytes) per launch, copy-scaled} from the
-    committed counter summary, or {} if it is missing or was taken on other sources."""
+    """{timer name: [(fetch bytes, write bytes, dispatches per step) per kernel]},
+    copy-scaled, from the committed counter summary, or {} if it is missing or
+    was taken on other sources."""
     path = traffic_file(workload)
     if not os.path.exists(path):
         return {}
@@ -127,9 +144,24 @@ def load_traffic(workload: str, digest: str) -> dict:
         f = line.split()
         if f[0] == "kernel":
             continue
-        out.setdefault(f[0], []).append((float(f[3]), float(f[4])))
-    # a timer name that covers several kernels has no single per-launch figure
-    return {k: v[0] for k, v in out.items() if len(v) == 1} if ok else {}
+        out.setdefault(f[0], []).append((float(f[3]), float(f[4]), int(f[5])))
+    return out if ok else {}
+
+
+def stage_traffic(counted: dict, stage: str, ran: set):
+    """HBM bytes per step of one stage from the counter summary (per-dispatch
+    bytes x dispatches of the one-step counter run), or None if a launch of the
+    stage that ran here has no counters."""
+    fetch = write = 0.0
+    for t in STAGES[stage]:
+        if t not in counted:
+            if t in ran:
+                return None
+            continue
+        for f, w, d in counted[t]:
+            fetch += f * d
+            write += w * d
+    return {"fetch_bytes": fetch, "write_bytes": write, "bytes": fetch + write}
 
 
 def summarize_profiles(trace_dir: str, pmc_dir: str, workload: str, trace_cmd: str, pmc_cmd: str):
@@ -199,15 +231,18 @@ def summarize_profiles(trace_dir: str, pmc_dir: str, workload: str, trace_cmd: s
              f"# copy calibration: {copy_sym} of {copy_bytes} B reads FETCH_SIZE {kib_f:.1f} KiB and "
              f"WRITE_SIZE {kib_w:.1f} KiB per dispatch",
              f"# scale factors: fetch x{ff:.4f}, write x{fw:.4f} (bytes = KiB * 1024 * factor)",
-             f"# sources {digest or source_digest()}",
-             f"{'kernel':<20}{'fetch_KiB':>16}{'write_KiB':>16}{'fetch_B':>18}{'write_B':>18}  symbol"]
+             f"# sources {digest or 'unknown'}",
+             "# per dispatch; dispatches = launches in the one-step counter run",
+             f"{'kernel':<20}{'fetch_KiB':>16}{'write_KiB':>16}{'fetch_B':>18}{'write_B':>18}{'dispatches':>11}"
+             "  symbol"]
     for sym in mf:
         t = timer_name(sym)
         if t is None or sym not in mw:
             continue
         f_kib = sum(mf[sym]) / len(mf[sym])
         w_kib = sum(mw[sym]) / len(mw[sym])
-        lines.append(f"{t:<20}{f_kib:>16.1f}{w_kib:>16.1f}{f_kib * 1024 * ff:>18.4e}{w_kib * 1024 * fw:>18.4e}  {sym}")
+        lines.append(f"{t:<20}{f_kib:>16.1f}{w_kib:>16.1f}{f_kib * 1024 * ff:>18.4e}{w_kib * 1024 * fw:>18.4e}"
+                     f"{len(mf[sym]):>11}  {sym}")
     with open(traffic_file(workload), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print(out1)
@@ -235,12 +270,12 @@ def copy_calibration():
 
 
 def cpu_baseline(seed: int) -> dict:
-    """The FP64 oracle on a bounded sample of the same recipe: a 192^3 grid box
+    """The FP64 oracle on a bounded sample of the same recipe: a 256^3 grid box
     with the same cell size, particle density, halo density and scale in cells."""
     import numpy as np
     from oracle import cwthf as O
     import synth
-    n, L = 192, 187.5
+    n, L = 256, 250.0
     np_ = n ** 3
     halos = int(round(1.2e-3 * L ** 3))
     kw = n / (1000.0 * 2.0)
@@ -263,7 +298,7 @@ def cpu_baseline(seed: int) -> dict:
     t["label"] = time.perf_counter() - t0
     total = sum(t.values())
     return {"value": np_ / total, "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": f"same recipe at n=192, L=187.5 Mpc/h, {np_} FP32 particles, {halos} halos, a=2 cells; "
+            "sample": f"same recipe at n={n}, L={L:g} Mpc/h, {np_} FP32 particles, {halos} halos, a=2 cells; "
                       f"numpy single-threaded; host os.cpu_count()={os.cpu_count()}",
             "stage_s": {k: round(v, 3) for k, v in t.items()}, "total_s": round(total, 3)}
 
@@ -371,18 +406,11 @@ def main():
     log(f"generated in {time.perf_counter() - t0:.1f} s")
 
     ctx = hfm.context(0)
-    rho = torch.empty((n, n, n), dtype=torch.int64, device=dev)
-    cwt = torch.empty((n, n, n), dtype=torch.float32, device=dev)
-    cell = torch.empty((n, n, n), dtype=torch.int32, device=dev)
-    part = torch.empty(cfg.n_particles, dtype=torch.int32, device=dev)
+    bufs = hfm.job_buffers(n, cfg.n_particles, dev, True)
+    log(f"workspace {bufs['ws'].numel() / 2**30:.2f} GiB")
 
     def step():
-        hfm.deposit(pos, L, n, out=rho, ctx=ctx)
-        hfm.cwt(rho, L, kw, args.kernel, out=cwt, ctx=ctx)
-        mx = hfm.maxima(cwt, 0.0, ctx=ctx, sync=False)
-        hfm.segment(cwt, 0.0, out=cell, ctx=ctx)
-        hfm.label(pos, L, n, cell, out=part, ctx=ctx)
-        return mx
+        hfm.find_halos_async(pos, L, n, kw, bufs, kernel=args.kernel, ctx=ctx)
 
     for i in range(args.warmup):
         step()
@@ -396,7 +424,7 @@ def main():
     w0 = time.perf_counter()
     start.record()
     for i in range(args.steps):
-        mx = step()
+        step()
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
@@ -407,32 +435,37 @@ def main():
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f})")
 
     # properties that hold at any size: exact mass, labelled roots are the maxima
+    rho, cell = bufs["rho"], bufs["cell_label"]
     lo = int((rho & 0xFFFFFFFF).sum().item())
     hi = int((rho >> 32).sum().item())
     mass_ok = (hi << 32) + lo == cfg.n_particles << (3 * 15)
-    buf, cnt = mx
-    nmax = int(cnt.item())
+    nmax = int(bufs["count"].item())
+    buf = bufs["maxima"]
     roots_ok = bool((cell.view(-1)[buf[:nmax].long()] == buf[:nmax]).all().item()) if nmax else True
 
     pos_bytes = 4 if cfg.dtype == "f32" else 8
-    kb = kernel_bytes(n, cfg.n_particles, pos_bytes)
+    sb = stage_bytes(n, cfg.n_particles, pos_bytes)
     kernels = {}
     for name, (ms, launches) in prof.items():
         if launches == 0:
             continue
-        per_launch = ms / launches
-        ab = kb.get(name, 0)
         kernels[name] = {"ms_per_step": round(ms / args.steps, 4), "launches_per_step": launches // args.steps,
-                         "avg_ms": round(per_launch, 4),
-                         "GBps": round(ab / per_launch / 1e6, 1) if ab else None}
-    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-    dom_avg = kernels[dom]["avg_ms"]
-    dom_bytes = kb.get(dom, 0)
-    achieved = dom_bytes / dom_avg / 1e6 if dom_bytes else 0.0
-    counted = load_traffic(tag, digest).get(dom)
-    traffic = ({"fetch_bytes": counted[0], "write_bytes": counted[1], "bytes": counted[0] + counted[1],
-                "source": os.path.relpath(traffic_file(tag), ROOT)} if counted else None)
-    model_bytes = sum(kb.values())
+                         "avg_ms": round(ms / launches, 4)}
+    counted = load_traffic(tag, digest)
+    stages = {}
+    for st, timers in STAGES.items():
+        ran = [t for t in timers if t in kernels]
+        if not ran:
+            continue
+        ms = sum(kernels[t]["ms_per_step"] for t in ran)
+        gbs = sb[st] / ms / 1e6
+        stages[st] = {"ms_per_step": round(ms, 4), "launches": {t: kernels[t]["launches_per_step"] for t in ran},
+                      "algorithmic_bytes": sb[st], "GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                      "traffic": stage_traffic(counted, st, set(ran)) if counted else None}
+    dom = max(stages, key=lambda k: stages[k]["ms_per_step"])
+    d = stages[dom]
+    traffic = d["traffic"]
+    model_bytes = sum(sb.values())
     e2e_gbs = model_bytes / ms_step / 1e6
     cells = n ** 3
     out = {
@@ -450,14 +483,16 @@ def main():
         "cells_per_s": cells / (ms_step / 1e3),
         "e2e_model_bytes": model_bytes,
         "e2e_hbm_roofline_frac": round(e2e_gbs / HBM_PEAK_GBS, 4),
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "bytes_per_launch": dom_bytes, "avg_ms": dom_avg,
-                     "traffic": traffic["bytes"] if traffic else None, "traffic_detail": traffic},
+        "roofline": {"kernel": f"{dom} stage", "launches": d["launches"], "bound": "hbm",
+                     "achieved": d["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["frac"],
+                     "bytes_per_step": sb[dom], "ms_per_step": d["ms_per_step"],
+                     "traffic": traffic["bytes"] if traffic else None, "traffic_detail": traffic,
+                     "traffic_source": os.path.relpath(traffic_file(tag), ROOT) if traffic else None},
+        "stages": stages,
         "kernels": kernels,
         "checks": {"mass_exact": mass_ok, "labelled_roots_are_maxima": roots_ok, "maxima": nmax},
     }
-    del pos, rho, cwt, cell, part
+    del pos, bufs, rho, cell, buf
     torch.cuda.empty_cache()
     if args.serve_jobs > 0:
         log(f"serving: {args.serve_jobs} requests")

@@ -71,8 +71,12 @@ typedef struct {
 } hf_box;
 
 /* Stage selectors for hf_workspace_size (bit mask: the result covers every
- * selected stage, so one buffer can serve them in turn). */
-enum { HF_STAGE_DEPOSIT = 1, HF_STAGE_CWT = 2, HF_STAGE_MAXIMA = 4, HF_STAGE_SEGMENT = 8 };
+ * selected stage, so one buffer can serve them in turn).  HF_STAGE_LABEL
+ * together with HF_STAGE_DEPOSIT adds, where the binned deposit applies (see
+ * hf_find_halos), a region that carries the deposit's particle order to the
+ * label step: about 16 bytes per particle plus 8 per particle of label scratch. */
+enum { HF_STAGE_DEPOSIT = 1, HF_STAGE_CWT = 2, HF_STAGE_MAXIMA = 4, HF_STAGE_SEGMENT = 8, HF_STAGE_LABEL = 16,
+       HF_STAGE_ALL = 31 };
 
 typedef struct hf_ctx hf_ctx;
 
@@ -158,9 +162,12 @@ hf_status hf_cwt_batch(hf_ctx *ctx, int32_t n, int32_t count, const hf_cwt_item 
 /* Steps 2-6 for one box in a single call (no host synchronisation inside):
  * hf_deposit, hf_cwt, hf_maxima, hf_segment and hf_label in order on the
  * context's stream, all sharing one workspace of
- * hf_workspace_size(box, np, HF_STAGE_ALL) bytes.  Device-detected errors are
+ * hf_workspace_size(box, np, HF_STAGE_ALL) bytes.  Where the deposit bins the
+ * particles (n a multiple of 16 with more than 512 tiles of 16-64 x 8 x 8
+ * cells, frac_bits <= 17, np < 2^32) the binned order is kept and step 6 runs
+ * through it: records are labelled tile by tile and the labels brought back
+ * to input order, with the same result as hf_label.  Device-detected errors are
  * reported by hf_sync as for the separate calls. */
-enum { HF_STAGE_ALL = 15 };
 typedef struct {
     const void *pos;         /* [np][3] positions */
     int64_t np;

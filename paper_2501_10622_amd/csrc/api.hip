@@ -19,6 +19,7 @@ const char *hf::kernel_name(int id) {
         "tables_1", "tables_2", "fft_x_fwd", "mass", "fft_y_fwd", "fft_z_mul", "fft_y_inv", "fft_x_inv",
         "maxima_mark", "maxima_count", "maxima_scan", "maxima_write",
         "parent", "jump_flags", "jump", "finalize",
+        "label_tiles", "label_level1", "label_input",
     };
     return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
@@ -159,12 +160,18 @@ extern "C" hf_status hf_workspace_size(const hf_box *box, int64_t np, int stage_
     if (!bytes || np < 0) return HF_ERR_ARG;
     hf_status s = check_box(box);
     if (s != HF_OK) return s;
-    if (stage_mask & ~(HF_STAGE_DEPOSIT | HF_STAGE_CWT | HF_STAGE_MAXIMA | HF_STAGE_SEGMENT)) return HF_ERR_ARG;
+    if (stage_mask & ~HF_STAGE_ALL) return HF_ERR_ARG;
+    // deposit + label: the deposit's particle order is kept for the labels in
+    // a region of its own in front of the part the stages share in turn
+    const bool order = (stage_mask & HF_STAGE_DEPOSIT) && (stage_mask & HF_STAGE_LABEL) &&
+                       particle_order_supported(*box, np);
     size_t need = 0;
-    if (stage_mask & HF_STAGE_DEPOSIT) need = need > deposit_ws_bytes(*box, np) ? need : deposit_ws_bytes(*box, np);
-    if (stage_mask & HF_STAGE_CWT) need = need > cwt_ws_bytes(*box) ? need : cwt_ws_bytes(*box);
-    if (stage_mask & HF_STAGE_MAXIMA) need = need > maxima_ws_bytes(*box) ? need : maxima_ws_bytes(*box);
-    if (stage_mask & HF_STAGE_SEGMENT) need = need > segment_ws_bytes(*box) ? need : segment_ws_bytes(*box);
-    *bytes = need;
+    auto take = [&need](size_t b) { need = need > b ? need : b; };
+    if (stage_mask & HF_STAGE_DEPOSIT) take(order ? deposit_tiled_ws_bytes(*box, np, true) : deposit_ws_bytes(*box, np));
+    if (stage_mask & HF_STAGE_CWT) take(cwt_ws_bytes(*box));
+    if (stage_mask & HF_STAGE_MAXIMA) take(maxima_ws_bytes(*box));
+    if (stage_mask & HF_STAGE_SEGMENT) take(segment_ws_bytes(*box));
+    if (order) take(label_scratch_bytes(np));
+    *bytes = (order ? particle_order_bytes(*box, np) : 0) + need;
     return HF_OK;
 }

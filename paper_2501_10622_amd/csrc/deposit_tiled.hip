@@ -14,9 +14,18 @@
 //
 // Tiles are long in x so that the fold's face accesses are mostly whole rows.
 // Each partition pass is a histogram pass plus a scatter pass whose writes are
-// staged in LDS so that each workgroup writes one contiguous run per bucket.
-// Every sum is an exact integer sum, so the grid does not depend on particle
-// order or on the order the atomics resolve in.
+// staged in LDS so that each workgroup writes one contiguous run per bucket
+// (per tile at level 2).  Every sum is an exact integer sum, so the grid does
+// not depend on particle order or on the order the atomics resolve in.
+//
+// With a caller-provided ParticleOrder the level-2 records and the bucket and
+// tile offsets outlive the deposit, together with every particle's level-1
+// slot and every level-1 record's level-2 slot.  Step 6 then labels the
+// records tile by tile from a copy of the tile's cell labels in LDS, and brings
+// the labels back to input order through the two slot maps.  Because every
+// scatter workgroup writes one run per destination, the slots a workgroup of
+// those passes reads form one run per bucket (per tile), which it reads into
+// LDS with consecutive lanes on consecutive slots.
 #include "hf_internal.h"
 
 using namespace hf;
@@ -35,6 +44,7 @@ constexpr int HCHUNK = CHUNK * HIST_CHUNKS;
 constexpr int REPLICAS = 64;   // level-1 counters are replicated to spread atomic traffic
 constexpr int MAX_DIGITS = 512;
 constexpr int ACC_THREADS = 256;
+constexpr uint32_t NO_SLOT = 0xffffffffu;  // slot of a particle whose position was rejected
 
 struct Geom {
     int n;              // grid cells per axis
@@ -147,6 +157,24 @@ __global__ void zero_u32_kernel(uint32_t *p, int64_t count) {
         p[i] = 0u;
 }
 
+// Scatter chunk of hardware block b, or -1 for a spare block.  Workgroups go
+// round-robin to the XCDs; this mapping gives XCD x the chunks of the
+// histogram workgroups h = x (mod 8), in order, so the level-1 counter replicas
+// h % REPLICAS it advances are its own: every replica's record runs are written
+// (and later read back in the same order) through one L2.  Launch
+// replica_grid(nchunks) blocks.
+__device__ __forceinline__ int64_t replica_chunk(uint32_t b, uint32_t nchunks) {
+    const uint32_t x = b % NUM_XCD, k = b / NUM_XCD;
+    const uint64_t c = uint64_t(HIST_CHUNKS) * (x + uint64_t(NUM_XCD) * (k / HIST_CHUNKS)) + k % HIST_CHUNKS;
+    return c < nchunks ? int64_t(c) : -1;
+}
+
+inline unsigned replica_grid(unsigned nchunks) {
+    const unsigned g = HIST_CHUNKS * NUM_XCD;
+    return (nchunks + g - 1) / g * g;
+}
+static_assert(REPLICAS % NUM_XCD == 0, "replicas split evenly over the XCDs");
+
 // ---------------------------------------------------------------- level 1
 template <typename T>
 __global__ void __launch_bounds__(PART_THREADS) l1_hist_kernel(const T *__restrict__ pos, int64_t np,
@@ -178,7 +206,8 @@ __global__ void __launch_bounds__(PART_THREADS) l1_hist_kernel(const T *__restri
 // number of level-2 scatter / histogram chunks per bucket.
 __global__ void __launch_bounds__(MAX_DIGITS) l1_scan_kernel(const uint32_t *__restrict__ count1, int nbuckets,
                                                              uint32_t *start1, uint32_t *cursor1,
-                                                             uint32_t *chunk_first, uint32_t *hchunk_first) {
+                                                             uint32_t *chunk_first, uint32_t *hchunk_first,
+                                                             uint32_t *nrec_out) {
     __shared__ uint32_t s[MAX_DIGITS], c[MAX_DIGITS], hc[MAX_DIGITS], tmp[MAX_DIGITS];
     const int t = threadIdx.x;
     uint32_t cnt = 0;
@@ -203,6 +232,7 @@ __global__ void __launch_bounds__(MAX_DIGITS) l1_scan_kernel(const uint32_t *__r
     }
     if (t == 0) {
         start1[nbuckets] = total;
+        if (nrec_out) *nrec_out = total;
         chunk_first[nbuckets] = chunks;
         hchunk_first[nbuckets] = hchunks;
     }
@@ -211,13 +241,16 @@ __global__ void __launch_bounds__(MAX_DIGITS) l1_scan_kernel(const uint32_t *__r
 template <typename T>
 __global__ void __launch_bounds__(PART_THREADS) l1_scatter_kernel(const T *__restrict__ pos, int64_t np,
                                                                   FixedPoint<T> fp, Geom g, uint32_t *cursor1,
-                                                                  Q3 *__restrict__ rec1) {
+                                                                  Q3 *__restrict__ rec1,
+                                                                  uint32_t *__restrict__ slot1) {
     __shared__ Q3 stage[CHUNK];
     __shared__ uint16_t sbk[CHUNK];
     __shared__ uint32_t h[MAX_DIGITS], off[MAX_DIGITS], gbase[MAX_DIGITS], tmp[MAX_DIGITS];
+    const int64_t chunk = replica_chunk(blockIdx.x, unsigned((np + CHUNK - 1) / CHUNK));
+    if (chunk < 0) return;
     for (int b = threadIdx.x; b < MAX_DIGITS; b += blockDim.x) h[b] = 0u;
     __syncthreads();
-    const int64_t base = int64_t(blockIdx.x) * CHUNK;
+    const int64_t base = chunk * CHUNK;
     static_assert(PART_PER == LBATCH, "one batch per scatter chunk");
     Q3 q[PART_PER];
     bool ok[PART_PER];
@@ -238,7 +271,7 @@ __global__ void __launch_bounds__(PART_THREADS) l1_scatter_kernel(const T *__res
     __syncthreads();
     const uint32_t total = block_exclusive_scan(off, tmp, g.nbuckets);
     // the histogram pass counted this chunk under replica (chunk / HIST_CHUNKS) % REPLICAS
-    uint32_t *mine = cursor1 + ((blockIdx.x / HIST_CHUNKS) % REPLICAS) * MAX_DIGITS;
+    uint32_t *mine = cursor1 + ((chunk / HIST_CHUNKS) % REPLICAS) * MAX_DIGITS;
     for (int b = threadIdx.x; b < g.nbuckets; b += blockDim.x)
         if (h[b]) gbase[b] = atomicAdd(&mine[b], h[b]);
 #pragma unroll
@@ -252,6 +285,13 @@ __global__ void __launch_bounds__(PART_THREADS) l1_scatter_kernel(const T *__res
     for (uint32_t s = threadIdx.x; s < total; s += PART_THREADS) {
         const int b = sbk[s];
         rec1[gbase[b] + (s - off[b])] = stage[s];
+    }
+    if (slot1) {
+#pragma unroll
+        for (int k = 0; k < PART_PER; ++k) {
+            const int64_t i = base + k * PART_THREADS + threadIdx.x;
+            if (i < np) slot1[i] = bk[k] >= 0 ? gbase[bk[k]] + rank[k] : NO_SLOT;
+        }
     }
 }
 
@@ -362,9 +402,11 @@ __global__ void __launch_bounds__(1024) l2_scan_kernel(const uint32_t *__restric
     if (t == 1023) start2[ntiles] = part[1023];
 }
 
+// map12 (optional, FROM_REC only) receives every level-1 record's level-2 slot.
 template <typename T, bool FROM_REC>
 __global__ void __launch_bounds__(PART_THREADS) l2_scatter_kernel(L2Input<T, FROM_REC> in, Geom g,
-                                                                  uint32_t *cursor2, uint64_t *__restrict__ rec2) {
+                                                                  uint32_t *cursor2, uint64_t *__restrict__ rec2,
+                                                                  uint32_t *__restrict__ map12) {
     __shared__ uint64_t stage[CHUNK];
     __shared__ uint16_t sdig[CHUNK];
     __shared__ uint32_t h[MAX_DIGITS], off[MAX_DIGITS], gbase[MAX_DIGITS], tmp[MAX_DIGITS];
@@ -415,6 +457,11 @@ __global__ void __launch_bounds__(PART_THREADS) l2_scatter_kernel(L2Input<T, FRO
     for (uint32_t s = threadIdx.x; s < total; s += PART_THREADS) {
         const int d = sdig[s];
         rec2[gbase[d] + (s - off[d])] = stage[s];
+    }
+    if (FROM_REC && map12) {
+#pragma unroll
+        for (int k = 0; k < PART_PER; ++k)
+            if (dg[k] >= 0) map12[lo + k * PART_THREADS + threadIdx.x] = gbase[dg[k]] + rank[k];
     }
 }
 
@@ -613,7 +660,183 @@ __global__ void __launch_bounds__(ACC_THREADS) skirt_fold_kernel(const unsigned 
     if (overflow) atomicOr(status, ST_OVERFLOW);
 }
 
-// ---------------------------------------------------------------- host side
+// ---------------------------------------------------------------- step 6 through the particle order
+// Pass 1, one workgroup per tile in level-2 order: the cell labels of the tile
+// and its +x/+y/+z skirt go to LDS; record k takes the label of its nearest
+// node, lab2[k].  A tile-local node is ((q_local + 2^(B-1)) >> B) per axis,
+// at most one cell past the tile, which the skirt holds.
+__global__ void __launch_bounds__(ACC_THREADS) tile_label_kernel(const uint64_t *__restrict__ rec2,
+                                                                 const uint32_t *__restrict__ start2, Geom g,
+                                                                 const int32_t *__restrict__ cell_label,
+                                                                 int32_t *__restrict__ lab2) {
+    __shared__ int32_t lab[MAX_ACC_CELLS];
+    const int slot = blockIdx.x;
+    const int b = slot / g.digits, d = slot % g.digits;
+    int tx, ty, tz;
+    tile_coords(g, b, d, tx, ty, tz);
+    const int ax = g.tx + 1;
+    const int ncells = ax * AYZ * AYZ;
+    const uint32_t n = uint32_t(g.n);
+    const uint32_t gx0 = uint32_t(tx) * g.tx, gy0 = uint32_t(ty) * TYZ, gz0 = uint32_t(tz) * TYZ;
+    for (int c = threadIdx.x; c < ncells; c += ACC_THREADS) {
+        const int x = c % ax, y = (c / ax) % AYZ, z = c / (ax * AYZ);
+        uint32_t gx = gx0 + x, gy = gy0 + y, gz = gz0 + z;
+        if (gx >= n) gx -= n;
+        if (gy >= n) gy -= n;
+        if (gz >= n) gz -= n;
+        lab[c] = cell_label[(gz * n + gy) * n + gx];
+    }
+    __syncthreads();
+    const int bits = g.bits, sx = 6 + bits, sy = 3 + bits;
+    const uint64_t mx = (1ull << sx) - 1ull, my = (1ull << sy) - 1ull;
+    const uint64_t half = 1ull << (bits - 1);
+    const uint32_t lo = start2[slot], hi = start2[slot + 1];
+    constexpr int RB = 4;
+    for (uint32_t i0 = lo + threadIdx.x; i0 < hi; i0 += ACC_THREADS * RB) {
+        uint64_t rr[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const uint32_t i = i0 + k * ACC_THREADS;
+            rr[k] = i < hi ? rec2[i] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const uint32_t i = i0 + k * ACC_THREADS;
+            if (i >= hi) break;
+            const uint64_t r = rr[k];
+            const int nx = int(((r & mx) + half) >> bits);
+            const int ny = int((((r >> sx) & my) + half) >> bits);
+            const int nz = int((((r >> (sx + sy)) & my) + half) >> bits);
+            lab2[i] = lab[(nz * AYZ + ny) * ax + nx];
+        }
+    }
+}
+
+// Last index d in [0, count) with table[d] <= v (table ascending, table[0] <= v).
+__device__ __forceinline__ int last_le(const uint32_t *table, int count, uint32_t v) {
+    int L = 0, R = count - 1;
+    while (L < R) {
+        const int m = (L + R + 1) >> 1;
+        if (table[m] <= v) L = m;
+        else R = m - 1;
+    }
+    return L;
+}
+
+// Gathers val[k] = src[slot[k]] for the CHUNK slots of one workgroup whose
+// slots form, per group d (of `groups`, group d owning [first[d], first[d+1])),
+// one run of consecutive values.  The runs are read into LDS with consecutive
+// lanes on consecutive slots, so a wavefront touches a few lines instead of
+// one line per lane; each lane then picks its value from LDS.  Lanes with
+// valid[k] false get -1.
+struct RunGather {
+    uint32_t first[MAX_DIGITS + 1], rlo[MAX_DIGITS], cnt[MAX_DIGITS], off[MAX_DIGITS], tmp[MAX_DIGITS];
+    uint16_t grp[CHUNK];
+    int32_t val[CHUNK];
+};
+
+__device__ void run_gather(RunGather &sh, int groups, const uint32_t (&slot)[PART_PER], const bool (&valid)[PART_PER],
+                           const int32_t *__restrict__ src, int32_t (&out)[PART_PER]) {
+    for (int d = threadIdx.x; d < groups; d += blockDim.x) {
+        sh.cnt[d] = 0u;
+        sh.rlo[d] = 0xffffffffu;
+    }
+    __syncthreads();
+    int gd[PART_PER];
+#pragma unroll
+    for (int k = 0; k < PART_PER; ++k) {
+        gd[k] = -1;
+        if (valid[k]) {
+            gd[k] = last_le(sh.first, groups, slot[k]);
+            atomicAdd(&sh.cnt[gd[k]], 1u);
+            atomicMin(&sh.rlo[gd[k]], slot[k]);
+        }
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < groups; d += blockDim.x) sh.off[d] = sh.cnt[d];
+    __syncthreads();
+    const uint32_t total = block_exclusive_scan(sh.off, sh.tmp, groups);
+    uint32_t at[PART_PER];
+#pragma unroll
+    for (int k = 0; k < PART_PER; ++k) {
+        at[k] = 0xffffffffu;
+        if (gd[k] >= 0) {
+            const uint32_t p = sh.off[gd[k]] + (slot[k] - sh.rlo[gd[k]]);
+            if (p < total) {  // always: a run holds exactly cnt consecutive slots
+                sh.grp[p] = uint16_t(gd[k]);
+                at[k] = p;
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < total; s += blockDim.x) {
+        const int d = sh.grp[s];
+        sh.val[s] = src[sh.rlo[d] + (s - sh.off[d])];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PART_PER; ++k) out[k] = at[k] != 0xffffffffu ? sh.val[at[k]] : -1;
+}
+
+// Pass 2, level-1 order: lab1[j] = lab2[map12[j]].  Workgroup w is level-2
+// scatter chunk w (CHUNK records of one bucket), whose level-2 slots form one
+// run per tile of the bucket.
+__global__ void __launch_bounds__(PART_THREADS) to_level1_kernel(const uint32_t *__restrict__ map12,
+                                                                 const uint32_t *__restrict__ start1,
+                                                                 const uint32_t *__restrict__ chunk_first,
+                                                                 const uint32_t *__restrict__ start2, int nbuckets,
+                                                                 int digits, const int32_t *__restrict__ lab2,
+                                                                 int32_t *__restrict__ lab1) {
+    __shared__ RunGather sh;
+    const uint32_t w = blockIdx.x;
+    if (w >= chunk_first[nbuckets]) return;
+    const int b = last_le(chunk_first, nbuckets, w);
+    const int64_t lo = int64_t(start1[b]) + int64_t(w - chunk_first[b]) * CHUNK;
+    const int64_t end = start1[b + 1];
+    const int64_t hi = lo + CHUNK < end ? lo + CHUNK : end;
+    for (int d = threadIdx.x; d <= digits; d += blockDim.x) sh.first[d] = start2[b * digits + d];
+    uint32_t m[PART_PER];
+    bool ok[PART_PER];
+#pragma unroll
+    for (int k = 0; k < PART_PER; ++k) {
+        const int64_t j = lo + k * PART_THREADS + threadIdx.x;
+        ok[k] = j < hi;
+        m[k] = ok[k] ? map12[j] : 0u;
+    }
+    int32_t v[PART_PER];
+    run_gather(sh, digits, m, ok, lab2, v);
+#pragma unroll
+    for (int k = 0; k < PART_PER; ++k)
+        if (ok[k]) lab1[lo + k * PART_THREADS + threadIdx.x] = v[k];
+}
+
+// Pass 3, input order: particle i -> lab1[slot1[i]] (-1 for a rejected
+// position).  Workgroup c is level-1 scatter chunk c, whose slots form one run
+// per bucket.
+__global__ void __launch_bounds__(PART_THREADS) to_input_kernel(const uint32_t *__restrict__ slot1, int64_t np,
+                                                                const uint32_t *__restrict__ start1, int nbuckets,
+                                                                const int32_t *__restrict__ lab1,
+                                                                int32_t *__restrict__ out) {
+    __shared__ RunGather sh;
+    const int64_t base = int64_t(blockIdx.x) * CHUNK;
+    for (int d = threadIdx.x; d <= nbuckets; d += blockDim.x) sh.first[d] = start1[d];
+    uint32_t sl[PART_PER];
+    bool ok[PART_PER];
+#pragma unroll
+    for (int k = 0; k < PART_PER; ++k) {
+        const int64_t i = base + k * PART_THREADS + threadIdx.x;
+        sl[k] = i < np ? slot1[i] : NO_SLOT;
+        ok[k] = sl[k] != NO_SLOT;
+    }
+    int32_t v[PART_PER];
+    run_gather(sh, nbuckets, sl, ok, lab1, v);
+#pragma unroll
+    for (int k = 0; k < PART_PER; ++k) {
+        const int64_t i = base + k * PART_THREADS + threadIdx.x;
+        if (i < np) out[i] = v[k];
+    }
+}
+
 // Tile and bucket shape for an n^3 grid; false if the binned form cannot hold it
 // (at most MAX_DIGITS tiles per bucket and MAX_DIGITS buckets).
 bool make_geom(const hf_box &box, Geom &out) {
@@ -672,7 +895,9 @@ struct DepLayout {
     size_t count1, start1, cursor1, chunk_first, hchunk_first, count2, start2, cursor2, rec1, rec2, skirt, total;
 };
 
-DepLayout dep_layout(const Geom &g, int64_t np) {
+// Deposit workspace; with keep_order the level-2 records and the bucket and
+// tile offsets live in the ParticleOrder region instead.
+DepLayout dep_layout(const Geom &g, int64_t np, bool keep_order) {
     DepLayout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -681,41 +906,70 @@ DepLayout dep_layout(const Geom &g, int64_t np) {
         return at;
     };
     L.count1 = take(sizeof(uint32_t) * MAX_DIGITS * REPLICAS);
-    L.count2 = take(sizeof(uint32_t) * size_t(g.ntiles));  // count1 and count2 are zeroed together
-    L.start1 = take(sizeof(uint32_t) * (MAX_DIGITS + 1));
+    L.count2 = take(sizeof(uint32_t) * size_t(g.ntiles));
+    L.start1 = take(keep_order ? 0 : sizeof(uint32_t) * (MAX_DIGITS + 1));
     L.cursor1 = take(sizeof(uint32_t) * MAX_DIGITS * REPLICAS);
-    L.chunk_first = take(sizeof(uint32_t) * (MAX_DIGITS + 1));
+    L.chunk_first = take(keep_order ? 0 : sizeof(uint32_t) * (MAX_DIGITS + 1));
     L.hchunk_first = take(sizeof(uint32_t) * (MAX_DIGITS + 1));
-    L.start2 = take(sizeof(uint32_t) * (size_t(g.ntiles) + 1));
+    L.start2 = take(keep_order ? 0 : sizeof(uint32_t) * (size_t(g.ntiles) + 1));
     L.cursor2 = take(sizeof(uint32_t) * size_t(g.ntiles));
     L.rec1 = take(g.nbuckets > 1 ? sizeof(Q3) * size_t(np) : 0);
-    L.rec2 = take(sizeof(uint64_t) * size_t(np));
+    L.rec2 = take(keep_order ? 0 : sizeof(uint64_t) * size_t(np));
     L.skirt = take(sizeof(unsigned long long) * size_t(g.skirt) * size_t(g.ntiles));
+    L.total = off;
+    return L;
+}
+
+// ParticleOrder region: rec2 [np] | start2 [ntiles + 1] | slot1 [np] | map12 [np] |
+// nrec | start1 [513] | chunk_first [513].
+struct OrderLayout {
+    size_t rec2, start2, slot1, map12, nrec, start1, chunk_first, total;
+};
+
+OrderLayout order_layout(const Geom &g, int64_t np) {
+    OrderLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L.rec2 = take(sizeof(uint64_t) * size_t(np));
+    L.start2 = take(sizeof(uint32_t) * (size_t(g.ntiles) + 1));
+    L.slot1 = take(sizeof(uint32_t) * size_t(np));
+    L.map12 = take(sizeof(uint32_t) * size_t(np));
+    L.nrec = take(sizeof(uint32_t));
+    L.start1 = take(sizeof(uint32_t) * (MAX_DIGITS + 1));
+    L.chunk_first = take(sizeof(uint32_t) * (MAX_DIGITS + 1));
     L.total = off;
     return L;
 }
 
 template <typename T>
 hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, unsigned long long *rho,
-                    char *ws) {
+                    char *ws, const ParticleOrder *order) {
     Geom g;
     if (!make_geom(box, g)) return HF_ERR_SIZE;
-    const DepLayout L = dep_layout(g, np);
+    if (order && g.nbuckets < 2) return HF_ERR_ARG;  // no level-1 records to keep
+    const DepLayout L = dep_layout(g, np, order != nullptr);
     auto *count1 = reinterpret_cast<uint32_t *>(ws + L.count1);
     auto *count2 = reinterpret_cast<uint32_t *>(ws + L.count2);
-    auto *start1 = reinterpret_cast<uint32_t *>(ws + L.start1);
+    auto *start1 = order ? order->start1 : reinterpret_cast<uint32_t *>(ws + L.start1);
     auto *cursor1 = reinterpret_cast<uint32_t *>(ws + L.cursor1);
-    auto *chunk_first = reinterpret_cast<uint32_t *>(ws + L.chunk_first);
+    auto *chunk_first = order ? order->chunk_first : reinterpret_cast<uint32_t *>(ws + L.chunk_first);
     auto *hchunk_first = reinterpret_cast<uint32_t *>(ws + L.hchunk_first);
-    auto *start2 = reinterpret_cast<uint32_t *>(ws + L.start2);
+    auto *start2 = order ? order->start2 : reinterpret_cast<uint32_t *>(ws + L.start2);
     auto *cursor2 = reinterpret_cast<uint32_t *>(ws + L.cursor2);
     auto *rec1 = reinterpret_cast<Q3 *>(ws + L.rec1);
-    auto *rec2 = reinterpret_cast<uint64_t *>(ws + L.rec2);
+    auto *rec2 = order ? order->rec2 : reinterpret_cast<uint64_t *>(ws + L.rec2);
     auto *skirt = reinterpret_cast<unsigned long long *>(ws + L.skirt);
+    uint32_t *slot1 = order ? order->slot1 : nullptr;
+    uint32_t *map12 = order ? order->map12 : nullptr;
+    uint32_t *nrec = order ? order->nrec : nullptr;
     hipStream_t st = ctx->stream;
     const FixedPoint<T> fp = make_fixed_point<T>(box);
-    const int64_t zero_count = int64_t((L.start1 - L.count1) / sizeof(uint32_t));
-    HF_LAUNCH(ctx, K_DEP_PREP, zero_u32_kernel, dim3(64), dim3(256), 0, st, count1, zero_count);
+    HF_LAUNCH(ctx, K_DEP_PREP, zero_u32_kernel, dim3(64), dim3(256), 0, st, count1, int64_t(MAX_DIGITS * REPLICAS));
+    HF_LAUNCH(ctx, K_DEP_PREP, zero_u32_kernel, dim3(64), dim3(256), 0, st, count2, int64_t(g.ntiles));
     const unsigned part_blocks = unsigned((np + CHUNK - 1) / CHUNK);
     const unsigned hist_blocks = unsigned((np + HCHUNK - 1) / HCHUNK);
     if (g.nbuckets > 1) {
@@ -723,17 +977,17 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
             HF_LAUNCH(ctx, K_DEP_L1_HIST, l1_hist_kernel<T>, dim3(hist_blocks), dim3(PART_THREADS), 0, st, pos, np,
                       fp, g, count1, ctx->d_status);
         HF_LAUNCH(ctx, K_DEP_PREP, l1_scan_kernel, dim3(1), dim3(MAX_DIGITS), 0, st, count1, g.nbuckets, start1,
-                  cursor1, chunk_first, hchunk_first);
+                  cursor1, chunk_first, hchunk_first, nrec);
         if (part_blocks)
-            HF_LAUNCH(ctx, K_DEP_L1_SCATTER, l1_scatter_kernel<T>, dim3(part_blocks), dim3(PART_THREADS), 0, st, pos,
-                      np, fp, g, cursor1, rec1);
+            HF_LAUNCH(ctx, K_DEP_L1_SCATTER, l1_scatter_kernel<T>, dim3(replica_grid(part_blocks)),
+                      dim3(PART_THREADS), 0, st, pos, np, fp, g, cursor1, rec1, slot1);
         const L2Input<T, true> hin{pos, np, fp, rec1, start1, hchunk_first, g.nbuckets, HCHUNK};
         const L2Input<T, true> sin{pos, np, fp, rec1, start1, chunk_first, g.nbuckets, CHUNK};
         HF_LAUNCH(ctx, K_DEP_L2_HIST, (l2_hist_kernel<T, true>), dim3(hist_blocks + unsigned(g.nbuckets)),
                   dim3(PART_THREADS), 0, st, hin, g, count2, ctx->d_status);
         HF_LAUNCH(ctx, K_DEP_PREP, l2_scan_kernel, dim3(1), dim3(1024), 0, st, count2, g.ntiles, start2, cursor2);
         HF_LAUNCH(ctx, K_DEP_L2_SCATTER, (l2_scatter_kernel<T, true>), dim3(part_blocks + unsigned(g.nbuckets)),
-                  dim3(PART_THREADS), 0, st, sin, g, cursor2, rec2);
+                  dim3(PART_THREADS), 0, st, sin, g, cursor2, rec2, map12);
     } else {
         const L2Input<T, false> hin{pos, np, fp, nullptr, nullptr, nullptr, 1, HCHUNK};
         const L2Input<T, false> sin{pos, np, fp, nullptr, nullptr, nullptr, 1, CHUNK};
@@ -743,7 +997,7 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
         HF_LAUNCH(ctx, K_DEP_PREP, l2_scan_kernel, dim3(1), dim3(1024), 0, st, count2, g.ntiles, start2, cursor2);
         if (part_blocks)
             HF_LAUNCH(ctx, K_DEP_L2_SCATTER, (l2_scatter_kernel<T, false>), dim3(part_blocks), dim3(PART_THREADS),
-                      0, st, sin, g, cursor2, rec2);
+                      0, st, sin, g, cursor2, rec2, nullptr);
     }
     HF_LAUNCH(ctx, K_DEPOSIT, tile_accum_kernel, dim3(g.ntiles), dim3(ACC_THREADS), 0, st, rec2, start2, g, rho,
               skirt, ctx->d_status);
@@ -761,14 +1015,62 @@ bool hf::deposit_tiled_supported(const hf_box &box, int64_t np) {
     return make_geom(box, g);
 }
 
-size_t hf::deposit_tiled_ws_bytes(const hf_box &box, int64_t np) {
+size_t hf::deposit_tiled_ws_bytes(const hf_box &box, int64_t np, bool keep_order) {
     Geom g;
-    return make_geom(box, g) ? dep_layout(g, np).total : 0;
+    return make_geom(box, g) ? dep_layout(g, np, keep_order).total : 0;
 }
 
 hf_status hf::deposit_tiled(hf_ctx *ctx, const hf_box &box, const void *pos, hf_dtype dtype, int64_t np,
-                            int64_t *rho, void *ws) {
+                            int64_t *rho, void *ws, const ParticleOrder *order) {
     auto *grid = reinterpret_cast<unsigned long long *>(rho);
-    if (dtype == HF_F32) return run_tiled<float>(ctx, box, static_cast<const float *>(pos), np, grid, static_cast<char *>(ws));
-    return run_tiled<double>(ctx, box, static_cast<const double *>(pos), np, grid, static_cast<char *>(ws));
+    char *w = static_cast<char *>(ws);
+    if (dtype == HF_F32) return run_tiled<float>(ctx, box, static_cast<const float *>(pos), np, grid, w, order);
+    return run_tiled<double>(ctx, box, static_cast<const double *>(pos), np, grid, w, order);
+}
+
+bool hf::particle_order_supported(const hf_box &box, int64_t np) {
+    Geom g;
+    return np > 0 && deposit_tiled_supported(box, np) && make_geom(box, g) && g.nbuckets > 1;
+}
+
+size_t hf::particle_order_bytes(const hf_box &box, int64_t np) {
+    Geom g;
+    return make_geom(box, g) ? order_layout(g, np).total : 0;
+}
+
+hf::ParticleOrder hf::particle_order_at(const hf_box &box, void *base, int64_t np) {
+    Geom g;
+    ParticleOrder o{};
+    if (!make_geom(box, g)) return o;
+    const OrderLayout L = order_layout(g, np);
+    char *p = static_cast<char *>(base);
+    o.rec2 = reinterpret_cast<uint64_t *>(p + L.rec2);
+    o.start2 = reinterpret_cast<uint32_t *>(p + L.start2);
+    o.slot1 = reinterpret_cast<uint32_t *>(p + L.slot1);
+    o.map12 = reinterpret_cast<uint32_t *>(p + L.map12);
+    o.nrec = reinterpret_cast<uint32_t *>(p + L.nrec);
+    o.start1 = reinterpret_cast<uint32_t *>(p + L.start1);
+    o.chunk_first = reinterpret_cast<uint32_t *>(p + L.chunk_first);
+    return o;
+}
+
+size_t hf::label_scratch_bytes(int64_t np) { return 2 * align_up(sizeof(int32_t) * size_t(np)); }
+
+hf_status hf::label_from_order(hf_ctx *ctx, const hf_box &box, int64_t np, const ParticleOrder &order,
+                               const int32_t *cell_label, int32_t *particle_label, void *scratch) {
+    if (np <= 0) return HF_OK;
+    Geom g;
+    if (!make_geom(box, g)) return HF_ERR_SIZE;
+    auto *lab2 = static_cast<int32_t *>(scratch);
+    auto *lab1 = reinterpret_cast<int32_t *>(static_cast<char *>(scratch) + align_up(sizeof(int32_t) * size_t(np)));
+    const unsigned blocks = unsigned((np + CHUNK - 1) / CHUNK);
+    HF_LAUNCH(ctx, K_LABEL_TILES, tile_label_kernel, dim3(g.ntiles), dim3(ACC_THREADS), 0, ctx->stream, order.rec2,
+              order.start2, g, cell_label, lab2);
+    // level-2 scatter chunks: at most one partial chunk per bucket beyond np / CHUNK
+    HF_LAUNCH(ctx, K_LABEL_LEVEL1, to_level1_kernel, dim3(blocks + unsigned(g.nbuckets)), dim3(PART_THREADS), 0,
+              ctx->stream, order.map12, order.start1, order.chunk_first, order.start2, g.nbuckets, g.digits, lab2,
+              lab1);
+    HF_LAUNCH(ctx, K_LABEL_INPUT, to_input_kernel, dim3(blocks), dim3(PART_THREADS), 0, ctx->stream, order.slot1, np,
+              order.start1, g.nbuckets, lab1, particle_label);
+    return launch_status();
 }

@@ -18,6 +18,7 @@ enum KernelId {
     K_TABLES_1, K_TABLES_2, K_X_FWD, K_MASS, K_Y_FWD, K_Z_MUL, K_Y_INV, K_X_INV,
     K_MAX_MARK, K_MAX_COUNT, K_MAX_SCAN, K_MAX_WRITE,
     K_PARENT, K_FLAGS, K_JUMP, K_FINALIZE,
+    K_LABEL_TILES, K_LABEL_LEVEL1, K_LABEL_INPUT,
     K_COUNT
 };
 const char *kernel_name(int id);
@@ -113,11 +114,37 @@ inline hf_status launch_status() {
     return hipGetLastError() == hipSuccess ? HF_OK : HF_ERR_DEVICE;
 }
 
-// Binned deposit (n % 16 == 0, B <= 17, np < 2^32).
+// The binned deposit's particle order, kept for the label stage: the level-2
+// records (tile order) and tile offsets, every particle's level-1 slot
+// (0xffffffff for a rejected position), every level-1 record's level-2 slot and
+// the number of records.  Lives in a caller workspace region of
+// particle_order_bytes(box, np).
+struct ParticleOrder {
+    uint64_t *rec2;
+    uint32_t *start2;
+    uint32_t *slot1;
+    uint32_t *map12;
+    uint32_t *nrec;
+    uint32_t *start1;       // [513] first record of each bucket
+    uint32_t *chunk_first;  // [513] first level-2 scatter chunk of each bucket
+};
+bool particle_order_supported(const hf_box &box, int64_t np);  // binned, more than one bucket
+size_t particle_order_bytes(const hf_box &box, int64_t np);
+ParticleOrder particle_order_at(const hf_box &box, void *base, int64_t np);
+
+// Binned deposit (n % 16 == 0, B <= 17, np < 2^32).  With `order`, the level-2
+// records and tile offsets go to the order region and the slot maps are
+// written; the workspace is then deposit_tiled_ws_bytes(box, np, true).
 bool deposit_tiled_supported(const hf_box &box, int64_t np);
-size_t deposit_tiled_ws_bytes(const hf_box &box, int64_t np);
+size_t deposit_tiled_ws_bytes(const hf_box &box, int64_t np, bool keep_order = false);
 hf_status deposit_tiled(hf_ctx *ctx, const hf_box &box, const void *pos, hf_dtype dtype, int64_t np, int64_t *rho,
-                        void *ws);
+                        void *ws, const ParticleOrder *order = nullptr);
+
+// Step 6 through a kept particle order, with label_scratch_bytes(np) of
+// scratch.  Same result as hf_label on the positions the order was built from.
+size_t label_scratch_bytes(int64_t np);
+hf_status label_from_order(hf_ctx *ctx, const hf_box &box, int64_t np, const ParticleOrder &order,
+                           const int32_t *cell_label, int32_t *particle_label, void *scratch);
 
 // Workspace requirements of each stage (defined next to each stage).
 size_t deposit_ws_bytes(const hf_box &box, int64_t np);

@@ -19,14 +19,29 @@ extern "C" hf_status hf_find_halos(hf_ctx *ctx, const hf_box *box, const hf_job 
         (job->kernel != HF_KERNEL_SAMPLED && job->kernel != HF_KERNEL_ANALYTIC) || !(job->kw > 0.0) ||
         job->tau != job->tau)
         return HF_ERR_ARG;
-    s = hf_deposit(ctx, box, job->pos, job->dtype, job->np, job->rho, ws, ws_bytes);
+    // With the binned deposit the particle order it builds is kept (in front of
+    // the workspace) and step 6 reuses it; every other stage gets the rest.
+    const bool order = particle_order_supported(*box, job->np);
+    char *sw = static_cast<char *>(ws);
+    size_t sb = ws_bytes;
+    ParticleOrder po{};
+    if (order) {
+        po = particle_order_at(*box, ws, job->np);
+        sw += particle_order_bytes(*box, job->np);
+        sb -= particle_order_bytes(*box, job->np);
+        if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+        s = deposit_tiled(ctx, *box, job->pos, job->dtype, job->np, job->rho, sw, &po);
+    } else {
+        s = hf_deposit(ctx, box, job->pos, job->dtype, job->np, job->rho, sw, sb);
+    }
     if (s != HF_OK) return s;
-    s = hf_cwt(ctx, box, job->rho, job->kw, job->kernel, job->cwt, ws, ws_bytes);
+    s = hf_cwt(ctx, box, job->rho, job->kw, job->kernel, job->cwt, sw, sb);
     if (s != HF_OK) return s;
-    s = hf_maxima(ctx, box, job->cwt, job->tau, job->max_idx, job->max_cap, job->d_count, ws, ws_bytes);
+    s = hf_maxima(ctx, box, job->cwt, job->tau, job->max_idx, job->max_cap, job->d_count, sw, sb);
     if (s != HF_OK) return s;
-    s = hf_segment(ctx, box, job->cwt, job->tau, job->cell_label, ws, ws_bytes);
+    s = hf_segment(ctx, box, job->cwt, job->tau, job->cell_label, sw, sb);
     if (s != HF_OK) return s;
+    if (order) return label_from_order(ctx, *box, job->np, po, job->cell_label, job->particle_label, sw);
     return hf_label(ctx, box, job->pos, job->dtype, job->np, job->cell_label, job->particle_label);
 }
 

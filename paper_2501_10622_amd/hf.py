@@ -19,14 +19,14 @@ HF_OK, HF_ERR_ARG, HF_ERR_SIZE, HF_ERR_WORKSPACE = 0, 1, 2, 3
 HF_ERR_OVERFLOW, HF_ERR_CAPACITY, HF_ERR_DEVICE, HF_ERR_INPUT = 4, 5, 6, 7
 HF_F32, HF_F64 = 0, 1
 KERNELS = {"sampled": 0, "analytic": 1}
-STAGE_DEPOSIT, STAGE_CWT, STAGE_MAXIMA, STAGE_SEGMENT = 1, 2, 4, 8
+STAGE_DEPOSIT, STAGE_CWT, STAGE_MAXIMA, STAGE_SEGMENT, STAGE_LABEL = 1, 2, 4, 8, 16
 
 EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_size",
            "hf_deposit", "hf_cwt", "hf_maxima", "hf_segment", "hf_label",
            "hf_profile_enable", "hf_profile_reset", "hf_profile_read",
            "hf_cwt_batch_ws_size", "hf_cwt_batch", "hf_find_halos", "hf_find_halos_group")
 CWT_BATCH_MAX = 32
-STAGE_ALL = 15
+STAGE_ALL = 31
 
 
 class HFError(RuntimeError):

@@ -70,6 +70,25 @@ def test_workspace_grows_with_n(lib):
     assert sizes[-1] >= 256 * 256 * 129 * 8
 
 
+def test_label_stage_keeps_deposit_order_only_where_binned(lib):
+    dep_seg = hf.STAGE_DEPOSIT | hf.STAGE_CWT | hf.STAGE_MAXIMA | hf.STAGE_SEGMENT
+    assert hf.STAGE_ALL == dep_seg | hf.STAGE_LABEL
+    np_ = 1_000_003
+    # 192^3 and 256^3 bin the particles into several buckets: the order region
+    # (16 B per particle) sits in front of the shared part
+    for n in (192, 256):
+        plain = hfm.workspace_size(n, 10.0, np_, dep_seg)
+        full = hfm.workspace_size(n, 10.0, np_, hf.STAGE_ALL)
+        assert full >= plain + 16 * np_ - 12 * np_  # level-1 records move out of the deposit's own part
+        assert full > plain
+    # a single bucket (64^3) or an unbinned size (B = 18) keeps no order
+    assert hfm.workspace_size(64, 10.0, np_, hf.STAGE_ALL) == hfm.workspace_size(64, 10.0, np_, dep_seg)
+    assert (hfm.workspace_size(256, 10.0, np_, hf.STAGE_ALL, frac_bits=18) ==
+            hfm.workspace_size(256, 10.0, np_, dep_seg, frac_bits=18))
+    # the label bit alone needs nothing
+    assert hfm.workspace_size(256, 10.0, np_, hf.STAGE_LABEL) == 0
+
+
 def test_null_context_rejected_before_any_device_call(lib):
     b = hf.Box(16, 15, 10.0)
     vp = ctypes.c_void_p

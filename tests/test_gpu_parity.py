@@ -255,6 +255,45 @@ def test_end_to_end(n, L, np_, halos, dtype, a, seed):
         assert agree >= LABEL_AGREEMENT
 
 
+@pytest.mark.parametrize("n,L,np_,halos,a,seed,bits", [
+    (192, 187.5, 192 ** 3, 7910, 2.0, 31, 15),      # several deposit buckets: labels through the kept order
+    (256, 250.0, 3_000_000, 18750, 1.5, 32, 15),
+    (288, 300.0, 2_000_001, 30000, 3.0, 33, 12),    # radix-3 grid, odd particle count, other fraction bits
+])
+def test_labels_through_deposit_order(n, L, np_, halos, a, seed, bits):
+    """The one-call pipeline labels particles through the deposit's binned order;
+    its labels must equal the separate label stage's and the oracle's on the
+    same cell labels, bit for bit, including wrapped, edge and rejected positions."""
+    from paper_2501_10622_amd import hf
+    from paper_2501_10622_amd.hf import HFError
+    pos = small_box(n, L, np_, halos, "f32", seed)
+    pos[:7] = np.array([[L, 0.0, 0.0], [-1e-3, L * 0.5, L - 1e-4], [L * 1.5, -L * 0.25, 2 * L],
+                        [np.nextafter(np.float32(L), np.float32(0)), 0.0, 0.0], [0.0, 0.0, 0.0],
+                        [L * 0.999999, L * 0.999999, L * 0.999999], [1e-7, 1e-7, 1e-7]], dtype=np.float32)
+    pos[11] = [np.nan, 1.0, 1.0]
+    kw = n / (1000.0 * a)
+    print(f"order labels n={n} np={np_} B={bits}", flush=True)
+    d = cuda(pos)
+    ctx = hf.context(0)
+    bufs = hf.job_buffers(n, np_, d.device, True, bits)
+    hf.find_halos_async(d, L, n, kw, bufs, frac_bits=bits, ctx=ctx)
+    with pytest.raises(HFError) as e:  # the NaN position is reported ...
+        ctx.sync()
+    assert e.value.code == hf.HF_ERR_INPUT
+    got = bufs["particle_label"][:np_].clone()
+    cell = bufs["cell_label"]
+    alone = torch.empty_like(got)
+    hf.label(d, L, n, cell, out=alone, frac_bits=bits, ctx=ctx)
+    with pytest.raises(HFError):
+        ctx.sync()
+    assert torch.equal(got, alone)
+    g = got.cpu().numpy()
+    assert g[11] == -1  # ... and its particle gets no label
+    ok = np.isfinite(pos).all(axis=1)
+    ref = O.label(pos[ok], L, n, cell.cpu().numpy(), frac_bits=bits)
+    np.testing.assert_array_equal(g[ok], ref)
+
+
 def test_end_to_end_deterministic():
     pos = cuda(small_box(48, 60.0, 200000, 80, "f32", 21))
     a = hfm().find_halos(pos, 60.0, 48, 0.024)
