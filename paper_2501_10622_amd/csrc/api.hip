@@ -171,6 +171,7 @@ extern "C" hf_status hf_workspace_size(const hf_box *box, int64_t np, int stage_
     if (stage_mask & HF_STAGE_CWT) take(cwt_ws_bytes(*box));
     if (stage_mask & HF_STAGE_MAXIMA) take(maxima_ws_bytes(*box));
     if (stage_mask & HF_STAGE_SEGMENT) take(segment_ws_bytes(*box));
+    if ((stage_mask & HF_STAGE_MAXIMA) && (stage_mask & HF_STAGE_SEGMENT)) take(maxima_segment_ws_bytes(*box));
     if (order) take(label_scratch_bytes(np));
     *bytes = (order ? particle_order_bytes(*box, np) : 0) + need;
     return HF_OK;

@@ -146,6 +146,12 @@ size_t label_scratch_bytes(int64_t np);
 hf_status label_from_order(hf_ctx *ctx, const hf_box &box, int64_t np, const ParticleOrder &order,
                            const int32_t *cell_label, int32_t *particle_label, void *scratch);
 
+// Steps 4 and 5 in one pass over the field where the grid is tiled (n % 32 ==
+// 0), else hf_maxima then hf_segment; workspace maxima_segment_ws_bytes(box).
+size_t maxima_segment_ws_bytes(const hf_box &box);
+hf_status maxima_segment(hf_ctx *ctx, const hf_box &box, const float *cwt, float tau, int32_t *max_idx,
+                         int64_t max_cap, int64_t *d_count, int32_t *cell_label, void *ws, size_t ws_bytes);
+
 // Workspace requirements of each stage (defined next to each stage).
 size_t deposit_ws_bytes(const hf_box &box, int64_t np);
 size_t cwt_ws_bytes(const hf_box &box);

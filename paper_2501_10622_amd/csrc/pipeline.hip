@@ -37,9 +37,8 @@ extern "C" hf_status hf_find_halos(hf_ctx *ctx, const hf_box *box, const hf_job 
     if (s != HF_OK) return s;
     s = hf_cwt(ctx, box, job->rho, job->kw, job->kernel, job->cwt, sw, sb);
     if (s != HF_OK) return s;
-    s = hf_maxima(ctx, box, job->cwt, job->tau, job->max_idx, job->max_cap, job->d_count, sw, sb);
-    if (s != HF_OK) return s;
-    s = hf_segment(ctx, box, job->cwt, job->tau, job->cell_label, sw, sb);
+    s = maxima_segment(ctx, *box, job->cwt, job->tau, job->max_idx, job->max_cap, job->d_count, job->cell_label, sw,
+                       sb);
     if (s != HF_OK) return s;
     if (order) return label_from_order(ctx, *box, job->np, po, job->cell_label, job->particle_label, sw);
     return hf_label(ctx, box, job->pos, job->dtype, job->np, job->cell_label, job->particle_label);
@@ -87,10 +86,8 @@ extern "C" hf_status hf_find_halos_group(hf_ctx *ctx, int32_t n, int32_t frac_bi
     for (int j = 0; j < count; ++j) {
         const hf_job &job = items[j].job;
         const hf_box box{n, frac_bits, items[j].box_len};
-        s = hf_maxima(ctx, &box, job.cwt, job.tau, job.max_idx, job.max_cap, job.d_count, items[j].ws,
-                      items[j].ws_bytes);
-        if (s != HF_OK) return s;
-        s = hf_segment(ctx, &box, job.cwt, job.tau, job.cell_label, items[j].ws, items[j].ws_bytes);
+        s = maxima_segment(ctx, box, job.cwt, job.tau, job.max_idx, job.max_cap, job.d_count, job.cell_label,
+                           items[j].ws, items[j].ws_bytes);
         if (s != HF_OK) return s;
         s = hf_label(ctx, &box, job.pos, job.dtype, job.np, job.cell_label, job.particle_label);
         if (s != HF_OK) return s;

@@ -56,7 +56,7 @@ constexpr int TCELLS = TX * TY * TZ;                          // 2048
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
 constexpr int HCELLS = HX * HY * HZ;                          // 3400
 constexpr int NBND = 2 * TX * TY + (TZ - 2) * (2 * TX + 2 * (TY - 2));  // 968 boundary cells per tile
-constexpr int SEG_THREADS = 256;
+constexpr int SEG_THREADS = 512;
 constexpr int PER_THREAD = TCELLS / SEG_THREADS;              // 8
 
 struct TileGrid {
@@ -147,18 +147,10 @@ __device__ __forceinline__ void tile_origin(const TileGrid &tg, int t, int &x0, 
     z0 = (t / (tg.ntx * tg.nty)) * TZ;
 }
 
-// Maxima bit mask: bit (j % 32) of word j / 32 is set iff cell j is a maximum.
-__global__ void __launch_bounds__(SEG_THREADS) max_tile_kernel(const float *__restrict__ c, TileGrid tg,
-                                                               uint32_t tau_ord, uint32_t *__restrict__ mask,
-                                                               uint32_t *status) {
-    __shared__ uint64_t K[HCELLS];
-    __shared__ uint64_t M[TX * HY * HZ];
-    int x0, y0, z0;
-    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    tile_origin(tg, int(tile), x0, y0, z0);
-    bool nan = false;
-    tile_parent_keys(c, tg.n, x0, y0, z0, K, M, nan);
-    const uint32_t n = uint32_t(tg.n);
+// Maxima bit mask of the tile from its parent keys M: bit (j % 32) of word
+// j / 32 is set iff cell j is its own parent with a value above tau.
+__device__ __forceinline__ void write_mask(const uint64_t *M, uint32_t n, int x0, int y0, int z0, uint32_t tau_ord,
+                                           uint32_t *__restrict__ mask) {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
         const int e = i * SEG_THREADS + threadIdx.x;  // a wavefront covers rows (y, z) and (y + 1, z)
@@ -172,13 +164,29 @@ __global__ void __launch_bounds__(SEG_THREADS) max_tile_kernel(const float *__re
             mask[(g + n) >> 5] = uint32_t(bits >> 32);  // next row of the tile
         }
     }
+}
+
+__global__ void __launch_bounds__(SEG_THREADS) max_tile_kernel(const float *__restrict__ c, TileGrid tg,
+                                                               uint32_t tau_ord, uint32_t *__restrict__ mask,
+                                                               uint32_t *status) {
+    __shared__ uint64_t K[HCELLS];
+    __shared__ uint64_t M[TX * HY * HZ];
+    int x0, y0, z0;
+    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    tile_origin(tg, int(tile), x0, y0, z0);
+    bool nan = false;
+    tile_parent_keys(c, tg.n, x0, y0, z0, K, M, nan);
+    write_mask(M, uint32_t(tg.n), x0, y0, z0, tau_ord, mask);
     if (nan) atomicOr(status, ST_INPUT);
 }
 
 // Parents resolved inside the tile.  ptr[g] = the root or the exit target of
-// cell g's chain; bnd[] holds the same for the tile's boundary cells.
+// cell g's chain; bnd[] holds the same for the tile's boundary cells.  With a
+// mask, the tile's maxima bits are written as well (the maxima are exactly the
+// cells that are their own parent, above tau).
 __global__ void __launch_bounds__(SEG_THREADS) seg_tile_kernel(const float *__restrict__ c, TileGrid tg,
                                                                int32_t *__restrict__ ptr, int32_t *__restrict__ bnd,
+                                                               uint32_t tau_ord, uint32_t *__restrict__ mask,
                                                                uint32_t *status) {
     __shared__ uint64_t K[HCELLS];
     __shared__ uint64_t M[TX * HY * HZ];
@@ -188,6 +196,7 @@ __global__ void __launch_bounds__(SEG_THREADS) seg_tile_kernel(const float *__re
     bool nan = false;
     tile_parent_keys(c, tg.n, x0, y0, z0, K, M, nan);
     const uint32_t n = uint32_t(tg.n);
+    if (mask) write_mask(M, n, x0, y0, z0, tau_ord, mask);
     // loc[e] >= 0: pointer to local cell loc[e];  loc[e] < 0: resolved to global -loc[e] - 1
     int32_t *loc = reinterpret_cast<int32_t *>(K);
     for (int e = threadIdx.x; e < TCELLS; e += SEG_THREADS) {
@@ -529,6 +538,77 @@ size_t hf::maxima_ws_bytes(const hf_box &box) { return maxima_layout(box.n).tota
 
 size_t hf::segment_ws_bytes(const hf_box &box) { return segment_layout(box.n).total; }
 
+namespace {
+
+// Count / scan / write passes: maxima bit mask (in the maxima workspace at w8)
+// -> sorted index list and its length.
+hf_status mask_to_list(hf_ctx *ctx, const MaximaLayout &L, char *w8, int32_t *max_idx, int64_t max_cap,
+                       int64_t *d_count) {
+    auto *mask = reinterpret_cast<uint32_t *>(w8 + L.mask);
+    auto *counts = reinterpret_cast<uint32_t *>(w8 + L.counts);
+    auto *offsets = reinterpret_cast<uint32_t *>(w8 + L.offsets);
+    HF_LAUNCH(ctx, K_MAX_COUNT, mask_count_kernel, dim3(L.nchunks), dim3(LIST_CHUNK_WORDS), 0, ctx->stream, mask,
+              L.words, counts);
+    HF_LAUNCH(ctx, K_MAX_SCAN, list_scan_kernel, dim3(1), dim3(1024), 0, ctx->stream, counts, L.nchunks, offsets,
+              max_cap, d_count, ctx->d_status);
+    HF_LAUNCH(ctx, K_MAX_WRITE, list_write_kernel, dim3(L.nchunks), dim3(LIST_CHUNK_WORDS), 0, ctx->stream, mask,
+              L.words, offsets, max_cap, max_idx);
+    return launch_status();
+}
+
+// Pointer-jumping rounds and the final mapping through the boundary array,
+// after seg_tile_kernel has filled ptr and bnd.
+hf_status segment_finish(hf_ctx *ctx, const SegmentLayout &L, char *w8, const TileGrid &tg, const float *cwt,
+                         float tau, int32_t *cell_label) {
+    auto *flags = reinterpret_cast<uint32_t *>(w8 + L.flags);
+    auto *ptr = reinterpret_cast<int32_t *>(w8 + L.ptr);
+    auto *bnd = reinterpret_cast<int32_t *>(w8 + L.bnd);
+    const int g = batched_grid(L.nbnd);
+    for (int r = 0; r < L.rounds; ++r)
+        HF_LAUNCH(ctx, K_JUMP, bnd_jump_kernel, dim3(g), dim3(256), 0, ctx->stream, bnd, L.nbnd, tg, flags, r);
+    const int64_t cells = int64_t(tg.n) * tg.n * tg.n;
+    HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel, dim3(batched_grid(cells)), dim3(256), 0, ctx->stream, ptr, bnd,
+              cwt, tg, tau, cell_label);
+    return launch_status();
+}
+
+}  // namespace
+
+size_t hf::maxima_segment_ws_bytes(const hf_box &box) {
+    return segment_layout(box.n).total + maxima_layout(box.n).total;
+}
+
+// Steps 4 and 5 together: on tiled grids one pass over the field yields both
+// the parents and the maxima mask.  Same results as hf_maxima then hf_segment.
+hf_status hf::maxima_segment(hf_ctx *ctx, const hf_box &box, const float *cwt, float tau, int32_t *max_idx,
+                             int64_t max_cap, int64_t *d_count, int32_t *cell_label, void *ws, size_t ws_bytes) {
+    const int n = box.n;
+    if (!tiled(n)) {
+        hf_status s = hf_maxima(ctx, &box, cwt, tau, max_idx, max_cap, d_count, ws, ws_bytes);
+        if (s != HF_OK) return s;
+        return hf_segment(ctx, &box, cwt, tau, cell_label, ws, ws_bytes);
+    }
+    if (!ctx || !cwt || !d_count || !cell_label || max_cap < 0 || (max_cap > 0 && !max_idx) || tau != tau)
+        return HF_ERR_ARG;
+    const SegmentLayout SL = segment_layout(n);
+    const MaximaLayout ML = maxima_layout(n);
+    hf_status s = check_ws(ws, ws_bytes, SL.total + ML.total);
+    if (s != HF_OK) return s;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    char *w8 = static_cast<char *>(ws);
+    char *wm = w8 + SL.total;
+    const TileGrid tg = tile_grid(n);
+    auto *flags = reinterpret_cast<uint32_t *>(w8 + SL.flags);
+    HF_LAUNCH(ctx, K_FLAGS, fill_flags_kernel, dim3((SL.rounds + 2 + 255) / 256), dim3(256), 0, ctx->stream, flags,
+              SL.rounds + 2);
+    HF_LAUNCH(ctx, K_PARENT, seg_tile_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(SEG_THREADS), 0, ctx->stream, cwt,
+              tg, reinterpret_cast<int32_t *>(w8 + SL.ptr), reinterpret_cast<int32_t *>(w8 + SL.bnd),
+              host_ordered_bits(tau), reinterpret_cast<uint32_t *>(wm + ML.mask), ctx->d_status);
+    s = mask_to_list(ctx, ML, wm, max_idx, max_cap, d_count);
+    if (s != HF_OK) return s;
+    return segment_finish(ctx, SL, w8, tg, cwt, tau, cell_label);
+}
+
 extern "C" hf_status hf_maxima(hf_ctx *ctx, const hf_box *box, const float *cwt, float tau, int32_t *max_idx,
                                int64_t max_cap, int64_t *d_count, void *ws, size_t ws_bytes) {
     if (!ctx || !cwt || !d_count || max_cap < 0 || (max_cap > 0 && !max_idx)) return HF_ERR_ARG;
@@ -541,8 +621,6 @@ extern "C" hf_status hf_maxima(hf_ctx *ctx, const hf_box *box, const float *cwt,
     if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
     char *w8 = static_cast<char *>(ws);
     auto *mask = reinterpret_cast<uint32_t *>(w8 + L.mask);
-    auto *counts = reinterpret_cast<uint32_t *>(w8 + L.counts);
-    auto *offsets = reinterpret_cast<uint32_t *>(w8 + L.offsets);
     const int n = box->n;
     if (tiled(n)) {
         const TileGrid tg = tile_grid(n);
@@ -553,13 +631,7 @@ extern "C" hf_status hf_maxima(hf_ctx *ctx, const hf_box *box, const float *cwt,
         HF_LAUNCH(ctx, K_MAX_MARK, max_direct_kernel, dim3(stride_grid(cells)), dim3(256), 0, ctx->stream, cwt, n,
                   tau, mask, ctx->d_status);
     }
-    HF_LAUNCH(ctx, K_MAX_COUNT, mask_count_kernel, dim3(L.nchunks), dim3(LIST_CHUNK_WORDS), 0, ctx->stream, mask,
-              L.words, counts);
-    HF_LAUNCH(ctx, K_MAX_SCAN, list_scan_kernel, dim3(1), dim3(1024), 0, ctx->stream, counts, L.nchunks, offsets,
-              max_cap, d_count, ctx->d_status);
-    HF_LAUNCH(ctx, K_MAX_WRITE, list_write_kernel, dim3(L.nchunks), dim3(LIST_CHUNK_WORDS), 0, ctx->stream, mask,
-              L.words, offsets, max_cap, max_idx);
-    return launch_status();
+    return mask_to_list(ctx, L, w8, max_idx, max_cap, d_count);
 }
 
 extern "C" hf_status hf_segment(hf_ctx *ctx, const hf_box *box, const float *cwt, float tau, int32_t *cell_label,
@@ -582,13 +654,8 @@ extern "C" hf_status hf_segment(hf_ctx *ctx, const hf_box *box, const float *cwt
         auto *ptr = reinterpret_cast<int32_t *>(w8 + L.ptr);
         auto *bnd = reinterpret_cast<int32_t *>(w8 + L.bnd);
         HF_LAUNCH(ctx, K_PARENT, seg_tile_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(SEG_THREADS), 0, ctx->stream,
-                  cwt, tg, ptr, bnd, ctx->d_status);
-        const int g = batched_grid(L.nbnd);
-        for (int r = 0; r < L.rounds; ++r)
-            HF_LAUNCH(ctx, K_JUMP, bnd_jump_kernel, dim3(g), dim3(256), 0, ctx->stream, bnd, L.nbnd, tg, flags, r);
-        const int64_t cells = int64_t(n) * n * n;
-        HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel, dim3(batched_grid(cells)), dim3(256), 0, ctx->stream, ptr,
-                  bnd, cwt, tg, tau, cell_label);
+                  cwt, tg, ptr, bnd, 0u, nullptr, ctx->d_status);
+        return segment_finish(ctx, L, w8, tg, cwt, tau, cell_label);
     } else {
         const uint32_t cells = uint32_t(n) * n * n;
         const int g = stride_grid(cells);

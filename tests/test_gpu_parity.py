@@ -292,6 +292,14 @@ def test_labels_through_deposit_order(n, L, np_, halos, a, seed, bits):
     ok = np.isfinite(pos).all(axis=1)
     ref = O.label(pos[ok], L, n, cell.cpu().numpy(), frac_bits=bits)
     np.testing.assert_array_equal(g[ok], ref)
+    # the one-call pipeline finds maxima and segments in one pass over the
+    # field: same results as the separate stages on its own CWT
+    cnt = int(bufs["count"].item())
+    mx_alone = hf.maxima(bufs["cwt"], 0.0, ctx=ctx)
+    cell_alone = hf.segment(bufs["cwt"], 0.0, ctx=ctx)
+    ctx.sync()
+    assert torch.equal(bufs["maxima"][:cnt], mx_alone)
+    assert torch.equal(cell, cell_alone)
 
 
 def test_end_to_end_deterministic():
