@@ -17,8 +17,12 @@
 //    doubling in LDS, so every cell ends at a root or at the first cell its
 //    chain reaches outside the tile.  Such exit targets are always on a tile
 //    boundary, so only the 968 boundary cells of each tile (kept in a compact
-//    array) take part in the global pointer-jumping rounds; a last pass maps
-//    every cell through them to its root and applies tau.
+//    array) take part in the global pointer-jumping rounds.  A root at or
+//    below tau is written as -1 by its own tile, so the rounds carry the
+//    threshold along and no later pass reads the field again.  A last pass,
+//    one workgroup per tile, loads the resolved entries of the one-cell shell
+//    around the tile (every exit target lies in it) into LDS and maps each
+//    cell of the tile through them.
 // Other sizes use direct per-cell kernels with the same results.
 #include "hf_internal.h"
 
@@ -197,18 +201,22 @@ __global__ void __launch_bounds__(SEG_THREADS) seg_tile_kernel(const float *__re
     tile_parent_keys(c, tg.n, x0, y0, z0, K, M, nan);
     const uint32_t n = uint32_t(tg.n);
     if (mask) write_mask(M, n, x0, y0, z0, tau_ord, mask);
-    // loc[e] >= 0: pointer to local cell loc[e];  loc[e] < 0: resolved to global -loc[e] - 1
+    // loc[e] >= 0: pointer to local cell loc[e];  loc[e] < 0: resolved, with
+    // u = -loc[e] - 1 either a local root index (u < TCELLS) or EXIT | global
+    // index of the first cell outside the tile (n^3 <= 2^30 leaves bit 30 free)
+    constexpr uint32_t EXIT = 1u << 30;
     int32_t *loc = reinterpret_cast<int32_t *>(K);
     for (int e = threadIdx.x; e < TCELLS; e += SEG_THREADS) {
         const int x = e % TX, y = (e / TX) % TY, z = e / (TX * TY);
         const uint32_t g = ((uint32_t(z0 + z) * n) + uint32_t(y0 + y)) * n + uint32_t(x0 + x);
         const uint32_t p = uint32_t(M[e]);
-        int32_t v = -int32_t(p) - 1;
+        int32_t v = -int32_t(e) - 1;  // a root
         if (p != g) {
             uint32_t px, py, pz;
             cell_coords(tg, p, px, py, pz);
             const int lx = int(px) - x0, ly = int(py) - y0, lz = int(pz) - z0;
-            if (lx >= 0 && lx < TX && ly >= 0 && ly < TY && lz >= 0 && lz < TZ) v = lx + TX * (ly + TY * lz);
+            v = (lx >= 0 && lx < TX && ly >= 0 && ly < TY && lz >= 0 && lz < TZ) ? lx + TX * (ly + TY * lz)
+                                                                                  : -int32_t(EXIT | p) - 1;
         }
         loc[e] = v;
     }
@@ -232,7 +240,16 @@ __global__ void __launch_bounds__(SEG_THREADS) seg_tile_kernel(const float *__re
     for (int e = threadIdx.x; e < TCELLS; e += SEG_THREADS) {
         const int x = e % TX, y = (e / TX) % TY, z = e / (TX * TY);
         const uint32_t g = ((uint32_t(z0 + z) * n) + uint32_t(y0 + y)) * n + uint32_t(x0 + x);
-        const int32_t t = -loc[e] - 1;
+        const uint32_t u = uint32_t(-loc[e] - 1);
+        int32_t t;
+        if (u & EXIT) {
+            t = int32_t(u & ~EXIT);
+        } else {  // a root of this tile: its own key is M[u]; -1 unless above tau
+            const int rx = int(u) % TX, ry = (int(u) / TX) % TY, rz = int(u) / (TX * TY);
+            t = uint32_t(M[u] >> 32) > tau_ord
+                    ? int32_t(((uint32_t(z0 + rz) * n) + uint32_t(y0 + ry)) * n + uint32_t(x0 + rx))
+                    : -1;
+        }
         ptr[g] = t;
         const int r = bnd_rank(x, y, z);
         if (r >= 0) bnd[int64_t(tile) * NBND + r] = t;
@@ -265,7 +282,8 @@ __global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd
 #pragma unroll
         for (int i = 0; i < BATCH; ++i) {
             const int64_t k = k0 + int64_t(i) * blockDim.x;
-            s[i] = k < count ? bnd_slot(tg, p[i]) : -1;  // an interior target is a root
+            // -1 (a root at or below tau) and interior targets (roots) are final
+            s[i] = k < count && p[i] >= 0 ? bnd_slot(tg, p[i]) : -1;
             q[i] = s[i] >= 0 ? bnd[s[i]] : p[i];
         }
 #pragma unroll
@@ -280,32 +298,58 @@ __global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd
     if (__any(changed) && (threadIdx.x & 63) == 0) flags[round + 1] = 1u;
 }
 
-__global__ void __launch_bounds__(256) seg_finalize_kernel(const int32_t *__restrict__ ptr,
-                                                           const int32_t *__restrict__ bnd,
-                                                           const float *__restrict__ c, TileGrid tg, float tau,
-                                                           int32_t *__restrict__ label) {
-    const int64_t cells = int64_t(tg.n) * tg.n * tg.n;
-    const int64_t step = int64_t(gridDim.x) * blockDim.x * BATCH;
-    for (int64_t j0 = blockIdx.x * int64_t(blockDim.x) * BATCH + threadIdx.x; j0 < cells; j0 += step) {
-        int32_t t[BATCH], r[BATCH];
-        float v[BATCH];
+// One workgroup per tile: the resolved boundary entries of the one-cell shell
+// around the tile go to LDS (they belong to the neighbouring tiles; every exit
+// target of the tile lies in the shell), then every cell of the tile maps its
+// pointer: -1 stays -1, a target inside the tile is a root above tau, a target
+// in the shell takes the shell's entry.
+__global__ void __launch_bounds__(SEG_THREADS) seg_finalize_kernel(const int32_t *__restrict__ ptr,
+                                                                   const int32_t *__restrict__ bnd, TileGrid tg,
+                                                                   int32_t *__restrict__ label) {
+    __shared__ int32_t shell[HCELLS];
+    int x0, y0, z0;
+    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    tile_origin(tg, int(tile), x0, y0, z0);
+    const int n = tg.n;
+    // shell cells: halo coordinates (hx, hy, hz) with at least one on the rim;
+    // all loads are issued before any is stored
+    constexpr int LOADS = (HCELLS + SEG_THREADS - 1) / SEG_THREADS;
+    int32_t v[LOADS];
+    bool rim[LOADS];
 #pragma unroll
-        for (int i = 0; i < BATCH; ++i) {
-            const int64_t j = j0 + int64_t(i) * blockDim.x;
-            t[i] = j < cells ? ptr[j] : 0;
+    for (int i = 0; i < LOADS; ++i) {
+        const int e = threadIdx.x + i * SEG_THREADS;
+        const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
+        rim[i] = e < HCELLS && (hx == 0 || hx == HX - 1 || hy == 0 || hy == HY - 1 || hz == 0 || hz == HZ - 1);
+        if (rim[i]) {
+            const uint32_t gx = wrap(x0 + hx - 1, n), gy = wrap(y0 + hy - 1, n), gz = wrap(z0 + hz - 1, n);
+            const int r = bnd_rank(int(gx % TX), int(gy % TY), int(gz % TZ));  // on its tile's boundary
+            const int64_t t = (int64_t(gz / TZ) * tg.nty + gy / TY) * tg.ntx + gx / TX;
+            v[i] = bnd[t * NBND + r];
         }
+    }
 #pragma unroll
-        for (int i = 0; i < BATCH; ++i) {
-            const int64_t s = bnd_slot(tg, t[i]);
-            r[i] = s < 0 ? t[i] : bnd[s];
+    for (int i = 0; i < LOADS; ++i)
+        if (rim[i]) shell[threadIdx.x + i * SEG_THREADS] = v[i];
+    __syncthreads();
+    const uint32_t un = uint32_t(n);
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; ++i) {
+        const int e = i * SEG_THREADS + threadIdx.x;
+        const int x = e % TX, y = (e / TX) % TY, z = e / (TX * TY);
+        const uint32_t g = ((uint32_t(z0 + z) * un) + uint32_t(y0 + y)) * un + uint32_t(x0 + x);
+        const int32_t t = ptr[g];
+        int32_t r = t;
+        if (t >= 0) {
+            uint32_t px, py, pz;
+            cell_coords(tg, uint32_t(t), px, py, pz);
+            // halo coordinates of the target, periodic
+            const int hx = int(wrap(int(px) - x0 + 1, n)), hy = int(wrap(int(py) - y0 + 1, n)),
+                      hz = int(wrap(int(pz) - z0 + 1, n));
+            const bool inside = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY && hz >= 1 && hz <= TZ;
+            if (!inside) r = shell[(hz * HY + hy) * HX + hx];
         }
-#pragma unroll
-        for (int i = 0; i < BATCH; ++i) v[i] = c[r[i]];
-#pragma unroll
-        for (int i = 0; i < BATCH; ++i) {
-            const int64_t j = j0 + int64_t(i) * blockDim.x;
-            if (j < cells) label[j] = v[i] > tau ? r[i] : -1;
-        }
+        label[g] = r;
     }
 }
 
@@ -566,9 +610,8 @@ hf_status segment_finish(hf_ctx *ctx, const SegmentLayout &L, char *w8, const Ti
     const int g = batched_grid(L.nbnd);
     for (int r = 0; r < L.rounds; ++r)
         HF_LAUNCH(ctx, K_JUMP, bnd_jump_kernel, dim3(g), dim3(256), 0, ctx->stream, bnd, L.nbnd, tg, flags, r);
-    const int64_t cells = int64_t(tg.n) * tg.n * tg.n;
-    HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel, dim3(batched_grid(cells)), dim3(256), 0, ctx->stream, ptr, bnd,
-              cwt, tg, tau, cell_label);
+    HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(SEG_THREADS), 0,
+              ctx->stream, ptr, bnd, tg, cell_label);
     return launch_status();
 }
 
@@ -654,7 +697,7 @@ extern "C" hf_status hf_segment(hf_ctx *ctx, const hf_box *box, const float *cwt
         auto *ptr = reinterpret_cast<int32_t *>(w8 + L.ptr);
         auto *bnd = reinterpret_cast<int32_t *>(w8 + L.bnd);
         HF_LAUNCH(ctx, K_PARENT, seg_tile_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(SEG_THREADS), 0, ctx->stream,
-                  cwt, tg, ptr, bnd, 0u, nullptr, ctx->d_status);
+                  cwt, tg, ptr, bnd, host_ordered_bits(tau), nullptr, ctx->d_status);
         return segment_finish(ctx, L, w8, tg, cwt, tau, cell_label);
     } else {
         const uint32_t cells = uint32_t(n) * n * n;
