@@ -7,7 +7,7 @@
 //             row, complex FFT along x, split into two half-spectrum rows;
 //             also the exact 128-bit mass of the rows.
 //   mass    : sums the row masses, mean density in FP64 -> overall scale.
-//   y_pass  : complex FFT along y on 16-column tiles (forward).
+//   y_pass  : complex FFT along y on tiles of YZ_TILE columns (forward).
 //   z_mul   : forward FFT along z, times the multiplier and the scale,
 //             inverse FFT along z, in LDS (one HBM round trip).
 //   y_pass  : inverse along y.
@@ -25,7 +25,8 @@ namespace {
 
 constexpr int MAX_STAGES = 12;
 constexpr int MAX_ELEMS = 16;  // complex values per thread per stage
-constexpr int YZ_TILE = 16;    // pencils per workgroup in the y and z passes
+constexpr int YZ_LOG = 3;
+constexpr int YZ_TILE = 1 << YZ_LOG;  // pencils per workgroup in the y and z passes
 
 struct FftPlan {
     int n;
@@ -547,7 +548,7 @@ __global__ void mass_kernel(CwtJobs J, CwtLayout L, int n, uint32_t *status) {
 }
 
 // ---------------------------------------------------------------------------
-// y and z passes on 16-column tiles of the half spectrum
+// y and z passes on tiles of YZ_TILE columns of the half spectrum
 // ---------------------------------------------------------------------------
 // Logical tile of a (tiles, rows, jobs) grid, XCD-contiguous over the whole launch.
 __device__ __forceinline__ void yz_tile(int &tile, int &row, int &job) {
@@ -579,7 +580,7 @@ __global__ void fft_y_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
 #pragma unroll
         for (int i = 0; i < MAX_ELEMS; ++i) {
             const int e = tid + i * nt;
-            const int p = e & (YZ_TILE - 1), y = e >> 4;
+            const int p = e & (YZ_TILE - 1), y = e >> YZ_LOG;
             v[i] = (e < n * YZ_TILE && p < valid) ? spec[zbase + size_t(y) * H + kx0 + p] : make_float2(0.f, 0.f);
         }
 #pragma unroll
@@ -589,9 +590,9 @@ __global__ void fft_y_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
         }
     }
     __syncthreads();
-    fft_lds<INV>(buf, YZ_TILE, 4, pl, tw, tid, nt);
+    fft_lds<INV>(buf, YZ_TILE, YZ_LOG, pl, tw, tid, nt);
     for (int e = tid; e < n * YZ_TILE; e += nt) {
-        const int p = e & (YZ_TILE - 1), y = e >> 4;
+        const int p = e & (YZ_TILE - 1), y = e >> YZ_LOG;
         if (p < valid) spec[zbase + size_t(y) * H + kx0 + p] = buf[e];
     }
 }
@@ -621,7 +622,7 @@ __global__ void fft_z_mul_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
 #pragma unroll
         for (int i = 0; i < MAX_ELEMS; ++i) {
             const int e = tid + i * nt;
-            const int p = e & (YZ_TILE - 1), z = e >> 4;
+            const int p = e & (YZ_TILE - 1), z = e >> YZ_LOG;
             v[i] = (e < n * YZ_TILE && p < valid) ? spec[size_t(z) * zstride + base + p] : make_float2(0.f, 0.f);
         }
 #pragma unroll
@@ -631,11 +632,11 @@ __global__ void fft_z_mul_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
         }
     }
     __syncthreads();
-    fft_lds<false>(buf, YZ_TILE, 4, pl, tw, tid, nt);
+    fft_lds<false>(buf, YZ_TILE, YZ_LOG, pl, tw, tid, nt);
     const float scale = float(scalars[0]);
     const float by = tab_b[ky], py = tab_p[ky];
     for (int e = tid; e < n * YZ_TILE; e += nt) {
-        const int p = e & (YZ_TILE - 1), z = e >> 4;
+        const int p = e & (YZ_TILE - 1), z = e >> YZ_LOG;
         const int kx = min(kx0 + p, H - 1);
         const float bx = tab_b[kx], px = tab_p[kx];
         const float bz = tab_b[z], pz = tab_p[z];
@@ -644,9 +645,9 @@ __global__ void fft_z_mul_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
         buf[e] = make_float2(v.x * m, v.y * m);
     }
     __syncthreads();
-    fft_lds<true>(buf, YZ_TILE, 4, pl, tw, tid, nt);
+    fft_lds<true>(buf, YZ_TILE, YZ_LOG, pl, tw, tid, nt);
     for (int e = tid; e < n * YZ_TILE; e += nt) {
-        const int p = e & (YZ_TILE - 1), z = e >> 4;
+        const int p = e & (YZ_TILE - 1), z = e >> YZ_LOG;
         if (p < valid) spec[size_t(z) * zstride + base + p] = buf[e];
     }
 }
