@@ -225,8 +225,8 @@ struct Mass128 {
 // Per-job workspace layout (offsets from the job's workspace base).
 struct CwtLayout {
     size_t scalars, tw, gtab, htab, btab, ptab, mass, spec, total;
-    int lp_x;       // log2 of row pairs per x-pass workgroup
-    int64_t xblocks;
+    int lp_x, lp_xi;          // log2 of row pairs per forward / inverse x-pass workgroup
+    int64_t xblocks, xblocks_i;
 };
 
 // Up to MAX_BATCH same-n transforms in one launch per pass; the job index is a
@@ -436,7 +436,7 @@ __global__ void fft_x_inv_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
     const float2 *__restrict__ spec = jv.spec;
     float *__restrict__ out = J.cwt[job];
     const float2 *__restrict__ tw_g = jv.tw;
-    const int lp = L.lp_x;
+    const int lp = L.lp_xi;
     const int n = pl.n, H = n / 2 + 1;
     const int xp = 1 << lp, pitch = xp + 1;
     float2 *tw = smem;
@@ -655,19 +655,23 @@ __global__ void fft_z_mul_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
 // ---------------------------------------------------------------------------
 // workspace layout
 // ---------------------------------------------------------------------------
-int x_log_pairs(int n) {
-    // about 4096 complex values per x-pass workgroup, between 4 and 16 row pairs
+// log2 of the row pairs per x-pass workgroup: at most `elems` complex values,
+// between 4 and 16 pairs.  The forward pass keeps two int64 per value in flight
+// per thread, so it takes fewer pairs than the inverse.
+int x_log_pairs(int n, int elems) {
     int lp = 4;
-    while (lp > 2 && (n << lp) > 4096) --lp;
+    while (lp > 2 && (n << lp) > elems) --lp;
     return lp;
 }
 
 CwtLayout cwt_layout(int n) {
     CwtLayout L{};
     const size_t H = size_t(n) / 2 + 1;
-    L.lp_x = x_log_pairs(n);
+    L.lp_x = x_log_pairs(n, 4096);
+    L.lp_xi = x_log_pairs(n, 8192);
     const int64_t pairs = int64_t(n) * n / 2;
     L.xblocks = (pairs + (1 << L.lp_x) - 1) >> L.lp_x;
+    L.xblocks_i = (pairs + (1 << L.lp_xi) - 1) >> L.lp_xi;
     size_t off = 0;
     L.scalars = off;
     off = align_up(off + 64);
@@ -713,23 +717,26 @@ hf_status run_cwt(hf_ctx *ctx, int n, const CwtJobs &J) {
     const size_t yz_shm = sizeof(float2) * (size_t(n) + size_t(n) * YZ_TILE);
     const int x_threads = threads_for((1 << L.lp_x) * n);
     const size_t x_shm = sizeof(float2) * (size_t(n) + size_t(n) * ((1 << L.lp_x) + 1));
-    if (yz_shm > 65536) {
-        // tiles of 16 pencils of length n need more than the default 64 KiB of LDS
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_y_kernel<false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(yz_shm)) != hipSuccess ||
-            hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_y_kernel<true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(yz_shm)) != hipSuccess ||
-            hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_z_mul_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(yz_shm)) != hipSuccess)
-            return HF_ERR_DEVICE;
-    }
+    const int xi_threads = threads_for((1 << L.lp_xi) * n);
+    const size_t xi_shm = sizeof(float2) * (size_t(n) + size_t(n) * ((1 << L.lp_xi) + 1));
+    // workgroups that need more than the default 64 KiB of dynamic LDS say so
+    auto allow = [](const void *f, size_t bytes) {
+        return bytes <= 65536 ||
+               hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)) == hipSuccess;
+    };
+    if (!allow(reinterpret_cast<const void *>(&fft_y_kernel<false>), yz_shm) ||
+        !allow(reinterpret_cast<const void *>(&fft_y_kernel<true>), yz_shm) ||
+        !allow(reinterpret_cast<const void *>(&fft_z_mul_kernel), yz_shm) ||
+        !allow(reinterpret_cast<const void *>(&fft_x_fwd_kernel), x_shm) ||
+        !allow(reinterpret_cast<const void *>(&fft_x_inv_kernel), xi_shm))
+        return HF_ERR_DEVICE;
     HF_LAUNCH(ctx, K_X_FWD, fft_x_fwd_kernel, dim3(unsigned(L.xblocks), jobs), dim3(x_threads), x_shm, st, J, L, pl,
               ctx->d_status);
     HF_LAUNCH(ctx, K_MASS, mass_kernel, dim3(jobs), dim3(1024), 0, st, J, L, n, ctx->d_status);
     HF_LAUNCH(ctx, K_Y_FWD, fft_y_kernel<false>, dim3(tiles, n, jobs), dim3(yz_threads), yz_shm, st, J, L, pl);
     HF_LAUNCH(ctx, K_Z_MUL, fft_z_mul_kernel, dim3(tiles, n, jobs), dim3(yz_threads), yz_shm, st, J, L, pl);
     HF_LAUNCH(ctx, K_Y_INV, fft_y_kernel<true>, dim3(tiles, n, jobs), dim3(yz_threads), yz_shm, st, J, L, pl);
-    HF_LAUNCH(ctx, K_X_INV, fft_x_inv_kernel, dim3(unsigned(L.xblocks), jobs), dim3(x_threads), x_shm, st, J, L,
+    HF_LAUNCH(ctx, K_X_INV, fft_x_inv_kernel, dim3(unsigned(L.xblocks_i), jobs), dim3(xi_threads), xi_shm, st, J, L,
               pl);
     return launch_status();
 }
