@@ -44,7 +44,31 @@ constexpr int HCHUNK = CHUNK * HIST_CHUNKS;
 constexpr int REPLICAS = 64;   // level-1 counters are replicated to spread atomic traffic
 constexpr int MAX_DIGITS = 512;
 constexpr int ACC_THREADS = 256;
-constexpr uint32_t NO_SLOT = 0xffffffffu;  // slot of a particle whose position was rejected
+constexpr uint16_t NO_POS = 0xffffu;  // staging position of a particle whose position was rejected
+constexpr int OFF_STRIDE = MAX_DIGITS + 2;  // per-chunk row of staging offsets (ndest + 1 used)
+
+// Where one level's scatter chunks put their elements, kept for step 6: the
+// position of every element in its chunk's destination-sorted staging order
+// (element order; NO_POS if rejected), the destination of every staging
+// position, and per chunk the first slot of each destination's run and the
+// staging offset of each destination (offset[ndest] = elements staged).
+struct RunMaps {
+    uint16_t *pos;     // [elements]
+    uint16_t *dest;    // [chunks * CHUNK]
+    uint32_t *base;    // [chunks * MAX_DIGITS]
+    uint16_t *offset;  // [chunks * OFF_STRIDE]
+};
+
+// Records one scatter chunk's run table (called by every thread after the
+// chunk's offsets and run starts are known).
+__device__ __forceinline__ void save_run_table(const RunMaps &m, int64_t chunk, int ndest, const uint32_t *h,
+                                               const uint32_t *off, const uint32_t *gbase, uint32_t total) {
+    for (int d = threadIdx.x; d < ndest; d += blockDim.x) {
+        m.base[chunk * MAX_DIGITS + d] = h[d] ? gbase[d] : 0u;
+        m.offset[chunk * OFF_STRIDE + d] = uint16_t(off[d]);
+    }
+    if (threadIdx.x == 0) m.offset[chunk * OFF_STRIDE + ndest] = uint16_t(total);
+}
 
 struct Geom {
     int n;              // grid cells per axis
@@ -241,8 +265,7 @@ __global__ void __launch_bounds__(MAX_DIGITS) l1_scan_kernel(const uint32_t *__r
 template <typename T>
 __global__ void __launch_bounds__(PART_THREADS) l1_scatter_kernel(const T *__restrict__ pos, int64_t np,
                                                                   FixedPoint<T> fp, Geom g, uint32_t *cursor1,
-                                                                  Q3 *__restrict__ rec1,
-                                                                  uint32_t *__restrict__ slot1) {
+                                                                  Q3 *__restrict__ rec1, RunMaps maps) {
     __shared__ Q3 stage[CHUNK];
     __shared__ uint16_t sbk[CHUNK];
     __shared__ uint32_t h[MAX_DIGITS], off[MAX_DIGITS], gbase[MAX_DIGITS], tmp[MAX_DIGITS];
@@ -285,12 +308,14 @@ __global__ void __launch_bounds__(PART_THREADS) l1_scatter_kernel(const T *__res
     for (uint32_t s = threadIdx.x; s < total; s += PART_THREADS) {
         const int b = sbk[s];
         rec1[gbase[b] + (s - off[b])] = stage[s];
+        if (maps.pos) maps.dest[chunk * CHUNK + s] = uint16_t(b);
     }
-    if (slot1) {
+    if (maps.pos) {
+        save_run_table(maps, chunk, g.nbuckets, h, off, gbase, total);
 #pragma unroll
         for (int k = 0; k < PART_PER; ++k) {
             const int64_t i = base + k * PART_THREADS + threadIdx.x;
-            if (i < np) slot1[i] = bk[k] >= 0 ? gbase[bk[k]] + rank[k] : NO_SLOT;
+            if (i < np) maps.pos[i] = bk[k] >= 0 ? uint16_t(off[bk[k]] + rank[k]) : NO_POS;
         }
     }
 }
@@ -402,11 +427,11 @@ __global__ void __launch_bounds__(1024) l2_scan_kernel(const uint32_t *__restric
     if (t == 1023) start2[ntiles] = part[1023];
 }
 
-// map12 (optional, FROM_REC only) receives every level-1 record's level-2 slot.
+// maps (optional, FROM_REC only) records where every level-1 record went.
 template <typename T, bool FROM_REC>
 __global__ void __launch_bounds__(PART_THREADS) l2_scatter_kernel(L2Input<T, FROM_REC> in, Geom g,
                                                                   uint32_t *cursor2, uint64_t *__restrict__ rec2,
-                                                                  uint32_t *__restrict__ map12) {
+                                                                  RunMaps maps) {
     __shared__ uint64_t stage[CHUNK];
     __shared__ uint16_t sdig[CHUNK];
     __shared__ uint32_t h[MAX_DIGITS], off[MAX_DIGITS], gbase[MAX_DIGITS], tmp[MAX_DIGITS];
@@ -454,14 +479,17 @@ __global__ void __launch_bounds__(PART_THREADS) l2_scatter_kernel(L2Input<T, FRO
             sdig[s] = uint16_t(dg[k]);
         }
     __syncthreads();
+    const bool keep = FROM_REC && maps.pos;
     for (uint32_t s = threadIdx.x; s < total; s += PART_THREADS) {
         const int d = sdig[s];
         rec2[gbase[d] + (s - off[d])] = stage[s];
+        if (keep) maps.dest[int64_t(blockIdx.x) * CHUNK + s] = uint16_t(d);
     }
-    if (FROM_REC && map12) {
+    if (keep) {
+        save_run_table(maps, blockIdx.x, g.digits, h, off, gbase, total);
 #pragma unroll
         for (int k = 0; k < PART_PER; ++k)
-            if (dg[k] >= 0) map12[lo + k * PART_THREADS + threadIdx.x] = gbase[dg[k]] + rank[k];
+            if (dg[k] >= 0) maps.pos[lo + k * PART_THREADS + threadIdx.x] = uint16_t(off[dg[k]] + rank[k]);
     }
 }
 
@@ -712,131 +740,82 @@ __global__ void __launch_bounds__(ACC_THREADS) tile_label_kernel(const uint64_t 
     }
 }
 
-// Last index d in [0, count) with table[d] <= v (table ascending, table[0] <= v).
-__device__ __forceinline__ int last_le(const uint32_t *table, int count, uint32_t v) {
-    int L = 0, R = count - 1;
-    while (L < R) {
-        const int m = (L + R + 1) >> 1;
-        if (table[m] <= v) L = m;
-        else R = m - 1;
-    }
-    return L;
-}
-
-// Gathers val[k] = src[slot[k]] for the CHUNK slots of one workgroup whose
-// slots form, per group d (of `groups`, group d owning [first[d], first[d+1])),
-// one run of consecutive values.  The runs are read into LDS with consecutive
-// lanes on consecutive slots, so a wavefront touches a few lines instead of
-// one line per lane; each lane then picks its value from LDS.  Lanes with
-// valid[k] false get -1.
-struct RunGather {
-    uint32_t first[MAX_DIGITS + 1], rlo[MAX_DIGITS], cnt[MAX_DIGITS], off[MAX_DIGITS], tmp[MAX_DIGITS];
-    uint16_t grp[CHUNK];
-    int32_t val[CHUNK];
-};
-
-__device__ void run_gather(RunGather &sh, int groups, const uint32_t (&slot)[PART_PER], const bool (&valid)[PART_PER],
-                           const int32_t *__restrict__ src, int32_t (&out)[PART_PER]) {
-    for (int d = threadIdx.x; d < groups; d += blockDim.x) {
-        sh.cnt[d] = 0u;
-        sh.rlo[d] = 0xffffffffu;
-    }
-    __syncthreads();
-    int gd[PART_PER];
+// One scatter chunk back to element order: dst[e] = src[slot of element e]
+// for the chunk's elements [e0, e1).  The chunk's runs are read into LDS in
+// staging order, consecutive lanes on consecutive slots of a run, so a
+// wavefront touches a few lines instead of one line per lane; element e then
+// takes the value at its staging position.  Rejected elements get -1.
+__device__ void chunk_gather(const RunMaps &m, int64_t chunk, int ndest, int64_t e0, int64_t e1,
+                             const int32_t *__restrict__ src, int32_t *__restrict__ dst) {
+    __shared__ uint32_t base_s[MAX_DIGITS];
+    __shared__ uint16_t off_s[OFF_STRIDE];
+    __shared__ int32_t val[CHUNK];
+    for (int d = threadIdx.x; d < ndest; d += blockDim.x) base_s[d] = m.base[chunk * MAX_DIGITS + d];
+    for (int d = threadIdx.x; d <= ndest; d += blockDim.x) off_s[d] = m.offset[chunk * OFF_STRIDE + d];
+    uint16_t p[PART_PER], dd[PART_PER];
 #pragma unroll
     for (int k = 0; k < PART_PER; ++k) {
-        gd[k] = -1;
-        if (valid[k]) {
-            gd[k] = last_le(sh.first, groups, slot[k]);
-            atomicAdd(&sh.cnt[gd[k]], 1u);
-            atomicMin(&sh.rlo[gd[k]], slot[k]);
-        }
+        const int64_t e = e0 + k * PART_THREADS + threadIdx.x;
+        p[k] = e < e1 ? m.pos[e] : NO_POS;
+        dd[k] = m.dest[chunk * CHUNK + k * PART_THREADS + threadIdx.x];  // used below only if staged
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < groups; d += blockDim.x) sh.off[d] = sh.cnt[d];
-    __syncthreads();
-    const uint32_t total = block_exclusive_scan(sh.off, sh.tmp, groups);
-    uint32_t at[PART_PER];
+    const uint32_t total = off_s[ndest];
+    int32_t v[PART_PER];
 #pragma unroll
     for (int k = 0; k < PART_PER; ++k) {
-        at[k] = 0xffffffffu;
-        if (gd[k] >= 0) {
-            const uint32_t p = sh.off[gd[k]] + (slot[k] - sh.rlo[gd[k]]);
-            if (p < total) {  // always: a run holds exactly cnt consecutive slots
-                sh.grp[p] = uint16_t(gd[k]);
-                at[k] = p;
-            }
+        const uint32_t s = k * PART_THREADS + threadIdx.x;
+        if (s < total) {
+            const int d = dd[k];
+            v[k] = src[base_s[d] + (s - off_s[d])];
         }
     }
-    __syncthreads();
-    for (uint32_t s = threadIdx.x; s < total; s += blockDim.x) {
-        const int d = sh.grp[s];
-        sh.val[s] = src[sh.rlo[d] + (s - sh.off[d])];
+#pragma unroll
+    for (int k = 0; k < PART_PER; ++k) {
+        const uint32_t s = k * PART_THREADS + threadIdx.x;
+        if (s < total) val[s] = v[k];
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < PART_PER; ++k) out[k] = at[k] != 0xffffffffu ? sh.val[at[k]] : -1;
+    for (int k = 0; k < PART_PER; ++k) {
+        const int64_t e = e0 + k * PART_THREADS + threadIdx.x;
+        if (e < e1) dst[e] = p[k] < total ? val[p[k]] : -1;
+    }
 }
 
-// Pass 2, level-1 order: lab1[j] = lab2[map12[j]].  Workgroup w is level-2
-// scatter chunk w (CHUNK records of one bucket), whose level-2 slots form one
-// run per tile of the bucket.
-__global__ void __launch_bounds__(PART_THREADS) to_level1_kernel(const uint32_t *__restrict__ map12,
-                                                                 const uint32_t *__restrict__ start1,
+// Pass 2, level-1 order: lab1[j] = lab2[level-2 slot of record j], one
+// workgroup per level-2 scatter chunk (CHUNK records of one bucket).
+__global__ void __launch_bounds__(PART_THREADS) to_level1_kernel(RunMaps m2, const uint32_t *__restrict__ start1,
                                                                  const uint32_t *__restrict__ chunk_first,
-                                                                 const uint32_t *__restrict__ start2, int nbuckets,
-                                                                 int digits, const int32_t *__restrict__ lab2,
+                                                                 int nbuckets, int digits,
+                                                                 const int32_t *__restrict__ lab2,
                                                                  int32_t *__restrict__ lab1) {
-    __shared__ RunGather sh;
     const uint32_t w = blockIdx.x;
     if (w >= chunk_first[nbuckets]) return;
-    const int b = last_le(chunk_first, nbuckets, w);
+    int L = 0, R = nbuckets - 1;  // last b with chunk_first[b] <= w
+    while (L < R) {
+        const int mid = (L + R + 1) >> 1;
+        if (chunk_first[mid] <= w) L = mid;
+        else R = mid - 1;
+    }
+    const int b = L;
     const int64_t lo = int64_t(start1[b]) + int64_t(w - chunk_first[b]) * CHUNK;
     const int64_t end = start1[b + 1];
     const int64_t hi = lo + CHUNK < end ? lo + CHUNK : end;
-    for (int d = threadIdx.x; d <= digits; d += blockDim.x) sh.first[d] = start2[b * digits + d];
-    uint32_t m[PART_PER];
-    bool ok[PART_PER];
-#pragma unroll
-    for (int k = 0; k < PART_PER; ++k) {
-        const int64_t j = lo + k * PART_THREADS + threadIdx.x;
-        ok[k] = j < hi;
-        m[k] = ok[k] ? map12[j] : 0u;
-    }
-    int32_t v[PART_PER];
-    run_gather(sh, digits, m, ok, lab2, v);
-#pragma unroll
-    for (int k = 0; k < PART_PER; ++k)
-        if (ok[k]) lab1[lo + k * PART_THREADS + threadIdx.x] = v[k];
+    chunk_gather(m2, w, digits, lo, hi, lab2, lab1);
 }
 
-// Pass 3, input order: particle i -> lab1[slot1[i]] (-1 for a rejected
-// position).  Workgroup c is level-1 scatter chunk c, whose slots form one run
-// per bucket.
-__global__ void __launch_bounds__(PART_THREADS) to_input_kernel(const uint32_t *__restrict__ slot1, int64_t np,
-                                                                const uint32_t *__restrict__ start1, int nbuckets,
+// Pass 3, input order: particle i -> lab1[level-1 slot of i], one workgroup
+// per level-1 scatter chunk.
+__global__ void __launch_bounds__(PART_THREADS) to_input_kernel(RunMaps m1, int64_t np, int nbuckets,
                                                                 const int32_t *__restrict__ lab1,
                                                                 int32_t *__restrict__ out) {
-    __shared__ RunGather sh;
-    const int64_t base = int64_t(blockIdx.x) * CHUNK;
-    for (int d = threadIdx.x; d <= nbuckets; d += blockDim.x) sh.first[d] = start1[d];
-    uint32_t sl[PART_PER];
-    bool ok[PART_PER];
-#pragma unroll
-    for (int k = 0; k < PART_PER; ++k) {
-        const int64_t i = base + k * PART_THREADS + threadIdx.x;
-        sl[k] = i < np ? slot1[i] : NO_SLOT;
-        ok[k] = sl[k] != NO_SLOT;
-    }
-    int32_t v[PART_PER];
-    run_gather(sh, nbuckets, sl, ok, lab1, v);
-#pragma unroll
-    for (int k = 0; k < PART_PER; ++k) {
-        const int64_t i = base + k * PART_THREADS + threadIdx.x;
-        if (i < np) out[i] = v[k];
-    }
+    const int64_t e0 = int64_t(blockIdx.x) * CHUNK;
+    const int64_t e1 = e0 + CHUNK < np ? e0 + CHUNK : np;
+    chunk_gather(m1, blockIdx.x, nbuckets, e0, e1, lab1, out);
 }
 
+// ---------------------------------------------------------------- host side
 // Tile and bucket shape for an n^3 grid; false if the binned form cannot hold it
 // (at most MAX_DIGITS tiles per bucket and MAX_DIGITS buckets).
 bool make_geom(const hf_box &box, Geom &out) {
@@ -920,10 +899,11 @@ DepLayout dep_layout(const Geom &g, int64_t np, bool keep_order) {
     return L;
 }
 
-// ParticleOrder region: rec2 [np] | start2 [ntiles + 1] | slot1 [np] | map12 [np] |
-// nrec | start1 [513] | chunk_first [513].
+// ParticleOrder region: rec2 [np] | start2 [ntiles + 1] | nrec | start1 [513] |
+// chunk_first [513] | the run maps of both levels (about 9 bytes per particle).
 struct OrderLayout {
-    size_t rec2, start2, slot1, map12, nrec, start1, chunk_first, total;
+    size_t rec2, start2, nrec, start1, chunk_first, total;
+    size_t pos[2], dest[2], base[2], offset[2];
 };
 
 OrderLayout order_layout(const Geom &g, int64_t np) {
@@ -936,11 +916,17 @@ OrderLayout order_layout(const Geom &g, int64_t np) {
     };
     L.rec2 = take(sizeof(uint64_t) * size_t(np));
     L.start2 = take(sizeof(uint32_t) * (size_t(g.ntiles) + 1));
-    L.slot1 = take(sizeof(uint32_t) * size_t(np));
-    L.map12 = take(sizeof(uint32_t) * size_t(np));
     L.nrec = take(sizeof(uint32_t));
     L.start1 = take(sizeof(uint32_t) * (MAX_DIGITS + 1));
     L.chunk_first = take(sizeof(uint32_t) * (MAX_DIGITS + 1));
+    const size_t chunks1 = (size_t(np) + CHUNK - 1) / CHUNK;
+    const size_t chunks[2] = {chunks1, chunks1 + size_t(g.nbuckets)};  // level 2: one partial chunk per bucket
+    for (int l = 0; l < 2; ++l) {
+        L.pos[l] = take(sizeof(uint16_t) * size_t(np));
+        L.dest[l] = take(sizeof(uint16_t) * chunks[l] * CHUNK);
+        L.base[l] = take(sizeof(uint32_t) * chunks[l] * MAX_DIGITS);
+        L.offset[l] = take(sizeof(uint16_t) * chunks[l] * OFF_STRIDE);
+    }
     L.total = off;
     return L;
 }
@@ -963,8 +949,11 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
     auto *rec1 = reinterpret_cast<Q3 *>(ws + L.rec1);
     auto *rec2 = order ? order->rec2 : reinterpret_cast<uint64_t *>(ws + L.rec2);
     auto *skirt = reinterpret_cast<unsigned long long *>(ws + L.skirt);
-    uint32_t *slot1 = order ? order->slot1 : nullptr;
-    uint32_t *map12 = order ? order->map12 : nullptr;
+    RunMaps m1{}, m2{};
+    if (order) {
+        __builtin_memcpy(&m1, order->maps[0], sizeof(m1));
+        __builtin_memcpy(&m2, order->maps[1], sizeof(m2));
+    }
     uint32_t *nrec = order ? order->nrec : nullptr;
     hipStream_t st = ctx->stream;
     const FixedPoint<T> fp = make_fixed_point<T>(box);
@@ -980,14 +969,14 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
                   cursor1, chunk_first, hchunk_first, nrec);
         if (part_blocks)
             HF_LAUNCH(ctx, K_DEP_L1_SCATTER, l1_scatter_kernel<T>, dim3(replica_grid(part_blocks)),
-                      dim3(PART_THREADS), 0, st, pos, np, fp, g, cursor1, rec1, slot1);
+                      dim3(PART_THREADS), 0, st, pos, np, fp, g, cursor1, rec1, m1);
         const L2Input<T, true> hin{pos, np, fp, rec1, start1, hchunk_first, g.nbuckets, HCHUNK};
         const L2Input<T, true> sin{pos, np, fp, rec1, start1, chunk_first, g.nbuckets, CHUNK};
         HF_LAUNCH(ctx, K_DEP_L2_HIST, (l2_hist_kernel<T, true>), dim3(hist_blocks + unsigned(g.nbuckets)),
                   dim3(PART_THREADS), 0, st, hin, g, count2, ctx->d_status);
         HF_LAUNCH(ctx, K_DEP_PREP, l2_scan_kernel, dim3(1), dim3(1024), 0, st, count2, g.ntiles, start2, cursor2);
         HF_LAUNCH(ctx, K_DEP_L2_SCATTER, (l2_scatter_kernel<T, true>), dim3(part_blocks + unsigned(g.nbuckets)),
-                  dim3(PART_THREADS), 0, st, sin, g, cursor2, rec2, map12);
+                  dim3(PART_THREADS), 0, st, sin, g, cursor2, rec2, m2);
     } else {
         const L2Input<T, false> hin{pos, np, fp, nullptr, nullptr, nullptr, 1, HCHUNK};
         const L2Input<T, false> sin{pos, np, fp, nullptr, nullptr, nullptr, 1, CHUNK};
@@ -997,7 +986,7 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
         HF_LAUNCH(ctx, K_DEP_PREP, l2_scan_kernel, dim3(1), dim3(1024), 0, st, count2, g.ntiles, start2, cursor2);
         if (part_blocks)
             HF_LAUNCH(ctx, K_DEP_L2_SCATTER, (l2_scatter_kernel<T, false>), dim3(part_blocks), dim3(PART_THREADS),
-                      0, st, sin, g, cursor2, rec2, nullptr);
+                      0, st, sin, g, cursor2, rec2, RunMaps{});
     }
     HF_LAUNCH(ctx, K_DEPOSIT, tile_accum_kernel, dim3(g.ntiles), dim3(ACC_THREADS), 0, st, rec2, start2, g, rho,
               skirt, ctx->d_status);
@@ -1046,11 +1035,15 @@ hf::ParticleOrder hf::particle_order_at(const hf_box &box, void *base, int64_t n
     char *p = static_cast<char *>(base);
     o.rec2 = reinterpret_cast<uint64_t *>(p + L.rec2);
     o.start2 = reinterpret_cast<uint32_t *>(p + L.start2);
-    o.slot1 = reinterpret_cast<uint32_t *>(p + L.slot1);
-    o.map12 = reinterpret_cast<uint32_t *>(p + L.map12);
     o.nrec = reinterpret_cast<uint32_t *>(p + L.nrec);
     o.start1 = reinterpret_cast<uint32_t *>(p + L.start1);
     o.chunk_first = reinterpret_cast<uint32_t *>(p + L.chunk_first);
+    static_assert(sizeof(RunMaps) <= sizeof(o.maps[0]), "run maps fit the opaque slots");
+    for (int l = 0; l < 2; ++l) {
+        const RunMaps m{reinterpret_cast<uint16_t *>(p + L.pos[l]), reinterpret_cast<uint16_t *>(p + L.dest[l]),
+                        reinterpret_cast<uint32_t *>(p + L.base[l]), reinterpret_cast<uint16_t *>(p + L.offset[l])};
+        __builtin_memcpy(o.maps[l], &m, sizeof(m));
+    }
     return o;
 }
 
@@ -1067,10 +1060,12 @@ hf_status hf::label_from_order(hf_ctx *ctx, const hf_box &box, int64_t np, const
     HF_LAUNCH(ctx, K_LABEL_TILES, tile_label_kernel, dim3(g.ntiles), dim3(ACC_THREADS), 0, ctx->stream, order.rec2,
               order.start2, g, cell_label, lab2);
     // level-2 scatter chunks: at most one partial chunk per bucket beyond np / CHUNK
+    RunMaps m1, m2;
+    __builtin_memcpy(&m1, order.maps[0], sizeof(m1));
+    __builtin_memcpy(&m2, order.maps[1], sizeof(m2));
     HF_LAUNCH(ctx, K_LABEL_LEVEL1, to_level1_kernel, dim3(blocks + unsigned(g.nbuckets)), dim3(PART_THREADS), 0,
-              ctx->stream, order.map12, order.start1, order.chunk_first, order.start2, g.nbuckets, g.digits, lab2,
-              lab1);
-    HF_LAUNCH(ctx, K_LABEL_INPUT, to_input_kernel, dim3(blocks), dim3(PART_THREADS), 0, ctx->stream, order.slot1, np,
-              order.start1, g.nbuckets, lab1, particle_label);
+              ctx->stream, m2, order.start1, order.chunk_first, g.nbuckets, g.digits, lab2, lab1);
+    HF_LAUNCH(ctx, K_LABEL_INPUT, to_input_kernel, dim3(blocks), dim3(PART_THREADS), 0, ctx->stream, m1, np,
+              g.nbuckets, lab1, particle_label);
     return launch_status();
 }

@@ -115,18 +115,18 @@ inline hf_status launch_status() {
 }
 
 // The binned deposit's particle order, kept for the label stage: the level-2
-// records (tile order) and tile offsets, every particle's level-1 slot
-// (0xffffffff for a rejected position), every level-1 record's level-2 slot and
-// the number of records.  Lives in a caller workspace region of
-// particle_order_bytes(box, np).
+// records (tile order), the bucket and tile offsets, the number of records and,
+// for both partition levels, where every element went.  Lives in a caller
+// workspace region of particle_order_bytes(box, np).
 struct ParticleOrder {
     uint64_t *rec2;
     uint32_t *start2;
-    uint32_t *slot1;
-    uint32_t *map12;
     uint32_t *nrec;
     uint32_t *start1;       // [513] first record of each bucket
     uint32_t *chunk_first;  // [513] first level-2 scatter chunk of each bucket
+    // where each level's scatter chunks put their elements (layout private to
+    // the deposit's translation unit)
+    alignas(8) unsigned char maps[2][32];
 };
 bool particle_order_supported(const hf_box &box, int64_t np);  // binned, more than one bucket
 size_t particle_order_bytes(const hf_box &box, int64_t np);
