@@ -36,13 +36,14 @@ constexpr int TYZ = 8;               // tile extent in y and z
 constexpr int AYZ = TYZ + 1;          // accumulator extent in y and z (tile + skirt)
 constexpr int MAX_TX = 64;            // tile extent in x: 64, 32 or 16
 constexpr int MAX_ACC_CELLS = (MAX_TX + 1) * AYZ * AYZ;
-constexpr int PART_THREADS = 512;
+constexpr int PART_THREADS = 1024;
 constexpr int PART_PER = 8;
 constexpr int CHUNK = PART_THREADS * PART_PER;                          // particles per scatter workgroup
-constexpr int HIST_CHUNKS = 16;                                         // scatter chunks per histogram workgroup
+constexpr int HIST_CHUNKS = 8;                                          // scatter chunks per histogram workgroup
 constexpr int HCHUNK = CHUNK * HIST_CHUNKS;
 constexpr int REPLICAS = 64;   // level-1 counters are replicated to spread atomic traffic
 constexpr int MAX_DIGITS = 512;
+constexpr int HIST_THREADS = 512;  // histogram workgroups stay at 512 threads
 constexpr int ACC_THREADS = 256;
 constexpr uint16_t NO_POS = 0xffffu;  // staging position of a particle whose position was rejected
 constexpr int OFF_STRIDE = MAX_DIGITS + 2;  // per-chunk row of staging offsets (ndest + 1 used)
@@ -201,7 +202,7 @@ static_assert(REPLICAS % NUM_XCD == 0, "replicas split evenly over the XCDs");
 
 // ---------------------------------------------------------------- level 1
 template <typename T>
-__global__ void __launch_bounds__(PART_THREADS) l1_hist_kernel(const T *__restrict__ pos, int64_t np,
+__global__ void __launch_bounds__(HIST_THREADS) l1_hist_kernel(const T *__restrict__ pos, int64_t np,
                                                                FixedPoint<T> fp, Geom g, uint32_t *count1,
                                                                uint32_t *status) {
     __shared__ uint32_t h[MAX_DIGITS];
@@ -210,10 +211,10 @@ __global__ void __launch_bounds__(PART_THREADS) l1_hist_kernel(const T *__restri
     bool bad = false;
     const int64_t base = int64_t(blockIdx.x) * HCHUNK;
     const int64_t end = base + HCHUNK < np ? base + HCHUNK : np;
-    for (int64_t i0 = base + threadIdx.x; i0 < end; i0 += PART_THREADS * LBATCH) {
+    for (int64_t i0 = base + threadIdx.x; i0 < end; i0 += HIST_THREADS * LBATCH) {
         Q3 q[LBATCH];
         bool ok[LBATCH];
-        load_q_batch(pos, i0, PART_THREADS, end, fp, q, ok, bad);
+        load_q_batch(pos, i0, HIST_THREADS, end, fp, q, ok, bad);
 #pragma unroll
         for (int k = 0; k < LBATCH; ++k)
             if (ok[k]) atomicAdd(&h[bucket_of(g, q[k].x >> g.bits, q[k].y >> g.bits, q[k].z >> g.bits)], 1u);
@@ -369,7 +370,7 @@ __device__ __forceinline__ bool l2_load(const L2Input<T, FROM_REC> &in, int64_t 
 }
 
 template <typename T, bool FROM_REC>
-__global__ void __launch_bounds__(PART_THREADS) l2_hist_kernel(L2Input<T, FROM_REC> in, Geom g, uint32_t *count2,
+__global__ void __launch_bounds__(HIST_THREADS) l2_hist_kernel(L2Input<T, FROM_REC> in, Geom g, uint32_t *count2,
                                                                uint32_t *status) {
     __shared__ uint32_t h[MAX_DIGITS];
     int b;
@@ -378,18 +379,18 @@ __global__ void __launch_bounds__(PART_THREADS) l2_hist_kernel(L2Input<T, FROM_R
     for (int d = threadIdx.x; d < MAX_DIGITS; d += blockDim.x) h[d] = 0u;
     __syncthreads();
     bool bad = false;
-    for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += PART_THREADS * LBATCH) {
+    for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += HIST_THREADS * LBATCH) {
         Q3 q[LBATCH];
         bool ok[LBATCH];
         if (FROM_REC) {
 #pragma unroll
             for (int k = 0; k < LBATCH; ++k) {
-                const int64_t i = i0 + k * PART_THREADS;
+                const int64_t i = i0 + k * HIST_THREADS;
                 ok[k] = i < hi;
                 if (ok[k]) q[k] = in.rec1[i];
             }
         } else {
-            load_q_batch(in.pos, i0, PART_THREADS, hi, in.fp, q, ok, bad);
+            load_q_batch(in.pos, i0, HIST_THREADS, hi, in.fp, q, ok, bad);
         }
 #pragma unroll
         for (int k = 0; k < LBATCH; ++k)
@@ -963,7 +964,7 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
     const unsigned hist_blocks = unsigned((np + HCHUNK - 1) / HCHUNK);
     if (g.nbuckets > 1) {
         if (hist_blocks)
-            HF_LAUNCH(ctx, K_DEP_L1_HIST, l1_hist_kernel<T>, dim3(hist_blocks), dim3(PART_THREADS), 0, st, pos, np,
+            HF_LAUNCH(ctx, K_DEP_L1_HIST, l1_hist_kernel<T>, dim3(hist_blocks), dim3(HIST_THREADS), 0, st, pos, np,
                       fp, g, count1, ctx->d_status);
         HF_LAUNCH(ctx, K_DEP_PREP, l1_scan_kernel, dim3(1), dim3(MAX_DIGITS), 0, st, count1, g.nbuckets, start1,
                   cursor1, chunk_first, hchunk_first, nrec);
@@ -973,7 +974,7 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
         const L2Input<T, true> hin{pos, np, fp, rec1, start1, hchunk_first, g.nbuckets, HCHUNK};
         const L2Input<T, true> sin{pos, np, fp, rec1, start1, chunk_first, g.nbuckets, CHUNK};
         HF_LAUNCH(ctx, K_DEP_L2_HIST, (l2_hist_kernel<T, true>), dim3(hist_blocks + unsigned(g.nbuckets)),
-                  dim3(PART_THREADS), 0, st, hin, g, count2, ctx->d_status);
+                  dim3(HIST_THREADS), 0, st, hin, g, count2, ctx->d_status);
         HF_LAUNCH(ctx, K_DEP_PREP, l2_scan_kernel, dim3(1), dim3(1024), 0, st, count2, g.ntiles, start2, cursor2);
         HF_LAUNCH(ctx, K_DEP_L2_SCATTER, (l2_scatter_kernel<T, true>), dim3(part_blocks + unsigned(g.nbuckets)),
                   dim3(PART_THREADS), 0, st, sin, g, cursor2, rec2, m2);
@@ -981,7 +982,7 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
         const L2Input<T, false> hin{pos, np, fp, nullptr, nullptr, nullptr, 1, HCHUNK};
         const L2Input<T, false> sin{pos, np, fp, nullptr, nullptr, nullptr, 1, CHUNK};
         if (hist_blocks)
-            HF_LAUNCH(ctx, K_DEP_L2_HIST, (l2_hist_kernel<T, false>), dim3(hist_blocks), dim3(PART_THREADS), 0, st,
+            HF_LAUNCH(ctx, K_DEP_L2_HIST, (l2_hist_kernel<T, false>), dim3(hist_blocks), dim3(HIST_THREADS), 0, st,
                       hin, g, count2, ctx->d_status);
         HF_LAUNCH(ctx, K_DEP_PREP, l2_scan_kernel, dim3(1), dim3(1024), 0, st, count2, g.ntiles, start2, cursor2);
         if (part_blocks)
