@@ -44,7 +44,7 @@ constexpr int HCHUNK = CHUNK * HIST_CHUNKS;
 constexpr int REPLICAS = 64;   // level-1 counters are replicated to spread atomic traffic
 constexpr int MAX_DIGITS = 512;
 constexpr int HIST_THREADS = 512;  // histogram workgroups stay at 512 threads
-constexpr int ACC_THREADS = 256;
+constexpr int ACC_THREADS = 512;
 constexpr uint16_t NO_POS = 0xffffu;  // staging position of a particle whose position was rejected
 constexpr int OFF_STRIDE = MAX_DIGITS + 2;  // per-chunk row of staging offsets (ndest + 1 used)
 
@@ -523,7 +523,7 @@ __device__ __forceinline__ void accumulate(const uint64_t *__restrict__ rec2, ui
     const uint64_t mx = (1ull << sx) - 1ull, my = (1ull << sy) - 1ull;
     const uint64_t one = 1ull << bits;
     const int plane = ax * AYZ;
-    constexpr int RB = 4;  // records per thread loaded together
+    constexpr int RB = 8;  // records per thread loaded together
     for (uint32_t i0 = lo + threadIdx.x; i0 < hi; i0 += ACC_THREADS * RB) {
         uint64_t rr[RB];
 #pragma unroll
@@ -720,7 +720,7 @@ __global__ void __launch_bounds__(ACC_THREADS) tile_label_kernel(const uint64_t 
     const uint64_t mx = (1ull << sx) - 1ull, my = (1ull << sy) - 1ull;
     const uint64_t half = 1ull << (bits - 1);
     const uint32_t lo = start2[slot], hi = start2[slot + 1];
-    constexpr int RB = 4;
+    constexpr int RB = 8;
     for (uint32_t i0 = lo + threadIdx.x; i0 < hi; i0 += ACC_THREADS * RB) {
         uint64_t rr[RB];
 #pragma unroll
