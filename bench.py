@@ -35,7 +35,7 @@ CSRC = os.path.join(ROOT, "paper_2501_10622_amd", "csrc")
 TIMER_SYMBOLS = {
     "zero_grid": ("fill_u64_kernel",), "deposit": ("tile_accum_kernel",), "label": ("label_kernel",),
     "deposit_atomic": ("deposit_atomic_kernel",),
-    "deposit_prep": ("l1_colscan_kernel", "l1_scan_kernel", "l2_colscan_kernel", "l2_scan_kernel"),
+    "deposit_prep": ("zero_u32_kernel", "l1_scan_kernel", "l2_scan_kernel"),
     "deposit_l1_hist": ("l1_hist_kernel",), "deposit_l1_scatter": ("l1_scatter_kernel",),
     "deposit_l2_hist": ("l2_hist_kernel",), "deposit_l2_scatter": ("l2_scatter_kernel",),
     "deposit_fold": ("skirt_fold_kernel",),
