@@ -262,14 +262,23 @@ __global__ void fill_flags_kernel(uint32_t *flags, int count) {
     if (i < count) flags[i] = (i == 0) ? 1u : 0u;
 }
 
-// One pointer-jumping round over the boundary cells, in place.  Round r runs
-// only if round r - 1 changed something, so a fixed number of launches is enough.
+// Pointer jumping over the boundary entries, in place.  Round 0 visits every
+// entry; each workgroup appends to its own slice of `list` (cap entries at
+// blockIdx * cap, count in counts[blockIdx]) the entries that changed and now
+// point at a boundary cell, whose own entry may still change: only those can
+// change again.  Later rounds run the same grid, each workgroup over its own
+// slice, so no global counter is shared.  Round r runs only if round r - 1
+// changed something, so a fixed number of launches is enough.
 constexpr int BATCH = 8;  // independent iterations per thread and pass, so their loads overlap
 
-__global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd, int64_t count, TileGrid tg,
-                                                       uint32_t *flags, int round) {
-    if (flags[round] == 0u) return;
-    bool changed = false;
+__global__ void __launch_bounds__(256) bnd_jump_first_kernel(int32_t *__restrict__ bnd, int64_t count, TileGrid tg,
+                                                             uint32_t *__restrict__ list, int64_t cap,
+                                                             uint32_t *__restrict__ counts, uint32_t *flags) {
+    __shared__ uint32_t lcount;
+    if (threadIdx.x == 0) lcount = 0u;
+    __syncthreads();
+    uint32_t *mine = list + int64_t(blockIdx.x) * cap;
+    const int lane = threadIdx.x & 63;
     const int64_t step = int64_t(gridDim.x) * blockDim.x * BATCH;
     for (int64_t k0 = blockIdx.x * int64_t(blockDim.x) * BATCH + threadIdx.x; k0 < count; k0 += step) {
         int32_t p[BATCH], q[BATCH];
@@ -289,8 +298,58 @@ __global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd
 #pragma unroll
         for (int i = 0; i < BATCH; ++i) {
             const int64_t k = k0 + int64_t(i) * blockDim.x;
+            bool again = false;
             if (k < count && q[i] != p[i]) {
                 bnd[k] = q[i];
+                again = q[i] >= 0 && bnd_slot(tg, q[i]) >= 0;
+            }
+            const unsigned long long bits = __ballot(again);
+            if (bits) {  // one LDS reservation per wavefront
+                const int leader = __ffsll(bits) - 1;
+                uint32_t at = 0;
+                if (lane == leader) at = atomicAdd(&lcount, uint32_t(__popcll(bits)));
+                at = __shfl(at, leader, 64);
+                if (again) mine[at + __popcll(bits & ((1ull << lane) - 1ull))] = uint32_t(k);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        counts[blockIdx.x] = lcount;
+        if (lcount) flags[1] = 1u;
+    }
+}
+
+__global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd, const uint32_t *__restrict__ list,
+                                                       int64_t cap, const uint32_t *__restrict__ counts, TileGrid tg,
+                                                       uint32_t *flags, int round) {
+    if (flags[round] == 0u) return;
+    const uint32_t *mine = list + int64_t(blockIdx.x) * cap;
+    const int64_t count = counts[blockIdx.x];
+    bool changed = false;
+    for (int64_t j0 = threadIdx.x; j0 < count; j0 += int64_t(blockDim.x) * BATCH) {
+        uint32_t k[BATCH];
+        int32_t p[BATCH], q[BATCH];
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i) {
+            const int64_t j = j0 + int64_t(i) * blockDim.x;
+            k[i] = j < count ? mine[j] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i) {
+            const int64_t j = j0 + int64_t(i) * blockDim.x;
+            p[i] = j < count ? bnd[k[i]] : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i) {
+            const int64_t sl = p[i] >= 0 ? bnd_slot(tg, p[i]) : -1;
+            q[i] = sl >= 0 ? bnd[sl] : p[i];
+        }
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i) {
+            const int64_t j = j0 + int64_t(i) * blockDim.x;
+            if (j < count && q[i] != p[i]) {
+                bnd[k[i]] = q[i];
                 changed = true;
             }
         }
@@ -541,10 +600,19 @@ MaximaLayout maxima_layout(int n) {
     return L;
 }
 
+int stride_grid(int64_t work) {
+    int64_t g = (work + 255) / 256;
+    return int(g > 4096 ? 4096 : (g < 1 ? 1 : g));
+}
+
+int batched_grid(int64_t work) { return stride_grid((work + BATCH - 1) / BATCH); }
+
 struct SegmentLayout {
-    size_t flags, ptr, bnd, total;
+    size_t flags, ptr, bnd, list, counts, total;
     int rounds;
     int64_t nbnd;
+    int jump_grid;      // workgroups of every jump round
+    int64_t list_cap;   // list entries per workgroup
 };
 
 SegmentLayout segment_layout(int n) {
@@ -561,6 +629,14 @@ SegmentLayout segment_layout(int n) {
         off = align_up(off + sizeof(int32_t) * cells);
         L.bnd = off;
         off = align_up(off + sizeof(int32_t) * size_t(L.nbnd));
+        // every round-0 workgroup visits at most cap entries
+        L.jump_grid = batched_grid(L.nbnd);
+        const int64_t per_pass = int64_t(L.jump_grid) * 256 * BATCH;
+        L.list_cap = (L.nbnd + per_pass - 1) / per_pass * 256 * BATCH;
+        L.list = off;
+        off = align_up(off + sizeof(uint32_t) * size_t(L.list_cap) * size_t(L.jump_grid));
+        L.counts = off;
+        off = align_up(off + sizeof(uint32_t) * size_t(L.jump_grid));
     } else {
         L.rounds = rounds_for(cells);
         off = align_up(off + sizeof(uint32_t) * (L.rounds + 2));
@@ -569,12 +645,6 @@ SegmentLayout segment_layout(int n) {
     return L;
 }
 
-int stride_grid(int64_t work) {
-    int64_t g = (work + 255) / 256;
-    return int(g > 4096 ? 4096 : (g < 1 ? 1 : g));
-}
-
-int batched_grid(int64_t work) { return stride_grid((work + BATCH - 1) / BATCH); }
 
 }  // namespace
 
@@ -607,9 +677,13 @@ hf_status segment_finish(hf_ctx *ctx, const SegmentLayout &L, char *w8, const Ti
     auto *flags = reinterpret_cast<uint32_t *>(w8 + L.flags);
     auto *ptr = reinterpret_cast<int32_t *>(w8 + L.ptr);
     auto *bnd = reinterpret_cast<int32_t *>(w8 + L.bnd);
-    const int g = batched_grid(L.nbnd);
-    for (int r = 0; r < L.rounds; ++r)
-        HF_LAUNCH(ctx, K_JUMP, bnd_jump_kernel, dim3(g), dim3(256), 0, ctx->stream, bnd, L.nbnd, tg, flags, r);
+    auto *list = reinterpret_cast<uint32_t *>(w8 + L.list);
+    auto *counts = reinterpret_cast<uint32_t *>(w8 + L.counts);
+    HF_LAUNCH(ctx, K_JUMP, bnd_jump_first_kernel, dim3(L.jump_grid), dim3(256), 0, ctx->stream, bnd, L.nbnd, tg, list,
+              L.list_cap, counts, flags);
+    for (int r = 1; r < L.rounds; ++r)
+        HF_LAUNCH(ctx, K_JUMP, bnd_jump_kernel, dim3(L.jump_grid), dim3(256), 0, ctx->stream, bnd, list, L.list_cap,
+                  counts, tg, flags, r);
     HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(SEG_THREADS), 0,
               ctx->stream, ptr, bnd, tg, cell_label);
     return launch_status();
