@@ -35,7 +35,7 @@ CSRC = os.path.join(ROOT, "paper_2501_10622_amd", "csrc")
 TIMER_SYMBOLS = {
     "zero_grid": ("fill_u64_kernel",), "deposit": ("tile_accum_kernel",), "label": ("label_kernel",),
     "deposit_atomic": ("deposit_atomic_kernel",),
-    "deposit_prep": ("zero_u32_kernel", "l1_scan_kernel", "l2_scan_kernel"),
+    "deposit_prep": ("zero_u32_kernel", "l1_scan_kernel", "seg_reduce_kernel<0>", "seg_scan_kernel<0>"),
     "deposit_l1_hist": ("l1_hist_kernel",), "deposit_l1_scatter": ("l1_scatter_kernel",),
     "deposit_l2_hist": ("l2_hist_kernel",), "deposit_l2_scatter": ("l2_scatter_kernel",),
     "deposit_fold": ("skirt_fold_kernel",),
@@ -43,7 +43,7 @@ TIMER_SYMBOLS = {
     "mass": ("mass_kernel",), "fft_y_fwd": ("fft_y_kernel<false>",), "fft_z_mul": ("fft_z_mul_kernel",),
     "fft_y_inv": ("fft_y_kernel<true>",), "fft_x_inv": ("fft_x_inv_kernel",),
     "maxima_mark": ("max_tile_kernel", "max_direct_kernel"), "maxima_count": ("mask_count_kernel",),
-    "maxima_scan": ("list_scan_kernel",), "maxima_write": ("list_write_kernel",),
+    "maxima_scan": ("seg_reduce_kernel<1>", "seg_scan_kernel<1>"), "maxima_write": ("list_write_kernel",),
     "parent": ("seg_tile_kernel", "parent_direct_kernel"), "jump_flags": ("fill_flags_kernel",),
     "jump": ("bnd_jump_kernel", "jump_direct_kernel"), "finalize": ("seg_finalize_kernel", "finalize_direct_kernel"),
     "label_tiles": ("tile_label_kernel",), "label_level1": ("to_level1_kernel",), "label_input": ("to_input_kernel",),
@@ -113,8 +113,8 @@ def short_symbol(name: str) -> str:
     if not m:
         return name
     tmpl = m.group(2) or ""
-    # keep a template argument only where it names a different pass (fft_y_kernel<INV>)
-    return m.group(1) + (tmpl if m.group(1) == "fft_y_kernel" else "")
+    # keep a template argument only where it names a different pass (fft_y_kernel<INV>, the scans' use)
+    return m.group(1) + (tmpl if m.group(1) in ("fft_y_kernel", "seg_reduce_kernel", "seg_scan_kernel") else "")
 
 
 def timer_name(symbol: str):

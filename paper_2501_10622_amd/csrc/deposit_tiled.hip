@@ -27,6 +27,7 @@
 // those passes reads form one run per bucket (per tile), which it reads into
 // LDS with consecutive lanes on consecutive slots.
 #include "hf_internal.h"
+#include "scan.h"
 
 using namespace hf;
 
@@ -402,31 +403,6 @@ __global__ void __launch_bounds__(HIST_THREADS) l2_hist_kernel(L2Input<T, FROM_R
     if (bad) atomicOr(status, ST_INPUT);
 }
 
-// start2 / cursor2 = exclusive scan of the per-tile counts (bucket-major order).
-__global__ void __launch_bounds__(1024) l2_scan_kernel(const uint32_t *__restrict__ count2, int ntiles,
-                                                       uint32_t *start2, uint32_t *cursor2) {
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int per = (ntiles + 1023) / 1024;
-    const int lo = t * per, hi = min(ntiles, lo + per);
-    uint32_t s = 0;
-    for (int i = lo; i < hi; ++i) s += count2[i];
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = t >= off ? part[t - off] : 0u;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    uint32_t run = t > 0 ? part[t - 1] : 0u;
-    for (int i = lo; i < hi; ++i) {
-        start2[i] = run;
-        cursor2[i] = run;
-        run += count2[i];
-    }
-    if (t == 1023) start2[ntiles] = part[1023];
-}
 
 // maps (optional, FROM_REC only) records where every level-1 record went.
 template <typename T, bool FROM_REC>
@@ -872,7 +848,8 @@ bool make_geom(const hf_box &box, Geom &out) {
 }
 
 struct DepLayout {
-    size_t count1, start1, cursor1, chunk_first, hchunk_first, count2, start2, cursor2, rec1, rec2, skirt, total;
+    size_t count1, start1, cursor1, chunk_first, hchunk_first, count2, start2, cursor2, partial, rec1, rec2, skirt,
+        total;
 };
 
 // Deposit workspace; with keep_order the level-2 records and the bucket and
@@ -893,6 +870,7 @@ DepLayout dep_layout(const Geom &g, int64_t np, bool keep_order) {
     L.hchunk_first = take(sizeof(uint32_t) * (MAX_DIGITS + 1));
     L.start2 = take(keep_order ? 0 : sizeof(uint32_t) * (size_t(g.ntiles) + 1));
     L.cursor2 = take(sizeof(uint32_t) * size_t(g.ntiles));
+    L.partial = take(sizeof(uint64_t) * SCAN_MAX_GROUPS);
     L.rec1 = take(g.nbuckets > 1 ? sizeof(Q3) * size_t(np) : 0);
     L.rec2 = take(keep_order ? 0 : sizeof(uint64_t) * size_t(np));
     L.skirt = take(sizeof(unsigned long long) * size_t(g.skirt) * size_t(g.ntiles));
@@ -947,6 +925,9 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
     auto *hchunk_first = reinterpret_cast<uint32_t *>(ws + L.hchunk_first);
     auto *start2 = order ? order->start2 : reinterpret_cast<uint32_t *>(ws + L.start2);
     auto *cursor2 = reinterpret_cast<uint32_t *>(ws + L.cursor2);
+    auto *partial = reinterpret_cast<uint64_t *>(ws + L.partial);
+    // start2 / cursor2 = exclusive scan of the per-tile counts (bucket-major order)
+    const ScanJob tile_scan = scan_job(count2, g.ntiles, partial, start2, cursor2);
     auto *rec1 = reinterpret_cast<Q3 *>(ws + L.rec1);
     auto *rec2 = order ? order->rec2 : reinterpret_cast<uint64_t *>(ws + L.rec2);
     auto *skirt = reinterpret_cast<unsigned long long *>(ws + L.skirt);
@@ -975,7 +956,10 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
         const L2Input<T, true> sin{pos, np, fp, rec1, start1, chunk_first, g.nbuckets, CHUNK};
         HF_LAUNCH(ctx, K_DEP_L2_HIST, (l2_hist_kernel<T, true>), dim3(hist_blocks + unsigned(g.nbuckets)),
                   dim3(HIST_THREADS), 0, st, hin, g, count2, ctx->d_status);
-        HF_LAUNCH(ctx, K_DEP_PREP, l2_scan_kernel, dim3(1), dim3(1024), 0, st, count2, g.ntiles, start2, cursor2);
+        HF_LAUNCH(ctx, K_DEP_PREP, seg_reduce_kernel<SCAN_TILES>, dim3(scan_groups(tile_scan)), dim3(SCAN_THREADS),
+                  0, st, tile_scan);
+        HF_LAUNCH(ctx, K_DEP_PREP, seg_scan_kernel<SCAN_TILES>, dim3(scan_groups(tile_scan)), dim3(SCAN_THREADS), 0,
+                  st, tile_scan);
         HF_LAUNCH(ctx, K_DEP_L2_SCATTER, (l2_scatter_kernel<T, true>), dim3(part_blocks + unsigned(g.nbuckets)),
                   dim3(PART_THREADS), 0, st, sin, g, cursor2, rec2, m2);
     } else {
@@ -984,7 +968,10 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
         if (hist_blocks)
             HF_LAUNCH(ctx, K_DEP_L2_HIST, (l2_hist_kernel<T, false>), dim3(hist_blocks), dim3(HIST_THREADS), 0, st,
                       hin, g, count2, ctx->d_status);
-        HF_LAUNCH(ctx, K_DEP_PREP, l2_scan_kernel, dim3(1), dim3(1024), 0, st, count2, g.ntiles, start2, cursor2);
+        HF_LAUNCH(ctx, K_DEP_PREP, seg_reduce_kernel<SCAN_TILES>, dim3(scan_groups(tile_scan)), dim3(SCAN_THREADS),
+                  0, st, tile_scan);
+        HF_LAUNCH(ctx, K_DEP_PREP, seg_scan_kernel<SCAN_TILES>, dim3(scan_groups(tile_scan)), dim3(SCAN_THREADS), 0,
+                  st, tile_scan);
         if (part_blocks)
             HF_LAUNCH(ctx, K_DEP_L2_SCATTER, (l2_scatter_kernel<T, false>), dim3(part_blocks), dim3(PART_THREADS),
                       0, st, sin, g, cursor2, rec2, RunMaps{});

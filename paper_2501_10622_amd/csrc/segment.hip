@@ -25,6 +25,7 @@
 //    cell of the tile through them.
 // Other sizes use direct per-cell kernels with the same results.
 #include "hf_internal.h"
+#include "scan.h"
 
 using namespace hf;
 
@@ -509,35 +510,6 @@ __global__ void __launch_bounds__(LIST_CHUNK_WORDS) mask_count_kernel(const uint
     if (threadIdx.x == 0) counts[blockIdx.x] = red[0] + red[1];
 }
 
-// Exclusive scan of the chunk counts (one workgroup, fixed order).
-__global__ void __launch_bounds__(1024) list_scan_kernel(const uint32_t *__restrict__ counts, int nchunks,
-                                                         uint32_t *__restrict__ offsets, int64_t cap,
-                                                         int64_t *d_count, uint32_t *status) {
-    __shared__ uint64_t part[1024];
-    const int t = threadIdx.x;
-    const int per = (nchunks + 1023) / 1024;
-    const int lo = t * per, hi = min(nchunks, lo + per);
-    uint64_t s = 0;
-    for (int i = lo; i < hi; ++i) s += counts[i];
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint64_t v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    uint64_t run = t > 0 ? part[t - 1] : 0;
-    for (int i = lo; i < hi; ++i) {
-        offsets[i] = uint32_t(run);
-        run += counts[i];
-    }
-    if (t == 1023) {
-        const uint64_t total = part[1023];
-        *d_count = int64_t(total);
-        if (int64_t(total) > cap) atomicOr(status, ST_CAPACITY);
-    }
-}
 
 __global__ void __launch_bounds__(LIST_CHUNK_WORDS) list_write_kernel(const uint32_t *__restrict__ mask,
                                                                       int64_t words,
@@ -579,7 +551,7 @@ int rounds_for(uint64_t count) {
 }
 
 struct MaximaLayout {
-    size_t mask, counts, offsets, total;
+    size_t mask, counts, offsets, partial, total;
     int64_t words;
     int nchunks;
 };
@@ -595,7 +567,9 @@ MaximaLayout maxima_layout(int n) {
     L.counts = off;
     off = align_up(off + sizeof(uint32_t) * L.nchunks);
     L.offsets = off;
-    off = align_up(off + sizeof(uint32_t) * L.nchunks);
+    off = align_up(off + sizeof(uint32_t) * (L.nchunks + 1));
+    L.partial = off;
+    off = align_up(off + sizeof(uint64_t) * SCAN_MAX_GROUPS);
     L.total = off;
     return L;
 }
@@ -663,8 +637,12 @@ hf_status mask_to_list(hf_ctx *ctx, const MaximaLayout &L, char *w8, int32_t *ma
     auto *offsets = reinterpret_cast<uint32_t *>(w8 + L.offsets);
     HF_LAUNCH(ctx, K_MAX_COUNT, mask_count_kernel, dim3(L.nchunks), dim3(LIST_CHUNK_WORDS), 0, ctx->stream, mask,
               L.words, counts);
-    HF_LAUNCH(ctx, K_MAX_SCAN, list_scan_kernel, dim3(1), dim3(1024), 0, ctx->stream, counts, L.nchunks, offsets,
-              max_cap, d_count, ctx->d_status);
+    const ScanJob sj = scan_job(counts, L.nchunks, reinterpret_cast<uint64_t *>(w8 + L.partial), offsets, nullptr,
+                                d_count, max_cap, ctx->d_status);
+    HF_LAUNCH(ctx, K_MAX_SCAN, seg_reduce_kernel<SCAN_MAXIMA>, dim3(scan_groups(sj)), dim3(SCAN_THREADS), 0,
+              ctx->stream, sj);
+    HF_LAUNCH(ctx, K_MAX_SCAN, seg_scan_kernel<SCAN_MAXIMA>, dim3(scan_groups(sj)), dim3(SCAN_THREADS), 0, ctx->stream,
+              sj);
     HF_LAUNCH(ctx, K_MAX_WRITE, list_write_kernel, dim3(L.nchunks), dim3(LIST_CHUNK_WORDS), 0, ctx->stream, mask,
               L.words, offsets, max_cap, max_idx);
     return launch_status();
