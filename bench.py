@@ -44,7 +44,7 @@ TIMER_SYMBOLS = {
     "fft_y_inv": ("fft_y_kernel<true>",), "fft_x_inv": ("fft_x_inv_kernel",),
     "maxima_mark": ("max_tile_kernel", "max_direct_kernel"), "maxima_count": ("mask_count_kernel",),
     "maxima_scan": ("seg_reduce_kernel<1>", "seg_scan_kernel<1>"), "maxima_write": ("list_write_kernel",),
-    "parent": ("seg_tile_kernel", "parent_direct_kernel"), "jump_flags": ("fill_flags_kernel",),
+    "parent": ("parent_tile_kernel", "parent_direct_kernel"), "resolve": ("resolve_tile_kernel",), "jump_flags": ("fill_flags_kernel",),
     "jump": ("bnd_jump_kernel", "jump_direct_kernel"), "finalize": ("seg_finalize_kernel", "finalize_direct_kernel"),
     "label_tiles": ("tile_label_kernel",), "label_level1": ("to_level1_kernel",), "label_input": ("to_input_kernel",),
 }
@@ -63,8 +63,9 @@ STAGES = {
     "cwt_z_mul": ("fft_z_mul",),
     "cwt_y_inv": ("fft_y_inv",),
     "cwt_x_inv": ("fft_x_inv",),
-    "maxima": ("maxima_mark", "maxima_count", "maxima_scan", "maxima_write"),
-    "segment": ("parent", "jump_flags", "jump", "finalize"),
+    # the one-call pipeline finds the maxima in the segmentation's parent pass
+    "maxima_segment": ("maxima_mark", "maxima_count", "maxima_scan", "maxima_write", "parent", "resolve",
+                       "jump_flags", "jump", "finalize"),
     "label": ("label", "label_tiles", "label_level1", "label_input"),
 }
 
@@ -74,8 +75,9 @@ def stage_bytes(n: int, np_: int, pos_bytes: int) -> dict:
 
     deposit 12 B/particle (FP32 positions) + 8 B/cell; the transform as five
     pencil sweeps: x forward 8 + 4.01, y 8.02, z*mul*z^-1 8.02, y^-1 8.02, x^-1
-    4.01 + 4 (44.06 B/cell); maxima 4 B/cell; segmentation 4 + 4 B/cell; labels
-    3 * pos + 4 (cell label) + 4 (label) B/particle.  Launches that exist only
+    4.01 + 4 (44.06 B/cell); maxima 4 B/cell and segmentation 4 + 4 B/cell,
+    one stage since one pass over the field serves both; labels 3 * pos + 4
+    (cell label) + 4 (label) B/particle.  Launches that exist only
     because of how a stage is built (histograms, scans, tables, pointer rounds,
     the kept particle order) add no algorithmic bytes.
     """
@@ -88,8 +90,7 @@ def stage_bytes(n: int, np_: int, pos_bytes: int) -> dict:
         "cwt_z_mul": 2 * half,
         "cwt_y_inv": 2 * half,
         "cwt_x_inv": half + 4 * cells,
-        "maxima": 4 * cells,
-        "segment": 8 * cells,
+        "maxima_segment": (4 + 8) * cells,
         "label": (pos_bytes * 3 + 4 + 4) * np_,
     }
 

@@ -19,7 +19,7 @@ const char *hf::kernel_name(int id) {
         "tables_1", "tables_2", "fft_x_fwd", "mass", "fft_y_fwd", "fft_z_mul", "fft_y_inv", "fft_x_inv",
         "maxima_mark", "maxima_count", "maxima_scan", "maxima_write",
         "parent", "jump_flags", "jump", "finalize",
-        "label_tiles", "label_level1", "label_input",
+        "label_tiles", "label_level1", "label_input", "resolve",
     };
     return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }

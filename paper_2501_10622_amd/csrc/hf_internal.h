@@ -18,7 +18,7 @@ enum KernelId {
     K_TABLES_1, K_TABLES_2, K_X_FWD, K_MASS, K_Y_FWD, K_Z_MUL, K_Y_INV, K_X_INV,
     K_MAX_MARK, K_MAX_COUNT, K_MAX_SCAN, K_MAX_WRITE,
     K_PARENT, K_FLAGS, K_JUMP, K_FINALIZE,
-    K_LABEL_TILES, K_LABEL_LEVEL1, K_LABEL_INPUT,
+    K_LABEL_TILES, K_LABEL_LEVEL1, K_LABEL_INPUT, K_RESOLVE,
     K_COUNT
 };
 const char *kernel_name(int id);

@@ -10,14 +10,17 @@
 //
 // Tiled path (n % 32 == 0): one workgroup per 32x8x8 tile holds the tile and a
 // one-cell halo of keys in LDS and forms the 3x3x3 maximum separably (x, y, z).
+// That pass writes every cell's parent index (the maxima mask as well when
+// asked); chains are then resolved on larger 32x16x16 tiles, whose int32
+// pointers alone fit LDS, so fewer cells sit on tile boundaries.
 //  - maxima: a wavefront covers two 32-cell rows, so its ballot is two aligned
 //    32-bit words of a linear-order bit mask; count / scan / write passes turn
 //    the mask into the sorted index list.
-//  - segmentation: parent chains are followed inside the tile by pointer
-//    doubling in LDS, so every cell ends at a root or at the first cell its
-//    chain reaches outside the tile.  Such exit targets are always on a tile
-//    boundary, so only the 968 boundary cells of each tile (kept in a compact
-//    array) take part in the global pointer-jumping rounds.  A root at or
+//  - segmentation: parent chains are followed inside each 32x16x16 tile by
+//    pointer doubling in LDS, so every cell ends at a root or at the first cell
+//    its chain reaches outside the tile.  Such exit targets are always on a
+//    tile boundary, so only the 2312 boundary cells of each tile (kept in a
+//    compact array) take part in the global pointer-jumping rounds.  A root at or
 //    below tau is written as -1 by its own tile, so the rounds carry the
 //    threshold along and no later pass reads the field again.  A last pass,
 //    one workgroup per tile, loads the resolved entries of the one-cell shell
@@ -60,9 +63,17 @@ constexpr int TX = 32, TY = 8, TZ = 8;
 constexpr int TCELLS = TX * TY * TZ;                          // 2048
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
 constexpr int HCELLS = HX * HY * HZ;                          // 3400
-constexpr int NBND = 2 * TX * TY + (TZ - 2) * (2 * TX + 2 * (TY - 2));  // 968 boundary cells per tile
 constexpr int SEG_THREADS = 512;
-constexpr int PER_THREAD = TCELLS / SEG_THREADS;              // 8
+constexpr int PER_THREAD = TCELLS / SEG_THREADS;              // 4
+
+// Resolve tiles: chains are followed inside RX x RY x RZ tiles.
+constexpr int RX = 32, RY = 16, RZ = 16;
+constexpr int RCELLS = RX * RY * RZ;                          // 8192
+constexpr int RHX = RX + 2, RHY = RY + 2, RHZ = RZ + 2;
+constexpr int RHCELLS = RHX * RHY * RHZ;                      // 11016 (tile plus one-cell shell)
+constexpr int NBND = 2 * RX * RY + (RZ - 2) * (2 * RX + 2 * (RY - 2));  // 2312 boundary cells per tile
+constexpr int RES_THREADS = 1024;
+constexpr int RES_PER = RCELLS / RES_THREADS;                 // 8
 
 struct TileGrid {
     int n;
@@ -77,28 +88,29 @@ __device__ __forceinline__ void cell_coords(const TileGrid &tg, uint32_t g, uint
     y = q - z * uint32_t(tg.n);
 }
 
-// Rank of local cell (x, y, z) among its tile's boundary cells, or -1.
-// Order: plane z = 0, planes 1..6 (row y = 0, then x = 0 / x = 31 of rows
-// 1..6, then row y = 7), plane z = 7.
+// Rank of local cell (x, y, z) among its resolve tile's boundary cells, or -1.
+// Order: plane z = 0, planes 1..RZ-2 (row y = 0, then x = 0 / x = RX-1 of rows
+// 1..RY-2, then row y = RY-1), plane z = RZ-1.
 __device__ __forceinline__ int bnd_rank(int x, int y, int z) {
-    if (z == 0) return y * TX + x;
-    constexpr int MID = 2 * TX + 2 * (TY - 2);  // 76
-    if (z == TZ - 1) return TX * TY + (TZ - 2) * MID + y * TX + x;
-    const int base = TX * TY + (z - 1) * MID;
+    if (z == 0) return y * RX + x;
+    constexpr int MID = 2 * RX + 2 * (RY - 2);
+    if (z == RZ - 1) return RX * RY + (RZ - 2) * MID + y * RX + x;
+    const int base = RX * RY + (z - 1) * MID;
     if (y == 0) return base + x;
-    if (y == TY - 1) return base + TX + 2 * (TY - 2) + x;
-    if (x == 0) return base + TX + 2 * (y - 1);
-    if (x == TX - 1) return base + TX + 2 * (y - 1) + 1;
+    if (y == RY - 1) return base + RX + 2 * (RY - 2) + x;
+    if (x == 0) return base + RX + 2 * (y - 1);
+    if (x == RX - 1) return base + RX + 2 * (y - 1) + 1;
     return -1;
 }
 
-// Where the compact boundary array keeps cell g, or -1 if g is interior.
-__device__ __forceinline__ int64_t bnd_slot(const TileGrid &tg, int32_t g) {
+// Where the compact boundary array keeps cell g (rg: the resolve-tile grid),
+// or -1 if g is interior to its tile.
+__device__ __forceinline__ int64_t bnd_slot(const TileGrid &rg, int32_t g) {
     uint32_t x, y, z;
-    cell_coords(tg, uint32_t(g), x, y, z);
-    const int r = bnd_rank(int(x % TX), int(y % TY), int(z % TZ));
+    cell_coords(rg, uint32_t(g), x, y, z);
+    const int r = bnd_rank(int(x % RX), int(y % RY), int(z % RZ));
     if (r < 0) return -1;
-    const int64_t tile = (int64_t(z / TZ) * tg.nty + y / TY) * tg.ntx + x / TX;
+    const int64_t tile = (int64_t(z / RZ) * rg.nty + y / RY) * rg.ntx + x / RX;
     return tile * NBND + r;
 }
 
@@ -152,6 +164,12 @@ __device__ __forceinline__ void tile_origin(const TileGrid &tg, int t, int &x0, 
     z0 = (t / (tg.ntx * tg.nty)) * TZ;
 }
 
+__device__ __forceinline__ void rtile_origin(const TileGrid &rg, int t, int &x0, int &y0, int &z0) {
+    x0 = (t % rg.ntx) * RX;
+    y0 = ((t / rg.ntx) % rg.nty) * RY;
+    z0 = (t / (rg.ntx * rg.nty)) * RZ;
+}
+
 // Maxima bit mask of the tile from its parent keys M: bit (j % 32) of word
 // j / 32 is set iff cell j is its own parent with a value above tau.
 __device__ __forceinline__ void write_mask(const uint64_t *M, uint32_t n, int x0, int y0, int z0, uint32_t tau_ord,
@@ -185,14 +203,13 @@ __global__ void __launch_bounds__(SEG_THREADS) max_tile_kernel(const float *__re
     if (nan) atomicOr(status, ST_INPUT);
 }
 
-// Parents resolved inside the tile.  ptr[g] = the root or the exit target of
-// cell g's chain; bnd[] holds the same for the tile's boundary cells.  With a
+// Parent of every cell: parent[g] = the index of the largest key of g's 3x3x3
+// neighbourhood, or -1 for a root (its own parent) at or below tau.  With a
 // mask, the tile's maxima bits are written as well (the maxima are exactly the
 // cells that are their own parent, above tau).
-__global__ void __launch_bounds__(SEG_THREADS) seg_tile_kernel(const float *__restrict__ c, TileGrid tg,
-                                                               int32_t *__restrict__ ptr, int32_t *__restrict__ bnd,
-                                                               uint32_t tau_ord, uint32_t *__restrict__ mask,
-                                                               uint32_t *status) {
+__global__ void __launch_bounds__(SEG_THREADS) parent_tile_kernel(const float *__restrict__ c, TileGrid tg,
+                                                                  uint32_t tau_ord, int32_t *__restrict__ parent,
+                                                                  uint32_t *__restrict__ mask, uint32_t *status) {
     __shared__ uint64_t K[HCELLS];
     __shared__ uint64_t M[TX * HY * HZ];
     int x0, y0, z0;
@@ -202,60 +219,79 @@ __global__ void __launch_bounds__(SEG_THREADS) seg_tile_kernel(const float *__re
     tile_parent_keys(c, tg.n, x0, y0, z0, K, M, nan);
     const uint32_t n = uint32_t(tg.n);
     if (mask) write_mask(M, n, x0, y0, z0, tau_ord, mask);
-    // loc[e] >= 0: pointer to local cell loc[e];  loc[e] < 0: resolved, with
-    // u = -loc[e] - 1 either a local root index (u < TCELLS) or EXIT | global
-    // index of the first cell outside the tile (n^3 <= 2^30 leaves bit 30 free)
-    constexpr uint32_t EXIT = 1u << 30;
-    int32_t *loc = reinterpret_cast<int32_t *>(K);
-    for (int e = threadIdx.x; e < TCELLS; e += SEG_THREADS) {
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; ++i) {
+        const int e = i * SEG_THREADS + threadIdx.x;
         const int x = e % TX, y = (e / TX) % TY, z = e / (TX * TY);
         const uint32_t g = ((uint32_t(z0 + z) * n) + uint32_t(y0 + y)) * n + uint32_t(x0 + x);
-        const uint32_t p = uint32_t(M[e]);
-        int32_t v = -int32_t(e) - 1;  // a root
-        if (p != g) {
+        const uint64_t k = M[e];
+        const uint32_t p = uint32_t(k);
+        parent[g] = (p == g && uint32_t(k >> 32) <= tau_ord) ? -1 : int32_t(p);
+    }
+    if (nan) atomicOr(status, ST_INPUT);
+}
+
+// Chains resolved inside a resolve tile, in place: ptr[] holds parents on
+// entry and, on exit, each cell's root (-1 for a root at or below tau) or the
+// first cell its chain reaches outside the tile; bnd[] holds the same for the
+// tile's boundary cells.  In LDS, loc[e] >= 0 points to local cell loc[e];
+// loc[e] < 0 is resolved to the value -2 - loc[e].
+__global__ void __launch_bounds__(RES_THREADS) resolve_tile_kernel(int32_t *__restrict__ ptr, TileGrid rg,
+                                                                   int32_t *__restrict__ bnd) {
+    __shared__ int32_t loc[RCELLS];
+    int x0, y0, z0;
+    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    rtile_origin(rg, int(tile), x0, y0, z0);
+    const uint32_t n = uint32_t(rg.n);
+    int32_t v[RES_PER];
+#pragma unroll
+    for (int i = 0; i < RES_PER; ++i) {
+        const int e = i * RES_THREADS + threadIdx.x;
+        const int x = e % RX, y = (e / RX) % RY, z = e / (RX * RY);
+        v[i] = ptr[((uint32_t(z0 + z) * n) + uint32_t(y0 + y)) * n + uint32_t(x0 + x)];
+    }
+#pragma unroll
+    for (int i = 0; i < RES_PER; ++i) {
+        const int e = i * RES_THREADS + threadIdx.x;
+        const int x = e % RX, y = (e / RX) % RY, z = e / (RX * RY);
+        const uint32_t g = ((uint32_t(z0 + z) * n) + uint32_t(y0 + y)) * n + uint32_t(x0 + x);
+        const int32_t p = v[i];
+        int32_t l = -2 - p;  // resolved: -1, a root, or a cell outside the tile
+        if (p >= 0 && uint32_t(p) != g) {
             uint32_t px, py, pz;
-            cell_coords(tg, p, px, py, pz);
+            cell_coords(rg, uint32_t(p), px, py, pz);
             const int lx = int(px) - x0, ly = int(py) - y0, lz = int(pz) - z0;
-            v = (lx >= 0 && lx < TX && ly >= 0 && ly < TY && lz >= 0 && lz < TZ) ? lx + TX * (ly + TY * lz)
-                                                                                  : -int32_t(EXIT | p) - 1;
+            if (lx >= 0 && lx < RX && ly >= 0 && ly < RY && lz >= 0 && lz < RZ) l = lx + RX * (ly + RY * lz);
         }
-        loc[e] = v;
+        loc[e] = l;
     }
     __syncthreads();
-    // pointer doubling inside the tile (chains are at most TCELLS - 1 long)
+    // pointer doubling inside the tile (chains are at most RCELLS - 1 long)
     bool open = true;
     while (open) {
-        int32_t nv[PER_THREAD];
+        int32_t nv[RES_PER];
         bool any = false;
 #pragma unroll
-        for (int i = 0; i < PER_THREAD; ++i) {
-            const int32_t v = loc[i * SEG_THREADS + threadIdx.x];
-            nv[i] = v >= 0 ? loc[v] : v;
+        for (int i = 0; i < RES_PER; ++i) {
+            const int32_t w = loc[i * RES_THREADS + threadIdx.x];
+            nv[i] = w >= 0 ? loc[w] : w;
             any |= nv[i] >= 0;
         }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < PER_THREAD; ++i) loc[i * SEG_THREADS + threadIdx.x] = nv[i];
+        for (int i = 0; i < RES_PER; ++i) loc[i * RES_THREADS + threadIdx.x] = nv[i];
         open = __syncthreads_or(any);
     }
-    for (int e = threadIdx.x; e < TCELLS; e += SEG_THREADS) {
-        const int x = e % TX, y = (e / TX) % TY, z = e / (TX * TY);
+#pragma unroll
+    for (int i = 0; i < RES_PER; ++i) {
+        const int e = i * RES_THREADS + threadIdx.x;
+        const int x = e % RX, y = (e / RX) % RY, z = e / (RX * RY);
         const uint32_t g = ((uint32_t(z0 + z) * n) + uint32_t(y0 + y)) * n + uint32_t(x0 + x);
-        const uint32_t u = uint32_t(-loc[e] - 1);
-        int32_t t;
-        if (u & EXIT) {
-            t = int32_t(u & ~EXIT);
-        } else {  // a root of this tile: its own key is M[u]; -1 unless above tau
-            const int rx = int(u) % TX, ry = (int(u) / TX) % TY, rz = int(u) / (TX * TY);
-            t = uint32_t(M[u] >> 32) > tau_ord
-                    ? int32_t(((uint32_t(z0 + rz) * n) + uint32_t(y0 + ry)) * n + uint32_t(x0 + rx))
-                    : -1;
-        }
+        const int32_t t = -2 - loc[e];
         ptr[g] = t;
         const int r = bnd_rank(x, y, z);
         if (r >= 0) bnd[int64_t(tile) * NBND + r] = t;
     }
-    if (nan) atomicOr(status, ST_INPUT);
 }
 
 __global__ void fill_flags_kernel(uint32_t *flags, int count) {
@@ -358,56 +394,61 @@ __global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd
     if (__any(changed) && (threadIdx.x & 63) == 0) flags[round + 1] = 1u;
 }
 
-// One workgroup per tile: the resolved boundary entries of the one-cell shell
-// around the tile go to LDS (they belong to the neighbouring tiles; every exit
-// target of the tile lies in the shell), then every cell of the tile maps its
-// pointer: -1 stays -1, a target inside the tile is a root above tau, a target
-// in the shell takes the shell's entry.
-__global__ void __launch_bounds__(SEG_THREADS) seg_finalize_kernel(const int32_t *__restrict__ ptr,
-                                                                   const int32_t *__restrict__ bnd, TileGrid tg,
+// One workgroup per resolve tile: the resolved boundary entries of the
+// one-cell shell around the tile go to LDS (they belong to the neighbouring
+// tiles; every exit target of the tile lies in the shell), then every cell of
+// the tile maps its pointer: -1 stays -1, a target inside the tile is a root
+// above tau, a target in the shell takes the shell's entry.
+__global__ void __launch_bounds__(RES_THREADS) seg_finalize_kernel(const int32_t *__restrict__ ptr,
+                                                                   const int32_t *__restrict__ bnd, TileGrid rg,
                                                                    int32_t *__restrict__ label) {
-    __shared__ int32_t shell[HCELLS];
+    __shared__ int32_t shell[RHCELLS];
     int x0, y0, z0;
     const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    tile_origin(tg, int(tile), x0, y0, z0);
-    const int n = tg.n;
-    // shell cells: halo coordinates (hx, hy, hz) with at least one on the rim;
-    // all loads are issued before any is stored
-    constexpr int LOADS = (HCELLS + SEG_THREADS - 1) / SEG_THREADS;
+    rtile_origin(rg, int(tile), x0, y0, z0);
+    const int n = rg.n;
+    const uint32_t un = uint32_t(n);
+    // this tile's pointers and the shell's entries, all loads issued before any is used
+    int32_t t[RES_PER];
+#pragma unroll
+    for (int i = 0; i < RES_PER; ++i) {
+        const int e = i * RES_THREADS + threadIdx.x;
+        const int x = e % RX, y = (e / RX) % RY, z = e / (RX * RY);
+        t[i] = ptr[((uint32_t(z0 + z) * un) + uint32_t(y0 + y)) * un + uint32_t(x0 + x)];
+    }
+    constexpr int LOADS = (RHCELLS + RES_THREADS - 1) / RES_THREADS;
     int32_t v[LOADS];
     bool rim[LOADS];
 #pragma unroll
     for (int i = 0; i < LOADS; ++i) {
-        const int e = threadIdx.x + i * SEG_THREADS;
-        const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
-        rim[i] = e < HCELLS && (hx == 0 || hx == HX - 1 || hy == 0 || hy == HY - 1 || hz == 0 || hz == HZ - 1);
+        const int e = threadIdx.x + i * RES_THREADS;
+        const int hx = e % RHX, hy = (e / RHX) % RHY, hz = e / (RHX * RHY);
+        rim[i] = e < RHCELLS && (hx == 0 || hx == RHX - 1 || hy == 0 || hy == RHY - 1 || hz == 0 || hz == RHZ - 1);
         if (rim[i]) {
             const uint32_t gx = wrap(x0 + hx - 1, n), gy = wrap(y0 + hy - 1, n), gz = wrap(z0 + hz - 1, n);
-            const int r = bnd_rank(int(gx % TX), int(gy % TY), int(gz % TZ));  // on its tile's boundary
-            const int64_t t = (int64_t(gz / TZ) * tg.nty + gy / TY) * tg.ntx + gx / TX;
-            v[i] = bnd[t * NBND + r];
+            const int r = bnd_rank(int(gx % RX), int(gy % RY), int(gz % RZ));  // on its tile's boundary
+            const int64_t nt = (int64_t(gz / RZ) * rg.nty + gy / RY) * rg.ntx + gx / RX;
+            v[i] = bnd[nt * NBND + r];
         }
     }
 #pragma unroll
     for (int i = 0; i < LOADS; ++i)
-        if (rim[i]) shell[threadIdx.x + i * SEG_THREADS] = v[i];
+        if (rim[i]) shell[threadIdx.x + i * RES_THREADS] = v[i];
     __syncthreads();
-    const uint32_t un = uint32_t(n);
 #pragma unroll
-    for (int i = 0; i < PER_THREAD; ++i) {
-        const int e = i * SEG_THREADS + threadIdx.x;
-        const int x = e % TX, y = (e / TX) % TY, z = e / (TX * TY);
+    for (int i = 0; i < RES_PER; ++i) {
+        const int e = i * RES_THREADS + threadIdx.x;
+        const int x = e % RX, y = (e / RX) % RY, z = e / (RX * RY);
         const uint32_t g = ((uint32_t(z0 + z) * un) + uint32_t(y0 + y)) * un + uint32_t(x0 + x);
-        const int32_t t = ptr[g];
-        int32_t r = t;
-        if (t >= 0) {
+        int32_t r = t[i];
+        if (r >= 0) {
             uint32_t px, py, pz;
-            cell_coords(tg, uint32_t(t), px, py, pz);
-            // halo coordinates of the target, periodic
+            cell_coords(rg, uint32_t(r), px, py, pz);
+            // shell coordinates of the target, periodic
             const int hx = int(wrap(int(px) - x0 + 1, n)), hy = int(wrap(int(py) - y0 + 1, n)),
                       hz = int(wrap(int(pz) - z0 + 1, n));
-            const bool inside = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY && hz >= 1 && hz <= TZ;
-            if (!inside) r = shell[(hz * HY + hy) * HX + hx];
+            const bool inside = hx >= 1 && hx <= RX && hy >= 1 && hy <= RY && hz >= 1 && hz <= RZ;
+            if (!inside) r = shell[(hz * RHY + hy) * RHX + hx];
         }
         label[g] = r;
     }
@@ -540,9 +581,11 @@ __global__ void __launch_bounds__(LIST_CHUNK_WORDS) list_write_kernel(const uint
 }
 
 // ------------------------------------------------------------------ host side
-bool tiled(int n) { return n % TX == 0; }  // TY = TZ = 8 divide every multiple of 32
+bool tiled(int n) { return n % TX == 0; }  // TY, TZ, RY and RZ (8 or 16) divide every multiple of 32
 
 TileGrid tile_grid(int n) { return TileGrid{n, n / TX, n / TY, n / TZ, FastDiv(uint32_t(n))}; }
+
+TileGrid resolve_grid(int n) { return TileGrid{n, n / RX, n / RY, n / RZ, FastDiv(uint32_t(n))}; }
 
 int rounds_for(uint64_t count) {
     int k = 0;
@@ -595,8 +638,8 @@ SegmentLayout segment_layout(int n) {
     size_t off = 0;
     L.flags = off;
     if (tiled(n)) {
-        const TileGrid tg = tile_grid(n);
-        L.nbnd = int64_t(tg.ntx) * tg.nty * tg.ntz * NBND;
+        const TileGrid rg = resolve_grid(n);
+        L.nbnd = int64_t(rg.ntx) * rg.nty * rg.ntz * NBND;
         L.rounds = rounds_for(uint64_t(L.nbnd));
         off = align_up(off + sizeof(uint32_t) * (L.rounds + 2));
         L.ptr = off;
@@ -648,13 +691,16 @@ hf_status mask_to_list(hf_ctx *ctx, const MaximaLayout &L, char *w8, int32_t *ma
     return launch_status();
 }
 
-// Pointer-jumping rounds and the final mapping through the boundary array,
-// after seg_tile_kernel has filled ptr and bnd.
-hf_status segment_finish(hf_ctx *ctx, const SegmentLayout &L, char *w8, const TileGrid &tg, const float *cwt,
-                         float tau, int32_t *cell_label) {
+// After parent_tile_kernel has filled ptr with parents: chains resolved per
+// resolve tile, pointer-jumping rounds over the boundary entries, and the final
+// mapping through them.
+hf_status segment_finish(hf_ctx *ctx, const SegmentLayout &L, char *w8, int n, int32_t *cell_label) {
+    const TileGrid tg = resolve_grid(n);
     auto *flags = reinterpret_cast<uint32_t *>(w8 + L.flags);
     auto *ptr = reinterpret_cast<int32_t *>(w8 + L.ptr);
     auto *bnd = reinterpret_cast<int32_t *>(w8 + L.bnd);
+    HF_LAUNCH(ctx, K_RESOLVE, resolve_tile_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(RES_THREADS), 0, ctx->stream,
+              ptr, tg, bnd);
     auto *list = reinterpret_cast<uint32_t *>(w8 + L.list);
     auto *counts = reinterpret_cast<uint32_t *>(w8 + L.counts);
     HF_LAUNCH(ctx, K_JUMP, bnd_jump_first_kernel, dim3(L.jump_grid), dim3(256), 0, ctx->stream, bnd, L.nbnd, tg, list,
@@ -662,7 +708,7 @@ hf_status segment_finish(hf_ctx *ctx, const SegmentLayout &L, char *w8, const Ti
     for (int r = 1; r < L.rounds; ++r)
         HF_LAUNCH(ctx, K_JUMP, bnd_jump_kernel, dim3(L.jump_grid), dim3(256), 0, ctx->stream, bnd, list, L.list_cap,
                   counts, tg, flags, r);
-    HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(SEG_THREADS), 0,
+    HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(RES_THREADS), 0,
               ctx->stream, ptr, bnd, tg, cell_label);
     return launch_status();
 }
@@ -696,12 +742,12 @@ hf_status hf::maxima_segment(hf_ctx *ctx, const hf_box &box, const float *cwt, f
     auto *flags = reinterpret_cast<uint32_t *>(w8 + SL.flags);
     HF_LAUNCH(ctx, K_FLAGS, fill_flags_kernel, dim3((SL.rounds + 2 + 255) / 256), dim3(256), 0, ctx->stream, flags,
               SL.rounds + 2);
-    HF_LAUNCH(ctx, K_PARENT, seg_tile_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(SEG_THREADS), 0, ctx->stream, cwt,
-              tg, reinterpret_cast<int32_t *>(w8 + SL.ptr), reinterpret_cast<int32_t *>(w8 + SL.bnd),
-              host_ordered_bits(tau), reinterpret_cast<uint32_t *>(wm + ML.mask), ctx->d_status);
+    HF_LAUNCH(ctx, K_PARENT, parent_tile_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(SEG_THREADS), 0, ctx->stream,
+              cwt, tg, host_ordered_bits(tau), reinterpret_cast<int32_t *>(w8 + SL.ptr),
+              reinterpret_cast<uint32_t *>(wm + ML.mask), ctx->d_status);
     s = mask_to_list(ctx, ML, wm, max_idx, max_cap, d_count);
     if (s != HF_OK) return s;
-    return segment_finish(ctx, SL, w8, tg, cwt, tau, cell_label);
+    return segment_finish(ctx, SL, w8, n, cell_label);
 }
 
 extern "C" hf_status hf_maxima(hf_ctx *ctx, const hf_box *box, const float *cwt, float tau, int32_t *max_idx,
@@ -746,11 +792,10 @@ extern "C" hf_status hf_segment(hf_ctx *ctx, const hf_box *box, const float *cwt
               L.rounds + 2);
     if (tiled(n)) {
         const TileGrid tg = tile_grid(n);
-        auto *ptr = reinterpret_cast<int32_t *>(w8 + L.ptr);
-        auto *bnd = reinterpret_cast<int32_t *>(w8 + L.bnd);
-        HF_LAUNCH(ctx, K_PARENT, seg_tile_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(SEG_THREADS), 0, ctx->stream,
-                  cwt, tg, ptr, bnd, host_ordered_bits(tau), nullptr, ctx->d_status);
-        return segment_finish(ctx, L, w8, tg, cwt, tau, cell_label);
+        HF_LAUNCH(ctx, K_PARENT, parent_tile_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(SEG_THREADS), 0,
+                  ctx->stream, cwt, tg, host_ordered_bits(tau), reinterpret_cast<int32_t *>(w8 + L.ptr), nullptr,
+                  ctx->d_status);
+        return segment_finish(ctx, L, w8, n, cell_label);
     } else {
         const uint32_t cells = uint32_t(n) * n * n;
         const int g = stride_grid(cells);
