@@ -71,6 +71,7 @@ constexpr int RX = 32, RY = 16, RZ = 16;
 constexpr int RCELLS = RX * RY * RZ;                          // 8192
 constexpr int RHX = RX + 2, RHY = RY + 2, RHZ = RZ + 2;
 constexpr int RHCELLS = RHX * RHY * RHZ;                      // 11016 (tile plus one-cell shell)
+static_assert(2 * RHX * RHY + (RHZ - 2) * (2 * RHX + 2 * (RHY - 2)) == RHCELLS - RCELLS, "shell enumeration");
 constexpr int NBND = 2 * RX * RY + (RZ - 2) * (2 * RX + 2 * (RY - 2));  // 2312 boundary cells per tile
 constexpr int RES_THREADS = 1024;
 constexpr int RES_PER = RCELLS / RES_THREADS;                 // 8
@@ -416,24 +417,46 @@ __global__ void __launch_bounds__(RES_THREADS) seg_finalize_kernel(const int32_t
         const int x = e % RX, y = (e / RX) % RY, z = e / (RX * RY);
         t[i] = ptr[((uint32_t(z0 + z) * un) + uint32_t(y0 + y)) * un + uint32_t(x0 + x)];
     }
-    constexpr int LOADS = (RHCELLS + RES_THREADS - 1) / RES_THREADS;
+    // the shell's cells, enumerated: the two z planes, then per inner plane the
+    // two y rows and the two x ends of the rows between them
+    constexpr int ZPLANE = RHX * RHY, RING = 2 * RHX + 2 * (RHY - 2);
+    constexpr int NSHELL = 2 * ZPLANE + (RHZ - 2) * RING;  // RHCELLS - RCELLS
+    constexpr int LOADS = (NSHELL + RES_THREADS - 1) / RES_THREADS;
     int32_t v[LOADS];
-    bool rim[LOADS];
+    int at[LOADS];
 #pragma unroll
     for (int i = 0; i < LOADS; ++i) {
-        const int e = threadIdx.x + i * RES_THREADS;
-        const int hx = e % RHX, hy = (e / RHX) % RHY, hz = e / (RHX * RHY);
-        rim[i] = e < RHCELLS && (hx == 0 || hx == RHX - 1 || hy == 0 || hy == RHY - 1 || hz == 0 || hz == RHZ - 1);
-        if (rim[i]) {
-            const uint32_t gx = wrap(x0 + hx - 1, n), gy = wrap(y0 + hy - 1, n), gz = wrap(z0 + hz - 1, n);
-            const int r = bnd_rank(int(gx % RX), int(gy % RY), int(gz % RZ));  // on its tile's boundary
-            const int64_t nt = (int64_t(gz / RZ) * rg.nty + gy / RY) * rg.ntx + gx / RX;
-            v[i] = bnd[nt * NBND + r];
+        const int k = threadIdx.x + i * RES_THREADS;
+        at[i] = -1;
+        if (k >= NSHELL) continue;
+        int hx, hy, hz;
+        if (k < 2 * ZPLANE) {
+            hz = k < ZPLANE ? 0 : RHZ - 1;
+            const int j = k % ZPLANE;
+            hy = j / RHX;
+            hx = j % RHX;
+        } else {
+            const int j = k - 2 * ZPLANE;
+            hz = 1 + j / RING;
+            const int r = j % RING;
+            if (r < 2 * RHX) {
+                hy = r < RHX ? 0 : RHY - 1;
+                hx = r % RHX;
+            } else {
+                const int q = r - 2 * RHX;
+                hy = 1 + q / 2;
+                hx = (q & 1) ? RHX - 1 : 0;
+            }
         }
+        const uint32_t gx = wrap(x0 + hx - 1, n), gy = wrap(y0 + hy - 1, n), gz = wrap(z0 + hz - 1, n);
+        const int r = bnd_rank(int(gx % RX), int(gy % RY), int(gz % RZ));  // on its tile's boundary
+        const int64_t nt = (int64_t(gz / RZ) * rg.nty + gy / RY) * rg.ntx + gx / RX;
+        v[i] = bnd[nt * NBND + r];
+        at[i] = (hz * RHY + hy) * RHX + hx;
     }
 #pragma unroll
     for (int i = 0; i < LOADS; ++i)
-        if (rim[i]) shell[threadIdx.x + i * RES_THREADS] = v[i];
+        if (at[i] >= 0) shell[at[i]] = v[i];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < RES_PER; ++i) {
