@@ -89,6 +89,9 @@ extern "C" hf_status hf_create(int device, void *hip_stream, hf_ctx **out) {
     hf_ctx *c = new hf_ctx{};
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->cus = cus;
     if (hipMalloc(&c->d_status, 256) != hipSuccess) {
         delete c;
         return HF_ERR_DEVICE;

@@ -114,34 +114,53 @@ __device__ __forceinline__ uint64_t pack_local(const Geom &g, const Q3 &q) {
 
 constexpr int LBATCH = 8;  // loads per thread issued together in the streaming passes
 
-// q of particles i0 + k * stride (k < LBATCH) below end; all loads are issued
-// before any conversion so they are in flight together.  valid[k] is false for
-// indices past the end and for positions the deposit rejects (bad set).
+// Raw coordinates of particles i0 + k * stride (k < LBATCH) below end, all
+// loads issued before any is used.
 template <typename T>
-__device__ __forceinline__ void load_q_batch(const T *__restrict__ pos, int64_t i0, int64_t stride, int64_t end,
-                                             const FixedPoint<T> &fp, Q3 (&q)[LBATCH], bool (&valid)[LBATCH],
-                                             bool &bad) {
+struct RawBatch {
     T x[LBATCH], y[LBATCH], z[LBATCH];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_raw(const T *__restrict__ pos, int64_t i0, int64_t stride, int64_t end,
+                                         RawBatch<T> &raw) {
 #pragma unroll
     for (int k = 0; k < LBATCH; ++k) {
         const int64_t i = i0 + k * stride;
         if (i < end) {
-            x[k] = pos[3 * i + 0];
-            y[k] = pos[3 * i + 1];
-            z[k] = pos[3 * i + 2];
+            raw.x[k] = pos[3 * i + 0];
+            raw.y[k] = pos[3 * i + 1];
+            raw.z[k] = pos[3 * i + 2];
         }
     }
+}
+
+// q of the batch; valid[k] is false for indices past the end and for
+// positions the deposit rejects (bad set).
+template <typename T>
+__device__ __forceinline__ void convert_raw(const RawBatch<T> &raw, int64_t i0, int64_t stride, int64_t end,
+                                            const FixedPoint<T> &fp, Q3 (&q)[LBATCH], bool (&valid)[LBATCH],
+                                            bool &bad) {
 #pragma unroll
     for (int k = 0; k < LBATCH; ++k) {
         valid[k] = false;
         if (i0 + k * stride < end) {
-            bool ok = fp.q(x[k], q[k].x);
-            ok = fp.q(y[k], q[k].y) && ok;
-            ok = fp.q(z[k], q[k].z) && ok;
+            bool ok = fp.q(raw.x[k], q[k].x);
+            ok = fp.q(raw.y[k], q[k].y) && ok;
+            ok = fp.q(raw.z[k], q[k].z) && ok;
             valid[k] = ok;
             bad |= !ok;
         }
     }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_q_batch(const T *__restrict__ pos, int64_t i0, int64_t stride, int64_t end,
+                                             const FixedPoint<T> &fp, Q3 (&q)[LBATCH], bool (&valid)[LBATCH],
+                                             bool &bad) {
+    RawBatch<T> raw;
+    load_raw(pos, i0, stride, end, raw);
+    convert_raw(raw, i0, stride, end, fp, q, valid, bad);
 }
 
 template <typename T>
@@ -183,19 +202,21 @@ __global__ void zero_u32_kernel(uint32_t *p, int64_t count) {
         p[i] = 0u;
 }
 
-// Scatter chunk of hardware block b, or -1 for a spare block.  Workgroups go
-// round-robin to the XCDs; this mapping gives XCD x the chunks of the
-// histogram workgroups h = x (mod 8), in order, so the level-1 counter replicas
-// h % REPLICAS it advances are its own: every replica's record runs are written
-// (and later read back in the same order) through one L2.  Launch
-// replica_grid(nchunks) blocks.
+// Scatter chunk of logical block b, or -1 for a spare block.  Workgroups go
+// round-robin to the XCDs, so a logical block b kept on XCD b % 8 (the
+// hardware block index, or one plus multiples of a grid size divisible by 8);
+// this mapping gives XCD x the chunks of the histogram workgroups h = x
+// (mod 8), in order, so the level-1 counter replicas h % REPLICAS it advances
+// are its own: every replica's record runs are written (and later read back in
+// the same order) through one L2.  The logical blocks are
+// [0, replica_grid(nchunks)).
 __device__ __forceinline__ int64_t replica_chunk(uint32_t b, uint32_t nchunks) {
     const uint32_t x = b % NUM_XCD, k = b / NUM_XCD;
     const uint64_t c = uint64_t(HIST_CHUNKS) * (x + uint64_t(NUM_XCD) * (k / HIST_CHUNKS)) + k % HIST_CHUNKS;
     return c < nchunks ? int64_t(c) : -1;
 }
 
-inline unsigned replica_grid(unsigned nchunks) {
+__host__ __device__ inline unsigned replica_grid(unsigned nchunks) {
     const unsigned g = HIST_CHUNKS * NUM_XCD;
     return (nchunks + g - 1) / g * g;
 }
@@ -264,6 +285,10 @@ __global__ void __launch_bounds__(MAX_DIGITS) l1_scan_kernel(const uint32_t *__r
     }
 }
 
+// Persistent: workgroup w takes the logical blocks w, w + G, w + 2G, ... of
+// the replica mapping (G = gridDim.x, a multiple of NUM_XCD, so they all stay
+// on one XCD).  The positions of its next chunk are loaded into registers
+// while the current chunk is staged and written out.
 template <typename T>
 __global__ void __launch_bounds__(PART_THREADS) l1_scatter_kernel(const T *__restrict__ pos, int64_t np,
                                                                   FixedPoint<T> fp, Geom g, uint32_t *cursor1,
@@ -271,54 +296,72 @@ __global__ void __launch_bounds__(PART_THREADS) l1_scatter_kernel(const T *__res
     __shared__ Q3 stage[CHUNK];
     __shared__ uint16_t sbk[CHUNK];
     __shared__ uint32_t h[MAX_DIGITS], off[MAX_DIGITS], gbase[MAX_DIGITS], tmp[MAX_DIGITS];
-    const int64_t chunk = replica_chunk(blockIdx.x, unsigned((np + CHUNK - 1) / CHUNK));
-    if (chunk < 0) return;
-    for (int b = threadIdx.x; b < MAX_DIGITS; b += blockDim.x) h[b] = 0u;
-    __syncthreads();
-    const int64_t base = chunk * CHUNK;
     static_assert(PART_PER == LBATCH, "one batch per scatter chunk");
-    Q3 q[PART_PER];
-    bool ok[PART_PER];
-    int bk[PART_PER];
-    uint32_t rank[PART_PER];
-    bool bad = false;
-    load_q_batch(pos, base + threadIdx.x, PART_THREADS, np, fp, q, ok, bad);
-#pragma unroll
-    for (int k = 0; k < PART_PER; ++k) {
-        bk[k] = -1;
-        if (ok[k]) {
-            bk[k] = bucket_of(g, q[k].x >> g.bits, q[k].y >> g.bits, q[k].z >> g.bits);
-            rank[k] = atomicAdd(&h[bk[k]], 1u);
+    const uint32_t nchunks = uint32_t((np + CHUNK - 1) / CHUNK);
+    const uint32_t logical = replica_grid(nchunks);
+    auto next_chunk = [&](uint32_t &L) -> int64_t {
+        for (; L < logical; L += gridDim.x) {
+            const int64_t c = replica_chunk(L, nchunks);
+            if (c >= 0) return c;
         }
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < g.nbuckets; b += blockDim.x) off[b] = h[b];
-    __syncthreads();
-    const uint32_t total = block_exclusive_scan(off, tmp, g.nbuckets);
-    // the histogram pass counted this chunk under replica (chunk / HIST_CHUNKS) % REPLICAS
-    uint32_t *mine = cursor1 + ((chunk / HIST_CHUNKS) % REPLICAS) * MAX_DIGITS;
-    for (int b = threadIdx.x; b < g.nbuckets; b += blockDim.x)
-        if (h[b]) gbase[b] = atomicAdd(&mine[b], h[b]);
-#pragma unroll
-    for (int k = 0; k < PART_PER; ++k)
-        if (bk[k] >= 0) {
-            const uint32_t s = off[bk[k]] + rank[k];
-            stage[s] = q[k];
-            sbk[s] = uint16_t(bk[k]);
-        }
-    __syncthreads();
-    for (uint32_t s = threadIdx.x; s < total; s += PART_THREADS) {
-        const int b = sbk[s];
-        rec1[gbase[b] + (s - off[b])] = stage[s];
-        if (maps.pos) maps.dest[chunk * CHUNK + s] = uint16_t(b);
-    }
-    if (maps.pos) {
-        save_run_table(maps, chunk, g.nbuckets, h, off, gbase, total);
+        return -1;
+    };
+    uint32_t L = blockIdx.x;
+    int64_t chunk = next_chunk(L);
+    RawBatch<T> raw;
+    if (chunk >= 0) load_raw(pos, chunk * CHUNK + threadIdx.x, PART_THREADS, np, raw);
+    while (chunk >= 0) {
+        L += gridDim.x;
+        const int64_t nxt = next_chunk(L);
+        const int64_t base = chunk * CHUNK;
+        Q3 q[PART_PER];
+        bool ok[PART_PER];
+        bool bad = false;  // reported by the histogram pass
+        convert_raw(raw, base + threadIdx.x, PART_THREADS, np, fp, q, ok, bad);
+        __syncthreads();  // the previous chunk is written out
+        for (int b = threadIdx.x; b < MAX_DIGITS; b += blockDim.x) h[b] = 0u;
+        __syncthreads();
+        int bk[PART_PER];
+        uint32_t rank[PART_PER];
 #pragma unroll
         for (int k = 0; k < PART_PER; ++k) {
-            const int64_t i = base + k * PART_THREADS + threadIdx.x;
-            if (i < np) maps.pos[i] = bk[k] >= 0 ? uint16_t(off[bk[k]] + rank[k]) : NO_POS;
+            bk[k] = -1;
+            if (ok[k]) {
+                bk[k] = bucket_of(g, q[k].x >> g.bits, q[k].y >> g.bits, q[k].z >> g.bits);
+                rank[k] = atomicAdd(&h[bk[k]], 1u);
+            }
         }
+        __syncthreads();
+        for (int b = threadIdx.x; b < g.nbuckets; b += blockDim.x) off[b] = h[b];
+        __syncthreads();
+        const uint32_t total = block_exclusive_scan(off, tmp, g.nbuckets);
+        // the histogram pass counted this chunk under replica (chunk / HIST_CHUNKS) % REPLICAS
+        uint32_t *mine = cursor1 + ((chunk / HIST_CHUNKS) % REPLICAS) * MAX_DIGITS;
+        for (int b = threadIdx.x; b < g.nbuckets; b += blockDim.x)
+            if (h[b]) gbase[b] = atomicAdd(&mine[b], h[b]);
+#pragma unroll
+        for (int k = 0; k < PART_PER; ++k)
+            if (bk[k] >= 0) {
+                const uint32_t s = off[bk[k]] + rank[k];
+                stage[s] = q[k];
+                sbk[s] = uint16_t(bk[k]);
+            }
+        __syncthreads();
+        if (nxt >= 0) load_raw(pos, nxt * CHUNK + threadIdx.x, PART_THREADS, np, raw);
+        for (uint32_t s = threadIdx.x; s < total; s += PART_THREADS) {
+            const int b = sbk[s];
+            rec1[gbase[b] + (s - off[b])] = stage[s];
+            if (maps.pos) maps.dest[chunk * CHUNK + s] = uint16_t(b);
+        }
+        if (maps.pos) {
+            save_run_table(maps, chunk, g.nbuckets, h, off, gbase, total);
+#pragma unroll
+            for (int k = 0; k < PART_PER; ++k) {
+                const int64_t i = base + k * PART_THREADS + threadIdx.x;
+                if (i < np) maps.pos[i] = bk[k] >= 0 ? uint16_t(off[bk[k]] + rank[k]) : NO_POS;
+            }
+        }
+        chunk = nxt;
     }
 }
 
@@ -910,6 +953,18 @@ OrderLayout order_layout(const Geom &g, int64_t np) {
     return L;
 }
 
+// Workgroups of the persistent level-1 scatter: as many as are resident at once
+// (a multiple of NUM_XCD), but no more than the blocks of work.
+unsigned resident_grid(const hf_ctx *ctx, const void *kernel, unsigned blocks) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, PART_THREADS, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    unsigned g = unsigned(per_cu) * unsigned(ctx->cus) / NUM_XCD * NUM_XCD;
+    if (g < NUM_XCD) g = NUM_XCD;
+    const unsigned need = (blocks + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
+    return g < need ? g : need;
+}
+
 template <typename T>
 hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, unsigned long long *rho,
                     char *ws, const ParticleOrder *order) {
@@ -950,7 +1005,9 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
         HF_LAUNCH(ctx, K_DEP_PREP, l1_scan_kernel, dim3(1), dim3(MAX_DIGITS), 0, st, count1, g.nbuckets, start1,
                   cursor1, chunk_first, hchunk_first, nrec);
         if (part_blocks)
-            HF_LAUNCH(ctx, K_DEP_L1_SCATTER, l1_scatter_kernel<T>, dim3(replica_grid(part_blocks)),
+            HF_LAUNCH(ctx, K_DEP_L1_SCATTER, l1_scatter_kernel<T>,
+                      dim3(resident_grid(ctx, reinterpret_cast<const void *>(&l1_scatter_kernel<T>),
+                                         replica_grid(part_blocks))),
                       dim3(PART_THREADS), 0, st, pos, np, fp, g, cursor1, rec1, m1);
         const L2Input<T, true> hin{pos, np, fp, rec1, start1, hchunk_first, g.nbuckets, HCHUNK};
         const L2Input<T, true> sin{pos, np, fp, rec1, start1, chunk_first, g.nbuckets, CHUNK};

@@ -13,8 +13,11 @@
 //   y_pass  : inverse along y.
 //   x_inv   : two half-spectrum rows -> one complex row, inverse FFT, the
 //             real and imaginary parts are the two output rows.
-// Every 1D transform is a Stockham autosort FFT over radices 8/4/3/2 held in
-// LDS, element n of pencil p at buf[n * pitch + p].
+// Every 1D transform is a Stockham autosort FFT over radices 16/8/4/3/2 on a
+// tile of pencils in LDS (element x of pencil p at row x, column p); the
+// y and z passes read their first stage straight from HBM into registers and
+// write their last stage straight back, and the z pass turns from forward to
+// inverse in registers.
 #include <cmath>
 
 #include "hf_internal.h"
@@ -46,18 +49,26 @@ FftPlan make_plan(int n) {
         p.radix[p.nst++] = 3;
         m /= 3;
     }
-    while (m % 8 == 0) {
-        p.radix[p.nst++] = 8;
-        m /= 8;
+    for (int r : {16, 8, 4, 2})
+        while (m % r == 0) {
+            p.radix[p.nst++] = r;
+            m /= r;
+        }
+    int ns = 1;
+    for (int s = 0; s < p.nst; ++s) {
+        p.ns[s] = FastDiv(uint32_t(ns));
+        ns *= p.radix[s];
     }
-    while (m % 4 == 0) {
-        p.radix[p.nst++] = 4;
-        m /= 4;
-    }
-    while (m % 2 == 0) {
-        p.radix[p.nst++] = 2;
-        m /= 2;
-    }
+    return p;
+}
+
+// The same factors with the last one moved to the front: the inverse transform
+// that follows a forward one in registers starts with the radix the forward
+// one ended with.
+FftPlan rotate_plan(const FftPlan &f) {
+    FftPlan p = f;
+    p.radix[0] = f.radix[f.nst - 1];
+    for (int s = 1; s < f.nst; ++s) p.radix[s] = f.radix[s - 1];
     int ns = 1;
     for (int s = 0; s < p.nst; ++s) {
         p.ns[s] = FastDiv(uint32_t(ns));
@@ -119,6 +130,35 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
         v[6] = csub(e2, o2);
         v[3] = cadd(e3, o3);
         v[7] = csub(e3, o3);
+    } else if constexpr (R == 16) {
+        // 16 = 4 x 4: element 4 a + b; length-4 transforms over a, the twiddles
+        // W16^(b c), length-4 transforms over b; output c + 4 d sits at 4 c + d
+        dft4<INV>(v[0], v[4], v[8], v[12]);
+        dft4<INV>(v[1], v[5], v[9], v[13]);
+        dft4<INV>(v[2], v[6], v[10], v[14]);
+        dft4<INV>(v[3], v[7], v[11], v[15]);
+        const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f, h = 0.70710678118654752440f;
+        const float sg = INV ? 1.f : -1.f;  // exp(-+ 2 pi i m / 16) = cos - + i sin
+        v[5] = cmul(v[5], make_float2(c1, sg * s1));     // m = 1
+        v[9] = cmul(v[9], make_float2(h, sg * h));       // m = 2
+        v[13] = cmul(v[13], make_float2(s1, sg * c1));   // m = 3
+        v[6] = cmul(v[6], make_float2(h, sg * h));       // m = 2
+        v[10] = mul_mi<INV>(v[10]);                      // m = 4
+        v[14] = cmul(v[14], make_float2(-h, sg * h));    // m = 6
+        v[7] = cmul(v[7], make_float2(s1, sg * c1));     // m = 3
+        v[11] = cmul(v[11], make_float2(-h, sg * h));    // m = 6
+        v[15] = cmul(v[15], make_float2(-c1, -sg * s1)); // m = 9
+        dft4<INV>(v[0], v[1], v[2], v[3]);
+        dft4<INV>(v[4], v[5], v[6], v[7]);
+        dft4<INV>(v[8], v[9], v[10], v[11]);
+        dft4<INV>(v[12], v[13], v[14], v[15]);
+        float2 t[16];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int d = 0; d < 4; ++d) t[c + 4 * d] = v[4 * c + d];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = t[e];
     } else if constexpr (R == 3) {
         const float c = -0.5f;
         const float s = INV ? 0.86602540378443864676f : -0.86602540378443864676f;
@@ -132,11 +172,27 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
     }
 }
 
-// One Stockham stage of radix R on P pencils (P = 1 << lp) of length n in LDS.
-// tw[m] = exp(-2 pi i m / n).  Ns = product of the radices already applied.
-template <int R, bool INV>
-__device__ __forceinline__ void fft_stage(float2 *buf, int pitch, int lp, int n, int Ns, const FastDiv &dns,
-                                          const float2 *tw, int tid, int nthreads) {
+// Stages whose inputs or outputs need not be in LDS.  Butterfly b = tid + i *
+// nthreads of a radix-R stage belongs to pencil p = b & (P - 1) and takes the
+// elements j + r n/R (j = b >> lp, r < R) through load(p, index); after the
+// twiddles (k = j mod Ns) and the length-R transform, element (j - k) R + k +
+// r Ns goes to store(p, index, value).  The first stage (Ns = 1) can read
+// straight from HBM and the last one (k = j) write straight back, so a
+// length-n transform touches LDS once per stage boundary.  In LDS, element x of
+// pencil p sits at buf[x P + p].
+
+// The thread index passes through an empty asm statement at the start of each
+// stage, so the stage's index arithmetic is computed there and not hoisted to
+// the kernel entry for every radix the kernel could run (which spills).
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+template <int R, bool INV, class Load, class Store>
+__device__ __forceinline__ void stage_rs(int n, int lp, int Ns, const FastDiv &dns, const float2 *tw, int tid_,
+                                         int nthreads, bool sync, Load &load, Store &store) {
+    const int tid = opaque(tid_);
     constexpr int MAXB = (MAX_ELEMS + R - 1) / R;
     const int nbf = n / R;
     const int total = nbf << lp;
@@ -147,12 +203,17 @@ __device__ __forceinline__ void fft_stage(float2 *buf, int pitch, int lp, int n,
     for (int i = 0; i < MAXB; ++i) {
         const int b = tid + i * nthreads;
         if (b < total) {
-            const int p = b & pmask;
-            const int j = b >> lp;
-            const int k = int(dns.mod(uint32_t(j)));
+            const int p = b & pmask, j = b >> lp;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = buf[(j + r * nbf) * pitch + p];
-            if (Ns > 1) {
+            for (int r = 0; r < R; ++r) v[i][r] = load(p, j + r * nbf);
+        }
+    }
+    if (Ns > 1) {
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i) {
+            const int b = tid + i * nthreads;
+            if (b < total) {
+                const int k = int(dns.mod(uint32_t(b >> lp)));
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
                     float2 w = tw[r * k * twstride];
@@ -162,38 +223,114 @@ __device__ __forceinline__ void fft_stage(float2 *buf, int pitch, int lp, int n,
             }
         }
     }
-    __syncthreads();
+    if (sync) __syncthreads();
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
         const int b = tid + i * nthreads;
         if (b < total) {
-            const int p = b & pmask;
-            const int j = b >> lp;
+            const int p = b & pmask, j = b >> lp;
             const int k = int(dns.mod(uint32_t(j)));
             dft<R, INV>(v[i]);
             const int base = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[(base + r * Ns) * pitch + p] = v[i][r];
+            for (int r = 0; r < R; ++r) store(p, base + r * Ns, v[i][r]);
         }
     }
-    __syncthreads();
 }
 
-template <bool INV>
-__device__ void fft_lds(float2 *buf, int pitch, int lp, const FftPlan &pl, const float2 *tw, int tid,
-                        int nthreads) {
+template <bool INV, class Load, class Store>
+__device__ __forceinline__ void stage_any(int R, int n, int lp, int Ns, const FastDiv &dns, const float2 *tw, int tid,
+                                          int nthreads, bool sync, Load &load, Store &store) {
+    switch (R) {
+        case 16: stage_rs<16, INV>(n, lp, Ns, dns, tw, tid, nthreads, sync, load, store); break;
+        case 8: stage_rs<8, INV>(n, lp, Ns, dns, tw, tid, nthreads, sync, load, store); break;
+        case 4: stage_rs<4, INV>(n, lp, Ns, dns, tw, tid, nthreads, sync, load, store); break;
+        case 2: stage_rs<2, INV>(n, lp, Ns, dns, tw, tid, nthreads, sync, load, store); break;
+        default: stage_rs<3, INV>(n, lp, Ns, dns, tw, tid, nthreads, sync, load, store); break;
+    }
+}
+
+// Stages [from, to) of plan pl on P = 1 << lp pencils held in buf (the LDS
+// rows above): stage `from` reads through load, stage to - 1 writes through
+// store, the others go from LDS to LDS, with a barrier after every stage but
+// the last.  A stage that reads and writes LDS (in place) also waits between
+// its reads and its writes; LOAD_LDS / STORE_LDS say whether load and store
+// are LDS accesses.  Ns of stage s is the product of the radices before it.
+template <bool INV, bool LOAD_LDS, bool STORE_LDS, class Load, class Store>
+__device__ __forceinline__ void fft_pencils(float2 *buf, int lp, const FftPlan &pl, int from, int to, const float2 *tw, int tid,
+                            int nthreads, Load &load, Store &store) {
+    auto lload = [buf, lp](int p, int x) { return buf[(x << lp) + p]; };
+    auto lstore = [buf, lp](int p, int x, float2 v) { buf[(x << lp) + p] = v; };
     int Ns = 1;
-    for (int s = 0; s < pl.nst; ++s) {
-        const int R = pl.radix[s];
-        if (R == 8)
-            fft_stage<8, INV>(buf, pitch, lp, pl.n, Ns, pl.ns[s], tw, tid, nthreads);
-        else if (R == 4)
-            fft_stage<4, INV>(buf, pitch, lp, pl.n, Ns, pl.ns[s], tw, tid, nthreads);
-        else if (R == 2)
-            fft_stage<2, INV>(buf, pitch, lp, pl.n, Ns, pl.ns[s], tw, tid, nthreads);
+    for (int s = 0; s < from; ++s) Ns *= pl.radix[s];
+    for (int s = from; s < to; ++s) {
+        const bool first = s == from, last = s == to - 1;
+        if (first && last)
+            stage_any<INV>(pl.radix[s], pl.n, lp, Ns, pl.ns[s], tw, tid, nthreads, LOAD_LDS && STORE_LDS, load, store);
+        else if (first)
+            stage_any<INV>(pl.radix[s], pl.n, lp, Ns, pl.ns[s], tw, tid, nthreads, LOAD_LDS, load, lstore);
+        else if (last)
+            stage_any<INV>(pl.radix[s], pl.n, lp, Ns, pl.ns[s], tw, tid, nthreads, STORE_LDS, lload, store);
         else
-            fft_stage<3, INV>(buf, pitch, lp, pl.n, Ns, pl.ns[s], tw, tid, nthreads);
-        Ns *= R;
+            stage_any<INV>(pl.radix[s], pl.n, lp, Ns, pl.ns[s], tw, tid, nthreads, true, lload, lstore);
+        if (!last) __syncthreads();
+        Ns *= pl.radix[s];
+    }
+}
+
+// The seam of the z pass: the last forward stage (Ns = n/R, so k = j and its
+// outputs are elements j + r n/R), the multiplier, and the first inverse stage
+// (Ns = 1, inputs j + r n/R, outputs j R + r), in registers.
+template <int R, class Load, class Store, class Mul>
+__device__ __forceinline__ void stage_seam(int n, int lp, const float2 *tw, int tid_, int nthreads, bool sync,
+                                           Load &load, Store &store, Mul &mul) {
+    const int tid = opaque(tid_);
+    constexpr int MAXB = (MAX_ELEMS + R - 1) / R;
+    const int nbf = n / R;
+    const int total = nbf << lp;
+    const int pmask = (1 << lp) - 1;
+    float2 v[MAXB][R];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = tid + i * nthreads;
+        if (b < total) {
+            const int p = b & pmask, j = b >> lp;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = load(p, j + r * nbf);
+            if (nbf > 1) {  // twstride = 1, k = j
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[r * j]);
+            }
+        }
+    }
+    if (sync) __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = tid + i * nthreads;
+        if (b < total) {
+            const int p = b & pmask, j = b >> lp;
+            dft<R, false>(v[i]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float m = mul(p, j + r * nbf);
+                v[i][r] = make_float2(v[i][r].x * m, v[i][r].y * m);
+            }
+            dft<R, true>(v[i]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) store(p, j * R + r, v[i][r]);
+        }
+    }
+}
+
+template <class Load, class Store, class Mul>
+__device__ __forceinline__ void seam_any(int R, int n, int lp, const float2 *tw, int tid, int nthreads, bool sync,
+                                         Load &load, Store &store, Mul &mul) {
+    switch (R) {
+        case 16: stage_seam<16>(n, lp, tw, tid, nthreads, sync, load, store, mul); break;
+        case 8: stage_seam<8>(n, lp, tw, tid, nthreads, sync, load, store, mul); break;
+        case 4: stage_seam<4>(n, lp, tw, tid, nthreads, sync, load, store, mul); break;
+        case 2: stage_seam<2>(n, lp, tw, tid, nthreads, sync, load, store, mul); break;
+        default: stage_seam<3>(n, lp, tw, tid, nthreads, sync, load, store, mul); break;
     }
 }
 
@@ -349,9 +486,9 @@ __global__ void fft_x_fwd_kernel(CwtJobs J, CwtLayout L, FftPlan pl, uint32_t *s
     Mass128 *__restrict__ mass = jv.mass;
     const int lp = L.lp_x;
     const int n = pl.n, H = n / 2 + 1;
-    const int xp = 1 << lp, pitch = xp + 1;
+    const int xp = 1 << lp;
     float2 *tw = smem;
-    float2 *buf = smem + n;
+    float2 *buf = smem + n;  // element x of pair p at buf[(x << lp) + p]
     const int tid = threadIdx.x, nt = blockDim.x;
     const int64_t pairs = int64_t(n) * n / 2;
     const int64_t q0 = int64_t(blockIdx.x) * xp;
@@ -383,7 +520,7 @@ __global__ void fft_x_fwd_kernel(CwtJobs J, CwtLayout L, FftPlan pl, uint32_t *s
                 neg |= (a < 0) | (b < 0);
                 add128(lo, hi, static_cast<unsigned long long>(a));
                 add128(lo, hi, static_cast<unsigned long long>(b));
-                buf[x * pitch + p] = make_float2(float(a), float(b));
+                buf[(x << lp) + p] = make_float2(float(a), float(b));
             }
         }
     }
@@ -414,14 +551,17 @@ __global__ void fft_x_fwd_kernel(CwtJobs J, CwtLayout L, FftPlan pl, uint32_t *s
         mass[blockIdx.x].lo = L;
         mass[blockIdx.x].hi = Hh;
     }
-    fft_lds<false>(buf, pitch, lp, pl, tw, tid, nt);
+    auto lload = [buf, lp](int p, int x) { return buf[(x << lp) + p]; };
+    auto lstore = [buf, lp](int p, int x, float2 v) { buf[(x << lp) + p] = v; };
+    fft_pencils<false, true, true>(buf, lp, pl, 0, pl.nst, tw, tid, nt, lload, lstore);
+    __syncthreads();
     // split Z = A + iB into the two real rows' spectra
     for (int e = tid; e < xp * H; e += nt) {
         const int p = int(pl.dh.div(uint32_t(e))), k = e - p * H;
         const int64_t q = q0 + p;
         if (q >= pairs) continue;
-        const float2 zk = buf[k * pitch + p];
-        const float2 zm = buf[((n - k) % n) * pitch + p];
+        const float2 zk = buf[(k << lp) + p];
+        const float2 zm = buf[(((n - k) % n) << lp) + p];
         const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
         const float2 B = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
         spec[(2 * q) * H + k] = A;
@@ -438,7 +578,7 @@ __global__ void fft_x_inv_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
     const float2 *__restrict__ tw_g = jv.tw;
     const int lp = L.lp_xi;
     const int n = pl.n, H = n / 2 + 1;
-    const int xp = 1 << lp, pitch = xp + 1;
+    const int xp = 1 << lp;
     float2 *tw = smem;
     float2 *buf = smem + n;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -468,19 +608,22 @@ __global__ void fft_x_inv_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
         const float2 A = va[i], B = vb[i];
         if (k == 0 || 2 * k == n) {
             // DC and Nyquist of a real row are real
-            buf[k * pitch + p] = make_float2(A.x, B.x);
+            buf[(k << lp) + p] = make_float2(A.x, B.x);
         } else {
-            buf[k * pitch + p] = make_float2(A.x - B.y, A.y + B.x);
-            buf[(n - k) * pitch + p] = make_float2(A.x + B.y, B.x - A.y);
+            buf[(k << lp) + p] = make_float2(A.x - B.y, A.y + B.x);
+            buf[((n - k) << lp) + p] = make_float2(A.x + B.y, B.x - A.y);
         }
     }
     __syncthreads();
-    fft_lds<true>(buf, pitch, lp, pl, tw, tid, nt);
+    auto lload = [buf, lp](int p, int x) { return buf[(x << lp) + p]; };
+    auto lstore = [buf, lp](int p, int x, float2 v) { buf[(x << lp) + p] = v; };
+    fft_pencils<true, true, true>(buf, lp, pl, 0, pl.nst, tw, tid, nt, lload, lstore);
+    __syncthreads();
     for (int e = tid; e < xp * n; e += nt) {
         const int p = int(pl.dn.div(uint32_t(e))), x = e - p * n;
         const int64_t q = q0 + p;
         if (q >= pairs) continue;
-        const float2 v = buf[x * pitch + p];
+        const float2 v = buf[(x << lp) + p];
         out[(2 * q) * n + x] = v.x;
         out[(2 * q + 1) * n + x] = v.y;
     }
@@ -566,47 +709,31 @@ __global__ void fft_y_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
     yz_tile(tile, zrow, job);
     const JobView jv = job_view(J, L, job);
     float2 *__restrict__ spec = jv.spec;
-    const float2 *__restrict__ tw_g = jv.tw;
     const int n = pl.n, H = n / 2 + 1;
     float2 *tw = smem;
     float2 *buf = smem + n;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int kx0 = tile * YZ_TILE;
     const int valid = min(YZ_TILE, H - kx0);
-    const size_t zbase = size_t(zrow) * n * H;
-    load_twiddles(tw, tw_g, n);
-    {
-        float2 v[MAX_ELEMS];
-#pragma unroll
-        for (int i = 0; i < MAX_ELEMS; ++i) {
-            const int e = tid + i * nt;
-            const int p = e & (YZ_TILE - 1), y = e >> YZ_LOG;
-            v[i] = (e < n * YZ_TILE && p < valid) ? spec[zbase + size_t(y) * H + kx0 + p] : make_float2(0.f, 0.f);
-        }
-#pragma unroll
-        for (int i = 0; i < MAX_ELEMS; ++i) {
-            const int e = tid + i * nt;
-            if (e < n * YZ_TILE) buf[e] = v[i];
-        }
-    }
-    __syncthreads();
-    fft_lds<INV>(buf, YZ_TILE, YZ_LOG, pl, tw, tid, nt);
-    for (int e = tid; e < n * YZ_TILE; e += nt) {
-        const int p = e & (YZ_TILE - 1), y = e >> YZ_LOG;
-        if (p < valid) spec[zbase + size_t(y) * H + kx0 + p] = buf[e];
-    }
+    float2 *col = spec + size_t(zrow) * n * H + kx0;  // element y of pencil p at col[y H + p]
+    load_twiddles(tw, jv.tw, n);                      // first read after the first stage's barrier
+    auto gload = [=](int p, int y) { return p < valid ? col[size_t(y) * H + p] : make_float2(0.f, 0.f); };
+    auto gstore = [=](int p, int y, float2 v) {
+        if (p < valid) col[size_t(y) * H + p] = v;
+    };
+    fft_pencils<INV, false, false>(buf, YZ_LOG, pl, 0, pl.nst, tw, tid, nt, gload, gstore);
 }
 
-__global__ void fft_z_mul_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
+// Forward z transform, multiplier, inverse z transform; pi is pl with its
+// last radix moved to the front.
+__global__ void fft_z_mul_kernel(CwtJobs J, CwtLayout L, FftPlan pl, FftPlan pi) {
     extern __shared__ float2 smem[];
     int tile, yrow, job;
     yz_tile(tile, yrow, job);
     const JobView jv = job_view(J, L, job);
     float2 *__restrict__ spec = jv.spec;
-    const float2 *__restrict__ tw_g = jv.tw;
     const float *__restrict__ tab_b = jv.btab;
     const float *__restrict__ tab_p = jv.ptab;
-    const double *__restrict__ scalars = jv.scalars;
     const int n = pl.n, H = n / 2 + 1;
     float2 *tw = smem;
     float2 *buf = smem + n;
@@ -615,41 +742,31 @@ __global__ void fft_z_mul_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
     const int ky = yrow;
     const int valid = min(YZ_TILE, H - kx0);
     const size_t zstride = size_t(n) * H;
-    const size_t base = size_t(ky) * H + kx0;
-    load_twiddles(tw, tw_g, n);
-    {
-        float2 v[MAX_ELEMS];
-#pragma unroll
-        for (int i = 0; i < MAX_ELEMS; ++i) {
-            const int e = tid + i * nt;
-            const int p = e & (YZ_TILE - 1), z = e >> YZ_LOG;
-            v[i] = (e < n * YZ_TILE && p < valid) ? spec[size_t(z) * zstride + base + p] : make_float2(0.f, 0.f);
-        }
-#pragma unroll
-        for (int i = 0; i < MAX_ELEMS; ++i) {
-            const int e = tid + i * nt;
-            if (e < n * YZ_TILE) buf[e] = v[i];
-        }
-    }
-    __syncthreads();
-    fft_lds<false>(buf, YZ_TILE, YZ_LOG, pl, tw, tid, nt);
-    const float scale = float(scalars[0]);
+    float2 *col = spec + size_t(ky) * H + kx0;  // element z of pencil p at col[z zstride + p]
+    load_twiddles(tw, jv.tw, n);
+    const float scale = float(jv.scalars[0]);
     const float by = tab_b[ky], py = tab_p[ky];
-    for (int e = tid; e < n * YZ_TILE; e += nt) {
-        const int p = e & (YZ_TILE - 1), z = e >> YZ_LOG;
-        const int kx = min(kx0 + p, H - 1);
-        const float bx = tab_b[kx], px = tab_p[kx];
-        const float bz = tab_b[z], pz = tab_p[z];
-        const float m = ((px * by + bx * py) * bz + bx * by * pz) * scale;
-        const float2 v = buf[e];
-        buf[e] = make_float2(v.x * m, v.y * m);
+    // the thread's pencil is the same in every stage (nthreads is a multiple of P)
+    const int kx = min(kx0 + (tid & (YZ_TILE - 1)), H - 1);
+    const float bx = tab_b[kx], px = tab_p[kx];
+    const float cxy = (px * by + bx * py) * scale, bxy = bx * by * scale;
+    auto gload = [=](int p, int z) { return p < valid ? col[size_t(z) * zstride + p] : make_float2(0.f, 0.f); };
+    auto gstore = [=](int p, int z, float2 v) {
+        if (p < valid) col[size_t(z) * zstride + p] = v;
+    };
+    auto mul = [=](int, int kz) { return cxy * tab_b[kz] + bxy * tab_p[kz]; };
+    auto lload = [buf](int p, int x) { return buf[(x << YZ_LOG) + p]; };
+    auto lstore = [buf](int p, int x, float2 v) { buf[(x << YZ_LOG) + p] = v; };
+    const int last = pl.nst - 1;
+    if (last == 0) {
+        seam_any(pl.radix[0], n, YZ_LOG, tw, tid, nt, false, gload, gstore, mul);
+        return;
     }
+    fft_pencils<false, false, true>(buf, YZ_LOG, pl, 0, last, tw, tid, nt, gload, lstore);
     __syncthreads();
-    fft_lds<true>(buf, YZ_TILE, YZ_LOG, pl, tw, tid, nt);
-    for (int e = tid; e < n * YZ_TILE; e += nt) {
-        const int p = e & (YZ_TILE - 1), z = e >> YZ_LOG;
-        if (p < valid) spec[size_t(z) * zstride + base + p] = buf[e];
-    }
+    seam_any(pl.radix[last], n, YZ_LOG, tw, tid, nt, true, lload, lstore, mul);
+    __syncthreads();
+    fft_pencils<true, true, false>(buf, YZ_LOG, pi, 1, pi.nst, tw, tid, nt, lload, gstore);
 }
 
 // ---------------------------------------------------------------------------
@@ -711,14 +828,15 @@ hf_status run_cwt(hf_ctx *ctx, int n, const CwtJobs &J) {
     HF_LAUNCH(ctx, K_TABLES_2, tables_stage2, dim3(tg, jobs), dim3(tb), 0, st, J, L, n);
 
     const FftPlan pl = make_plan(n);
+    const FftPlan pi = rotate_plan(pl);
     const int H = n / 2 + 1;
     const int tiles = (H + YZ_TILE - 1) / YZ_TILE;
     const int yz_threads = threads_for(n * YZ_TILE);
     const size_t yz_shm = sizeof(float2) * (size_t(n) + size_t(n) * YZ_TILE);
     const int x_threads = threads_for((1 << L.lp_x) * n);
-    const size_t x_shm = sizeof(float2) * (size_t(n) + size_t(n) * ((1 << L.lp_x) + 1));
+    const size_t x_shm = sizeof(float2) * (size_t(n) + size_t(n) * (1 << L.lp_x));
     const int xi_threads = threads_for((1 << L.lp_xi) * n);
-    const size_t xi_shm = sizeof(float2) * (size_t(n) + size_t(n) * ((1 << L.lp_xi) + 1));
+    const size_t xi_shm = sizeof(float2) * (size_t(n) + size_t(n) * (1 << L.lp_xi));
     // workgroups that need more than the default 64 KiB of dynamic LDS say so
     auto allow = [](const void *f, size_t bytes) {
         return bytes <= 65536 ||
@@ -734,7 +852,7 @@ hf_status run_cwt(hf_ctx *ctx, int n, const CwtJobs &J) {
               ctx->d_status);
     HF_LAUNCH(ctx, K_MASS, mass_kernel, dim3(jobs), dim3(1024), 0, st, J, L, n, ctx->d_status);
     HF_LAUNCH(ctx, K_Y_FWD, fft_y_kernel<false>, dim3(tiles, n, jobs), dim3(yz_threads), yz_shm, st, J, L, pl);
-    HF_LAUNCH(ctx, K_Z_MUL, fft_z_mul_kernel, dim3(tiles, n, jobs), dim3(yz_threads), yz_shm, st, J, L, pl);
+    HF_LAUNCH(ctx, K_Z_MUL, fft_z_mul_kernel, dim3(tiles, n, jobs), dim3(yz_threads), yz_shm, st, J, L, pl, pi);
     HF_LAUNCH(ctx, K_Y_INV, fft_y_kernel<true>, dim3(tiles, n, jobs), dim3(yz_threads), yz_shm, st, J, L, pl);
     HF_LAUNCH(ctx, K_X_INV, fft_x_inv_kernel, dim3(unsigned(L.xblocks_i), jobs), dim3(xi_threads), xi_shm, st, J, L,
               pl);

@@ -32,6 +32,7 @@ struct ProfRecord {
 
 struct hf_ctx {
     int device;
+    int cus = 256;  // compute units of the device
     hipStream_t stream;
     uint32_t *d_status;  // device status block: [0] error bit mask
     uint32_t *h_status;  // pinned host mirror
