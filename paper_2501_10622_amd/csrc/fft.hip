@@ -181,14 +181,9 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
 // length-n transform touches LDS once per stage boundary.  In LDS, element x of
 // pencil p sits at buf[x P + p].
 
-// The thread index passes through an empty asm statement at the start of each
-// stage, so the stage's index arithmetic is computed there and not hoisted to
-// the kernel entry for every radix the kernel could run (which spills).
-__device__ __forceinline__ int opaque(int x) {
-    asm volatile("" : "+v"(x));
-    return x;
-}
-
+// Each stage passes the thread index through opaque(), so the stage's index
+// arithmetic is computed there and not hoisted to the kernel entry for every
+// radix the kernel could run (which spills).
 template <int R, bool INV, class Load, class Store>
 __device__ __forceinline__ void stage_rs(int n, int lp, int Ns, const FastDiv &dns, const float2 *tw, int tid_,
                                          int nthreads, bool sync, Load &load, Store &store) {

@@ -174,6 +174,16 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
 }
 
 // ---------------------------------------------------------------------------
+// A value the compiler cannot see through: code that uses opaque(threadIdx.x)
+// computes its index arithmetic where it stands instead of hoisting it out of
+// loops and branches, where it would stay live (and spill) for the whole kernel.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// ---------------------------------------------------------------------------
 // Division of 32-bit unsigned integers by an invariant divisor d >= 1 with a
 // multiply-high and shifts (Granlund & Montgomery, "Division by invariant
 // integers using multiplication", 1994): with l = ceil(log2 d) and
