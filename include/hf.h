@@ -74,7 +74,7 @@ typedef struct {
  * selected stage, so one buffer can serve them in turn).  HF_STAGE_LABEL
  * together with HF_STAGE_DEPOSIT adds, where the binned deposit applies (see
  * hf_find_halos), a region that carries the deposit's particle order to the
- * label step: about 16 bytes per particle plus 8 per particle of label scratch. */
+ * label step: about 13 bytes per particle plus 8 per particle of label scratch. */
 enum { HF_STAGE_DEPOSIT = 1, HF_STAGE_CWT = 2, HF_STAGE_MAXIMA = 4, HF_STAGE_SEGMENT = 8, HF_STAGE_LABEL = 16,
        HF_STAGE_ALL = 31 };
 

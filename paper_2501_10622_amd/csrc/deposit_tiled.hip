@@ -51,12 +51,12 @@ constexpr int OFF_STRIDE = MAX_DIGITS + 2;  // per-chunk row of staging offsets 
 
 // Where one level's scatter chunks put their elements, kept for step 6: the
 // position of every element in its chunk's destination-sorted staging order
-// (element order; NO_POS if rejected), the destination of every staging
-// position, and per chunk the first slot of each destination's run and the
-// staging offset of each destination (offset[ndest] = elements staged).
+// (element order; NO_POS if rejected), and per chunk the first slot of each
+// destination's run and the staging offset of each destination
+// (offset[ndest] = elements staged).  The destination of a staging position is
+// not stored: the runs are in destination order, so the offsets give it.
 struct RunMaps {
     uint16_t *pos;     // [elements]
-    uint16_t *dest;    // [chunks * CHUNK]
     uint32_t *base;    // [chunks * MAX_DIGITS]
     uint16_t *offset;  // [chunks * OFF_STRIDE]
 };
@@ -351,7 +351,6 @@ __global__ void __launch_bounds__(PART_THREADS) l1_scatter_kernel(const T *__res
         for (uint32_t s = threadIdx.x; s < total; s += PART_THREADS) {
             const int b = sbk[s];
             rec1[gbase[b] + (s - off[b])] = stage[s];
-            if (maps.pos) maps.dest[chunk * CHUNK + s] = uint16_t(b);
         }
         if (maps.pos) {
             save_run_table(maps, chunk, g.nbuckets, h, off, gbase, total);
@@ -503,7 +502,6 @@ __global__ void __launch_bounds__(PART_THREADS) l2_scatter_kernel(L2Input<T, FRO
     for (uint32_t s = threadIdx.x; s < total; s += PART_THREADS) {
         const int d = sdig[s];
         rec2[gbase[d] + (s - off[d])] = stage[s];
-        if (keep) maps.dest[int64_t(blockIdx.x) * CHUNK + s] = uint16_t(d);
     }
     if (keep) {
         save_run_table(maps, blockIdx.x, g.digits, h, off, gbase, total);
@@ -760,6 +758,46 @@ __global__ void __launch_bounds__(ACC_THREADS) tile_label_kernel(const uint64_t 
     }
 }
 
+// Destination of the staging positions k * PART_THREADS + threadIdx.x of a
+// chunk, from its run offsets: each nonempty run's first position is marked
+// with its destination, and an inclusive max-scan over the positions carries
+// every mark over its run (runs are in destination order).  mark holds CHUNK
+// words and is free again on return.
+__device__ void slot_dest(const uint16_t *off_s, int ndest, uint32_t *mark, uint16_t (&dd)[PART_PER]) {
+    __shared__ uint32_t wmax[PART_THREADS / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int j = 0; j < PART_PER; ++j) mark[t * PART_PER + j] = 0u;
+    __syncthreads();
+    for (int d = t; d < ndest; d += PART_THREADS)
+        if (off_s[d + 1] > off_s[d]) mark[off_s[d]] = uint32_t(d);
+    __syncthreads();
+    // this thread's PART_PER consecutive positions, then the threads before it
+    uint32_t v[PART_PER], run = 0u;
+#pragma unroll
+    for (int j = 0; j < PART_PER; ++j) {
+        run = max(run, mark[t * PART_PER + j]);
+        v[j] = run;
+    }
+    uint32_t incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl = max(incl, y);
+    }
+    if (lane == 63) wmax[wave] = incl;
+    const uint32_t prev = __shfl_up(incl, 1, 64);
+    __syncthreads();
+    uint32_t before = lane > 0 ? prev : 0u;
+    for (int w = 0; w < wave; ++w) before = max(before, wmax[w]);
+#pragma unroll
+    for (int j = 0; j < PART_PER; ++j) mark[t * PART_PER + j] = max(v[j], before);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PART_PER; ++k) dd[k] = uint16_t(mark[k * PART_THREADS + t]);
+    __syncthreads();
+}
+
 // One scatter chunk back to element order: dst[e] = src[slot of element e]
 // for the chunk's elements [e0, e1).  The chunk's runs are read into LDS in
 // staging order, consecutive lanes on consecutive slots of a run, so a
@@ -770,6 +808,7 @@ __device__ void chunk_gather(const RunMaps &m, int64_t chunk, int ndest, int64_t
     __shared__ uint32_t base_s[MAX_DIGITS];
     __shared__ uint16_t off_s[OFF_STRIDE];
     __shared__ int32_t val[CHUNK];
+    static_assert(CHUNK == PART_THREADS * PART_PER, "one staging position per thread and slot");
     for (int d = threadIdx.x; d < ndest; d += blockDim.x) base_s[d] = m.base[chunk * MAX_DIGITS + d];
     for (int d = threadIdx.x; d <= ndest; d += blockDim.x) off_s[d] = m.offset[chunk * OFF_STRIDE + d];
     uint16_t p[PART_PER], dd[PART_PER];
@@ -777,9 +816,9 @@ __device__ void chunk_gather(const RunMaps &m, int64_t chunk, int ndest, int64_t
     for (int k = 0; k < PART_PER; ++k) {
         const int64_t e = e0 + k * PART_THREADS + threadIdx.x;
         p[k] = e < e1 ? m.pos[e] : NO_POS;
-        dd[k] = m.dest[chunk * CHUNK + k * PART_THREADS + threadIdx.x];  // used below only if staged
     }
     __syncthreads();
+    slot_dest(off_s, ndest, reinterpret_cast<uint32_t *>(val), dd);
     const uint32_t total = off_s[ndest];
     int32_t v[PART_PER];
 #pragma unroll
@@ -922,10 +961,11 @@ DepLayout dep_layout(const Geom &g, int64_t np, bool keep_order) {
 }
 
 // ParticleOrder region: rec2 [np] | start2 [ntiles + 1] | nrec | start1 [513] |
-// chunk_first [513] | the run maps of both levels (about 9 bytes per particle).
+// chunk_first [513] | the run maps of both levels (about 12.5 bytes per
+// particle in all).
 struct OrderLayout {
     size_t rec2, start2, nrec, start1, chunk_first, total;
-    size_t pos[2], dest[2], base[2], offset[2];
+    size_t pos[2], base[2], offset[2];
 };
 
 OrderLayout order_layout(const Geom &g, int64_t np) {
@@ -945,7 +985,6 @@ OrderLayout order_layout(const Geom &g, int64_t np) {
     const size_t chunks[2] = {chunks1, chunks1 + size_t(g.nbuckets)};  // level 2: one partial chunk per bucket
     for (int l = 0; l < 2; ++l) {
         L.pos[l] = take(sizeof(uint16_t) * size_t(np));
-        L.dest[l] = take(sizeof(uint16_t) * chunks[l] * CHUNK);
         L.base[l] = take(sizeof(uint32_t) * chunks[l] * MAX_DIGITS);
         L.offset[l] = take(sizeof(uint16_t) * chunks[l] * OFF_STRIDE);
     }
@@ -1085,8 +1124,8 @@ hf::ParticleOrder hf::particle_order_at(const hf_box &box, void *base, int64_t n
     o.chunk_first = reinterpret_cast<uint32_t *>(p + L.chunk_first);
     static_assert(sizeof(RunMaps) <= sizeof(o.maps[0]), "run maps fit the opaque slots");
     for (int l = 0; l < 2; ++l) {
-        const RunMaps m{reinterpret_cast<uint16_t *>(p + L.pos[l]), reinterpret_cast<uint16_t *>(p + L.dest[l]),
-                        reinterpret_cast<uint32_t *>(p + L.base[l]), reinterpret_cast<uint16_t *>(p + L.offset[l])};
+        const RunMaps m{reinterpret_cast<uint16_t *>(p + L.pos[l]), reinterpret_cast<uint32_t *>(p + L.base[l]),
+                        reinterpret_cast<uint16_t *>(p + L.offset[l])};
         __builtin_memcpy(o.maps[l], &m, sizeof(m));
     }
     return o;
