@@ -2,7 +2,8 @@
 // wavelet's DFT-domain multiplier, and an inverse FFT, all in FP32 with
 // FP64 only for the mean density and for table generation.
 //
-// Data flow (n^3 grid, H = n/2 + 1, half spectrum S[z][y][kx] complex64):
+// Data flow (n^3 grid, H = n/2 + 1, half spectrum S complex64 stored in tiles
+// of YZ_TILE columns, see spec_tile):
 //   x_fwd   : rows of int64 rho -> float, two real rows packed as one complex
 //             row, complex FFT along x, split into two half-spectrum rows;
 //             also the exact 128-bit mass of the rows.
@@ -30,6 +31,25 @@ constexpr int MAX_STAGES = 12;
 constexpr int MAX_ELEMS = 16;  // complex values per thread per stage
 constexpr int YZ_LOG = 3;
 constexpr int YZ_TILE = 1 << YZ_LOG;  // pencils per workgroup in the y and z passes
+
+// The half spectrum in HBM, in tiles of YZ_TILE columns: element (kx, y, z) of
+// an n^3 grid at spec_at(n, kx / YZ_TILE, z, y) + kx % YZ_TILE.  A tile is an
+// [z][y][column] block whose z planes are n + 1 rows apart, and tiles are
+// n (n + 1) + 1 rows apart.  A y-pass tile (YZ_TILE columns at one z) is one
+// contiguous run of n * YZ_TILE elements, a z-pass tile's elements are
+// (n + 1) YZ_TILE apart inside one tile, and the x passes move YZ_TILE-column
+// blocks of consecutive rows.  The spare rows keep those strides off powers of
+// two, which would put a workgroup's accesses on few HBM channels.  Columns
+// H .. tiles * YZ_TILE - 1 and the spare rows are padding that no pass reads.
+__host__ __device__ inline int spec_tiles(int n) { return (n / 2 + 1 + YZ_TILE - 1) / YZ_TILE; }
+
+__host__ __device__ inline size_t spec_tile_rows(int n) { return size_t(n) * (n + 1) + 1; }
+
+__device__ __forceinline__ size_t spec_at(int n, int tile, int z, int y) {
+    return (size_t(tile) * spec_tile_rows(n) + size_t(z) * (n + 1) + size_t(y)) * YZ_TILE;
+}
+
+
 
 struct FftPlan {
     int n;
@@ -550,17 +570,21 @@ __global__ void fft_x_fwd_kernel(CwtJobs J, CwtLayout L, FftPlan pl, uint32_t *s
     auto lstore = [buf, lp](int p, int x, float2 v) { buf[(x << lp) + p] = v; };
     fft_pencils<false, true, true>(buf, lp, pl, 0, pl.nst, tw, tid, nt, lload, lstore);
     __syncthreads();
-    // split Z = A + iB into the two real rows' spectra
-    for (int e = tid; e < xp * H; e += nt) {
-        const int p = int(pl.dh.div(uint32_t(e))), k = e - p * H;
+    // split Z = A + iB into the two real rows' spectra; a wavefront writes one
+    // column tile of the workgroup's 2 xp consecutive rows
+    const int rows = 2 * xp;
+    const int ntile = spec_tiles(n);
+    for (int e = tid; e < ntile * YZ_TILE * rows; e += nt) {
+        const int c = e & (YZ_TILE - 1), r = (e >> YZ_LOG) % rows, tile = (e >> YZ_LOG) / rows;
+        const int k = tile * YZ_TILE + c, p = r >> 1;
         const int64_t q = q0 + p;
-        if (q >= pairs) continue;
+        if (k >= H || q >= pairs) continue;
         const float2 zk = buf[(k << lp) + p];
         const float2 zm = buf[(((n - k) % n) << lp) + p];
-        const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-        const float2 B = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-        spec[(2 * q) * H + k] = A;
-        spec[(2 * q + 1) * H + k] = B;
+        const float2 v = (r & 1) ? make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x))  // B, row 2q + 1
+                                 : make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));  // A, row 2q
+        const uint32_t row = uint32_t(2 * q + (r & 1)), z = pl.dn.div(row);
+        spec[spec_at(n, tile, int(z), int(row - z * uint32_t(n))) + c] = v;
     }
 }
 
@@ -580,26 +604,35 @@ __global__ void fft_x_inv_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
     const int64_t pairs = int64_t(n) * n / 2;
     const int64_t q0 = int64_t(blockIdx.x) * xp;
     load_twiddles(tw, tw_g, n);
+    // element e: column c of tile `tile` for pair p; a wavefront reads one column
+    // tile of consecutive rows
+    const int ntile = spec_tiles(n);
+    const int span = ntile * YZ_TILE * xp;  // at most xp n, so MAX_ELEMS per thread suffice
     float2 va[MAX_ELEMS], vb[MAX_ELEMS];
 #pragma unroll
     for (int i = 0; i < MAX_ELEMS; ++i) {
         const int e = tid + i * nt;
         va[i] = make_float2(0.f, 0.f);
         vb[i] = va[i];
-        if (e < xp * H) {
-            const int p = int(pl.dh.div(uint32_t(e))), k = e - p * H;
+        if (e < span) {
+            const int c = e & (YZ_TILE - 1), p = (e >> YZ_LOG) % xp, tile = (e >> YZ_LOG) / xp;
             const int64_t q = q0 + p;
-            if (q < pairs) {
-                va[i] = spec[(2 * q) * H + k];
-                vb[i] = spec[(2 * q + 1) * H + k];
+            if (tile * YZ_TILE + c < H && q < pairs) {
+                // rows 2q and 2q + 1 share z (n is even)
+                const uint32_t row = uint32_t(2 * q), z = pl.dn.div(row);
+                const size_t at = spec_at(n, tile, int(z), int(row - z * uint32_t(n))) + c;
+                va[i] = spec[at];
+                vb[i] = spec[at + YZ_TILE];
             }
         }
     }
 #pragma unroll
     for (int i = 0; i < MAX_ELEMS; ++i) {
         const int e = tid + i * nt;
-        if (e >= xp * H) continue;
-        const int p = int(pl.dh.div(uint32_t(e))), k = e - p * H;
+        if (e >= span) continue;
+        const int c = e & (YZ_TILE - 1), p = (e >> YZ_LOG) % xp, tile = (e >> YZ_LOG) / xp;
+        const int k = tile * YZ_TILE + c;
+        if (k >= H) continue;
         const float2 A = va[i], B = vb[i];
         if (k == 0 || 2 * k == n) {
             // DC and Nyquist of a real row are real
@@ -710,11 +743,11 @@ __global__ void fft_y_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int kx0 = tile * YZ_TILE;
     const int valid = min(YZ_TILE, H - kx0);
-    float2 *col = spec + size_t(zrow) * n * H + kx0;  // element y of pencil p at col[y H + p]
+    float2 *col = spec + spec_at(n, tile, zrow, 0);  // element y of pencil p at col[y YZ_TILE + p]
     load_twiddles(tw, jv.tw, n);                      // first read after the first stage's barrier
-    auto gload = [=](int p, int y) { return p < valid ? col[size_t(y) * H + p] : make_float2(0.f, 0.f); };
+    auto gload = [=](int p, int y) { return p < valid ? col[y * YZ_TILE + p] : make_float2(0.f, 0.f); };
     auto gstore = [=](int p, int y, float2 v) {
-        if (p < valid) col[size_t(y) * H + p] = v;
+        if (p < valid) col[y * YZ_TILE + p] = v;
     };
     fft_pencils<INV, false, false>(buf, YZ_LOG, pl, 0, pl.nst, tw, tid, nt, gload, gstore);
 }
@@ -736,8 +769,8 @@ __global__ void fft_z_mul_kernel(CwtJobs J, CwtLayout L, FftPlan pl, FftPlan pi)
     const int kx0 = tile * YZ_TILE;
     const int ky = yrow;
     const int valid = min(YZ_TILE, H - kx0);
-    const size_t zstride = size_t(n) * H;
-    float2 *col = spec + size_t(ky) * H + kx0;  // element z of pencil p at col[z zstride + p]
+    const size_t zstride = size_t(n + 1) * YZ_TILE;
+    float2 *col = spec + spec_at(n, tile, 0, ky);  // element z of pencil p at col[z zstride + p]
     load_twiddles(tw, jv.tw, n);
     const float scale = float(jv.scalars[0]);
     const float by = tab_b[ky], py = tab_p[ky];
@@ -768,8 +801,7 @@ __global__ void fft_z_mul_kernel(CwtJobs J, CwtLayout L, FftPlan pl, FftPlan pi)
 // workspace layout
 // ---------------------------------------------------------------------------
 // log2 of the row pairs per x-pass workgroup: at most `elems` complex values,
-// between 4 and 16 pairs.  The forward pass keeps two int64 per value in flight
-// per thread, so it takes fewer pairs than the inverse.
+// between 4 and 16 pairs.  More pairs make longer runs in each spectrum tile.
 int x_log_pairs(int n, int elems) {
     int lp = 4;
     while (lp > 2 && (n << lp) > elems) --lp;
@@ -778,8 +810,7 @@ int x_log_pairs(int n, int elems) {
 
 CwtLayout cwt_layout(int n) {
     CwtLayout L{};
-    const size_t H = size_t(n) / 2 + 1;
-    L.lp_x = x_log_pairs(n, 4096);
+    L.lp_x = x_log_pairs(n, 8192);
     L.lp_xi = x_log_pairs(n, 8192);
     const int64_t pairs = int64_t(n) * n / 2;
     L.xblocks = (pairs + (1 << L.lp_x) - 1) >> L.lp_x;
@@ -800,7 +831,7 @@ CwtLayout cwt_layout(int n) {
     L.mass = off;
     off = align_up(off + sizeof(Mass128) * size_t(L.xblocks));
     L.spec = off;
-    off = align_up(off + sizeof(float2) * size_t(n) * n * H);
+    off = align_up(off + sizeof(float2) * size_t(spec_tiles(n)) * spec_tile_rows(n) * YZ_TILE);
     L.total = off;
     return L;
 }
