@@ -44,7 +44,7 @@ TIMER_SYMBOLS = {
     "fft_y_inv": ("fft_y_kernel<true>",), "fft_x_inv": ("fft_x_inv_kernel",),
     "maxima_mark": ("max_tile_kernel", "max_direct_kernel"), "maxima_count": ("mask_count_kernel",),
     "maxima_scan": ("seg_reduce_kernel<1>", "seg_scan_kernel<1>"), "maxima_write": ("list_write_kernel",),
-    "parent": ("parent_tile_kernel", "parent_direct_kernel"), "resolve": ("resolve_tile_kernel",), "jump_flags": ("fill_flags_kernel",),
+    "parent": ("parent_walk_kernel", "parent_direct_kernel"), "resolve": ("resolve_tile_kernel",), "jump_flags": ("fill_flags_kernel",),
     "jump": ("bnd_jump_first_kernel", "bnd_jump_kernel", "jump_direct_kernel"), "finalize": ("seg_finalize_kernel", "finalize_direct_kernel"),
     "label_tiles": ("tile_label_kernel",), "label_level1": ("to_level1_kernel",), "label_input": ("to_input_kernel",),
 }

@@ -208,26 +208,87 @@ __global__ void __launch_bounds__(SEG_THREADS) max_tile_kernel(const float *__re
 // neighbourhood, or -1 for a root (its own parent) at or below tau.  With a
 // mask, the tile's maxima bits are written as well (the maxima are exactly the
 // cells that are their own parent, above tau).
-__global__ void __launch_bounds__(SEG_THREADS) parent_tile_kernel(const float *__restrict__ c, TileGrid tg,
-                                                                  uint32_t tau_ord, int32_t *__restrict__ parent,
-                                                                  uint32_t *__restrict__ mask, uint32_t *status) {
-    __shared__ uint64_t K[HCELLS];
-    __shared__ uint64_t M[TX * HY * HZ];
-    int x0, y0, z0;
+//
+// One workgroup per WX x 8 x 8 tile (WX = 64 where n allows, else 32) keeps
+// the tile and a one-cell halo of the field in LDS as 32-bit order-preserving
+// bits (the index half of a key is formed in registers), and each thread walks
+// one z column of the tile: the largest key of each 3x3 halo plane around the
+// column is formed once, and a cell's parent is the largest of the three plane
+// maxima around it.  That is about 11 LDS reads of 4 bytes per cell; the wide
+// tiles read the field in long row pieces.
+template <int WX>
+__global__ void __launch_bounds__(WX * TY) parent_walk_kernel(const float *__restrict__ c, TileGrid tg,
+                                                              uint32_t tau_ord, int32_t *__restrict__ parent,
+                                                              uint32_t *__restrict__ mask, uint32_t *status) {
+    constexpr int THREADS = WX * TY;  // one z column each
+    constexpr int WHX = WX + 2, WCELLS = WHX * HY * HZ;
+    __shared__ uint32_t V[WCELLS];
     const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    tile_origin(tg, int(tile), x0, y0, z0);
+    const int x0 = int(tile % uint32_t(tg.ntx)) * WX;
+    const int y0 = int((tile / uint32_t(tg.ntx)) % uint32_t(tg.nty)) * TY;
+    const int z0 = int(tile / uint32_t(tg.ntx * tg.nty)) * TZ;
+    const int n = tg.n;
+    const uint32_t un = uint32_t(n);
     bool nan = false;
-    tile_parent_keys(c, tg.n, x0, y0, z0, K, M, nan);
-    const uint32_t n = uint32_t(tg.n);
-    if (mask) write_mask(M, n, x0, y0, z0, tau_ord, mask);
+    {
+        // all loads of the halo tile are issued before any is used
+        constexpr int LOADS = (WCELLS + THREADS - 1) / THREADS;
+        float v[LOADS];
 #pragma unroll
-    for (int i = 0; i < PER_THREAD; ++i) {
-        const int e = i * SEG_THREADS + threadIdx.x;
-        const int x = e % TX, y = (e / TX) % TY, z = e / (TX * TY);
-        const uint32_t g = ((uint32_t(z0 + z) * n) + uint32_t(y0 + y)) * n + uint32_t(x0 + x);
-        const uint64_t k = M[e];
-        const uint32_t p = uint32_t(k);
-        parent[g] = (p == g && uint32_t(k >> 32) <= tau_ord) ? -1 : int32_t(p);
+        for (int i = 0; i < LOADS; ++i) {
+            const int e = threadIdx.x + i * THREADS;
+            const int hx = e % WHX, hy = (e / WHX) % HY, hz = e / (WHX * HY);
+            if (e < WCELLS)
+                v[i] = c[(wrap(z0 + hz - 1, n) * un + wrap(y0 + hy - 1, n)) * un + wrap(x0 + hx - 1, n)];
+        }
+#pragma unroll
+        for (int i = 0; i < LOADS; ++i) {
+            const int e = threadIdx.x + i * THREADS;
+            if (e < WCELLS) V[e] = ordered_bits(v[i], nan);
+        }
+    }
+    __syncthreads();
+    // the thread's column (x, y); a wavefront covers 64 consecutive x of one
+    // row (WX = 64) or rows y and y + 1 (WX = 32)
+    const int x = threadIdx.x % WX, y = threadIdx.x / WX;
+    const int lane = threadIdx.x & 63;
+    uint32_t gx[3], gy[3];  // global x / y of the halo columns / rows x - 1 .. x + 1, y - 1 .. y + 1
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        gx[d] = wrap(x0 + x + d - 1, n);
+        gy[d] = wrap(y0 + y + d - 1, n);
+    }
+    // largest key of halo plane hz around the column
+    auto plane_max = [&](int hz) {
+        const uint32_t row0 = wrap(z0 + hz - 1, n) * un;
+        uint64_t best = 0;
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const uint32_t row = (row0 + gy[dy]) * un;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+                best = kmax(best, (uint64_t(V[(hz * HY + y + dy) * WHX + x + dx]) << 32) | (row + gx[dx]));
+        }
+        return best;
+    };
+    uint64_t b0 = plane_max(0), b1 = plane_max(1);
+#pragma unroll
+    for (int z = 0; z < TZ; ++z) {
+        const uint64_t b2 = plane_max(z + 2);
+        const uint64_t best = kmax(kmax(b0, b1), b2);
+        const uint32_t g = (uint32_t(z0 + z) * un + gy[1]) * un + gx[1];
+        const uint32_t p = uint32_t(best);
+        const bool high = uint32_t(best >> 32) > tau_ord;
+        if (mask) {
+            const unsigned long long bits = __ballot(p == g && high);
+            if (lane == 0) {
+                mask[g >> 5] = uint32_t(bits);
+                mask[(g + (WX == 64 ? 32u : un)) >> 5] = uint32_t(bits >> 32);
+            }
+        }
+        parent[g] = (p == g && !high) ? -1 : int32_t(p);
+        b0 = b1;
+        b1 = b2;
     }
     if (nan) atomicOr(status, ST_INPUT);
 }
@@ -714,7 +775,22 @@ hf_status mask_to_list(hf_ctx *ctx, const MaximaLayout &L, char *w8, int32_t *ma
     return launch_status();
 }
 
-// After parent_tile_kernel has filled ptr with parents: chains resolved per
+// Parents (and the maxima mask when given) of a tiled grid.
+hf_status launch_parents(hf_ctx *ctx, int n, const float *cwt, float tau, int32_t *parent, uint32_t *mask) {
+    const uint32_t tau_ord = host_ordered_bits(tau);
+    if (n % 64 == 0) {
+        const TileGrid wg{n, n / 64, n / TY, n / TZ, FastDiv(uint32_t(n))};
+        HF_LAUNCH(ctx, K_PARENT, parent_walk_kernel<64>, dim3(wg.ntx * wg.nty * wg.ntz), dim3(64 * TY), 0,
+                  ctx->stream, cwt, wg, tau_ord, parent, mask, ctx->d_status);
+    } else {
+        const TileGrid tg = tile_grid(n);
+        HF_LAUNCH(ctx, K_PARENT, parent_walk_kernel<TX>, dim3(tg.ntx * tg.nty * tg.ntz), dim3(TX * TY), 0,
+                  ctx->stream, cwt, tg, tau_ord, parent, mask, ctx->d_status);
+    }
+    return launch_status();
+}
+
+// After launch_parents has filled ptr with parents: chains resolved per
 // resolve tile, pointer-jumping rounds over the boundary entries, and the final
 // mapping through them.
 hf_status segment_finish(hf_ctx *ctx, const SegmentLayout &L, char *w8, int n, int32_t *cell_label) {
@@ -761,13 +837,12 @@ hf_status hf::maxima_segment(hf_ctx *ctx, const hf_box &box, const float *cwt, f
     if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
     char *w8 = static_cast<char *>(ws);
     char *wm = w8 + SL.total;
-    const TileGrid tg = tile_grid(n);
     auto *flags = reinterpret_cast<uint32_t *>(w8 + SL.flags);
     HF_LAUNCH(ctx, K_FLAGS, fill_flags_kernel, dim3((SL.rounds + 2 + 255) / 256), dim3(256), 0, ctx->stream, flags,
               SL.rounds + 2);
-    HF_LAUNCH(ctx, K_PARENT, parent_tile_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(SEG_THREADS), 0, ctx->stream,
-              cwt, tg, host_ordered_bits(tau), reinterpret_cast<int32_t *>(w8 + SL.ptr),
-              reinterpret_cast<uint32_t *>(wm + ML.mask), ctx->d_status);
+    s = launch_parents(ctx, n, cwt, tau, reinterpret_cast<int32_t *>(w8 + SL.ptr),
+                       reinterpret_cast<uint32_t *>(wm + ML.mask));
+    if (s != HF_OK) return s;
     s = mask_to_list(ctx, ML, wm, max_idx, max_cap, d_count);
     if (s != HF_OK) return s;
     return segment_finish(ctx, SL, w8, n, cell_label);
@@ -814,10 +889,8 @@ extern "C" hf_status hf_segment(hf_ctx *ctx, const hf_box *box, const float *cwt
     HF_LAUNCH(ctx, K_FLAGS, fill_flags_kernel, dim3((L.rounds + 2 + 255) / 256), dim3(256), 0, ctx->stream, flags,
               L.rounds + 2);
     if (tiled(n)) {
-        const TileGrid tg = tile_grid(n);
-        HF_LAUNCH(ctx, K_PARENT, parent_tile_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(SEG_THREADS), 0,
-                  ctx->stream, cwt, tg, host_ordered_bits(tau), reinterpret_cast<int32_t *>(w8 + L.ptr), nullptr,
-                  ctx->d_status);
+        s = launch_parents(ctx, n, cwt, tau, reinterpret_cast<int32_t *>(w8 + L.ptr), nullptr);
+        if (s != HF_OK) return s;
         return segment_finish(ctx, L, w8, n, cell_label);
     } else {
         const uint32_t cells = uint32_t(n) * n * n;
