@@ -362,13 +362,29 @@ __global__ void fill_flags_kernel(uint32_t *flags, int count) {
 }
 
 // Pointer jumping over the boundary entries, in place.  Round 0 visits every
-// entry; each workgroup appends to its own slice of `list` (cap entries at
+// entry; each workgroup appends to its own slice of a list (cap entries at
 // blockIdx * cap, count in counts[blockIdx]) the entries that changed and now
 // point at a boundary cell, whose own entry may still change: only those can
-// change again.  Later rounds run the same grid, each workgroup over its own
-// slice, so no global counter is shared.  Round r runs only if round r - 1
-// changed something, so a fixed number of launches is enough.
+// change again (an entry that does not change points at a root, which is
+// final).  Each later round visits its workgroup's slice of the previous
+// round's list and writes the entries still active to the other list, so no
+// global counter is shared and the lists shrink.  Round r runs only if round
+// r - 1 left an entry active, so a fixed number of launches is enough.
 constexpr int BATCH = 8;  // independent iterations per thread and pass, so their loads overlap
+
+// Appends the entries k with `again` set to this workgroup's slice `mine`
+// (one LDS reservation per wavefront).
+__device__ __forceinline__ void append_active(bool again, uint32_t k, uint32_t *mine, uint32_t *lcount) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long bits = __ballot(again);
+    if (bits) {
+        const int leader = __ffsll(bits) - 1;
+        uint32_t at = 0;
+        if (lane == leader) at = atomicAdd(lcount, uint32_t(__popcll(bits)));
+        at = __shfl(at, leader, 64);
+        if (again) mine[at + __popcll(bits & ((1ull << lane) - 1ull))] = k;
+    }
+}
 
 __global__ void __launch_bounds__(256) bnd_jump_first_kernel(int32_t *__restrict__ bnd, int64_t count, TileGrid tg,
                                                              uint32_t *__restrict__ list, int64_t cap,
@@ -377,7 +393,6 @@ __global__ void __launch_bounds__(256) bnd_jump_first_kernel(int32_t *__restrict
     if (threadIdx.x == 0) lcount = 0u;
     __syncthreads();
     uint32_t *mine = list + int64_t(blockIdx.x) * cap;
-    const int lane = threadIdx.x & 63;
     const int64_t step = int64_t(gridDim.x) * blockDim.x * BATCH;
     for (int64_t k0 = blockIdx.x * int64_t(blockDim.x) * BATCH + threadIdx.x; k0 < count; k0 += step) {
         int32_t p[BATCH], q[BATCH];
@@ -402,14 +417,7 @@ __global__ void __launch_bounds__(256) bnd_jump_first_kernel(int32_t *__restrict
                 bnd[k] = q[i];
                 again = q[i] >= 0 && bnd_slot(tg, q[i]) >= 0;
             }
-            const unsigned long long bits = __ballot(again);
-            if (bits) {  // one LDS reservation per wavefront
-                const int leader = __ffsll(bits) - 1;
-                uint32_t at = 0;
-                if (lane == leader) at = atomicAdd(&lcount, uint32_t(__popcll(bits)));
-                at = __shfl(at, leader, 64);
-                if (again) mine[at + __popcll(bits & ((1ull << lane) - 1ull))] = uint32_t(k);
-            }
+            append_active(again, uint32_t(k), mine, &lcount);
         }
     }
     __syncthreads();
@@ -419,20 +427,27 @@ __global__ void __launch_bounds__(256) bnd_jump_first_kernel(int32_t *__restrict
     }
 }
 
-__global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd, const uint32_t *__restrict__ list,
-                                                       int64_t cap, const uint32_t *__restrict__ counts, TileGrid tg,
+// Round r >= 1: list_in / counts_in hold round r - 1's active entries, the
+// entries still active after this round go to list_out / counts_out.
+__global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd, const uint32_t *__restrict__ list_in,
+                                                       const uint32_t *__restrict__ counts_in,
+                                                       uint32_t *__restrict__ list_out,
+                                                       uint32_t *__restrict__ counts_out, int64_t cap, TileGrid tg,
                                                        uint32_t *flags, int round) {
     if (flags[round] == 0u) return;
-    const uint32_t *mine = list + int64_t(blockIdx.x) * cap;
-    const int64_t count = counts[blockIdx.x];
-    bool changed = false;
+    __shared__ uint32_t lcount;
+    if (threadIdx.x == 0) lcount = 0u;
+    __syncthreads();
+    const uint32_t *from = list_in + int64_t(blockIdx.x) * cap;
+    uint32_t *mine = list_out + int64_t(blockIdx.x) * cap;
+    const int64_t count = counts_in[blockIdx.x];
     for (int64_t j0 = threadIdx.x; j0 < count; j0 += int64_t(blockDim.x) * BATCH) {
         uint32_t k[BATCH];
         int32_t p[BATCH], q[BATCH];
 #pragma unroll
         for (int i = 0; i < BATCH; ++i) {
             const int64_t j = j0 + int64_t(i) * blockDim.x;
-            k[i] = j < count ? mine[j] : 0u;
+            k[i] = j < count ? from[j] : 0u;
         }
 #pragma unroll
         for (int i = 0; i < BATCH; ++i) {
@@ -447,13 +462,19 @@ __global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd
 #pragma unroll
         for (int i = 0; i < BATCH; ++i) {
             const int64_t j = j0 + int64_t(i) * blockDim.x;
+            bool again = false;
             if (j < count && q[i] != p[i]) {
                 bnd[k[i]] = q[i];
-                changed = true;
+                again = q[i] >= 0 && bnd_slot(tg, q[i]) >= 0;
             }
+            append_active(again, k[i], mine, &lcount);
         }
     }
-    if (__any(changed) && (threadIdx.x & 63) == 0) flags[round + 1] = 1u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        counts_out[blockIdx.x] = lcount;
+        if (lcount) flags[round + 1] = 1u;
+    }
 }
 
 // One workgroup per resolve tile: the resolved boundary entries of the
@@ -709,7 +730,7 @@ int stride_grid(int64_t work) {
 int batched_grid(int64_t work) { return stride_grid((work + BATCH - 1) / BATCH); }
 
 struct SegmentLayout {
-    size_t flags, ptr, bnd, list, counts, total;
+    size_t flags, ptr, bnd, list[2], counts[2], total;
     int rounds;
     int64_t nbnd;
     int jump_grid;      // workgroups of every jump round
@@ -734,10 +755,12 @@ SegmentLayout segment_layout(int n) {
         L.jump_grid = batched_grid(L.nbnd);
         const int64_t per_pass = int64_t(L.jump_grid) * 256 * BATCH;
         L.list_cap = (L.nbnd + per_pass - 1) / per_pass * 256 * BATCH;
-        L.list = off;
-        off = align_up(off + sizeof(uint32_t) * size_t(L.list_cap) * size_t(L.jump_grid));
-        L.counts = off;
-        off = align_up(off + sizeof(uint32_t) * size_t(L.jump_grid));
+        for (int b = 0; b < 2; ++b) {  // the active lists of even and odd rounds
+            L.list[b] = off;
+            off = align_up(off + sizeof(uint32_t) * size_t(L.list_cap) * size_t(L.jump_grid));
+            L.counts[b] = off;
+            off = align_up(off + sizeof(uint32_t) * size_t(L.jump_grid));
+        }
     } else {
         L.rounds = rounds_for(cells);
         off = align_up(off + sizeof(uint32_t) * (L.rounds + 2));
@@ -800,13 +823,16 @@ hf_status segment_finish(hf_ctx *ctx, const SegmentLayout &L, char *w8, int n, i
     auto *bnd = reinterpret_cast<int32_t *>(w8 + L.bnd);
     HF_LAUNCH(ctx, K_RESOLVE, resolve_tile_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(RES_THREADS), 0, ctx->stream,
               ptr, tg, bnd);
-    auto *list = reinterpret_cast<uint32_t *>(w8 + L.list);
-    auto *counts = reinterpret_cast<uint32_t *>(w8 + L.counts);
-    HF_LAUNCH(ctx, K_JUMP, bnd_jump_first_kernel, dim3(L.jump_grid), dim3(256), 0, ctx->stream, bnd, L.nbnd, tg, list,
-              L.list_cap, counts, flags);
+    uint32_t *list[2], *counts[2];
+    for (int b = 0; b < 2; ++b) {
+        list[b] = reinterpret_cast<uint32_t *>(w8 + L.list[b]);
+        counts[b] = reinterpret_cast<uint32_t *>(w8 + L.counts[b]);
+    }
+    HF_LAUNCH(ctx, K_JUMP, bnd_jump_first_kernel, dim3(L.jump_grid), dim3(256), 0, ctx->stream, bnd, L.nbnd, tg,
+              list[0], L.list_cap, counts[0], flags);
     for (int r = 1; r < L.rounds; ++r)
-        HF_LAUNCH(ctx, K_JUMP, bnd_jump_kernel, dim3(L.jump_grid), dim3(256), 0, ctx->stream, bnd, list, L.list_cap,
-                  counts, tg, flags, r);
+        HF_LAUNCH(ctx, K_JUMP, bnd_jump_kernel, dim3(L.jump_grid), dim3(256), 0, ctx->stream, bnd, list[(r - 1) & 1],
+                  counts[(r - 1) & 1], list[r & 1], counts[r & 1], L.list_cap, tg, flags, r);
     HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(RES_THREADS), 0,
               ctx->stream, ptr, bnd, tg, cell_label);
     return launch_status();
