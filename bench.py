@@ -151,7 +151,7 @@ def load_traffic(workload: str, digest: str) -> dict:
 
 def stage_traffic(counted: dict, stage: str, ran: set):
     """HBM bytes per step of one stage from the counter summary (per-dispatch
-    bytes x dispatches of the one-step counter run), or None if a launch of the
+    bytes x dispatches per step of the counter run), or None if a launch of the
     stage that ran here has no counters."""
     fetch = write = 0.0
     for t in STAGES[stage]:
@@ -163,6 +163,12 @@ def stage_traffic(counted: dict, stage: str, ran: set):
             fetch += f * d
             write += w * d
     return {"fetch_bytes": fetch, "write_bytes": write, "bytes": fetch + write}
+
+
+def steps_run(bench_line: dict) -> int:
+    """Steps a bench run executed: its warmup, the headline steps and as many
+    steps with the kernel timer."""
+    return bench_line["warmup"] + 2 * bench_line["steps"]
 
 
 def summarize_profiles(trace_dir: str, pmc_dir: str, workload: str, trace_cmd: str, pmc_cmd: str):
@@ -187,13 +193,13 @@ def summarize_profiles(trace_dir: str, pmc_dir: str, workload: str, trace_cmd: s
             continue
         rows.append((t, sym, int(r["Calls"]), float(r["AverageNs"]) / 1e6, float(r["TotalDurationNs"]) / 1e6))
     rows.sort(key=lambda x: -x[4])
-    steps = (bench_line["steps"] + bench_line["warmup"]) if bench_line else None
+    steps = steps_run(bench_line) if bench_line else None
     lines = [f"# rocprofv3 kernel trace, libhf kernels, workload {workload}",
              f"# command: {trace_cmd}",
              f"# bench line of the traced run: ms_per_step={bench_line['ms_per_step'] if bench_line else '?'} "
              f"(steps={bench_line['steps'] if bench_line else '?'}, warmup={bench_line['warmup'] if bench_line else '?'})",
              "# avg_ms = rocprofv3 average duration per dispatch; timer_avg_ms = the library's HIP-event timer in",
-             "# the same run (timed steps only)",
+             "# the same run (its timer steps); ms/step = total over the run's warmup, headline and timer steps",
              f"{'timer':<20}{'symbol':<26}{'calls':>7}{'avg_ms':>11}{'timer_avg_ms':>14}{'ms/step':>10}"]
     for t, sym, calls, avg, tot in rows:
         tk = (bench_line or {}).get("kernels", {}).get(t)
@@ -222,18 +228,21 @@ def summarize_profiles(trace_dir: str, pmc_dir: str, workload: str, trace_cmd: s
     mf = per_kernel(glob.glob(os.path.join(pmc_dir, "m4_FETCH_SIZE_counter_collection.csv"))[0])
     mw = per_kernel(glob.glob(os.path.join(pmc_dir, "m4_WRITE_SIZE_counter_collection.csv"))[0])
     digest = None
+    runs = 1  # steps the counter run executed
     plog = os.path.join(os.path.dirname(pmc_dir.rstrip("/")), "pmc_m4_FETCH_SIZE.log")
     if os.path.exists(plog):
         for line in open(plog):
             if "libhf sources" in line:
                 digest = line.split()[-1]
+            if line.startswith("{"):
+                runs = steps_run(json.loads(line))
     lines = [f"# HBM traffic per dispatch from rocprofv3 counters, libhf kernels, workload {workload}",
              f"# commands: {pmc_cmd}",
              f"# copy calibration: {copy_sym} of {copy_bytes} B reads FETCH_SIZE {kib_f:.1f} KiB and "
              f"WRITE_SIZE {kib_w:.1f} KiB per dispatch",
              f"# scale factors: fetch x{ff:.4f}, write x{fw:.4f} (bytes = KiB * 1024 * factor)",
              f"# sources {digest or 'unknown'}",
-             "# per dispatch; dispatches = launches in the one-step counter run",
+             f"# per dispatch; dispatches = launches per step (the counter run executed {runs} steps)",
              f"{'kernel':<20}{'fetch_KiB':>16}{'write_KiB':>16}{'fetch_B':>18}{'write_B':>18}{'dispatches':>11}"
              "  symbol"]
     for sym in mf:
@@ -243,7 +252,7 @@ def summarize_profiles(trace_dir: str, pmc_dir: str, workload: str, trace_cmd: s
         f_kib = sum(mf[sym]) / len(mf[sym])
         w_kib = sum(mw[sym]) / len(mw[sym])
         lines.append(f"{t:<20}{f_kib:>16.1f}{w_kib:>16.1f}{f_kib * 1024 * ff:>18.4e}{w_kib * 1024 * fw:>18.4e}"
-                     f"{len(mf[sym]):>11}  {sym}")
+                     f"{round(len(mf[sym]) / runs):>11}  {sym}")
     with open(traffic_file(workload), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print(out1)
