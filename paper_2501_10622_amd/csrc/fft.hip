@@ -721,12 +721,14 @@ __global__ void mass_kernel(CwtJobs J, CwtLayout L, int n, uint32_t *status) {
 // ---------------------------------------------------------------------------
 // y and z passes on tiles of YZ_TILE columns of the half spectrum
 // ---------------------------------------------------------------------------
-// Logical tile of a (tiles, rows, jobs) grid, XCD-contiguous over the whole launch.
-__device__ __forceinline__ void yz_tile(int &tile, int &row, int &job) {
+// Logical block (x, y, job) of an (X, Y, jobs) grid, XCD-contiguous over the
+// whole launch: x = column tile, y = row in the y pass; x = row, y = column
+// tile in the z pass.
+__device__ __forceinline__ void yz_tile(int &x, int &y, int &job) {
     const uint32_t X = gridDim.x, Y = gridDim.y;
     const uint32_t lt = xcd_remap(blockIdx.x + X * (blockIdx.y + Y * blockIdx.z), X * Y * gridDim.z);
-    tile = int(lt % X);
-    row = int((lt / X) % Y);
+    x = int(lt % X);
+    y = int((lt / X) % Y);
     job = int(lt / (X * Y));
 }
 
@@ -754,10 +756,13 @@ __global__ void fft_y_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
 
 // Forward z transform, multiplier, inverse z transform; pi is pl with its
 // last radix moved to the front.
+// The z pass walks its tiles ky-fastest (grid (n, tiles, jobs)): the tiles of
+// rows ky and ky + 1 read the two halves of the same 128-byte lines, so they
+// run together on one XCD and each line comes from HBM once.
 __global__ void fft_z_mul_kernel(CwtJobs J, CwtLayout L, FftPlan pl, FftPlan pi) {
     extern __shared__ float2 smem[];
     int tile, yrow, job;
-    yz_tile(tile, yrow, job);
+    yz_tile(yrow, tile, job);
     const JobView jv = job_view(J, L, job);
     float2 *__restrict__ spec = jv.spec;
     const float *__restrict__ tab_b = jv.btab;
@@ -878,7 +883,7 @@ hf_status run_cwt(hf_ctx *ctx, int n, const CwtJobs &J) {
               ctx->d_status);
     HF_LAUNCH(ctx, K_MASS, mass_kernel, dim3(jobs), dim3(1024), 0, st, J, L, n, ctx->d_status);
     HF_LAUNCH(ctx, K_Y_FWD, fft_y_kernel<false>, dim3(tiles, n, jobs), dim3(yz_threads), yz_shm, st, J, L, pl);
-    HF_LAUNCH(ctx, K_Z_MUL, fft_z_mul_kernel, dim3(tiles, n, jobs), dim3(yz_threads), yz_shm, st, J, L, pl, pi);
+    HF_LAUNCH(ctx, K_Z_MUL, fft_z_mul_kernel, dim3(n, tiles, jobs), dim3(yz_threads), yz_shm, st, J, L, pl, pi);
     HF_LAUNCH(ctx, K_Y_INV, fft_y_kernel<true>, dim3(tiles, n, jobs), dim3(yz_threads), yz_shm, st, J, L, pl);
     HF_LAUNCH(ctx, K_X_INV, fft_x_inv_kernel, dim3(unsigned(L.xblocks_i), jobs), dim3(xi_threads), xi_shm, st, J, L,
               pl);
