@@ -379,10 +379,14 @@ struct L2Input {
     int chunk;                    // records per workgroup
 };
 
+// Level-2 chunk of this workgroup: XCD-contiguous, so neighbouring chunks of
+// a bucket (whose runs share lines) go through one L2.
+__device__ __forceinline__ uint32_t l2_chunk_index() { return xcd_remap(blockIdx.x, gridDim.x); }
+
 // Locates this workgroup's chunk: bucket b and the index range [lo, hi).
 template <typename T, bool FROM_REC>
 __device__ __forceinline__ bool l2_chunk(const L2Input<T, FROM_REC> &in, int &b, int64_t &lo, int64_t &hi) {
-    const uint32_t w = blockIdx.x;
+    const uint32_t w = l2_chunk_index();
     if (!FROM_REC) {
         b = 0;
         lo = int64_t(w) * in.chunk;
@@ -504,7 +508,7 @@ __global__ void __launch_bounds__(PART_THREADS) l2_scatter_kernel(L2Input<T, FRO
         rec2[gbase[d] + (s - off[d])] = stage[s];
     }
     if (keep) {
-        save_run_table(maps, blockIdx.x, g.digits, h, off, gbase, total);
+        save_run_table(maps, l2_chunk_index(), g.digits, h, off, gbase, total);
 #pragma unroll
         for (int k = 0; k < PART_PER; ++k)
             if (dg[k] >= 0) maps.pos[lo + k * PART_THREADS + threadIdx.x] = uint16_t(off[dg[k]] + rank[k]);
@@ -716,7 +720,7 @@ __global__ void __launch_bounds__(ACC_THREADS) tile_label_kernel(const uint64_t 
                                                                  const int32_t *__restrict__ cell_label,
                                                                  int32_t *__restrict__ lab2) {
     __shared__ int32_t lab[MAX_ACC_CELLS];
-    const int slot = blockIdx.x;
+    const int slot = int(xcd_remap(blockIdx.x, gridDim.x));  // neighbouring tiles share skirt lines
     const int b = slot / g.digits, d = slot % g.digits;
     int tx, ty, tz;
     tile_coords(g, b, d, tx, ty, tz);
@@ -849,7 +853,7 @@ __global__ void __launch_bounds__(PART_THREADS) to_level1_kernel(RunMaps m2, con
                                                                  int nbuckets, int digits,
                                                                  const int32_t *__restrict__ lab2,
                                                                  int32_t *__restrict__ lab1) {
-    const uint32_t w = blockIdx.x;
+    const uint32_t w = xcd_remap(blockIdx.x, gridDim.x);  // as the level-2 scatter placed them
     if (w >= chunk_first[nbuckets]) return;
     int L = 0, R = nbuckets - 1;  // last b with chunk_first[b] <= w
     while (L < R) {
@@ -869,9 +873,13 @@ __global__ void __launch_bounds__(PART_THREADS) to_level1_kernel(RunMaps m2, con
 __global__ void __launch_bounds__(PART_THREADS) to_input_kernel(RunMaps m1, int64_t np, int nbuckets,
                                                                 const int32_t *__restrict__ lab1,
                                                                 int32_t *__restrict__ out) {
-    const int64_t e0 = int64_t(blockIdx.x) * CHUNK;
+    // the level-1 scatter's chunk order: each XCD reads the runs of the counter
+    // replicas it wrote, in the order it wrote them, so runs sharing lines meet in one L2
+    const int64_t chunk = replica_chunk(blockIdx.x, unsigned((np + CHUNK - 1) / CHUNK));
+    if (chunk < 0) return;
+    const int64_t e0 = chunk * CHUNK;
     const int64_t e1 = e0 + CHUNK < np ? e0 + CHUNK : np;
-    chunk_gather(m1, blockIdx.x, nbuckets, e0, e1, lab1, out);
+    chunk_gather(m1, chunk, nbuckets, e0, e1, lab1, out);
 }
 
 // ---------------------------------------------------------------- host side
@@ -1149,7 +1157,7 @@ hf_status hf::label_from_order(hf_ctx *ctx, const hf_box &box, int64_t np, const
     __builtin_memcpy(&m2, order.maps[1], sizeof(m2));
     HF_LAUNCH(ctx, K_LABEL_LEVEL1, to_level1_kernel, dim3(blocks + unsigned(g.nbuckets)), dim3(PART_THREADS), 0,
               ctx->stream, m2, order.start1, order.chunk_first, g.nbuckets, g.digits, lab2, lab1);
-    HF_LAUNCH(ctx, K_LABEL_INPUT, to_input_kernel, dim3(blocks), dim3(PART_THREADS), 0, ctx->stream, m1, np,
-              g.nbuckets, lab1, particle_label);
+    HF_LAUNCH(ctx, K_LABEL_INPUT, to_input_kernel, dim3(replica_grid(blocks)), dim3(PART_THREADS), 0, ctx->stream,
+              m1, np, g.nbuckets, lab1, particle_label);
     return launch_status();
 }

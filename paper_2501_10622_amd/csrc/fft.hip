@@ -376,7 +376,7 @@ struct Mass128 {
 
 // Per-job workspace layout (offsets from the job's workspace base).
 struct CwtLayout {
-    size_t scalars, tw, gtab, htab, btab, ptab, mass, spec, total;
+    size_t scalars, tw, gtab, htab, ctab, btab, ptab, mass, spec, total;
     int lp_x, lp_xi;          // log2 of row pairs per forward / inverse x-pass workgroup
     int64_t xblocks, xblocks_i;
 };
@@ -399,7 +399,7 @@ struct CwtJobs {
 struct JobView {
     double *scalars;
     float2 *tw;
-    double *gtab, *htab;
+    double *gtab, *htab, *ctab;
     float *btab, *ptab;
     Mass128 *mass;
     float2 *spec;
@@ -412,6 +412,7 @@ __device__ __forceinline__ JobView job_view(const CwtJobs &J, const CwtLayout &L
     v.tw = reinterpret_cast<float2 *>(b + L.tw);
     v.gtab = reinterpret_cast<double *>(b + L.gtab);
     v.htab = reinterpret_cast<double *>(b + L.htab);
+    v.ctab = reinterpret_cast<double *>(b + L.ctab);
     v.btab = reinterpret_cast<float *>(b + L.btab);
     v.ptab = reinterpret_cast<float *>(b + L.ptab);
     v.mass = reinterpret_cast<Mass128 *>(b + L.mass);
@@ -419,7 +420,8 @@ __device__ __forceinline__ JobView job_view(const CwtJobs &J, const CwtLayout &L
     return v;
 }
 
-// twiddles tw[m] = exp(-2 pi i m / n); periodised 1D Gaussian factors of the
+// twiddles tw[m] = exp(-2 pi i m / n), the cosines ctab[m] = cos(2 pi m / n)
+// in FP64 for stage 2; periodised 1D Gaussian factors of the
 // sampled wavelet: G_j = sum_m g(x_j + m L), Hs_j = sum_m (x_j + m L)^2 g(...)
 // with g(t) = exp(-w^2 t^2 / 4) and x_j the minimum-image offset of node j.
 // Job = blockIdx.y.
@@ -432,6 +434,7 @@ __global__ void tables_stage1(CwtJobs J, CwtLayout L, int n) {
     double s, c;
     sincospi(2.0 * double(j) / double(n), &s, &c);
     v.tw[j] = make_float2(float(c), float(-s));
+    v.ctab[j] = cospi(2.0 * double(j) / double(n));  // the DFT cosines of stage 2, one per phase
     const double dx = box_len / n;
     const int jc = (j + n / 2) % n - n / 2;
     double G = 0.0, Hs = 0.0;
@@ -450,13 +453,17 @@ __global__ void tables_stage1(CwtJobs J, CwtLayout L, int n) {
 //            alpha = 6 dx^3 w^1.5, beta = -dx^3 w^3.5 (Eq. (4) split into
 //            6 g g g - w^2 (x^2 g g g + ...), periodised and transformed);
 //  analytic: B = exp(-k^2/w^2), P = 32 pi^1.5 w^-3.5 k^2 B (the transform of Eq. (4)).
-__global__ void tables_stage2(CwtJobs J, CwtLayout L, int n) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+// One workgroup of TAB_THREADS per frequency k: thread t sums the terms
+// j = t, t + TAB_THREADS, ... and the partial sums are added in a fixed order.
+constexpr int TAB_THREADS = 256;
+
+__global__ void __launch_bounds__(TAB_THREADS) tables_stage2(CwtJobs J, CwtLayout L, int n) {
+    const int k = blockIdx.x;
     const int job = blockIdx.y;
     const JobView v = job_view(J, L, job);
     const double w = J.w[job], box_len = J.box_len[job];
     if (J.mode == HF_KERNEL_ANALYTIC) {
+        if (threadIdx.x != 0) return;
         const int ks = k <= n / 2 ? k : k - n;
         const double kk = 2.0 * M_PI * ks / box_len;
         const double B = exp(-(kk * kk) / (w * w));
@@ -466,12 +473,29 @@ __global__ void tables_stage2(CwtJobs J, CwtLayout L, int n) {
         return;
     }
     double B = 0.0, A = 0.0;
-    for (int j = 0; j < n; ++j) {
-        const long long ph = (static_cast<long long>(j) * k) % n;
-        const double c = cospi(2.0 * double(ph) / double(n));
+    const int step = int((int64_t(TAB_THREADS) * k) % n);  // phase step between a thread's terms
+    int ph = int((int64_t(threadIdx.x) * k) % n);
+    for (int j = threadIdx.x; j < n; j += TAB_THREADS) {
+        const double c = v.ctab[ph];
         B += v.gtab[j] * c;
         A += v.htab[j] * c;
+        ph += step;
+        if (ph >= n) ph -= n;
     }
+    __shared__ double rb[TAB_THREADS], ra[TAB_THREADS];
+    rb[threadIdx.x] = B;
+    ra[threadIdx.x] = A;
+    __syncthreads();
+    for (int h = TAB_THREADS / 2; h > 0; h >>= 1) {
+        if (int(threadIdx.x) < h) {
+            rb[threadIdx.x] += rb[threadIdx.x + h];
+            ra[threadIdx.x] += ra[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    B = rb[0];
+    A = ra[0];
     const double dx = box_len / n;
     const double dx3 = dx * dx * dx;
     const double alpha = 6.0 * dx3 * pow(w, 1.5);
@@ -829,6 +853,8 @@ CwtLayout cwt_layout(int n) {
     off = align_up(off + sizeof(double) * n);
     L.htab = off;
     off = align_up(off + sizeof(double) * n);
+    L.ctab = off;
+    off = align_up(off + sizeof(double) * n);
     L.btab = off;
     off = align_up(off + sizeof(float) * n);
     L.ptab = off;
@@ -856,7 +882,7 @@ hf_status run_cwt(hf_ctx *ctx, int n, const CwtJobs &J) {
     const unsigned jobs = unsigned(J.count);
     const int tb = 256, tg = (n + tb - 1) / tb;
     HF_LAUNCH(ctx, K_TABLES_1, tables_stage1, dim3(tg, jobs), dim3(tb), 0, st, J, L, n);
-    HF_LAUNCH(ctx, K_TABLES_2, tables_stage2, dim3(tg, jobs), dim3(tb), 0, st, J, L, n);
+    HF_LAUNCH(ctx, K_TABLES_2, tables_stage2, dim3(n, jobs), dim3(TAB_THREADS), 0, st, J, L, n);
 
     const FftPlan pl = make_plan(n);
     const FftPlan pi = rotate_plan(pl);
