@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(SEG_THREADS) max_tile_kernel(const float *__re
 // mask, the tile's maxima bits are written as well (the maxima are exactly the
 // cells that are their own parent, above tau).
 //
-// One workgroup per WX x 8 x 8 tile (WX = 64 where n allows, else 32) keeps
+// One workgroup per WX x 8 x 8 tile (WX = 128 or 64 where n allows, else 32) keeps
 // the tile and a one-cell halo of the field in LDS as 32-bit order-preserving
 // bits (the index half of a key is formed in registers), and each thread walks
 // one z column of the tile: the largest key of each 3x3 halo plane around the
@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(WX * TY) parent_walk_kernel(const float *__res
     }
     __syncthreads();
     // the thread's column (x, y); a wavefront covers 64 consecutive x of one
-    // row (WX = 64) or rows y and y + 1 (WX = 32)
+    // row (WX >= 64) or rows y and y + 1 (WX = 32)
     const int x = threadIdx.x % WX, y = threadIdx.x / WX;
     const int lane = threadIdx.x & 63;
     uint32_t gx[3], gy[3];  // global x / y of the halo columns / rows x - 1 .. x + 1, y - 1 .. y + 1
@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(WX * TY) parent_walk_kernel(const float *__res
             const unsigned long long bits = __ballot(p == g && high);
             if (lane == 0) {
                 mask[g >> 5] = uint32_t(bits);
-                mask[(g + (WX == 64 ? 32u : un)) >> 5] = uint32_t(bits >> 32);
+                mask[(g + (WX >= 64 ? 32u : un)) >> 5] = uint32_t(bits >> 32);
             }
         }
         parent[g] = (p == g && !high) ? -1 : int32_t(p);
@@ -801,7 +801,11 @@ hf_status mask_to_list(hf_ctx *ctx, const MaximaLayout &L, char *w8, int32_t *ma
 // Parents (and the maxima mask when given) of a tiled grid.
 hf_status launch_parents(hf_ctx *ctx, int n, const float *cwt, float tau, int32_t *parent, uint32_t *mask) {
     const uint32_t tau_ord = host_ordered_bits(tau);
-    if (n % 64 == 0) {
+    if (n % 128 == 0) {
+        const TileGrid wg{n, n / 128, n / TY, n / TZ, FastDiv(uint32_t(n))};
+        HF_LAUNCH(ctx, K_PARENT, parent_walk_kernel<128>, dim3(wg.ntx * wg.nty * wg.ntz), dim3(128 * TY), 0,
+                  ctx->stream, cwt, wg, tau_ord, parent, mask, ctx->d_status);
+    } else if (n % 64 == 0) {
         const TileGrid wg{n, n / 64, n / TY, n / TZ, FastDiv(uint32_t(n))};
         HF_LAUNCH(ctx, K_PARENT, parent_walk_kernel<64>, dim3(wg.ntx * wg.nty * wg.ntz), dim3(64 * TY), 0,
                   ctx->stream, cwt, wg, tau_ord, parent, mask, ctx->d_status);
