@@ -259,10 +259,10 @@ def summarize_profiles(trace_dir: str, pmc_dir: str, workload: str, trace_cmd: s
     print(traffic_file(workload))
 
 
-def copy_calibration():
-    """A plain device copy of 4 GiB, for scaling FETCH_SIZE / WRITE_SIZE counters."""
+def copy_rate(nbytes: int = 4 << 30, reps: int = 5) -> dict:
+    """A plain device-to-device copy of `nbytes`: read + written bytes over the
+    average time of `reps` copies, the measured counterpart of the vendor HBM peak."""
     import torch
-    nbytes = 4 << 30
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     for _ in range(3):
@@ -270,13 +270,75 @@ def copy_calibration():
     torch.cuda.synchronize()
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s.record()
-    for _ in range(5):
+    for _ in range(reps):
         b.copy_(a)
     e.record()
     torch.cuda.synchronize()
-    ms = s.elapsed_time(e) / 5
-    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "ms": ms,
-                      "GBps": 2 * nbytes / ms / 1e6}))
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "ms": ms, "GBps": 2 * nbytes / ms / 1e6}
+
+
+def copy_calibration():
+    """A plain device copy of 4 GiB, for scaling FETCH_SIZE / WRITE_SIZE counters."""
+    print(json.dumps(copy_rate()))
+
+
+def h2d_rate(total_bytes: int, chunk_bytes: int = 1 << 30) -> dict:
+    """Host-to-device transfer of `total_bytes` (the positions) from pinned host
+    memory, in chunks of `chunk_bytes` into one device buffer."""
+    import torch
+    chunk = min(chunk_bytes, total_bytes)
+    host = torch.empty(chunk, dtype=torch.uint8, pin_memory=True)
+    host.fill_(1)
+    dev = torch.empty(chunk, dtype=torch.uint8, device="cuda")
+    dev.copy_(host, non_blocking=True)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    left = total_bytes
+    while left > 0:
+        k = min(chunk, left)
+        dev[:k].copy_(host[:k], non_blocking=True)
+        left -= k
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e)
+    del host, dev
+    torch.cuda.empty_cache()
+    return {"bytes": total_bytes, "ms": round(ms, 3), "GBps": round(total_bytes / ms / 1e6, 2),
+            "method": f"pinned host to device, {chunk >> 20} MiB chunks, one stream"}
+
+
+def host_info() -> dict:
+    model, mem_kb = None, None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    mem_kb = int(line.split()[1])
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "affinity_cpus": aff,
+            "ram_gib": round(mem_kb / 2**20, 1) if mem_kb else None}
+
+
+def fft_threads() -> int:
+    """Worker threads for the multi-threaded CPU FFT: the CPUs this process may
+    use, capped by OMP_NUM_THREADS where that is set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(n, 1)
 
 
 def cpu_baseline(seed: int) -> dict:
@@ -307,16 +369,39 @@ def cpu_baseline(seed: int) -> dict:
     O.label(pos, L, n, cell)
     t["label"] = time.perf_counter() - t0
     total = sum(t.values())
+    # the transform's two 3D FFTs again with scipy's multi-threaded pocketfft (not
+    # the oracle: a library timing of the FFT alone, the CWT stage's main cost)
+    import scipy.fft as sfft
+    workers = fft_threads()
+    f = O.normalise(rho)
+    t0 = time.perf_counter()
+    spec = sfft.rfftn(f, axes=(0, 1, 2), workers=workers)
+    sfft.irfftn(spec, s=f.shape, axes=(0, 1, 2), workers=workers)
+    fft_mt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    spec = np.fft.rfftn(f, axes=(0, 1, 2))
+    np.fft.irfftn(spec, s=f.shape, axes=(0, 1, 2))
+    fft_1 = time.perf_counter() - t0
     return {"value": np_ / total, "unit": "particles/s", "cores": 1, "kind": "oracle",
             "sample": f"same recipe at n={n}, L={L:g} Mpc/h, {np_} FP32 particles, {halos} halos, a=2 cells; "
-                      f"numpy single-threaded; host os.cpu_count()={os.cpu_count()}",
-            "stage_s": {k: round(v, 3) for k, v in t.items()}, "total_s": round(total, 3)}
+                      f"numpy single-threaded",
+            "stage_s": {k: round(v, 3) for k, v in t.items()}, "total_s": round(total, 3),
+            "fft_pair_s": {"numpy_1_thread": round(fft_1, 3), "scipy_threads": round(fft_mt, 3),
+                           "threads": workers,
+                           "what": f"rfftn + irfftn of the normalised {n}^3 FP64 grid"},
+            "host": host_info()}
 
 
-def serving_bench(n_jobs: int, budget_gb: float, n_streams: int, max_batch: int, load: float) -> dict:
+def serving_bench(n_jobs: int, budget_gb: float, n_streams: int, max_batch: int, load: float,
+                  sweep: list, big_budget_gb: float) -> dict:
     """Served (continuous batching) against the plain per-request loop on the
     serving workload: grid sizes 64..256, N_p = n^3 U[0.5, 2], scale U[1, 4]
-    cells; particles resident (8 pool boxes per size)."""
+    cells; particles resident (8 pool boxes per size).  Capacity with every
+    request waiting at t = 0; latency under Poisson arrivals at `load` times the
+    plain loop's capacity, then at each load of `sweep`; capacity and the
+    headline load once more with an HBM budget of `big_budget_gb`.  Each budget
+    has one server, whose buffer pool a full untimed pass fills first (steady
+    state, as a long-running server); it is released before the next budget."""
     import torch
     import synth
     from paper_2501_10622_amd.serve import Request, Server, plain_loop, summarize
@@ -330,30 +415,66 @@ def serving_bench(n_jobs: int, budget_gb: float, n_streams: int, max_batch: int,
     def requests(arrivals):
         return [Request(jb.job_id, jb.n, jb.box_len, jb.kw, pool[jb.box_seed], t) for jb, t in zip(jobs, arrivals)]
 
-    warm = requests([0.0] * min(len(jobs), 60))
-    plain_loop(warm)
-    Server(budget_bytes=int(budget_gb * (1 << 30)), n_streams=n_streams, max_batch=max_batch).run(warm)
-    # capacity: every request waiting at t = 0
+    def warm_server(gb):
+        srv = Server(budget_bytes=int(gb * (1 << 30)), n_streams=n_streams, max_batch=max_batch)
+        srv.run(requests([0.0] * len(jobs)))
+        return srv
+
+    r = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+    plain_loop(requests([0.0] * min(len(jobs), 60)))
     cap_plain = summarize(plain_loop(requests([0.0] * len(jobs))))
-    srv = Server(budget_bytes=int(budget_gb * (1 << 30)), n_streams=n_streams, max_batch=max_batch)
+    srv = warm_server(budget_gb)
     cap_served = summarize(srv.run(requests([0.0] * len(jobs))))
     groups = dict(srv.stats)
     log(f"serving capacity: plain {cap_plain['jobs_per_s']:.1f} jobs/s, served {cap_served['jobs_per_s']:.1f} jobs/s")
-    # latency under Poisson arrivals at `load` x the plain loop's capacity
-    rate = load * cap_plain["jobs_per_s"]
-    arr = synth.poisson_arrivals(len(jobs), rate, seed=5)
-    lat_plain = summarize(plain_loop(requests(arr)))
-    lat_served = summarize(Server(budget_bytes=int(budget_gb * (1 << 30)), n_streams=n_streams,
-                                  max_batch=max_batch).run(requests(arr)))
-    log(f"serving at {rate:.1f} jobs/s: p50/p99 plain {lat_plain['p50_ms']:.2f}/{lat_plain['p99_ms']:.2f} ms, "
-        f"served {lat_served['p50_ms']:.2f}/{lat_served['p99_ms']:.2f} ms")
-    r = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
-    return {"jobs": len(jobs), "pool_boxes": len(pool), "budget_gb": budget_gb, "streams": n_streams,
-            "max_batch": max_batch, "capacity": {"plain": r(cap_plain), "served": r(cap_served),
-                                                 "served_groups": groups},
-            "throughput_ratio": round(cap_served["jobs_per_s"] / cap_plain["jobs_per_s"], 3),
-            "poisson_rate_per_s": round(rate, 2), "load": load,
-            "latency": {"plain": r(lat_plain), "served": r(lat_served)}}
+
+    def at_load(ld, with_plain=True):
+        rate = ld * cap_plain["jobs_per_s"]
+        arr = synth.poisson_arrivals(len(jobs), rate, seed=5)
+        res = {"load": ld, "poisson_rate_per_s": round(rate, 2)}
+        if with_plain:
+            res["plain"] = r(summarize(plain_loop(requests(arr))))
+        res["served"] = r(summarize(srv.run(requests(arr))))
+        log(f"serving at load {ld:g} ({rate:.1f} jobs/s, budget {srv.budget / 2**30:g} GB): p50/p99 "
+            + (f"plain {res['plain']['p50_ms']:.2f}/{res['plain']['p99_ms']:.2f} ms, " if with_plain else "")
+            + f"served {res['served']['p50_ms']:.2f}/{res['served']['p99_ms']:.2f} ms")
+        return res
+
+    head = at_load(load)
+    out = {"jobs": len(jobs), "pool_boxes": len(pool), "budget_gb": budget_gb, "streams": n_streams,
+           "max_batch": max_batch, "capacity": {"plain": r(cap_plain), "served": r(cap_served),
+                                                "served_groups": groups},
+           "throughput_ratio": round(cap_served["jobs_per_s"] / cap_plain["jobs_per_s"], 3),
+           "poisson_rate_per_s": head["poisson_rate_per_s"], "load": load,
+           "latency": {"plain": head["plain"], "served": head["served"]}}
+    out["load_sweep"] = [at_load(ld) for ld in sweep]
+    del srv
+    torch.cuda.empty_cache()
+    if big_budget_gb > 0:
+        srv = warm_server(big_budget_gb)
+        cap_big = summarize(srv.run(requests([0.0] * len(jobs))))
+        log(f"serving capacity at budget {big_budget_gb:g} GB: {cap_big['jobs_per_s']:.1f} jobs/s")
+        out["big_budget"] = {"budget_gb": big_budget_gb, "capacity_served": r(cap_big),
+                             "served_groups": dict(srv.stats),
+                             "latency_served": at_load(load, with_plain=False)["served"]}
+        del srv
+        torch.cuda.empty_cache()
+    return out
+
+
+def cwt_summary(stages: dict, cells: int) -> dict:
+    """The five transform passes together, against the pencil-sweep byte model
+    (44.06 B/cell) and against the strict compulsory bound of reading the
+    density and writing the field (8 + 4 B/cell)."""
+    parts = [k for k in stages if k.startswith("cwt_")]
+    if not parts:
+        return {}
+    ms = sum(stages[k]["ms_per_step"] for k in parts)
+    model = sum(stages[k]["algorithmic_bytes"] for k in parts)
+    strict = 12 * cells
+    return {"ms_per_step": round(ms, 4), "model_bytes": model, "strict_bytes": strict,
+            "GBps_model": round(model / ms / 1e6, 1), "frac_model": round(model / ms / 1e6 / HBM_PEAK_GBS, 4),
+            "GBps_strict": round(strict / ms / 1e6, 1), "frac_strict": round(strict / ms / 1e6 / HBM_PEAK_GBS, 4)}
 
 
 def synth_n(config: str) -> int:
@@ -379,6 +500,8 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=16)
     ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-sweep", default="0.5,1.0,1.5", help="further loads for the latency sweep ('' skips)")
+    ap.add_argument("--serve-big-budget-gb", type=float, default=250.0, help="second HBM budget (0 skips)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -429,17 +552,23 @@ def main():
 
     # the headline: K steps as a caller runs them, the library's kernel timer off
     torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # (an event between steps, on the library's stream, gives each step's time)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    start, stop = evs[0], evs[-1]
     w0 = time.perf_counter()
     start.record()
     for i in range(args.steps):
         step()
-    stop.record()
+        evs[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ctx.sync()
     ms_step = start.elapsed_time(stop) / args.steps
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f})")
+    per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
+    ms_median = per_step[len(per_step) // 2] if len(per_step) % 2 else \
+        0.5 * (per_step[len(per_step) // 2 - 1] + per_step[len(per_step) // 2])
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, median {ms_median:.3f} "
+        f"(wall {1e3 * wall / args.steps:.3f})")
     # the breakdown: K more steps with the kernel timer (HIP events around every
     # launch, on the library's stream); its markers add a little to each step
     ctx.profile(True)
@@ -496,6 +625,8 @@ def main():
         "unit": "particles/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_median": round(ms_median, 4),
+        "ms_per_step_min_max": [round(per_step[0], 4), round(per_step[-1], 4)],
         "ms_per_step_with_kernel_timer": round(ms_step_timer, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
@@ -512,15 +643,27 @@ def main():
                      "traffic": traffic["bytes"] if traffic else None, "traffic_detail": traffic,
                      "traffic_source": os.path.relpath(traffic_file(tag), ROOT) if traffic else None},
         "stages": stages,
+        "cwt": cwt_summary(stages, cells),
         "kernels": kernels,
         "checks": {"mass_exact": mass_ok, "labelled_roots_are_maxima": roots_ok, "maxima": nmax},
     }
     del pos, bufs, rho, cell, buf
     torch.cuda.empty_cache()
+    cp = copy_rate()
+    out["hbm_copy_measured"] = {"GBps": round(cp["GBps"], 1), "frac_of_peak": round(cp["GBps"] / HBM_PEAK_GBS, 4),
+                                "what": "device copy of 4 GiB (read + write bytes / time), torch copy_"}
+    out["roofline"]["frac_of_measured_copy"] = round(d["GBps"] / cp["GBps"], 4)
+    out["e2e_frac_of_measured_copy"] = round(e2e_gbs / cp["GBps"], 4)
+    log(f"device copy {cp['GBps']:.0f} GB/s")
+    h2d = h2d_rate(pos_bytes * 3 * cfg.n_particles)
+    h2d["particles_per_s_including_h2d"] = cfg.n_particles / ((ms_step + h2d["ms"]) / 1e3)
+    out["h2d_positions"] = h2d
+    log(f"positions host to device: {h2d['ms']:.1f} ms ({h2d['GBps']:.1f} GB/s)")
     if args.serve_jobs > 0:
         log(f"serving: {args.serve_jobs} requests")
+        sweep = [float(x) for x in args.serve_sweep.split(",") if x.strip()]
         out["serving"] = serving_bench(args.serve_jobs, args.serve_budget_gb, args.serve_streams, args.serve_batch,
-                                       args.serve_load)
+                                       args.serve_load, sweep, args.serve_big_budget_gb)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(cfg.seed)
