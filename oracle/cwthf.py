@@ -14,6 +14,9 @@ one scale:
   step 5  segmentation by the maxima (Sec. 2.3)     -> ``segment``
   step 6  particles take their cell's label         -> ``label``
 
+and, after them, the group statistics of steps 5 and 7 with Table 1's
+thresholds dens_th and particle_th                  -> ``group_stats``
+
 Readings taken where the paper is silent are listed in the design notes and
 repeated at each function.  Everything here is deliberately unblocked and
 unfused; numpy's FFT is used as a library primitive for the periodic
@@ -29,7 +32,7 @@ __all__ = [
     "scale_w", "fixed_point", "deposit", "total_mass", "mean_mass", "normalise",
     "wavelet", "wavelet_hat", "sampled_kernel", "kernel_hat", "cwt_field", "cwt",
     "neighbour_offsets", "maxima", "parents", "segment", "ngp_nodes", "label",
-    "find_halos", "DepositOverflow",
+    "find_halos", "group_stats", "DepositOverflow",
 ]
 
 
@@ -307,6 +310,54 @@ def label(pos: np.ndarray, box_len: float, n: int, cell_label: np.ndarray,
           frac_bits: int = 15) -> np.ndarray:
     """Step 6: a particle gets the label (temporary ID) of its segmented cell."""
     return np.asarray(cell_label).ravel()[ngp_nodes(pos, box_len, n, frac_bits)]
+
+
+# --------------------------------------------------------------------------
+# steps 5 and 7: group volume, mass and density; Table 1 thresholds
+# --------------------------------------------------------------------------
+def group_stats(cell_label, particle_label, roots, n: int, np_total: int, dens_th: float = 4.0,
+                particle_th: int = 15) -> dict:
+    """Grid volume, particle number and density filter of every group.
+
+    Step 5 gives each segmented structure its grid volume: the cells that carry
+    its label, each of volume (L/n)^3.  Step 6 makes the particles of one label
+    a group; the particles have equal mass, so a group's mass is its particle
+    number.  Step 7 disposes of groups whose density is below dens_th times the
+    mean density of the whole box, N_p / L^3 (Table 1: dens_th = 4), and
+    Table 1's particle_th (15) is the minimum particle number.
+
+    Reading: the density test N_g / (V_g (L/n)^3) >= dens_th N_p / L^3 is,
+    with V_g counted in cells, N_g n^3 >= dens_th V_g N_p; it is decided in FP64
+    as float(N_g) * float(n^3) >= (dens_th * float(V_g)) * float(N_p).  A group
+    is kept if it passes that test and has at least particle_th particles.
+
+    ``roots`` is the sorted maxima list (the labels in use); the per-group
+    arrays are indexed like it.  Returns the particle number, the cell count and
+    the keep flag of every group, and both label arrays with the labels of
+    disposed groups replaced by -1.
+    """
+    roots = np.asarray(roots, dtype=np.int64).ravel()
+    cl = np.asarray(cell_label).ravel().astype(np.int64)
+    pl = np.asarray(particle_label).ravel().astype(np.int64)
+    ncell = n ** 3
+    # per root cell: cells and particles carrying that label
+    cells_at = np.bincount(cl[cl >= 0], minlength=ncell)
+    parts_at = np.bincount(pl[pl >= 0], minlength=ncell)
+    g_cells = cells_at[roots]
+    g_parts = parts_at[roots]
+    dense = g_parts.astype(np.float64) * float(ncell) >= (float(dens_th) * g_cells.astype(np.float64)) * float(np_total)
+    keep = dense & (g_parts >= particle_th)
+    keep_at = np.zeros(ncell, dtype=bool)
+    keep_at[roots[keep]] = True
+    new_pl = np.where(pl >= 0, np.where(keep_at[np.maximum(pl, 0)], pl, -1), -1)
+    new_cl = np.where(cl >= 0, np.where(keep_at[np.maximum(cl, 0)], cl, -1), -1)
+    return {
+        "particles": g_parts.astype(np.int64),
+        "cells": g_cells.astype(np.int64),
+        "keep": keep,
+        "particle_label": new_pl.astype(np.int32),
+        "cell_label": new_cl.astype(np.int32).reshape(np.shape(cell_label)),
+    }
 
 
 # --------------------------------------------------------------------------
