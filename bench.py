@@ -47,6 +47,9 @@ TIMER_SYMBOLS = {
     "parent": ("parent_walk_kernel", "parent_direct_kernel"), "resolve": ("resolve_tile_kernel",), "jump_flags": ("fill_flags_kernel",),
     "jump": ("bnd_jump_first_kernel", "bnd_jump_kernel", "jump_direct_kernel"), "finalize": ("seg_finalize_kernel", "finalize_direct_kernel"),
     "label_tiles": ("tile_label_kernel",), "label_level1": ("to_level1_kernel",), "label_input": ("to_input_kernel",),
+    "groups_clear": ("groups_clear_kernel",), "groups_cells": ("groups_cells_kernel",),
+    "groups_particles": ("groups_particles_kernel",), "groups_decide": ("groups_decide_kernel",),
+    "groups_filter": ("groups_filter_kernel",),
 }
 
 
@@ -477,6 +480,50 @@ def cwt_summary(stages: dict, cells: int) -> dict:
             "GBps_strict": round(strict / ms / 1e6, 1), "frac_strict": round(strict / ms / 1e6 / HBM_PEAK_GBS, 4)}
 
 
+def groups_bench(bufs: dict, n: int, np_: int, warmup: int, iters: int, ctx) -> dict:
+    """Group statistics and filters (steps 5 and 7, dens_th = 4, particle_th = 15)
+    on the step's own outputs: `warmup` untimed calls, then `iters` calls under
+    the library's kernel timer (so a trace of the run sees warmup + iters calls,
+    as many as the step's launches).  Algorithmic bytes: the cell labels read
+    for the volumes and again for the filter, which writes them (12 B/cell), and
+    the same for the particle labels (12 B/particle)."""
+    import torch
+    import paper_2501_10622_amd as hfm
+    nmax = int(bufs["count"].item())
+    roots, cl, pl = bufs["maxima"][:nmax], bufs["cell_label"], bufs["particle_label"][:np_]
+    for _ in range(warmup):
+        out = hfm.groups(cl, pl, roots, np_, 4.0, 15, ctx=ctx)
+    ctx.sync()
+    ctx.profile(True)
+    ctx.profile_reset()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(iters):
+        out = hfm.groups(cl, pl, roots, np_, 4.0, 15, ctx=ctx)
+    stop.record()
+    torch.cuda.synchronize()
+    ctx.sync()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ms = start.elapsed_time(stop) / iters
+    kernels = {k: {"ms_per_call": round(v[0] / iters, 4), "launches_per_call": v[1] // iters}
+               for k, v in prof.items() if k.startswith("groups_") and v[1]}
+    kernel_ms = sum(k["ms_per_call"] for k in kernels.values())
+    nbytes = 12 * n ** 3 + 12 * np_
+    keep = out["keep"].bool()
+    kept = int(keep.sum().item())
+    checks = {
+        "cells_sum_is_labelled_cells": int(out["cells"].long().sum().item()) == int((cl >= 0).sum().item()),
+        "particles_sum_is_labelled_particles": int(out["particles"].long().sum().item()) == int((pl >= 0).sum().item()),
+        "kept_particles": int(out["particles"].long()[keep].sum().item()) == int((out["particle_label"] >= 0).sum().item()),
+    }
+    log(f"groups: {ms:.3f} ms per call, {kept} of {nmax} groups kept")
+    return {"what": "group volume, particle number, density >= 4 x mean and >= 15 particles, labels filtered",
+            "ms_per_call": round(ms, 4), "kernels": kernels, "groups": nmax, "kept": kept,
+            "algorithmic_bytes": nbytes, "GBps": round(nbytes / kernel_ms / 1e6, 1),
+            "frac": round(nbytes / kernel_ms / 1e6 / HBM_PEAK_GBS, 4), "checks": checks}
+
+
 def synth_n(config: str) -> int:
     import synth
     return synth.CONFIGS[config].n
@@ -490,6 +537,7 @@ def main():
     ap.add_argument("--config", default="M4", choices=["M1", "M2", "M3", "M4"])
     ap.add_argument("--kernel", default="sampled", choices=["sampled", "analytic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-groups", action="store_true", help="skip the group statistics measurement")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--summarize-profiles", nargs=2, metavar=("TRACE_DIR", "PMC_DIR"),
                     help="write the committed summaries of a kernel trace and of the counter runs")
@@ -647,6 +695,8 @@ def main():
         "kernels": kernels,
         "checks": {"mass_exact": mass_ok, "labelled_roots_are_maxima": roots_ok, "maxima": nmax},
     }
+    if not args.no_groups:
+        out["groups"] = groups_bench(bufs, n, cfg.n_particles, args.warmup, 2 * args.steps, ctx)
     del pos, bufs, rho, cell, buf
     torch.cuda.empty_cache()
     cp = copy_rate()

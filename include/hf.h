@@ -9,6 +9,8 @@
  *   hf_maxima   step 4  local maxima of the grid CWT
  *   hf_segment  step 5  segmentation of the grid by the maxima (Sec. 2.3)
  *   hf_label    step 6  particles take the label of their segmented cell
+ *   hf_groups   steps 5 and 7  grid volume, particle number and density filter
+ *                       of every group (Table 1: dens_th, particle_th)
  *
  * Conventions shared by every call
  * --------------------------------
@@ -76,7 +78,7 @@ typedef struct {
  * hf_find_halos), a region that carries the deposit's particle order to the
  * label step: about 13 bytes per particle plus 8 per particle of label scratch. */
 enum { HF_STAGE_DEPOSIT = 1, HF_STAGE_CWT = 2, HF_STAGE_MAXIMA = 4, HF_STAGE_SEGMENT = 8, HF_STAGE_LABEL = 16,
-       HF_STAGE_ALL = 31 };
+       HF_STAGE_ALL = 31, HF_STAGE_GROUPS = 32 /* hf_groups; not part of HF_STAGE_ALL */ };
 
 typedef struct hf_ctx hf_ctx;
 
@@ -141,6 +143,37 @@ hf_status hf_segment(hf_ctx *ctx, const hf_box *box, const float *cwt, float tau
  * hf_deposit would reject get label -1 and set HF_ERR_INPUT. */
 hf_status hf_label(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np,
                    const int32_t *cell_label, int32_t *particle_label);
+
+/* Steps 5 and 7 with Table 1's thresholds: group statistics and filters.
+ * A group is the set of cells and particles carrying one label (a root of the
+ * segmentation).  For every root of roots[0..nroots) (the strictly increasing
+ * hf_maxima list whose labels cell_label and particle_label carry):
+ *   group_cells[i]      cells labelled roots[i] (the grid volume, step 5, in
+ *                       cells of volume (box_len/n)^3),
+ *   group_particles[i]  particles labelled roots[i] (the group's mass in
+ *                       particles, which have equal mass),
+ *   group_keep[i]       1 iff the group's density is at least dens_th times the
+ *                       box's mean density np / box_len^3 (step 7; Table 1:
+ *                       dens_th = 4) and it has at least particle_th particles
+ *                       (Table 1: particle_th = 15), else 0.  The density test
+ *                       is decided in FP64 as
+ *                       double(P) * n^3 >= (dens_th * double(V)) * double(np).
+ * cell_label_out [n^3] and particle_label_out [np] (either may be NULL, and
+ * either may be the corresponding input) receive the labels with those of
+ * disposed groups replaced by -1; with nroots == 0 every label becomes -1.
+ * np is the number of particles in the box (all of them, labelled or not),
+ * at most 2^32 - 1; particle_label may be NULL when np == 0.
+ * Errors: HF_ERR_ARG for a null required pointer, np or nroots out of range,
+ * a negative or non-finite dens_th or a negative particle_th; a label outside
+ * [-1, n^3) or a root outside [0, n^3) sets HF_ERR_INPUT (the label is
+ * treated as -1).  Labels >= 0 that are not among the roots give undefined
+ * statistics for themselves (never a memory fault).
+ * Workspace: HF_STAGE_GROUPS (8 bytes per cell; only the roots' entries are
+ * touched). */
+hf_status hf_groups(hf_ctx *ctx, const hf_box *box, int64_t np, const int32_t *roots, int64_t nroots,
+                    const int32_t *cell_label, const int32_t *particle_label, double dens_th,
+                    int64_t particle_th, uint32_t *group_particles, uint32_t *group_cells, uint8_t *group_keep,
+                    int32_t *cell_label_out, int32_t *particle_label_out, void *ws, size_t ws_bytes);
 
 /* Batched step 3 for serving: `count` (1..HF_CWT_BATCH_MAX) transforms of the
  * same grid size n, each with its own box length and scale, enqueued as one

@@ -1,9 +1,11 @@
 """MI355X-native single-scale hot path of the CWT halo finder (arXiv:2501.10622).
 
 Stages (HIP kernels in libhf.so, C ABI in include/hf.h): CIC deposit, grid CWT
-by FFT, 26-neighbour maxima, steepest-ascent segmentation, particle labels.
+by FFT, 26-neighbour maxima, steepest-ascent segmentation, particle labels, and
+the group statistics and density filter that follow them.
 """
 from .hf import (  # noqa: F401
     CWT_BATCH_MAX, EXPORTS, HFError, LIB_PATH, Context, context, cwt, cwt_batch, cwt_batch_ws_bytes, deposit,
-    find_halos, find_halos_async, find_halos_group_async, job_buffers, label, load_library, maxima, segment, status_str, sync, workspace_size,
+    find_halos, find_halos_async, find_halos_group_async, groups, job_buffers, label, load_library, maxima, segment,
+    status_str, sync, workspace_size,
 )

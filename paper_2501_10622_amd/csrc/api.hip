@@ -20,6 +20,7 @@ const char *hf::kernel_name(int id) {
         "maxima_mark", "maxima_count", "maxima_scan", "maxima_write",
         "parent", "jump_flags", "jump", "finalize",
         "label_tiles", "label_level1", "label_input", "resolve",
+        "groups_clear", "groups_cells", "groups_particles", "groups_decide", "groups_filter",
     };
     return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
@@ -163,7 +164,7 @@ extern "C" hf_status hf_workspace_size(const hf_box *box, int64_t np, int stage_
     if (!bytes || np < 0) return HF_ERR_ARG;
     hf_status s = check_box(box);
     if (s != HF_OK) return s;
-    if (stage_mask & ~HF_STAGE_ALL) return HF_ERR_ARG;
+    if (stage_mask & ~(HF_STAGE_ALL | HF_STAGE_GROUPS)) return HF_ERR_ARG;
     // deposit + label: the deposit's particle order is kept for the labels in
     // a region of its own in front of the part the stages share in turn
     const bool order = (stage_mask & HF_STAGE_DEPOSIT) && (stage_mask & HF_STAGE_LABEL) &&
@@ -175,6 +176,7 @@ extern "C" hf_status hf_workspace_size(const hf_box *box, int64_t np, int stage_
     if (stage_mask & HF_STAGE_MAXIMA) take(maxima_ws_bytes(*box));
     if (stage_mask & HF_STAGE_SEGMENT) take(segment_ws_bytes(*box));
     if ((stage_mask & HF_STAGE_MAXIMA) && (stage_mask & HF_STAGE_SEGMENT)) take(maxima_segment_ws_bytes(*box));
+    if (stage_mask & HF_STAGE_GROUPS) take(groups_ws_bytes(*box));
     if (order) take(label_scratch_bytes(np));
     *bytes = (order ? particle_order_bytes(*box, np) : 0) + need;
     return HF_OK;

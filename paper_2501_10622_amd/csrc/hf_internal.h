@@ -19,6 +19,7 @@ enum KernelId {
     K_MAX_MARK, K_MAX_COUNT, K_MAX_SCAN, K_MAX_WRITE,
     K_PARENT, K_FLAGS, K_JUMP, K_FINALIZE,
     K_LABEL_TILES, K_LABEL_LEVEL1, K_LABEL_INPUT, K_RESOLVE,
+    K_GROUP_CLEAR, K_GROUP_CELLS, K_GROUP_PARTICLES, K_GROUP_DECIDE, K_GROUP_FILTER,
     K_COUNT
 };
 const char *kernel_name(int id);
@@ -158,6 +159,7 @@ size_t deposit_ws_bytes(const hf_box &box, int64_t np);
 size_t cwt_ws_bytes(const hf_box &box);
 size_t maxima_ws_bytes(const hf_box &box);
 size_t segment_ws_bytes(const hf_box &box);
+size_t groups_ws_bytes(const hf_box &box);
 
 // ---------------------------------------------------------------------------
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.

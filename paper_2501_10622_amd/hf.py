@@ -24,9 +24,10 @@ STAGE_DEPOSIT, STAGE_CWT, STAGE_MAXIMA, STAGE_SEGMENT, STAGE_LABEL = 1, 2, 4, 8,
 EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_size",
            "hf_deposit", "hf_cwt", "hf_maxima", "hf_segment", "hf_label",
            "hf_profile_enable", "hf_profile_reset", "hf_profile_read",
-           "hf_cwt_batch_ws_size", "hf_cwt_batch", "hf_find_halos", "hf_find_halos_group")
+           "hf_cwt_batch_ws_size", "hf_cwt_batch", "hf_find_halos", "hf_find_halos_group", "hf_groups")
 CWT_BATCH_MAX = 32
 STAGE_ALL = 31
+STAGE_GROUPS = 32
 
 
 class HFError(RuntimeError):
@@ -93,6 +94,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "hf_find_halos": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job), vp, sz]),
             "hf_find_halos_group": (ctypes.c_int, [vp, i32, i32, i32, ctypes.POINTER(GroupItem), ctypes.c_int,
                                                    vp, sz]),
+            "hf_groups": (ctypes.c_int, [vp, bp, i64, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp, sz]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -309,6 +311,41 @@ def label(pos: torch.Tensor, box_len: float, n: int, cell_label: torch.Tensor, f
     b = box(n, box_len, frac_bits)
     _check(load_library().hf_label(ctx.handle, ctypes.byref(b), _ptr(pos), _dtype_code(pos), pos.shape[0],
                                    _ptr(cell_label), _ptr(out)), "hf_label")
+    return out
+
+
+def groups(cell_label: torch.Tensor, particle_label: torch.Tensor, roots: torch.Tensor, n_particles: int,
+           dens_th: float = 4.0, particle_th: int = 15, filter_cells: bool = True, filter_particles: bool = True,
+           ctx=None) -> dict:
+    """Steps 5 and 7 (Table 1's dens_th, particle_th): per-group cell and
+    particle numbers and keep flags for the sorted maxima list ``roots``, and
+    the labels with disposed groups set to -1 (new tensors).  The counts are
+    the library's uint32 values held in int32 tensors (below 2^31 for any box
+    of fewer than 2^31 particles)."""
+    _require_cuda(cell_label, "cell_label")
+    if cell_label.dtype != torch.int32 or cell_label.ndim != 3:
+        raise ValueError("cell_label must be an int32 [n, n, n] grid")
+    if particle_label.dtype != torch.int32 or roots.dtype != torch.int32:
+        raise ValueError("particle_label and roots must be int32")
+    n = cell_label.shape[0]
+    dev = cell_label.device
+    ctx = ctx or context(dev.index)
+    nroots = roots.numel()
+    out = {
+        "particles": torch.empty(max(nroots, 1), dtype=torch.int32, device=dev)[:nroots],
+        "cells": torch.empty(max(nroots, 1), dtype=torch.int32, device=dev)[:nroots],
+        "keep": torch.empty(max(nroots, 1), dtype=torch.uint8, device=dev)[:nroots],
+        "cell_label": torch.empty_like(cell_label) if filter_cells else None,
+        "particle_label": torch.empty_like(particle_label) if filter_particles else None,
+    }
+    b = box(n, 1.0)
+    need = workspace_size(n, 1.0, 0, STAGE_GROUPS)
+    ws = workspace(need, dev.index)
+    _check(load_library().hf_groups(ctx.handle, ctypes.byref(b), int(n_particles), _ptr(roots), int(nroots),
+                                    _ptr(cell_label), _ptr(particle_label), float(dens_th), int(particle_th),
+                                    _ptr(out["particles"]), _ptr(out["cells"]), _ptr(out["keep"]),
+                                    _ptr(out["cell_label"]), _ptr(out["particle_label"]), _ptr(ws), need),
+           "hf_groups")
     return out
 
 

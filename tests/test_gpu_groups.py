@@ -1,0 +1,173 @@
+"""GPU parity of the group statistics and filters (steps 5 and 7, Table 1's
+dens_th and particle_th) against the oracle, through the C ABI.
+
+Every output is integer (counts, keep flags, labels) and must be bit-exact.
+The labels fed to both sides come from the oracle's own single-scale pipeline
+or from seeded synthetic labellings, never from the GPU path.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import O, cuda, ensure_built, small_box
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    ensure_built()
+
+
+def hfm():
+    import paper_2501_10622_amd as m
+    return m
+
+
+def synthetic_labels(n, ngroups, np_, seed, unlabelled=0.2):
+    """Clustered labellings: groups own slabs of consecutive cells of random
+    lengths (so wavefronts see one or a few labels, as in a segmentation), a
+    root labels its own cell, and each particle picks a group with probability
+    proportional to its cells times a log-uniform density factor in
+    [1/4, 16], so that a few percent of the groups pass dens_th = 4; a tenth of
+    the particles stay unlabelled."""
+    rng = np.random.default_rng(seed)
+    ncell = n ** 3
+    roots = np.sort(rng.choice(ncell, size=ngroups, replace=False)).astype(np.int32)
+    cuts = np.sort(rng.choice(np.arange(1, ncell), size=ngroups - 1, replace=False)) if ngroups > 1 else []
+    owner = np.zeros(ncell, dtype=np.int64)
+    owner[np.asarray(cuts, dtype=np.int64)] = 1
+    owner = np.cumsum(owner)
+    label_of = roots[rng.permutation(ngroups)]
+    cl = label_of[owner]
+    cl = np.where(rng.random(ncell) < unlabelled, -1, cl).astype(np.int32)
+    cl[roots] = roots
+    if np_ == 0:
+        return roots, cl.reshape(n, n, n), np.zeros(0, np.int32)
+    cells = np.bincount(np.searchsorted(roots, cl[cl >= 0]), minlength=ngroups).astype(np.float64)
+    weight = cells * np.exp(rng.uniform(np.log(0.25), np.log(16.0), size=ngroups))
+    pl = roots[rng.choice(ngroups, size=np_, p=weight / weight.sum())]
+    pl = np.where(rng.random(np_) < 0.1, -1, pl).astype(np.int32)
+    return roots, cl.reshape(n, n, n), pl
+
+
+def run_gpu(cl, pl, roots, np_total, dens_th, pth):
+    out = hfm().groups(cuda(cl), cuda(pl), cuda(roots), np_total, dens_th, pth)
+    hfm().sync()
+    return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+
+
+def assert_same(got, want):
+    np.testing.assert_array_equal(got["particles"].astype(np.int64), want["particles"])
+    np.testing.assert_array_equal(got["cells"].astype(np.int64), want["cells"])
+    np.testing.assert_array_equal(got["keep"].astype(bool), want["keep"])
+    np.testing.assert_array_equal(got["particle_label"], want["particle_label"])
+    np.testing.assert_array_equal(got["cell_label"], want["cell_label"])
+
+
+@pytest.mark.parametrize("n,L,np_,halos,a,seed", [
+    (32, 40.0, 40000, 60, 1.5, 21),
+    (64, 100.0, 64 ** 3, 200, 2.0, 22),
+    (96, 96.0, 500000, 300, 1.0, 23),
+])
+@pytest.mark.parametrize("dens_th,pth", [(4.0, 15), (1.0, 0), (2.5, 40)])
+def test_groups_of_oracle_pipeline(n, L, np_, halos, a, seed, dens_th, pth):
+    pos = small_box(n, L, np_, halos, "f32", seed)
+    res = O.find_halos(pos, L, n, n / (1000.0 * a))
+    cl, pl, roots = res["cell_label"].astype(np.int32), res["particle_label"].astype(np.int32), res["maxima"]
+    roots = np.asarray(roots, dtype=np.int32)
+    print(f"groups n={n} np={np_} roots={len(roots)} dens_th={dens_th} particle_th={pth}", flush=True)
+    want = O.group_stats(cl, pl, roots, n, np_, dens_th, pth)
+    assert_same(run_gpu(cl, pl, roots, np_, dens_th, pth), want)
+
+
+@pytest.mark.parametrize("n,ngroups,np_,seed", [
+    (16, 7, 5000, 1), (48, 300, 200000, 2), (128, 20000, 3000001, 3), (256, 150000, 5000000, 4),
+    (512, 400000, 20000000, 5),
+])
+def test_groups_synthetic_labellings(n, ngroups, np_, seed):
+    roots, cl, pl = synthetic_labels(n, ngroups, np_, seed)
+    print(f"groups synthetic n={n} groups={ngroups} np={np_}", flush=True)
+    want = O.group_stats(cl, pl, roots, n, np_, 4.0, 15)
+    got = run_gpu(cl, pl, roots, np_, 4.0, 15)
+    assert_same(got, want)
+    assert 0 < want["keep"].sum() < len(roots) or n == 16
+
+
+def test_hand_worked_example_and_equality():
+    n = 8
+    cl = np.full(n ** 3, -1, dtype=np.int32)
+    cl[[5, 6, 13, 14]] = 5           # 4 cells
+    cl[100:180] = 100                # 80 cells
+    pl = np.array([5] * 20 + [100] * 30 + [-1] * 50, dtype=np.int32)
+    roots = np.array([5, 100], dtype=np.int32)
+    # group 5: 20 particles in 4 cells; mean 100 / 512 per cell; ratio 20 * 512 / (4 * 100) = 25.6
+    # group 100: 30 in 80 cells: ratio 30 * 512 / (80 * 100) = 1.92
+    for dens_th, keep in ((25.6, [True, False]), (25.600001, [False, False]), (1.92, [True, True]),
+                          (1.9200001, [True, False])):
+        want = O.group_stats(cl.reshape(n, n, n), pl, roots, n, 100, dens_th, 15)
+        assert want["keep"].tolist() == keep
+        assert_same(run_gpu(cl.reshape(n, n, n), pl, roots, 100, dens_th, 15), want)
+
+
+def test_no_groups_and_no_particles():
+    n = 16
+    cl = np.full((n, n, n), -1, dtype=np.int32)
+    got = run_gpu(cl, np.full(10, -1, np.int32), np.zeros(0, np.int32), 10, 4.0, 15)
+    assert got["particles"].size == 0 and (got["cell_label"] == -1).all() and (got["particle_label"] == -1).all()
+    roots, cl2, _ = synthetic_labels(n, 5, 0, 9)
+    want = O.group_stats(cl2, np.zeros(0, np.int32), roots, n, 0, 4.0, 0)
+    assert_same(run_gpu(cl2, np.zeros(0, np.int32), roots, 0, 4.0, 0), want)
+
+
+def test_in_place_outputs_and_repeat_calls():
+    # the C ABI allows the label outputs to be the inputs; the workspace keeps
+    # the first call's counters and must not leak them into the second
+    from paper_2501_10622_amd import hf
+    import ctypes
+    n = 32
+    roots, cl, pl = synthetic_labels(n, 50, 30000, 11)
+    want1 = O.group_stats(cl, pl, roots, n, 30000, 4.0, 15)
+    want2 = O.group_stats(want1["cell_label"], want1["particle_label"], roots, n, 30000, 4.0, 15)
+    dcl, dpl, droots = cuda(cl), cuda(pl), cuda(roots)
+    gp = torch.empty(len(roots), dtype=torch.int32, device="cuda")
+    gc = torch.empty_like(gp)
+    gk = torch.empty(len(roots), dtype=torch.uint8, device="cuda")
+    ctx = hfm().context(0)
+    b = hf.box(n, 1.0)
+    need = hf.workspace_size(n, 1.0, 0, hf.STAGE_GROUPS)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    p = hf._ptr
+    for want in (want1, want2):
+        code = hf.load_library().hf_groups(ctx.handle, ctypes.byref(b), 30000, p(droots), len(roots), p(dcl), p(dpl),
+                                           4.0, 15, p(gp), p(gc), p(gk), p(dcl), p(dpl), p(ws), need)
+        assert code == 0
+        ctx.sync()
+        np.testing.assert_array_equal(gp.cpu().numpy(), want["particles"])
+        np.testing.assert_array_equal(gc.cpu().numpy(), want["cells"])
+        np.testing.assert_array_equal(gk.cpu().numpy().astype(bool), want["keep"])
+        np.testing.assert_array_equal(dcl.cpu().numpy(), want["cell_label"])
+        np.testing.assert_array_equal(dpl.cpu().numpy(), want["particle_label"])
+    assert (want2["keep"] == want1["keep"]).all()
+
+
+def test_bad_labels_and_arguments():
+    from paper_2501_10622_amd import HFError, hf
+    n = 8
+    cl = np.full((n, n, n), -1, dtype=np.int32)
+    cl[0, 0, 0] = 0
+    cl[0, 0, 1] = n ** 3 + 5  # out of range: reported, treated as -1
+    pl = np.array([0, 0, -3], dtype=np.int32)  # -3 out of range
+    out = hfm().groups(cuda(cl), cuda(pl), cuda(np.array([0], np.int32)), 3, 1.0, 0)
+    with pytest.raises(HFError) as e:
+        hfm().sync()
+    assert e.value.code == hf.HF_ERR_INPUT
+    assert out["cells"].cpu().tolist() == [1] and out["particles"].cpu().tolist() == [2]
+    assert out["cell_label"].cpu().numpy().ravel()[1] == -1 and out["particle_label"].cpu().tolist()[2] == -1
+    hfm().sync()  # cleared
+    with pytest.raises(HFError) as e:
+        hfm().groups(cuda(cl), cuda(pl), cuda(np.array([0], np.int32)), 3, -1.0, 0)
+    assert e.value.code == hf.HF_ERR_ARG
+    with pytest.raises(HFError) as e:
+        hfm().groups(cuda(cl), cuda(pl), cuda(np.array([0], np.int32)), 3, float("nan"), 0)
+    assert e.value.code == hf.HF_ERR_ARG
