@@ -524,6 +524,70 @@ def groups_bench(bufs: dict, n: int, np_: int, warmup: int, iters: int, ctx) -> 
             "frac": round(nbytes / kernel_ms / 1e6 / HBM_PEAK_GBS, 4), "checks": checks}
 
 
+def filtered_bench(pos, box_len: float, n: int, kw: float, bufs: dict, warmup: int, steps: int, kernel: str, ctx,
+                   ms_plain: float) -> dict:
+    """The whole step with the group statistics and filters fused in
+    (hf_find_halos_filtered: particles counted in the deposit's tile order, the
+    filter applied on the way back to input order), timed like the headline,
+    and its cost over the plain step.  Its extra algorithmic bytes are the cell
+    labels read for the group volumes and read and written by the cell-label
+    filter (12 B/cell); the particle counts and filter ride on passes the step
+    makes anyway."""
+    import torch
+    import paper_2501_10622_amd as hfm
+    from paper_2501_10622_amd import hf
+    np_ = pos.shape[0]
+    cap = bufs["maxima"].numel()
+    dev = pos.device
+    bufs.pop("ws")  # the plain step's workspace makes room for the larger one
+    torch.cuda.empty_cache()
+    need = hf.workspace_size(n, 1.0, np_, hf.STAGE_ALL | hf.STAGE_GROUPS)
+    fb = dict(bufs)
+    fb.update(ws=torch.empty(need, dtype=torch.uint8, device=dev),
+              group_particles=torch.empty(cap, dtype=torch.int32, device=dev),
+              group_cells=torch.empty(cap, dtype=torch.int32, device=dev),
+              group_keep=torch.empty(cap, dtype=torch.uint8, device=dev),
+              cell_label_kept=torch.empty_like(bufs["cell_label"]))
+
+    def step():
+        hfm.find_halos_filtered_async(pos, box_len, n, kw, fb, 4.0, 15, kernel=kernel, ctx=ctx)
+
+    for _ in range(warmup):
+        step()
+    ctx.sync()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        step()
+    stop.record()
+    torch.cuda.synchronize()
+    ctx.sync()
+    ms = start.elapsed_time(stop) / steps
+    ctx.profile(True)
+    ctx.profile_reset()
+    for _ in range(steps):
+        step()
+    ctx.sync()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    kernels = {k: round(v[0] / steps, 4) for k, v in prof.items()
+               if v[1] and (k.startswith("groups_") or k.startswith("label_"))}
+    cnt = int(fb["count"].item())
+    keep = fb["group_keep"][:cnt].bool()
+    parts = fb["group_particles"][:cnt].long()
+    checks = {
+        "kept_particles_are_labelled": int(parts[keep].sum().item()) == int((fb["particle_label"][:np_] >= 0).sum().item()),
+        "cells_sum_is_labelled_cells": int(fb["group_cells"][:cnt].long().sum().item())
+        == int((fb["cell_label"] >= 0).sum().item()),
+    }
+    log(f"filtered step: {ms:.3f} ms ({ms - ms_plain:+.3f} over the plain step), {int(keep.sum())} of {cnt} groups kept")
+    return {"what": "steps 2-6 with the group statistics and filters of steps 5 and 7 fused in "
+                    "(dens_th = 4, particle_th = 15)",
+            "ms_per_step": round(ms, 4), "over_plain_ms": round(ms - ms_plain, 4),
+            "particles_per_s": np_ / (ms / 1e3), "extra_algorithmic_bytes": 12 * n ** 3,
+            "kernels_ms_per_step": kernels, "groups": cnt, "kept": int(keep.sum()), "checks": checks}
+
+
 def synth_n(config: str) -> int:
     import synth
     return synth.CONFIGS[config].n
@@ -697,6 +761,8 @@ def main():
     }
     if not args.no_groups:
         out["groups"] = groups_bench(bufs, n, cfg.n_particles, args.warmup, 2 * args.steps, ctx)
+        out["filtered_pipeline"] = filtered_bench(pos, L, n, kw, bufs, args.warmup, args.steps, args.kernel, ctx,
+                                                  ms_step)
     del pos, bufs, rho, cell, buf
     torch.cuda.empty_cache()
     cp = copy_rate()

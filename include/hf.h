@@ -218,6 +218,27 @@ typedef struct {
 } hf_job;
 hf_status hf_find_halos(hf_ctx *ctx, const hf_box *box, const hf_job *job, void *ws, size_t ws_bytes);
 
+/* Steps 2-6 as hf_find_halos, then steps 5 and 7 as hf_groups on its own
+ * results (the roots are job->max_idx[0 .. min(*d_count, max_cap))):
+ * job->cell_label keeps the segmentation, job->particle_label receives the
+ * labels AFTER the filter (disposed groups -> -1), gf->group_* [max_cap] are
+ * indexed like job->max_idx (entries past the count are not written), and
+ * gf->cell_label_kept [n^3] (may be NULL) receives the filtered cell labels.
+ * With the binned deposit each label's particles are counted in the deposit's
+ * tile order and the filter is applied on the way back to input order.
+ * job->np must be below 2^32.  Workspace:
+ * hf_workspace_size(box, np, HF_STAGE_ALL | HF_STAGE_GROUPS). */
+typedef struct {
+    double dens_th;            /* Table 1: 4 */
+    int64_t particle_th;       /* Table 1: 15 */
+    uint32_t *group_particles; /* [max_cap] */
+    uint32_t *group_cells;     /* [max_cap] */
+    uint8_t *group_keep;       /* [max_cap] */
+    int32_t *cell_label_kept;  /* [n^3] or NULL */
+} hf_group_filter;
+hf_status hf_find_halos_filtered(hf_ctx *ctx, const hf_box *box, const hf_job *job, const hf_group_filter *gf,
+                                 void *ws, size_t ws_bytes);
+
 /* Serving form of steps 2-6 for `count` (1..HF_CWT_BATCH_MAX) boxes of the same
  * grid size n: per-box deposits, ONE batched transform (hf_cwt_batch) for the
  * group, then per-box maxima, segmentation and labels, all on the context's

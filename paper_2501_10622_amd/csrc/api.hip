@@ -176,8 +176,11 @@ extern "C" hf_status hf_workspace_size(const hf_box *box, int64_t np, int stage_
     if (stage_mask & HF_STAGE_MAXIMA) take(maxima_ws_bytes(*box));
     if (stage_mask & HF_STAGE_SEGMENT) take(segment_ws_bytes(*box));
     if ((stage_mask & HF_STAGE_MAXIMA) && (stage_mask & HF_STAGE_SEGMENT)) take(maxima_segment_ws_bytes(*box));
-    if (stage_mask & HF_STAGE_GROUPS) take(groups_ws_bytes(*box));
     if (order) take(label_scratch_bytes(np));
-    *bytes = (order ? particle_order_bytes(*box, np) : 0) + need;
+    // the group counters live through step 6 when it runs through the kept
+    // order (hf_find_halos_filtered): then they get a region of their own
+    const bool groups_apart = order && (stage_mask & HF_STAGE_GROUPS);
+    if ((stage_mask & HF_STAGE_GROUPS) && !groups_apart) take(groups_ws_bytes(*box));
+    *bytes = (order ? particle_order_bytes(*box, np) : 0) + (groups_apart ? groups_ws_bytes(*box) : 0) + need;
     return HF_OK;
 }

@@ -715,10 +715,18 @@ __global__ void __launch_bounds__(ACC_THREADS) skirt_fold_kernel(const unsigned 
 // and its +x/+y/+z skirt go to LDS; record k takes the label of its nearest
 // node, lab2[k].  A tile-local node is ((q_local + 2^(B-1)) >> B) per axis,
 // at most one cell past the tile, which the skirt holds.
+//
+// With COUNT, each label's particles are also counted into parts[label] (the
+// group statistics of steps 5 and 7): a tile's records carry a few dozen
+// labels at most, counted in an LDS table and added to parts once per tile.
+// The record loop then runs whole sweeps on every thread, so that all lanes
+// take part in each wavefront step of the count.
+template <bool COUNT>
 __global__ void __launch_bounds__(ACC_THREADS) tile_label_kernel(const uint64_t *__restrict__ rec2,
                                                                  const uint32_t *__restrict__ start2, Geom g,
                                                                  const int32_t *__restrict__ cell_label,
-                                                                 int32_t *__restrict__ lab2) {
+                                                                 int32_t *__restrict__ lab2,
+                                                                 uint32_t *__restrict__ parts) {
     __shared__ int32_t lab[MAX_ACC_CELLS];
     const int slot = int(xcd_remap(blockIdx.x, gridDim.x));  // neighbouring tiles share skirt lines
     const int b = slot / g.digits, d = slot % g.digits;
@@ -742,23 +750,54 @@ __global__ void __launch_bounds__(ACC_THREADS) tile_label_kernel(const uint64_t 
     const uint64_t half = 1ull << (bits - 1);
     const uint32_t lo = start2[slot], hi = start2[slot + 1];
     constexpr int RB = 8;
-    for (uint32_t i0 = lo + threadIdx.x; i0 < hi; i0 += ACC_THREADS * RB) {
-        uint64_t rr[RB];
+    auto node_label = [&](uint64_t r) {
+        const int nx = int(((r & mx) + half) >> bits);
+        const int ny = int((((r >> sx) & my) + half) >> bits);
+        const int nz = int((((r >> (sx + sy)) & my) + half) >> bits);
+        return lab[(nz * AYZ + ny) * ax + nx];
+    };
+    if constexpr (!COUNT) {
+        for (uint32_t i0 = lo + threadIdx.x; i0 < hi; i0 += ACC_THREADS * RB) {
+            uint64_t rr[RB];
 #pragma unroll
-        for (int k = 0; k < RB; ++k) {
-            const uint32_t i = i0 + k * ACC_THREADS;
-            rr[k] = i < hi ? rec2[i] : 0ull;
-        }
+            for (int k = 0; k < RB; ++k) {
+                const uint32_t i = i0 + k * ACC_THREADS;
+                rr[k] = i < hi ? rec2[i] : 0ull;
+            }
 #pragma unroll
-        for (int k = 0; k < RB; ++k) {
-            const uint32_t i = i0 + k * ACC_THREADS;
-            if (i >= hi) break;
-            const uint64_t r = rr[k];
-            const int nx = int(((r & mx) + half) >> bits);
-            const int ny = int((((r >> sx) & my) + half) >> bits);
-            const int nz = int((((r >> (sx + sy)) & my) + half) >> bits);
-            lab2[i] = lab[(nz * AYZ + ny) * ax + nx];
+            for (int k = 0; k < RB; ++k) {
+                const uint32_t i = i0 + k * ACC_THREADS;
+                if (i >= hi) break;
+                lab2[i] = node_label(rr[k]);
+            }
         }
+    } else {
+        constexpr int HT = 256;
+        __shared__ int32_t hkey[HT];
+        __shared__ uint32_t hcnt[HT];
+        lds_tally_init<HT>(hkey, hcnt);
+        __syncthreads();
+        for (uint32_t b0 = lo; b0 < hi; b0 += ACC_THREADS * RB) {
+            const uint32_t i0 = b0 + threadIdx.x;
+            uint64_t rr[RB];
+#pragma unroll
+            for (int k = 0; k < RB; ++k) {
+                const uint32_t i = i0 + k * ACC_THREADS;
+                rr[k] = i < hi ? rec2[i] : 0ull;
+            }
+#pragma unroll
+            for (int k = 0; k < RB; ++k) {
+                const uint32_t i = i0 + k * ACC_THREADS;
+                int32_t l = -1;
+                if (i < hi) {
+                    l = node_label(rr[k]);
+                    lab2[i] = l;
+                }
+                lds_tally_wave<HT>(hkey, hcnt, parts, l);
+            }
+        }
+        __syncthreads();
+        lds_tally_flush<HT>(hkey, hcnt, parts);
     }
 }
 
@@ -806,9 +845,12 @@ __device__ void slot_dest(const uint16_t *off_s, int ndest, uint32_t *mark, uint
 // for the chunk's elements [e0, e1).  The chunk's runs are read into LDS in
 // staging order, consecutive lanes on consecutive slots of a run, so a
 // wavefront touches a few lines instead of one line per lane; element e then
-// takes the value at its staging position.  Rejected elements get -1.
+// takes the value at its staging position.  Rejected elements get -1.  With
+// keep, a label l >= 0 whose keep[l] is 0 becomes -1 (the group filter of
+// step 7; labels of a chunk's runs are few, so these reads stay in cache).
 __device__ void chunk_gather(const RunMaps &m, int64_t chunk, int ndest, int64_t e0, int64_t e1,
-                             const int32_t *__restrict__ src, int32_t *__restrict__ dst) {
+                             const int32_t *__restrict__ src, int32_t *__restrict__ dst,
+                             const uint32_t *__restrict__ keep = nullptr) {
     __shared__ uint32_t base_s[MAX_DIGITS];
     __shared__ uint16_t off_s[OFF_STRIDE];
     __shared__ int32_t val[CHUNK];
@@ -831,6 +873,7 @@ __device__ void chunk_gather(const RunMaps &m, int64_t chunk, int ndest, int64_t
         if (s < total) {
             const int d = dd[k];
             v[k] = src[base_s[d] + (s - off_s[d])];
+            if (keep && v[k] >= 0 && !keep[v[k]]) v[k] = -1;
         }
     }
 #pragma unroll
@@ -852,7 +895,8 @@ __global__ void __launch_bounds__(PART_THREADS) to_level1_kernel(RunMaps m2, con
                                                                  const uint32_t *__restrict__ chunk_first,
                                                                  int nbuckets, int digits,
                                                                  const int32_t *__restrict__ lab2,
-                                                                 int32_t *__restrict__ lab1) {
+                                                                 int32_t *__restrict__ lab1,
+                                                                 const uint32_t *__restrict__ keep) {
     const uint32_t w = xcd_remap(blockIdx.x, gridDim.x);  // as the level-2 scatter placed them
     if (w >= chunk_first[nbuckets]) return;
     int L = 0, R = nbuckets - 1;  // last b with chunk_first[b] <= w
@@ -865,7 +909,7 @@ __global__ void __launch_bounds__(PART_THREADS) to_level1_kernel(RunMaps m2, con
     const int64_t lo = int64_t(start1[b]) + int64_t(w - chunk_first[b]) * CHUNK;
     const int64_t end = start1[b + 1];
     const int64_t hi = lo + CHUNK < end ? lo + CHUNK : end;
-    chunk_gather(m2, w, digits, lo, hi, lab2, lab1);
+    chunk_gather(m2, w, digits, lo, hi, lab2, lab1, keep);
 }
 
 // Pass 3, input order: particle i -> lab1[level-1 slot of i], one workgroup
@@ -1141,23 +1185,42 @@ hf::ParticleOrder hf::particle_order_at(const hf_box &box, void *base, int64_t n
 
 size_t hf::label_scratch_bytes(int64_t np) { return 2 * align_up(sizeof(int32_t) * size_t(np)); }
 
-hf_status hf::label_from_order(hf_ctx *ctx, const hf_box &box, int64_t np, const ParticleOrder &order,
-                               const int32_t *cell_label, int32_t *particle_label, void *scratch) {
+hf_status hf::label_tiles(hf_ctx *ctx, const hf_box &box, int64_t np, const ParticleOrder &order,
+                          const int32_t *cell_label, void *scratch, uint32_t *parts) {
+    if (np <= 0) return HF_OK;
+    Geom g;
+    if (!make_geom(box, g)) return HF_ERR_SIZE;
+    auto *lab2 = static_cast<int32_t *>(scratch);
+    if (parts)
+        HF_LAUNCH(ctx, K_LABEL_TILES, tile_label_kernel<true>, dim3(g.ntiles), dim3(ACC_THREADS), 0, ctx->stream,
+                  order.rec2, order.start2, g, cell_label, lab2, parts);
+    else
+        HF_LAUNCH(ctx, K_LABEL_TILES, tile_label_kernel<false>, dim3(g.ntiles), dim3(ACC_THREADS), 0, ctx->stream,
+                  order.rec2, order.start2, g, cell_label, lab2, nullptr);
+    return launch_status();
+}
+
+hf_status hf::label_back(hf_ctx *ctx, const hf_box &box, int64_t np, const ParticleOrder &order,
+                         int32_t *particle_label, void *scratch, const uint32_t *keep) {
     if (np <= 0) return HF_OK;
     Geom g;
     if (!make_geom(box, g)) return HF_ERR_SIZE;
     auto *lab2 = static_cast<int32_t *>(scratch);
     auto *lab1 = reinterpret_cast<int32_t *>(static_cast<char *>(scratch) + align_up(sizeof(int32_t) * size_t(np)));
     const unsigned blocks = unsigned((np + CHUNK - 1) / CHUNK);
-    HF_LAUNCH(ctx, K_LABEL_TILES, tile_label_kernel, dim3(g.ntiles), dim3(ACC_THREADS), 0, ctx->stream, order.rec2,
-              order.start2, g, cell_label, lab2);
     // level-2 scatter chunks: at most one partial chunk per bucket beyond np / CHUNK
     RunMaps m1, m2;
     __builtin_memcpy(&m1, order.maps[0], sizeof(m1));
     __builtin_memcpy(&m2, order.maps[1], sizeof(m2));
     HF_LAUNCH(ctx, K_LABEL_LEVEL1, to_level1_kernel, dim3(blocks + unsigned(g.nbuckets)), dim3(PART_THREADS), 0,
-              ctx->stream, m2, order.start1, order.chunk_first, g.nbuckets, g.digits, lab2, lab1);
+              ctx->stream, m2, order.start1, order.chunk_first, g.nbuckets, g.digits, lab2, lab1, keep);
     HF_LAUNCH(ctx, K_LABEL_INPUT, to_input_kernel, dim3(replica_grid(blocks)), dim3(PART_THREADS), 0, ctx->stream,
               m1, np, g.nbuckets, lab1, particle_label);
     return launch_status();
+}
+
+hf_status hf::label_from_order(hf_ctx *ctx, const hf_box &box, int64_t np, const ParticleOrder &order,
+                               const int32_t *cell_label, int32_t *particle_label, void *scratch) {
+    hf_status s = label_tiles(ctx, box, np, order, cell_label, scratch, nullptr);
+    return s == HF_OK ? label_back(ctx, box, np, order, particle_label, scratch, nullptr) : s;
 }

@@ -11,36 +11,18 @@ namespace {
 constexpr int GB = 256;  // threads per workgroup
 constexpr int GPER = 4;  // elements per thread per sweep in the streaming passes
 
-// The per-group counters are two n^3 uint32 arrays of the workspace indexed by
-// the root's linear cell index, so a label addresses its group's counters
-// directly.  Only the entries of the listed roots are cleared, counted and
-// read; after the decision, cells[root] holds the keep flag (1 or 0).
-struct GroupCounters {
-    uint32_t *parts;
-    uint32_t *cells;
-};
-
-// Adds one per lane whose label l is >= 0 into ctr[l], with one atomic per
-// distinct label of the wavefront: labels of neighbouring cells mostly agree,
-// so a wavefront of one grid row usually issues one or two atomics.  Every
-// lane of the wavefront must call it (the loop is wavefront-uniform).
-__device__ __forceinline__ void wave_count(uint32_t *ctr, int32_t l) {
-    bool pending = l >= 0;
-    const int lane = int(__lane_id());
-    for (;;) {
-        const unsigned long long m = __ballot(pending);
-        if (m == 0) break;
-        const int leader = __ffsll((long long)m) - 1;
-        const int32_t ll = __shfl(l, leader, 64);
-        const bool mine = pending && l == ll;
-        const unsigned long long sm = __ballot(mine);
-        if (lane == leader) atomicAdd(ctr + ll, uint32_t(__popcll(sm)));
-        pending = pending && !mine;
-    }
+// Number of roots: min(*d_count, cap) when the count is on the device (the
+// maxima list of the one-call pipeline), else cap.
+__device__ __forceinline__ int64_t root_count(const int64_t *d_count, int64_t cap) {
+    if (!d_count) return cap;
+    const int64_t c = *d_count;
+    return c < cap ? c : cap;
 }
 
-__global__ void __launch_bounds__(GB) groups_clear_kernel(const int32_t *__restrict__ roots, int64_t nroots,
-                                                          int64_t ncells, GroupCounters g, uint32_t *status) {
+__global__ void __launch_bounds__(GB) groups_clear_kernel(const int32_t *__restrict__ roots, const int64_t *d_count,
+                                                          int64_t cap, int64_t ncells, GroupCounters g,
+                                                          uint32_t *status) {
+    const int64_t nroots = root_count(d_count, cap);
     bool bad = false;
     for (int64_t i = blockIdx.x * int64_t(GB) + threadIdx.x; i < nroots; i += int64_t(gridDim.x) * GB) {
         const int32_t r = roots[i];
@@ -54,19 +36,27 @@ __global__ void __launch_bounds__(GB) groups_clear_kernel(const int32_t *__restr
     if (bad) atomicOr(status, ST_INPUT);
 }
 
-// Step 5: the grid volume of every group, in cells.  Whole workgroups sweep
-// GB * GPER consecutive cells at a time, so every wavefront takes part in
-// every wave_count.
+// Step 5: the grid volume of every group, in cells.  One workgroup counts a
+// contiguous range of GCHUNK cells (a few grid rows, a few hundred labels) in
+// an LDS table and adds it to the counters once.
+constexpr int GCHUNK = 16384;
+constexpr int CELL_HT = 1024;
+
 __global__ void __launch_bounds__(GB) groups_cells_kernel(const int32_t *__restrict__ cell_label, int64_t ncells,
                                                           uint32_t *__restrict__ cells, uint32_t *status) {
+    __shared__ int32_t hkey[CELL_HT];
+    __shared__ uint32_t hcnt[CELL_HT];
+    lds_tally_init<CELL_HT>(hkey, hcnt);
+    __syncthreads();
     bool bad = false;
-    const int64_t sweep = int64_t(GB) * GPER;
-    for (int64_t base = blockIdx.x * sweep; base < ncells; base += int64_t(gridDim.x) * sweep) {
+    const int64_t c0 = int64_t(blockIdx.x) * GCHUNK;
+    const int64_t c1 = c0 + GCHUNK < ncells ? c0 + GCHUNK : ncells;
+    for (int64_t base = c0; base < c1; base += int64_t(GB) * GPER) {
         int32_t l[GPER];
 #pragma unroll
         for (int k = 0; k < GPER; ++k) {
             const int64_t i = base + k * GB + threadIdx.x;
-            l[k] = i < ncells ? cell_label[i] : -1;
+            l[k] = i < c1 ? cell_label[i] : -1;
         }
 #pragma unroll
         for (int k = 0; k < GPER; ++k) {
@@ -74,15 +64,16 @@ __global__ void __launch_bounds__(GB) groups_cells_kernel(const int32_t *__restr
                 bad = true;
                 l[k] = -1;
             }
-            wave_count(cells, l[k]);
+            lds_tally_wave<CELL_HT>(hkey, hcnt, cells, l[k]);
         }
     }
+    __syncthreads();
+    lds_tally_flush<CELL_HT>(hkey, hcnt, cells);
     if (bad) atomicOr(status, ST_INPUT);
 }
 
-// Step 6 groups: the particle number of every group.  Particle labels come in
-// input order, where neighbouring lanes rarely share a group, so every
-// labelled particle adds with its own atomic.
+// Step 6 groups from labels in input order, where neighbouring lanes rarely
+// share a group: every labelled particle adds with its own atomic.
 __global__ void __launch_bounds__(GB) groups_particles_kernel(const int32_t *__restrict__ plabel, int64_t np,
                                                               int64_t ncells, uint32_t *__restrict__ parts,
                                                               uint32_t *status) {
@@ -109,12 +100,13 @@ __global__ void __launch_bounds__(GB) groups_particles_kernel(const int32_t *__r
 // (L/n)^3) and N_g >= particle_th.  Decided in FP64 as
 // double(N_g) * n^3 >= (dens_th * double(V_g)) * N_p (products only, so no
 // contraction changes the rounding).
-__global__ void __launch_bounds__(GB) groups_decide_kernel(const int32_t *__restrict__ roots, int64_t nroots,
-                                                           int64_t ncells, GroupCounters g, double dens_th,
-                                                           double np_total, int64_t particle_th,
+__global__ void __launch_bounds__(GB) groups_decide_kernel(const int32_t *__restrict__ roots, const int64_t *d_count,
+                                                           int64_t cap, int64_t ncells, GroupCounters g,
+                                                           double dens_th, double np_total, int64_t particle_th,
                                                            uint32_t *__restrict__ out_parts,
                                                            uint32_t *__restrict__ out_cells,
                                                            uint8_t *__restrict__ out_keep) {
+    const int64_t nroots = root_count(d_count, cap);
     for (int64_t i = blockIdx.x * int64_t(GB) + threadIdx.x; i < nroots; i += int64_t(gridDim.x) * GB) {
         const int32_t r = roots[i];
         if (r < 0 || r >= ncells) {  // reported by the clear pass
@@ -167,11 +159,53 @@ unsigned grid_of(const hf_ctx *ctx, int64_t work, int64_t per_block) {
     return unsigned(want < 1 ? 1 : (want > cap ? cap : want));
 }
 
+int64_t cells_of(const hf_box &box) { return int64_t(box.n) * box.n * box.n; }
+
 }  // namespace
 
-size_t hf::groups_ws_bytes(const hf_box &box) {
-    const size_t cells = size_t(box.n) * size_t(box.n) * size_t(box.n);
-    return 2 * align_up(cells * sizeof(uint32_t));
+size_t hf::groups_ws_bytes(const hf_box &box) { return 2 * align_up(size_t(cells_of(box)) * sizeof(uint32_t)); }
+
+GroupCounters hf::group_counters_at(const hf_box &box, void *region) {
+    unsigned char *base = static_cast<unsigned char *>(region);
+    return GroupCounters{reinterpret_cast<uint32_t *>(base),
+                         reinterpret_cast<uint32_t *>(base + align_up(size_t(cells_of(box)) * sizeof(uint32_t)))};
+}
+
+hf_status hf::groups_count_cells(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count,
+                                 int64_t cap, const int32_t *cell_label, const GroupCounters &g) {
+    const int64_t ncells = cells_of(box);
+    if (cap <= 0) return HF_OK;
+    HF_LAUNCH(ctx, K_GROUP_CLEAR, groups_clear_kernel, dim3(grid_of(ctx, cap, GB)), dim3(GB), 0, ctx->stream, roots,
+              d_count, cap, ncells, g, ctx->d_status);
+    HF_LAUNCH(ctx, K_GROUP_CELLS, groups_cells_kernel, dim3(unsigned((ncells + GCHUNK - 1) / GCHUNK)), dim3(GB), 0,
+              ctx->stream, cell_label, ncells, g.cells, ctx->d_status);
+    return launch_status();
+}
+
+hf_status hf::groups_count_particles(hf_ctx *ctx, const hf_box &box, const int32_t *particle_label, int64_t np,
+                                     const GroupCounters &g) {
+    if (np <= 0) return HF_OK;
+    HF_LAUNCH(ctx, K_GROUP_PARTICLES, groups_particles_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0,
+              ctx->stream, particle_label, np, cells_of(box), g.parts, ctx->d_status);
+    return launch_status();
+}
+
+hf_status hf::groups_decide(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count, int64_t cap,
+                            const GroupCounters &g, double dens_th, int64_t np, int64_t particle_th,
+                            uint32_t *group_particles, uint32_t *group_cells, uint8_t *group_keep) {
+    if (cap <= 0) return HF_OK;
+    HF_LAUNCH(ctx, K_GROUP_DECIDE, groups_decide_kernel, dim3(grid_of(ctx, cap, GB)), dim3(GB), 0, ctx->stream, roots,
+              d_count, cap, cells_of(box), g, dens_th, double(np), particle_th, group_particles, group_cells,
+              group_keep);
+    return launch_status();
+}
+
+hf_status hf::groups_filter(hf_ctx *ctx, const hf_box &box, const int32_t *in, int32_t *out, int64_t count,
+                            const GroupCounters &g, bool any_roots) {
+    if (count <= 0 || !out) return HF_OK;
+    HF_LAUNCH(ctx, K_GROUP_FILTER, groups_filter_kernel, dim3(grid_of(ctx, count, GB * GPER)), dim3(GB), 0,
+              ctx->stream, in, out, count, cells_of(box), g.cells, any_roots ? 1 : 0, ctx->d_status);
+    return launch_status();
 }
 
 extern "C" hf_status hf_groups(hf_ctx *ctx, const hf_box *box, int64_t np, const int32_t *roots, int64_t nroots,
@@ -182,7 +216,7 @@ extern "C" hf_status hf_groups(hf_ctx *ctx, const hf_box *box, int64_t np, const
     if (!ctx || !cell_label) return HF_ERR_ARG;
     hf_status s = check_box(box);
     if (s != HF_OK) return s;
-    const int64_t ncells = int64_t(box->n) * box->n * box->n;
+    const int64_t ncells = cells_of(*box);
     if (np < 0 || np > int64_t(UINT32_MAX) || nroots < 0 || nroots > ncells) return HF_ERR_ARG;
     if (!(dens_th >= 0.0) || !(dens_th < 1e300) || particle_th < 0) return HF_ERR_ARG;
     if (np > 0 && !particle_label) return HF_ERR_ARG;
@@ -190,27 +224,16 @@ extern "C" hf_status hf_groups(hf_ctx *ctx, const hf_box *box, int64_t np, const
     s = check_ws(ws, ws_bytes, groups_ws_bytes(*box));
     if (s != HF_OK) return s;
     if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
-    const hipStream_t st = ctx->stream;
-    unsigned char *base = static_cast<unsigned char *>(ws);
-    GroupCounters g{reinterpret_cast<uint32_t *>(base),
-                    reinterpret_cast<uint32_t *>(base + align_up(size_t(ncells) * sizeof(uint32_t)))};
+    const GroupCounters g = group_counters_at(*box, ws);
     if (nroots > 0) {
-        HF_LAUNCH(ctx, K_GROUP_CLEAR, groups_clear_kernel, dim3(grid_of(ctx, nroots, GB)), dim3(GB), 0, st, roots,
-                  nroots, ncells, g, ctx->d_status);
-        HF_LAUNCH(ctx, K_GROUP_CELLS, groups_cells_kernel, dim3(grid_of(ctx, ncells, GB * GPER)), dim3(GB), 0, st,
-                  cell_label, ncells, g.cells, ctx->d_status);
-        if (np > 0)
-            HF_LAUNCH(ctx, K_GROUP_PARTICLES, groups_particles_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0,
-                      st, particle_label, np, ncells, g.parts, ctx->d_status);
-        HF_LAUNCH(ctx, K_GROUP_DECIDE, groups_decide_kernel, dim3(grid_of(ctx, nroots, GB)), dim3(GB), 0, st, roots,
-                  nroots, ncells, g, dens_th, double(np), particle_th, group_particles, group_cells, group_keep);
+        s = groups_count_cells(ctx, *box, roots, nullptr, nroots, cell_label, g);
+        if (s == HF_OK) s = groups_count_particles(ctx, *box, particle_label, np, g);
+        if (s == HF_OK)
+            s = groups_decide(ctx, *box, roots, nullptr, nroots, g, dens_th, np, particle_th, group_particles,
+                              group_cells, group_keep);
+        if (s != HF_OK) return s;
     }
-    const int any = nroots > 0 ? 1 : 0;
-    if (cell_label_out)
-        HF_LAUNCH(ctx, K_GROUP_FILTER, groups_filter_kernel, dim3(grid_of(ctx, ncells, GB * GPER)), dim3(GB), 0, st,
-                  cell_label, cell_label_out, ncells, ncells, g.cells, any, ctx->d_status);
-    if (particle_label_out && np > 0)
-        HF_LAUNCH(ctx, K_GROUP_FILTER, groups_filter_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0, st,
-                  particle_label, particle_label_out, np, ncells, g.cells, any, ctx->d_status);
-    return launch_status();
+    s = groups_filter(ctx, *box, cell_label, cell_label_out, ncells, g, nroots > 0);
+    if (s == HF_OK) s = groups_filter(ctx, *box, particle_label, particle_label_out, np, g, nroots > 0);
+    return s;
 }

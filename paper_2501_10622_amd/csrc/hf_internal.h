@@ -154,6 +154,38 @@ size_t maxima_segment_ws_bytes(const hf_box &box);
 hf_status maxima_segment(hf_ctx *ctx, const hf_box &box, const float *cwt, float tau, int32_t *max_idx,
                          int64_t max_cap, int64_t *d_count, int32_t *cell_label, void *ws, size_t ws_bytes);
 
+// Group statistics (steps 5 and 7): per-root counters in two n^3 uint32 arrays
+// indexed by the root's cell (only the listed roots' entries are touched);
+// after the decision cells[root] holds the keep flag.  groups_ws_bytes(box).
+struct GroupCounters {
+    uint32_t *parts;
+    uint32_t *cells;
+};
+GroupCounters group_counters_at(const hf_box &box, void *region);
+// Clears the counters of roots[0, min(*d_count, cap)) (all cap with d_count
+// null) and counts every group's cells.
+hf_status groups_count_cells(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count,
+                             int64_t cap, const int32_t *cell_label, const GroupCounters &g);
+// Counts particle labels in input order (one atomic per labelled particle).
+hf_status groups_count_particles(hf_ctx *ctx, const hf_box &box, const int32_t *particle_label, int64_t np,
+                                 const GroupCounters &g);
+// Decides every group and writes the per-group outputs; then, where given,
+// the filtered cell labels.
+hf_status groups_decide(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count, int64_t cap,
+                        const GroupCounters &g, double dens_th, int64_t np, int64_t particle_th,
+                        uint32_t *group_particles, uint32_t *group_cells, uint8_t *group_keep);
+hf_status groups_filter(hf_ctx *ctx, const hf_box &box, const int32_t *in, int32_t *out, int64_t count,
+                        const GroupCounters &g, bool any_roots);
+
+// Step 6 through a kept particle order in its two halves: the tile pass
+// (counting each label's particles into parts when given) and the two passes
+// back to input order (labels of groups whose keep flag is 0 become -1 when
+// keep is given).  label_from_order is the two in turn.
+hf_status label_tiles(hf_ctx *ctx, const hf_box &box, int64_t np, const ParticleOrder &order,
+                      const int32_t *cell_label, void *scratch, uint32_t *parts);
+hf_status label_back(hf_ctx *ctx, const hf_box &box, int64_t np, const ParticleOrder &order,
+                     int32_t *particle_label, void *scratch, const uint32_t *keep);
+
 // Workspace requirements of each stage (defined next to each stage).
 size_t deposit_ws_bytes(const hf_box &box, int64_t np);
 size_t cwt_ws_bytes(const hf_box &box);
@@ -173,6 +205,58 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
     const uint32_t q = G / NUM_XCD, r = G % NUM_XCD;
     const uint32_t x = b % NUM_XCD, k = b / NUM_XCD;
     return x * q + (x < r ? x : r) + k;
+}
+
+// ---------------------------------------------------------------------------
+// Counting labels per workgroup in an LDS hash table of HT (a power of two)
+// slots of (label, count), keys -1 when empty, linear probing; a label that
+// finds the table full adds to ctr[label] directly.  lds_tally_wave first
+// merges the lanes that share the first pending lane's label with one ballot
+// round (the commonest case: a run of one label), then adds the other lanes'
+// labels one by one.  Every lane of the wavefront must call it; labels below 0
+// are not counted.  After a barrier, lds_tally_flush adds the table to ctr.
+// ---------------------------------------------------------------------------
+template <int HT>
+__device__ __forceinline__ void lds_tally_add(int32_t *hkey, uint32_t *hcnt, uint32_t *ctr, int32_t l, uint32_t c) {
+    static_assert((HT & (HT - 1)) == 0 && HT >= 2, "power-of-two table");
+    constexpr int BITS = __builtin_ctz(unsigned(HT));
+    uint32_t h = (uint32_t(l) * 2654435761u) >> (32 - BITS);  // Knuth's multiplicative hash, top bits
+    for (int probe = 0; probe < HT; ++probe) {
+        int32_t k = hkey[h];
+        if (k == -1) k = atomicCAS(hkey + h, -1, l);  // -1 back: this lane took the slot
+        if (k == -1 || k == l) {
+            atomicAdd(hcnt + h, c);
+            return;
+        }
+        h = (h + 1) & uint32_t(HT - 1);
+    }
+    atomicAdd(ctr + l, c);
+}
+
+template <int HT>
+__device__ __forceinline__ void lds_tally_wave(int32_t *hkey, uint32_t *hcnt, uint32_t *ctr, int32_t l) {
+    const unsigned long long m = __ballot(l >= 0);
+    if (m == 0) return;
+    const int leader = __ffsll((long long)m) - 1;
+    const int32_t ll = __shfl(l, leader, 64);
+    const bool mine = l >= 0 && l == ll;
+    const uint32_t c = uint32_t(__popcll(__ballot(mine)));
+    if (int(__lane_id()) == leader) lds_tally_add<HT>(hkey, hcnt, ctr, ll, c);
+    if (l >= 0 && !mine) lds_tally_add<HT>(hkey, hcnt, ctr, l, 1u);
+}
+
+template <int HT>
+__device__ __forceinline__ void lds_tally_init(int32_t *hkey, uint32_t *hcnt) {
+    for (int s = threadIdx.x; s < HT; s += blockDim.x) {
+        hkey[s] = -1;
+        hcnt[s] = 0u;
+    }
+}
+
+template <int HT>
+__device__ __forceinline__ void lds_tally_flush(const int32_t *hkey, const uint32_t *hcnt, uint32_t *ctr) {
+    for (int s = threadIdx.x; s < HT; s += blockDim.x)
+        if (hkey[s] >= 0 && hcnt[s]) atomicAdd(ctr + hkey[s], hcnt[s]);
 }
 
 // ---------------------------------------------------------------------------

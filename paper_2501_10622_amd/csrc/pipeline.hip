@@ -44,6 +44,83 @@ extern "C" hf_status hf_find_halos(hf_ctx *ctx, const hf_box *box, const hf_job 
     return hf_label(ctx, box, job->pos, job->dtype, job->np, job->cell_label, job->particle_label);
 }
 
+// Steps 2-6 as hf_find_halos, then the group statistics and filters of steps 5
+// and 7.  Through the kept particle order, step 6 counts each label's particles
+// in tile order and its pass back to input order drops the disposed groups;
+// otherwise the labels are counted and filtered in input order.
+extern "C" hf_status hf_find_halos_filtered(hf_ctx *ctx, const hf_box *box, const hf_job *job,
+                                           const hf_group_filter *gf, void *ws, size_t ws_bytes) {
+    if (!ctx || !job || !gf) return HF_ERR_ARG;
+    hf_status s = check_box(box);
+    if (s != HF_OK) return s;
+    const int64_t ncells = int64_t(box->n) * box->n * box->n;
+    if (!(gf->dens_th >= 0.0) || !(gf->dens_th < 1e300) || gf->particle_th < 0 || job->np > int64_t(UINT32_MAX))
+        return HF_ERR_ARG;
+    if (job->max_cap > 0 && (!gf->group_particles || !gf->group_cells || !gf->group_keep)) return HF_ERR_ARG;
+    if (job->max_cap > ncells) return HF_ERR_ARG;
+    size_t need = 0;
+    s = hf_workspace_size(box, job->np, HF_STAGE_ALL | HF_STAGE_GROUPS, &need);
+    if (s != HF_OK) return s;
+    s = check_ws(ws, ws_bytes, need);
+    if (s != HF_OK) return s;
+    if (!job->rho || !job->cwt || !job->d_count || !job->cell_label || job->np < 0 || job->max_cap < 0 ||
+        (job->max_cap > 0 && !job->max_idx) || (job->np > 0 && (!job->pos || !job->particle_label)) ||
+        (job->dtype != HF_F32 && job->dtype != HF_F64) ||
+        (job->kernel != HF_KERNEL_SAMPLED && job->kernel != HF_KERNEL_ANALYTIC) || !(job->kw > 0.0) ||
+        job->tau != job->tau)
+        return HF_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    const bool order = particle_order_supported(*box, job->np);
+    char *sw = static_cast<char *>(ws);
+    size_t sb = ws_bytes;
+    ParticleOrder po{};
+    GroupCounters g{};
+    if (order) {
+        po = particle_order_at(*box, ws, job->np);
+        sw += particle_order_bytes(*box, job->np);
+        sb -= particle_order_bytes(*box, job->np);
+        g = group_counters_at(*box, sw);
+        sw += groups_ws_bytes(*box);
+        sb -= groups_ws_bytes(*box);
+        s = deposit_tiled(ctx, *box, job->pos, job->dtype, job->np, job->rho, sw, &po);
+    } else {
+        s = hf_deposit(ctx, box, job->pos, job->dtype, job->np, job->rho, sw, sb);
+    }
+    if (s != HF_OK) return s;
+    s = hf_cwt(ctx, box, job->rho, job->kw, job->kernel, job->cwt, sw, sb);
+    if (s != HF_OK) return s;
+    s = maxima_segment(ctx, *box, job->cwt, job->tau, job->max_idx, job->max_cap, job->d_count, job->cell_label, sw,
+                       sb);
+    if (s != HF_OK) return s;
+    const int64_t cap = job->max_cap;
+    if (order) {
+        s = groups_count_cells(ctx, *box, job->max_idx, job->d_count, cap, job->cell_label, g);
+        if (s == HF_OK) s = label_tiles(ctx, *box, job->np, po, job->cell_label, sw, cap > 0 ? g.parts : nullptr);
+        if (s == HF_OK)
+            s = groups_decide(ctx, *box, job->max_idx, job->d_count, cap, g, gf->dens_th, job->np, gf->particle_th,
+                              gf->group_particles, gf->group_cells, gf->group_keep);
+        if (s == HF_OK && cap > 0) s = label_back(ctx, *box, job->np, po, job->particle_label, sw, g.cells);
+        if (s == HF_OK && cap == 0) {
+            s = label_back(ctx, *box, job->np, po, job->particle_label, sw, nullptr);
+            if (s == HF_OK) s = groups_filter(ctx, *box, job->particle_label, job->particle_label, job->np, g, false);
+        }
+    } else {
+        // the shared region is free again once the segmentation is done
+        g = group_counters_at(*box, sw);
+        s = hf_label(ctx, box, job->pos, job->dtype, job->np, job->cell_label, job->particle_label);
+        if (s == HF_OK) s = groups_count_cells(ctx, *box, job->max_idx, job->d_count, cap, job->cell_label, g);
+        if (s == HF_OK && cap > 0) s = groups_count_particles(ctx, *box, job->particle_label, job->np, g);
+        if (s == HF_OK)
+            s = groups_decide(ctx, *box, job->max_idx, job->d_count, cap, g, gf->dens_th, job->np, gf->particle_th,
+                              gf->group_particles, gf->group_cells, gf->group_keep);
+        if (s == HF_OK)
+            s = groups_filter(ctx, *box, job->particle_label, job->particle_label, job->np, g, cap > 0);
+    }
+    if (s == HF_OK && gf->cell_label_kept)
+        s = groups_filter(ctx, *box, job->cell_label, gf->cell_label_kept, ncells, g, cap > 0);
+    return s;
+}
+
 // A group of same-n boxes: per-box deposits, one batched transform for all of
 // them, then per-box maxima, segmentation and labels, in that order on the
 // context's stream.

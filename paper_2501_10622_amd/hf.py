@@ -24,7 +24,8 @@ STAGE_DEPOSIT, STAGE_CWT, STAGE_MAXIMA, STAGE_SEGMENT, STAGE_LABEL = 1, 2, 4, 8,
 EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_size",
            "hf_deposit", "hf_cwt", "hf_maxima", "hf_segment", "hf_label",
            "hf_profile_enable", "hf_profile_reset", "hf_profile_read",
-           "hf_cwt_batch_ws_size", "hf_cwt_batch", "hf_find_halos", "hf_find_halos_group", "hf_groups")
+           "hf_cwt_batch_ws_size", "hf_cwt_batch", "hf_find_halos", "hf_find_halos_group", "hf_groups",
+           "hf_find_halos_filtered")
 CWT_BATCH_MAX = 32
 STAGE_ALL = 31
 STAGE_GROUPS = 32
@@ -51,6 +52,12 @@ class Job(ctypes.Structure):
                 ("rho", ctypes.c_void_p), ("cwt", ctypes.c_void_p), ("max_idx", ctypes.c_void_p),
                 ("max_cap", ctypes.c_int64), ("d_count", ctypes.c_void_p), ("cell_label", ctypes.c_void_p),
                 ("particle_label", ctypes.c_void_p)]
+
+
+class GroupFilter(ctypes.Structure):
+    _fields_ = [("dens_th", ctypes.c_double), ("particle_th", ctypes.c_int64), ("group_particles", ctypes.c_void_p),
+                ("group_cells", ctypes.c_void_p), ("group_keep", ctypes.c_void_p),
+                ("cell_label_kept", ctypes.c_void_p)]
 
 
 class GroupItem(ctypes.Structure):
@@ -95,6 +102,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "hf_find_halos_group": (ctypes.c_int, [vp, i32, i32, i32, ctypes.POINTER(GroupItem), ctypes.c_int,
                                                    vp, sz]),
             "hf_groups": (ctypes.c_int, [vp, bp, i64, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp, sz]),
+            "hf_find_halos_filtered": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job), ctypes.POINTER(GroupFilter), vp,
+                                                      sz]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -378,12 +387,24 @@ def cwt_batch(rhos, box_lens, kws, kernel: str = "sampled", outs=None, ws=None, 
     return outs
 
 
-def job_buffers(n: int, np_: int, device, with_cwt_ws: bool = True, frac_bits: int = 15) -> dict:
-    """Output and workspace tensors for one box (allocated on the current stream)."""
+def job_buffers(n: int, np_: int, device, with_cwt_ws: bool = True, frac_bits: int = 15,
+                with_groups: bool = False) -> dict:
+    """Output and workspace tensors for one box (allocated on the current stream);
+    with_groups adds the group outputs and workspace of find_halos_filtered_async."""
     stages = STAGE_ALL if with_cwt_ws else (STAGE_DEPOSIT | STAGE_MAXIMA | STAGE_SEGMENT)
+    if with_groups:
+        stages |= STAGE_GROUPS
     need = workspace_size(n, 1.0, np_, stages, frac_bits)
     cap = ((n + 1) // 2) ** 3
-    return {
+    extra = {}
+    if with_groups:
+        extra = {
+            "group_particles": torch.empty(cap, dtype=torch.int32, device=device),
+            "group_cells": torch.empty(cap, dtype=torch.int32, device=device),
+            "group_keep": torch.empty(cap, dtype=torch.uint8, device=device),
+            "cell_label_kept": torch.empty((n, n, n), dtype=torch.int32, device=device),
+        }
+    return extra | {
         "rho": torch.empty((n, n, n), dtype=torch.int64, device=device),
         "cwt": torch.empty((n, n, n), dtype=torch.float32, device=device),
         "maxima": torch.empty(cap, dtype=torch.int32, device=device),
@@ -403,6 +424,24 @@ def find_halos_async(pos: torch.Tensor, box_len: float, n: int, kw: float, bufs:
     job = _job_struct(pos, kw, bufs, tau, kernel)
     _check(load_library().hf_find_halos(ctx.handle, ctypes.byref(b), ctypes.byref(job), _ptr(bufs["ws"]),
                                         bufs["ws"].numel()), "hf_find_halos")
+
+
+def find_halos_filtered_async(pos: torch.Tensor, box_len: float, n: int, kw: float, bufs: dict,
+                              dens_th: float = 4.0, particle_th: int = 15, frac_bits: int = 15, tau: float = 0.0,
+                              kernel: str = "sampled", ctx=None):
+    """Enqueue steps 2-6 and the group statistics and filters of steps 5 and 7
+    (bufs from job_buffers(..., with_groups=True)); bufs["particle_label"]
+    receives the labels after the filter, bufs["cell_label"] the segmentation
+    and bufs["cell_label_kept"] the filtered cell labels."""
+    _require_cuda(pos, "pos")
+    ctx = ctx or context(pos.device.index)
+    b = box(n, box_len, frac_bits)
+    job = _job_struct(pos, kw, bufs, tau, kernel)
+    gf = GroupFilter(float(dens_th), int(particle_th), bufs["group_particles"].data_ptr(),
+                     bufs["group_cells"].data_ptr(), bufs["group_keep"].data_ptr(),
+                     bufs["cell_label_kept"].data_ptr())
+    _check(load_library().hf_find_halos_filtered(ctx.handle, ctypes.byref(b), ctypes.byref(job), ctypes.byref(gf),
+                                                 _ptr(bufs["ws"]), bufs["ws"].numel()), "hf_find_halos_filtered")
 
 
 def cwt_batch_ws_bytes(n: int, count: int) -> int:
