@@ -846,11 +846,12 @@ __device__ void slot_dest(const uint16_t *off_s, int ndest, uint32_t *mark, uint
 // staging order, consecutive lanes on consecutive slots of a run, so a
 // wavefront touches a few lines instead of one line per lane; element e then
 // takes the value at its staging position.  Rejected elements get -1.  With
-// keep, a label l >= 0 whose keep[l] is 0 becomes -1 (the group filter of
+// FILTER, a label l >= 0 whose keep[l] is 0 becomes -1 (the group filter of
 // step 7; labels of a chunk's runs are few, so these reads stay in cache).
+template <bool FILTER>
 __device__ void chunk_gather(const RunMaps &m, int64_t chunk, int ndest, int64_t e0, int64_t e1,
                              const int32_t *__restrict__ src, int32_t *__restrict__ dst,
-                             const uint32_t *__restrict__ keep = nullptr) {
+                             const uint32_t *__restrict__ keep) {
     __shared__ uint32_t base_s[MAX_DIGITS];
     __shared__ uint16_t off_s[OFF_STRIDE];
     __shared__ int32_t val[CHUNK];
@@ -873,7 +874,7 @@ __device__ void chunk_gather(const RunMaps &m, int64_t chunk, int ndest, int64_t
         if (s < total) {
             const int d = dd[k];
             v[k] = src[base_s[d] + (s - off_s[d])];
-            if (keep && v[k] >= 0 && !keep[v[k]]) v[k] = -1;
+            if (FILTER && v[k] >= 0 && !keep[v[k]]) v[k] = -1;
         }
     }
 #pragma unroll
@@ -890,7 +891,9 @@ __device__ void chunk_gather(const RunMaps &m, int64_t chunk, int ndest, int64_t
 }
 
 // Pass 2, level-1 order: lab1[j] = lab2[level-2 slot of record j], one
-// workgroup per level-2 scatter chunk (CHUNK records of one bucket).
+// workgroup per level-2 scatter chunk (CHUNK records of one bucket); with
+// FILTER, labels of disposed groups (keep[label] == 0) become -1.
+template <bool FILTER>
 __global__ void __launch_bounds__(PART_THREADS) to_level1_kernel(RunMaps m2, const uint32_t *__restrict__ start1,
                                                                  const uint32_t *__restrict__ chunk_first,
                                                                  int nbuckets, int digits,
@@ -909,7 +912,7 @@ __global__ void __launch_bounds__(PART_THREADS) to_level1_kernel(RunMaps m2, con
     const int64_t lo = int64_t(start1[b]) + int64_t(w - chunk_first[b]) * CHUNK;
     const int64_t end = start1[b + 1];
     const int64_t hi = lo + CHUNK < end ? lo + CHUNK : end;
-    chunk_gather(m2, w, digits, lo, hi, lab2, lab1, keep);
+    chunk_gather<FILTER>(m2, w, digits, lo, hi, lab2, lab1, keep);
 }
 
 // Pass 3, input order: particle i -> lab1[level-1 slot of i], one workgroup
@@ -923,7 +926,7 @@ __global__ void __launch_bounds__(PART_THREADS) to_input_kernel(RunMaps m1, int6
     if (chunk < 0) return;
     const int64_t e0 = chunk * CHUNK;
     const int64_t e1 = e0 + CHUNK < np ? e0 + CHUNK : np;
-    chunk_gather(m1, chunk, nbuckets, e0, e1, lab1, out);
+    chunk_gather<false>(m1, chunk, nbuckets, e0, e1, lab1, out, nullptr);
 }
 
 // ---------------------------------------------------------------- host side
@@ -1212,8 +1215,14 @@ hf_status hf::label_back(hf_ctx *ctx, const hf_box &box, int64_t np, const Parti
     RunMaps m1, m2;
     __builtin_memcpy(&m1, order.maps[0], sizeof(m1));
     __builtin_memcpy(&m2, order.maps[1], sizeof(m2));
-    HF_LAUNCH(ctx, K_LABEL_LEVEL1, to_level1_kernel, dim3(blocks + unsigned(g.nbuckets)), dim3(PART_THREADS), 0,
-              ctx->stream, m2, order.start1, order.chunk_first, g.nbuckets, g.digits, lab2, lab1, keep);
+    if (keep)
+        HF_LAUNCH(ctx, K_LABEL_LEVEL1, to_level1_kernel<true>, dim3(blocks + unsigned(g.nbuckets)),
+                  dim3(PART_THREADS), 0, ctx->stream, m2, order.start1, order.chunk_first, g.nbuckets, g.digits, lab2,
+                  lab1, keep);
+    else
+        HF_LAUNCH(ctx, K_LABEL_LEVEL1, to_level1_kernel<false>, dim3(blocks + unsigned(g.nbuckets)),
+                  dim3(PART_THREADS), 0, ctx->stream, m2, order.start1, order.chunk_first, g.nbuckets, g.digits, lab2,
+                  lab1, nullptr);
     HF_LAUNCH(ctx, K_LABEL_INPUT, to_input_kernel, dim3(replica_grid(blocks)), dim3(PART_THREADS), 0, ctx->stream,
               m1, np, g.nbuckets, lab1, particle_label);
     return launch_status();
