@@ -262,8 +262,10 @@ def test_end_to_end(n, L, np_, halos, dtype, a, seed):
 ])
 def test_labels_through_deposit_order(n, L, np_, halos, a, seed, bits):
     """The one-call pipeline labels particles through the deposit's binned order;
-    its labels must equal the separate label stage's and the oracle's on the
-    same cell labels, bit for bit, including wrapped, edge and rejected positions."""
+    its labels must equal the separate label stage's on the same cell labels,
+    bit for bit, including wrapped, edge and rejected positions, and the
+    separate label stage must equal the oracle's on a seeded labelling of the
+    grid that both sides are given (no oracle input comes from the GPU)."""
     from paper_2501_10622_amd import hf
     from paper_2501_10622_amd.hf import HFError
     pos = small_box(n, L, np_, halos, "f32", seed)
@@ -290,8 +292,12 @@ def test_labels_through_deposit_order(n, L, np_, halos, a, seed, bits):
     g = got.cpu().numpy()
     assert g[11] == -1  # ... and its particle gets no label
     ok = np.isfinite(pos).all(axis=1)
-    ref = O.label(pos[ok], L, n, cell.cpu().numpy(), frac_bits=bits)
-    np.testing.assert_array_equal(g[ok], ref)
+    synth_cells = np.random.default_rng(seed).integers(-1, n ** 3, size=(n, n, n), dtype=np.int64).astype(np.int32)
+    on_synth = hf.label(d, L, n, cuda(synth_cells), frac_bits=bits, ctx=ctx)
+    with pytest.raises(HFError):  # the NaN position again
+        ctx.sync()
+    np.testing.assert_array_equal(on_synth.cpu().numpy()[ok], O.label(pos[ok], L, n, synth_cells, frac_bits=bits))
+    assert on_synth.cpu().numpy()[11] == -1
     # the one-call pipeline finds maxima and segments in one pass over the
     # field: same results as the separate stages on its own CWT
     cnt = int(bufs["count"].item())
