@@ -287,15 +287,17 @@ __global__ void __launch_bounds__(MAX_DIGITS) l1_scan_kernel(const uint32_t *__r
 
 // Persistent: workgroup w takes the logical blocks w, w + G, w + 2G, ... of
 // the replica mapping (G = gridDim.x, a multiple of NUM_XCD, so they all stay
-// on one XCD).  The positions of its next chunk are loaded into registers
-// while the current chunk is staged and written out.
+// on one XCD).  Software-pipelined over two sets of bucket counts, offsets and
+// cursor bases: while chunk c is written out from LDS, the positions of chunk
+// c + 1 are converted, counted and scanned and its cursor atomics issued, so
+// their latency hides behind c's stores; c + 1 is then staged without waiting.
 template <typename T>
 __global__ void __launch_bounds__(PART_THREADS) l1_scatter_kernel(const T *__restrict__ pos, int64_t np,
                                                                   FixedPoint<T> fp, Geom g, uint32_t *cursor1,
                                                                   Q3 *__restrict__ rec1, RunMaps maps) {
     __shared__ Q3 stage[CHUNK];
     __shared__ uint16_t sbk[CHUNK];
-    __shared__ uint32_t h[MAX_DIGITS], off[MAX_DIGITS], gbase[MAX_DIGITS], tmp[MAX_DIGITS];
+    __shared__ uint32_t h[2][MAX_DIGITS], off[2][MAX_DIGITS], gbase[2][MAX_DIGITS], tmp[MAX_DIGITS];
     static_assert(PART_PER == LBATCH, "one batch per scatter chunk");
     const uint32_t nchunks = uint32_t((np + CHUNK - 1) / CHUNK);
     const uint32_t logical = replica_grid(nchunks);
@@ -308,59 +310,76 @@ __global__ void __launch_bounds__(PART_THREADS) l1_scatter_kernel(const T *__res
     };
     uint32_t L = blockIdx.x;
     int64_t chunk = next_chunk(L);
+    if (chunk < 0) return;  // the same for the whole workgroup
     RawBatch<T> raw;
-    if (chunk >= 0) load_raw(pos, chunk * CHUNK + threadIdx.x, PART_THREADS, np, raw);
-    while (chunk >= 0) {
-        L += gridDim.x;
-        const int64_t nxt = next_chunk(L);
-        const int64_t base = chunk * CHUNK;
-        Q3 q[PART_PER];
+    Q3 q[PART_PER];
+    int bk[PART_PER];
+    uint32_t rank[PART_PER];
+    for (int b = threadIdx.x; b < MAX_DIGITS; b += blockDim.x) {
+        h[0][b] = 0u;
+        h[1][b] = 0u;
+    }
+    load_raw(pos, chunk * CHUNK + threadIdx.x, PART_THREADS, np, raw);
+    __syncthreads();
+    // chunk c from raw into set j (h[j] zeroed): bucket and rank of every
+    // element, offsets, and the cursor bases (returned into gbase[j] later)
+    auto prepare = [&](int64_t c, int j) -> uint32_t {
         bool ok[PART_PER];
         bool bad = false;  // reported by the histogram pass
-        convert_raw(raw, base + threadIdx.x, PART_THREADS, np, fp, q, ok, bad);
-        __syncthreads();  // the previous chunk is written out
-        for (int b = threadIdx.x; b < MAX_DIGITS; b += blockDim.x) h[b] = 0u;
-        __syncthreads();
-        int bk[PART_PER];
-        uint32_t rank[PART_PER];
+        convert_raw(raw, c * CHUNK + threadIdx.x, PART_THREADS, np, fp, q, ok, bad);
 #pragma unroll
         for (int k = 0; k < PART_PER; ++k) {
             bk[k] = -1;
             if (ok[k]) {
                 bk[k] = bucket_of(g, q[k].x >> g.bits, q[k].y >> g.bits, q[k].z >> g.bits);
-                rank[k] = atomicAdd(&h[bk[k]], 1u);
+                rank[k] = atomicAdd(&h[j][bk[k]], 1u);
             }
         }
         __syncthreads();
-        for (int b = threadIdx.x; b < g.nbuckets; b += blockDim.x) off[b] = h[b];
+        for (int b = threadIdx.x; b < g.nbuckets; b += blockDim.x) off[j][b] = h[j][b];
         __syncthreads();
-        const uint32_t total = block_exclusive_scan(off, tmp, g.nbuckets);
-        // the histogram pass counted this chunk under replica (chunk / HIST_CHUNKS) % REPLICAS
-        uint32_t *mine = cursor1 + ((chunk / HIST_CHUNKS) % REPLICAS) * MAX_DIGITS;
+        const uint32_t total = block_exclusive_scan(off[j], tmp, g.nbuckets);
+        // the histogram pass counted this chunk under replica (c / HIST_CHUNKS) % REPLICAS
+        uint32_t *mine = cursor1 + ((c / HIST_CHUNKS) % REPLICAS) * MAX_DIGITS;
         for (int b = threadIdx.x; b < g.nbuckets; b += blockDim.x)
-            if (h[b]) gbase[b] = atomicAdd(&mine[b], h[b]);
+            if (h[j][b]) gbase[j][b] = atomicAdd(&mine[b], h[j][b]);
+        return total;
+    };
+    uint32_t total = prepare(chunk, 0);
+    int j = 0;
+    for (;;) {
+        L += gridDim.x;
+        const int64_t nxt = next_chunk(L);
+        const int64_t base = chunk * CHUNK;
 #pragma unroll
         for (int k = 0; k < PART_PER; ++k)
             if (bk[k] >= 0) {
-                const uint32_t s = off[bk[k]] + rank[k];
+                const uint32_t s = off[j][bk[k]] + rank[k];
                 stage[s] = q[k];
                 sbk[s] = uint16_t(bk[k]);
             }
-        __syncthreads();
-        if (nxt >= 0) load_raw(pos, nxt * CHUNK + threadIdx.x, PART_THREADS, np, raw);
-        for (uint32_t s = threadIdx.x; s < total; s += PART_THREADS) {
-            const int b = sbk[s];
-            rec1[gbase[b] + (s - off[b])] = stage[s];
-        }
         if (maps.pos) {
-            save_run_table(maps, chunk, g.nbuckets, h, off, gbase, total);
 #pragma unroll
             for (int k = 0; k < PART_PER; ++k) {
                 const int64_t i = base + k * PART_THREADS + threadIdx.x;
-                if (i < np) maps.pos[i] = bk[k] >= 0 ? uint16_t(off[bk[k]] + rank[k]) : NO_POS;
+                if (i < np) maps.pos[i] = bk[k] >= 0 ? uint16_t(off[j][bk[k]] + rank[k]) : NO_POS;
             }
         }
+        __syncthreads();  // staged, and gbase[j] is in
+        if (nxt >= 0) load_raw(pos, nxt * CHUNK + threadIdx.x, PART_THREADS, np, raw);
+        for (uint32_t s = threadIdx.x; s < total; s += PART_THREADS) {
+            const int b = sbk[s];
+            rec1[gbase[j][b] + (s - off[j][b])] = stage[s];
+        }
+        if (maps.pos) save_run_table(maps, chunk, g.nbuckets, h[j], off[j], gbase[j], total);
+        if (nxt < 0) break;
+        // set j ^ 1 was last read by the previous chunk's write-out, which every
+        // thread finished before the barrier above
+        for (int b = threadIdx.x; b < MAX_DIGITS; b += blockDim.x) h[j ^ 1][b] = 0u;
+        __syncthreads();
+        total = prepare(nxt, j ^ 1);
         chunk = nxt;
+        j ^= 1;
     }
 }
 
