@@ -524,6 +524,40 @@ def groups_bench(bufs: dict, n: int, np_: int, warmup: int, iters: int, ctx) -> 
             "frac": round(nbytes / kernel_ms / 1e6 / HBM_PEAK_GBS, 4), "checks": checks}
 
 
+def scales_bench(rho, box_len: float, n: int, kernel: str, iters: int, ctx) -> dict:
+    """The transform of the step's density at three scales (a = 1, 2 and 4 cells),
+    once with one forward transform for all of them (hf_cwt_scales) and once as
+    three separate hf_cwt calls; `iters` timed repetitions of each after one
+    untimed one.  The shared form skips two of the three forward x and y passes."""
+    import torch
+    import paper_2501_10622_amd as hfm
+    kws = [n / (1000.0 * a) for a in (1.0, 2.0, 4.0)]
+    outs = [torch.empty_like(rho, dtype=torch.float32) for _ in kws]
+    ws_multi = torch.empty(hfm.cwt_batch_ws_bytes(n, len(kws)), dtype=torch.uint8, device=rho.device)
+
+    def timed(fn):
+        fn()
+        ctx.sync()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(iters):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        ctx.sync()
+        return s.elapsed_time(e) / iters
+
+    ms_multi = timed(lambda: hfm.cwt_scales(rho, box_len, kws, kernel, outs=outs, ws=ws_multi, ctx=ctx))
+    first = [o.clone() for o in outs]
+    ms_sep = timed(lambda: [hfm.cwt(rho, box_len, kw, kernel, out=o, ctx=ctx) for kw, o in zip(kws, outs)])
+    same = all(bool(torch.equal(a, b)) for a, b in zip(first, outs))
+    del ws_multi, outs, first
+    torch.cuda.empty_cache()
+    log(f"three scales: {ms_multi:.3f} ms with one forward transform, {ms_sep:.3f} ms as three transforms")
+    return {"scales_cells": [1.0, 2.0, 4.0], "ms_shared_forward": round(ms_multi, 4), "ms_separate": round(ms_sep, 4),
+            "saved_ms": round(ms_sep - ms_multi, 4), "identical_fields": same}
+
+
 def filtered_bench(pos, box_len: float, n: int, kw: float, bufs: dict, warmup: int, steps: int, kernel: str, ctx,
                    ms_plain: float) -> dict:
     """The whole step with the group statistics and filters fused in
@@ -760,6 +794,7 @@ def main():
         "checks": {"mass_exact": mass_ok, "labelled_roots_are_maxima": roots_ok, "maxima": nmax},
     }
     if not args.no_groups:
+        out["cwt_scales"] = scales_bench(bufs["rho"], L, n, args.kernel, 3, ctx)
         out["groups"] = groups_bench(bufs, n, cfg.n_particles, args.warmup, 2 * args.steps, ctx)
         out["filtered_pipeline"] = filtered_bench(pos, L, n, kw, bufs, args.warmup, args.steps, args.kernel, ctx,
                                                   ms_step)

@@ -6,6 +6,7 @@
  *
  *   hf_deposit  step 2  cloud-in-cell mass on a periodic n^3 grid, Eq. (1)
  *   hf_cwt      step 3  grid CWT with the Mexican-hat wavelet, Eqs. (2)-(4)
+ *               (hf_cwt_batch: several grids; hf_cwt_scales: several scales)
  *   hf_maxima   step 4  local maxima of the grid CWT
  *   hf_segment  step 5  segmentation of the grid by the maxima (Sec. 2.3)
  *   hf_label    step 6  particles take the label of their segmented cell
@@ -189,6 +190,17 @@ typedef struct {
     double kw;
 } hf_cwt_item;
 hf_status hf_cwt_batch_ws_size(int32_t n, int32_t count, size_t *bytes);
+
+/* Step 3 at `count` (1..HF_CWT_BATCH_MAX) scales of one density grid (the
+ * identification loop of Sec. 2 visits one scale after another, step 1):
+ * the forward transform of rho (x and y passes, and the mean density) is made
+ * once, then each scale applies its multiplier (Eq. (4)) in its own z pass and
+ * its own inverse transform.  kws[] and cwts[] are HOST arrays (cwts holds
+ * device pointers to [n^3] FP32 outputs); cwts[s] receives exactly what hf_cwt
+ * gives at kws[s].  Workspace: hf_cwt_batch_ws_size(n, count) (one half
+ * spectrum and table set per scale). */
+hf_status hf_cwt_scales(hf_ctx *ctx, const hf_box *box, const int64_t *rho, int32_t count, const double *kws,
+                        hf_kernel kernel, float *const *cwts, void *ws, size_t ws_bytes);
 hf_status hf_cwt_batch(hf_ctx *ctx, int32_t n, int32_t count, const hf_cwt_item *items, hf_kernel kernel,
                        void *ws, size_t ws_bytes);
 

@@ -394,6 +394,12 @@ struct CwtJobs {
     size_t stride;
     int mode;  // hf_kernel
     int count;
+    // every job transforms job 0's density (one grid, several scales): the
+    // forward x and y passes run for job 0 only and each job's z pass reads
+    // job 0's half spectrum (and its normalisation) into its own; job 0's own
+    // z pass, in place, runs in a launch after the others
+    int shared_forward;
+    int job_base;  // the z pass's first job (its launch covers job_base .. job_base + grid jobs - 1)
 };
 
 struct JobView {
@@ -787,8 +793,10 @@ __global__ void fft_z_mul_kernel(CwtJobs J, CwtLayout L, FftPlan pl, FftPlan pi)
     extern __shared__ float2 smem[];
     int tile, yrow, job;
     yz_tile(yrow, tile, job);
+    job += J.job_base;
     const JobView jv = job_view(J, L, job);
-    float2 *__restrict__ spec = jv.spec;
+    const JobView src = J.shared_forward ? job_view(J, L, 0) : jv;  // forward spectrum and normalisation
+    float2 *spec = jv.spec;  // the same memory as src.spec unless the forward transform is shared
     const float *__restrict__ tab_b = jv.btab;
     const float *__restrict__ tab_p = jv.ptab;
     const int n = pl.n, H = n / 2 + 1;
@@ -800,14 +808,15 @@ __global__ void fft_z_mul_kernel(CwtJobs J, CwtLayout L, FftPlan pl, FftPlan pi)
     const int valid = min(YZ_TILE, H - kx0);
     const size_t zstride = size_t(n + 1) * YZ_TILE;
     float2 *col = spec + spec_at(n, tile, 0, ky);  // element z of pencil p at col[z zstride + p]
+    const float2 *col_in = src.spec + spec_at(n, tile, 0, ky);  // the same place, or job 0's
     load_twiddles(tw, jv.tw, n);
-    const float scale = float(jv.scalars[0]);
+    const float scale = float(src.scalars[0]);
     const float by = tab_b[ky], py = tab_p[ky];
     // the thread's pencil is the same in every stage (nthreads is a multiple of P)
     const int kx = min(kx0 + (tid & (YZ_TILE - 1)), H - 1);
     const float bx = tab_b[kx], px = tab_p[kx];
     const float cxy = (px * by + bx * py) * scale, bxy = bx * by * scale;
-    auto gload = [=](int p, int z) { return p < valid ? col[size_t(z) * zstride + p] : make_float2(0.f, 0.f); };
+    auto gload = [=](int p, int z) { return p < valid ? col_in[size_t(z) * zstride + p] : make_float2(0.f, 0.f); };
     auto gstore = [=](int p, int z, float2 v) {
         if (p < valid) col[size_t(z) * zstride + p] = v;
     };
@@ -905,11 +914,21 @@ hf_status run_cwt(hf_ctx *ctx, int n, const CwtJobs &J) {
         !allow(reinterpret_cast<const void *>(&fft_x_fwd_kernel), x_shm) ||
         !allow(reinterpret_cast<const void *>(&fft_x_inv_kernel), xi_shm))
         return HF_ERR_DEVICE;
-    HF_LAUNCH(ctx, K_X_FWD, fft_x_fwd_kernel, dim3(unsigned(L.xblocks), jobs), dim3(x_threads), x_shm, st, J, L, pl,
-              ctx->d_status);
-    HF_LAUNCH(ctx, K_MASS, mass_kernel, dim3(jobs), dim3(1024), 0, st, J, L, n, ctx->d_status);
-    HF_LAUNCH(ctx, K_Y_FWD, fft_y_kernel<false>, dim3(tiles, n, jobs), dim3(yz_threads), yz_shm, st, J, L, pl);
-    HF_LAUNCH(ctx, K_Z_MUL, fft_z_mul_kernel, dim3(n, tiles, jobs), dim3(yz_threads), yz_shm, st, J, L, pl, pi);
+    const unsigned fwd_jobs = J.shared_forward ? 1u : jobs;
+    HF_LAUNCH(ctx, K_X_FWD, fft_x_fwd_kernel, dim3(unsigned(L.xblocks), fwd_jobs), dim3(x_threads), x_shm, st, J, L,
+              pl, ctx->d_status);
+    HF_LAUNCH(ctx, K_MASS, mass_kernel, dim3(fwd_jobs), dim3(1024), 0, st, J, L, n, ctx->d_status);
+    HF_LAUNCH(ctx, K_Y_FWD, fft_y_kernel<false>, dim3(tiles, n, fwd_jobs), dim3(yz_threads), yz_shm, st, J, L, pl);
+    if (J.shared_forward && jobs > 1) {
+        // the other scales read job 0's forward spectrum before job 0 overwrites it
+        CwtJobs Jr = J;
+        Jr.job_base = 1;
+        HF_LAUNCH(ctx, K_Z_MUL, fft_z_mul_kernel, dim3(n, tiles, jobs - 1), dim3(yz_threads), yz_shm, st, Jr, L, pl,
+                  pi);
+        HF_LAUNCH(ctx, K_Z_MUL, fft_z_mul_kernel, dim3(n, tiles, 1), dim3(yz_threads), yz_shm, st, J, L, pl, pi);
+    } else {
+        HF_LAUNCH(ctx, K_Z_MUL, fft_z_mul_kernel, dim3(n, tiles, jobs), dim3(yz_threads), yz_shm, st, J, L, pl, pi);
+    }
     HF_LAUNCH(ctx, K_Y_INV, fft_y_kernel<true>, dim3(tiles, n, jobs), dim3(yz_threads), yz_shm, st, J, L, pl);
     HF_LAUNCH(ctx, K_X_INV, fft_x_inv_kernel, dim3(unsigned(L.xblocks_i), jobs), dim3(xi_threads), xi_shm, st, J, L,
               pl);
@@ -948,6 +967,28 @@ extern "C" hf_status hf_cwt(hf_ctx *ctx, const hf_box *box, const int64_t *rho, 
     J.stride = need;
     J.mode = kernel;
     J.count = 1;
+    return run_cwt(ctx, box->n, J);
+}
+
+extern "C" hf_status hf_cwt_scales(hf_ctx *ctx, const hf_box *box, const int64_t *rho, int32_t count,
+                                   const double *kws, hf_kernel kernel, float *const *cwts, void *ws,
+                                   size_t ws_bytes) {
+    if (!ctx || !rho || !kws || !cwts || count < 1 || count > HF_CWT_BATCH_MAX) return HF_ERR_ARG;
+    if (kernel != HF_KERNEL_SAMPLED && kernel != HF_KERNEL_ANALYTIC) return HF_ERR_ARG;
+    hf_status s = check_box(box);
+    if (s != HF_OK) return s;
+    const size_t per = cwt_layout(box->n).total;
+    s = check_ws(ws, ws_bytes, per * size_t(count));
+    if (s != HF_OK) return s;
+    CwtJobs J{};
+    for (int j = 0; j < count; ++j)
+        if (!fill_job(J, j, rho, cwts[j], box->box_len, kws[j])) return HF_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    J.ws = static_cast<char *>(ws);
+    J.stride = per;
+    J.mode = kernel;
+    J.count = count;
+    J.shared_forward = 1;
     return run_cwt(ctx, box->n, J);
 }
 

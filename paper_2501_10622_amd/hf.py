@@ -25,7 +25,7 @@ EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_
            "hf_deposit", "hf_cwt", "hf_maxima", "hf_segment", "hf_label",
            "hf_profile_enable", "hf_profile_reset", "hf_profile_read",
            "hf_cwt_batch_ws_size", "hf_cwt_batch", "hf_find_halos", "hf_find_halos_group", "hf_groups",
-           "hf_find_halos_filtered")
+           "hf_find_halos_filtered", "hf_cwt_scales")
 CWT_BATCH_MAX = 32
 STAGE_ALL = 31
 STAGE_GROUPS = 32
@@ -98,6 +98,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
             "hf_cwt_batch_ws_size": (ctypes.c_int, [i32, i32, ctypes.POINTER(sz)]),
             "hf_cwt_batch": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(CwtItem), ctypes.c_int, vp, sz]),
+            "hf_cwt_scales": (ctypes.c_int, [vp, bp, vp, i32, ctypes.POINTER(dbl), ctypes.c_int,
+                                             ctypes.POINTER(vp), vp, sz]),
             "hf_find_halos": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job), vp, sz]),
             "hf_find_halos_group": (ctypes.c_int, [vp, i32, i32, i32, ctypes.POINTER(GroupItem), ctypes.c_int,
                                                    vp, sz]),
@@ -384,6 +386,31 @@ def cwt_batch(rhos, box_lens, kws, kernel: str = "sampled", outs=None, ws=None, 
     items = (CwtItem * count)(*[CwtItem(r.data_ptr(), o.data_ptr(), float(L), float(k))
                                  for r, o, L, k in zip(rhos, outs, box_lens, kws)])
     _check(lib.hf_cwt_batch(ctx.handle, n, count, items, KERNELS[kernel], _ptr(ws), ws.numel()), "hf_cwt_batch")
+    return outs
+
+
+def cwt_scales(rho: torch.Tensor, box_len: float, kws, kernel: str = "sampled", outs=None, ws=None, ctx=None,
+               frac_bits: int = 15) -> list:
+    """Step 3 of one int64 grid at several scales (at most CWT_BATCH_MAX): one
+    forward transform, then a multiplier and inverse transform per scale."""
+    _require_cuda(rho, "rho")
+    if rho.dtype != torch.int64 or rho.ndim != 3:
+        raise ValueError("rho must be an int64 [n, n, n] grid")
+    count = len(kws)
+    if count < 1 or count > CWT_BATCH_MAX:
+        raise ValueError(f"number of scales must be 1..{CWT_BATCH_MAX}")
+    n = rho.shape[0]
+    ctx = ctx or context(rho.device.index)
+    if outs is None:
+        outs = [torch.empty((n, n, n), dtype=torch.float32, device=rho.device) for _ in range(count)]
+    need = cwt_batch_ws_bytes(n, count)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=rho.device)
+    b = box(n, box_len, frac_bits)
+    k = (ctypes.c_double * count)(*[float(x) for x in kws])
+    o = (ctypes.c_void_p * count)(*[t.data_ptr() for t in outs])
+    _check(load_library().hf_cwt_scales(ctx.handle, ctypes.byref(b), _ptr(rho), count, k, KERNELS[kernel], o,
+                                        _ptr(ws), ws.numel()), "hf_cwt_scales")
     return outs
 
 
