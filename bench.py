@@ -73,7 +73,7 @@ STAGES = {
 }
 
 
-def stage_bytes(n: int, np_: int, pos_bytes: int) -> dict:
+def stage_bytes(n: int, np_: int, pos_bytes: int, scales: int = 1) -> dict:
     """Algorithmic (compulsory) HBM bytes of each stage for one box.
 
     deposit 12 B/particle (FP32 positions) + 8 B/cell; the transform as five
@@ -86,15 +86,17 @@ def stage_bytes(n: int, np_: int, pos_bytes: int) -> dict:
     """
     cells = n ** 3
     half = n * n * (n // 2 + 1) * 8  # complex64 half spectrum
+    # with several scales the deposit and the forward x and y passes run once
+    # and everything after them once per scale
     return {
         "deposit": pos_bytes * 3 * np_ + 8 * cells,
         "cwt_x_fwd": 8 * cells + half,
         "cwt_y_fwd": 2 * half,
-        "cwt_z_mul": 2 * half,
-        "cwt_y_inv": 2 * half,
-        "cwt_x_inv": half + 4 * cells,
-        "maxima_segment": (4 + 8) * cells,
-        "label": (pos_bytes * 3 + 4 + 4) * np_,
+        "cwt_z_mul": 2 * half * scales,
+        "cwt_y_inv": 2 * half * scales,
+        "cwt_x_inv": (half + 4 * cells) * scales,
+        "maxima_segment": (4 + 8) * cells * scales,
+        "label": (pos_bytes * 3 + 4 + 4) * np_ * scales,
     }
 
 
@@ -465,16 +467,17 @@ def serving_bench(n_jobs: int, budget_gb: float, n_streams: int, max_batch: int,
     return out
 
 
-def cwt_summary(stages: dict, cells: int) -> dict:
+def cwt_summary(stages: dict, cells: int, scales: int = 1) -> dict:
     """The five transform passes together, against the pencil-sweep byte model
-    (44.06 B/cell) and against the strict compulsory bound of reading the
-    density and writing the field (8 + 4 B/cell)."""
+    (44.06 B/cell for one scale) and against the strict compulsory bound of
+    reading the density once and writing each scale's field (8 + 4 B/cell per
+    scale)."""
     parts = [k for k in stages if k.startswith("cwt_")]
     if not parts:
         return {}
     ms = sum(stages[k]["ms_per_step"] for k in parts)
     model = sum(stages[k]["algorithmic_bytes"] for k in parts)
-    strict = 12 * cells
+    strict = (8 + 4 * scales) * cells
     return {"ms_per_step": round(ms, 4), "model_bytes": model, "strict_bytes": strict,
             "GBps_model": round(model / ms / 1e6, 1), "frac_model": round(model / ms / 1e6 / HBM_PEAK_GBS, 4),
             "GBps_strict": round(strict / ms / 1e6, 1), "frac_strict": round(strict / ms / 1e6 / HBM_PEAK_GBS, 4)}
@@ -675,7 +678,9 @@ def main():
         _b.build(verbose=False)
     cfg = synth.CONFIGS[args.config]
     n, L = cfg.n, cfg.box_len
-    kw = cfg.kw_list[0]
+    kws = list(cfg.kw_list)
+    kw = kws[0]
+    multi = len(kws) > 1  # several scales: one deposit and forward transform, the rest per scale
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     log(f"generating {args.config}: n={n} np={cfg.n_particles} on the GPU")
@@ -685,11 +690,17 @@ def main():
     log(f"generated in {time.perf_counter() - t0:.1f} s")
 
     ctx = hfm.context(0)
-    bufs = hfm.job_buffers(n, cfg.n_particles, dev, True)
+    if multi:
+        bufs = hfm.scales_buffers(n, cfg.n_particles, len(kws), dev)
+    else:
+        bufs = hfm.job_buffers(n, cfg.n_particles, dev, True)
     log(f"workspace {bufs['ws'].numel() / 2**30:.2f} GiB")
 
     def step():
-        hfm.find_halos_async(pos, L, n, kw, bufs, kernel=args.kernel, ctx=ctx)
+        if multi:
+            hfm.find_halos_scales_async(pos, L, n, kws, bufs, kernel=args.kernel, ctx=ctx)
+        else:
+            hfm.find_halos_async(pos, L, n, kw, bufs, kernel=args.kernel, ctx=ctx)
 
     for i in range(args.warmup):
         step()
@@ -732,16 +743,23 @@ def main():
     log(f"{args.steps} steps with the kernel timer: {ms_step_timer:.3f} ms/step")
 
     # properties that hold at any size: exact mass, labelled roots are the maxima
-    rho, cell = bufs["rho"], bufs["cell_label"]
+    rho = bufs["rho"]
     lo = int((rho & 0xFFFFFFFF).sum().item())
     hi = int((rho >> 32).sum().item())
     mass_ok = (hi << 32) + lo == cfg.n_particles << (3 * 15)
-    nmax = int(bufs["count"].item())
-    buf = bufs["maxima"]
-    roots_ok = bool((cell.view(-1)[buf[:nmax].long()] == buf[:nmax]).all().item()) if nmax else True
+    per_scale = [(bufs["cell_label"][j], bufs["count"][j], bufs["maxima"][j]) for j in range(len(kws))] if multi \
+        else [(bufs["cell_label"], bufs["count"], bufs["maxima"])]
+    roots_ok, nmaxs = True, []
+    for cell, cnt_t, buf in per_scale:
+        nmax = int(cnt_t.item())
+        nmaxs.append(nmax)
+        if nmax:
+            roots_ok &= bool((cell.view(-1)[buf[:nmax].long()] == buf[:nmax]).all().item())
+    nmax = nmaxs[0] if not multi else nmaxs
+    cell, buf = per_scale[0][0], per_scale[0][2]
 
     pos_bytes = 4 if cfg.dtype == "f32" else 8
-    sb = stage_bytes(n, cfg.n_particles, pos_bytes)
+    sb = stage_bytes(n, cfg.n_particles, pos_bytes, len(kws))
     kernels = {}
     for name, (ms, launches) in prof.items():
         if launches == 0:
@@ -778,8 +796,13 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.config}: periodic box L={L:g} Mpc/h, {n}^3 grid, {cfg.n_particles} "
                                f"{'FP32' if pos_bytes == 4 else 'FP64'} particles, {cfg.n_halos} NFW halos (60%) + "
-                               f"uniform, random order, one scale a=2 cells (k_w={kw:g}), {args.kernel} kernel",
-                   "grid": n, "particles": cfg.n_particles, "kw": kw, "kernel": args.kernel, "seed": cfg.seed},
+                               f"uniform, random order, "
+                               + (f"{len(kws)} scales a={'/'.join(f'{a:g}' for a in cfg.scales_cells)} cells "
+                                  f"(k_w={'/'.join(f'{k:g}' for k in kws)}; one deposit and forward transform)"
+                                  if multi else f"one scale a={cfg.scales_cells[0]:g} cells (k_w={kw:g})")
+                               + f", {args.kernel} kernel",
+                   "grid": n, "particles": cfg.n_particles, "kw": kws if multi else kw, "kernel": args.kernel,
+                   "seed": cfg.seed},
         "cells_per_s": cells / (ms_step / 1e3),
         "e2e_model_bytes": model_bytes,
         "e2e_hbm_roofline_frac": round(e2e_gbs / HBM_PEAK_GBS, 4),
@@ -789,11 +812,11 @@ def main():
                      "traffic": traffic["bytes"] if traffic else None, "traffic_detail": traffic,
                      "traffic_source": os.path.relpath(traffic_file(tag), ROOT) if traffic else None},
         "stages": stages,
-        "cwt": cwt_summary(stages, cells),
+        "cwt": cwt_summary(stages, cells, len(kws)),
         "kernels": kernels,
         "checks": {"mass_exact": mass_ok, "labelled_roots_are_maxima": roots_ok, "maxima": nmax},
     }
-    if not args.no_groups:
+    if not args.no_groups and not multi:
         out["cwt_scales"] = scales_bench(bufs["rho"], L, n, args.kernel, 3, ctx)
         out["groups"] = groups_bench(bufs, n, cfg.n_particles, args.warmup, 2 * args.steps, ctx)
         out["filtered_pipeline"] = filtered_bench(pos, L, n, kw, bufs, args.warmup, args.steps, args.kernel, ctx,

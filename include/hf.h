@@ -251,6 +251,28 @@ typedef struct {
 hf_status hf_find_halos_filtered(hf_ctx *ctx, const hf_box *box, const hf_job *job, const hf_group_filter *gf,
                                  void *ws, size_t ws_bytes);
 
+/* Steps 2-6 of one box at `count` (1..HF_CWT_BATCH_MAX) scales, as the
+ * identification loop of Sec. 2 visits scales one after another: one deposit
+ * into rho, one forward transform shared by every scale (as hf_cwt_scales),
+ * then per scale its inverse transform, maxima, segmentation and particle
+ * labels (through the deposit's particle order where it bins, as
+ * hf_find_halos).  Each scale's outputs equal those of hf_find_halos at its
+ * k_w.  scales[] is a HOST array of device output pointers; pos, np, dtype,
+ * kernel and tau as in hf_job.  Workspace: hf_find_halos_scales_ws_size. */
+typedef struct {
+    double kw;               /* scale k_w = w box_len / 1000 */
+    float *cwt;              /* [n^3] FP32 CWT at this scale */
+    int32_t *max_idx;        /* [max_cap] sorted maxima */
+    int64_t max_cap;
+    int64_t *d_count;        /* device int64: number of maxima */
+    int32_t *cell_label;     /* [n^3] */
+    int32_t *particle_label; /* [np] */
+} hf_scale_job;
+hf_status hf_find_halos_scales_ws_size(const hf_box *box, int64_t np, int32_t count, size_t *bytes);
+hf_status hf_find_halos_scales(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np,
+                               hf_kernel kernel, float tau, int64_t *rho, int32_t count, const hf_scale_job *scales,
+                               void *ws, size_t ws_bytes);
+
 /* Serving form of steps 2-6 for `count` (1..HF_CWT_BATCH_MAX) boxes of the same
  * grid size n: per-box deposits, ONE batched transform (hf_cwt_batch) for the
  * group, then per-box maxima, segmentation and labels, all on the context's

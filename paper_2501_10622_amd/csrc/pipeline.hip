@@ -121,6 +121,73 @@ extern "C" hf_status hf_find_halos_filtered(hf_ctx *ctx, const hf_box *box, cons
     return s;
 }
 
+// Steps 2-6 of one box at several scales: one deposit (and, where it bins,
+// one kept particle order), one forward transform shared by every scale
+// (hf_cwt_scales), then per scale the multiplier and inverse transform,
+// maxima and segmentation, and the labels through the same particle order.
+extern "C" hf_status hf_find_halos_scales_ws_size(const hf_box *box, int64_t np, int32_t count, size_t *bytes) {
+    if (!bytes || np < 0 || count < 1 || count > HF_CWT_BATCH_MAX) return HF_ERR_ARG;
+    hf_status s = check_box(box);
+    if (s != HF_OK) return s;
+    size_t all = 0, cw = 0;
+    s = hf_workspace_size(box, np, HF_STAGE_ALL, &all);
+    if (s == HF_OK) s = hf_cwt_batch_ws_size(box->n, count, &cw);
+    if (s != HF_OK) return s;
+    const size_t ord = particle_order_supported(*box, np) ? particle_order_bytes(*box, np) : 0;
+    const size_t shared = all - ord;  // every stage's share, one transform included
+    *bytes = ord + (shared > cw ? shared : cw);
+    return HF_OK;
+}
+
+extern "C" hf_status hf_find_halos_scales(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np,
+                                          hf_kernel kernel, float tau, int64_t *rho, int32_t count,
+                                          const hf_scale_job *scales, void *ws, size_t ws_bytes) {
+    if (!ctx || !rho || !scales || count < 1 || count > HF_CWT_BATCH_MAX || np < 0 || (np > 0 && !pos)) return HF_ERR_ARG;
+    if ((dtype != HF_F32 && dtype != HF_F64) || (kernel != HF_KERNEL_SAMPLED && kernel != HF_KERNEL_ANALYTIC) ||
+        tau != tau)
+        return HF_ERR_ARG;
+    hf_status s = check_box(box);
+    if (s != HF_OK) return s;
+    size_t need = 0;
+    s = hf_find_halos_scales_ws_size(box, np, count, &need);
+    if (s != HF_OK) return s;
+    s = check_ws(ws, ws_bytes, need);
+    if (s != HF_OK) return s;
+    double kws[HF_CWT_BATCH_MAX];
+    float *cwts[HF_CWT_BATCH_MAX];
+    for (int j = 0; j < count; ++j) {
+        const hf_scale_job &sj = scales[j];
+        if (!sj.cwt || !sj.d_count || !sj.cell_label || sj.max_cap < 0 || (sj.max_cap > 0 && !sj.max_idx) ||
+            (np > 0 && !sj.particle_label) || !(sj.kw > 0.0))
+            return HF_ERR_ARG;
+        kws[j] = sj.kw;
+        cwts[j] = sj.cwt;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    const bool order = particle_order_supported(*box, np);
+    char *sw = static_cast<char *>(ws);
+    size_t sb = ws_bytes;
+    ParticleOrder po{};
+    if (order) {
+        po = particle_order_at(*box, ws, np);
+        sw += particle_order_bytes(*box, np);
+        sb -= particle_order_bytes(*box, np);
+        s = deposit_tiled(ctx, *box, pos, dtype, np, rho, sw, &po);
+    } else {
+        s = hf_deposit(ctx, box, pos, dtype, np, rho, sw, sb);
+    }
+    if (s != HF_OK) return s;
+    s = hf_cwt_scales(ctx, box, rho, count, kws, kernel, cwts, sw, sb);
+    for (int j = 0; j < count && s == HF_OK; ++j) {
+        const hf_scale_job &sj = scales[j];
+        s = maxima_segment(ctx, *box, sj.cwt, tau, sj.max_idx, sj.max_cap, sj.d_count, sj.cell_label, sw, sb);
+        if (s != HF_OK) break;
+        s = order ? label_from_order(ctx, *box, np, po, sj.cell_label, sj.particle_label, sw)
+                  : hf_label(ctx, box, pos, dtype, np, sj.cell_label, sj.particle_label);
+    }
+    return s;
+}
+
 // A group of same-n boxes: per-box deposits, one batched transform for all of
 // them, then per-box maxima, segmentation and labels, in that order on the
 // context's stream.

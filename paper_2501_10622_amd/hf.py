@@ -25,7 +25,8 @@ EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_
            "hf_deposit", "hf_cwt", "hf_maxima", "hf_segment", "hf_label",
            "hf_profile_enable", "hf_profile_reset", "hf_profile_read",
            "hf_cwt_batch_ws_size", "hf_cwt_batch", "hf_find_halos", "hf_find_halos_group", "hf_groups",
-           "hf_find_halos_filtered", "hf_cwt_scales")
+           "hf_find_halos_filtered", "hf_cwt_scales",
+           "hf_find_halos_scales_ws_size", "hf_find_halos_scales")
 CWT_BATCH_MAX = 32
 STAGE_ALL = 31
 STAGE_GROUPS = 32
@@ -50,6 +51,12 @@ class Job(ctypes.Structure):
     _fields_ = [("pos", ctypes.c_void_p), ("np", ctypes.c_int64), ("dtype", ctypes.c_int),
                 ("kw", ctypes.c_double), ("kernel", ctypes.c_int), ("tau", ctypes.c_float),
                 ("rho", ctypes.c_void_p), ("cwt", ctypes.c_void_p), ("max_idx", ctypes.c_void_p),
+                ("max_cap", ctypes.c_int64), ("d_count", ctypes.c_void_p), ("cell_label", ctypes.c_void_p),
+                ("particle_label", ctypes.c_void_p)]
+
+
+class ScaleJob(ctypes.Structure):
+    _fields_ = [("kw", ctypes.c_double), ("cwt", ctypes.c_void_p), ("max_idx", ctypes.c_void_p),
                 ("max_cap", ctypes.c_int64), ("d_count", ctypes.c_void_p), ("cell_label", ctypes.c_void_p),
                 ("particle_label", ctypes.c_void_p)]
 
@@ -100,6 +107,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "hf_cwt_batch": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(CwtItem), ctypes.c_int, vp, sz]),
             "hf_cwt_scales": (ctypes.c_int, [vp, bp, vp, i32, ctypes.POINTER(dbl), ctypes.c_int,
                                              ctypes.POINTER(vp), vp, sz]),
+            "hf_find_halos_scales_ws_size": (ctypes.c_int, [bp, i64, i32, ctypes.POINTER(sz)]),
+            "hf_find_halos_scales": (ctypes.c_int, [vp, bp, vp, ctypes.c_int, i64, ctypes.c_int, flt, vp, i32,
+                                                    ctypes.POINTER(ScaleJob), vp, sz]),
             "hf_find_halos": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job), vp, sz]),
             "hf_find_halos_group": (ctypes.c_int, [vp, i32, i32, i32, ctypes.POINTER(GroupItem), ctypes.c_int,
                                                    vp, sz]),
@@ -451,6 +461,43 @@ def find_halos_async(pos: torch.Tensor, box_len: float, n: int, kw: float, bufs:
     job = _job_struct(pos, kw, bufs, tau, kernel)
     _check(load_library().hf_find_halos(ctx.handle, ctypes.byref(b), ctypes.byref(job), _ptr(bufs["ws"]),
                                         bufs["ws"].numel()), "hf_find_halos")
+
+
+def scales_buffers(n: int, np_: int, count: int, device, frac_bits: int = 15) -> dict:
+    """Outputs (one list entry per scale) and workspace for find_halos_scales_async."""
+    out = ctypes.c_size_t()
+    b = box(n, 1.0, frac_bits)
+    _check(load_library().hf_find_halos_scales_ws_size(ctypes.byref(b), int(np_), int(count), ctypes.byref(out)),
+           "hf_find_halos_scales_ws_size")
+    cap = ((n + 1) // 2) ** 3
+    return {
+        "rho": torch.empty((n, n, n), dtype=torch.int64, device=device),
+        "cwt": [torch.empty((n, n, n), dtype=torch.float32, device=device) for _ in range(count)],
+        "maxima": [torch.empty(cap, dtype=torch.int32, device=device) for _ in range(count)],
+        "count": [torch.empty(1, dtype=torch.int64, device=device) for _ in range(count)],
+        "cell_label": [torch.empty((n, n, n), dtype=torch.int32, device=device) for _ in range(count)],
+        "particle_label": [torch.empty(max(np_, 1), dtype=torch.int32, device=device) for _ in range(count)],
+        "ws": torch.empty(max(out.value, 256), dtype=torch.uint8, device=device),
+    }
+
+
+def find_halos_scales_async(pos: torch.Tensor, box_len: float, n: int, kws, bufs: dict, frac_bits: int = 15,
+                            tau: float = 0.0, kernel: str = "sampled", ctx=None):
+    """Enqueue steps 2-6 at several scales of one box: one deposit and one
+    forward transform, then per scale the rest (bufs from scales_buffers)."""
+    _require_cuda(pos, "pos")
+    ctx = ctx or context(pos.device.index)
+    count = len(kws)
+    if count != len(bufs["cwt"]):
+        raise ValueError("one buffer set per scale")
+    jobs = (ScaleJob * count)(*[ScaleJob(float(kw), bufs["cwt"][j].data_ptr(), bufs["maxima"][j].data_ptr(),
+                                         bufs["maxima"][j].numel(), bufs["count"][j].data_ptr(),
+                                         bufs["cell_label"][j].data_ptr(), bufs["particle_label"][j].data_ptr())
+                                for j, kw in enumerate(kws)])
+    b = box(n, box_len, frac_bits)
+    _check(load_library().hf_find_halos_scales(ctx.handle, ctypes.byref(b), _ptr(pos), _dtype_code(pos),
+                                               pos.shape[0], KERNELS[kernel], float(tau), _ptr(bufs["rho"]), count,
+                                               jobs, _ptr(bufs["ws"]), bufs["ws"].numel()), "hf_find_halos_scales")
 
 
 def find_halos_filtered_async(pos: torch.Tensor, box_len: float, n: int, kw: float, bufs: dict,

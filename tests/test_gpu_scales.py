@@ -70,3 +70,31 @@ def test_scales_arguments():
     assert lib.hf_cwt_scales(ctx.handle, ctypes.byref(b), hf._ptr(rho), 1, k, 0, o, hf._ptr(ws), ws.numel()) == hf.HF_OK
     ctx.sync()
     assert torch.equal(out, hfm().cwt(rho, 20.0, 0.01))
+
+
+@pytest.mark.parametrize("n,L,np_,halos,scales,bits", [
+    (192, 187.5, 2_000_001, 7910, (1.0, 2.0, 4.0), 15),   # binned deposit: labels through the kept order
+    (48, 60.0, 200_000, 80, (1.5, 3.0), 12),              # one bucket: labels by gather
+])
+def test_scales_pipeline_equals_single_scale_pipeline(n, L, np_, halos, scales, bits):
+    """hf_find_halos_scales (one deposit, one forward transform) gives every
+    scale exactly hf_find_halos's outputs at that scale."""
+    from paper_2501_10622_amd import hf
+    pos = cuda(small_box(n, L, np_, halos, "f32", 54))
+    kws = [n / (1000.0 * a) for a in scales]
+    print(f"scales pipeline n={n} count={len(kws)}", flush=True)
+    ctx = hf.context(0)
+    mb = hf.scales_buffers(n, np_, len(kws), pos.device, bits)
+    hf.find_halos_scales_async(pos, L, n, kws, mb, frac_bits=bits, ctx=ctx)
+    ctx.sync()
+    for j, kw in enumerate(kws):
+        sb = hf.job_buffers(n, np_, pos.device, True, bits)
+        hf.find_halos_async(pos, L, n, kw, sb, frac_bits=bits, ctx=ctx)
+        ctx.sync()
+        assert torch.equal(mb["rho"], sb["rho"])
+        assert torch.equal(mb["cwt"][j], sb["cwt"]), f"cwt scale {j}"
+        cnt = int(sb["count"].item())
+        assert int(mb["count"][j].item()) == cnt
+        assert torch.equal(mb["maxima"][j][:cnt], sb["maxima"][:cnt])
+        assert torch.equal(mb["cell_label"][j], sb["cell_label"]), f"cells scale {j}"
+        assert torch.equal(mb["particle_label"][j][:np_], sb["particle_label"][:np_]), f"labels scale {j}"
