@@ -655,7 +655,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(jobs and boxes are sharded one per GPU by the caller).", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:

@@ -15,7 +15,7 @@ everything in FP64.  For each scale the report gives:
   tie_free  whether C64 is certified tie-free for the FP32 error measured, in
             which case maxima and labels must agree exactly
 
-Run on a GPU host:  python tests/precision_study.py --out gpurun_out/precision_m3.json
+Run on a GPU host:  python tests/precision_study.py --out precision_m3.json
 The oracle work for the scales runs in threads before the GPU is touched.
 """
 from __future__ import annotations
@@ -65,7 +65,7 @@ def oracle_scale(rho, pos, L, n, kw):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--config", default="M3", choices=list(synth.CONFIGS))
-    ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "precision.json"))
+    ap.add_argument("--out", default="precision.json", help="where the JSON report goes")
     ap.add_argument("--skip-tie-check", action="store_true")
     args = ap.parse_args()
     cfg = synth.CONFIGS[args.config]
