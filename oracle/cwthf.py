@@ -16,6 +16,7 @@ one scale:
 
 and, after them, the group statistics of steps 5 and 7 with Table 1's
 thresholds dens_th and particle_th                  -> ``group_stats``
+and the cross-scale maximum check of step 8         -> ``cross_scale``
 
 Readings taken where the paper is silent are listed in the design notes and
 repeated at each function.  Everything here is deliberately unblocked and
@@ -32,7 +33,7 @@ __all__ = [
     "scale_w", "fixed_point", "deposit", "total_mass", "mean_mass", "normalise",
     "wavelet", "wavelet_hat", "sampled_kernel", "kernel_hat", "cwt_field", "cwt",
     "neighbour_offsets", "maxima", "parents", "segment", "ngp_nodes", "label",
-    "find_halos", "group_stats", "DepositOverflow",
+    "find_halos", "group_stats", "cross_scale", "DepositOverflow",
 ]
 
 
@@ -358,6 +359,34 @@ def group_stats(cell_label, particle_label, roots, n: int, np_total: int, dens_t
         "particle_label": new_pl.astype(np.int32),
         "cell_label": new_cl.astype(np.int32).reshape(np.shape(cell_label)),
     }
+
+
+# --------------------------------------------------------------------------
+# step 8: cross-scale maxima
+# --------------------------------------------------------------------------
+def cross_scale(c_scale: np.ndarray, c_smaller: np.ndarray, roots) -> np.ndarray:
+    """Which maxima of one scale are also maxima across scale (step 8 and the
+    comparison of the two grids described with the flowchart in Sec. 2).
+
+    A local maximum of the grid CWT at one scale is kept if its value exceeds
+    the values of all grid points near the same position in the CWT of the
+    adjacent smaller scale.  Reading: both fields are on the same n^3 grid (one
+    grid for every scale of a box), "near" is the maximum's cell and its 26
+    periodic neighbours, and "exceeds" is strict.  The paper corrects grid
+    maxima for the cube size before comparing across grids of different
+    spacing (App. B); with one spacing there is no such correction.
+
+    Returns one flag per root of ``roots`` (linear cell indices).
+    """
+    cs = _check_field(c_scale)
+    cm = _check_field(c_smaller)
+    if cs.shape != cm.shape:
+        raise ValueError("both scales must be on the same grid")
+    near = cm.copy()
+    for off in neighbour_offsets():
+        near = np.maximum(near, np.roll(cm, tuple(-o for o in off), axis=(0, 1, 2)))
+    roots = np.asarray(roots, dtype=np.int64).ravel()
+    return cs.ravel()[roots] > near.ravel()[roots]
 
 
 # --------------------------------------------------------------------------
