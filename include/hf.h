@@ -12,6 +12,7 @@
  *   hf_label    step 6  particles take the label of their segmented cell
  *   hf_groups   steps 5 and 7  grid volume, particle number and density filter
  *                       of every group (Table 1: dens_th, particle_th)
+ *   hf_cross_scale  step 8  maxima that are also maxima across scale
  *
  * Conventions shared by every call
  * --------------------------------
@@ -156,8 +157,10 @@ hf_status hf_label(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dty
  *   group_keep[i]       1 iff the group's density is at least dens_th times the
  *                       box's mean density np / box_len^3 (step 7; Table 1:
  *                       dens_th = 4) and it has at least particle_th particles
- *                       (Table 1: particle_th = 15), else 0.  The density test
- *                       is decided in FP64 as
+ *                       (Table 1: particle_th = 15) and, when root_ok is given
+ *                       (device [nroots] flags, e.g. from hf_cross_scale),
+ *                       root_ok[i] != 0; else 0.  The density test is decided
+ *                       in FP64 as
  *                       double(P) * n^3 >= (dens_th * double(V)) * double(np).
  * cell_label_out [n^3] and particle_label_out [np] (either may be NULL, and
  * either may be the corresponding input) receive the labels with those of
@@ -173,8 +176,21 @@ hf_status hf_label(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dty
  * touched). */
 hf_status hf_groups(hf_ctx *ctx, const hf_box *box, int64_t np, const int32_t *roots, int64_t nroots,
                     const int32_t *cell_label, const int32_t *particle_label, double dens_th,
-                    int64_t particle_th, uint32_t *group_particles, uint32_t *group_cells, uint8_t *group_keep,
-                    int32_t *cell_label_out, int32_t *particle_label_out, void *ws, size_t ws_bytes);
+                    int64_t particle_th, const uint8_t *root_ok, uint32_t *group_particles, uint32_t *group_cells,
+                    uint8_t *group_keep, int32_t *cell_label_out, int32_t *particle_label_out, void *ws,
+                    size_t ws_bytes);
+
+/* Step 8: cross-scale maxima.  pass[i] = 1 iff cwt_scale[roots[i]] exceeds
+ * (strictly) cwt_smaller at the root's cell and its 26 periodic neighbours,
+ * where cwt_smaller is the CWT of the same box at the adjacent smaller scale
+ * on the same n^3 grid (the comparison of the two grids described with the
+ * flowchart of Sec. 2; with one grid spacing no cube-size correction, App. B,
+ * applies).  roots [nroots] (device, e.g. hf_maxima's list at this scale),
+ * pass [nroots] (device).  A NaN in either field or a root outside [0, n^3)
+ * sets HF_ERR_INPUT.  The flags can go to hf_groups as root_ok (groups
+ * without a cross-scale maximum are disposed of).  No workspace. */
+hf_status hf_cross_scale(hf_ctx *ctx, const hf_box *box, const int32_t *roots, int64_t nroots,
+                         const float *cwt_scale, const float *cwt_smaller, uint8_t *pass);
 
 /* Batched step 3 for serving: `count` (1..HF_CWT_BATCH_MAX) transforms of the
  * same grid size n, each with its own box length and scale, enqueued as one

@@ -317,7 +317,7 @@ def label(pos: np.ndarray, box_len: float, n: int, cell_label: np.ndarray,
 # steps 5 and 7: group volume, mass and density; Table 1 thresholds
 # --------------------------------------------------------------------------
 def group_stats(cell_label, particle_label, roots, n: int, np_total: int, dens_th: float = 4.0,
-                particle_th: int = 15) -> dict:
+                particle_th: int = 15, root_ok=None) -> dict:
     """Grid volume, particle number and density filter of every group.
 
     Step 5 gives each segmented structure its grid volume: the cells that carry
@@ -333,7 +333,9 @@ def group_stats(cell_label, particle_label, roots, n: int, np_total: int, dens_t
     is kept if it passes that test and has at least particle_th particles.
 
     ``roots`` is the sorted maxima list (the labels in use); the per-group
-    arrays are indexed like it.  Returns the particle number, the cell count and
+    arrays are indexed like it.  ``root_ok`` (optional, one flag per root)
+    disposes of the groups whose maximum failed another test, such as the
+    cross-scale check of step 8.  Returns the particle number, the cell count and
     the keep flag of every group, and both label arrays with the labels of
     disposed groups replaced by -1.
     """
@@ -348,6 +350,8 @@ def group_stats(cell_label, particle_label, roots, n: int, np_total: int, dens_t
     g_parts = parts_at[roots]
     dense = g_parts.astype(np.float64) * float(ncell) >= (float(dens_th) * g_cells.astype(np.float64)) * float(np_total)
     keep = dense & (g_parts >= particle_th)
+    if root_ok is not None:
+        keep &= np.asarray(root_ok, dtype=bool).ravel()
     keep_at = np.zeros(ncell, dtype=bool)
     keep_at[roots[keep]] = True
     new_pl = np.where(pl >= 0, np.where(keep_at[np.maximum(pl, 0)], pl, -1), -1)

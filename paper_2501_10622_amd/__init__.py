@@ -5,7 +5,8 @@ by FFT, 26-neighbour maxima, steepest-ascent segmentation, particle labels, and
 the group statistics and density filter that follow them.
 """
 from .hf import (  # noqa: F401
-    CWT_BATCH_MAX, EXPORTS, HFError, LIB_PATH, Context, context, cwt, cwt_batch, cwt_batch_ws_bytes, cwt_scales, deposit,
+    CWT_BATCH_MAX, EXPORTS, HFError, LIB_PATH, Context, context, cross_scale, cwt, cwt_batch, cwt_batch_ws_bytes,
+    cwt_scales, deposit,
     find_halos, find_halos_async, find_halos_filtered_async, find_halos_group_async, find_halos_scales_async,
     groups, job_buffers, label, load_library, maxima, scales_buffers, segment,
     status_str, sync, workspace_size,

@@ -103,6 +103,7 @@ __global__ void __launch_bounds__(GB) groups_particles_kernel(const int32_t *__r
 __global__ void __launch_bounds__(GB) groups_decide_kernel(const int32_t *__restrict__ roots, const int64_t *d_count,
                                                            int64_t cap, int64_t ncells, GroupCounters g,
                                                            double dens_th, double np_total, int64_t particle_th,
+                                                           const uint8_t *__restrict__ root_ok,
                                                            uint32_t *__restrict__ out_parts,
                                                            uint32_t *__restrict__ out_cells,
                                                            uint8_t *__restrict__ out_keep) {
@@ -118,7 +119,7 @@ __global__ void __launch_bounds__(GB) groups_decide_kernel(const int32_t *__rest
         const uint32_t p = g.parts[r], c = g.cells[r];
         const double lhs = double(p) * double(ncells);
         const double rhs = (dens_th * double(c)) * np_total;
-        const bool keep = int64_t(p) >= particle_th && lhs >= rhs;
+        const bool keep = int64_t(p) >= particle_th && lhs >= rhs && (!root_ok || root_ok[i]);
         out_parts[i] = p;
         out_cells[i] = c;
         out_keep[i] = keep ? 1 : 0;
@@ -149,6 +150,42 @@ __global__ void __launch_bounds__(GB) groups_filter_kernel(const int32_t *in, in
             else if (l[k] >= 0 && any_roots && keep[l[k]]) v = l[k];
             out[i] = v;
         }
+    }
+    if (bad) atomicOr(status, ST_INPUT);
+}
+
+// Step 8: maximum i of one scale is kept if its value exceeds the adjacent
+// smaller scale's field at its cell and the 26 periodic neighbours (both on
+// the same grid; strict).  One thread per maximum; a NaN is reported.
+__global__ void __launch_bounds__(GB) cross_scale_kernel(const int32_t *__restrict__ roots, int64_t nroots, int n,
+                                                         const float *__restrict__ c_scale,
+                                                         const float *__restrict__ c_smaller,
+                                                         uint8_t *__restrict__ pass, uint32_t *status) {
+    bool bad = false;
+    const uint32_t un = uint32_t(n), ncells = un * un * un;
+    for (int64_t i = blockIdx.x * int64_t(GB) + threadIdx.x; i < nroots; i += int64_t(gridDim.x) * GB) {
+        const int32_t r = roots[i];
+        if (r < 0 || uint32_t(r) >= ncells) {
+            bad = true;
+            pass[i] = 0;
+            continue;
+        }
+        const uint32_t x = uint32_t(r) % un, y = (uint32_t(r) / un) % un, z = uint32_t(r) / (un * un);
+        const float v = c_scale[r];
+        bool above = v == v;
+        bad |= !above;
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const uint32_t gz = (z + un + dz) % un, gy = (y + un + dy) % un, gx = (x + un + dx) % un;
+                    const float u = c_smaller[(gz * un + gy) * un + gx];
+                    bad |= u != u;
+                    above = above && v > u;
+                }
+        pass[i] = above ? 1 : 0;
     }
     if (bad) atomicOr(status, ST_INPUT);
 }
@@ -192,10 +229,11 @@ hf_status hf::groups_count_particles(hf_ctx *ctx, const hf_box &box, const int32
 
 hf_status hf::groups_decide(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count, int64_t cap,
                             const GroupCounters &g, double dens_th, int64_t np, int64_t particle_th,
-                            uint32_t *group_particles, uint32_t *group_cells, uint8_t *group_keep) {
+                            const uint8_t *root_ok, uint32_t *group_particles, uint32_t *group_cells,
+                            uint8_t *group_keep) {
     if (cap <= 0) return HF_OK;
     HF_LAUNCH(ctx, K_GROUP_DECIDE, groups_decide_kernel, dim3(grid_of(ctx, cap, GB)), dim3(GB), 0, ctx->stream, roots,
-              d_count, cap, cells_of(box), g, dens_th, double(np), particle_th, group_particles, group_cells,
+              d_count, cap, cells_of(box), g, dens_th, double(np), particle_th, root_ok, group_particles, group_cells,
               group_keep);
     return launch_status();
 }
@@ -208,9 +246,24 @@ hf_status hf::groups_filter(hf_ctx *ctx, const hf_box &box, const int32_t *in, i
     return launch_status();
 }
 
+extern "C" hf_status hf_cross_scale(hf_ctx *ctx, const hf_box *box, const int32_t *roots, int64_t nroots,
+                                    const float *cwt_scale, const float *cwt_smaller, uint8_t *pass) {
+    if (!ctx) return HF_ERR_ARG;
+    hf_status s = check_box(box);
+    if (s != HF_OK) return s;
+    if (nroots < 0 || nroots > cells_of(*box)) return HF_ERR_ARG;
+    if (nroots == 0) return HF_OK;
+    if (!roots || !cwt_scale || !cwt_smaller || !pass) return HF_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    HF_LAUNCH(ctx, K_GROUP_CROSS, cross_scale_kernel, dim3(grid_of(ctx, nroots, GB)), dim3(GB), 0, ctx->stream, roots,
+              nroots, box->n, cwt_scale, cwt_smaller, pass, ctx->d_status);
+    return launch_status();
+}
+
 extern "C" hf_status hf_groups(hf_ctx *ctx, const hf_box *box, int64_t np, const int32_t *roots, int64_t nroots,
                                const int32_t *cell_label, const int32_t *particle_label, double dens_th,
-                               int64_t particle_th, uint32_t *group_particles, uint32_t *group_cells,
+                               int64_t particle_th, const uint8_t *root_ok, uint32_t *group_particles,
+                               uint32_t *group_cells,
                                uint8_t *group_keep, int32_t *cell_label_out, int32_t *particle_label_out, void *ws,
                                size_t ws_bytes) {
     if (!ctx || !cell_label) return HF_ERR_ARG;
@@ -229,8 +282,8 @@ extern "C" hf_status hf_groups(hf_ctx *ctx, const hf_box *box, int64_t np, const
         s = groups_count_cells(ctx, *box, roots, nullptr, nroots, cell_label, g);
         if (s == HF_OK) s = groups_count_particles(ctx, *box, particle_label, np, g);
         if (s == HF_OK)
-            s = groups_decide(ctx, *box, roots, nullptr, nroots, g, dens_th, np, particle_th, group_particles,
-                              group_cells, group_keep);
+            s = groups_decide(ctx, *box, roots, nullptr, nroots, g, dens_th, np, particle_th, root_ok,
+                              group_particles, group_cells, group_keep);
         if (s != HF_OK) return s;
     }
     s = groups_filter(ctx, *box, cell_label, cell_label_out, ncells, g, nroots > 0);

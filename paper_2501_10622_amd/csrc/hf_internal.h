@@ -19,7 +19,7 @@ enum KernelId {
     K_MAX_MARK, K_MAX_COUNT, K_MAX_SCAN, K_MAX_WRITE,
     K_PARENT, K_FLAGS, K_JUMP, K_FINALIZE,
     K_LABEL_TILES, K_LABEL_LEVEL1, K_LABEL_INPUT, K_RESOLVE,
-    K_GROUP_CLEAR, K_GROUP_CELLS, K_GROUP_PARTICLES, K_GROUP_DECIDE, K_GROUP_FILTER,
+    K_GROUP_CLEAR, K_GROUP_CELLS, K_GROUP_PARTICLES, K_GROUP_DECIDE, K_GROUP_FILTER, K_GROUP_CROSS,
     K_COUNT
 };
 const char *kernel_name(int id);
@@ -173,7 +173,8 @@ hf_status groups_count_particles(hf_ctx *ctx, const hf_box &box, const int32_t *
 // the filtered cell labels.
 hf_status groups_decide(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count, int64_t cap,
                         const GroupCounters &g, double dens_th, int64_t np, int64_t particle_th,
-                        uint32_t *group_particles, uint32_t *group_cells, uint8_t *group_keep);
+                        const uint8_t *root_ok, uint32_t *group_particles, uint32_t *group_cells,
+                        uint8_t *group_keep);
 hf_status groups_filter(hf_ctx *ctx, const hf_box &box, const int32_t *in, int32_t *out, int64_t count,
                         const GroupCounters &g, bool any_roots);
 

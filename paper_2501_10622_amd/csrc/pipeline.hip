@@ -98,7 +98,7 @@ extern "C" hf_status hf_find_halos_filtered(hf_ctx *ctx, const hf_box *box, cons
         if (s == HF_OK) s = label_tiles(ctx, *box, job->np, po, job->cell_label, sw, cap > 0 ? g.parts : nullptr);
         if (s == HF_OK)
             s = groups_decide(ctx, *box, job->max_idx, job->d_count, cap, g, gf->dens_th, job->np, gf->particle_th,
-                              gf->group_particles, gf->group_cells, gf->group_keep);
+                              nullptr, gf->group_particles, gf->group_cells, gf->group_keep);
         if (s == HF_OK && cap > 0) s = label_back(ctx, *box, job->np, po, job->particle_label, sw, g.cells);
         if (s == HF_OK && cap == 0) {
             s = label_back(ctx, *box, job->np, po, job->particle_label, sw, nullptr);
@@ -112,7 +112,7 @@ extern "C" hf_status hf_find_halos_filtered(hf_ctx *ctx, const hf_box *box, cons
         if (s == HF_OK && cap > 0) s = groups_count_particles(ctx, *box, job->particle_label, job->np, g);
         if (s == HF_OK)
             s = groups_decide(ctx, *box, job->max_idx, job->d_count, cap, g, gf->dens_th, job->np, gf->particle_th,
-                              gf->group_particles, gf->group_cells, gf->group_keep);
+                              nullptr, gf->group_particles, gf->group_cells, gf->group_keep);
         if (s == HF_OK)
             s = groups_filter(ctx, *box, job->particle_label, job->particle_label, job->np, g, cap > 0);
     }

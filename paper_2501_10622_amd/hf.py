@@ -26,7 +26,7 @@ EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_
            "hf_profile_enable", "hf_profile_reset", "hf_profile_read",
            "hf_cwt_batch_ws_size", "hf_cwt_batch", "hf_find_halos", "hf_find_halos_group", "hf_groups",
            "hf_find_halos_filtered", "hf_cwt_scales",
-           "hf_find_halos_scales_ws_size", "hf_find_halos_scales")
+           "hf_find_halos_scales_ws_size", "hf_find_halos_scales", "hf_cross_scale")
 CWT_BATCH_MAX = 32
 STAGE_ALL = 31
 STAGE_GROUPS = 32
@@ -113,7 +113,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "hf_find_halos": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job), vp, sz]),
             "hf_find_halos_group": (ctypes.c_int, [vp, i32, i32, i32, ctypes.POINTER(GroupItem), ctypes.c_int,
                                                    vp, sz]),
-            "hf_groups": (ctypes.c_int, [vp, bp, i64, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp, sz]),
+            "hf_groups": (ctypes.c_int, [vp, bp, i64, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp, vp, sz]),
+            "hf_cross_scale": (ctypes.c_int, [vp, bp, vp, i64, vp, vp, vp]),
             "hf_find_halos_filtered": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job), ctypes.POINTER(GroupFilter), vp,
                                                       sz]),
         }
@@ -335,9 +336,26 @@ def label(pos: torch.Tensor, box_len: float, n: int, cell_label: torch.Tensor, f
     return out
 
 
+def cross_scale(c_scale: torch.Tensor, c_smaller: torch.Tensor, roots: torch.Tensor, ctx=None) -> torch.Tensor:
+    """Step 8: uint8 flags, 1 where the maximum roots[i] of c_scale exceeds
+    c_smaller (the adjacent smaller scale, same grid) at its 27 grid points."""
+    _require_cuda(c_scale, "cwt")
+    if c_scale.dtype != torch.float32 or c_smaller.dtype != torch.float32 or c_scale.shape != c_smaller.shape:
+        raise ValueError("both fields must be float32 [n, n, n]")
+    if roots.dtype != torch.int32:
+        raise ValueError("roots must be int32")
+    n = c_scale.shape[0]
+    ctx = ctx or context(c_scale.device.index)
+    out = torch.empty(max(roots.numel(), 1), dtype=torch.uint8, device=c_scale.device)[: roots.numel()]
+    b = box(n, 1.0)
+    _check(load_library().hf_cross_scale(ctx.handle, ctypes.byref(b), _ptr(roots), roots.numel(), _ptr(c_scale),
+                                         _ptr(c_smaller), _ptr(out)), "hf_cross_scale")
+    return out
+
+
 def groups(cell_label: torch.Tensor, particle_label: torch.Tensor, roots: torch.Tensor, n_particles: int,
            dens_th: float = 4.0, particle_th: int = 15, filter_cells: bool = True, filter_particles: bool = True,
-           ctx=None) -> dict:
+           ctx=None, root_ok: torch.Tensor | None = None) -> dict:
     """Steps 5 and 7 (Table 1's dens_th, particle_th): per-group cell and
     particle numbers and keep flags for the sorted maxima list ``roots``, and
     the labels with disposed groups set to -1 (new tensors).  The counts are
@@ -362,9 +380,11 @@ def groups(cell_label: torch.Tensor, particle_label: torch.Tensor, roots: torch.
     b = box(n, 1.0)
     need = workspace_size(n, 1.0, 0, STAGE_GROUPS)
     ws = workspace(need, dev.index)
+    if root_ok is not None and (root_ok.dtype != torch.uint8 or root_ok.numel() != nroots):
+        raise ValueError("root_ok must be uint8 with one flag per root")
     _check(load_library().hf_groups(ctx.handle, ctypes.byref(b), int(n_particles), _ptr(roots), int(nroots),
                                     _ptr(cell_label), _ptr(particle_label), float(dens_th), int(particle_th),
-                                    _ptr(out["particles"]), _ptr(out["cells"]), _ptr(out["keep"]),
+                                    _ptr(root_ok), _ptr(out["particles"]), _ptr(out["cells"]), _ptr(out["keep"]),
                                     _ptr(out["cell_label"]), _ptr(out["particle_label"]), _ptr(ws), need),
            "hf_groups")
     return out

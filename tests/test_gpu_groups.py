@@ -140,7 +140,7 @@ def test_in_place_outputs_and_repeat_calls():
     p = hf._ptr
     for want in (want1, want2):
         code = hf.load_library().hf_groups(ctx.handle, ctypes.byref(b), 30000, p(droots), len(roots), p(dcl), p(dpl),
-                                           4.0, 15, p(gp), p(gc), p(gk), p(dcl), p(dpl), p(ws), need)
+                                           4.0, 15, None, p(gp), p(gc), p(gk), p(dcl), p(dpl), p(ws), need)
         assert code == 0
         ctx.sync()
         np.testing.assert_array_equal(gp.cpu().numpy(), want["particles"])
