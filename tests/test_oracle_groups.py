@@ -112,3 +112,19 @@ def test_invariants_and_idempotence_on_a_segmented_box():
     assert (r2["keep"] == r["keep"]).all()
     assert (r2["particle_label"] == r["particle_label"]).all()
     assert (r2["cell_label"] == r["cell_label"]).all()
+
+
+def test_root_mask_disposes_of_groups():
+    # step 8: a group whose maximum failed the cross-scale check goes, whatever its density
+    n = 4
+    cl = np.full(64, -1, dtype=np.int32)
+    cl[[5, 6, 9, 10]] = 5
+    cl[40:44] = 40
+    pl = np.array([5] * 10 + [40] * 10 + [-1] * 20, dtype=np.int32)
+    both = O.group_stats(cl.reshape(4, 4, 4), pl, [5, 40], n, 40, dens_th=1.0, particle_th=1)
+    assert both["keep"].tolist() == [True, True]
+    one = O.group_stats(cl.reshape(4, 4, 4), pl, [5, 40], n, 40, dens_th=1.0, particle_th=1, root_ok=[True, False])
+    assert one["keep"].tolist() == [True, False]
+    assert one["particles"].tolist() == both["particles"].tolist()
+    assert (one["particle_label"] == np.array([5] * 10 + [-1] * 30)).all()
+    assert set(one["cell_label"].ravel().tolist()) == {-1, 5}
