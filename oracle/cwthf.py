@@ -11,6 +11,7 @@ one scale:
   step 2  CIC assignment, Eq. (1)                   -> ``deposit``
   step 3  grid CWT, Eqs. (2)-(4)                    -> ``cwt``
   step 4  local maxima of the grid CWT              -> ``maxima``
+          and their correction for the grid (App. B) -> ``peaks``
   step 5  segmentation by the maxima (Sec. 2.3)     -> ``segment``
   step 6  particles take their cell's label         -> ``label``
 
@@ -33,7 +34,7 @@ __all__ = [
     "scale_w", "fixed_point", "deposit", "total_mass", "mean_mass", "normalise",
     "wavelet", "wavelet_hat", "sampled_kernel", "kernel_hat", "cwt_field", "cwt",
     "neighbour_offsets", "maxima", "parents", "segment", "ngp_nodes", "label",
-    "find_halos", "group_stats", "cross_scale", "DepositOverflow",
+    "find_halos", "group_stats", "cross_scale", "peaks", "DepositOverflow",
 ]
 
 
@@ -258,6 +259,44 @@ def maxima(c: np.ndarray, tau: float = 0.0) -> np.ndarray:
 # --------------------------------------------------------------------------
 # step 5: segmentation
 # --------------------------------------------------------------------------
+def peaks(c: np.ndarray, roots, box_len: float):
+    """Step 4's correction of grid maxima for the finite grid (App. B): per
+    axis, a quadratic through the maximum B and its two neighbours, A the
+    larger and C the smaller one.  With l1 = A - C and l2 = B - C the
+    quadratic's top lies l1^2 / (16 l2 - 8 l1) above B and, solving for its
+    vertex, l1 / (2 (2 l2 - l1)) cells from B towards A.  The three axes'
+    corrections are added to B's value and their shifts to B's position.
+
+    Reading: a flat axis (l2 = 0, so A = B = C) contributes nothing; the
+    comparison of maxima between grids of different spacing (the rest of
+    App. B) is not made, since every scale of a box uses one grid.  FP64.
+    Returns positions [k][3] (x, y, z) in box units, wrapped into [0, L), and
+    the corrected values [k].
+    """
+    c = _check_field(c).astype(np.float64)
+    n = c.shape[0]
+    dx = box_len / n
+    roots = np.asarray(roots, dtype=np.int64).ravel()
+    z, y, x = roots // (n * n), (roots // n) % n, roots % n
+    centre = c[z, y, x]
+    value = centre.copy()
+    pos = np.stack([x, y, z], axis=1).astype(np.float64)
+    for ax, (ex, ey, ez) in enumerate(((1, 0, 0), (0, 1, 0), (0, 0, 1))):
+        up = c[(z + ez) % n, (y + ey) % n, (x + ex) % n]
+        down = c[(z - ez) % n, (y - ey) % n, (x - ex) % n]
+        a = np.maximum(up, down)
+        low = np.minimum(up, down)
+        l1, l2 = a - low, centre - low
+        flat = l2 == 0.0
+        den = np.where(flat, 1.0, 16.0 * l2 - 8.0 * l1)
+        corr = np.where(flat, 0.0, l1 * l1 / den)
+        toward = np.where(up >= down, 1.0, -1.0)
+        shift = np.where(flat, 0.0, toward * l1 / np.where(flat, 1.0, 2.0 * (2.0 * l2 - l1)))
+        value = value + corr
+        pos[:, ax] = pos[:, ax] + shift
+    return np.mod(pos * dx, box_len), value
+
+
 def parents(c: np.ndarray) -> np.ndarray:
     """parent(j) = the cell of {j} + N26(j) that is largest in the (value, index) order."""
     c = _check_field(c)
