@@ -12,6 +12,7 @@
  *   hf_label    step 6  particles take the label of their segmented cell
  *   hf_groups   steps 5 and 7  grid volume, particle number and density filter
  *                       of every group (Table 1: dens_th, particle_th)
+ *   hf_peaks    step 4  sub-cell position and value of each maximum (App. B)
  *   hf_cross_scale  step 8  maxima that are also maxima across scale
  *
  * Conventions shared by every call
@@ -179,6 +180,21 @@ hf_status hf_groups(hf_ctx *ctx, const hf_box *box, int64_t np, const int32_t *r
                     int64_t particle_th, const uint8_t *root_ok, uint32_t *group_particles, uint32_t *group_cells,
                     uint8_t *group_keep, int32_t *cell_label_out, int32_t *particle_label_out, void *ws,
                     size_t ws_bytes);
+
+/* Step 4's correction of the grid maxima for the finite grid (App. B).  For
+ * each maximum roots[i] (device, e.g. hf_maxima's list) of the FP32 field cwt:
+ * per axis, with the maximum B and its two periodic neighbours A (the larger)
+ * and C (the smaller), l1 = A - C and l2 = B - C, the quadratic through them
+ * peaks l1^2 / (16 l2 - 8 l1) above B and l1 / (2 (2 l2 - l1)) cells from B
+ * towards A; a flat axis (l2 = 0) adds nothing.  value[i] = B plus the three
+ * axes' corrections; pos[3 i + 0..2] = (x, y, z) of B plus the shifts, in
+ * box_len units, wrapped into [0, box_len).  FP64, each operation rounded as
+ * written (no contraction).  pos [nroots][3], value [nroots]: device doubles.
+ * A NaN or a root outside [0, n^3) sets HF_ERR_INPUT.  The comparison of
+ * maxima between grids of different spacing (the rest of App. B) does not
+ * arise: every scale of a box uses one grid. */
+hf_status hf_peaks(hf_ctx *ctx, const hf_box *box, const float *cwt, const int32_t *roots, int64_t nroots,
+                   double *pos, double *value);
 
 /* Step 8: cross-scale maxima.  pass[i] = 1 iff cwt_scale[roots[i]] exceeds
  * (strictly) cwt_smaller at the root's cell and its 26 periodic neighbours,

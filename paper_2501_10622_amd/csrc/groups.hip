@@ -190,6 +190,55 @@ __global__ void __launch_bounds__(GB) cross_scale_kernel(const int32_t *__restri
     if (bad) atomicOr(status, ST_INPUT);
 }
 
+// Step 4's correction of grid maxima (App. B), in FP64 on the FP32 field: per
+// axis, with the maximum B and its neighbours A (larger) and C (smaller),
+// l1 = A - C and l2 = B - C, the quadratic through them peaks
+// l1^2 / (16 l2 - 8 l1) above B and l1 / (2 (2 l2 - l1)) cells towards A.  A
+// flat axis (l2 = 0) adds nothing.  Products, quotients and differences are
+// rounded one at a time (no contraction), as written.
+__global__ void __launch_bounds__(GB) peaks_kernel(const int32_t *__restrict__ roots, int64_t nroots, int n,
+                                                   double dx, double box_len, const float *__restrict__ c,
+                                                   double *__restrict__ pos, double *__restrict__ value,
+                                                   uint32_t *status) {
+    bool bad = false;
+    const uint32_t un = uint32_t(n), ncells = un * un * un;
+    for (int64_t i = blockIdx.x * int64_t(GB) + threadIdx.x; i < nroots; i += int64_t(gridDim.x) * GB) {
+        const int32_t r = roots[i];
+        if (r < 0 || uint32_t(r) >= ncells) {
+            bad = true;
+            continue;
+        }
+        const uint32_t g[3] = {uint32_t(r) % un, (uint32_t(r) / un) % un, uint32_t(r) / (un * un)};
+        const double b = double(c[r]);
+        bad |= b != b;
+        double v = b;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            uint32_t up[3] = {g[0], g[1], g[2]}, dn[3] = {g[0], g[1], g[2]};
+            up[ax] = (g[ax] + 1) % un;
+            dn[ax] = (g[ax] + un - 1) % un;
+            const double cu = double(c[(up[2] * un + up[1]) * un + up[0]]);
+            const double cd = double(c[(dn[2] * un + dn[1]) * un + dn[0]]);
+            bad |= (cu != cu) || (cd != cd);
+            const double a = cu > cd ? cu : cd, low = cu > cd ? cd : cu;
+            const double l1 = __dsub_rn(a, low), l2 = __dsub_rn(b, low);
+            double shift = 0.0;
+            if (l2 != 0.0) {
+                const double corr = __ddiv_rn(__dmul_rn(l1, l1), __dsub_rn(__dmul_rn(16.0, l2), __dmul_rn(8.0, l1)));
+                v = __dadd_rn(v, corr);
+                shift = __ddiv_rn(l1, __dmul_rn(2.0, __dsub_rn(__dmul_rn(2.0, l2), l1)));
+                if (!(cu >= cd)) shift = -shift;
+            }
+            double p = __dmul_rn(__dadd_rn(double(g[ax]), shift), dx);
+            p = fmod(p, box_len);
+            if (p < 0.0) p = __dadd_rn(p, box_len);
+            pos[3 * i + ax] = p;
+        }
+        value[i] = v;
+    }
+    if (bad) atomicOr(status, ST_INPUT);
+}
+
 unsigned grid_of(const hf_ctx *ctx, int64_t work, int64_t per_block) {
     const int64_t want = (work + per_block - 1) / per_block;
     const int64_t cap = int64_t(ctx->cus) * 32;
@@ -243,6 +292,20 @@ hf_status hf::groups_filter(hf_ctx *ctx, const hf_box &box, const int32_t *in, i
     if (count <= 0 || !out) return HF_OK;
     HF_LAUNCH(ctx, K_GROUP_FILTER, groups_filter_kernel, dim3(grid_of(ctx, count, GB * GPER)), dim3(GB), 0,
               ctx->stream, in, out, count, cells_of(box), g.cells, any_roots ? 1 : 0, ctx->d_status);
+    return launch_status();
+}
+
+extern "C" hf_status hf_peaks(hf_ctx *ctx, const hf_box *box, const float *cwt, const int32_t *roots, int64_t nroots,
+                              double *pos, double *value) {
+    if (!ctx) return HF_ERR_ARG;
+    hf_status s = check_box(box);
+    if (s != HF_OK) return s;
+    if (nroots < 0 || nroots > cells_of(*box)) return HF_ERR_ARG;
+    if (nroots == 0) return HF_OK;
+    if (!cwt || !roots || !pos || !value) return HF_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    HF_LAUNCH(ctx, K_PEAKS, peaks_kernel, dim3(grid_of(ctx, nroots, GB)), dim3(GB), 0, ctx->stream, roots, nroots,
+              box->n, box->box_len / box->n, box->box_len, cwt, pos, value, ctx->d_status);
     return launch_status();
 }
 

@@ -26,7 +26,7 @@ EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_
            "hf_profile_enable", "hf_profile_reset", "hf_profile_read",
            "hf_cwt_batch_ws_size", "hf_cwt_batch", "hf_find_halos", "hf_find_halos_group", "hf_groups",
            "hf_find_halos_filtered", "hf_cwt_scales",
-           "hf_find_halos_scales_ws_size", "hf_find_halos_scales", "hf_cross_scale")
+           "hf_find_halos_scales_ws_size", "hf_find_halos_scales", "hf_cross_scale", "hf_peaks")
 CWT_BATCH_MAX = 32
 STAGE_ALL = 31
 STAGE_GROUPS = 32
@@ -115,6 +115,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                                    vp, sz]),
             "hf_groups": (ctypes.c_int, [vp, bp, i64, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp, vp, sz]),
             "hf_cross_scale": (ctypes.c_int, [vp, bp, vp, i64, vp, vp, vp]),
+            "hf_peaks": (ctypes.c_int, [vp, bp, vp, vp, i64, vp, vp]),
             "hf_find_halos_filtered": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job), ctypes.POINTER(GroupFilter), vp,
                                                       sz]),
         }
@@ -334,6 +335,25 @@ def label(pos: torch.Tensor, box_len: float, n: int, cell_label: torch.Tensor, f
     _check(load_library().hf_label(ctx.handle, ctypes.byref(b), _ptr(pos), _dtype_code(pos), pos.shape[0],
                                    _ptr(cell_label), _ptr(out)), "hf_label")
     return out
+
+
+def peaks(c: torch.Tensor, roots: torch.Tensor, box_len: float, ctx=None):
+    """Step 4's correction of the maxima roots of c (App. B): FP64 positions
+    [k, 3] (x, y, z) in box units and corrected values [k]."""
+    _require_cuda(c, "cwt")
+    if c.dtype != torch.float32 or c.ndim != 3:
+        raise ValueError("cwt must be a float32 [n, n, n] grid")
+    if roots.dtype != torch.int32:
+        raise ValueError("roots must be int32")
+    n = c.shape[0]
+    ctx = ctx or context(c.device.index)
+    k = roots.numel()
+    pos = torch.empty((max(k, 1), 3), dtype=torch.float64, device=c.device)[:k]
+    val = torch.empty(max(k, 1), dtype=torch.float64, device=c.device)[:k]
+    b = box(n, box_len)
+    _check(load_library().hf_peaks(ctx.handle, ctypes.byref(b), _ptr(c), _ptr(roots), k, _ptr(pos), _ptr(val)),
+           "hf_peaks")
+    return pos, val
 
 
 def cross_scale(c_scale: torch.Tensor, c_smaller: torch.Tensor, roots: torch.Tensor, ctx=None) -> torch.Tensor:
