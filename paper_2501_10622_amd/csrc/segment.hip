@@ -252,19 +252,20 @@ __global__ void __launch_bounds__(WX * TY) parent_walk_kernel(const float *__res
     // row (WX >= 64) or rows y and y + 1 (WX = 32)
     const int x = threadIdx.x % WX, y = threadIdx.x / WX;
     const int lane = threadIdx.x & 63;
-    uint32_t gx[3], gy[3];  // global x / y of the halo columns / rows x - 1 .. x + 1, y - 1 .. y + 1
+    uint32_t gx[3], gy[3], gyn[3];  // global x / y of the halo columns / rows x - 1 .. x + 1, y - 1 .. y + 1
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         gx[d] = wrap(x0 + x + d - 1, n);
         gy[d] = wrap(y0 + y + d - 1, n);
+        gyn[d] = gy[d] * un;  // once per thread; the plane's part of the index is the same for the workgroup
     }
     // largest key of halo plane hz around the column
     auto plane_max = [&](int hz) {
-        const uint32_t row0 = wrap(z0 + hz - 1, n) * un;
+        const uint32_t plane = wrap(z0 + hz - 1, n) * un * un;
         uint64_t best = 0;
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
-            const uint32_t row = (row0 + gy[dy]) * un;
+            const uint32_t row = plane + gyn[dy];
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx)
                 best = kmax(best, (uint64_t(V[(hz * HY + y + dy) * WHX + x + dx]) << 32) | (row + gx[dx]));
