@@ -115,3 +115,23 @@ def test_serving_footprint_and_summary(lib):
     s = summarize(done)
     assert s["jobs"] == 100 and s["p50_ms"] <= s["p99_ms"] <= 5.0 + 1e-9
     assert abs(s["particles_per_s"] - 100 * 1000 / s["makespan_s"]) < 1e-6
+
+
+def test_header_is_plain_c99(tmp_path):
+    """include/hf.h is a C header: it compiles as strict C99 (no C++ in the
+    ABI), and every struct the entry points take is complete."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use_hf.c"
+    src.write_text('#include "hf.h"\n'
+                   "int main(void) {\n"
+                   "    return (int)(sizeof(hf_box) + sizeof(hf_job) + sizeof(hf_cwt_item) + sizeof(hf_group_item)\n"
+                   "                 + sizeof(hf_group_filter) + sizeof(hf_scale_job)) == 0;\n"
+                   "}\n")
+    include = os.path.join(ROOT, "include")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", "-I", include,
+                        str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
