@@ -10,6 +10,7 @@ one scale:
   step 1  k_w = w L / 1000                          -> ``scale_w``
   step 2  CIC assignment, Eq. (1)                   -> ``deposit``
   step 3  grid CWT, Eqs. (2)-(4)                    -> ``cwt``
+          or with the truncated stencil (Sec. 2.1)  -> ``stencil_cwt``
   step 4  local maxima of the grid CWT              -> ``maxima``
           and their correction for the grid (App. B) -> ``peaks``
   step 5  segmentation by the maxima (Sec. 2.3)     -> ``segment``
@@ -33,6 +34,7 @@ import numpy as np
 __all__ = [
     "scale_w", "fixed_point", "deposit", "total_mass", "mean_mass", "normalise",
     "wavelet", "wavelet_hat", "sampled_kernel", "kernel_hat", "cwt_field", "cwt",
+    "gdw_resolution", "stencil", "stencil_cwt_field", "stencil_cwt",
     "neighbour_offsets", "maxima", "parents", "segment", "ngp_nodes", "label",
     "find_halos", "group_stats", "cross_scale", "peaks", "DepositOverflow",
 ]
@@ -211,6 +213,60 @@ def cwt_field(f: np.ndarray, box_len: float, w: float, mode: str = "sampled") ->
 def cwt(rho: np.ndarray, box_len: float, kw: float, mode: str = "sampled") -> np.ndarray:
     """Step 3 on a CIC grid: normalise to the mean density, then Eq. (2)."""
     return cwt_field(normalise(rho), box_len, scale_w(kw, box_len), mode)
+
+
+# --------------------------------------------------------------------------
+# step 3 by the paper's own discretisation: the truncated real-space stencil
+# --------------------------------------------------------------------------
+def gdw_resolution(kw: float) -> int:
+    """Table 1's wavelet grid resolution Int(1.5 / k_w + 5).
+
+    Read as the stencil's half-width in cells: offsets -h..h on every axis,
+    2h + 1 points per axis (the paper does not say whether the count is the
+    half or the full width)."""
+    return int(1.5 / kw + 5.0)
+
+
+def stencil(n: int, box_len: float, w: float, half_width: int) -> np.ndarray:
+    """dx^3 Psi(w, d dx) on the cube of node offsets |d_i| <= h, [2h+1]^3.
+
+    Sec. 2.1: the wavelet sampled on the CIC grid spacing, truncated to the
+    stencil, with no periodic images (the stencil itself wraps on the box)."""
+    dx = box_len / n
+    d = np.arange(-half_width, half_width + 1, dtype=np.float64) * dx
+    r2 = d[:, None, None] ** 2 + d[None, :, None] ** 2 + d[None, None, :] ** 2
+    return wavelet(w, r2) * dx ** 3
+
+
+def stencil_cwt_field(f: np.ndarray, box_len: float, w: float, half_width: int) -> np.ndarray:
+    """Sec. 2.1's superposition: every grid point g adds f_g times the stencil
+    centred on g, periodically, C_j = sum_{|d_i| <= h} S_d f_{j - d}.
+
+    Points with f_g = 0 add nothing, so the sum runs over all of them at once:
+    one shifted copy of the grid per stencil offset, weighted and added (the
+    array additions the paper describes).  A stencil wider than the box
+    (2h + 1 > n) adds a point's wrapped offsets onto the same cells."""
+    f = np.asarray(f, dtype=np.float64)
+    n = f.shape[0]
+    h = int(half_width)
+    s = stencil(n, box_len, w, h)
+    c = np.zeros_like(f)
+    for iz, dz in enumerate(range(-h, h + 1)):
+        fz = np.roll(f, dz, axis=0)
+        for iy, dy in enumerate(range(-h, h + 1)):
+            fzy = np.roll(fz, dy, axis=1)
+            for ix, dxo in enumerate(range(-h, h + 1)):
+                c += s[iz, iy, ix] * np.roll(fzy, dxo, axis=2)
+    return c
+
+
+def stencil_cwt(rho: np.ndarray, box_len: float, kw: float, half_width: int | None = None) -> np.ndarray:
+    """Step 3 with the truncated stencil: normalise to the mean density, then
+    superpose; the half-width defaults to Table 1's gdw_resolution(k_w)."""
+    h = gdw_resolution(kw) if half_width is None else int(half_width)
+    if h < 0:
+        raise ValueError("half_width must be >= 0")
+    return stencil_cwt_field(normalise(rho), box_len, scale_w(kw, box_len), h)
 
 
 # --------------------------------------------------------------------------
