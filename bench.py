@@ -50,6 +50,8 @@ TIMER_SYMBOLS = {
     "groups_clear": ("groups_clear_kernel",), "groups_cells": ("groups_cells_kernel",),
     "groups_particles": ("groups_particles_kernel",), "groups_decide": ("groups_decide_kernel",),
     "groups_filter": ("groups_filter_kernel",),
+    "stencil_x": ("stencil_x_kernel",), "stencil_mass": ("stencil_mass_kernel",),
+    "stencil_y": ("stencil_axis_kernel<false>",), "stencil_z": ("stencil_axis_kernel<true>",),
 }
 
 
@@ -120,7 +122,8 @@ def short_symbol(name: str) -> str:
         return name
     tmpl = m.group(2) or ""
     # keep a template argument only where it names a different pass (fft_y_kernel<INV>, the scans' use)
-    return m.group(1) + (tmpl if m.group(1) in ("fft_y_kernel", "seg_reduce_kernel", "seg_scan_kernel") else "")
+    return m.group(1) + (tmpl if m.group(1) in ("fft_y_kernel", "seg_reduce_kernel", "seg_scan_kernel",
+                                                               "stencil_axis_kernel") else "")
 
 
 def timer_name(symbol: str):
@@ -527,6 +530,61 @@ def groups_bench(bufs: dict, n: int, np_: int, warmup: int, iters: int, ctx) -> 
             "frac": round(nbytes / kernel_ms / 1e6 / HBM_PEAK_GBS, 4), "checks": checks}
 
 
+def stencil_bench(rho, c_fft, box_len: float, n: int, kw: float, warmup: int, iters: int, ctx) -> dict:
+    """Step 3 by the paper's truncated real-space stencil (hf_cwt_stencil with
+    Table 1's half-width) on the step's density: `warmup` untimed calls, then
+    `iters` under the library's kernel timer (a trace sees warmup + iters calls,
+    as many as the step's launches).  Algorithmic bytes: the x pass reads rho and
+    writes two FP32 fields (16 B/cell), the y pass reads two and writes two
+    (16 B/cell), the z pass reads two and writes C (12 B/cell): 44 B/cell; the
+    strict bound reads rho and writes C (12 B/cell).  Also reported: the largest
+    difference from the step's FFT field relative to its peak, which is what the
+    stencil's truncation changes."""
+    import torch
+    import paper_2501_10622_amd as hfm
+    from paper_2501_10622_amd import hf
+    h = hfm.gdw_resolution(kw)
+    out = torch.empty_like(c_fft)
+    ws = torch.empty(hf.workspace_size(n, box_len, 0, hf.STAGE_STENCIL), dtype=torch.uint8, device=rho.device)
+    for _ in range(warmup):
+        hfm.cwt_stencil(rho, box_len, kw, h, out=out, ctx=ctx, ws=ws)
+    ctx.sync()
+    ctx.profile(True)
+    ctx.profile_reset()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(iters):
+        hfm.cwt_stencil(rho, box_len, kw, h, out=out, ctx=ctx, ws=ws)
+    stop.record()
+    torch.cuda.synchronize()
+    ctx.sync()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ms = start.elapsed_time(stop) / iters
+    kernels = {k: {"ms_per_call": round(v[0] / iters, 4), "launches_per_call": v[1] // iters}
+               for k, v in prof.items() if k.startswith("stencil_") and v[1]}
+    kernel_ms = sum(k["ms_per_call"] for k in kernels.values())
+    cells = n ** 3
+    model, strict = 44 * cells, 12 * cells
+    per_pass = {"stencil_x": 16 * cells, "stencil_y": 16 * cells, "stencil_z": 12 * cells}
+    for k, b in per_pass.items():
+        if k in kernels:
+            kernels[k]["GBps"] = round(b / kernels[k]["ms_per_call"] / 1e6, 1)
+    peak = float(c_fft.abs().max())
+    diff = float((out - c_fft).abs().max()) / peak
+    del ws, out
+    torch.cuda.empty_cache()
+    log(f"stencil CWT (half-width {h}): {ms:.3f} ms per call, {model / kernel_ms / 1e6:.0f} GB/s on 44 B/cell; "
+        f"max |C_stencil - C_fft| = {diff:.3e} of the peak")
+    return {"what": "grid CWT by the truncated real-space stencil of Sec. 2.1, three separable passes",
+            "half_width": h, "ms_per_call": round(ms, 4), "kernels": kernels,
+            "model_bytes": model, "GBps_model": round(model / kernel_ms / 1e6, 1),
+            "frac_model": round(model / kernel_ms / 1e6 / HBM_PEAK_GBS, 4),
+            "strict_bytes": strict, "GBps_strict": round(strict / kernel_ms / 1e6, 1),
+            "frac_strict": round(strict / kernel_ms / 1e6 / HBM_PEAK_GBS, 4),
+            "max_abs_diff_from_fft_rel_peak": diff}
+
+
 def scales_bench(rho, box_len: float, n: int, kernel: str, iters: int, ctx) -> dict:
     """The transform of the step's density at three scales (a = 1, 2 and 4 cells),
     once with one forward transform for all of them (hf_cwt_scales) and once as
@@ -639,6 +697,7 @@ def main():
     ap.add_argument("--kernel", default="sampled", choices=["sampled", "analytic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-groups", action="store_true", help="skip the group statistics measurement")
+    ap.add_argument("--no-stencil", action="store_true", help="skip the real-space stencil CWT measurement")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--summarize-profiles", nargs=2, metavar=("TRACE_DIR", "PMC_DIR"),
                     help="write the committed summaries of a kernel trace and of the counter runs")
@@ -816,6 +875,8 @@ def main():
         "kernels": kernels,
         "checks": {"mass_exact": mass_ok, "labelled_roots_are_maxima": roots_ok, "maxima": nmax},
     }
+    if not multi and not args.no_stencil:
+        out["stencil"] = stencil_bench(bufs["rho"], bufs["cwt"], L, n, kw, args.warmup, 2 * args.steps, ctx)
     if not args.no_groups and not multi:
         out["cwt_scales"] = scales_bench(bufs["rho"], L, n, args.kernel, 3, ctx)
         out["groups"] = groups_bench(bufs, n, cfg.n_particles, args.warmup, 2 * args.steps, ctx)

@@ -6,7 +6,8 @@
  *
  *   hf_deposit  step 2  cloud-in-cell mass on a periodic n^3 grid, Eq. (1)
  *   hf_cwt      step 3  grid CWT with the Mexican-hat wavelet, Eqs. (2)-(4)
- *               (hf_cwt_batch: several grids; hf_cwt_scales: several scales)
+ *               (hf_cwt_batch: several grids; hf_cwt_scales: several scales;
+ *               hf_cwt_stencil: the truncated real-space stencil of Sec. 2.1)
  *   hf_maxima   step 4  local maxima of the grid CWT
  *   hf_segment  step 5  segmentation of the grid by the maxima (Sec. 2.3)
  *   hf_label    step 6  particles take the label of their segmented cell
@@ -81,7 +82,8 @@ typedef struct {
  * hf_find_halos), a region that carries the deposit's particle order to the
  * label step: about 13 bytes per particle plus 8 per particle of label scratch. */
 enum { HF_STAGE_DEPOSIT = 1, HF_STAGE_CWT = 2, HF_STAGE_MAXIMA = 4, HF_STAGE_SEGMENT = 8, HF_STAGE_LABEL = 16,
-       HF_STAGE_ALL = 31, HF_STAGE_GROUPS = 32 /* hf_groups; not part of HF_STAGE_ALL */ };
+       HF_STAGE_ALL = 31, HF_STAGE_GROUPS = 32 /* hf_groups; not part of HF_STAGE_ALL */,
+       HF_STAGE_STENCIL = 64 /* hf_cwt_stencil; not part of HF_STAGE_ALL */ };
 
 typedef struct hf_ctx hf_ctx;
 
@@ -121,6 +123,23 @@ hf_status hf_deposit(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype d
  *  all-zero rho -> HF_ERR_INPUT.  Workspace: HF_STAGE_CWT. */
 hf_status hf_cwt(hf_ctx *ctx, const hf_box *box, const int64_t *rho, double kw, hf_kernel kernel,
                  float *cwt, void *ws, size_t ws_bytes);
+
+/* Step 3 by the paper's own discretisation (Sec. 2.1, Eq. (2) last line):
+ * every grid point adds its mass times the wavelet of Eq. (4), sampled at the
+ * grid spacing on the cube of node offsets |d_i| <= half_width around it
+ * (periodic; no wavelet images).  Table 1's gdw_resolution, Int(1.5/k_w + 5),
+ * is the paper's half_width; a stencil wider than the box wraps onto itself.
+ *  rho [n][n][n] int64 (>= 0, not all zero); cwt [n][n][n] FP32 (overwritten).
+ *  C_j = sum_{|d_i| <= h} S_d f_{j-d}, f = rho / mean(rho) as in hf_cwt and
+ *  S_d = dx^3 Psi(w, |d| dx).  Computed in FP32 as seven one-dimensional
+ *  convolutions in three passes (the cube stencil is a sum of four separable
+ *  terms); weights and the mean in FP64.  0 <= half_width <=
+ *  HF_STENCIL_MAX_HALF_WIDTH, else HF_ERR_ARG.  rho and cwt must not overlap
+ *  each other or the workspace.  Negative or all-zero rho -> HF_ERR_INPUT.
+ *  Workspace: HF_STAGE_STENCIL (three FP32 grids). */
+#define HF_STENCIL_MAX_HALF_WIDTH 64
+hf_status hf_cwt_stencil(hf_ctx *ctx, const hf_box *box, const int64_t *rho, double kw, int32_t half_width,
+                         float *cwt, void *ws, size_t ws_bytes);
 
 /* Step 4: local maxima.  Cell j is a maximum iff (C_j, j) beats all 26
  * periodic neighbours in the order "larger value, then larger index"

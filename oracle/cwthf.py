@@ -34,7 +34,7 @@ import numpy as np
 __all__ = [
     "scale_w", "fixed_point", "deposit", "total_mass", "mean_mass", "normalise",
     "wavelet", "wavelet_hat", "sampled_kernel", "kernel_hat", "cwt_field", "cwt",
-    "gdw_resolution", "stencil", "stencil_cwt_field", "stencil_cwt",
+    "gdw_resolution", "stencil", "stencil_cwt_field", "stencil_cwt", "stencil_cwt_at",
     "neighbour_offsets", "maxima", "parents", "segment", "ngp_nodes", "label",
     "find_halos", "group_stats", "cross_scale", "peaks", "DepositOverflow",
 ]
@@ -258,6 +258,29 @@ def stencil_cwt_field(f: np.ndarray, box_len: float, w: float, half_width: int) 
             for ix, dxo in enumerate(range(-h, h + 1)):
                 c += s[iz, iy, ix] * np.roll(fzy, dxo, axis=2)
     return c
+
+
+def stencil_cwt_at(rho: np.ndarray, box_len: float, kw: float, half_width: int, cells) -> np.ndarray:
+    """stencil_cwt at the given linear cell indices only, each a sum over its
+    own (2h+1)^3 window of f = rho / mean, for grids too large to superpose
+    whole.  The mean is that of the whole grid."""
+    rho = np.asarray(rho)
+    n = rho.shape[0]
+    h = int(half_width)
+    mbar = mean_mass(rho)
+    if mbar == 0.0:
+        raise ValueError("empty grid: the mean density is zero")
+    s = stencil(n, box_len, scale_w(kw, box_len), h)
+    out = np.empty(len(cells), dtype=np.float64)
+    for k, j in enumerate(np.asarray(cells, dtype=np.int64).tolist()):
+        z, y, x = j // (n * n), (j // n) % n, j % n
+        # window[a, b, c] = f at (z, y, x) - d for d = (a, b, c) - h, matching S_d
+        iz = [(z - d) % n for d in range(-h, h + 1)]
+        iy = [(y - d) % n for d in range(-h, h + 1)]
+        ix = [(x - d) % n for d in range(-h, h + 1)]
+        win = rho[np.ix_(iz, iy, ix)].astype(np.float64) / mbar
+        out[k] = float(np.sum(s * win))
+    return out
 
 
 def stencil_cwt(rho: np.ndarray, box_len: float, kw: float, half_width: int | None = None) -> np.ndarray:

@@ -1,13 +1,13 @@
 """MI355X-native single-scale hot path of the CWT halo finder (arXiv:2501.10622).
 
 Stages (HIP kernels in libhf.so, C ABI in include/hf.h): CIC deposit, grid CWT
-by FFT, 26-neighbour maxima, steepest-ascent segmentation, particle labels, and
+by FFT (or by the paper's truncated real-space stencil), 26-neighbour maxima, steepest-ascent segmentation, particle labels, and
 the group statistics and density filter that follow them.
 """
 from .hf import (  # noqa: F401
     CWT_BATCH_MAX, EXPORTS, HFError, LIB_PATH, Context, context, cross_scale, cwt, cwt_batch, cwt_batch_ws_bytes,
-    cwt_scales, deposit,
+    cwt_scales, cwt_stencil, deposit, gdw_resolution,
     find_halos, find_halos_async, find_halos_filtered_async, find_halos_group_async, find_halos_scales_async,
-    groups, job_buffers, label, load_library, maxima, peaks, scales_buffers, segment,
+    groups, job_buffers, label, load_library, maxima, peaks, scales_buffers, segment, STENCIL_MAX_HALF_WIDTH,
     status_str, sync, workspace_size,
 )

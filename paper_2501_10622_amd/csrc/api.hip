@@ -21,7 +21,7 @@ const char *hf::kernel_name(int id) {
         "parent", "jump_flags", "jump", "finalize",
         "label_tiles", "label_level1", "label_input", "resolve",
         "groups_clear", "groups_cells", "groups_particles", "groups_decide", "groups_filter", "cross_scale",
-        "peaks",
+        "peaks", "stencil_x", "stencil_mass", "stencil_y", "stencil_z",
     };
     return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
@@ -165,7 +165,7 @@ extern "C" hf_status hf_workspace_size(const hf_box *box, int64_t np, int stage_
     if (!bytes || np < 0) return HF_ERR_ARG;
     hf_status s = check_box(box);
     if (s != HF_OK) return s;
-    if (stage_mask & ~(HF_STAGE_ALL | HF_STAGE_GROUPS)) return HF_ERR_ARG;
+    if (stage_mask & ~(HF_STAGE_ALL | HF_STAGE_GROUPS | HF_STAGE_STENCIL)) return HF_ERR_ARG;
     // deposit + label: the deposit's particle order is kept for the labels in
     // a region of its own in front of the part the stages share in turn
     const bool order = (stage_mask & HF_STAGE_DEPOSIT) && (stage_mask & HF_STAGE_LABEL) &&
@@ -174,6 +174,7 @@ extern "C" hf_status hf_workspace_size(const hf_box *box, int64_t np, int stage_
     auto take = [&need](size_t b) { need = need > b ? need : b; };
     if (stage_mask & HF_STAGE_DEPOSIT) take(order ? deposit_tiled_ws_bytes(*box, np, true) : deposit_ws_bytes(*box, np));
     if (stage_mask & HF_STAGE_CWT) take(cwt_ws_bytes(*box));
+    if (stage_mask & HF_STAGE_STENCIL) take(stencil_ws_bytes(*box));
     if (stage_mask & HF_STAGE_MAXIMA) take(maxima_ws_bytes(*box));
     if (stage_mask & HF_STAGE_SEGMENT) take(segment_ws_bytes(*box));
     if ((stage_mask & HF_STAGE_MAXIMA) && (stage_mask & HF_STAGE_SEGMENT)) take(maxima_segment_ws_bytes(*box));

@@ -370,10 +370,6 @@ __device__ __forceinline__ void load_twiddles(float2 *tw_s, const float2 *tw_g, 
 // ---------------------------------------------------------------------------
 // Tables, generated in FP64 and stored as FP32.
 // ---------------------------------------------------------------------------
-struct Mass128 {
-    unsigned long long lo, hi;
-};
-
 // Per-job workspace layout (offsets from the job's workspace base).
 struct CwtLayout {
     size_t scalars, tw, gtab, htab, ctab, btab, ptab, mass, spec, total;
@@ -514,11 +510,6 @@ __global__ void __launch_bounds__(TAB_THREADS) tables_stage2(CwtJobs J, CwtLayou
 // x passes
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void add128(unsigned long long &lo, unsigned long long &hi, unsigned long long v) {
-    unsigned long long t = lo + v;
-    hi += (t < lo);
-    lo = t;
-}
 
 // One workgroup = xp row pairs (rows 2q, 2q+1 of the n*n rows of x).
 __global__ void fft_x_fwd_kernel(CwtJobs J, CwtLayout L, FftPlan pl, uint32_t *status) {
@@ -690,20 +681,6 @@ __global__ void fft_x_inv_kernel(CwtJobs J, CwtLayout L, FftPlan pl) {
 // ---------------------------------------------------------------------------
 // mean density and overall scale
 // ---------------------------------------------------------------------------
-// Correctly rounded conversion of a 128-bit unsigned integer to double.
-__device__ double u128_to_double(unsigned long long lo, unsigned long long hi) {
-    if (hi == 0) {
-        // split into 32-bit halves: both converts are exact, one rounding in the add
-        return double(uint32_t(lo >> 32)) * 4294967296.0 + double(uint32_t(lo));
-    }
-    const int lz = __clzll(hi);
-    const int sh = 64 - lz;  // bits to drop so the value fits 64 bits
-    unsigned long long top = (hi << lz) | (lo >> sh);
-    const unsigned long long dropped = lo & ((1ull << sh) - 1ull);
-    top |= (dropped != 0);  // sticky bit keeps round-to-nearest correct
-    const double t = double(uint32_t(top >> 32)) * 4294967296.0 + double(uint32_t(top));
-    return ldexp(t, sh);
-}
 
 __global__ void mass_kernel(CwtJobs J, CwtLayout L, int n, uint32_t *status) {
     const JobView jv = job_view(J, L, blockIdx.x);

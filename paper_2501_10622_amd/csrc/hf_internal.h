@@ -20,6 +20,7 @@ enum KernelId {
     K_PARENT, K_FLAGS, K_JUMP, K_FINALIZE,
     K_LABEL_TILES, K_LABEL_LEVEL1, K_LABEL_INPUT, K_RESOLVE,
     K_GROUP_CLEAR, K_GROUP_CELLS, K_GROUP_PARTICLES, K_GROUP_DECIDE, K_GROUP_FILTER, K_GROUP_CROSS, K_PEAKS,
+    K_ST_X, K_ST_MASS, K_ST_Y, K_ST_Z,
     K_COUNT
 };
 const char *kernel_name(int id);
@@ -193,6 +194,36 @@ size_t cwt_ws_bytes(const hf_box &box);
 size_t maxima_ws_bytes(const hf_box &box);
 size_t segment_ws_bytes(const hf_box &box);
 size_t groups_ws_bytes(const hf_box &box);
+size_t stencil_ws_bytes(const hf_box &box);
+
+// ---------------------------------------------------------------------------
+// Exact 128-bit sums of non-negative int64 cell masses (the mean density of a
+// grid is formed from the exact total).
+// ---------------------------------------------------------------------------
+struct Mass128 {
+    unsigned long long lo, hi;
+};
+
+__device__ __forceinline__ void add128(unsigned long long &lo, unsigned long long &hi, unsigned long long v) {
+    unsigned long long t = lo + v;
+    hi += (t < lo);
+    lo = t;
+}
+
+// Correctly rounded conversion of a 128-bit unsigned integer to double.
+__device__ inline double u128_to_double(unsigned long long lo, unsigned long long hi) {
+    if (hi == 0) {
+        // split into 32-bit halves: both converts are exact, one rounding in the add
+        return double(uint32_t(lo >> 32)) * 4294967296.0 + double(uint32_t(lo));
+    }
+    const int lz = __clzll(hi);
+    const int sh = 64 - lz;  // bits to drop so the value fits 64 bits
+    unsigned long long top = (hi << lz) | (lo >> sh);
+    const unsigned long long dropped = lo & ((1ull << sh) - 1ull);
+    top |= (dropped != 0);  // sticky bit keeps round-to-nearest correct
+    const double t = double(uint32_t(top >> 32)) * 4294967296.0 + double(uint32_t(top));
+    return ldexp(t, sh);
+}
 
 // ---------------------------------------------------------------------------
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.

@@ -1,0 +1,310 @@
+// Step 3 by the paper's own discretisation (Sec. 2.1): the grid CWT as the
+// superposition, around every grid point, of the wavelet of Eq. (4) sampled at
+// the grid spacing on the cube of node offsets |d_i| <= h (h = Table 1's
+// gdw_resolution by default), periodically wrapped on the box.
+//
+// On a cube of offsets the sampled wavelet is a sum of separable terms.  With
+// u = (w dx d)^2 per axis, A(d) = exp(-u/4), B(d) = u A(d) and P = dx^3 w^1.5,
+//   dx^3 Psi(w, d dx) = P [6 A_x A_y A_z - B_x A_y A_z - A_x B_y A_z - A_x A_y B_z],
+// so the (2h+1)^3-point superposition equals seven one-dimensional periodic
+// convolutions of 2h+1 taps, made in three streaming passes over the grid:
+//   x pass:  fA = A * rho,  fB = B * rho                (cell-mass units)
+//   y pass:  G = A * fA,    S = 6 G - A * fB - B * fA
+//   z pass:  C = (P / mean) (A * S - B * G)
+// Each pass reads its lines (plus h cells of halo at each end) into LDS and
+// every output sums its taps in pairs d, -d.  The mean cell mass comes from the
+// exact 128-bit total of rho, reduced in FP64 between the x and y passes.
+#include <cmath>
+
+#include "hf_internal.h"
+
+using namespace hf;
+
+namespace {
+
+constexpr int ST_THREADS = 256;
+constexpr int ST_LANES = 64;          // x columns of a y- or z-pass tile (one wavefront row)
+constexpr int ST_GROUPS = ST_THREADS / ST_LANES;
+constexpr int ST_T = 64;              // outputs along the pass axis per tile
+constexpr int ST_X_CELLS = 4096;      // line-buffer cells per x-pass workgroup (whole rows)
+
+struct StencilLayout {
+    size_t scalars, mass, g0, g1, g2, total;
+    int64_t xblocks;
+    int xrows;
+};
+
+StencilLayout stencil_layout(int n) {
+    StencilLayout L{};
+    // about ST_X_CELLS cells of line buffer per workgroup at the widest stencil
+    const int64_t rows = int64_t(n) * n;
+    const int64_t per = ST_X_CELLS / (n + 2 * HF_STENCIL_MAX_HALF_WIDTH);
+    L.xrows = int(per < 1 ? 1 : (per < rows ? per : rows));
+    L.xblocks = (rows + L.xrows - 1) / L.xrows;
+    const size_t grid = sizeof(float) * size_t(n) * size_t(n) * size_t(n);
+    size_t off = 0;
+    L.scalars = off;
+    off = align_up(off + 2 * sizeof(double));
+    L.mass = off;
+    off = align_up(off + sizeof(Mass128) * size_t(L.xblocks));
+    L.g0 = off;
+    off = align_up(off + grid);
+    L.g1 = off;
+    off = align_up(off + grid);
+    L.g2 = off;
+    off = align_up(off + grid);
+    L.total = off;
+    return L;
+}
+
+// A(d) and B(d) for d = 0..h into LDS, in FP64 rounded once to FP32.
+__device__ __forceinline__ void stencil_weights(float *wa, float *wb, int h, double wdx) {
+    for (int d = threadIdx.x; d <= h; d += blockDim.x) {
+        const double t = wdx * double(d);
+        const double u = t * t;
+        const double a = exp(-0.25 * u);
+        wa[d] = float(a);
+        wb[d] = float(u * a);
+    }
+}
+
+__device__ __forceinline__ int wrap(int t, int n) {
+    t %= n;
+    return t < 0 ? t + n : t;
+}
+
+// x pass: xrows whole rows per workgroup; row r of the grid (r = z n + y) is
+// read once with h cells of periodic halo on either side.
+__global__ void __launch_bounds__(ST_THREADS)
+    stencil_x_kernel(const int64_t *__restrict__ rho, float *__restrict__ fa, float *__restrict__ fb,
+                     Mass128 *__restrict__ mass, int n, int h, int xrows, double wdx, uint32_t *status) {
+    extern __shared__ float sm[];
+    float *wa = sm, *wb = sm + (h + 1);
+    float *buf = sm + 2 * (h + 1);
+    const int tid = threadIdx.x;
+    const int W = n + 2 * h;
+    const int64_t nrows = int64_t(n) * n;
+    const int64_t row0 = int64_t(blockIdx.x) * xrows;
+    const int rows = int(nrows - row0 < xrows ? nrows - row0 : xrows);
+    stencil_weights(wa, wb, h, wdx);
+    unsigned long long lo = 0, hi = 0;
+    bool neg = false;
+    for (int r = 0; r < rows; ++r) {
+        const int64_t *src = rho + (row0 + r) * n;
+        float *line = buf + r * W;
+        for (int i = tid; i < W; i += ST_THREADS) {
+            const int x = wrap(i - h, n);
+            const int64_t v = src[x];
+            if (i >= h && i < h + n) {  // each cell counted once, from its own slot
+                neg |= v < 0;
+                add128(lo, hi, static_cast<unsigned long long>(v));
+            }
+            line[i] = float(v);
+        }
+    }
+    if (neg) atomicOr(status, ST_INPUT);
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long olo = __shfl_down(lo, off, 64);
+        const unsigned long long ohi = __shfl_down(hi, off, 64);
+        add128(lo, hi, olo);
+        hi += ohi;
+    }
+    __shared__ unsigned long long red_lo[ST_THREADS / 64], red_hi[ST_THREADS / 64];
+    if ((tid & 63) == 0) {
+        red_lo[tid >> 6] = lo;
+        red_hi[tid >> 6] = hi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long L = 0, H = 0;
+        for (int w = 0; w < ST_THREADS / 64; ++w) {
+            add128(L, H, red_lo[w]);
+            H += red_hi[w];
+        }
+        mass[blockIdx.x].lo = L;
+        mass[blockIdx.x].hi = H;
+    }
+    const float a0 = wa[0];
+    for (int r = 0; r < rows; ++r) {
+        const float *line = buf + r * W + h;
+        float *oa = fa + (row0 + r) * n;
+        float *ob = fb + (row0 + r) * n;
+        for (int x = tid; x < n; x += ST_THREADS) {
+            const float *c = line + x;
+            float sa = a0 * c[0], sb = 0.0f;  // B(0) = 0
+            for (int d = 1; d <= h; ++d) {
+                const float s = c[d] + c[-d];
+                sa = fmaf(wa[d], s, sa);
+                sb = fmaf(wb[d], s, sb);
+            }
+            oa[x] = sa;
+            ob[x] = sb;
+        }
+    }
+}
+
+// Mean cell mass from the x pass's exact partial sums; scalars[0] = P / mean.
+__global__ void __launch_bounds__(1024)
+    stencil_mass_kernel(const Mass128 *__restrict__ mass, int64_t nparts, int n, double pref, double *scalars,
+                        uint32_t *status) {
+    __shared__ unsigned long long red_lo[16], red_hi[16];
+    unsigned long long lo = 0, hi = 0;
+    for (int64_t i = threadIdx.x; i < nparts; i += blockDim.x) {
+        add128(lo, hi, mass[i].lo);
+        hi += mass[i].hi;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long olo = __shfl_down(lo, off, 64);
+        const unsigned long long ohi = __shfl_down(hi, off, 64);
+        add128(lo, hi, olo);
+        hi += ohi;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red_lo[threadIdx.x >> 6] = lo;
+        red_hi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long L = 0, H = 0;
+        for (int w = 0; w < int(blockDim.x >> 6); ++w) {
+            add128(L, H, red_lo[w]);
+            H += red_hi[w];
+        }
+        const double cells = double(n) * double(n) * double(n);
+        const double mbar = u128_to_double(L, H) / cells;
+        if (!(mbar > 0.0)) {
+            atomicOr(status, ST_INPUT);
+            scalars[0] = 0.0;
+        } else {
+            scalars[0] = pref / mbar;
+        }
+        scalars[1] = mbar;
+    }
+}
+
+// y (ZPASS false, axis stride n) and z (ZPASS true, axis stride n^2) passes.
+// A tile is ST_LANES x columns by ST_T outputs along the axis at one value of
+// the third coordinate; it reads ST_T + 2h lines of both inputs into LDS.
+// Tiles that neighbour along the axis (and share halo lines) are consecutive
+// logical blocks, which xcd_remap keeps on one XCD.
+template <bool ZPASS>
+__global__ void __launch_bounds__(ST_THREADS)
+    stencil_axis_kernel(const float *__restrict__ in0, const float *__restrict__ in1, float *__restrict__ out0,
+                        float *__restrict__ out1, const double *__restrict__ scalars, int n, int h, int tiles_x,
+                        int tiles_t, double wdx) {
+    extern __shared__ float sm[];
+    const int R = ST_T + 2 * h;
+    float *wa = sm, *wb = sm + (h + 1);
+    float *b0 = sm + 2 * (h + 1);
+    float *b1 = b0 + R * ST_LANES;
+    const uint32_t lt = xcd_remap(blockIdx.x, gridDim.x);
+    const int tt = int(lt % uint32_t(tiles_t));
+    const uint32_t rest = lt / uint32_t(tiles_t);
+    const int tx = int(rest % uint32_t(tiles_x));
+    const int o = int(rest / uint32_t(tiles_x));
+    const int lane = threadIdx.x % ST_LANES, grp = threadIdx.x / ST_LANES;
+    const int x = tx * ST_LANES + lane;
+    const int t0 = tt * ST_T;
+    const size_t sn = size_t(n);
+    // element (x, t, o): y pass (z = o, y = t), z pass (z = t, y = o)
+    auto at = [sn, x, o](int t) -> size_t {
+        return ZPASS ? (size_t(t) * sn + size_t(o)) * sn + size_t(x) : (size_t(o) * sn + size_t(t)) * sn + size_t(x);
+    };
+    stencil_weights(wa, wb, h, wdx);
+    if (x < n) {
+        for (int r = grp; r < R; r += ST_GROUPS) {
+            const size_t e = at(wrap(t0 - h + r, n));
+            b0[r * ST_LANES + lane] = in0[e];
+            b1[r * ST_LANES + lane] = in1[e];
+        }
+    }
+    __syncthreads();
+    if (x >= n) return;
+    const float a0 = wa[0];
+    const double factor = ZPASS ? scalars[0] : 0.0;
+    for (int k = grp; k < ST_T; k += ST_GROUPS) {
+        const int t = t0 + k;
+        if (t >= n) break;
+        const float *c0 = b0 + (k + h) * ST_LANES + lane;
+        const float *c1 = b1 + (k + h) * ST_LANES + lane;
+        const size_t e = at(t);
+        if (!ZPASS) {
+            // in0 = fA, in1 = fB: G = A*fA, S = 6 G - A*fB - B*fA
+            float g = a0 * c0[0], ab = a0 * c1[0], ba = 0.0f;
+            for (int d = 1; d <= h; ++d) {
+                const float s0 = c0[d * ST_LANES] + c0[-d * ST_LANES];
+                const float s1 = c1[d * ST_LANES] + c1[-d * ST_LANES];
+                g = fmaf(wa[d], s0, g);
+                ab = fmaf(wa[d], s1, ab);
+                ba = fmaf(wb[d], s0, ba);
+            }
+            out0[e] = g;
+            out1[e] = 6.0f * g - ab - ba;
+        } else {
+            // in0 = G, in1 = S: C = (P / mean) (A*S - B*G)
+            float as = a0 * c1[0], bg = 0.0f;
+            for (int d = 1; d <= h; ++d) {
+                const float s0 = c0[d * ST_LANES] + c0[-d * ST_LANES];
+                const float s1 = c1[d * ST_LANES] + c1[-d * ST_LANES];
+                as = fmaf(wa[d], s1, as);
+                bg = fmaf(wb[d], s0, bg);
+            }
+            out0[e] = float(double(as - bg) * factor);
+        }
+    }
+}
+
+}  // namespace
+
+size_t hf::stencil_ws_bytes(const hf_box &box) { return stencil_layout(box.n).total; }
+
+extern "C" hf_status hf_cwt_stencil(hf_ctx *ctx, const hf_box *box, const int64_t *rho, double kw,
+                                    int32_t half_width, float *cwt, void *ws, size_t ws_bytes) {
+    if (!ctx || !rho || !cwt) return HF_ERR_ARG;
+    if (!(kw > 0.0) || !std::isfinite(kw)) return HF_ERR_ARG;
+    if (half_width < 0 || half_width > HF_STENCIL_MAX_HALF_WIDTH) return HF_ERR_ARG;
+    hf_status s = check_box(box);
+    if (s != HF_OK) return s;
+    const int n = box->n, h = half_width;
+    const StencilLayout L = stencil_layout(n);
+    s = check_ws(ws, ws_bytes, L.total);
+    if (s != HF_OK) return s;
+    const double dx = box->box_len / n;
+    const double w = 1000.0 * kw / box->box_len;
+    const double wdx = w * dx;
+    const double pref = dx * dx * dx * std::pow(w, 1.5);
+    if (!std::isfinite(wdx) || !(pref > 0.0) || !std::isfinite(pref)) return HF_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    char *b = static_cast<char *>(ws);
+    double *scalars = reinterpret_cast<double *>(b + L.scalars);
+    Mass128 *mass = reinterpret_cast<Mass128 *>(b + L.mass);
+    float *g0 = reinterpret_cast<float *>(b + L.g0);
+    float *g1 = reinterpret_cast<float *>(b + L.g1);
+    float *g2 = reinterpret_cast<float *>(b + L.g2);
+    const size_t x_shm = sizeof(float) * (2 * size_t(h + 1) + size_t(L.xrows) * size_t(n + 2 * h));
+    const size_t a_shm = sizeof(float) * (2 * size_t(h + 1) + 2 * size_t(ST_T + 2 * h) * ST_LANES);
+    auto allow = [](const void *f, size_t bytes) {
+        return bytes <= 65536 ||
+               hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)) == hipSuccess;
+    };
+    if (!allow(reinterpret_cast<const void *>(&stencil_x_kernel), x_shm) ||
+        !allow(reinterpret_cast<const void *>(&stencil_axis_kernel<false>), a_shm) ||
+        !allow(reinterpret_cast<const void *>(&stencil_axis_kernel<true>), a_shm))
+        return HF_ERR_DEVICE;
+    const int tiles_x = (n + ST_LANES - 1) / ST_LANES;
+    const int tiles_t = (n + ST_T - 1) / ST_T;
+    const unsigned tiles = unsigned(tiles_x) * unsigned(tiles_t) * unsigned(n);
+    hipStream_t st = ctx->stream;
+    // x pass: fA -> g0, fB -> cwt (the output doubles as the x pass's second field)
+    HF_LAUNCH(ctx, K_ST_X, stencil_x_kernel, dim3(unsigned(L.xblocks)), dim3(ST_THREADS), x_shm, st, rho, g0, cwt,
+              mass, n, h, L.xrows, wdx, ctx->d_status);
+    HF_LAUNCH(ctx, K_ST_MASS, stencil_mass_kernel, dim3(1), dim3(1024), 0, st, mass, L.xblocks, n, pref, scalars,
+              ctx->d_status);
+    // y pass: (fA, fB) -> (G -> g1, S -> g2)
+    HF_LAUNCH(ctx, K_ST_Y, stencil_axis_kernel<false>, dim3(tiles), dim3(ST_THREADS), a_shm, st, g0, cwt, g1, g2,
+              scalars, n, h, tiles_x, tiles_t, wdx);
+    // z pass: (G, S) -> C
+    HF_LAUNCH(ctx, K_ST_Z, stencil_axis_kernel<true>, dim3(tiles), dim3(ST_THREADS), a_shm, st, g1, g2, cwt, nullptr,
+              scalars, n, h, tiles_x, tiles_t, wdx);
+    return launch_status();
+}

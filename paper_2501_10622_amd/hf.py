@@ -26,10 +26,13 @@ EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_
            "hf_profile_enable", "hf_profile_reset", "hf_profile_read",
            "hf_cwt_batch_ws_size", "hf_cwt_batch", "hf_find_halos", "hf_find_halos_group", "hf_groups",
            "hf_find_halos_filtered", "hf_cwt_scales",
-           "hf_find_halos_scales_ws_size", "hf_find_halos_scales", "hf_cross_scale", "hf_peaks")
+           "hf_find_halos_scales_ws_size", "hf_find_halos_scales", "hf_cross_scale", "hf_peaks",
+           "hf_cwt_stencil")
 CWT_BATCH_MAX = 32
 STAGE_ALL = 31
 STAGE_GROUPS = 32
+STAGE_STENCIL = 64
+STENCIL_MAX_HALF_WIDTH = 64
 
 
 class HFError(RuntimeError):
@@ -96,6 +99,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "hf_workspace_size": (ctypes.c_int, [bp, i64, ctypes.c_int, ctypes.POINTER(sz)]),
             "hf_deposit": (ctypes.c_int, [vp, bp, vp, ctypes.c_int, i64, vp, vp, sz]),
             "hf_cwt": (ctypes.c_int, [vp, bp, vp, dbl, ctypes.c_int, vp, vp, sz]),
+            "hf_cwt_stencil": (ctypes.c_int, [vp, bp, vp, dbl, i32, vp, vp, sz]),
             "hf_maxima": (ctypes.c_int, [vp, bp, vp, flt, vp, i64, vp, vp, sz]),
             "hf_segment": (ctypes.c_int, [vp, bp, vp, flt, vp, vp, sz]),
             "hf_label": (ctypes.c_int, [vp, bp, vp, ctypes.c_int, i64, vp, vp]),
@@ -276,6 +280,34 @@ def cwt(rho: torch.Tensor, box_len: float, kw: float, kernel: str = "sampled", o
     ws = workspace(need, rho.device.index)
     _check(load_library().hf_cwt(ctx.handle, ctypes.byref(b), _ptr(rho), float(kw), KERNELS[kernel], _ptr(out),
                                  _ptr(ws), need), "hf_cwt")
+    return out
+
+
+def gdw_resolution(kw: float) -> int:
+    """Table 1's wavelet grid resolution Int(1.5 / k_w + 5): the stencil half-width."""
+    return int(1.5 / kw + 5.0)
+
+
+def cwt_stencil(rho: torch.Tensor, box_len: float, kw: float, half_width: int | None = None, out=None, ctx=None,
+                frac_bits: int = 15, ws=None) -> torch.Tensor:
+    """Step 3 by the truncated real-space stencil of Sec. 2.1 (FP32), half-width
+    gdw_resolution(kw) unless given.  Enqueued on the context's stream."""
+    _require_cuda(rho, "rho")
+    if rho.dtype != torch.int64 or rho.ndim != 3:
+        raise ValueError("rho must be an int64 [n, n, n] grid")
+    n = rho.shape[0]
+    h = gdw_resolution(kw) if half_width is None else int(half_width)
+    ctx = ctx or context(rho.device.index)
+    if out is None:
+        out = torch.empty((n, n, n), dtype=torch.float32, device=rho.device)
+    b = box(n, box_len, frac_bits)
+    need = workspace_size(n, box_len, 0, STAGE_STENCIL, frac_bits)
+    if ws is None:
+        ws = workspace(need, rho.device.index)
+    elif ws.numel() * ws.element_size() < need:
+        raise ValueError("workspace too small for hf_cwt_stencil")
+    _check(load_library().hf_cwt_stencil(ctx.handle, ctypes.byref(b), _ptr(rho), float(kw), h, _ptr(out), _ptr(ws),
+                                         ws.numel() * ws.element_size()), "hf_cwt_stencil")
     return out
 
 

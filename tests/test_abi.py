@@ -59,7 +59,10 @@ def test_frac_bits_and_box_checks(lib):
         assert lib.hf_workspace_size(ctypes.byref(b), 0, hf.STAGE_DEPOSIT, ctypes.byref(out)) == hf.HF_ERR_ARG
     b = hf.Box(16, 15, 10.0)
     assert lib.hf_workspace_size(ctypes.byref(b), -1, hf.STAGE_DEPOSIT, ctypes.byref(out)) == hf.HF_ERR_ARG
-    assert lib.hf_workspace_size(ctypes.byref(b), 0, 64, ctypes.byref(out)) == hf.HF_ERR_ARG
+    assert lib.hf_workspace_size(ctypes.byref(b), 0, 128, ctypes.byref(out)) == hf.HF_ERR_ARG
+    # the stencil stage: three FP32 grids and a few partial sums
+    assert lib.hf_workspace_size(ctypes.byref(b), 0, hf.STAGE_STENCIL, ctypes.byref(out)) == hf.HF_OK
+    assert 3 * 4 * 16 ** 3 <= out.value <= 3 * 4 * 16 ** 3 + 64 * 1024
 
 
 def test_workspace_grows_with_n(lib):

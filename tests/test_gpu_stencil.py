@@ -1,0 +1,128 @@
+"""Step 3 by the truncated real-space stencil (Sec. 2.1; hf_cwt_stencil) against
+the FP64 oracle's superposition: max |C32 - C64| <= 1e-5 max |C64|, the CWT
+tolerance, on seeded clustered boxes whose grids span several tiles with ragged
+edges, at sub-cell scales, with the one-tap stencil and with stencils wider
+than the box; at 1024^3 on sampled cells in the benchmark's configuration."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import CWT_RTOL, O, cuda, cwt_error, ensure_built, small_box
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    ensure_built()
+
+
+def hfm():
+    import paper_2501_10622_amd as m
+    return m
+
+
+@pytest.mark.parametrize("n,L,np_,halos,a,h", [
+    (32, 32.0, 32 ** 3, 40, 1.0, 4),
+    (64, 100.0, 64 ** 3, 200, 2.0, 7),     # one full 64 x 64 tile per pass
+    (96, 96.0, 300000, 100, 3.0, 5),       # radix 3: ragged x tiles and line tails
+    (48, 60.0, 100000, 50, 0.46, 5),       # sub-cell scale (the paper's k_w = 2.5 regime)
+    (24, 30.0, 50000, 20, 1.5, 15),        # 2h + 1 = 31 > 24: the stencil wraps onto itself
+    (32, 40.0, 60000, 30, 2.5, 12),
+    (8, 10.0, 2000, 3, 1.0, 0),            # one tap: C = 6 P f
+    (8, 10.0, 2000, 3, 1.0, 9),            # 19 taps on an 8-cell axis
+])
+def test_stencil_within_tolerance(n, L, np_, halos, a, h):
+    pos = small_box(n, L, np_, halos, "f32", 61)
+    kw = n / (1000.0 * a)
+    print(f"stencil n={n} a={a} h={h}", flush=True)
+    rho = hfm().deposit(cuda(pos), L, n)
+    c = hfm().cwt_stencil(rho, L, kw, h)
+    hfm().sync()
+    c64 = O.stencil_cwt(rho.cpu().numpy(), L, kw, h)
+    assert cwt_error(c.cpu().numpy(), c64) <= CWT_RTOL
+
+
+def test_widest_stencil_matches_the_fft_path():
+    # h = 64 on a 128 box at a = 1.5 cells: the truncation and the one wrapped
+    # line weigh exp(-(64/1.5)^2/4) ~ 1e-198, so both paths compute the sampled
+    # periodic convolution; each is within 1e-5 of it
+    n, L, a = 128, 128.0, 1.5
+    pos = small_box(n, L, 400000, 300, "f32", 62)
+    kw = n / (1000.0 * a)
+    rho = hfm().deposit(cuda(pos), L, n)
+    c_st = hfm().cwt_stencil(rho, L, kw, hfm().STENCIL_MAX_HALF_WIDTH)
+    c_fft = hfm().cwt(rho, L, kw, "sampled")
+    hfm().sync()
+    peak = float(c_fft.abs().max())
+    assert float((c_st - c_fft).abs().max()) <= 2 * CWT_RTOL * peak
+
+
+def test_default_half_width_is_table1_rule():
+    n, L = 64, 64.0
+    pos = small_box(n, L, 100000, 60, "f32", 63)
+    kw = 0.5  # gdw_resolution = Int(3 + 5) = 8
+    assert hfm().gdw_resolution(kw) == 8
+    rho = hfm().deposit(cuda(pos), L, n)
+    a = hfm().cwt_stencil(rho, L, kw)
+    b = hfm().cwt_stencil(rho, L, kw, 8)
+    hfm().sync()
+    assert torch.equal(a, b)  # fixed summation order: deterministic
+
+
+def test_errors():
+    from paper_2501_10622_amd.hf import HF_ERR_ARG, HF_ERR_INPUT, HFError
+    n, L = 16, 16.0
+    rho = torch.zeros((n, n, n), dtype=torch.int64, device="cuda")
+    for h in (-1, 65):
+        with pytest.raises(HFError) as e:
+            hfm().cwt_stencil(rho, L, 0.5, h)
+        assert e.value.code == HF_ERR_ARG
+    for kw in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(HFError) as e:
+            hfm().cwt_stencil(rho, L, kw, 2)
+        assert e.value.code == HF_ERR_ARG
+    hfm().cwt_stencil(rho, L, 0.5, 2)  # all-zero grid: found on the device
+    with pytest.raises(HFError) as e:
+        hfm().sync()
+    assert e.value.code == HF_ERR_INPUT
+    rho[3, 4, 5] = 1 << 40
+    rho[0, 0, 1] = -7
+    hfm().cwt_stencil(rho, L, 0.5, 2)
+    with pytest.raises(HFError) as e:
+        hfm().sync()
+    assert e.value.code == HF_ERR_INPUT
+    rho[0, 0, 1] = 0
+    c = hfm().cwt_stencil(rho, L, 0.5, 2)
+    hfm().sync()
+    # a unit point: the stencil itself around it, zero beyond the half-width
+    s = O.stencil(n, L, O.scale_w(0.5, L), 2) * n ** 3
+    got = c.cpu().numpy()
+    np.testing.assert_allclose(got[1:6, 2:7, 3:8], s, rtol=1e-5, atol=1e-5 * np.abs(s).max())
+    got[1:6, 2:7, 3:8] = 0.0
+    assert not got.any()
+
+
+def test_full_size_sampled_cells():
+    # 1024^3 box of 2^30 particles, a = 2 cells: k_w = 0.512, Table 1's half-width 7
+    import synth
+    cfg = synth.CONFIGS["M4"]
+    n, L = cfg.n, cfg.box_len
+    kw = cfg.kw_list[0]
+    h = hfm().gdw_resolution(kw)
+    print(f"stencil full size n={n} kw={kw} h={h}", flush=True)
+    pos = synth.make_config_box(cfg, device="cuda")
+    rho = hfm().deposit(pos, L, n)
+    del pos
+    c = hfm().cwt_stencil(rho, L, kw)
+    hfm().sync()
+    # the 64 largest values (halo cores) and 192 seeded random cells
+    top = torch.topk(c.view(-1), 64).indices.cpu().numpy()
+    rnd = np.random.default_rng(64).integers(0, n ** 3, size=192)
+    cells = np.concatenate([top, rnd])
+    got = c.view(-1)[torch.as_tensor(cells, device="cuda")].cpu().numpy().astype(np.float64)
+    rho_h = rho.cpu().numpy()
+    del rho, c
+    want = O.stencil_cwt_at(rho_h, L, kw, h, cells)
+    peak = np.abs(want[:64]).max()
+    assert np.max(np.abs(got - want)) <= CWT_RTOL * peak

@@ -131,3 +131,15 @@ def test_default_half_width_and_normalisation():
                                rtol=1e-13, atol=1e-13)
     with pytest.raises(ValueError):
         O.stencil_cwt(rho, box_len, kw, -1)
+
+
+@pytest.mark.parametrize("n,h", [(10, 3), (6, 4)])
+def test_pointwise_windows_equal_the_superposition(n, h):
+    # (6, 4): 2h + 1 = 9 > 6, so windows repeat cells, as the wrapped stencil does
+    rng = np.random.default_rng(n + h)
+    rho = rng.integers(0, 1 << 44, size=(n, n, n)) * (rng.random((n, n, n)) < 0.7)
+    box_len, kw = 25.0, 0.35
+    full = O.stencil_cwt(rho, box_len, kw, h)
+    cells = np.arange(n ** 3)
+    np.testing.assert_allclose(O.stencil_cwt_at(rho, box_len, kw, h, cells), full.ravel(), rtol=1e-12,
+                               atol=1e-12 * np.abs(full).max())
