@@ -534,8 +534,8 @@ def stencil_bench(rho, c_fft, box_len: float, n: int, kw: float, warmup: int, it
     """Step 3 by the paper's truncated real-space stencil (hf_cwt_stencil with
     Table 1's half-width) on the step's density: `warmup` untimed calls, then
     `iters` under the library's kernel timer (a trace sees warmup + iters calls,
-    as many as the step's launches).  Algorithmic bytes: the x pass reads rho and
-    writes two FP32 fields (16 B/cell), the y pass reads two and writes two
+    as many as the step's launches).  Algorithmic bytes: the x pass reads rho
+    and writes two FP32 fields (16 B/cell), the y pass reads two and writes two
     (16 B/cell), the z pass reads two and writes C (12 B/cell): 44 B/cell; the
     strict bound reads rho and writes C (12 B/cell).  Also reported: the largest
     difference from the step's FFT field relative to its peak, which is what the
@@ -574,9 +574,11 @@ def stencil_bench(rho, c_fft, box_len: float, n: int, kw: float, warmup: int, it
     diff = float((out - c_fft).abs().max()) / peak
     del ws, out
     torch.cuda.empty_cache()
-    log(f"stencil CWT (half-width {h}): {ms:.3f} ms per call, {model / kernel_ms / 1e6:.0f} GB/s on 44 B/cell; "
+    log(f"stencil CWT (half-width {h}): {ms:.3f} ms per call, {model / kernel_ms / 1e6:.0f} GB/s on "
+        f"{model // cells} B/cell; "
         f"max |C_stencil - C_fft| = {diff:.3e} of the peak")
-    return {"what": "grid CWT by the truncated real-space stencil of Sec. 2.1, three separable passes",
+    return {"what": "grid CWT by the truncated real-space stencil of Sec. 2.1, seven separable convolutions "
+                    "in x, y and z passes",
             "half_width": h, "ms_per_call": round(ms, 4), "kernels": kernels,
             "model_bytes": model, "GBps_model": round(model / kernel_ms / 1e6, 1),
             "frac_model": round(model / kernel_ms / 1e6 / HBM_PEAK_GBS, 4),

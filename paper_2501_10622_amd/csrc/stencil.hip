@@ -11,9 +11,11 @@
 //   x pass:  fA = A * rho,  fB = B * rho                (cell-mass units)
 //   y pass:  G = A * fA,    S = 6 G - A * fB - B * fA
 //   z pass:  C = (P / mean) (A * S - B * G)
-// Each pass reads its lines (plus h cells of halo at each end) into LDS and
-// every output sums its taps in pairs d, -d.  The mean cell mass comes from the
-// exact 128-bit total of rho, reduced in FP64 between the x and y passes.
+// Each pass reads its lines (plus h cells of halo at each end) into LDS, with
+// several loads in flight per lane, and every output sums its taps in pairs
+// d, -d.  The mean cell mass comes from the exact 128-bit total of rho, reduced
+// in FP64 between the x and y passes.  (A fused x-y pass over 2D tiles, which
+// keeps fA and fB in LDS, measured slower than the two passes.)
 #include <cmath>
 
 #include "hf_internal.h"
@@ -25,7 +27,7 @@ namespace {
 constexpr int ST_THREADS = 256;
 constexpr int ST_LANES = 64;          // x columns of a y- or z-pass tile (one wavefront row)
 constexpr int ST_GROUPS = ST_THREADS / ST_LANES;
-constexpr int ST_T = 64;              // outputs along the pass axis per tile
+constexpr int ST_T = 32;              // outputs along the pass axis per tile (32 measured faster than 48, 64, 128)
 constexpr int ST_X_CELLS = 4096;      // line-buffer cells per x-pass workgroup (whole rows)
 
 struct StencilLayout {
@@ -73,6 +75,36 @@ __device__ __forceinline__ int wrap(int t, int n) {
     return t < 0 ? t + n : t;
 }
 
+// wrap with a fast path for the common in-range index
+__device__ __forceinline__ int wrapq(int t, int n) { return unsigned(t) < unsigned(n) ? t : wrap(t, n); }
+
+constexpr int LOAD_BATCH = 4;  // rows whose loads are issued together before any is used
+
+// Workgroup sum of the threads' 128-bit masses, in a fixed order, to *out.
+__device__ __forceinline__ void block_mass(unsigned long long lo, unsigned long long hi, Mass128 *out) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long olo = __shfl_down(lo, off, 64);
+        const unsigned long long ohi = __shfl_down(hi, off, 64);
+        add128(lo, hi, olo);
+        hi += ohi;
+    }
+    __shared__ unsigned long long red_lo[ST_THREADS / 64], red_hi[ST_THREADS / 64];
+    if ((threadIdx.x & 63) == 0) {
+        red_lo[threadIdx.x >> 6] = lo;
+        red_hi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long L = 0, H = 0;
+        for (int w = 0; w < ST_THREADS / 64; ++w) {
+            add128(L, H, red_lo[w]);
+            H += red_hi[w];
+        }
+        out->lo = L;
+        out->hi = H;
+    }
+}
+
 // x pass: xrows whole rows per workgroup; row r of the grid (r = z n + y) is
 // read once with h cells of periodic halo on either side.
 __global__ void __launch_bounds__(ST_THREADS)
@@ -89,41 +121,34 @@ __global__ void __launch_bounds__(ST_THREADS)
     stencil_weights(wa, wb, h, wdx);
     unsigned long long lo = 0, hi = 0;
     bool neg = false;
-    for (int r = 0; r < rows; ++r) {
-        const int64_t *src = rho + (row0 + r) * n;
-        float *line = buf + r * W;
-        for (int i = tid; i < W; i += ST_THREADS) {
-            const int x = wrap(i - h, n);
-            const int64_t v = src[x];
-            if (i >= h && i < h + n) {  // each cell counted once, from its own slot
-                neg |= v < 0;
-                add128(lo, hi, static_cast<unsigned long long>(v));
+    // the rows' line buffers as one run of rows * W slots, LOAD_BATCH loads in flight per thread
+    const int slots = rows * W;
+    for (int s0 = tid; s0 < slots; s0 += ST_THREADS * LOAD_BATCH) {
+        int64_t v[LOAD_BATCH];
+#pragma unroll
+        for (int u = 0; u < LOAD_BATCH; ++u) {
+            const int sl = s0 + u * ST_THREADS;
+            v[u] = 0;
+            if (sl < slots) {
+                const int r = sl / W, i = sl - r * W;
+                v[u] = rho[(row0 + r) * n + wrapq(i - h, n)];
             }
-            line[i] = float(v);
+        }
+#pragma unroll
+        for (int u = 0; u < LOAD_BATCH; ++u) {
+            const int sl = s0 + u * ST_THREADS;
+            if (sl < slots) {
+                const int i = sl % W;
+                if (i >= h && i < h + n) {  // each cell counted once, from its own slot
+                    neg |= v[u] < 0;
+                    add128(lo, hi, static_cast<unsigned long long>(v[u]));
+                }
+                buf[sl] = float(v[u]);
+            }
         }
     }
     if (neg) atomicOr(status, ST_INPUT);
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long olo = __shfl_down(lo, off, 64);
-        const unsigned long long ohi = __shfl_down(hi, off, 64);
-        add128(lo, hi, olo);
-        hi += ohi;
-    }
-    __shared__ unsigned long long red_lo[ST_THREADS / 64], red_hi[ST_THREADS / 64];
-    if ((tid & 63) == 0) {
-        red_lo[tid >> 6] = lo;
-        red_hi[tid >> 6] = hi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        unsigned long long L = 0, H = 0;
-        for (int w = 0; w < ST_THREADS / 64; ++w) {
-            add128(L, H, red_lo[w]);
-            H += red_hi[w];
-        }
-        mass[blockIdx.x].lo = L;
-        mass[blockIdx.x].hi = H;
-    }
+    block_mass(lo, hi, mass + blockIdx.x);  // its barrier also publishes the line buffers
     const float a0 = wa[0];
     for (int r = 0; r < rows; ++r) {
         const float *line = buf + r * W + h;
@@ -143,13 +168,26 @@ __global__ void __launch_bounds__(ST_THREADS)
     }
 }
 
-// Mean cell mass from the x pass's exact partial sums; scalars[0] = P / mean.
+// Mean cell mass from the exact partial sums; scalars[0] = P / mean.
 __global__ void __launch_bounds__(1024)
     stencil_mass_kernel(const Mass128 *__restrict__ mass, int64_t nparts, int n, double pref, double *scalars,
                         uint32_t *status) {
     __shared__ unsigned long long red_lo[16], red_hi[16];
     unsigned long long lo = 0, hi = 0;
-    for (int64_t i = threadIdx.x; i < nparts; i += blockDim.x) {
+    constexpr int U = 8;  // partial sums in flight per thread
+    const int64_t step = int64_t(blockDim.x) * U;
+    int64_t i0 = threadIdx.x;
+    for (; i0 + (U - 1) * int64_t(blockDim.x) < nparts; i0 += step) {
+        Mass128 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = mass[i0 + u * int64_t(blockDim.x)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            add128(lo, hi, v[u].lo);
+            hi += v[u].hi;
+        }
+    }
+    for (int64_t i = i0; i < nparts; i += blockDim.x) {
         add128(lo, hi, mass[i].lo);
         hi += mass[i].hi;
     }
@@ -212,10 +250,27 @@ __global__ void __launch_bounds__(ST_THREADS)
     };
     stencil_weights(wa, wb, h, wdx);
     if (x < n) {
-        for (int r = grp; r < R; r += ST_GROUPS) {
-            const size_t e = at(wrap(t0 - h + r, n));
-            b0[r * ST_LANES + lane] = in0[e];
-            b1[r * ST_LANES + lane] = in1[e];
+        constexpr int UB = 2 * LOAD_BATCH;  // 2 UB loads in flight per lane
+        for (int rb = grp; rb < R; rb += ST_GROUPS * UB) {
+            float v0[UB], v1[UB];
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const int r = rb + u * ST_GROUPS;
+                v0[u] = v1[u] = 0.0f;
+                if (r < R) {
+                    const size_t e = at(wrapq(t0 - h + r, n));
+                    v0[u] = in0[e];
+                    v1[u] = in1[e];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const int r = rb + u * ST_GROUPS;
+                if (r < R) {
+                    b0[r * ST_LANES + lane] = v0[u];
+                    b1[r * ST_LANES + lane] = v1[u];
+                }
+            }
         }
     }
     __syncthreads();

@@ -43,7 +43,7 @@ def test_stencil_within_tolerance(n, L, np_, halos, a, h):
     assert cwt_error(c.cpu().numpy(), c64) <= CWT_RTOL
 
 
-def test_widest_stencil_matches_the_fft_path():
+def test_wide_stencils_match_the_fft_path():
     # h = 64 on a 128 box at a = 1.5 cells: the truncation and the one wrapped
     # line weigh exp(-(64/1.5)^2/4) ~ 1e-198, so both paths compute the sampled
     # periodic convolution; each is within 1e-5 of it
@@ -52,10 +52,12 @@ def test_widest_stencil_matches_the_fft_path():
     kw = n / (1000.0 * a)
     rho = hfm().deposit(cuda(pos), L, n)
     c_st = hfm().cwt_stencil(rho, L, kw, hfm().STENCIL_MAX_HALF_WIDTH)
+    c_32 = hfm().cwt_stencil(rho, L, kw, 32)
     c_fft = hfm().cwt(rho, L, kw, "sampled")
     hfm().sync()
     peak = float(c_fft.abs().max())
-    assert float((c_st - c_fft).abs().max()) <= 2 * CWT_RTOL * peak
+    for c in (c_st, c_32):
+        assert float((c - c_fft).abs().max()) <= 2 * CWT_RTOL * peak
 
 
 def test_default_half_width_is_table1_rule():
