@@ -19,6 +19,7 @@ one scale:
 and, after them, the group statistics of steps 5 and 7 with Table 1's
 thresholds dens_th and particle_th                  -> ``group_stats``
 and the cross-scale maximum check of step 8         -> ``cross_scale``
+and the loop over scales of the flowchart           -> ``identify``
 
 Readings taken where the paper is silent are listed in the design notes and
 repeated at each function.  Everything here is deliberately unblocked and
@@ -36,7 +37,7 @@ __all__ = [
     "wavelet", "wavelet_hat", "sampled_kernel", "kernel_hat", "cwt_field", "cwt",
     "gdw_resolution", "stencil", "stencil_cwt_field", "stencil_cwt", "stencil_cwt_at",
     "neighbour_offsets", "maxima", "parents", "segment", "ngp_nodes", "label",
-    "find_halos", "group_stats", "cross_scale", "peaks", "DepositOverflow",
+    "find_halos", "group_stats", "cross_scale", "peaks", "identify", "DepositOverflow",
 ]
 
 
@@ -509,6 +510,52 @@ def cross_scale(c_scale: np.ndarray, c_smaller: np.ndarray, roots) -> np.ndarray
         near = np.maximum(near, np.roll(cm, tuple(-o for o in off), axis=(0, 1, 2)))
     roots = np.asarray(roots, dtype=np.int64).ravel()
     return cs.ravel()[roots] > near.ravel()[roots]
+
+
+# --------------------------------------------------------------------------
+# the identification loop over scales (Sec. 2 and its flowchart)
+# --------------------------------------------------------------------------
+def identify(pos, box_len: float, n: int, kws, dens_th: float = 4.0, particle_th: int = 15,
+             frac_bits: int = 15, tau: float = 0.0, mode: str = "sampled", decide_dtype=np.float64) -> dict:
+    """Steps 2-8 over the scales ``kws`` (increasing k_w: from the largest
+    scale length down), without the self-boundness check of steps 9-10.
+
+    The flowchart keeps two grids: the one being identified and the next
+    (smaller) scale's.  Each scale in turn: its maxima and segmentation; the
+    particles that no earlier scale has claimed take their cell's label (a
+    temporary ID); groups are formed from those particles and a group is
+    discarded unless it passes the density and particle-number thresholds
+    (step 7) and its maximum exceeds the next scale's field near it (step 8;
+    after the last scale the next grid is all zeros).  The particles of a kept
+    group are claimed at this scale with the group's root as their ID.
+    Reading: every scale is on the box's one n^3 grid (the paper re-grids
+    each scale, N_g = Int(400 k_w + 150)), and the density of a group counts
+    the particles it takes at its scale against the mean of all particles.
+    """
+    kws = [float(k) for k in kws]
+    if not kws or any(b <= a for a, b in zip(kws, kws[1:])):
+        raise ValueError("scales must be given in increasing k_w")
+    np_total = len(pos)
+    rho = deposit(pos, box_len, n, frac_bits)
+    fields = [cwt(rho, box_len, kw, mode).astype(decide_dtype) for kw in kws]
+    halo_scale = np.full(np_total, -1, dtype=np.int64)
+    halo_root = np.full(np_total, -1, dtype=np.int64)
+    per_scale = []
+    for i, c in enumerate(fields):
+        nxt = fields[i + 1] if i + 1 < len(fields) else np.zeros_like(c)  # the flowchart's zero current_grid
+        roots = maxima(c, tau)
+        cell = segment(c, tau)
+        pl = label(pos, box_len, n, cell, frac_bits)
+        pl = np.where(halo_scale >= 0, -1, pl)  # only particles with no label yet
+        ok = cross_scale(c, nxt, roots)
+        g = group_stats(cell, pl, roots, n, np_total, dens_th, particle_th, root_ok=ok)
+        take = g["particle_label"] >= 0
+        halo_scale[take] = i
+        halo_root[take] = g["particle_label"][take]
+        per_scale.append({"cwt": c, "maxima": roots, "cell_label": cell, "cross_scale": ok,
+                          "particles": g["particles"], "cells": g["cells"], "keep": g["keep"],
+                          "particle_label": g["particle_label"]})
+    return {"rho": rho, "scales": per_scale, "halo_scale": halo_scale, "halo_root": halo_root}
 
 
 # --------------------------------------------------------------------------
