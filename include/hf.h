@@ -15,6 +15,8 @@
  *                       of every group (Table 1: dens_th, particle_th)
  *   hf_peaks    step 4  sub-cell position and value of each maximum (App. B)
  *   hf_cross_scale  step 8  maxima that are also maxima across scale
+ *   hf_identify steps 2-8   the loop over scales, largest first, that claims
+ *                       particles for halos (Sec. 2 and its flowchart)
  *
  * Conventions shared by every call
  * --------------------------------
@@ -323,6 +325,40 @@ hf_status hf_find_halos_scales_ws_size(const hf_box *box, int64_t np, int32_t co
 hf_status hf_find_halos_scales(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np,
                                hf_kernel kernel, float tau, int64_t *rho, int32_t count, const hf_scale_job *scales,
                                void *ws, size_t ws_bytes);
+
+/* Sec. 2's identification loop over scales (steps 2-8; the self-boundness
+ * check of steps 9-10 is not made), as its flowchart runs it with a pair of
+ * grids, on the box's one n^3 grid.  scales[0..count) in strictly increasing
+ * k_w (largest scale length first).  Every scale's field, maxima, segmentation
+ * and step-6 labels are made as hf_find_halos_scales makes them; then, scale
+ * by scale: particles claimed by an earlier scale are given label -1; the
+ * groups of the remaining particles are measured (steps 5 and 7, as hf_groups,
+ * with the mean density of all np particles); a group is kept iff it passes
+ * dens_th and particle_th and its maximum exceeds the next scale's field at
+ * its cell and 26 neighbours (step 8; after the last scale, the zero grid);
+ * the kept groups' particles are claimed.
+ * On return:
+ *  scales[j].particle_label [np]: the root of the kept group that claimed the
+ *    particle at scale j, else -1 (so each particle is >= 0 at one scale at most);
+ *  scales[j].cell_label: scale j's whole segmentation (unfiltered);
+ *  groups[j]: per maximum of scale j (indexed like its max_idx) the particles
+ *    still unclaimed in its group, its cells, and 1 iff it became a halo;
+ *  halo_scale [np]: the scale index that claimed the particle, -1 for none;
+ *  halo_root [np]: the root cell of that group, -1 for none.
+ * scales[] and groups[] are HOST arrays of device pointers.
+ * Workspace: hf_identify_ws_size (that of hf_find_halos_scales, the group
+ * counters and one byte per maximum of the largest list). */
+typedef struct {
+    uint32_t *group_particles; /* [max_cap] */
+    uint32_t *group_cells;     /* [max_cap] */
+    uint8_t *group_keep;       /* [max_cap] */
+} hf_identify_groups;
+hf_status hf_identify_ws_size(const hf_box *box, int64_t np, int32_t count, const hf_scale_job *scales,
+                              size_t *bytes);
+hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np, hf_kernel kernel,
+                      float tau, int64_t *rho, int32_t count, const hf_scale_job *scales,
+                      const hf_identify_groups *groups, double dens_th, int64_t particle_th, int32_t *halo_scale,
+                      int32_t *halo_root, void *ws, size_t ws_bytes);
 
 /* Serving form of steps 2-6 for `count` (1..HF_CWT_BATCH_MAX) boxes of the same
  * grid size n: per-box deposits, ONE batched transform (hf_cwt_batch) for the

@@ -8,6 +8,6 @@ from .hf import (  # noqa: F401
     CWT_BATCH_MAX, EXPORTS, HFError, LIB_PATH, Context, context, cross_scale, cwt, cwt_batch, cwt_batch_ws_bytes,
     cwt_scales, cwt_stencil, deposit, gdw_resolution,
     find_halos, find_halos_async, find_halos_filtered_async, find_halos_group_async, find_halos_scales_async,
-    groups, job_buffers, label, load_library, maxima, peaks, scales_buffers, segment, STENCIL_MAX_HALF_WIDTH,
+    groups, identify_async, identify_buffers, job_buffers, label, load_library, maxima, peaks, scales_buffers, segment, STENCIL_MAX_HALF_WIDTH,
     status_str, sync, workspace_size,
 )

@@ -156,11 +156,13 @@ __global__ void __launch_bounds__(GB) groups_filter_kernel(const int32_t *in, in
 
 // Step 8: maximum i of one scale is kept if its value exceeds the adjacent
 // smaller scale's field at its cell and the 26 periodic neighbours (both on
-// the same grid; strict).  One thread per maximum; a NaN is reported.
-__global__ void __launch_bounds__(GB) cross_scale_kernel(const int32_t *__restrict__ roots, int64_t nroots, int n,
-                                                         const float *__restrict__ c_scale,
+// the same grid; strict).  c_smaller null stands for the all-zero grid (the
+// identification loop's last scale).  One thread per maximum; a NaN is reported.
+__global__ void __launch_bounds__(GB) cross_scale_kernel(const int32_t *__restrict__ roots, const int64_t *d_count,
+                                                         int64_t cap, int n, const float *__restrict__ c_scale,
                                                          const float *__restrict__ c_smaller,
                                                          uint8_t *__restrict__ pass, uint32_t *status) {
+    const int64_t nroots = root_count(d_count, cap);
     bool bad = false;
     const uint32_t un = uint32_t(n), ncells = un * un * un;
     for (int64_t i = blockIdx.x * int64_t(GB) + threadIdx.x; i < nroots; i += int64_t(gridDim.x) * GB) {
@@ -181,13 +183,44 @@ __global__ void __launch_bounds__(GB) cross_scale_kernel(const int32_t *__restri
 #pragma unroll
                 for (int dx = -1; dx <= 1; ++dx) {
                     const uint32_t gz = (z + un + dz) % un, gy = (y + un + dy) % un, gx = (x + un + dx) % un;
-                    const float u = c_smaller[(gz * un + gy) * un + gx];
+                    const float u = c_smaller ? c_smaller[(gz * un + gy) * un + gx] : 0.0f;
                     bad |= u != u;
                     above = above && v > u;
                 }
         pass[i] = above ? 1 : 0;
     }
     if (bad) atomicOr(status, ST_INPUT);
+}
+
+// The identification loop's per-particle bookkeeping: halo_scale[p] is the
+// scale that claimed particle p (-1 while none has), halo_root[p] the root of
+// its group there.
+__global__ void __launch_bounds__(GB) claim_init_kernel(int32_t *__restrict__ halo_scale,
+                                                        int32_t *__restrict__ halo_root, int64_t np) {
+    for (int64_t i = blockIdx.x * int64_t(GB) + threadIdx.x; i < np; i += int64_t(gridDim.x) * GB) {
+        halo_scale[i] = -1;
+        halo_root[i] = -1;
+    }
+}
+
+// Particles an earlier scale has claimed take no label at this one.
+__global__ void __launch_bounds__(GB) claim_mask_kernel(int32_t *__restrict__ label,
+                                                        const int32_t *__restrict__ halo_scale, int64_t np) {
+    for (int64_t i = blockIdx.x * int64_t(GB) + threadIdx.x; i < np; i += int64_t(gridDim.x) * GB)
+        if (halo_scale[i] >= 0) label[i] = -1;
+}
+
+// Particles whose filtered label at this scale is a kept group are claimed.
+__global__ void __launch_bounds__(GB) claim_take_kernel(const int32_t *__restrict__ label,
+                                                        int32_t *__restrict__ halo_scale,
+                                                        int32_t *__restrict__ halo_root, int64_t np, int32_t scale) {
+    for (int64_t i = blockIdx.x * int64_t(GB) + threadIdx.x; i < np; i += int64_t(gridDim.x) * GB) {
+        const int32_t v = label[i];
+        if (v >= 0) {
+            halo_scale[i] = scale;
+            halo_root[i] = v;
+        }
+    }
 }
 
 // Step 4's correction of grid maxima (App. B), in FP64 on the FP32 field: per
@@ -295,6 +328,36 @@ hf_status hf::groups_filter(hf_ctx *ctx, const hf_box &box, const int32_t *in, i
     return launch_status();
 }
 
+hf_status hf::cross_scale_dev(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count,
+                              int64_t cap, const float *c_scale, const float *c_smaller, uint8_t *pass) {
+    if (cap <= 0) return HF_OK;
+    HF_LAUNCH(ctx, K_GROUP_CROSS, cross_scale_kernel, dim3(grid_of(ctx, cap, GB)), dim3(GB), 0, ctx->stream, roots,
+              d_count, cap, box.n, c_scale, c_smaller, pass, ctx->d_status);
+    return launch_status();
+}
+
+hf_status hf::claim_init(hf_ctx *ctx, int32_t *halo_scale, int32_t *halo_root, int64_t np) {
+    if (np <= 0) return HF_OK;
+    HF_LAUNCH(ctx, K_CLAIM, claim_init_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0, ctx->stream,
+              halo_scale, halo_root, np);
+    return launch_status();
+}
+
+hf_status hf::claim_mask(hf_ctx *ctx, int32_t *label, const int32_t *halo_scale, int64_t np) {
+    if (np <= 0) return HF_OK;
+    HF_LAUNCH(ctx, K_CLAIM, claim_mask_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0, ctx->stream, label,
+              halo_scale, np);
+    return launch_status();
+}
+
+hf_status hf::claim_take(hf_ctx *ctx, const int32_t *label, int32_t *halo_scale, int32_t *halo_root, int64_t np,
+                         int32_t scale) {
+    if (np <= 0) return HF_OK;
+    HF_LAUNCH(ctx, K_CLAIM, claim_take_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0, ctx->stream, label,
+              halo_scale, halo_root, np, scale);
+    return launch_status();
+}
+
 extern "C" hf_status hf_peaks(hf_ctx *ctx, const hf_box *box, const float *cwt, const int32_t *roots, int64_t nroots,
                               double *pos, double *value) {
     if (!ctx) return HF_ERR_ARG;
@@ -319,7 +382,7 @@ extern "C" hf_status hf_cross_scale(hf_ctx *ctx, const hf_box *box, const int32_
     if (!roots || !cwt_scale || !cwt_smaller || !pass) return HF_ERR_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
     HF_LAUNCH(ctx, K_GROUP_CROSS, cross_scale_kernel, dim3(grid_of(ctx, nroots, GB)), dim3(GB), 0, ctx->stream, roots,
-              nroots, box->n, cwt_scale, cwt_smaller, pass, ctx->d_status);
+              nullptr, nroots, box->n, cwt_scale, cwt_smaller, pass, ctx->d_status);
     return launch_status();
 }
 

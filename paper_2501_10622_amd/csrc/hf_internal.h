@@ -20,7 +20,7 @@ enum KernelId {
     K_PARENT, K_FLAGS, K_JUMP, K_FINALIZE,
     K_LABEL_TILES, K_LABEL_LEVEL1, K_LABEL_INPUT, K_RESOLVE,
     K_GROUP_CLEAR, K_GROUP_CELLS, K_GROUP_PARTICLES, K_GROUP_DECIDE, K_GROUP_FILTER, K_GROUP_CROSS, K_PEAKS,
-    K_ST_X, K_ST_MASS, K_ST_Y, K_ST_Z,
+    K_ST_X, K_ST_MASS, K_ST_Y, K_ST_Z, K_CLAIM,
     K_COUNT
 };
 const char *kernel_name(int id);
@@ -194,6 +194,15 @@ size_t cwt_ws_bytes(const hf_box &box);
 size_t maxima_ws_bytes(const hf_box &box);
 size_t segment_ws_bytes(const hf_box &box);
 size_t groups_ws_bytes(const hf_box &box);
+// Step 8 with the maxima count on the device (cap = the list's capacity);
+// c_smaller null compares with the all-zero grid.
+hf_status cross_scale_dev(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count, int64_t cap,
+                          const float *c_scale, const float *c_smaller, uint8_t *pass);
+// The identification loop's particle bookkeeping (halo_scale / halo_root).
+hf_status claim_init(hf_ctx *ctx, int32_t *halo_scale, int32_t *halo_root, int64_t np);
+hf_status claim_mask(hf_ctx *ctx, int32_t *label, const int32_t *halo_scale, int64_t np);
+hf_status claim_take(hf_ctx *ctx, const int32_t *label, int32_t *halo_scale, int32_t *halo_root, int64_t np,
+                     int32_t scale);
 size_t stencil_ws_bytes(const hf_box &box);
 
 // ---------------------------------------------------------------------------

@@ -188,6 +188,70 @@ extern "C" hf_status hf_find_halos_scales(hf_ctx *ctx, const hf_box *box, const 
     return s;
 }
 
+extern "C" hf_status hf_identify_ws_size(const hf_box *box, int64_t np, int32_t count, const hf_scale_job *scales,
+                                        size_t *bytes) {
+    if (!bytes || !scales) return HF_ERR_ARG;
+    size_t base = 0;
+    hf_status s = hf_find_halos_scales_ws_size(box, np, count, &base);
+    if (s != HF_OK) return s;
+    int64_t cap = 0;
+    for (int j = 0; j < count; ++j) {
+        if (scales[j].max_cap < 0) return HF_ERR_ARG;
+        cap = scales[j].max_cap > cap ? scales[j].max_cap : cap;
+    }
+    *bytes = align_up(base) + groups_ws_bytes(*box) + align_up(size_t(cap));
+    return HF_OK;
+}
+
+// Sec. 2's identification loop at one grid: every scale's field, maxima,
+// segmentation and step-6 labels as hf_find_halos_scales, then scale by scale
+// (largest first) the flowchart's pair of grids: the cross-scale flags of this
+// scale's maxima against the next scale's field (the zero grid after the last),
+// the labels of particles already claimed masked, the groups' statistics and
+// the step-7/8 decision, the filter, and the claim of the kept groups' particles.
+extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np,
+                                 hf_kernel kernel, float tau, int64_t *rho, int32_t count, const hf_scale_job *scales,
+                                 const hf_identify_groups *groups, double dens_th, int64_t particle_th,
+                                 int32_t *halo_scale, int32_t *halo_root, void *ws, size_t ws_bytes) {
+    if (!ctx || !scales || !groups || count < 1 || count > HF_CWT_BATCH_MAX) return HF_ERR_ARG;
+    if (np < 0 || np > int64_t(UINT32_MAX) || (np > 0 && (!halo_scale || !halo_root))) return HF_ERR_ARG;
+    if (!(dens_th >= 0.0) || !(dens_th < 1e300) || particle_th < 0) return HF_ERR_ARG;
+    for (int j = 0; j < count; ++j) {
+        if (j > 0 && !(scales[j].kw > scales[j - 1].kw)) return HF_ERR_ARG;  // largest scale first
+        if (scales[j].max_cap > 0 && (!groups[j].group_particles || !groups[j].group_cells || !groups[j].group_keep))
+            return HF_ERR_ARG;
+    }
+    hf_status s = check_box(box);
+    if (s != HF_OK) return s;
+    size_t need = 0, base = 0;
+    s = hf_identify_ws_size(box, np, count, scales, &need);
+    if (s == HF_OK) s = hf_find_halos_scales_ws_size(box, np, count, &base);
+    if (s != HF_OK) return s;
+    s = check_ws(ws, ws_bytes, need);
+    if (s != HF_OK) return s;
+    s = hf_find_halos_scales(ctx, box, pos, dtype, np, kernel, tau, rho, count, scales, ws, base);
+    if (s != HF_OK) return s;
+    char *rest = static_cast<char *>(ws) + align_up(base);
+    const GroupCounters g = group_counters_at(*box, rest);
+    uint8_t *pass = reinterpret_cast<uint8_t *>(rest + groups_ws_bytes(*box));
+    s = claim_init(ctx, halo_scale, halo_root, np);
+    for (int j = 0; j < count && s == HF_OK; ++j) {
+        const hf_scale_job &sj = scales[j];
+        const hf_identify_groups &gj = groups[j];
+        const float *next = j + 1 < count ? scales[j + 1].cwt : nullptr;
+        s = cross_scale_dev(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, sj.cwt, next, pass);
+        if (s == HF_OK) s = claim_mask(ctx, sj.particle_label, halo_scale, np);
+        if (s == HF_OK) s = groups_count_cells(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, sj.cell_label, g);
+        if (s == HF_OK && sj.max_cap > 0) s = groups_count_particles(ctx, *box, sj.particle_label, np, g);
+        if (s == HF_OK)
+            s = groups_decide(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, g, dens_th, np, particle_th, pass,
+                              gj.group_particles, gj.group_cells, gj.group_keep);
+        if (s == HF_OK) s = groups_filter(ctx, *box, sj.particle_label, sj.particle_label, np, g, sj.max_cap > 0);
+        if (s == HF_OK) s = claim_take(ctx, sj.particle_label, halo_scale, halo_root, np, j);
+    }
+    return s;
+}
+
 // A group of same-n boxes: per-box deposits, one batched transform for all of
 // them, then per-box maxima, segmentation and labels, in that order on the
 // context's stream.

@@ -27,7 +27,7 @@ EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_
            "hf_cwt_batch_ws_size", "hf_cwt_batch", "hf_find_halos", "hf_find_halos_group", "hf_groups",
            "hf_find_halos_filtered", "hf_cwt_scales",
            "hf_find_halos_scales_ws_size", "hf_find_halos_scales", "hf_cross_scale", "hf_peaks",
-           "hf_cwt_stencil")
+           "hf_cwt_stencil", "hf_identify_ws_size", "hf_identify")
 CWT_BATCH_MAX = 32
 STAGE_ALL = 31
 STAGE_GROUPS = 32
@@ -62,6 +62,11 @@ class ScaleJob(ctypes.Structure):
     _fields_ = [("kw", ctypes.c_double), ("cwt", ctypes.c_void_p), ("max_idx", ctypes.c_void_p),
                 ("max_cap", ctypes.c_int64), ("d_count", ctypes.c_void_p), ("cell_label", ctypes.c_void_p),
                 ("particle_label", ctypes.c_void_p)]
+
+
+class IdentifyGroups(ctypes.Structure):
+    _fields_ = [("group_particles", ctypes.c_void_p), ("group_cells", ctypes.c_void_p),
+                ("group_keep", ctypes.c_void_p)]
 
 
 class GroupFilter(ctypes.Structure):
@@ -115,6 +120,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "hf_find_halos_scales": (ctypes.c_int, [vp, bp, vp, ctypes.c_int, i64, ctypes.c_int, flt, vp, i32,
                                                     ctypes.POINTER(ScaleJob), vp, sz]),
             "hf_find_halos": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job), vp, sz]),
+            "hf_identify_ws_size": (ctypes.c_int, [bp, i64, i32, ctypes.POINTER(ScaleJob), ctypes.POINTER(sz)]),
+            "hf_identify": (ctypes.c_int, [vp, bp, vp, ctypes.c_int, i64, ctypes.c_int, flt, vp, i32,
+                                           ctypes.POINTER(ScaleJob), ctypes.POINTER(IdentifyGroups), dbl, i64, vp,
+                                           vp, vp, sz]),
             "hf_find_halos_group": (ctypes.c_int, [vp, i32, i32, i32, ctypes.POINTER(GroupItem), ctypes.c_int,
                                                    vp, sz]),
             "hf_groups": (ctypes.c_int, [vp, bp, i64, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp, vp, sz]),
@@ -570,6 +579,53 @@ def find_halos_scales_async(pos: torch.Tensor, box_len: float, n: int, kws, bufs
     _check(load_library().hf_find_halos_scales(ctx.handle, ctypes.byref(b), _ptr(pos), _dtype_code(pos),
                                                pos.shape[0], KERNELS[kernel], float(tau), _ptr(bufs["rho"]), count,
                                                jobs, _ptr(bufs["ws"]), bufs["ws"].numel()), "hf_find_halos_scales")
+
+
+def _scale_jobs(kws, bufs):
+    return (ScaleJob * len(kws))(*[ScaleJob(float(kw), bufs["cwt"][j].data_ptr(), bufs["maxima"][j].data_ptr(),
+                                            bufs["maxima"][j].numel(), bufs["count"][j].data_ptr(),
+                                            bufs["cell_label"][j].data_ptr(), bufs["particle_label"][j].data_ptr())
+                                   for j, kw in enumerate(kws)])
+
+
+def identify_buffers(n: int, np_: int, count: int, device, frac_bits: int = 15) -> dict:
+    """Outputs and workspace for identify_async: those of scales_buffers, the
+    per-maximum group outputs of every scale and the per-particle halo_scale
+    and halo_root."""
+    bufs = scales_buffers(n, np_, count, device, frac_bits)
+    cap = bufs["maxima"][0].numel()
+    bufs["group_particles"] = [torch.empty(cap, dtype=torch.int32, device=device) for _ in range(count)]
+    bufs["group_cells"] = [torch.empty(cap, dtype=torch.int32, device=device) for _ in range(count)]
+    bufs["group_keep"] = [torch.empty(cap, dtype=torch.uint8, device=device) for _ in range(count)]
+    bufs["halo_scale"] = torch.empty(max(np_, 1), dtype=torch.int32, device=device)
+    bufs["halo_root"] = torch.empty(max(np_, 1), dtype=torch.int32, device=device)
+    out = ctypes.c_size_t()
+    b = box(n, 1.0, frac_bits)
+    jobs = _scale_jobs([1.0 + j for j in range(count)], bufs)
+    _check(load_library().hf_identify_ws_size(ctypes.byref(b), int(np_), int(count), jobs, ctypes.byref(out)),
+           "hf_identify_ws_size")
+    bufs["ws"] = torch.empty(max(out.value, 256), dtype=torch.uint8, device=device)
+    return bufs
+
+
+def identify_async(pos: torch.Tensor, box_len: float, n: int, kws, bufs: dict, dens_th: float = 4.0,
+                   particle_th: int = 15, frac_bits: int = 15, tau: float = 0.0, kernel: str = "sampled", ctx=None):
+    """Enqueue Sec. 2's identification loop over the scales kws (increasing k_w),
+    steps 2-8 without unbinding (bufs from identify_buffers)."""
+    _require_cuda(pos, "pos")
+    ctx = ctx or context(pos.device.index)
+    count = len(kws)
+    if count != len(bufs["cwt"]):
+        raise ValueError("one buffer set per scale")
+    jobs = _scale_jobs(kws, bufs)
+    groups = (IdentifyGroups * count)(*[IdentifyGroups(bufs["group_particles"][j].data_ptr(),
+                                                       bufs["group_cells"][j].data_ptr(),
+                                                       bufs["group_keep"][j].data_ptr()) for j in range(count)])
+    b = box(n, box_len, frac_bits)
+    _check(load_library().hf_identify(ctx.handle, ctypes.byref(b), _ptr(pos), _dtype_code(pos), pos.shape[0],
+                                      KERNELS[kernel], float(tau), _ptr(bufs["rho"]), count, jobs, groups,
+                                      float(dens_th), int(particle_th), _ptr(bufs["halo_scale"]),
+                                      _ptr(bufs["halo_root"]), _ptr(bufs["ws"]), bufs["ws"].numel()), "hf_identify")
 
 
 def find_halos_filtered_async(pos: torch.Tensor, box_len: float, n: int, kw: float, bufs: dict,

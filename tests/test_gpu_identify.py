@@ -1,0 +1,143 @@
+"""Sec. 2's identification loop over scales (hf_identify) against the oracle's
+loop, and against the composition of the already-tested entry points it
+chains (hf_find_halos_scales, hf_cross_scale, hf_groups) with the claiming
+done in torch: the latter bit-exact at any size, the former exact where every
+decision the loop makes is certified away from a tie, else by agreement."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import LABEL_AGREEMENT, O, cuda, ensure_built, small_box, tie_free
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    ensure_built()
+
+
+def hfm():
+    import paper_2501_10622_amd as m
+    return m
+
+
+def run(pos, L, n, kws, dens_th, pth):
+    bufs = hfm().identify_buffers(n, len(pos), len(kws), "cuda")
+    hfm().identify_async(cuda(pos), L, n, kws, bufs, dens_th, pth)
+    hfm().sync()
+    return bufs
+
+
+def _two_halo_box():
+    rng = np.random.default_rng(0)
+    L = 64.0
+    return (np.concatenate([rng.normal(loc=(20.0, 20.0, 20.0), scale=0.7, size=(3000, 3)),
+                            rng.normal(loc=(44.0, 40.0, 30.0), scale=4.0, size=(20000, 3)),
+                            rng.random((30000, 3)) * L]) % L).astype(np.float32), L
+
+
+def _cross_margin_ok(fields, roots_list, eps):
+    # every step-8 comparison decided more than 2 eps away from equality
+    n = fields[0].shape[0]
+    for i, roots in enumerate(roots_list):
+        nxt = fields[i + 1] if i + 1 < len(fields) else np.zeros_like(fields[i])
+        for r in roots.tolist():
+            z, y, x = r // (n * n), (r // n) % n, r % n
+            v = fields[i][z, y, x]
+            for a in (-1, 0, 1):
+                for b in (-1, 0, 1):
+                    for c in (-1, 0, 1):
+                        if abs(v - nxt[(z + a) % n, (y + b) % n, (x + c) % n]) <= 2 * eps:
+                            return False
+    return True
+
+
+@pytest.mark.parametrize("case", ["two_halos", "clustered_32", "clustered_48"])
+def test_matches_oracle_loop(case):
+    if case == "two_halos":
+        pos, L = _two_halo_box()
+        n, scales, dens_th, pth = 32, (4.0, 2.0, 1.0), 4.0, 15
+    else:
+        n = 32 if case == "clustered_32" else 48
+        L = float(n) * 1.25
+        pos = small_box(n, L, 60000, 40, "f32", 71 + n)
+        scales, dens_th, pth = (3.0, 2.0, 1.5, 1.0), 2.0, 15
+    kws = [n / (1000.0 * a) for a in scales]
+    print(f"identify {case} n={n} scales={scales}", flush=True)
+    got = run(pos, L, n, kws, dens_th, pth)
+    ref = O.identify(pos, L, n, kws, dens_th, pth)
+    np.testing.assert_array_equal(got["rho"].cpu().numpy(), ref["rho"])
+    fields64 = [sc["cwt"] for sc in ref["scales"]]
+    eps = max(float(np.max(np.abs(got["cwt"][i].cpu().numpy().astype(np.float64) - fields64[i])))
+              for i in range(len(kws)))
+    hs, hr = got["halo_scale"].cpu().numpy(), got["halo_root"].cpu().numpy()
+    certified = all(tie_free(f, eps) for f in fields64) and \
+        _cross_margin_ok(fields64, [sc["maxima"] for sc in ref["scales"]], eps)
+    if certified:
+        np.testing.assert_array_equal(hs, ref["halo_scale"])
+        np.testing.assert_array_equal(hr, ref["halo_root"])
+        for i, sc in enumerate(ref["scales"]):
+            k = int(got["count"][i].item())
+            assert k == len(sc["maxima"])
+            np.testing.assert_array_equal(got["group_keep"][i][:k].cpu().numpy().astype(bool), sc["keep"])
+            np.testing.assert_array_equal(got["group_particles"][i][:k].cpu().numpy(), sc["particles"])
+            np.testing.assert_array_equal(got["group_cells"][i][:k].cpu().numpy(), sc["cells"])
+            np.testing.assert_array_equal(got["particle_label"][i].cpu().numpy(), sc["particle_label"])
+    else:
+        agree = float(np.mean((hs == ref["halo_scale"]) & (hr == ref["halo_root"])))
+        print(f"  not certified tie-free; agreement {agree:.6f}", flush=True)
+        assert agree >= LABEL_AGREEMENT
+    if case == "two_halos":
+        assert set(np.unique(hs).tolist()) >= {1, 2}  # the extended halo at a = 2, the compact one at a = 1
+
+
+@pytest.mark.parametrize("n,L,np_,halos,scales", [
+    (128, 125.0, 128 ** 3, 1200, (4.0, 2.0, 1.0)),
+    (96, 96.0, 500000, 300, (3.0, 2.5, 2.0, 1.5, 1.0)),
+])
+def test_equals_composition_of_entry_points(n, L, np_, halos, scales):
+    pos = cuda(small_box(n, L, np_, halos, "f32", 72))
+    kws = [n / (1000.0 * a) for a in scales]
+    dens_th, pth = 2.0, 15
+    print(f"identify composition n={n} scales={len(kws)}", flush=True)
+    bufs = hfm().identify_buffers(n, np_, len(kws), "cuda")
+    hfm().identify_async(pos, L, n, kws, bufs, dens_th, pth)
+    hfm().sync()
+    sb = hfm().scales_buffers(n, np_, len(kws), "cuda")
+    hfm().find_halos_scales_async(pos, L, n, kws, sb)
+    hfm().sync()
+    claimed = torch.full((np_,), -1, dtype=torch.int32, device="cuda")
+    root = torch.full((np_,), -1, dtype=torch.int32, device="cuda")
+    for i in range(len(kws)):
+        k = int(sb["count"][i].item())
+        roots = sb["maxima"][i][:k]
+        nxt = sb["cwt"][i + 1] if i + 1 < len(kws) else torch.zeros_like(sb["cwt"][i])
+        ok = hfm().cross_scale(sb["cwt"][i], nxt, roots)
+        pl = torch.where(claimed >= 0, torch.full_like(claimed, -1), sb["particle_label"][i][:np_])
+        g = hfm().groups(sb["cell_label"][i], pl, roots, np_, dens_th, pth, root_ok=ok)
+        hfm().sync()
+        assert torch.equal(bufs["group_keep"][i][:k], g["keep"])
+        assert torch.equal(bufs["group_particles"][i][:k].view(torch.int32), g["particles"].view(torch.int32))
+        assert torch.equal(bufs["group_cells"][i][:k].view(torch.int32), g["cells"].view(torch.int32))
+        take = g["particle_label"] >= 0
+        assert torch.equal(bufs["particle_label"][i][:np_], g["particle_label"])
+        claimed = torch.where(take, torch.full_like(claimed, i), claimed)
+        root = torch.where(take, g["particle_label"], root)
+    assert torch.equal(bufs["halo_scale"][:np_], claimed)
+    assert torch.equal(bufs["halo_root"][:np_], root)
+    assert int((claimed >= 0).sum()) > 0
+
+
+def test_scale_order_and_arguments_checked():
+    from paper_2501_10622_amd.hf import HF_ERR_ARG, HFError
+    pos, L = _two_halo_box()
+    n = 32
+    bufs = hfm().identify_buffers(n, len(pos), 2, "cuda")
+    for kws in ([0.016, 0.008], [0.016, 0.016]):
+        with pytest.raises(HFError) as e:
+            hfm().identify_async(cuda(pos), L, n, kws, bufs)
+        assert e.value.code == HF_ERR_ARG
+    with pytest.raises(HFError) as e:
+        hfm().identify_async(cuda(pos), L, n, [0.008, 0.016], bufs, dens_th=-1.0)
+    assert e.value.code == HF_ERR_ARG
