@@ -52,6 +52,7 @@ TIMER_SYMBOLS = {
     "groups_filter": ("groups_filter_kernel",),
     "stencil_x": ("stencil_x_kernel",), "stencil_mass": ("stencil_mass_kernel",),
     "stencil_y": ("stencil_axis_kernel<false>",), "stencil_z": ("stencil_axis_kernel<true>",),
+    "claim": ("claim_init_kernel", "claim_mask_kernel", "claim_take_kernel"),
 }
 
 
@@ -530,6 +531,51 @@ def groups_bench(bufs: dict, n: int, np_: int, warmup: int, iters: int, ctx) -> 
             "frac": round(nbytes / kernel_ms / 1e6 / HBM_PEAK_GBS, 4), "checks": checks}
 
 
+def identify_bench(pos, box_len: float, n: int, ctx, iters: int = 2) -> dict:
+    """Sec. 2's identification loop (hf_identify) on the step's box at three
+    scales, a = 4, 2 and 1 cells (largest first), dens_th = 4, particle_th = 15:
+    one untimed call, then `iters` timed ones; per scale the maxima, the groups
+    kept and the particles claimed, with the invariants that every claimed
+    particle's root is a kept maximum of its scale and that each scale's kept
+    groups hold exactly the particles it claims."""
+    import torch
+    import paper_2501_10622_amd as hfm
+    np_ = pos.shape[0]
+    scales = (4.0, 2.0, 1.0)
+    kws = [n / (1000.0 * a) for a in scales]
+    bufs = hfm.identify_buffers(n, np_, len(kws), pos.device)
+    hfm.identify_async(pos, box_len, n, kws, bufs, 4.0, 15, ctx=ctx)
+    ctx.sync()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(iters):
+        hfm.identify_async(pos, box_len, n, kws, bufs, 4.0, 15, ctx=ctx)
+    stop.record()
+    torch.cuda.synchronize()
+    ctx.sync()
+    ms = start.elapsed_time(stop) / iters
+    hs = bufs["halo_scale"][:np_]
+    per, ok = [], True
+    for i in range(len(kws)):
+        k = int(bufs["count"][i].item())
+        keep = bufs["group_keep"][i][:k].bool()
+        mine = hs == i
+        claimed = int(mine.sum().item())
+        kept_parts = int(bufs["group_particles"][i][:k].long()[keep].sum().item())
+        ok = ok and kept_parts == claimed
+        ok = ok and bool((bufs["particle_label"][i][:np_][mine] == bufs["halo_root"][:np_][mine]).all().item())
+        per.append({"a_cells": scales[i], "kw": kws[i], "maxima": k, "kept": int(keep.sum().item()),
+                    "particles_claimed": claimed})
+    claimed_all = int((hs >= 0).sum().item())
+    del bufs
+    torch.cuda.empty_cache()
+    log(f"identify (3 scales): {ms:.1f} ms per call, {claimed_all} of {np_} particles claimed")
+    return {"what": "identification loop over scales a = 4, 2, 1 cells (steps 2-8, no unbinding), "
+                    "dens_th = 4, particle_th = 15", "ms_per_call": round(ms, 3),
+            "particles_per_s": np_ / (ms / 1e3), "scales": per, "particles_claimed": claimed_all,
+            "checks": {"claimed_equals_kept_group_particles_and_roots": ok}}
+
+
 def stencil_bench(rho, c_fft, box_len: float, n: int, kw: float, warmup: int, iters: int, ctx) -> dict:
     """Step 3 by the paper's truncated real-space stencil (hf_cwt_stencil with
     Table 1's half-width) on the step's density: `warmup` untimed calls, then
@@ -884,7 +930,11 @@ def main():
         out["groups"] = groups_bench(bufs, n, cfg.n_particles, args.warmup, 2 * args.steps, ctx)
         out["filtered_pipeline"] = filtered_bench(pos, L, n, kw, bufs, args.warmup, args.steps, args.kernel, ctx,
                                                   ms_step)
-    del pos, bufs, rho, cell, buf
+    del bufs, rho, cell, buf
+    torch.cuda.empty_cache()
+    if not args.no_groups and not multi:
+        out["identify"] = identify_bench(pos, L, n, ctx)
+    del pos
     torch.cuda.empty_cache()
     cp = copy_rate()
     out["hbm_copy_measured"] = {"GBps": round(cp["GBps"], 1), "frac_of_peak": round(cp["GBps"] / HBM_PEAK_GBS, 4),
