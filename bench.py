@@ -52,7 +52,7 @@ TIMER_SYMBOLS = {
     "groups_filter": ("groups_filter_kernel",),
     "stencil_x": ("stencil_x_kernel",), "stencil_mass": ("stencil_mass_kernel",),
     "stencil_y": ("stencil_axis_kernel<false>",), "stencil_z": ("stencil_axis_kernel<true>",),
-    "claim": ("claim_init_kernel", "claim_mask_kernel", "claim_take_kernel"),
+    "claim": ("claim_init_kernel", "claim_filter_kernel"),
 }
 
 

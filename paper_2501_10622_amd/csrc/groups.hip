@@ -73,8 +73,11 @@ __global__ void __launch_bounds__(GB) groups_cells_kernel(const int32_t *__restr
 }
 
 // Step 6 groups from labels in input order, where neighbouring lanes rarely
-// share a group: every labelled particle adds with its own atomic.
-__global__ void __launch_bounds__(GB) groups_particles_kernel(const int32_t *__restrict__ plabel, int64_t np,
+// share a group: every labelled particle adds with its own atomic.  With
+// skip, particles whose skip entry is >= 0 (claimed by an earlier scale of the
+// identification loop) are not counted.
+__global__ void __launch_bounds__(GB) groups_particles_kernel(const int32_t *__restrict__ plabel,
+                                                              const int32_t *__restrict__ skip, int64_t np,
                                                               int64_t ncells, uint32_t *__restrict__ parts,
                                                               uint32_t *status) {
     bool bad = false;
@@ -85,6 +88,7 @@ __global__ void __launch_bounds__(GB) groups_particles_kernel(const int32_t *__r
         for (int k = 0; k < GPER; ++k) {
             const int64_t i = i0 + k * stride;
             l[k] = i < np ? plabel[i] : -1;
+            if (skip && i < np && skip[i] >= 0) l[k] = -1;
         }
 #pragma unroll
         for (int k = 0; k < GPER; ++k) {
@@ -203,24 +207,39 @@ __global__ void __launch_bounds__(GB) claim_init_kernel(int32_t *__restrict__ ha
     }
 }
 
-// Particles an earlier scale has claimed take no label at this one.
-__global__ void __launch_bounds__(GB) claim_mask_kernel(int32_t *__restrict__ label,
-                                                        const int32_t *__restrict__ halo_scale, int64_t np) {
-    for (int64_t i = blockIdx.x * int64_t(GB) + threadIdx.x; i < np; i += int64_t(gridDim.x) * GB)
-        if (halo_scale[i] >= 0) label[i] = -1;
-}
-
-// Particles whose filtered label at this scale is a kept group are claimed.
-__global__ void __launch_bounds__(GB) claim_take_kernel(const int32_t *__restrict__ label,
-                                                        int32_t *__restrict__ halo_scale,
-                                                        int32_t *__restrict__ halo_root, int64_t np, int32_t scale) {
-    for (int64_t i = blockIdx.x * int64_t(GB) + threadIdx.x; i < np; i += int64_t(gridDim.x) * GB) {
-        const int32_t v = label[i];
-        if (v >= 0) {
-            halo_scale[i] = scale;
-            halo_root[i] = v;
+// One pass per scale after the decision: a particle keeps its label iff no
+// earlier scale claimed it and its group is kept (else -1), and a kept
+// label claims the particle for this scale.
+__global__ void __launch_bounds__(GB) claim_filter_kernel(int32_t *__restrict__ label,
+                                                          int32_t *__restrict__ halo_scale,
+                                                          int32_t *__restrict__ halo_root, int64_t np,
+                                                          int64_t ncells, const uint32_t *__restrict__ keep,
+                                                          int any_roots, int32_t scale, uint32_t *status) {
+    bool bad = false;
+    const int64_t stride = int64_t(gridDim.x) * GB;
+    for (int64_t i0 = blockIdx.x * int64_t(GB) + threadIdx.x; i0 < np; i0 += stride * GPER) {
+        int32_t l[GPER], hs[GPER];
+#pragma unroll
+        for (int k = 0; k < GPER; ++k) {
+            const int64_t i = i0 + k * stride;
+            l[k] = i < np ? label[i] : -1;
+            hs[k] = i < np ? halo_scale[i] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < GPER; ++k) {
+            const int64_t i = i0 + k * stride;
+            if (i >= np) continue;
+            int32_t v = -1;
+            if (l[k] >= ncells || l[k] < -1) bad = true;
+            else if (hs[k] < 0 && l[k] >= 0 && any_roots && keep[l[k]]) v = l[k];
+            label[i] = v;
+            if (v >= 0) {
+                halo_scale[i] = scale;
+                halo_root[i] = v;
+            }
         }
     }
+    if (bad) atomicOr(status, ST_INPUT);
 }
 
 // Step 4's correction of grid maxima (App. B), in FP64 on the FP32 field: per
@@ -302,10 +321,10 @@ hf_status hf::groups_count_cells(hf_ctx *ctx, const hf_box &box, const int32_t *
 }
 
 hf_status hf::groups_count_particles(hf_ctx *ctx, const hf_box &box, const int32_t *particle_label, int64_t np,
-                                     const GroupCounters &g) {
+                                     const GroupCounters &g, const int32_t *skip) {
     if (np <= 0) return HF_OK;
     HF_LAUNCH(ctx, K_GROUP_PARTICLES, groups_particles_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0,
-              ctx->stream, particle_label, np, cells_of(box), g.parts, ctx->d_status);
+              ctx->stream, particle_label, skip, np, cells_of(box), g.parts, ctx->d_status);
     return launch_status();
 }
 
@@ -343,18 +362,11 @@ hf_status hf::claim_init(hf_ctx *ctx, int32_t *halo_scale, int32_t *halo_root, i
     return launch_status();
 }
 
-hf_status hf::claim_mask(hf_ctx *ctx, int32_t *label, const int32_t *halo_scale, int64_t np) {
+hf_status hf::claim_filter(hf_ctx *ctx, const hf_box &box, int32_t *label, int32_t *halo_scale, int32_t *halo_root,
+                           int64_t np, const GroupCounters &g, bool any_roots, int32_t scale) {
     if (np <= 0) return HF_OK;
-    HF_LAUNCH(ctx, K_CLAIM, claim_mask_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0, ctx->stream, label,
-              halo_scale, np);
-    return launch_status();
-}
-
-hf_status hf::claim_take(hf_ctx *ctx, const int32_t *label, int32_t *halo_scale, int32_t *halo_root, int64_t np,
-                         int32_t scale) {
-    if (np <= 0) return HF_OK;
-    HF_LAUNCH(ctx, K_CLAIM, claim_take_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0, ctx->stream, label,
-              halo_scale, halo_root, np, scale);
+    HF_LAUNCH(ctx, K_CLAIM, claim_filter_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0, ctx->stream, label,
+              halo_scale, halo_root, np, cells_of(box), g.cells, any_roots ? 1 : 0, scale, ctx->d_status);
     return launch_status();
 }
 

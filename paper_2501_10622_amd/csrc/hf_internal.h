@@ -169,7 +169,7 @@ hf_status groups_count_cells(hf_ctx *ctx, const hf_box &box, const int32_t *root
                              int64_t cap, const int32_t *cell_label, const GroupCounters &g);
 // Counts particle labels in input order (one atomic per labelled particle).
 hf_status groups_count_particles(hf_ctx *ctx, const hf_box &box, const int32_t *particle_label, int64_t np,
-                                 const GroupCounters &g);
+                                 const GroupCounters &g, const int32_t *skip = nullptr);
 // Decides every group and writes the per-group outputs; then, where given,
 // the filtered cell labels.
 hf_status groups_decide(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count, int64_t cap,
@@ -200,9 +200,10 @@ hf_status cross_scale_dev(hf_ctx *ctx, const hf_box &box, const int32_t *roots, 
                           const float *c_scale, const float *c_smaller, uint8_t *pass);
 // The identification loop's particle bookkeeping (halo_scale / halo_root).
 hf_status claim_init(hf_ctx *ctx, int32_t *halo_scale, int32_t *halo_root, int64_t np);
-hf_status claim_mask(hf_ctx *ctx, int32_t *label, const int32_t *halo_scale, int64_t np);
-hf_status claim_take(hf_ctx *ctx, const int32_t *label, int32_t *halo_scale, int32_t *halo_root, int64_t np,
-                     int32_t scale);
+// After the decision: labels of claimed particles and of disposed groups
+// become -1, and the kept ones claim their particles for `scale`.
+hf_status claim_filter(hf_ctx *ctx, const hf_box &box, int32_t *label, int32_t *halo_scale, int32_t *halo_root,
+                       int64_t np, const GroupCounters &g, bool any_roots, int32_t scale);
 size_t stencil_ws_bytes(const hf_box &box);
 
 // ---------------------------------------------------------------------------

@@ -207,8 +207,9 @@ extern "C" hf_status hf_identify_ws_size(const hf_box *box, int64_t np, int32_t 
 // segmentation and step-6 labels as hf_find_halos_scales, then scale by scale
 // (largest first) the flowchart's pair of grids: the cross-scale flags of this
 // scale's maxima against the next scale's field (the zero grid after the last),
-// the labels of particles already claimed masked, the groups' statistics and
-// the step-7/8 decision, the filter, and the claim of the kept groups' particles.
+// the groups' statistics over the particles not yet claimed, the step-7/8
+// decision, and one pass that filters the labels and claims the kept groups'
+// particles.
 extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np,
                                  hf_kernel kernel, float tau, int64_t *rho, int32_t count, const hf_scale_job *scales,
                                  const hf_identify_groups *groups, double dens_th, int64_t particle_th,
@@ -240,14 +241,14 @@ extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos
         const hf_identify_groups &gj = groups[j];
         const float *next = j + 1 < count ? scales[j + 1].cwt : nullptr;
         s = cross_scale_dev(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, sj.cwt, next, pass);
-        if (s == HF_OK) s = claim_mask(ctx, sj.particle_label, halo_scale, np);
         if (s == HF_OK) s = groups_count_cells(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, sj.cell_label, g);
-        if (s == HF_OK && sj.max_cap > 0) s = groups_count_particles(ctx, *box, sj.particle_label, np, g);
+        // particles already claimed are not counted
+        if (s == HF_OK && sj.max_cap > 0) s = groups_count_particles(ctx, *box, sj.particle_label, np, g, halo_scale);
         if (s == HF_OK)
             s = groups_decide(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, g, dens_th, np, particle_th, pass,
                               gj.group_particles, gj.group_cells, gj.group_keep);
-        if (s == HF_OK) s = groups_filter(ctx, *box, sj.particle_label, sj.particle_label, np, g, sj.max_cap > 0);
-        if (s == HF_OK) s = claim_take(ctx, sj.particle_label, halo_scale, halo_root, np, j);
+        if (s == HF_OK)
+            s = claim_filter(ctx, *box, sj.particle_label, halo_scale, halo_root, np, g, sj.max_cap > 0, j);
     }
     return s;
 }
