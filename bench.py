@@ -47,8 +47,8 @@ TIMER_SYMBOLS = {
     "parent": ("parent_walk_kernel", "parent_direct_kernel"), "resolve": ("resolve_tile_kernel",), "jump_flags": ("fill_flags_kernel",),
     "jump": ("bnd_jump_first_kernel", "bnd_jump_kernel", "jump_direct_kernel"), "finalize": ("seg_finalize_kernel", "finalize_direct_kernel"),
     "label_tiles": ("tile_label_kernel",), "label_level1": ("to_level1_kernel",), "label_input": ("to_input_kernel",),
-    "groups_clear": ("groups_clear_kernel",), "groups_cells": ("groups_cells_kernel",),
-    "groups_particles": ("groups_particles_kernel",), "groups_decide": ("groups_decide_kernel",),
+    "groups_clear": ("groups_clear_kernel",), "groups_cells": ("groups_tally_kernel<false>",),
+    "groups_particles": ("groups_particles_kernel", "groups_tally_kernel<true>"), "groups_decide": ("groups_decide_kernel",),
     "groups_filter": ("groups_filter_kernel",),
     "stencil_x": ("stencil_x_kernel",), "stencil_mass": ("stencil_mass_kernel",),
     "stencil_y": ("stencil_axis_kernel<false>",), "stencil_z": ("stencil_axis_kernel<true>",),
@@ -124,7 +124,7 @@ def short_symbol(name: str) -> str:
     tmpl = m.group(2) or ""
     # keep a template argument only where it names a different pass (fft_y_kernel<INV>, the scans' use)
     return m.group(1) + (tmpl if m.group(1) in ("fft_y_kernel", "seg_reduce_kernel", "seg_scan_kernel",
-                                                               "stencil_axis_kernel") else "")
+                                                               "stencil_axis_kernel", "groups_tally_kernel") else "")
 
 
 def timer_name(symbol: str):
@@ -558,6 +558,14 @@ def identify_bench(pos, box_len: float, n: int, ctx, iters: int = 2) -> dict:
     torch.cuda.synchronize()
     ctx.sync()
     ms = start.elapsed_time(stop) / iters
+    # one more call under the kernel timer: where the time goes
+    ctx.profile(True)
+    ctx.profile_reset()
+    hfm.identify_async(pos, box_len, n, kws, bufs, 4.0, 15, ctx=ctx)
+    ctx.sync()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    kernels = {k: round(v[0], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0]) if v[1]}
     hs = bufs["halo_scale"][:np_]
     per, ok = [], True
     for i in range(len(kws)):
@@ -577,6 +585,7 @@ def identify_bench(pos, box_len: float, n: int, ctx, iters: int = 2) -> dict:
     return {"what": "identification loop over scales a = 4, 2, 1 cells (steps 2-8, no unbinding), "
                     "dens_th = 4, particle_th = 15", "ms_per_call": round(ms, 3),
             "particles_per_s": np_ / (ms / 1e3), "scales": per, "particles_claimed": claimed_all,
+            "kernels_ms_per_call": kernels,
             "checks": {"claimed_equals_kept_group_particles_and_roots": ok}}
 
 

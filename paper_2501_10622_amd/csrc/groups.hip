@@ -38,25 +38,31 @@ __global__ void __launch_bounds__(GB) groups_clear_kernel(const int32_t *__restr
 
 // Step 5: the grid volume of every group, in cells.  One workgroup counts a
 // contiguous range of GCHUNK cells (a few grid rows, a few hundred labels) in
-// an LDS table and adds it to the counters once.
+// an LDS table and adds it to the counters once.  With MASKED the same count
+// runs over `count` labels of particles in the deposit's tile order (spatially
+// coherent, like cells), skipping those whose mask entry is >= 0.
 constexpr int GCHUNK = 16384;
 constexpr int CELL_HT = 1024;
 
-__global__ void __launch_bounds__(GB) groups_cells_kernel(const int32_t *__restrict__ cell_label, int64_t ncells,
-                                                          uint32_t *__restrict__ cells, uint32_t *status) {
+template <bool MASKED>
+__global__ void __launch_bounds__(GB) groups_tally_kernel(const int32_t *__restrict__ label,
+                                                          const int32_t *__restrict__ mask, int64_t count,
+                                                          int64_t ncells, uint32_t *__restrict__ cells,
+                                                          uint32_t *status) {
     __shared__ int32_t hkey[CELL_HT];
     __shared__ uint32_t hcnt[CELL_HT];
     lds_tally_init<CELL_HT>(hkey, hcnt);
     __syncthreads();
     bool bad = false;
     const int64_t c0 = int64_t(blockIdx.x) * GCHUNK;
-    const int64_t c1 = c0 + GCHUNK < ncells ? c0 + GCHUNK : ncells;
+    const int64_t c1 = c0 + GCHUNK < count ? c0 + GCHUNK : count;
     for (int64_t base = c0; base < c1; base += int64_t(GB) * GPER) {
         int32_t l[GPER];
 #pragma unroll
         for (int k = 0; k < GPER; ++k) {
             const int64_t i = base + k * GB + threadIdx.x;
-            l[k] = i < c1 ? cell_label[i] : -1;
+            l[k] = i < c1 ? label[i] : -1;
+            if (MASKED && i < c1 && mask[i] >= 0) l[k] = -1;
         }
 #pragma unroll
         for (int k = 0; k < GPER; ++k) {
@@ -315,8 +321,16 @@ hf_status hf::groups_count_cells(hf_ctx *ctx, const hf_box &box, const int32_t *
     if (cap <= 0) return HF_OK;
     HF_LAUNCH(ctx, K_GROUP_CLEAR, groups_clear_kernel, dim3(grid_of(ctx, cap, GB)), dim3(GB), 0, ctx->stream, roots,
               d_count, cap, ncells, g, ctx->d_status);
-    HF_LAUNCH(ctx, K_GROUP_CELLS, groups_cells_kernel, dim3(unsigned((ncells + GCHUNK - 1) / GCHUNK)), dim3(GB), 0,
-              ctx->stream, cell_label, ncells, g.cells, ctx->d_status);
+    HF_LAUNCH(ctx, K_GROUP_CELLS, groups_tally_kernel<false>, dim3(unsigned((ncells + GCHUNK - 1) / GCHUNK)), dim3(GB),
+              0, ctx->stream, cell_label, nullptr, ncells, ncells, g.cells, ctx->d_status);
+    return launch_status();
+}
+
+hf_status hf::groups_count_particles_tiled(hf_ctx *ctx, const hf_box &box, const int32_t *label, const int32_t *mask,
+                                           int64_t np, const GroupCounters &g) {
+    if (np <= 0) return HF_OK;
+    HF_LAUNCH(ctx, K_GROUP_PARTICLES, groups_tally_kernel<true>, dim3(unsigned((np + GCHUNK - 1) / GCHUNK)), dim3(GB),
+              0, ctx->stream, label, mask, np, cells_of(box), g.parts, ctx->d_status);
     return launch_status();
 }
 

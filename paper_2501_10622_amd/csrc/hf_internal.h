@@ -170,6 +170,10 @@ hf_status groups_count_cells(hf_ctx *ctx, const hf_box &box, const int32_t *root
 // Counts particle labels in input order (one atomic per labelled particle).
 hf_status groups_count_particles(hf_ctx *ctx, const hf_box &box, const int32_t *particle_label, int64_t np,
                                  const GroupCounters &g, const int32_t *skip = nullptr);
+// The same count over labels in the deposit's tile order (LDS tables; entries
+// whose mask is >= 0 skipped).
+hf_status groups_count_particles_tiled(hf_ctx *ctx, const hf_box &box, const int32_t *label, const int32_t *mask,
+                                       int64_t np, const GroupCounters &g);
 // Decides every group and writes the per-group outputs; then, where given,
 // the filtered cell labels.
 hf_status groups_decide(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count, int64_t cap,

@@ -188,67 +188,139 @@ extern "C" hf_status hf_find_halos_scales(hf_ctx *ctx, const hf_box *box, const 
     return s;
 }
 
-extern "C" hf_status hf_identify_ws_size(const hf_box *box, int64_t np, int32_t count, const hf_scale_job *scales,
-                                        size_t *bytes) {
-    if (!bytes || !scales) return HF_ERR_ARG;
-    size_t base = 0;
-    hf_status s = hf_find_halos_scales_ws_size(box, np, count, &base);
+// Workspace of hf_identify: that of hf_find_halos_scales, then the group
+// counters, one pass flag per maximum of the largest list and, where the
+// deposit keeps its particle order, the claim state in that order.
+namespace {
+struct IdentifyLayout {
+    size_t base, groups, pass, claim, total;
+};
+
+hf_status identify_layout(const hf_box *box, int64_t np, int32_t count, const hf_scale_job *scales,
+                          IdentifyLayout &L) {
+    if (!scales) return HF_ERR_ARG;
+    hf_status s = hf_find_halos_scales_ws_size(box, np, count, &L.base);
     if (s != HF_OK) return s;
     int64_t cap = 0;
     for (int j = 0; j < count; ++j) {
         if (scales[j].max_cap < 0) return HF_ERR_ARG;
         cap = scales[j].max_cap > cap ? scales[j].max_cap : cap;
     }
-    *bytes = align_up(base) + groups_ws_bytes(*box) + align_up(size_t(cap));
+    L.groups = align_up(L.base);
+    L.pass = L.groups + groups_ws_bytes(*box);
+    L.claim = L.pass + align_up(size_t(cap));
+    const bool order = particle_order_supported(*box, np);
+    L.total = L.claim + (order ? 2 * align_up(sizeof(int32_t) * size_t(np)) : 0);
     return HF_OK;
 }
+}  // namespace
 
-// Sec. 2's identification loop at one grid: every scale's field, maxima,
-// segmentation and step-6 labels as hf_find_halos_scales, then scale by scale
+extern "C" hf_status hf_identify_ws_size(const hf_box *box, int64_t np, int32_t count, const hf_scale_job *scales,
+                                        size_t *bytes) {
+    if (!bytes) return HF_ERR_ARG;
+    IdentifyLayout L{};
+    hf_status s = identify_layout(box, np, count, scales, L);
+    if (s == HF_OK) *bytes = L.total;
+    return s;
+}
+
+// Sec. 2's identification loop at one grid: one deposit and one forward
+// transform, every scale's field, maxima and segmentation, then scale by scale
 // (largest first) the flowchart's pair of grids: the cross-scale flags of this
 // scale's maxima against the next scale's field (the zero grid after the last),
 // the groups' statistics over the particles not yet claimed, the step-7/8
 // decision, and one pass that filters the labels and claims the kept groups'
-// particles.
+// particles.  Where the deposit keeps its particle order, labels, counts and
+// claims run in that (tile) order, whose neighbouring particles share groups,
+// and are brought back to input order once per scale; the claim state is
+// brought back at the end.
 extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np,
                                  hf_kernel kernel, float tau, int64_t *rho, int32_t count, const hf_scale_job *scales,
                                  const hf_identify_groups *groups, double dens_th, int64_t particle_th,
                                  int32_t *halo_scale, int32_t *halo_root, void *ws, size_t ws_bytes) {
-    if (!ctx || !scales || !groups || count < 1 || count > HF_CWT_BATCH_MAX) return HF_ERR_ARG;
-    if (np < 0 || np > int64_t(UINT32_MAX) || (np > 0 && (!halo_scale || !halo_root))) return HF_ERR_ARG;
+    if (!ctx || !rho || !scales || !groups || count < 1 || count > HF_CWT_BATCH_MAX) return HF_ERR_ARG;
+    if (np < 0 || np > int64_t(UINT32_MAX) || (np > 0 && (!pos || !halo_scale || !halo_root))) return HF_ERR_ARG;
+    if ((dtype != HF_F32 && dtype != HF_F64) || (kernel != HF_KERNEL_SAMPLED && kernel != HF_KERNEL_ANALYTIC) ||
+        tau != tau)
+        return HF_ERR_ARG;
     if (!(dens_th >= 0.0) || !(dens_th < 1e300) || particle_th < 0) return HF_ERR_ARG;
+    double kws[HF_CWT_BATCH_MAX];
+    float *cwts[HF_CWT_BATCH_MAX];
     for (int j = 0; j < count; ++j) {
-        if (j > 0 && !(scales[j].kw > scales[j - 1].kw)) return HF_ERR_ARG;  // largest scale first
-        if (scales[j].max_cap > 0 && (!groups[j].group_particles || !groups[j].group_cells || !groups[j].group_keep))
+        const hf_scale_job &sj = scales[j];
+        if (j > 0 && !(sj.kw > scales[j - 1].kw)) return HF_ERR_ARG;  // largest scale first
+        if (!sj.cwt || !sj.d_count || !sj.cell_label || sj.max_cap < 0 || (sj.max_cap > 0 && !sj.max_idx) ||
+            (np > 0 && !sj.particle_label) || !(sj.kw > 0.0))
             return HF_ERR_ARG;
+        if (sj.max_cap > 0 && (!groups[j].group_particles || !groups[j].group_cells || !groups[j].group_keep))
+            return HF_ERR_ARG;
+        kws[j] = sj.kw;
+        cwts[j] = sj.cwt;
     }
     hf_status s = check_box(box);
     if (s != HF_OK) return s;
-    size_t need = 0, base = 0;
-    s = hf_identify_ws_size(box, np, count, scales, &need);
-    if (s == HF_OK) s = hf_find_halos_scales_ws_size(box, np, count, &base);
+    IdentifyLayout L{};
+    s = identify_layout(box, np, count, scales, L);
     if (s != HF_OK) return s;
-    s = check_ws(ws, ws_bytes, need);
+    s = check_ws(ws, ws_bytes, L.total);
     if (s != HF_OK) return s;
-    s = hf_find_halos_scales(ctx, box, pos, dtype, np, kernel, tau, rho, count, scales, ws, base);
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    const bool order = particle_order_supported(*box, np);
+    char *w0 = static_cast<char *>(ws);
+    char *sw = w0;
+    size_t sb = L.base;
+    ParticleOrder po{};
+    if (order) {
+        po = particle_order_at(*box, ws, np);
+        sw += particle_order_bytes(*box, np);
+        sb -= particle_order_bytes(*box, np);
+        s = deposit_tiled(ctx, *box, pos, dtype, np, rho, sw, &po);
+    } else {
+        s = hf_deposit(ctx, box, pos, dtype, np, rho, sw, sb);
+    }
+    if (s == HF_OK) s = hf_cwt_scales(ctx, box, rho, count, kws, kernel, cwts, sw, sb);
+    for (int j = 0; j < count && s == HF_OK; ++j) {
+        const hf_scale_job &sj = scales[j];
+        s = maxima_segment(ctx, *box, sj.cwt, tau, sj.max_idx, sj.max_cap, sj.d_count, sj.cell_label, sw, sb);
+    }
     if (s != HF_OK) return s;
-    char *rest = static_cast<char *>(ws) + align_up(base);
-    const GroupCounters g = group_counters_at(*box, rest);
-    uint8_t *pass = reinterpret_cast<uint8_t *>(rest + groups_ws_bytes(*box));
-    s = claim_init(ctx, halo_scale, halo_root, np);
+    const GroupCounters g = group_counters_at(*box, w0 + L.groups);
+    uint8_t *pass = reinterpret_cast<uint8_t *>(w0 + L.pass);
+    // claim state: in tile order where the order is kept (brought back at the end)
+    int32_t *cs = order ? reinterpret_cast<int32_t *>(w0 + L.claim) : halo_scale;
+    int32_t *cr = order ? reinterpret_cast<int32_t *>(w0 + L.claim + align_up(sizeof(int32_t) * size_t(np)))
+                        : halo_root;
+    int32_t *lab2 = reinterpret_cast<int32_t *>(sw);  // tile-order labels (label scratch)
+    s = claim_init(ctx, cs, cr, np);
     for (int j = 0; j < count && s == HF_OK; ++j) {
         const hf_scale_job &sj = scales[j];
         const hf_identify_groups &gj = groups[j];
         const float *next = j + 1 < count ? scales[j + 1].cwt : nullptr;
+        int32_t *lab = order ? lab2 : sj.particle_label;
         s = cross_scale_dev(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, sj.cwt, next, pass);
+        if (s == HF_OK)
+            s = order ? label_tiles(ctx, *box, np, po, sj.cell_label, sw, nullptr)
+                      : hf_label(ctx, box, pos, dtype, np, sj.cell_label, sj.particle_label);
         if (s == HF_OK) s = groups_count_cells(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, sj.cell_label, g);
         // particles already claimed are not counted
-        if (s == HF_OK && sj.max_cap > 0) s = groups_count_particles(ctx, *box, sj.particle_label, np, g, halo_scale);
+        if (s == HF_OK && sj.max_cap > 0)
+            s = order ? groups_count_particles_tiled(ctx, *box, lab, cs, np, g)
+                      : groups_count_particles(ctx, *box, lab, np, g, cs);
         if (s == HF_OK)
             s = groups_decide(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, g, dens_th, np, particle_th, pass,
                               gj.group_particles, gj.group_cells, gj.group_keep);
-        if (s == HF_OK)
-            s = claim_filter(ctx, *box, sj.particle_label, halo_scale, halo_root, np, g, sj.max_cap > 0, j);
+        if (s == HF_OK) s = claim_filter(ctx, *box, lab, cs, cr, np, g, sj.max_cap > 0, j);
+        if (s == HF_OK && order) s = label_back(ctx, *box, np, po, sj.particle_label, sw, nullptr);
+    }
+    if (s == HF_OK && order && np > 0) {
+        // the claim state back to input order through the same maps
+        const size_t bytes = sizeof(int32_t) * size_t(np);
+        if (hipMemcpyAsync(lab2, cs, bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess) return HF_ERR_DEVICE;
+        s = label_back(ctx, *box, np, po, halo_scale, sw, nullptr);
+        if (s == HF_OK &&
+            hipMemcpyAsync(lab2, cr, bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
+            return HF_ERR_DEVICE;
+        if (s == HF_OK) s = label_back(ctx, *box, np, po, halo_root, sw, nullptr);
     }
     return s;
 }
