@@ -203,19 +203,19 @@ __global__ void __launch_bounds__(GB) cross_scale_kernel(const int32_t *__restri
 }
 
 // The identification loop's per-particle bookkeeping: halo_scale[p] is the
-// scale that claimed particle p (-1 while none has), halo_root[p] the root of
-// its group there.
+// scale that claimed particle p (-1 while none has), halo_root[p] (may be
+// null) the root of its group there.
 __global__ void __launch_bounds__(GB) claim_init_kernel(int32_t *__restrict__ halo_scale,
                                                         int32_t *__restrict__ halo_root, int64_t np) {
     for (int64_t i = blockIdx.x * int64_t(GB) + threadIdx.x; i < np; i += int64_t(gridDim.x) * GB) {
         halo_scale[i] = -1;
-        halo_root[i] = -1;
+        if (halo_root) halo_root[i] = -1;
     }
 }
 
 // One pass per scale after the decision: a particle keeps its label iff no
 // earlier scale claimed it and its group is kept (else -1), and a kept
-// label claims the particle for this scale.
+// label claims the particle for this scale (halo_root may be null).
 __global__ void __launch_bounds__(GB) claim_filter_kernel(int32_t *__restrict__ label,
                                                           int32_t *__restrict__ halo_scale,
                                                           int32_t *__restrict__ halo_root, int64_t np,
@@ -241,11 +241,34 @@ __global__ void __launch_bounds__(GB) claim_filter_kernel(int32_t *__restrict__ 
             label[i] = v;
             if (v >= 0) {
                 halo_scale[i] = scale;
-                halo_root[i] = v;
+                if (halo_root) halo_root[i] = v;
             }
         }
     }
     if (bad) atomicOr(status, ST_INPUT);
+}
+
+// A scale's filtered labels in input order claim their particles.
+__global__ void __launch_bounds__(GB) claim_take_kernel(const int32_t *__restrict__ label,
+                                                        int32_t *__restrict__ halo_scale,
+                                                        int32_t *__restrict__ halo_root, int64_t np, int32_t scale) {
+    const int64_t stride = int64_t(gridDim.x) * GB;
+    for (int64_t i0 = blockIdx.x * int64_t(GB) + threadIdx.x; i0 < np; i0 += stride * GPER) {
+        int32_t l[GPER];
+#pragma unroll
+        for (int k = 0; k < GPER; ++k) {
+            const int64_t i = i0 + k * stride;
+            l[k] = i < np ? label[i] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < GPER; ++k) {
+            const int64_t i = i0 + k * stride;
+            if (l[k] >= 0) {
+                halo_scale[i] = scale;
+                halo_root[i] = l[k];
+            }
+        }
+    }
 }
 
 // Step 4's correction of grid maxima (App. B), in FP64 on the FP32 field: per
@@ -381,6 +404,14 @@ hf_status hf::claim_filter(hf_ctx *ctx, const hf_box &box, int32_t *label, int32
     if (np <= 0) return HF_OK;
     HF_LAUNCH(ctx, K_CLAIM, claim_filter_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0, ctx->stream, label,
               halo_scale, halo_root, np, cells_of(box), g.cells, any_roots ? 1 : 0, scale, ctx->d_status);
+    return launch_status();
+}
+
+hf_status hf::claim_take(hf_ctx *ctx, const int32_t *label, int32_t *halo_scale, int32_t *halo_root, int64_t np,
+                         int32_t scale) {
+    if (np <= 0) return HF_OK;
+    HF_LAUNCH(ctx, K_CLAIM, claim_take_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0, ctx->stream, label,
+              halo_scale, halo_root, np, scale);
     return launch_status();
 }
 

@@ -205,9 +205,14 @@ hf_status cross_scale_dev(hf_ctx *ctx, const hf_box &box, const int32_t *roots, 
 // The identification loop's particle bookkeeping (halo_scale / halo_root).
 hf_status claim_init(hf_ctx *ctx, int32_t *halo_scale, int32_t *halo_root, int64_t np);
 // After the decision: labels of claimed particles and of disposed groups
-// become -1, and the kept ones claim their particles for `scale`.
+// become -1, and the kept ones claim their particles for `scale` (halo_root
+// may be null).
 hf_status claim_filter(hf_ctx *ctx, const hf_box &box, int32_t *label, int32_t *halo_scale, int32_t *halo_root,
                        int64_t np, const GroupCounters &g, bool any_roots, int32_t scale);
+// Filtered labels (input order) claim their particles: halo_scale = scale,
+// halo_root = the label, where the label is >= 0.
+hf_status claim_take(hf_ctx *ctx, const int32_t *label, int32_t *halo_scale, int32_t *halo_root, int64_t np,
+                     int32_t scale);
 size_t stencil_ws_bytes(const hf_box &box);
 
 // ---------------------------------------------------------------------------

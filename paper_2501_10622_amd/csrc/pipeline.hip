@@ -210,7 +210,7 @@ hf_status identify_layout(const hf_box *box, int64_t np, int32_t count, const hf
     L.pass = L.groups + groups_ws_bytes(*box);
     L.claim = L.pass + align_up(size_t(cap));
     const bool order = particle_order_supported(*box, np);
-    L.total = L.claim + (order ? 2 * align_up(sizeof(int32_t) * size_t(np)) : 0);
+    L.total = L.claim + (order ? align_up(sizeof(int32_t) * size_t(np)) : 0);
     return HF_OK;
 }
 }  // namespace
@@ -231,9 +231,9 @@ extern "C" hf_status hf_identify_ws_size(const hf_box *box, int64_t np, int32_t 
 // the groups' statistics over the particles not yet claimed, the step-7/8
 // decision, and one pass that filters the labels and claims the kept groups'
 // particles.  Where the deposit keeps its particle order, labels, counts and
-// claims run in that (tile) order, whose neighbouring particles share groups,
-// and are brought back to input order once per scale; the claim state is
-// brought back at the end.
+// claims run in that (tile) order, whose neighbouring particles share groups;
+// each scale's filtered labels come back to input order once and claim their
+// particles there too.
 extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np,
                                  hf_kernel kernel, float tau, int64_t *rho, int32_t count, const hf_scale_job *scales,
                                  const hf_identify_groups *groups, double dens_th, int64_t particle_th,
@@ -286,12 +286,12 @@ extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos
     if (s != HF_OK) return s;
     const GroupCounters g = group_counters_at(*box, w0 + L.groups);
     uint8_t *pass = reinterpret_cast<uint8_t *>(w0 + L.pass);
-    // claim state: in tile order where the order is kept (brought back at the end)
+    // which scale claimed each particle, also kept in tile order where the
+    // order is kept (the masks of the counts and the claims there)
     int32_t *cs = order ? reinterpret_cast<int32_t *>(w0 + L.claim) : halo_scale;
-    int32_t *cr = order ? reinterpret_cast<int32_t *>(w0 + L.claim + align_up(sizeof(int32_t) * size_t(np)))
-                        : halo_root;
     int32_t *lab2 = reinterpret_cast<int32_t *>(sw);  // tile-order labels (label scratch)
-    s = claim_init(ctx, cs, cr, np);
+    s = claim_init(ctx, halo_scale, halo_root, np);
+    if (s == HF_OK && order) s = claim_init(ctx, cs, nullptr, np);
     for (int j = 0; j < count && s == HF_OK; ++j) {
         const hf_scale_job &sj = scales[j];
         const hf_identify_groups &gj = groups[j];
@@ -309,18 +309,10 @@ extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos
         if (s == HF_OK)
             s = groups_decide(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, g, dens_th, np, particle_th, pass,
                               gj.group_particles, gj.group_cells, gj.group_keep);
-        if (s == HF_OK) s = claim_filter(ctx, *box, lab, cs, cr, np, g, sj.max_cap > 0, j);
+        if (s == HF_OK)
+            s = claim_filter(ctx, *box, lab, cs, order ? nullptr : halo_root, np, g, sj.max_cap > 0, j);
         if (s == HF_OK && order) s = label_back(ctx, *box, np, po, sj.particle_label, sw, nullptr);
-    }
-    if (s == HF_OK && order && np > 0) {
-        // the claim state back to input order through the same maps
-        const size_t bytes = sizeof(int32_t) * size_t(np);
-        if (hipMemcpyAsync(lab2, cs, bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess) return HF_ERR_DEVICE;
-        s = label_back(ctx, *box, np, po, halo_scale, sw, nullptr);
-        if (s == HF_OK &&
-            hipMemcpyAsync(lab2, cr, bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
-            return HF_ERR_DEVICE;
-        if (s == HF_OK) s = label_back(ctx, *box, np, po, halo_root, sw, nullptr);
+        if (s == HF_OK && order) s = claim_take(ctx, sj.particle_label, halo_scale, halo_root, np, j);
     }
     return s;
 }
