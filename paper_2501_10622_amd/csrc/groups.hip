@@ -78,6 +78,60 @@ __global__ void __launch_bounds__(GB) groups_tally_kernel(const int32_t *__restr
     if (bad) atomicOr(status, ST_INPUT);
 }
 
+// Step 5 by runs: each thread takes CELL_RUN consecutive cells of a row (one
+// vector load per four) and adds each run of equal labels to the LDS table
+// once, so a basin a few cells wide costs one insert per run instead of one
+// per cell.
+constexpr int CELL_RUN = 16;
+
+__global__ void __launch_bounds__(GB) groups_cell_runs_kernel(const int32_t *__restrict__ cell_label, int64_t ncells,
+                                                              uint32_t *__restrict__ cells, uint32_t *status) {
+    __shared__ int32_t hkey[CELL_HT];
+    __shared__ uint32_t hcnt[CELL_HT];
+    lds_tally_init<CELL_HT>(hkey, hcnt);
+    __syncthreads();
+    bool bad = false;
+    const int64_t c0 = int64_t(blockIdx.x) * GCHUNK;
+    const int64_t c1 = c0 + GCHUNK < ncells ? c0 + GCHUNK : ncells;
+    for (int64_t b = c0 + int64_t(threadIdx.x) * CELL_RUN; b < c1; b += int64_t(GB) * CELL_RUN) {
+        int32_t v[CELL_RUN];
+        if (b + CELL_RUN <= c1) {
+            const int4 *p = reinterpret_cast<const int4 *>(cell_label + b);
+#pragma unroll
+            for (int q = 0; q < CELL_RUN / 4; ++q) {
+                const int4 w = p[q];
+                v[4 * q] = w.x;
+                v[4 * q + 1] = w.y;
+                v[4 * q + 2] = w.z;
+                v[4 * q + 3] = w.w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < CELL_RUN; ++q) v[q] = b + q < c1 ? cell_label[b + q] : -1;
+        }
+        int32_t run = -1;
+        uint32_t len = 0;
+#pragma unroll
+        for (int q = 0; q < CELL_RUN; ++q) {
+            int32_t l = v[q];
+            if (l >= ncells || l < -1) {
+                bad = true;
+                l = -1;
+            }
+            if (l != run) {
+                if (run >= 0) lds_tally_add<CELL_HT>(hkey, hcnt, cells, run, len);
+                run = l;
+                len = 0;
+            }
+            ++len;
+        }
+        if (run >= 0) lds_tally_add<CELL_HT>(hkey, hcnt, cells, run, len);
+    }
+    __syncthreads();
+    lds_tally_flush<CELL_HT>(hkey, hcnt, cells);
+    if (bad) atomicOr(status, ST_INPUT);
+}
+
 // Step 6 groups from labels in input order, where neighbouring lanes rarely
 // share a group: every labelled particle adds with its own atomic.  With
 // skip, particles whose skip entry is >= 0 (claimed by an earlier scale of the
@@ -344,8 +398,13 @@ hf_status hf::groups_count_cells(hf_ctx *ctx, const hf_box &box, const int32_t *
     if (cap <= 0) return HF_OK;
     HF_LAUNCH(ctx, K_GROUP_CLEAR, groups_clear_kernel, dim3(grid_of(ctx, cap, GB)), dim3(GB), 0, ctx->stream, roots,
               d_count, cap, ncells, g, ctx->d_status);
-    HF_LAUNCH(ctx, K_GROUP_CELLS, groups_tally_kernel<false>, dim3(unsigned((ncells + GCHUNK - 1) / GCHUNK)), dim3(GB),
-              0, ctx->stream, cell_label, nullptr, ncells, ncells, g.cells, ctx->d_status);
+    const dim3 grid(unsigned((ncells + GCHUNK - 1) / GCHUNK));
+    if (reinterpret_cast<uintptr_t>(cell_label) % sizeof(int4) == 0)
+        HF_LAUNCH(ctx, K_GROUP_CELLS, groups_cell_runs_kernel, grid, dim3(GB), 0, ctx->stream, cell_label, ncells,
+                  g.cells, ctx->d_status);
+    else  // rows not 16-byte aligned: one label per lane
+        HF_LAUNCH(ctx, K_GROUP_CELLS, groups_tally_kernel<false>, grid, dim3(GB), 0, ctx->stream, cell_label, nullptr,
+                  ncells, ncells, g.cells, ctx->d_status);
     return launch_status();
 }
 

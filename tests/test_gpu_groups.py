@@ -260,3 +260,19 @@ def test_filtered_pipeline_equals_pipeline_then_groups(n, L, np_, halos, a, seed
         assert torch.equal(fb[k][:cnt], fb2[k][:cnt]), k
     for k in ("particle_label", "cell_label_kept"):
         assert torch.equal(fb[k], fb2[k]), k
+
+
+@pytest.mark.parametrize("offset", [0, 1, 3])
+def test_cell_counts_on_unaligned_labels(offset):
+    # the cell counts read four labels per load where the grid is 16-byte
+    # aligned and one per lane otherwise: both give the oracle's counts
+    n = 48
+    roots, cl, pl = synthetic_labels(n, 500, 100000, 9)
+    want = O.group_stats(cl, pl, roots, n, len(pl), 4.0, 15)
+    buf = torch.empty(n ** 3 + offset, dtype=torch.int32, device="cuda")
+    view = buf[offset:].view(n, n, n)
+    view.copy_(cuda(cl))
+    out = hfm().groups(view, cuda(pl), cuda(roots), len(pl), 4.0, 15)
+    hfm().sync()
+    np.testing.assert_array_equal(out["cells"].cpu().numpy().astype(np.int64), want["cells"])
+    np.testing.assert_array_equal(out["keep"].cpu().numpy().astype(bool), want["keep"])
