@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(ST_THREADS)
     };
     stencil_weights(wa, wb, h, wdx);
     if (x < n) {
-        constexpr int UB = 2 * LOAD_BATCH;  // 2 UB loads in flight per lane
+        constexpr int UB = 4 * LOAD_BATCH;  // 2 UB loads in flight per lane (all of a tile's lines at h <= 16)
         for (int rb = grp; rb < R; rb += ST_GROUPS * UB) {
             float v0[UB], v1[UB];
 #pragma unroll
