@@ -47,8 +47,8 @@ TIMER_SYMBOLS = {
     "parent": ("parent_walk_kernel", "parent_direct_kernel"), "resolve": ("resolve_tile_kernel",), "jump_flags": ("fill_flags_kernel",),
     "jump": ("bnd_jump_first_kernel", "bnd_jump_kernel", "jump_direct_kernel"), "finalize": ("seg_finalize_kernel", "finalize_direct_kernel"),
     "label_tiles": ("tile_label_kernel",), "label_level1": ("to_level1_kernel",), "label_input": ("to_input_kernel",),
-    "groups_clear": ("groups_clear_kernel",), "groups_cells": ("groups_tally_kernel<false>",),
-    "groups_particles": ("groups_particles_kernel", "groups_tally_kernel<true>"), "groups_decide": ("groups_decide_kernel",),
+    "groups_clear": ("groups_clear_kernel",), "groups_cells": ("groups_runs_kernel<false>", "groups_tally_kernel<false>"),
+    "groups_particles": ("groups_particles_kernel", "groups_runs_kernel<true>", "groups_tally_kernel<true>"), "groups_decide": ("groups_decide_kernel",),
     "groups_filter": ("groups_filter_kernel",),
     "stencil_x": ("stencil_x_kernel",), "stencil_mass": ("stencil_mass_kernel",),
     "stencil_y": ("stencil_axis_kernel<false>",), "stencil_z": ("stencil_axis_kernel<true>",),
@@ -124,7 +124,8 @@ def short_symbol(name: str) -> str:
     tmpl = m.group(2) or ""
     # keep a template argument only where it names a different pass (fft_y_kernel<INV>, the scans' use)
     return m.group(1) + (tmpl if m.group(1) in ("fft_y_kernel", "seg_reduce_kernel", "seg_scan_kernel",
-                                                               "stencil_axis_kernel", "groups_tally_kernel") else "")
+                                                               "stencil_axis_kernel", "groups_tally_kernel",
+                                                               "groups_runs_kernel") else "")
 
 
 def timer_name(symbol: str):

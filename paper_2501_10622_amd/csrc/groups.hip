@@ -81,22 +81,27 @@ __global__ void __launch_bounds__(GB) groups_tally_kernel(const int32_t *__restr
 // Step 5 by runs: each thread takes CELL_RUN consecutive cells of a row (one
 // vector load per four) and adds each run of equal labels to the LDS table
 // once, so a basin a few cells wide costs one insert per run instead of one
-// per cell.
+// per cell.  With MASKED, the same over particle labels in the deposit's tile
+// order, skipping those whose mask entry is >= 0.  Both arrays 16-byte aligned.
 constexpr int CELL_RUN = 16;
 
-__global__ void __launch_bounds__(GB) groups_cell_runs_kernel(const int32_t *__restrict__ cell_label, int64_t ncells,
-                                                              uint32_t *__restrict__ cells, uint32_t *status) {
+template <bool MASKED>
+__global__ void __launch_bounds__(GB) groups_runs_kernel(const int32_t *__restrict__ cell_label,
+                                                         const int32_t *__restrict__ mask, int64_t count,
+                                                         int64_t ncells, uint32_t *__restrict__ cells,
+                                                         uint32_t *status) {
     __shared__ int32_t hkey[CELL_HT];
     __shared__ uint32_t hcnt[CELL_HT];
     lds_tally_init<CELL_HT>(hkey, hcnt);
     __syncthreads();
     bool bad = false;
     const int64_t c0 = int64_t(blockIdx.x) * GCHUNK;
-    const int64_t c1 = c0 + GCHUNK < ncells ? c0 + GCHUNK : ncells;
+    const int64_t c1 = c0 + GCHUNK < count ? c0 + GCHUNK : count;
     for (int64_t b = c0 + int64_t(threadIdx.x) * CELL_RUN; b < c1; b += int64_t(GB) * CELL_RUN) {
         int32_t v[CELL_RUN];
         if (b + CELL_RUN <= c1) {
             const int4 *p = reinterpret_cast<const int4 *>(cell_label + b);
+            const int4 *pm = MASKED ? reinterpret_cast<const int4 *>(mask + b) : nullptr;
 #pragma unroll
             for (int q = 0; q < CELL_RUN / 4; ++q) {
                 const int4 w = p[q];
@@ -104,10 +109,20 @@ __global__ void __launch_bounds__(GB) groups_cell_runs_kernel(const int32_t *__r
                 v[4 * q + 1] = w.y;
                 v[4 * q + 2] = w.z;
                 v[4 * q + 3] = w.w;
+                if (MASKED) {
+                    const int4 m = pm[q];
+                    if (m.x >= 0) v[4 * q] = -1;
+                    if (m.y >= 0) v[4 * q + 1] = -1;
+                    if (m.z >= 0) v[4 * q + 2] = -1;
+                    if (m.w >= 0) v[4 * q + 3] = -1;
+                }
             }
         } else {
 #pragma unroll
-            for (int q = 0; q < CELL_RUN; ++q) v[q] = b + q < c1 ? cell_label[b + q] : -1;
+            for (int q = 0; q < CELL_RUN; ++q) {
+                v[q] = b + q < c1 ? cell_label[b + q] : -1;
+                if (MASKED && b + q < c1 && mask[b + q] >= 0) v[q] = -1;
+            }
         }
         int32_t run = -1;
         uint32_t len = 0;
@@ -400,8 +415,8 @@ hf_status hf::groups_count_cells(hf_ctx *ctx, const hf_box &box, const int32_t *
               d_count, cap, ncells, g, ctx->d_status);
     const dim3 grid(unsigned((ncells + GCHUNK - 1) / GCHUNK));
     if (reinterpret_cast<uintptr_t>(cell_label) % sizeof(int4) == 0)
-        HF_LAUNCH(ctx, K_GROUP_CELLS, groups_cell_runs_kernel, grid, dim3(GB), 0, ctx->stream, cell_label, ncells,
-                  g.cells, ctx->d_status);
+        HF_LAUNCH(ctx, K_GROUP_CELLS, groups_runs_kernel<false>, grid, dim3(GB), 0, ctx->stream, cell_label, nullptr,
+                  ncells, ncells, g.cells, ctx->d_status);
     else  // rows not 16-byte aligned: one label per lane
         HF_LAUNCH(ctx, K_GROUP_CELLS, groups_tally_kernel<false>, grid, dim3(GB), 0, ctx->stream, cell_label, nullptr,
                   ncells, ncells, g.cells, ctx->d_status);
@@ -411,8 +426,13 @@ hf_status hf::groups_count_cells(hf_ctx *ctx, const hf_box &box, const int32_t *
 hf_status hf::groups_count_particles_tiled(hf_ctx *ctx, const hf_box &box, const int32_t *label, const int32_t *mask,
                                            int64_t np, const GroupCounters &g) {
     if (np <= 0) return HF_OK;
-    HF_LAUNCH(ctx, K_GROUP_PARTICLES, groups_tally_kernel<true>, dim3(unsigned((np + GCHUNK - 1) / GCHUNK)), dim3(GB),
-              0, ctx->stream, label, mask, np, cells_of(box), g.parts, ctx->d_status);
+    const dim3 grid(unsigned((np + GCHUNK - 1) / GCHUNK));
+    if (reinterpret_cast<uintptr_t>(label) % sizeof(int4) == 0 && reinterpret_cast<uintptr_t>(mask) % sizeof(int4) == 0)
+        HF_LAUNCH(ctx, K_GROUP_PARTICLES, groups_runs_kernel<true>, grid, dim3(GB), 0, ctx->stream, label, mask, np,
+                  cells_of(box), g.parts, ctx->d_status);
+    else
+        HF_LAUNCH(ctx, K_GROUP_PARTICLES, groups_tally_kernel<true>, grid, dim3(GB), 0, ctx->stream, label, mask, np,
+                  cells_of(box), g.parts, ctx->d_status);
     return launch_status();
 }
 
