@@ -102,6 +102,31 @@ def test_null_context_rejected_before_any_device_call(lib):
     assert lib.hf_label(None, ctypes.byref(b), vp(0), 0, 0, vp(0), vp(0)) == hf.HF_ERR_ARG
     assert lib.hf_sync(None) == hf.HF_ERR_ARG
     assert lib.hf_destroy(None) == hf.HF_ERR_ARG
+    assert lib.hf_cwt_stencil(None, ctypes.byref(b), vp(0), 0.1, 3, vp(0), vp(0), 0) == hf.HF_ERR_ARG
+    jobs = (hf.ScaleJob * 1)(hf.ScaleJob(0.1, 0, 0, 0, 0, 0, 0))
+    groups = (hf.IdentifyGroups * 1)(hf.IdentifyGroups(0, 0, 0))
+    assert lib.hf_identify(None, ctypes.byref(b), vp(0), 0, 0, 0, 0.0, vp(0), 1, jobs, groups, 4.0, 15, vp(0),
+                           vp(0), vp(0), 0) == hf.HF_ERR_ARG
+
+
+def test_identify_workspace(lib):
+    # that of the multi-scale step, the group counters (8 B a cell) and one
+    # byte per maximum of the largest list; more with more particles
+    b = hf.Box(64, 15, 100.0)
+    out, base = ctypes.c_size_t(), ctypes.c_size_t()
+
+    def jobs(*caps):
+        return (hf.ScaleJob * len(caps))(*[hf.ScaleJob(0.1 * (j + 1), 0, 0, c, 0, 0, 0) for j, c in enumerate(caps)])
+
+    assert lib.hf_find_halos_scales_ws_size(ctypes.byref(b), 100000, 2, ctypes.byref(base)) == hf.HF_OK
+    assert lib.hf_identify_ws_size(ctypes.byref(b), 100000, 2, jobs(1000, 5000), ctypes.byref(out)) == hf.HF_OK
+    assert out.value >= base.value + 8 * 64 ** 3 + 5000
+    small = out.value
+    assert lib.hf_identify_ws_size(ctypes.byref(b), 100000, 2, jobs(1000, 50000), ctypes.byref(out)) == hf.HF_OK
+    assert out.value >= small + 45000 - 256
+    assert lib.hf_identify_ws_size(ctypes.byref(b), 100000, 2, jobs(1000, -1), ctypes.byref(out)) == hf.HF_ERR_ARG
+    assert lib.hf_identify_ws_size(ctypes.byref(b), 100000, 0, jobs(1000), ctypes.byref(out)) == hf.HF_ERR_ARG
+    assert lib.hf_identify_ws_size(ctypes.byref(b), 100000, 1, None, ctypes.byref(out)) == hf.HF_ERR_ARG
 
 
 def test_create_out_pointer_checked(lib):
