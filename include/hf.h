@@ -68,8 +68,14 @@ typedef enum { HF_F32 = 0, HF_F64 = 1 } hf_dtype;
  *            over periodic images (the paper's discretised convolution,
  *            Sec. 2.1), applied through its exact DFT.
  *  ANALYTIC: the continuum Fourier transform of Eq. (4),
- *            32 pi^1.5 w^-1.5 (k/w)^2 exp(-(k/w)^2), at the DFT wavenumbers. */
-typedef enum { HF_KERNEL_SAMPLED = 0, HF_KERNEL_ANALYTIC = 1 } hf_kernel;
+ *            32 pi^1.5 w^-1.5 (k/w)^2 exp(-(k/w)^2), at the DFT wavenumbers.
+ *  STENCIL:  the sampled wavelet truncated to the cube of half-width
+ *            Int(1.5/k_w + 5) (Table 1's gdw_resolution), no images, applied
+ *            in real space as hf_cwt_stencil does.  Taken by hf_cwt,
+ *            hf_find_halos and hf_find_halos_filtered (half-widths up to
+ *            HF_STENCIL_MAX_HALF_WIDTH, else HF_ERR_ARG); the batched and
+ *            multi-scale calls, which share FFT passes, return HF_ERR_ARG. */
+typedef enum { HF_KERNEL_SAMPLED = 0, HF_KERNEL_ANALYTIC = 1, HF_KERNEL_STENCIL = 2 } hf_kernel;
 
 /* Periodic box: n^3 grid on a side of box_len (Mpc/h); node g sits at g*box_len/n. */
 typedef struct {

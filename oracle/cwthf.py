@@ -212,7 +212,11 @@ def cwt_field(f: np.ndarray, box_len: float, w: float, mode: str = "sampled") ->
 
 
 def cwt(rho: np.ndarray, box_len: float, kw: float, mode: str = "sampled") -> np.ndarray:
-    """Step 3 on a CIC grid: normalise to the mean density, then Eq. (2)."""
+    """Step 3 on a CIC grid: normalise to the mean density, then Eq. (2).
+    ``stencil`` is the truncated real-space stencil of Sec. 2.1 with Table 1's
+    half-width (``stencil_cwt``)."""
+    if mode == "stencil":
+        return stencil_cwt(rho, box_len, kw)
     return cwt_field(normalise(rho), box_len, scale_w(kw, box_len), mode)
 
 

@@ -925,13 +925,23 @@ bool fill_job(CwtJobs &J, int j, const int64_t *rho, float *cwt, double box_len,
 
 }  // namespace
 
-size_t hf::cwt_ws_bytes(const hf_box &box) { return cwt_layout(box.n).total; }
+// HF_STAGE_CWT covers either transform: the FFT's spectrum and tables or the
+// real-space stencil's three grids.
+size_t hf::cwt_ws_bytes(const hf_box &box) {
+    const size_t f = cwt_layout(box.n).total, st = stencil_ws_bytes(box);
+    return f > st ? f : st;
+}
 
 extern "C" hf_status hf_cwt(hf_ctx *ctx, const hf_box *box, const int64_t *rho, double kw, hf_kernel kernel,
                             float *cwt, void *ws, size_t ws_bytes) {
     if (!ctx || !rho || !cwt) return HF_ERR_ARG;
-    if (kernel != HF_KERNEL_SAMPLED && kernel != HF_KERNEL_ANALYTIC) return HF_ERR_ARG;
+    if (kernel != HF_KERNEL_SAMPLED && kernel != HF_KERNEL_ANALYTIC && kernel != HF_KERNEL_STENCIL) return HF_ERR_ARG;
     if (!(kw > 0.0) || !std::isfinite(kw)) return HF_ERR_ARG;
+    if (kernel == HF_KERNEL_STENCIL) {
+        const int32_t h = stencil_half_width(kw);  // Table 1's gdw_resolution
+        if (h < 0) return HF_ERR_ARG;
+        return hf_cwt_stencil(ctx, box, rho, kw, h, cwt, ws, ws_bytes);
+    }
     hf_status s = check_box(box);
     if (s != HF_OK) return s;
     const size_t need = cwt_layout(box->n).total;

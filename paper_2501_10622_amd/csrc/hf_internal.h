@@ -214,6 +214,12 @@ hf_status claim_filter(hf_ctx *ctx, const hf_box &box, int32_t *label, int32_t *
 hf_status claim_take(hf_ctx *ctx, const int32_t *label, int32_t *halo_scale, int32_t *halo_root, int64_t np,
                      int32_t scale);
 size_t stencil_ws_bytes(const hf_box &box);
+// Table 1's stencil half-width Int(1.5/k_w + 5) for HF_KERNEL_STENCIL, or -1
+// when it exceeds HF_STENCIL_MAX_HALF_WIDTH.
+inline int32_t stencil_half_width(double kw) {
+    const double h = __builtin_floor(1.5 / kw + 5.0);
+    return h <= double(HF_STENCIL_MAX_HALF_WIDTH) ? int32_t(h) : -1;
+}
 
 // ---------------------------------------------------------------------------
 // Exact 128-bit sums of non-negative int64 cell masses (the mean density of a

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libhf.so")
 HF_OK, HF_ERR_ARG, HF_ERR_SIZE, HF_ERR_WORKSPACE = 0, 1, 2, 3
 HF_ERR_OVERFLOW, HF_ERR_CAPACITY, HF_ERR_DEVICE, HF_ERR_INPUT = 4, 5, 6, 7
 HF_F32, HF_F64 = 0, 1
-KERNELS = {"sampled": 0, "analytic": 1}
+KERNELS = {"sampled": 0, "analytic": 1, "stencil": 2}
 STAGE_DEPOSIT, STAGE_CWT, STAGE_MAXIMA, STAGE_SEGMENT, STAGE_LABEL = 1, 2, 4, 8, 16
 
 EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_size",

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import CWT_RTOL, O, cuda, cwt_error, ensure_built, small_box
+from gpu_helpers import CWT_RTOL, LABEL_AGREEMENT, O, cuda, cwt_error, ensure_built, small_box, tie_free
 
 pytestmark = pytest.mark.gpu
 
@@ -128,3 +128,43 @@ def test_full_size_sampled_cells():
     want = O.stencil_cwt_at(rho_h, L, kw, h, cells)
     peak = np.abs(want[:64]).max()
     assert np.max(np.abs(got - want)) <= CWT_RTOL * peak
+
+
+def test_stencil_kernel_in_the_transform_and_the_pipeline():
+    # HF_KERNEL_STENCIL: hf_cwt and hf_find_halos take the paper's truncated
+    # stencil with Table 1's half-width (k_w = 0.25: h = 11)
+    n, L, kw = 32, 40.0, 0.25
+    pos = small_box(n, L, 40000, 60, "f32", 65)
+    rho = hfm().deposit(cuda(pos), L, n)
+    a = hfm().cwt(rho, L, kw, "stencil")
+    b = hfm().cwt_stencil(rho, L, kw, 11)
+    out = hfm().find_halos(cuda(pos), L, n, kw, kernel="stencil")
+    hfm().sync()
+    assert torch.equal(a, b) and torch.equal(out["cwt"], b)
+    ref = O.find_halos(pos, L, n, kw, mode="stencil")
+    c32 = out["cwt"].cpu().numpy()
+    assert cwt_error(c32, ref["cwt"]) <= CWT_RTOL
+    eps = float(np.max(np.abs(c32.astype(np.float64) - ref["cwt"])))
+    got = out["particle_label"].cpu().numpy()
+    if tie_free(ref["cwt"], eps):
+        np.testing.assert_array_equal(out["maxima"].cpu().numpy(), ref["maxima"])
+        np.testing.assert_array_equal(got, ref["particle_label"])
+    else:
+        assert float(np.mean(got == ref["particle_label"])) >= LABEL_AGREEMENT
+
+
+def test_stencil_kernel_limits():
+    from paper_2501_10622_amd.hf import HF_ERR_ARG, HFError
+    n, L = 16, 16.0
+    rho = torch.ones((n, n, n), dtype=torch.int64, device="cuda")
+    # k_w = 0.02: Int(75 + 5) = 80 > the widest stencil
+    with pytest.raises(HFError) as e:
+        hfm().cwt(rho, L, 0.02, "stencil")
+    assert e.value.code == HF_ERR_ARG
+    # the calls that share FFT passes take no stencil
+    with pytest.raises(HFError) as e:
+        hfm().cwt_scales(rho, L, [0.3, 0.6], "stencil")
+    assert e.value.code == HF_ERR_ARG
+    with pytest.raises(HFError) as e:
+        hfm().cwt_batch([rho, rho], [L, L], [0.3, 0.3], "stencil")
+    assert e.value.code == HF_ERR_ARG

@@ -143,3 +143,10 @@ def test_pointwise_windows_equal_the_superposition(n, h):
     cells = np.arange(n ** 3)
     np.testing.assert_allclose(O.stencil_cwt_at(rho, box_len, kw, h, cells), full.ravel(), rtol=1e-12,
                                atol=1e-12 * np.abs(full).max())
+
+
+def test_cwt_stencil_mode_is_the_stencil_with_table1_half_width():
+    rng = np.random.default_rng(11)
+    n, box_len, kw = 12, 20.0, 0.6  # gdw_resolution(0.6) = 7
+    rho = rng.integers(0, 1 << 40, size=(n, n, n))
+    np.testing.assert_array_equal(O.cwt(rho, box_len, kw, "stencil"), O.stencil_cwt(rho, box_len, kw, 7))
