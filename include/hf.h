@@ -128,7 +128,8 @@ hf_status hf_deposit(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype d
  *  and K the kernel selected by `kernel` (dx^3 Psi sampled, or the analytic
  *  transform), computed as a real 3D FFT, a multiply and an inverse FFT in FP32.
  *  The mean is formed from the exact integer total in FP64.  Negative or
- *  all-zero rho -> HF_ERR_INPUT.  Workspace: HF_STAGE_CWT. */
+ *  all-zero rho -> HF_ERR_INPUT.  Workspace: HF_STAGE_CWT (HF_STAGE_STENCIL
+ *  with HF_KERNEL_STENCIL). */
 hf_status hf_cwt(hf_ctx *ctx, const hf_box *box, const int64_t *rho, double kw, hf_kernel kernel,
                  float *cwt, void *ws, size_t ws_bytes);
 
@@ -266,7 +267,8 @@ hf_status hf_cwt_batch(hf_ctx *ctx, int32_t n, int32_t count, const hf_cwt_item 
 /* Steps 2-6 for one box in a single call (no host synchronisation inside):
  * hf_deposit, hf_cwt, hf_maxima, hf_segment and hf_label in order on the
  * context's stream, all sharing one workspace of
- * hf_workspace_size(box, np, HF_STAGE_ALL) bytes.  Where the deposit bins the
+ * hf_workspace_size(box, np, HF_STAGE_ALL) bytes (| HF_STAGE_STENCIL with
+ * HF_KERNEL_STENCIL).  Where the deposit bins the
  * particles (n a multiple of 16 with more than 512 tiles of 16-64 x 8 x 8
  * cells, frac_bits <= 17, np < 2^32) the binned order is kept and step 6 runs
  * through it: records are labelled tile by tile and the labels brought back
@@ -298,7 +300,8 @@ hf_status hf_find_halos(hf_ctx *ctx, const hf_box *box, const hf_job *job, void 
  * With the binned deposit each label's particles are counted in the deposit's
  * tile order and the filter is applied on the way back to input order.
  * job->np must be below 2^32.  Workspace:
- * hf_workspace_size(box, np, HF_STAGE_ALL | HF_STAGE_GROUPS). */
+ * hf_workspace_size(box, np, HF_STAGE_ALL | HF_STAGE_GROUPS) (| HF_STAGE_STENCIL
+ * with HF_KERNEL_STENCIL). */
 typedef struct {
     double dens_th;            /* Table 1: 4 */
     int64_t particle_th;       /* Table 1: 15 */

@@ -925,12 +925,7 @@ bool fill_job(CwtJobs &J, int j, const int64_t *rho, float *cwt, double box_len,
 
 }  // namespace
 
-// HF_STAGE_CWT covers either transform: the FFT's spectrum and tables or the
-// real-space stencil's three grids.
-size_t hf::cwt_ws_bytes(const hf_box &box) {
-    const size_t f = cwt_layout(box.n).total, st = stencil_ws_bytes(box);
-    return f > st ? f : st;
-}
+size_t hf::cwt_ws_bytes(const hf_box &box) { return cwt_layout(box.n).total; }
 
 extern "C" hf_status hf_cwt(hf_ctx *ctx, const hf_box *box, const int64_t *rho, double kw, hf_kernel kernel,
                             float *cwt, void *ws, size_t ws_bytes) {

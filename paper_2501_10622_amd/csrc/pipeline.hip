@@ -8,7 +8,8 @@ extern "C" hf_status hf_find_halos(hf_ctx *ctx, const hf_box *box, const hf_job 
     hf_status s = check_box(box);
     if (s != HF_OK) return s;
     size_t need = 0;
-    s = hf_workspace_size(box, job->np, HF_STAGE_ALL, &need);
+    s = hf_workspace_size(box, job->np, HF_STAGE_ALL | (job->kernel == HF_KERNEL_STENCIL ? HF_STAGE_STENCIL : 0),
+                          &need);
     if (s != HF_OK) return s;
     s = check_ws(ws, ws_bytes, need);
     if (s != HF_OK) return s;
@@ -60,7 +61,9 @@ extern "C" hf_status hf_find_halos_filtered(hf_ctx *ctx, const hf_box *box, cons
     if (job->max_cap > 0 && (!gf->group_particles || !gf->group_cells || !gf->group_keep)) return HF_ERR_ARG;
     if (job->max_cap > ncells) return HF_ERR_ARG;
     size_t need = 0;
-    s = hf_workspace_size(box, job->np, HF_STAGE_ALL | HF_STAGE_GROUPS, &need);
+    s = hf_workspace_size(box, job->np,
+                          HF_STAGE_ALL | HF_STAGE_GROUPS | (job->kernel == HF_KERNEL_STENCIL ? HF_STAGE_STENCIL : 0),
+                          &need);
     if (s != HF_OK) return s;
     s = check_ws(ws, ws_bytes, need);
     if (s != HF_OK) return s;

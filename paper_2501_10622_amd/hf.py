@@ -285,7 +285,7 @@ def cwt(rho: torch.Tensor, box_len: float, kw: float, kernel: str = "sampled", o
     if out is None:
         out = torch.empty((n, n, n), dtype=torch.float32, device=rho.device)
     b = box(n, box_len, frac_bits)
-    need = workspace_size(n, box_len, 0, STAGE_CWT, frac_bits)
+    need = workspace_size(n, box_len, 0, STAGE_STENCIL if kernel == "stencil" else STAGE_CWT, frac_bits)
     ws = workspace(need, rho.device.index)
     _check(load_library().hf_cwt(ctx.handle, ctypes.byref(b), _ptr(rho), float(kw), KERNELS[kernel], _ptr(out),
                                  _ptr(ws), need), "hf_cwt")
@@ -506,12 +506,15 @@ def cwt_scales(rho: torch.Tensor, box_len: float, kws, kernel: str = "sampled", 
 
 
 def job_buffers(n: int, np_: int, device, with_cwt_ws: bool = True, frac_bits: int = 15,
-                with_groups: bool = False) -> dict:
+                with_groups: bool = False, with_stencil: bool = False) -> dict:
     """Output and workspace tensors for one box (allocated on the current stream);
-    with_groups adds the group outputs and workspace of find_halos_filtered_async."""
+    with_groups adds the group outputs and workspace of find_halos_filtered_async,
+    with_stencil the workspace of the "stencil" transform."""
     stages = STAGE_ALL if with_cwt_ws else (STAGE_DEPOSIT | STAGE_MAXIMA | STAGE_SEGMENT)
     if with_groups:
         stages |= STAGE_GROUPS
+    if with_stencil:
+        stages |= STAGE_STENCIL
     need = workspace_size(n, 1.0, np_, stages, frac_bits)
     cap = ((n + 1) // 2) ** 3
     extra = {}
@@ -678,7 +681,7 @@ def find_halos(pos: torch.Tensor, box_len: float, n: int, kw: float, frac_bits: 
                kernel: str = "sampled") -> dict:
     """Steps 2-6 at one scale, all on the GPU through one native call; one sync at the end."""
     ctx = context(pos.device.index)
-    bufs = job_buffers(n, pos.shape[0], pos.device, True, frac_bits)
+    bufs = job_buffers(n, pos.shape[0], pos.device, True, frac_bits, with_stencil=kernel == "stencil")
     find_halos_async(pos, box_len, n, kw, bufs, frac_bits, tau, kernel, ctx)
     ctx.sync()
     cnt = int(bufs["count"].item())
