@@ -168,3 +168,26 @@ def test_stencil_kernel_limits():
     with pytest.raises(HFError) as e:
         hfm().cwt_batch([rho, rho], [L, L], [0.3, 0.3], "stencil")
     assert e.value.code == HF_ERR_ARG
+
+
+def test_stencil_kernel_in_the_filtered_pipeline():
+    # the fused group filter on the stencil transform equals the plain step
+    # with the same transform followed by hf_groups (tile-order path at 192^3)
+    from paper_2501_10622_amd import hf
+    n, L, kw = 192, 187.5, 0.3  # h = 10
+    pos = cuda(small_box(n, L, 2_000_000, 7910, "f32", 66))
+    np_ = pos.shape[0]
+    ctx = hf.context(0)
+    fb = hf.job_buffers(n, np_, pos.device, True, with_groups=True, with_stencil=True)
+    hf.find_halos_filtered_async(pos, L, n, kw, fb, 2.0, 15, kernel="stencil", ctx=ctx)
+    pb = hf.job_buffers(n, np_, pos.device, True, with_stencil=True)
+    hf.find_halos_async(pos, L, n, kw, pb, kernel="stencil", ctx=ctx)
+    ctx.sync()
+    cnt = int(pb["count"].item())
+    assert cnt == int(fb["count"].item()) and torch.equal(pb["cwt"], fb["cwt"])
+    alone = hf.groups(pb["cell_label"], pb["particle_label"][:np_], pb["maxima"][:cnt], np_, 2.0, 15, ctx=ctx)
+    ctx.sync()
+    assert torch.equal(alone["keep"], fb["group_keep"][:cnt])
+    assert torch.equal(alone["particles"], fb["group_particles"][:cnt])
+    assert torch.equal(alone["particle_label"], fb["particle_label"][:np_])
+    assert 0 < int(alone["keep"].sum()) < cnt
