@@ -37,7 +37,7 @@ __all__ = [
     "wavelet", "wavelet_hat", "sampled_kernel", "kernel_hat", "cwt_field", "cwt",
     "gdw_resolution", "stencil", "stencil_cwt_field", "stencil_cwt", "stencil_cwt_at",
     "neighbour_offsets", "maxima", "parents", "segment", "ngp_nodes", "label",
-    "find_halos", "group_stats", "cross_scale", "peaks", "identify", "DepositOverflow",
+    "find_halos", "group_stats", "cross_scale", "peaks", "cube_size_term", "identify", "DepositOverflow",
 ]
 
 
@@ -343,28 +343,28 @@ def maxima(c: np.ndarray, tau: float = 0.0) -> np.ndarray:
 # --------------------------------------------------------------------------
 # step 5: segmentation
 # --------------------------------------------------------------------------
-def peaks(c: np.ndarray, roots, box_len: float):
-    """Step 4's correction of grid maxima for the finite grid (App. B): per
-    axis, a quadratic through the maximum B and its two neighbours, A the
-    larger and C the smaller one.  With l1 = A - C and l2 = B - C the
-    quadratic's top lies l1^2 / (16 l2 - 8 l1) above B and, solving for its
-    vertex, l1 / (2 (2 l2 - l1)) cells from B towards A.  The three axes'
-    corrections are added to B's value and their shifts to B's position.
+def _peak_fits(c: np.ndarray, roots):
+    """Step 4's per-axis quadratic through each grid maximum (App. B), FP64.
 
-    Reading: a flat axis (l2 = 0, so A = B = C) contributes nothing; the
-    comparison of maxima between grids of different spacing (the rest of
-    App. B) is not made, since every scale of a box uses one grid.  FP64.
-    Returns positions [k][3] (x, y, z) in box units, wrapped into [0, L), and
-    the corrected values [k].
+    For the maximum B and its two neighbours along an axis, A the larger and
+    C the smaller one, take l1 = A - C and l2 = B - C (App. B puts A, B, C at
+    heights l1, l2, 0, one cell apart).  The parabola through the three points
+    tops out l1^2 / (16 l2 - 8 l1) above B, and its vertex lies
+    l1 / (2 (2 l2 - l1)) cells from B towards A.  A flat axis (l2 = 0, hence
+    A = B = C) contributes nothing.
+
+    Returns the shift of every root in cells [k][3] (x, y, z), the grid value
+    plus the three axes' corrections added in the order x, y, z [k], and the
+    means of l1 and of l2 over the three axes [k] (used by the cube-size term).
     """
     c = _check_field(c).astype(np.float64)
     n = c.shape[0]
-    dx = box_len / n
     roots = np.asarray(roots, dtype=np.int64).ravel()
     z, y, x = roots // (n * n), (roots // n) % n, roots % n
     centre = c[z, y, x]
     value = centre.copy()
-    pos = np.stack([x, y, z], axis=1).astype(np.float64)
+    shift = np.zeros((roots.size, 3), dtype=np.float64)
+    l1s, l2s = [], []
     for ax, (ex, ey, ez) in enumerate(((1, 0, 0), (0, 1, 0), (0, 0, 1))):
         up = c[(z + ez) % n, (y + ey) % n, (x + ex) % n]
         down = c[(z - ez) % n, (y - ey) % n, (x - ex) % n]
@@ -375,10 +375,48 @@ def peaks(c: np.ndarray, roots, box_len: float):
         den = np.where(flat, 1.0, 16.0 * l2 - 8.0 * l1)
         corr = np.where(flat, 0.0, l1 * l1 / den)
         toward = np.where(up >= down, 1.0, -1.0)
-        shift = np.where(flat, 0.0, toward * l1 / np.where(flat, 1.0, 2.0 * (2.0 * l2 - l1)))
+        shift[:, ax] = np.where(flat, 0.0, toward * l1 / np.where(flat, 1.0, 2.0 * (2.0 * l2 - l1)))
         value = value + corr
-        pos[:, ax] = pos[:, ax] + shift
+        l1s.append(l1)
+        l2s.append(l2)
+    l1bar = (l1s[0] + l1s[1] + l1s[2]) / 3.0
+    l2bar = (l2s[0] + l2s[1] + l2s[2]) / 3.0
+    return shift, value, l1bar, l2bar
+
+
+def peaks(c: np.ndarray, roots, box_len: float):
+    """Step 4's correction of grid maxima for the finite grid (App. B, first
+    part): each maximum moves to the vertex of its per-axis quadratics and its
+    value rises by their corrections (``_peak_fits``).
+
+    Returns positions [k][3] (x, y, z) in box units, wrapped into [0, L), and
+    the corrected values [k].
+    """
+    c = _check_field(c)
+    n = c.shape[0]
+    dx = box_len / n
+    roots = np.asarray(roots, dtype=np.int64).ravel()
+    z, y, x = roots // (n * n), (roots // n) % n, roots % n
+    shift, value, _, _ = _peak_fits(c, roots)
+    pos = np.stack([x, y, z], axis=1).astype(np.float64) + shift
     return np.mod(pos * dx, box_len), value
+
+
+def cube_size_term(l1bar, l2bar, n_scale: int, n_smaller: int):
+    """App. B's second correction, made to a maximum of the larger scale before
+    it is compared with a smaller scale on a finer grid: the grid value of a
+    peak is the average over its cube, and the average over the smaller cube of
+    the finer grid is higher.  With the peak taken as the average of the three
+    per-axis quadratics, the difference is (3/16)(2 l2bar - l1bar)
+    [1 - (r1/r2)^2], r2 and r1 the two grid spacings; the paper removes the
+    factor 3/5 from it, leaving (5/16)(2 l2bar - l1bar)[1 - (r1/r2)^2].
+
+    r1 / r2 = (L / n_smaller) / (L / n_scale) = n_scale / n_smaller, so the
+    term vanishes when both scales share one grid.  Evaluated in FP64 as
+    (0.3125 (2 l2bar - l1bar)) (1 - r r) with r = n_scale / n_smaller.
+    """
+    r = float(n_scale) / float(n_smaller)
+    return (0.3125 * (2.0 * np.asarray(l2bar) - np.asarray(l1bar))) * (1.0 - r * r)
 
 
 def parents(c: np.ndarray) -> np.ndarray:
@@ -492,28 +530,41 @@ def group_stats(cell_label, particle_label, roots, n: int, np_total: int, dens_t
 # step 8: cross-scale maxima
 # --------------------------------------------------------------------------
 def cross_scale(c_scale: np.ndarray, c_smaller: np.ndarray, roots) -> np.ndarray:
-    """Which maxima of one scale are also maxima across scale (step 8 and the
-    comparison of the two grids described with the flowchart in Sec. 2).
+    """Which maxima of one scale are also maxima across scale (step 8, with
+    the comparison of the flowchart's two grids described in Sec. 2).
 
-    A local maximum of the grid CWT at one scale is kept if its value exceeds
-    the values of all grid points near the same position in the CWT of the
-    adjacent smaller scale.  Reading: both fields are on the same n^3 grid (one
-    grid for every scale of a box), "near" is the maximum's cell and its 26
-    periodic neighbours, and "exceeds" is strict.  The paper corrects grid
-    maxima for the cube size before comparing across grids of different
-    spacing (App. B); with one spacing there is no such correction.
+    Each maximum is first corrected for the grid (step 4, App. B): its value
+    becomes the top of its per-axis quadratics plus the cube-size term for the
+    smaller scale's grid spacing, and its position the vertex of those
+    quadratics.  It is kept if that value strictly exceeds the smaller scale's
+    CWT at every grid point near the same physical position.
 
-    Returns one flag per root of ``roots`` (linear cell indices).
+    Readings: "near" is the smaller scale's grid node nearest the corrected
+    position (half a cell rounds up) and its 26 periodic neighbours; the
+    smaller scale's values are its raw grid values (App. B adjusts the larger
+    scale's maxima only).  The two fields may be on grids of different size
+    n_scale and n_smaller over the same box; on one grid the cube-size term is
+    zero.  The position in the smaller grid's cells is
+    ((g + shift) n_smaller) / n_scale, FP64 throughout.
+
+    Returns one flag per root of ``roots`` (linear cell indices of c_scale).
     """
     cs = _check_field(c_scale)
-    cm = _check_field(c_smaller)
-    if cs.shape != cm.shape:
-        raise ValueError("both scales must be on the same grid")
-    near = cm.copy()
-    for off in neighbour_offsets():
-        near = np.maximum(near, np.roll(cm, tuple(-o for o in off), axis=(0, 1, 2)))
+    cm = _check_field(c_smaller).astype(np.float64)
+    n2, n1 = cs.shape[0], cm.shape[0]
     roots = np.asarray(roots, dtype=np.int64).ravel()
-    return cs.ravel()[roots] > near.ravel()[roots]
+    shift, value, l1bar, l2bar = _peak_fits(cs, roots)
+    value = value + cube_size_term(l1bar, l2bar, n2, n1)
+    g = np.stack([roots % n2, (roots // n2) % n2, roots // (n2 * n2)], axis=1).astype(np.float64)
+    u = ((g + shift) * float(n1)) / float(n2)
+    node = np.mod(np.floor(u + 0.5).astype(np.int64), n1)  # (x, y, z) on the smaller grid
+    near = np.full(roots.size, -np.inf)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                v = cm[(node[:, 2] + dz) % n1, (node[:, 1] + dy) % n1, (node[:, 0] + dx) % n1]
+                near = np.maximum(near, v)
+    return value > near
 
 
 # --------------------------------------------------------------------------
@@ -529,8 +580,9 @@ def identify(pos, box_len: float, n: int, kws, dens_th: float = 4.0, particle_th
     particles that no earlier scale has claimed take their cell's label (a
     temporary ID); groups are formed from those particles and a group is
     discarded unless it passes the density and particle-number thresholds
-    (step 7) and its maximum exceeds the next scale's field near it (step 8;
-    after the last scale the next grid is all zeros).  The particles of a kept
+    (step 7) and its maximum, corrected for the grid as step 4 asks (App. B),
+    exceeds the next scale's field near its corrected position (step 8; after
+    the last scale the next grid is all zeros).  The particles of a kept
     group are claimed at this scale with the group's root as their ID.
     Reading: every scale is on the box's one n^3 grid (the paper re-grids
     each scale, N_g = Int(400 k_w + 150)), and the density of a group counts

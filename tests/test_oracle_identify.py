@@ -32,7 +32,8 @@ def test_one_scale_is_the_single_scale_path_and_filters():
     r = O.identify(pos, L, n, [kw], 2.0, 15)
     s = O.find_halos(pos, L, n, kw)
     c = s["cwt"]
-    ok = c.ravel()[s["maxima"]] > 0.0
+    _, val = O.peaks(c, s["maxima"], L)  # against the zero grid: the corrected value must be positive
+    ok = val > 0.0
     g = O.group_stats(s["cell_label"], s["particle_label"], s["maxima"], n, len(pos), 2.0, 15, root_ok=ok)
     assert (r["scales"][0]["keep"] == g["keep"]).all()
     assert (r["halo_root"] == g["particle_label"]).all()
@@ -62,13 +63,15 @@ def test_bookkeeping_by_brute_force(seed, dens_th, pth):
             if claimed[p] < 0 and raw[p] >= 0:
                 parts[raw[p]] = parts.get(raw[p], 0) + 1
         nxt = fields[i + 1] if i + 1 < len(kws) else np.zeros_like(fields[i])
+        # step 4's corrected value and position of each maximum (one grid: no cube-size term)
+        ppos, pval = O.peaks(fields[i], roots, L) if roots else (np.zeros((0, 3)), np.zeros(0))
         keep = {}
         for k, rt in enumerate(roots):
-            z, y, x = rt // (n * n), (rt // n) % n, rt % n
+            x, y, z = (int(math.floor(ppos[k][a] / (L / n) + 0.5)) % n for a in range(3))
             near = max(nxt[(z + a) % n, (y + b) % n, (x + c) % n]
                        for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1))
             p_, c_ = parts.get(rt, 0), cells.get(rt, 0)
-            keep[rt] = (fields[i].ravel()[rt] > near and p_ * n ** 3 >= dens_th * c_ * npt and p_ >= pth)
+            keep[rt] = (pval[k] > near and p_ * n ** 3 >= dens_th * c_ * npt and p_ >= pth)
             assert sc["particles"][k] == p_ and sc["cells"][k] == c_
             assert bool(sc["keep"][k]) == keep[rt]
         for p in range(npt):
