@@ -603,7 +603,7 @@ def stencil_bench(rho, c_fft, box_len: float, n: int, kw: float, warmup: int, it
     import torch
     import paper_2501_10622_amd as hfm
     from paper_2501_10622_amd import hf
-    h = hfm.gdw_resolution(kw)
+    h = hfm.stencil_half_width(kw, n)
     out = torch.empty_like(c_fft)
     ws = torch.empty(hf.workspace_size(n, box_len, 0, hf.STAGE_STENCIL), dtype=torch.uint8, device=rho.device)
     for _ in range(warmup):

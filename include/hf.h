@@ -69,9 +69,13 @@ typedef enum { HF_F32 = 0, HF_F64 = 1 } hf_dtype;
  *            Sec. 2.1), applied through its exact DFT.
  *  ANALYTIC: the continuum Fourier transform of Eq. (4),
  *            32 pi^1.5 w^-1.5 (k/w)^2 exp(-(k/w)^2), at the DFT wavenumbers.
- *  STENCIL:  the sampled wavelet truncated to the cube of half-width
- *            Int(1.5/k_w + 5) (Table 1's gdw_resolution), no images, applied
- *            in real space as hf_cwt_stencil does.  Taken by hf_cwt,
+ *  STENCIL:  the sampled wavelet truncated to a cube of half-width
+ *            ceil(Int(1.5/k_w + 5) n / Int(400 k_w + 150)) cells: Table 1's
+ *            gdw_resolution counts cells of the flowchart's grid for the
+ *            scale, N_g = Int(400 k_w + 150), where it spans 10-12 scale
+ *            lengths, and the same physical extent is kept on the n^3 grid
+ *            (the count itself when n = N_g).  No images; applied in real
+ *            space as hf_cwt_stencil does.  Taken by hf_cwt,
  *            hf_find_halos and hf_find_halos_filtered (half-widths up to
  *            HF_STENCIL_MAX_HALF_WIDTH, else HF_ERR_ARG); the batched and
  *            multi-scale calls, which share FFT passes, return HF_ERR_ARG. */
@@ -137,7 +141,9 @@ hf_status hf_cwt(hf_ctx *ctx, const hf_box *box, const int64_t *rho, double kw, 
  * every grid point adds its mass times the wavelet of Eq. (4), sampled at the
  * grid spacing on the cube of node offsets |d_i| <= half_width around it
  * (periodic; no wavelet images).  Table 1's gdw_resolution, Int(1.5/k_w + 5),
- * is the paper's half_width; a stencil wider than the box wraps onto itself.
+ * is the paper's half_width on its grid N_g = Int(400 k_w + 150); HF_KERNEL_STENCIL
+ * keeps that extent on other grids.  A stencil wider than the box wraps onto
+ * itself.
  *  rho [n][n][n] int64 (>= 0, not all zero); cwt [n][n][n] FP32 (overwritten).
  *  C_j = sum_{|d_i| <= h} S_d f_{j-d}, f = rho / mean(rho) as in hf_cwt and
  *  S_d = dx^3 Psi(w, |d| dx).  Computed in FP32 as seven one-dimensional
@@ -147,6 +153,12 @@ hf_status hf_cwt(hf_ctx *ctx, const hf_box *box, const int64_t *rho, double kw, 
  *  each other or the workspace.  Negative or all-zero rho -> HF_ERR_INPUT.
  *  Workspace: HF_STAGE_STENCIL (three FP32 grids). */
 #define HF_STENCIL_MAX_HALF_WIDTH 64
+/* The half-width HF_KERNEL_STENCIL takes on an n^3 grid at scale kw (Table 1's
+ * gdw_resolution kept at its extent on the flowchart's grid N_g, see
+ * hf_kernel): ceil(Int(1.5/k_w + 5) n / Int(400 k_w + 150)).  Host only, no
+ * context.  HF_ERR_ARG for a null out pointer, kw not finite and positive, n
+ * outside [1, 1024], or a result above HF_STENCIL_MAX_HALF_WIDTH. */
+hf_status hf_stencil_half_width(double kw, int32_t n, int32_t *half_width);
 hf_status hf_cwt_stencil(hf_ctx *ctx, const hf_box *box, const int64_t *rho, double kw, int32_t half_width,
                          float *cwt, void *ws, size_t ws_bytes);
 
@@ -224,17 +236,23 @@ hf_status hf_groups(hf_ctx *ctx, const hf_box *box, int64_t np, const int32_t *r
 hf_status hf_peaks(hf_ctx *ctx, const hf_box *box, const float *cwt, const int32_t *roots, int64_t nroots,
                    double *pos, double *value);
 
-/* Step 8: cross-scale maxima.  pass[i] = 1 iff cwt_scale[roots[i]] exceeds
- * (strictly) cwt_smaller at the root's cell and its 26 periodic neighbours,
- * where cwt_smaller is the CWT of the same box at the adjacent smaller scale
- * on the same n^3 grid (the comparison of the two grids described with the
- * flowchart of Sec. 2; with one grid spacing no cube-size correction, App. B,
- * applies).  roots [nroots] (device, e.g. hf_maxima's list at this scale),
- * pass [nroots] (device).  A NaN in either field or a root outside [0, n^3)
- * sets HF_ERR_INPUT.  The flags can go to hf_groups as root_ok (groups
- * without a cross-scale maximum are disposed of).  No workspace. */
+/* Step 8: cross-scale maxima, each maximum first corrected for the grid as
+ * step 4 asks (App. B).  For maximum roots[i] of cwt_scale (n^3, the box's
+ * grid): its value becomes the top of its per-axis quadratics (as hf_peaks)
+ * plus App. B's cube-size term for the smaller scale's grid with the paper's
+ * 3/5 factor removed, (5/16)(2 l2bar - l1bar)(1 - (n / n_smaller)^2), l1bar and
+ * l2bar the means of l1 and l2 over the three axes (zero when
+ * n_smaller == n).  pass[i] = 1 iff that value (FP64) strictly exceeds
+ * cwt_smaller (n_smaller^3 FP32 over the same box: the CWT at the adjacent
+ * smaller scale, the flowchart's current grid) at the node of that grid
+ * nearest the corrected position, ((g + shift) n_smaller) / n in its cells
+ * with half a cell rounding up, and at that node's 26 periodic neighbours.
+ * roots [nroots] (device, e.g. hf_maxima's list at this scale), pass [nroots]
+ * (device).  n_smaller in [1, 1024].  A NaN in either field or a root outside
+ * [0, n^3) sets HF_ERR_INPUT.  The flags can go to hf_groups as root_ok
+ * (groups without a cross-scale maximum are disposed of).  No workspace. */
 hf_status hf_cross_scale(hf_ctx *ctx, const hf_box *box, const int32_t *roots, int64_t nroots,
-                         const float *cwt_scale, const float *cwt_smaller, uint8_t *pass);
+                         const float *cwt_scale, int32_t n_smaller, const float *cwt_smaller, uint8_t *pass);
 
 /* Batched step 3 for serving: `count` (1..HF_CWT_BATCH_MAX) transforms of the
  * same grid size n, each with its own box length and scale, enqueued as one

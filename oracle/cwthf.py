@@ -35,7 +35,7 @@ import numpy as np
 __all__ = [
     "scale_w", "fixed_point", "deposit", "total_mass", "mean_mass", "normalise",
     "wavelet", "wavelet_hat", "sampled_kernel", "kernel_hat", "cwt_field", "cwt",
-    "gdw_resolution", "stencil", "stencil_cwt_field", "stencil_cwt", "stencil_cwt_at",
+    "gdw_resolution", "paper_grid", "stencil_half_width", "stencil", "stencil_cwt_field", "stencil_cwt", "stencil_cwt_at",
     "neighbour_offsets", "maxima", "parents", "segment", "ngp_nodes", "label",
     "find_halos", "group_stats", "cross_scale", "peaks", "cube_size_term", "identify", "DepositOverflow",
 ]
@@ -214,7 +214,7 @@ def cwt_field(f: np.ndarray, box_len: float, w: float, mode: str = "sampled") ->
 def cwt(rho: np.ndarray, box_len: float, kw: float, mode: str = "sampled") -> np.ndarray:
     """Step 3 on a CIC grid: normalise to the mean density, then Eq. (2).
     ``stencil`` is the truncated real-space stencil of Sec. 2.1 with Table 1's
-    half-width (``stencil_cwt``)."""
+    extent (``stencil_cwt``)."""
     if mode == "stencil":
         return stencil_cwt(rho, box_len, kw)
     return cwt_field(normalise(rho), box_len, scale_w(kw, box_len), mode)
@@ -226,10 +226,29 @@ def cwt(rho: np.ndarray, box_len: float, kw: float, mode: str = "sampled") -> np
 def gdw_resolution(kw: float) -> int:
     """Table 1's wavelet grid resolution Int(1.5 / k_w + 5).
 
-    Read as the stencil's half-width in cells: offsets -h..h on every axis,
-    2h + 1 points per axis (the paper does not say whether the count is the
-    half or the full width)."""
+    Read as the stencil's half-width in cells of the paper's grid for that
+    scale: offsets -h..h on every axis, 2h + 1 points per axis (the paper does
+    not say whether the count is the half or the full width)."""
     return int(1.5 / kw + 5.0)
+
+
+def paper_grid(kw: float) -> int:
+    """The flowchart's grid size for a scale, N_g = Int(400 k_w + 150)."""
+    return int(400.0 * kw + 150.0)
+
+
+def stencil_half_width(kw: float, n: int) -> int:
+    """Half-width in cells of an n^3 grid covering the physical extent of
+    Table 1's count on the paper's own grid: ceil(gdw_resolution(k_w) n / N_g).
+
+    Reading: the flowchart deposits each scale on N_g = Int(400 k_w + 150)
+    cells, where the scale length is 0.4 + 0.15 / k_w cells and Table 1's
+    count spans 10-12 scale lengths, far enough that the truncated Mexican hat
+    keeps its zero mean.  On another grid the same count of cells would cover
+    a different extent (3.5 scale lengths at n = 1024, k_w = 0.512), so the
+    extent is kept instead; on the paper's grid this is the count itself."""
+    c, ng = gdw_resolution(kw), paper_grid(kw)
+    return (c * int(n) + ng - 1) // ng
 
 
 def stencil(n: int, box_len: float, w: float, half_width: int) -> np.ndarray:
@@ -290,8 +309,9 @@ def stencil_cwt_at(rho: np.ndarray, box_len: float, kw: float, half_width: int, 
 
 def stencil_cwt(rho: np.ndarray, box_len: float, kw: float, half_width: int | None = None) -> np.ndarray:
     """Step 3 with the truncated stencil: normalise to the mean density, then
-    superpose; the half-width defaults to Table 1's gdw_resolution(k_w)."""
-    h = gdw_resolution(kw) if half_width is None else int(half_width)
+    superpose; the half-width defaults to Table 1's extent on this grid
+    (``stencil_half_width``)."""
+    h = stencil_half_width(kw, np.asarray(rho).shape[0]) if half_width is None else int(half_width)
     if h < 0:
         raise ValueError("half_width must be >= 0")
     return stencil_cwt_field(normalise(rho), box_len, scale_w(kw, box_len), h)

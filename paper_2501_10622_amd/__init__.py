@@ -6,7 +6,7 @@ the group statistics and density filter that follow them.
 """
 from .hf import (  # noqa: F401
     CWT_BATCH_MAX, EXPORTS, HFError, LIB_PATH, Context, context, cross_scale, cwt, cwt_batch, cwt_batch_ws_bytes,
-    cwt_scales, cwt_stencil, deposit, gdw_resolution,
+    cwt_scales, cwt_stencil, deposit, stencil_half_width,
     find_halos, find_halos_async, find_halos_filtered_async, find_halos_group_async, find_halos_scales_async,
     groups, identify_async, identify_buffers, job_buffers, label, load_library, maxima, peaks, scales_buffers, segment, STENCIL_MAX_HALF_WIDTH,
     status_str, sync, workspace_size,

@@ -933,7 +933,8 @@ extern "C" hf_status hf_cwt(hf_ctx *ctx, const hf_box *box, const int64_t *rho, 
     if (kernel != HF_KERNEL_SAMPLED && kernel != HF_KERNEL_ANALYTIC && kernel != HF_KERNEL_STENCIL) return HF_ERR_ARG;
     if (!(kw > 0.0) || !std::isfinite(kw)) return HF_ERR_ARG;
     if (kernel == HF_KERNEL_STENCIL) {
-        const int32_t h = stencil_half_width(kw);  // Table 1's gdw_resolution
+        if (!box) return HF_ERR_ARG;
+        const int32_t h = stencil_half_width(kw, box->n);  // Table 1's extent on this grid
         if (h < 0) return HF_ERR_ARG;
         return hf_cwt_stencil(ctx, box, rho, kw, h, cwt, ws, ws_bytes);
     }

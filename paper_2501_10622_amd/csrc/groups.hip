@@ -233,38 +233,104 @@ __global__ void __launch_bounds__(GB) groups_filter_kernel(const int32_t *in, in
     if (bad) atomicOr(status, ST_INPUT);
 }
 
-// Step 8: maximum i of one scale is kept if its value exceeds the adjacent
-// smaller scale's field at its cell and the 26 periodic neighbours (both on
-// the same grid; strict).  c_smaller null stands for the all-zero grid (the
-// identification loop's last scale).  One thread per maximum; a NaN is reported.
+// Step 4's correction of one grid maximum (App. B), in FP64 on the FP32
+// field: per axis, with the maximum B and its neighbours A (larger) and C
+// (smaller), l1 = A - C and l2 = B - C, the quadratic through them peaks
+// l1^2 / (16 l2 - 8 l1) above B and l1 / (2 (2 l2 - l1)) cells towards A.  A
+// flat axis (l2 = 0) adds nothing.  The value takes the three corrections in
+// the order x, y, z; l1bar and l2bar are the means over the axes (for the
+// cube-size term).  Every operation is rounded as written (no contraction).
+struct PeakFit {
+    double shift[3];  // cells, (x, y, z)
+    double value;
+    double l1bar, l2bar;
+    bool nan;
+};
+
+__device__ PeakFit peak_fit(const float *__restrict__ c, uint32_t un, const uint32_t g[3], uint32_t r) {
+    PeakFit f;
+    const double b = double(c[r]);
+    f.nan = b != b;
+    f.value = b;
+    double l1s[3], l2s[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        uint32_t up[3] = {g[0], g[1], g[2]}, dn[3] = {g[0], g[1], g[2]};
+        up[ax] = (g[ax] + 1) % un;
+        dn[ax] = (g[ax] + un - 1) % un;
+        const double cu = double(c[(up[2] * un + up[1]) * un + up[0]]);
+        const double cd = double(c[(dn[2] * un + dn[1]) * un + dn[0]]);
+        f.nan |= (cu != cu) || (cd != cd);
+        const double a = cu > cd ? cu : cd, low = cu > cd ? cd : cu;
+        const double l1 = __dsub_rn(a, low), l2 = __dsub_rn(b, low);
+        double corr = 0.0, shift = 0.0;
+        if (l2 != 0.0) {
+            corr = __ddiv_rn(__dmul_rn(l1, l1), __dsub_rn(__dmul_rn(16.0, l2), __dmul_rn(8.0, l1)));
+            shift = __ddiv_rn(l1, __dmul_rn(2.0, __dsub_rn(__dmul_rn(2.0, l2), l1)));
+            if (!(cu >= cd)) shift = -shift;
+        }
+        f.value = __dadd_rn(f.value, corr);
+        f.shift[ax] = shift;
+        l1s[ax] = l1;
+        l2s[ax] = l2;
+    }
+    f.l1bar = __ddiv_rn(__dadd_rn(__dadd_rn(l1s[0], l1s[1]), l1s[2]), 3.0);
+    f.l2bar = __ddiv_rn(__dadd_rn(__dadd_rn(l2s[0], l2s[1]), l2s[2]), 3.0);
+    return f;
+}
+
+// Step 8: maximum i of one scale (field c_scale on an n2^3 grid) is kept if
+// its value, corrected for the grid (step 4, App. B), strictly exceeds the
+// adjacent smaller scale's field (n1^3 grid over the same box) at every grid
+// point near the same physical position.  The correction is the per-axis
+// quadratic top plus App. B's cube-size term with the 3/5 factor removed,
+// (5/16)(2 l2bar - l1bar)(1 - (n2/n1)^2), which vanishes on one grid.  "Near"
+// is the smaller grid's node nearest the corrected position (half a cell
+// rounds up), ((g + shift) n1) / n2 in its cells, and its 26 periodic
+// neighbours.  c_smaller null stands for the all-zero grid (the
+// identification loop's last scale).  One thread per maximum; a NaN is
+// reported.
 __global__ void __launch_bounds__(GB) cross_scale_kernel(const int32_t *__restrict__ roots, const int64_t *d_count,
-                                                         int64_t cap, int n, const float *__restrict__ c_scale,
-                                                         const float *__restrict__ c_smaller,
+                                                         int64_t cap, int n2, const float *__restrict__ c_scale,
+                                                         int n1, const float *__restrict__ c_smaller,
                                                          uint8_t *__restrict__ pass, uint32_t *status) {
     const int64_t nroots = root_count(d_count, cap);
     bool bad = false;
-    const uint32_t un = uint32_t(n), ncells = un * un * un;
+    const uint32_t un = uint32_t(n2), ncells = un * un * un, um = uint32_t(n1);
+    const double r = __ddiv_rn(double(n2), double(n1));
+    const double shrink = __dsub_rn(1.0, __dmul_rn(r, r));
     for (int64_t i = blockIdx.x * int64_t(GB) + threadIdx.x; i < nroots; i += int64_t(gridDim.x) * GB) {
-        const int32_t r = roots[i];
-        if (r < 0 || uint32_t(r) >= ncells) {
+        const int32_t root = roots[i];
+        if (root < 0 || uint32_t(root) >= ncells) {
             bad = true;
             pass[i] = 0;
             continue;
         }
-        const uint32_t x = uint32_t(r) % un, y = (uint32_t(r) / un) % un, z = uint32_t(r) / (un * un);
-        const float v = c_scale[r];
-        bool above = v == v;
-        bad |= !above;
+        const uint32_t g[3] = {uint32_t(root) % un, (uint32_t(root) / un) % un, uint32_t(root) / (un * un)};
+        const PeakFit f = peak_fit(c_scale, un, g, uint32_t(root));
+        bad |= f.nan;
+        const double term = __dmul_rn(__dmul_rn(0.3125, __dsub_rn(__dmul_rn(2.0, f.l2bar), f.l1bar)), shrink);
+        const double v = __dadd_rn(f.value, term);
+        uint32_t node[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const double u = __ddiv_rn(__dmul_rn(__dadd_rn(double(g[ax]), f.shift[ax]), double(n1)), double(n2));
+            int64_t k = int64_t(floor(__dadd_rn(u, 0.5))) % int64_t(n1);
+            if (k < 0) k += n1;
+            node[ax] = uint32_t(k);
+        }
+        bool above = !f.nan;
 #pragma unroll
         for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
             for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
                 for (int dx = -1; dx <= 1; ++dx) {
-                    const uint32_t gz = (z + un + dz) % un, gy = (y + un + dy) % un, gx = (x + un + dx) % un;
-                    const float u = c_smaller ? c_smaller[(gz * un + gy) * un + gx] : 0.0f;
+                    const uint32_t gz = (node[2] + um + dz) % um, gy = (node[1] + um + dy) % um,
+                                   gx = (node[0] + um + dx) % um;
+                    const float u = c_smaller ? c_smaller[(gz * um + gy) * um + gx] : 0.0f;
                     bad |= u != u;
-                    above = above && v > u;
+                    above = above && v > double(u);
                 }
         pass[i] = above ? 1 : 0;
     }
@@ -340,12 +406,8 @@ __global__ void __launch_bounds__(GB) claim_take_kernel(const int32_t *__restric
     }
 }
 
-// Step 4's correction of grid maxima (App. B), in FP64 on the FP32 field: per
-// axis, with the maximum B and its neighbours A (larger) and C (smaller),
-// l1 = A - C and l2 = B - C, the quadratic through them peaks
-// l1^2 / (16 l2 - 8 l1) above B and l1 / (2 (2 l2 - l1)) cells towards A.  A
-// flat axis (l2 = 0) adds nothing.  Products, quotients and differences are
-// rounded one at a time (no contraction), as written.
+// Step 4's correction of grid maxima (App. B): each maximum's corrected
+// position (wrapped into [0, L)) and value, from peak_fit.
 __global__ void __launch_bounds__(GB) peaks_kernel(const int32_t *__restrict__ roots, int64_t nroots, int n,
                                                    double dx, double box_len, const float *__restrict__ c,
                                                    double *__restrict__ pos, double *__restrict__ value,
@@ -359,32 +421,16 @@ __global__ void __launch_bounds__(GB) peaks_kernel(const int32_t *__restrict__ r
             continue;
         }
         const uint32_t g[3] = {uint32_t(r) % un, (uint32_t(r) / un) % un, uint32_t(r) / (un * un)};
-        const double b = double(c[r]);
-        bad |= b != b;
-        double v = b;
+        const PeakFit f = peak_fit(c, un, g, uint32_t(r));
+        bad |= f.nan;
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            uint32_t up[3] = {g[0], g[1], g[2]}, dn[3] = {g[0], g[1], g[2]};
-            up[ax] = (g[ax] + 1) % un;
-            dn[ax] = (g[ax] + un - 1) % un;
-            const double cu = double(c[(up[2] * un + up[1]) * un + up[0]]);
-            const double cd = double(c[(dn[2] * un + dn[1]) * un + dn[0]]);
-            bad |= (cu != cu) || (cd != cd);
-            const double a = cu > cd ? cu : cd, low = cu > cd ? cd : cu;
-            const double l1 = __dsub_rn(a, low), l2 = __dsub_rn(b, low);
-            double shift = 0.0;
-            if (l2 != 0.0) {
-                const double corr = __ddiv_rn(__dmul_rn(l1, l1), __dsub_rn(__dmul_rn(16.0, l2), __dmul_rn(8.0, l1)));
-                v = __dadd_rn(v, corr);
-                shift = __ddiv_rn(l1, __dmul_rn(2.0, __dsub_rn(__dmul_rn(2.0, l2), l1)));
-                if (!(cu >= cd)) shift = -shift;
-            }
-            double p = __dmul_rn(__dadd_rn(double(g[ax]), shift), dx);
+            double p = __dmul_rn(__dadd_rn(double(g[ax]), f.shift[ax]), dx);
             p = fmod(p, box_len);
             if (p < 0.0) p = __dadd_rn(p, box_len);
             pos[3 * i + ax] = p;
         }
-        value[i] = v;
+        value[i] = f.value;
     }
     if (bad) atomicOr(status, ST_INPUT);
 }
@@ -467,7 +513,7 @@ hf_status hf::cross_scale_dev(hf_ctx *ctx, const hf_box &box, const int32_t *roo
                               int64_t cap, const float *c_scale, const float *c_smaller, uint8_t *pass) {
     if (cap <= 0) return HF_OK;
     HF_LAUNCH(ctx, K_GROUP_CROSS, cross_scale_kernel, dim3(grid_of(ctx, cap, GB)), dim3(GB), 0, ctx->stream, roots,
-              d_count, cap, box.n, c_scale, c_smaller, pass, ctx->d_status);
+              d_count, cap, box.n, c_scale, box.n, c_smaller, pass, ctx->d_status);
     return launch_status();
 }
 
@@ -509,16 +555,18 @@ extern "C" hf_status hf_peaks(hf_ctx *ctx, const hf_box *box, const float *cwt, 
 }
 
 extern "C" hf_status hf_cross_scale(hf_ctx *ctx, const hf_box *box, const int32_t *roots, int64_t nroots,
-                                    const float *cwt_scale, const float *cwt_smaller, uint8_t *pass) {
+                                    const float *cwt_scale, int32_t n_smaller, const float *cwt_smaller,
+                                    uint8_t *pass) {
     if (!ctx) return HF_ERR_ARG;
     hf_status s = check_box(box);
     if (s != HF_OK) return s;
+    if (n_smaller < 1 || n_smaller > 1024) return HF_ERR_SIZE;
     if (nroots < 0 || nroots > cells_of(*box)) return HF_ERR_ARG;
     if (nroots == 0) return HF_OK;
     if (!roots || !cwt_scale || !cwt_smaller || !pass) return HF_ERR_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
     HF_LAUNCH(ctx, K_GROUP_CROSS, cross_scale_kernel, dim3(grid_of(ctx, nroots, GB)), dim3(GB), 0, ctx->stream, roots,
-              nullptr, nroots, box->n, cwt_scale, cwt_smaller, pass, ctx->d_status);
+              nullptr, nroots, box->n, cwt_scale, int(n_smaller), cwt_smaller, pass, ctx->d_status);
     return launch_status();
 }
 

@@ -214,11 +214,21 @@ hf_status claim_filter(hf_ctx *ctx, const hf_box &box, int32_t *label, int32_t *
 hf_status claim_take(hf_ctx *ctx, const int32_t *label, int32_t *halo_scale, int32_t *halo_root, int64_t np,
                      int32_t scale);
 size_t stencil_ws_bytes(const hf_box &box);
-// Table 1's stencil half-width Int(1.5/k_w + 5) for HF_KERNEL_STENCIL, or -1
-// when it exceeds HF_STENCIL_MAX_HALF_WIDTH.
-inline int32_t stencil_half_width(double kw) {
-    const double h = __builtin_floor(1.5 / kw + 5.0);
-    return h <= double(HF_STENCIL_MAX_HALF_WIDTH) ? int32_t(h) : -1;
+// The stencil half-width of HF_KERNEL_STENCIL on an n^3 grid: Table 1's
+// count Int(1.5/k_w + 5) is in cells of the flowchart's grid for the scale,
+// N_g = Int(400 k_w + 150), where it spans 10-12 scale lengths; on n cells the
+// same physical extent is ceil(count n / N_g) cells (the count itself when
+// n = N_g).  -1 when that exceeds HF_STENCIL_MAX_HALF_WIDTH.  Each FP64 sum
+// is its own statement, so the host compiler cannot fuse it into an FMA.
+inline int32_t stencil_half_width(double kw, int n) {
+    double c = 1.5 / kw;
+    c = c + 5.0;
+    double g = 400.0 * kw;
+    g = g + 150.0;
+    if (!(c < 1e9) || !(g < 1e9)) return -1;
+    const int64_t count = int64_t(__builtin_floor(c)), ng = int64_t(__builtin_floor(g));
+    const int64_t h = (count * n + ng - 1) / ng;
+    return h <= HF_STENCIL_MAX_HALF_WIDTH ? int32_t(h) : -1;
 }
 
 // ---------------------------------------------------------------------------

@@ -18,7 +18,7 @@ extern "C" hf_status hf_find_halos(hf_ctx *ctx, const hf_box *box, const hf_job 
         (job->max_cap > 0 && !job->max_idx) || (job->np > 0 && (!job->pos || !job->particle_label)) ||
         (job->dtype != HF_F32 && job->dtype != HF_F64) ||
         (job->kernel != HF_KERNEL_SAMPLED && job->kernel != HF_KERNEL_ANALYTIC && job->kernel != HF_KERNEL_STENCIL) ||
-        !(job->kw > 0.0) || (job->kernel == HF_KERNEL_STENCIL && stencil_half_width(job->kw) < 0) ||
+        !(job->kw > 0.0) || (job->kernel == HF_KERNEL_STENCIL && stencil_half_width(job->kw, box->n) < 0) ||
         job->tau != job->tau)
         return HF_ERR_ARG;
     // With the binned deposit the particle order it builds is kept (in front of
@@ -71,7 +71,7 @@ extern "C" hf_status hf_find_halos_filtered(hf_ctx *ctx, const hf_box *box, cons
         (job->max_cap > 0 && !job->max_idx) || (job->np > 0 && (!job->pos || !job->particle_label)) ||
         (job->dtype != HF_F32 && job->dtype != HF_F64) ||
         (job->kernel != HF_KERNEL_SAMPLED && job->kernel != HF_KERNEL_ANALYTIC && job->kernel != HF_KERNEL_STENCIL) ||
-        !(job->kw > 0.0) || (job->kernel == HF_KERNEL_STENCIL && stencil_half_width(job->kw) < 0) ||
+        !(job->kw > 0.0) || (job->kernel == HF_KERNEL_STENCIL && stencil_half_width(job->kw, box->n) < 0) ||
         job->tau != job->tau)
         return HF_ERR_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;

@@ -313,6 +313,14 @@ __global__ void __launch_bounds__(ST_THREADS)
 
 size_t hf::stencil_ws_bytes(const hf_box &box) { return stencil_layout(box.n).total; }
 
+extern "C" hf_status hf_stencil_half_width(double kw, int32_t n, int32_t *half_width) {
+    if (!half_width || !(kw > 0.0) || !std::isfinite(kw) || n < 1 || n > 1024) return HF_ERR_ARG;
+    const int32_t h = stencil_half_width(kw, n);
+    if (h < 0) return HF_ERR_ARG;
+    *half_width = h;
+    return HF_OK;
+}
+
 extern "C" hf_status hf_cwt_stencil(hf_ctx *ctx, const hf_box *box, const int64_t *rho, double kw,
                                     int32_t half_width, float *cwt, void *ws, size_t ws_bytes) {
     if (!ctx || !rho || !cwt) return HF_ERR_ARG;

@@ -27,7 +27,7 @@ EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_
            "hf_cwt_batch_ws_size", "hf_cwt_batch", "hf_find_halos", "hf_find_halos_group", "hf_groups",
            "hf_find_halos_filtered", "hf_cwt_scales",
            "hf_find_halos_scales_ws_size", "hf_find_halos_scales", "hf_cross_scale", "hf_peaks",
-           "hf_cwt_stencil", "hf_identify_ws_size", "hf_identify")
+           "hf_cwt_stencil", "hf_stencil_half_width", "hf_identify_ws_size", "hf_identify")
 CWT_BATCH_MAX = 32
 STAGE_ALL = 31
 STAGE_GROUPS = 32
@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "hf_deposit": (ctypes.c_int, [vp, bp, vp, ctypes.c_int, i64, vp, vp, sz]),
             "hf_cwt": (ctypes.c_int, [vp, bp, vp, dbl, ctypes.c_int, vp, vp, sz]),
             "hf_cwt_stencil": (ctypes.c_int, [vp, bp, vp, dbl, i32, vp, vp, sz]),
+            "hf_stencil_half_width": (ctypes.c_int, [dbl, i32, ctypes.POINTER(i32)]),
             "hf_maxima": (ctypes.c_int, [vp, bp, vp, flt, vp, i64, vp, vp, sz]),
             "hf_segment": (ctypes.c_int, [vp, bp, vp, flt, vp, vp, sz]),
             "hf_label": (ctypes.c_int, [vp, bp, vp, ctypes.c_int, i64, vp, vp]),
@@ -127,7 +128,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "hf_find_halos_group": (ctypes.c_int, [vp, i32, i32, i32, ctypes.POINTER(GroupItem), ctypes.c_int,
                                                    vp, sz]),
             "hf_groups": (ctypes.c_int, [vp, bp, i64, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp, vp, sz]),
-            "hf_cross_scale": (ctypes.c_int, [vp, bp, vp, i64, vp, vp, vp]),
+            "hf_cross_scale": (ctypes.c_int, [vp, bp, vp, i64, vp, i32, vp, vp]),
             "hf_peaks": (ctypes.c_int, [vp, bp, vp, vp, i64, vp, vp]),
             "hf_find_halos_filtered": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job), ctypes.POINTER(GroupFilter), vp,
                                                       sz]),
@@ -292,20 +293,23 @@ def cwt(rho: torch.Tensor, box_len: float, kw: float, kernel: str = "sampled", o
     return out
 
 
-def gdw_resolution(kw: float) -> int:
-    """Table 1's wavelet grid resolution Int(1.5 / k_w + 5): the stencil half-width."""
-    return int(1.5 / kw + 5.0)
+def stencil_half_width(kw: float, n: int) -> int:
+    """The library's default stencil half-width on an n^3 grid (hf_stencil_half_width:
+    Table 1's count Int(1.5/k_w + 5) kept at its extent on the grid N_g = Int(400 k_w + 150))."""
+    h = ctypes.c_int32()
+    _check(load_library().hf_stencil_half_width(float(kw), int(n), ctypes.byref(h)), "hf_stencil_half_width")
+    return int(h.value)
 
 
 def cwt_stencil(rho: torch.Tensor, box_len: float, kw: float, half_width: int | None = None, out=None, ctx=None,
                 frac_bits: int = 15, ws=None) -> torch.Tensor:
     """Step 3 by the truncated real-space stencil of Sec. 2.1 (FP32), half-width
-    gdw_resolution(kw) unless given.  Enqueued on the context's stream."""
+    stencil_half_width(kw, n) unless given.  Enqueued on the context's stream."""
     _require_cuda(rho, "rho")
     if rho.dtype != torch.int64 or rho.ndim != 3:
         raise ValueError("rho must be an int64 [n, n, n] grid")
     n = rho.shape[0]
-    h = gdw_resolution(kw) if half_width is None else int(half_width)
+    h = stencil_half_width(kw, n) if half_width is None else int(half_width)
     ctx = ctx or context(rho.device.index)
     if out is None:
         out = torch.empty((n, n, n), dtype=torch.float32, device=rho.device)
@@ -398,11 +402,16 @@ def peaks(c: torch.Tensor, roots: torch.Tensor, box_len: float, ctx=None):
 
 
 def cross_scale(c_scale: torch.Tensor, c_smaller: torch.Tensor, roots: torch.Tensor, ctx=None) -> torch.Tensor:
-    """Step 8: uint8 flags, 1 where the maximum roots[i] of c_scale exceeds
-    c_smaller (the adjacent smaller scale, same grid) at its 27 grid points."""
+    """Step 8: uint8 flags, 1 where the maximum roots[i] of c_scale, corrected
+    for the grid (step 4, App. B), exceeds c_smaller (the adjacent smaller
+    scale over the same box, on a grid of its own size) near its corrected
+    position."""
     _require_cuda(c_scale, "cwt")
-    if c_scale.dtype != torch.float32 or c_smaller.dtype != torch.float32 or c_scale.shape != c_smaller.shape:
-        raise ValueError("both fields must be float32 [n, n, n]")
+    if c_scale.dtype != torch.float32 or c_smaller.dtype != torch.float32:
+        raise ValueError("both fields must be float32")
+    for c in (c_scale, c_smaller):
+        if c.dim() != 3 or not (c.shape[0] == c.shape[1] == c.shape[2]) or not c.is_contiguous():
+            raise ValueError("fields must be contiguous [n, n, n]")
     if roots.dtype != torch.int32:
         raise ValueError("roots must be int32")
     n = c_scale.shape[0]
@@ -410,7 +419,7 @@ def cross_scale(c_scale: torch.Tensor, c_smaller: torch.Tensor, roots: torch.Ten
     out = torch.empty(max(roots.numel(), 1), dtype=torch.uint8, device=c_scale.device)[: roots.numel()]
     b = box(n, 1.0)
     _check(load_library().hf_cross_scale(ctx.handle, ctypes.byref(b), _ptr(roots), roots.numel(), _ptr(c_scale),
-                                         _ptr(c_smaller), _ptr(out)), "hf_cross_scale")
+                                         c_smaller.shape[0], _ptr(c_smaller), _ptr(out)), "hf_cross_scale")
     return out
 
 

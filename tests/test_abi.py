@@ -163,3 +163,27 @@ def test_header_is_plain_c99(tmp_path):
     r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", "-I", include,
                         str(src)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_stencil_half_width_rule_matches_the_oracle(lib):
+    """hf_stencil_half_width (host only) gives the oracle's reading of Table 1's
+    gdw_resolution on any grid, and rejects what the stencil kernels cannot take."""
+    from oracle import cwthf as O
+    h = ctypes.c_int32()
+    for kw in (0.0123, 0.05, 0.1, 0.128, 0.256, 0.3, 0.512, 0.75, 1.024, 1.7, 2.5, 4.0):
+        for n in (8, 16, 24, 64, 96, 190, 256, 354, 512, 559, 1024):
+            want = O.stencil_half_width(kw, n)
+            code = lib.hf_stencil_half_width(ctypes.c_double(kw), n, ctypes.byref(h))
+            if want <= 64:
+                assert code == hf.HF_OK and h.value == want, (kw, n)
+            else:
+                assert code == hf.HF_ERR_ARG, (kw, n)
+    for kw, n in ((0.0, 64), (-1.0, 64), (float("nan"), 64), (float("inf"), 64), (0.5, 0), (0.5, 1025)):
+        assert lib.hf_stencil_half_width(ctypes.c_double(kw), n, ctypes.byref(h)) == hf.HF_ERR_ARG
+    assert lib.hf_stencil_half_width(ctypes.c_double(0.5), 64, None) == hf.HF_ERR_ARG
+
+
+def test_cross_scale_rejects_before_any_device_call(lib):
+    b = hf.Box(16, 15, 10.0)
+    vp = ctypes.c_void_p
+    assert lib.hf_cross_scale(None, ctypes.byref(b), vp(0), 0, vp(0), 16, vp(0), vp(0)) == hf.HF_ERR_ARG

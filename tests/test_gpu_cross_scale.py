@@ -1,7 +1,8 @@
-"""GPU parity of the cross-scale maximum check (step 8) and of the group filter
-that uses it, against the oracle, through the C ABI.  Both sides decide on the
-same FP32 fields, which the oracle produces (stage-isolated), so the flags and
-labels must agree bit for bit."""
+"""GPU parity of the cross-scale maximum check (step 8, each maximum corrected
+for the grid as step 4 asks, App. B) and of the group filter that uses it,
+against the oracle, through the C ABI.  Both sides decide on the same FP32
+fields, which the oracle produces (stage-isolated), so the flags and labels
+must agree bit for bit, on one grid and across grids of different size."""
 import numpy as np
 import pytest
 import torch
@@ -41,6 +42,46 @@ def test_cross_scale_matches_oracle(n, L, np_, halos, seed, scales):
     want = O.cross_scale(c1, c2, roots)
     np.testing.assert_array_equal(got.cpu().numpy().astype(bool), want)
     assert want.any() and not want.all()
+
+
+@pytest.mark.parametrize("n2,n1,L,np_,seed,a2,a1", [
+    # scales 2-3% apart in box units, so that some maxima pass and some fail
+    (48, 64, 60.0, 200000, 71, 2.0, 2.6),    # finer grid for the smaller scale, ratio 4/3
+    (32, 96, 40.0, 100000, 72, 1.5, 4.4),    # three times finer
+    (64, 48, 64.0, 300000, 73, 1.5, 1.1),    # coarser (the cube-size term changes sign)
+])
+def test_cross_scale_across_grids_matches_oracle(n2, n1, L, np_, seed, a2, a1):
+    pos = small_box(max(n1, n2), L, np_, 200, "f32", seed)
+    c2 = O.cwt(O.deposit(pos, L, n2), L, n2 / (1000.0 * a2)).astype(np.float32)
+    c1 = O.cwt(O.deposit(pos, L, n1), L, n1 / (1000.0 * a1)).astype(np.float32)
+    roots = O.maxima(c2)
+    print(f"cross scale across grids n2={n2} n1={n1} roots={len(roots)}", flush=True)
+    got = hfm().cross_scale(cuda(c2), cuda(c1), cuda(roots.astype(np.int32)))
+    hfm().sync()
+    want = O.cross_scale(c2, c1, roots)
+    np.testing.assert_array_equal(got.cpu().numpy().astype(bool), want)
+    assert want.any() and not want.all()
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_cross_scale_off_grid_paraboloid(seed):
+    # the raw grid value is below the flat smaller-scale field, the corrected top above it
+    rng = np.random.default_rng(seed)
+    n = 16
+    x0 = np.array([6.0, 9.0, 5.0]) + rng.uniform(0.2, 0.45, 3) * rng.choice([-1, 1], 3)
+    k = rng.uniform(0.5, 2.0, 3)
+    g = np.arange(n, dtype=np.float64)
+    Z, Y, X = np.meshgrid(g, g, g, indexing="ij")
+    c = (40.0 - k[0] * (X - x0[0]) ** 2 - k[1] * (Y - x0[1]) ** 2 - k[2] * (Z - x0[2]) ** 2).astype(np.float32)
+    r = np.round(x0).astype(int)
+    root = np.array([(r[2] * n + r[1]) * n + r[0]], dtype=np.int32)
+    B = float(c.ravel()[root[0]])
+    for level, expect in ((0.5 * (B + 40.0), 1), (40.0 + 0.01, 0)):
+        flat = np.full((n, n, n), level, np.float32)
+        assert O.cross_scale(c, flat, root).tolist() == [bool(expect)]
+        got = hfm().cross_scale(cuda(c), cuda(flat), cuda(root))
+        hfm().sync()
+        assert got.cpu().tolist() == [expect]
 
 
 def test_cross_scale_blob():

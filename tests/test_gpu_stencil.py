@@ -60,14 +60,19 @@ def test_wide_stencils_match_the_fft_path():
         assert float((c - c_fft).abs().max()) <= 2 * CWT_RTOL * peak
 
 
-def test_default_half_width_is_table1_rule():
+def test_default_half_width_is_table1_extent():
+    # the library's rule equals the oracle's on the paper's grids, the 1024^3
+    # box's scales and small test grids
+    for kw, n in ((0.1, 190), (2.5, 1150 // 2), (0.512, 1024), (1.024, 1024), (0.256, 1024), (0.5, 64),
+                  (0.02, 16), (0.05, 24), (0.3, 192)):
+        assert hfm().stencil_half_width(kw, n) == O.stencil_half_width(kw, n), (kw, n)
     n, L = 64, 64.0
     pos = small_box(n, L, 100000, 60, "f32", 63)
-    kw = 0.5  # gdw_resolution = Int(3 + 5) = 8
-    assert hfm().gdw_resolution(kw) == 8
+    kw = 0.02  # Int(75 + 5) = 80 cells of N_g = 158: ceil(80 * 64 / 158) = 33
+    assert hfm().stencil_half_width(kw, n) == 33
     rho = hfm().deposit(cuda(pos), L, n)
     a = hfm().cwt_stencil(rho, L, kw)
-    b = hfm().cwt_stencil(rho, L, kw, 8)
+    b = hfm().cwt_stencil(rho, L, kw, 33)
     hfm().sync()
     assert torch.equal(a, b)  # fixed summation order: deterministic
 
@@ -106,12 +111,14 @@ def test_errors():
 
 
 def test_full_size_sampled_cells():
-    # 1024^3 box of 2^30 particles, a = 2 cells: k_w = 0.512, Table 1's half-width 7
+    # 1024^3 box of 2^30 particles, a = 2 cells: k_w = 0.512, Table 1's 7 cells
+    # of N_g = 354 kept at their extent: half-width 21
     import synth
     cfg = synth.CONFIGS["M4"]
     n, L = cfg.n, cfg.box_len
     kw = cfg.kw_list[0]
-    h = hfm().gdw_resolution(kw)
+    h = hfm().stencil_half_width(kw, n)
+    assert h == 21
     print(f"stencil full size n={n} kw={kw} h={h}", flush=True)
     pos = synth.make_config_box(cfg, device="cuda")
     rho = hfm().deposit(pos, L, n)
@@ -132,12 +139,12 @@ def test_full_size_sampled_cells():
 
 def test_stencil_kernel_in_the_transform_and_the_pipeline():
     # HF_KERNEL_STENCIL: hf_cwt and hf_find_halos take the paper's truncated
-    # stencil with Table 1's half-width (k_w = 0.25: h = 11)
-    n, L, kw = 32, 40.0, 0.25
+    # stencil with Table 1's extent (k_w = 0.02: ceil(80 * 32 / 158) = 17, a = 1.6 cells)
+    n, L, kw = 32, 40.0, 0.02
     pos = small_box(n, L, 40000, 60, "f32", 65)
     rho = hfm().deposit(cuda(pos), L, n)
     a = hfm().cwt(rho, L, kw, "stencil")
-    b = hfm().cwt_stencil(rho, L, kw, 11)
+    b = hfm().cwt_stencil(rho, L, kw, 17)
     out = hfm().find_halos(cuda(pos), L, n, kw, kernel="stencil")
     hfm().sync()
     assert torch.equal(a, b) and torch.equal(out["cwt"], b)
@@ -157,10 +164,12 @@ def test_stencil_kernel_limits():
     from paper_2501_10622_amd.hf import HF_ERR_ARG, HFError
     n, L = 16, 16.0
     rho = torch.ones((n, n, n), dtype=torch.int64, device="cuda")
-    # k_w = 0.02: Int(75 + 5) = 80 > the widest stencil
+    # k_w = 0.0005: Int(3000 + 5) = 3005 cells of N_g = 150 make 321 here, above the widest stencil
     with pytest.raises(HFError) as e:
-        hfm().cwt(rho, L, 0.02, "stencil")
+        hfm().cwt(rho, L, 0.0005, "stencil")
     assert e.value.code == HF_ERR_ARG
+    with pytest.raises(HFError):
+        hfm().stencil_half_width(0.0005, n)
     # the calls that share FFT passes take no stencil
     with pytest.raises(HFError) as e:
         hfm().cwt_scales(rho, L, [0.3, 0.6], "stencil")
@@ -174,7 +183,7 @@ def test_stencil_kernel_in_the_filtered_pipeline():
     # the fused group filter on the stencil transform equals the plain step
     # with the same transform followed by hf_groups (tile-order path at 192^3)
     from paper_2501_10622_amd import hf
-    n, L, kw = 192, 187.5, 0.3  # h = 10
+    n, L, kw = 192, 187.5, 0.3  # h = ceil(10 * 192 / 270) = 8
     pos = cuda(small_box(n, L, 2_000_000, 7910, "f32", 66))
     np_ = pos.shape[0]
     ctx = hf.context(0)

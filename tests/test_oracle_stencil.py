@@ -1,5 +1,12 @@
 """Pins for the oracle's real-space truncated-stencil CWT (Sec. 2.1; Table 1's
-gdw_resolution).
+gdw_resolution, kept at its physical extent on the paper's grid N_g).
+
+- On the paper's own grid the default half-width is Table 1's count; on any
+  grid it spans at least ten scale lengths, and the stencil then sums to zero
+  (the Mexican hat's zero mean) to 1e-7 of its peak at the 1024^3 box's
+  scales, where Table 1's count taken in the box's cells leaves a sum 21.6 and
+  661 times the peak (a = 2 and 4 cells).  The sums use the one-dimensional
+  factorisation, not the oracle's stencil.
 
 - A pure-Python gather over every (target, source) pair and every stencil
   offset congruent to their separation fixes the direction of the shifts, the
@@ -23,6 +30,45 @@ from oracle import cwthf as O
 def test_gdw_resolution_table1(kw, h):
     # Int(1.5 / k_w + 5); the two ends of Table 1's k_w range give 20 and 5
     assert O.gdw_resolution(kw) == h
+
+
+@pytest.mark.parametrize("kw", [0.1, 0.2, 0.35, 0.5, 1.0, 2.5])
+def test_default_half_width_on_the_paper_grid_is_table1(kw):
+    ng = int(400.0 * kw + 150.0)  # the flowchart's N_g
+    assert O.paper_grid(kw) == ng
+    assert O.stencil_half_width(kw, ng) == O.gdw_resolution(kw)
+
+
+def _stencil_sum_over_peak(n, box_len, kw, h):
+    # sum over the cube |d_i| <= h of dx^3 Psi(w, d dx), Psi = w^1.5 (6 - u) e^(-u/4)
+    # with u = w^2 r^2, factorises into 1D sums: 6 G^3 - 3 G^2 H, G = sum e^(-u_d/4),
+    # H = sum u_d e^(-u_d/4); the peak tap is 6 dx^3 w^1.5
+    w = 1000.0 * kw / box_len
+    u = (w * np.arange(-h, h + 1) * (box_len / n)) ** 2
+    G, H = np.sum(np.exp(-u / 4)), np.sum(u * np.exp(-u / 4))
+    return (6 * G ** 3 - 3 * G * G * H) / 6.0
+
+
+@pytest.mark.parametrize("a,h_expect,raw_sum", [(1.0, 11, 2.9e-3), (2.0, 21, 21.6), (4.0, 41, 661.5)])
+def test_default_stencil_keeps_zero_mean_at_the_1024_box(a, h_expect, raw_sum):
+    n, box_len = 1024, 1000.0
+    kw = n / (1000.0 * a)
+    h = O.stencil_half_width(kw, n)
+    assert h == h_expect
+    assert h * (1000.0 * kw / box_len) * (box_len / n) >= 10.0  # at least ten scale lengths
+    assert abs(_stencil_sum_over_peak(n, box_len, kw, h)) < 1e-7
+    raw = _stencil_sum_over_peak(n, box_len, kw, O.gdw_resolution(kw))
+    assert raw == pytest.approx(raw_sum, rel=2e-2)
+
+
+@pytest.mark.parametrize("n,kw", [(64, 0.02), (96, 0.05), (256, 0.1), (512, 0.3), (1024, 0.8), (150, 0.0)])
+def test_default_half_width_spans_ten_scale_lengths(n, kw):
+    if kw == 0.0:  # the paper's smallest grid at its largest default scale
+        kw, n = 0.1, 190
+    h = O.stencil_half_width(kw, n)
+    a_cells = n / (1000.0 * kw)
+    assert h / a_cells >= 10.0
+    assert (h - 1) / a_cells < 12.2  # and not much more (ceil of at most 12 scale lengths)
 
 
 def _brute(f, box_len, w, h):
@@ -127,7 +173,9 @@ def test_default_half_width_and_normalisation():
     rho = rng.integers(0, 1 << 40, size=(n, n, n))
     c = O.stencil_cwt(rho, box_len, kw)
     f = rho / (rho.sum() / n ** 3)
-    np.testing.assert_allclose(c, O.stencil_cwt_field(f, box_len, O.scale_w(kw, box_len), O.gdw_resolution(kw)),
+    h = O.stencil_half_width(kw, n)
+    assert h == 1  # Int(1.5 / 0.9 + 5) = 6 cells of N_g = 510 cover 0.14 of these 12 cells
+    np.testing.assert_allclose(c, O.stencil_cwt_field(f, box_len, O.scale_w(kw, box_len), h),
                                rtol=1e-13, atol=1e-13)
     with pytest.raises(ValueError):
         O.stencil_cwt(rho, box_len, kw, -1)
@@ -145,8 +193,8 @@ def test_pointwise_windows_equal_the_superposition(n, h):
                                atol=1e-12 * np.abs(full).max())
 
 
-def test_cwt_stencil_mode_is_the_stencil_with_table1_half_width():
+def test_cwt_stencil_mode_is_the_stencil_with_table1_extent():
     rng = np.random.default_rng(11)
-    n, box_len, kw = 12, 20.0, 0.6  # gdw_resolution(0.6) = 7
+    n, box_len, kw = 24, 20.0, 0.05  # Int(30 + 5) = 35 cells of N_g = 170: ceil(35 * 24 / 170) = 5
     rho = rng.integers(0, 1 << 40, size=(n, n, n))
-    np.testing.assert_array_equal(O.cwt(rho, box_len, kw, "stencil"), O.stencil_cwt(rho, box_len, kw, 7))
+    np.testing.assert_array_equal(O.cwt(rho, box_len, kw, "stencil"), O.stencil_cwt(rho, box_len, kw, 5))
