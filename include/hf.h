@@ -309,6 +309,23 @@ typedef struct {
 } hf_job;
 hf_status hf_find_halos(hf_ctx *ctx, const hf_box *box, const hf_job *job, void *ws, size_t ws_bytes);
 
+/* hf_find_halos for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same steps and results, with no workspace argument.  Its workspace is a
+ * static device array of HF_NOALLOC_SCRATCH_BYTES (64 MiB) per device, made
+ * resident when the first context on that device is created and held until the
+ * process ends; the call itself allocates nothing.  Enough for every box whose
+ * hf_workspace_size(box, np, HF_STAGE_ALL) (plus HF_STAGE_STENCIL with that
+ * transform) fits, e.g. n <= 128 with up to 2 n^3 particles; larger jobs get
+ * HF_ERR_WORKSPACE before anything is enqueued.  Every call on a device
+ * shares that device's array: calls that overlap on one device (two streams,
+ * or two host threads) race and must be serialised by the caller.  The
+ * array's contents persist between calls; the steps never read what they have
+ * not written in the same call.  HF_ERR_DEVICE if the array's address could
+ * not be resolved when the context was created. */
+#define HF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+hf_status hf_find_halos_noalloc(hf_ctx *ctx, const hf_box *box, const hf_job *job);
+
 /* Steps 2-6 as hf_find_halos, then steps 5 and 7 as hf_groups on its own
  * results (the roots are job->max_idx[0 .. min(*d_count, max_cap))):
  * job->cell_label keeps the segmentation, job->particle_label receives the

@@ -1,12 +1,38 @@
 // Context management, status reporting and workspace sizing of libhf.
 #include "hf_internal.h"
 
+#include <mutex>
+
 using namespace hf;
 
 namespace {
 
 __global__ void clear_status_kernel(uint32_t *st) {
     if (threadIdx.x == 0) st[0] = 0u;
+}
+
+// The workspace of hf_find_halos_noalloc: one array per device, resident from
+// the first context on that device until the process ends.  Host code never
+// names it except through HIP_SYMBOL: its device address on each device comes
+// from hipGetSymbolAddress (bind_scratch) and is kept in g_scratch.
+__device__ __align__(256) unsigned char scratch[HF_NOALLOC_SCRATCH_BYTES];
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[SCRATCH_DEVICES] = {};
+
+// Resolves the scratch array's address on `device`, which must be current.
+// Once per device; a failure leaves it unresolved (hf_find_halos_noalloc then
+// returns HF_ERR_DEVICE) and costs the other entry points nothing.
+void *bind_scratch(int device) {
+    if (device < 0 || device >= SCRATCH_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p) g_scratch[device] = p;
+        else (void)hipGetLastError();
+    }
+    return g_scratch[device];
 }
 
 }  // namespace
@@ -104,6 +130,7 @@ extern "C" hf_status hf_create(int device, void *hip_stream, hf_ctx **out) {
         return HF_ERR_DEVICE;
     }
     c->h_status[0] = 0;
+    c->scratch = bind_scratch(device);
     hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, c->stream, c->d_status);
     if (hipStreamSynchronize(c->stream) != hipSuccess) {
         (void)hipFree(c->d_status);
@@ -185,4 +212,18 @@ extern "C" hf_status hf_workspace_size(const hf_box *box, int64_t np, int stage_
     if ((stage_mask & HF_STAGE_GROUPS) && !groups_apart) take(groups_ws_bytes(*box));
     *bytes = (order ? particle_order_bytes(*box, np) : 0) + (groups_apart ? groups_ws_bytes(*box) : 0) + need;
     return HF_OK;
+}
+
+// Steps 2-6 as hf_find_halos, with the device's scratch array as workspace.
+extern "C" hf_status hf_find_halos_noalloc(hf_ctx *ctx, const hf_box *box, const hf_job *job) {
+    if (!ctx || !job) return HF_ERR_ARG;
+    hf_status s = check_box(box);
+    if (s != HF_OK) return s;
+    size_t need = 0;
+    s = hf_workspace_size(box, job->np, HF_STAGE_ALL | (job->kernel == HF_KERNEL_STENCIL ? HF_STAGE_STENCIL : 0),
+                          &need);
+    if (s != HF_OK) return s;
+    if (need > HF_NOALLOC_SCRATCH_BYTES) return HF_ERR_WORKSPACE;
+    if (!ctx->scratch) return HF_ERR_DEVICE;
+    return hf_find_halos(ctx, box, job, ctx->scratch, HF_NOALLOC_SCRATCH_BYTES);
 }

@@ -38,6 +38,7 @@ struct hf_ctx {
     hipStream_t stream;
     uint32_t *d_status;  // device status block: [0] error bit mask
     uint32_t *h_status;  // pinned host mirror
+    void *scratch = nullptr;  // this device's hf_find_halos_noalloc workspace
     // kernel timer (off unless hf_profile_enable): events around every launch
     bool prof = false;
     std::vector<hf::ProfRecord> pending;

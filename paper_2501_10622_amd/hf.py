@@ -27,7 +27,8 @@ EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_
            "hf_cwt_batch_ws_size", "hf_cwt_batch", "hf_find_halos", "hf_find_halos_group", "hf_groups",
            "hf_find_halos_filtered", "hf_cwt_scales",
            "hf_find_halos_scales_ws_size", "hf_find_halos_scales", "hf_cross_scale", "hf_peaks",
-           "hf_cwt_stencil", "hf_stencil_half_width", "hf_identify_ws_size", "hf_identify")
+           "hf_cwt_stencil", "hf_stencil_half_width", "hf_identify_ws_size", "hf_identify",
+           "hf_find_halos_noalloc")
 CWT_BATCH_MAX = 32
 STAGE_ALL = 31
 STAGE_GROUPS = 32
@@ -121,6 +122,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "hf_find_halos_scales": (ctypes.c_int, [vp, bp, vp, ctypes.c_int, i64, ctypes.c_int, flt, vp, i32,
                                                     ctypes.POINTER(ScaleJob), vp, sz]),
             "hf_find_halos": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job), vp, sz]),
+            "hf_find_halos_noalloc": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job)]),
             "hf_identify_ws_size": (ctypes.c_int, [bp, i64, i32, ctypes.POINTER(ScaleJob), ctypes.POINTER(sz)]),
             "hf_identify": (ctypes.c_int, [vp, bp, vp, ctypes.c_int, i64, ctypes.c_int, flt, vp, i32,
                                            ctypes.POINTER(ScaleJob), ctypes.POINTER(IdentifyGroups), dbl, i64, vp,
@@ -554,6 +556,22 @@ def find_halos_async(pos: torch.Tensor, box_len: float, n: int, kw: float, bufs:
     job = _job_struct(pos, kw, bufs, tau, kernel)
     _check(load_library().hf_find_halos(ctx.handle, ctypes.byref(b), ctypes.byref(job), _ptr(bufs["ws"]),
                                         bufs["ws"].numel()), "hf_find_halos")
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def find_halos_noalloc_async(pos: torch.Tensor, box_len: float, n: int, kw: float, bufs: dict, frac_bits: int = 15,
+                             tau: float = 0.0, kernel: str = "sampled", ctx=None):
+    """Enqueue steps 2-6 through hf_find_halos_noalloc: outputs in bufs (as from
+    job_buffers; its "ws" entry is not used), the workspace the library's own
+    per-device scratch array.  Calls that overlap on one device race."""
+    _require_cuda(pos, "pos")
+    ctx = ctx or context(pos.device.index)
+    b = box(n, box_len, frac_bits)
+    job = _job_struct(pos, kw, bufs, tau, kernel)
+    _check(load_library().hf_find_halos_noalloc(ctx.handle, ctypes.byref(b), ctypes.byref(job)),
+           "hf_find_halos_noalloc")
 
 
 def scales_buffers(n: int, np_: int, count: int, device, frac_bits: int = 15) -> dict:
