@@ -36,7 +36,7 @@ __all__ = [
     "scale_w", "fixed_point", "deposit", "total_mass", "mean_mass", "normalise",
     "wavelet", "wavelet_hat", "sampled_kernel", "kernel_hat", "cwt_field", "cwt",
     "gdw_resolution", "paper_grid", "stencil_half_width", "stencil", "stencil_cwt_field", "stencil_cwt", "stencil_cwt_at",
-    "neighbour_offsets", "maxima", "parents", "segment", "ngp_nodes", "label",
+    "neighbour_offsets", "maxima", "is_maximum_at", "parents", "segment", "follow", "ngp_nodes", "label",
     "find_halos", "group_stats", "cross_scale", "peaks", "cube_size_term", "identify", "DepositOverflow",
 ]
 
@@ -159,9 +159,11 @@ def wavelet_hat(w: float, k) -> np.ndarray:
 
 
 def _image_count(w: float, box_len: float) -> int:
-    # Images beyond |m| = I lie at distance >= (I + 1/2) L from every node;
-    # choose I so that w (I + 1/2) L >= 16, where |Psi| / Psi(0) < 1e-25.
-    return max(1, int(math.ceil(16.0 / (w * box_len) - 0.5)))
+    # Images beyond |m| = I lie at distance >= (I + 1/2) L from every node
+    # (offsets are minimum-image); choose the least I >= 0 with
+    # w (I + 1/2) L >= 16, where |Psi| / Psi(0) < 1e-25: the images left out
+    # sum to below 1e-24 of the peak, far under the FP64 rounding of the rest.
+    return max(0, int(math.ceil(16.0 / (w * box_len) - 0.5)))
 
 
 def sampled_kernel(n: int, box_len: float, w: float) -> np.ndarray:
@@ -360,6 +362,27 @@ def maxima(c: np.ndarray, tau: float = 0.0) -> np.ndarray:
     return np.flatnonzero(is_max.ravel()).astype(np.int64)
 
 
+def is_maximum_at(c: np.ndarray, cells, tau: float = 0.0) -> np.ndarray:
+    """``maxima``'s test evaluated at the given linear cells only: the cell beats
+    each of its 26 periodic neighbours in the (value, index) order and exceeds
+    tau.  For fields too large to test whole."""
+    c = np.asarray(c)
+    n = c.shape[0]
+    cells = np.asarray(cells, dtype=np.int64).ravel()
+    z, y, x = cells // (n * n), (cells // n) % n, cells % n
+    v = c[z, y, x]
+    if np.any(np.isnan(v)):
+        raise ValueError("NaN in the CWT field")
+    ok = v > c.dtype.type(tau)
+    for (dz, dy, dx) in neighbour_offsets():
+        k = (((z + dz) % n) * n + (y + dy) % n) * n + (x + dx) % n
+        u = c.ravel()[k]
+        if np.any(np.isnan(u)):
+            raise ValueError("NaN in the CWT field")
+        ok &= _beats(v, cells, u, k)
+    return ok
+
+
 # --------------------------------------------------------------------------
 # step 5: segmentation
 # --------------------------------------------------------------------------
@@ -472,6 +495,35 @@ def segment(c: np.ndarray, tau: float = 0.0) -> np.ndarray:
         active = active[par[root[active]] != root[active]]
     flat = c.ravel()
     return np.where(flat[root] > flat.dtype.type(tau), root, -1).astype(np.int64).reshape(c.shape)
+
+
+def follow(c: np.ndarray, cells, tau: float = 0.0) -> np.ndarray:
+    """``segment``'s label of the given linear cells only, by walking the
+    steepest-ascent path from each: step to the largest of the cell and its 26
+    periodic neighbours in the (value, index) order until the cell is its own
+    largest.  For fields too large to segment whole."""
+    c = np.asarray(c)
+    n = c.shape[0]
+    flat = c.ravel()
+    offs = np.array(neighbour_offsets() + [(0, 0, 0)], dtype=np.int64)
+    cur = np.asarray(cells, dtype=np.int64).ravel().copy()
+    active = np.arange(cur.size)
+    while active.size:
+        j = cur[active]
+        z, y, x = j // (n * n), (j // n) % n, j % n
+        cand = (((z[:, None] + offs[:, 0]) % n) * n + (y[:, None] + offs[:, 1]) % n) * n + (x[:, None] + offs[:, 2]) % n
+        vals = flat[cand]
+        if np.any(np.isnan(vals)):
+            raise ValueError("NaN in the CWT field")
+        best_v, best_i = vals[:, 0].copy(), cand[:, 0].copy()
+        for k in range(1, cand.shape[1]):
+            take = _beats(vals[:, k], cand[:, k], best_v, best_i)
+            best_v = np.where(take, vals[:, k], best_v)
+            best_i = np.where(take, cand[:, k], best_i)
+        moved = best_i != j
+        cur[active] = best_i
+        active = active[moved]
+    return np.where(flat[cur] > flat.dtype.type(tau), cur, -1).astype(np.int64)
 
 
 # --------------------------------------------------------------------------
