@@ -1,6 +1,7 @@
 """Seeded synthetic inputs for the CWT halo-finder hot path.
 
-This module only draws random particle boxes and job streams.  It holds none of
+This module only draws random particle boxes, job streams and smooth test
+fields.  It holds none of
 the halo finder's arithmetic (no deposit, transform, maxima or segmentation), so
 both the FP64 oracle and the GPU path can take their inputs from it.
 
@@ -135,6 +136,33 @@ def make_box(box_len: float, n_particles: int, n_halos: int, dtype: str, seed: i
     out = torch.where(out >= top, out - top, out)  # values rounded up to L wrap to 0
     perm = torch.randperm(n_particles, generator=gen, device=device)
     return out[perm].contiguous()
+
+
+def smooth_field(n: int, seed: int, device="cpu", half_width: int = 2, passes: int = 2) -> torch.Tensor:
+    """A seeded smooth random FP32 field [n][n][n] with many local maxima, for
+    testing maxima and segmentation on their own at any size.
+
+    White noise U[0, 1) is smoothed by ``passes`` periodic moving averages of
+    2 ``half_width`` + 1 cells along each axis (about a Gaussian of width
+    half_width sqrt(passes) cells), and a weak long-wavelength ripple is added
+    so that some ascent paths run across many cells.  This is an input
+    generator, not a transform of the method: it only shapes test data."""
+    device = torch.device(device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    f = torch.rand((n, n, n), generator=gen, dtype=torch.float32, device=device)
+    for _ in range(passes):
+        for axis in range(3):
+            acc = f.clone()
+            for d in range(1, half_width + 1):
+                acc += torch.roll(f, d, axis)
+                acc += torch.roll(f, -d, axis)
+            f = acc / float(2 * half_width + 1)
+            del acc
+    g = torch.arange(n, dtype=torch.float32, device=device) * (2.0 * math.pi / n)
+    ripple = torch.cos(g)[:, None, None] + torch.cos(2.0 * g)[None, :, None] + torch.cos(g)[None, None, :]
+    f += 0.005 * ripple
+    return (f - 0.5).contiguous()
 
 
 def make_config_box(cfg: BoxConfig, device="cpu") -> torch.Tensor:

@@ -38,26 +38,41 @@ def _two_halo_box():
 
 
 def _cross_margin_ok(fields, roots_list, eps):
-    # every step-8 comparison decided more than 2 eps away from equality
+    # every step-8 comparison decided more than 8 eps away from equality: the
+    # corrected value (step 4, App. B) against every point near either of the
+    # two candidate nodes of its corrected position, and that position more
+    # than 0.05 cell from a rounding boundary
     n = fields[0].shape[0]
     for i, roots in enumerate(roots_list):
+        if len(roots) == 0:
+            continue
         nxt = fields[i + 1] if i + 1 < len(fields) else np.zeros_like(fields[i])
-        for r in roots.tolist():
-            z, y, x = r // (n * n), (r // n) % n, r % n
-            v = fields[i][z, y, x]
-            for a in (-1, 0, 1):
-                for b in (-1, 0, 1):
-                    for c in (-1, 0, 1):
-                        if abs(v - nxt[(z + a) % n, (y + b) % n, (x + c) % n]) <= 2 * eps:
-                            return False
+        shift, value, _, _ = O._peak_fits(fields[i], roots)
+        r = np.asarray(roots)
+        g = np.stack([r % n, (r // n) % n, r // (n * n)], axis=1) + shift  # (x, y, z) in cells
+        frac = g + 0.5 - np.floor(g + 0.5)
+        if np.any(np.minimum(frac, 1.0 - frac) <= 0.05):
+            return False
+        base = np.floor(g).astype(np.int64)
+        for k in range(len(r)):
+            x0, y0, z0 = base[k]
+            near = nxt[np.ix_([(z0 + d) % n for d in range(-1, 3)], [(y0 + d) % n for d in range(-1, 3)],
+                              [(x0 + d) % n for d in range(-1, 3)])]
+            if np.any(np.abs(value[k] - near) <= 8 * eps):
+                return False
     return True
 
 
-@pytest.mark.parametrize("case", ["two_halos", "clustered_32", "clustered_48"])
+@pytest.mark.parametrize("case", ["two_halos", "clustered_32", "clustered_48", "binned_144"])
 def test_matches_oracle_loop(case):
     if case == "two_halos":
         pos, L = _two_halo_box()
         n, scales, dens_th, pth = 32, (4.0, 2.0, 1.0), 4.0, 15
+    elif case == "binned_144":
+        # the deposit's kept particle order (several buckets): the tile-order loop
+        n, L = 144, 140.0
+        pos = small_box(n, L, 2_500_000, 3300, "f32", 144)
+        scales, dens_th, pth = (4.0, 2.0, 1.0), 4.0, 15
     else:
         n = 32 if case == "clustered_32" else 48
         L = float(n) * 1.25

@@ -41,3 +41,45 @@ def test_three_scales(box, a):
     if tie_free(c64, eps):
         assert agree == 1.0
     assert agree >= LABEL_AGREEMENT
+
+
+def test_precision_study_512_three_scales():
+    """The precision configuration itself: L = 500 Mpc/h, 512^3 FP32 particles
+    (150000 NFW halos), 512^3 grid, scales a = 1, 2, 4 cells, through the
+    multi-scale step the benchmark times for it (hf_find_halos_scales).  Per
+    scale: the density bit-exact (once), the FP32 CWT within 1e-5 of max |C| of
+    the FP64 oracle, particle labels agreeing on >= 99.99% of particles."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    import synth
+    from oracle import cic
+    from paper_2501_10622_amd import hf
+    ensure_built()
+    cfg = synth.CONFIGS["M3"]
+    n, L, kws = cfg.n, cfg.box_len, cfg.kw_list
+    print(f"precision 512^3: generating {cfg.n_particles} particles", flush=True)
+    pos = synth.make_config_box(cfg, device="cuda")
+    ctx = hf.context(0)
+    bufs = hf.scales_buffers(n, pos.shape[0], len(kws), pos.device)
+    hf.find_halos_scales_async(pos, L, n, kws, bufs, ctx=ctx)
+    ctx.sync()
+    del bufs["ws"]
+    pos_h = pos.cpu().numpy()
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    rho64 = cic.deposit_c(pos_h, L, n, 15, threads=threads)
+    assert np.array_equal(bufs["rho"].cpu().numpy(), rho64)
+
+    def oracle_scale(kw):
+        c64 = O.cwt(rho64, L, kw)
+        return c64, O.label(pos_h, L, n, O.segment(c64))
+
+    print("precision 512^3: oracle scales in threads", flush=True)
+    with ThreadPoolExecutor(max_workers=len(kws)) as ex:
+        ref = list(ex.map(oracle_scale, kws))
+    for j, (a, (c64, lab64)) in enumerate(zip(cfg.scales_cells, ref)):
+        err = cwt_error(bufs["cwt"][j].cpu().numpy(), c64)
+        agree = float(np.mean(bufs["particle_label"][j][: pos_h.shape[0]].cpu().numpy() == lab64))
+        print(f"precision 512^3 a={a}: cwt rel err {err:.2e}, particle-label agreement {agree:.7f}", flush=True)
+        assert err <= CWT_RTOL
+        assert agree >= LABEL_AGREEMENT
