@@ -225,12 +225,19 @@ def context(device=None, stream=None) -> Context:
     return ctx
 
 
-def workspace(nbytes: int, device: int) -> torch.Tensor:
-    """A reusable device workspace of at least nbytes (one per device)."""
-    cur = _ws.get(device)
+def workspace(nbytes: int, ctx: Context) -> torch.Tensor:
+    """A reusable device workspace of at least nbytes, one per (device, stream).
+
+    It is allocated on the context's own stream, the only stream its kernels
+    run on, so when a larger one replaces it the caching allocator cannot hand
+    the old memory to work still queued on another stream; two contexts on
+    different streams never share one."""
+    key = (ctx.device, ctx.stream.cuda_stream)
+    cur = _ws.get(key)
     if cur is None or cur.numel() < nbytes:
-        cur = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=torch.device("cuda", device))
-        _ws[device] = cur
+        with torch.cuda.stream(ctx.stream):
+            cur = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=torch.device("cuda", ctx.device))
+        _ws[key] = cur
     return cur
 
 
@@ -271,7 +278,7 @@ def deposit(pos: torch.Tensor, box_len: float, n: int, frac_bits: int = 15, out=
         out = torch.empty((n, n, n), dtype=torch.int64, device=pos.device)
     b = box(n, box_len, frac_bits)
     need = workspace_size(n, box_len, pos.shape[0], STAGE_DEPOSIT, frac_bits)
-    ws = workspace(need, pos.device.index) if need else None
+    ws = workspace(need, ctx) if need else None
     _check(load_library().hf_deposit(ctx.handle, ctypes.byref(b), _ptr(pos), _dtype_code(pos), pos.shape[0],
                                      _ptr(out), _ptr(ws), need), "hf_deposit")
     return out
@@ -289,7 +296,7 @@ def cwt(rho: torch.Tensor, box_len: float, kw: float, kernel: str = "sampled", o
         out = torch.empty((n, n, n), dtype=torch.float32, device=rho.device)
     b = box(n, box_len, frac_bits)
     need = workspace_size(n, box_len, 0, STAGE_STENCIL if kernel == "stencil" else STAGE_CWT, frac_bits)
-    ws = workspace(need, rho.device.index)
+    ws = workspace(need, ctx)
     _check(load_library().hf_cwt(ctx.handle, ctypes.byref(b), _ptr(rho), float(kw), KERNELS[kernel], _ptr(out),
                                  _ptr(ws), need), "hf_cwt")
     return out
@@ -318,7 +325,7 @@ def cwt_stencil(rho: torch.Tensor, box_len: float, kw: float, half_width: int | 
     b = box(n, box_len, frac_bits)
     need = workspace_size(n, box_len, 0, STAGE_STENCIL, frac_bits)
     if ws is None:
-        ws = workspace(need, rho.device.index)
+        ws = workspace(need, ctx)
     elif ws.numel() * ws.element_size() < need:
         raise ValueError("workspace too small for hf_cwt_stencil")
     _check(load_library().hf_cwt_stencil(ctx.handle, ctypes.byref(b), _ptr(rho), float(kw), h, _ptr(out), _ptr(ws),
@@ -342,7 +349,7 @@ def maxima(c: torch.Tensor, tau: float = 0.0, capacity: int | None = None, ctx=N
     cnt = torch.empty(1, dtype=torch.int64, device=c.device)
     b = box(n, 1.0)
     need = workspace_size(n, 1.0, 0, STAGE_MAXIMA)
-    ws = workspace(need, c.device.index)
+    ws = workspace(need, ctx)
     _check(load_library().hf_maxima(ctx.handle, ctypes.byref(b), _ptr(c), float(tau), _ptr(buf), int(capacity),
                                     _ptr(cnt), _ptr(ws), need), "hf_maxima")
     if not sync:
@@ -362,7 +369,7 @@ def segment(c: torch.Tensor, tau: float = 0.0, out=None, ctx=None) -> torch.Tens
         out = torch.empty((n, n, n), dtype=torch.int32, device=c.device)
     b = box(n, 1.0)
     need = workspace_size(n, 1.0, 0, STAGE_SEGMENT)
-    ws = workspace(need, c.device.index)
+    ws = workspace(need, ctx)
     _check(load_library().hf_segment(ctx.handle, ctypes.byref(b), _ptr(c), float(tau), _ptr(out), _ptr(ws), need),
            "hf_segment")
     return out
@@ -451,7 +458,7 @@ def groups(cell_label: torch.Tensor, particle_label: torch.Tensor, roots: torch.
     }
     b = box(n, 1.0)
     need = workspace_size(n, 1.0, 0, STAGE_GROUPS)
-    ws = workspace(need, dev.index)
+    ws = workspace(need, ctx)
     if root_ok is not None and (root_ok.dtype != torch.uint8 or root_ok.numel() != nroots):
         raise ValueError("root_ok must be uint8 with one flag per root")
     _check(load_library().hf_groups(ctx.handle, ctypes.byref(b), int(n_particles), _ptr(roots), int(nroots),
