@@ -643,7 +643,8 @@ def cross_scale(c_scale: np.ndarray, c_smaller: np.ndarray, roots) -> np.ndarray
 # the identification loop over scales (Sec. 2 and its flowchart)
 # --------------------------------------------------------------------------
 def identify(pos, box_len: float, n: int, kws, dens_th: float = 4.0, particle_th: int = 15,
-             frac_bits: int = 15, tau: float = 0.0, mode: str = "sampled", decide_dtype=np.float64) -> dict:
+             frac_bits: int = 15, tau: float = 0.0, mode: str = "sampled", decide_dtype=np.float64,
+             grids=None) -> dict:
     """Steps 2-8 over the scales ``kws`` (increasing k_w: from the largest
     scale length down), without the self-boundness check of steps 9-10.
 
@@ -654,36 +655,58 @@ def identify(pos, box_len: float, n: int, kws, dens_th: float = 4.0, particle_th
     discarded unless it passes the density and particle-number thresholds
     (step 7) and its maximum, corrected for the grid as step 4 asks (App. B),
     exceeds the next scale's field near its corrected position (step 8; after
-    the last scale the next grid is all zeros).  The particles of a kept
-    group are claimed at this scale with the group's root as their ID.
-    Reading: every scale is on the box's one n^3 grid (the paper re-grids
-    each scale, N_g = Int(400 k_w + 150)), and the density of a group counts
-    the particles it takes at its scale against the mean of all particles.
+    the last scale the next grid is all zeros, of the last scale's size).  The
+    particles of a kept group are claimed at this scale with the group's root
+    as their ID.
+
+    Grids: by default every scale uses the box's n^3 grid.  ``grids`` gives
+    each scale its own grid size instead; ``grids="paper"`` is the flowchart's
+    N_g = Int(400 k_w + 150) per scale (step 1), where each scale deposits the
+    particles afresh (step 2) and the cross-scale check compares grids of
+    different spacing with App. B's cube-size term.  A group's grid volume and
+    the density test count cells of its own scale's grid.  Reading: the density
+    of a group counts the particles it takes at its scale against the mean of
+    all particles.
     """
     kws = [float(k) for k in kws]
     if not kws or any(b <= a for a, b in zip(kws, kws[1:])):
         raise ValueError("scales must be given in increasing k_w")
+    if grids is None:
+        sizes = [int(n)] * len(kws)
+    elif isinstance(grids, str):
+        if grids != "paper":
+            raise ValueError("grids must be None, 'paper' or one size per scale")
+        sizes = [paper_grid(kw) for kw in kws]
+    else:
+        sizes = [int(g) for g in grids]
+        if len(sizes) != len(kws):
+            raise ValueError("one grid size per scale")
     np_total = len(pos)
-    rho = deposit(pos, box_len, n, frac_bits)
-    fields = [cwt(rho, box_len, kw, mode).astype(decide_dtype) for kw in kws]
+    rhos = {}
+    for size in sizes:
+        if size not in rhos:
+            rhos[size] = deposit(pos, box_len, size, frac_bits)
+    fields = [cwt(rhos[size], box_len, kw, mode).astype(decide_dtype) for size, kw in zip(sizes, kws)]
     halo_scale = np.full(np_total, -1, dtype=np.int64)
     halo_root = np.full(np_total, -1, dtype=np.int64)
     per_scale = []
     for i, c in enumerate(fields):
+        ni = sizes[i]
         nxt = fields[i + 1] if i + 1 < len(fields) else np.zeros_like(c)  # the flowchart's zero current_grid
         roots = maxima(c, tau)
         cell = segment(c, tau)
-        pl = label(pos, box_len, n, cell, frac_bits)
+        pl = label(pos, box_len, ni, cell, frac_bits)
         pl = np.where(halo_scale >= 0, -1, pl)  # only particles with no label yet
         ok = cross_scale(c, nxt, roots)
-        g = group_stats(cell, pl, roots, n, np_total, dens_th, particle_th, root_ok=ok)
+        g = group_stats(cell, pl, roots, ni, np_total, dens_th, particle_th, root_ok=ok)
         take = g["particle_label"] >= 0
         halo_scale[take] = i
         halo_root[take] = g["particle_label"][take]
-        per_scale.append({"cwt": c, "maxima": roots, "cell_label": cell, "cross_scale": ok,
+        per_scale.append({"grid": ni, "cwt": c, "maxima": roots, "cell_label": cell, "cross_scale": ok,
                           "particles": g["particles"], "cells": g["cells"], "keep": g["keep"],
                           "particle_label": g["particle_label"]})
-    return {"rho": rho, "scales": per_scale, "halo_scale": halo_scale, "halo_root": halo_root}
+    return {"rho": rhos[sizes[0]], "rhos": [rhos[size] for size in sizes], "grids": sizes, "scales": per_scale,
+            "halo_scale": halo_scale, "halo_root": halo_root}
 
 
 # --------------------------------------------------------------------------

@@ -83,6 +83,72 @@ def test_bookkeeping_by_brute_force(seed, dens_th, pth):
     assert len(set(claimed) - {-1}) >= 2 or seed != 2  # the first case claims at more than one scale
 
 
+def test_one_grid_per_scale_given_explicitly_is_the_default():
+    pos, L, n = _box(6), 64.0, 32
+    kws = [n / (1000.0 * a) for a in (3.0, 1.5)]
+    a = O.identify(pos, L, n, kws, 2.0, 15)
+    b = O.identify(pos, L, n, kws, 2.0, 15, grids=[n, n])
+    assert (a["halo_scale"] == b["halo_scale"]).all() and (a["halo_root"] == b["halo_root"]).all()
+    assert b["grids"] == [n, n]
+
+
+@pytest.mark.parametrize("seed,grids,scales,dens_th,pth", [
+    (7, (24, 32, 40), (2.5, 2.0, 1.5), 1.0, 5),      # finer grid per smaller scale, as the flowchart's N_g
+    (9, (40, 30, 36), (3.0, 2.2, 1.6), 1.0, 5),      # not monotone: the comparison still crosses grids
+])
+def test_per_scale_grids_by_brute_force(seed, grids, scales, dens_th, pth):
+    # scales given in cells of a 32^3 grid; each scale is deposited, transformed,
+    # segmented and labelled on its own grid, and step 8 compares across grids
+    pos, L = _box(seed), 64.0
+    kws = [32 / (1000.0 * a) for a in scales]
+    r = O.identify(pos, L, 32, kws, dens_th, pth, grids=list(grids))
+    assert r["grids"] == list(grids)
+    npt = len(pos)
+    claimed = [-1] * npt
+    root_of = [-1] * npt
+    fields = [O.cwt(O.deposit(pos, L, g), L, kw) for g, kw in zip(grids, kws)]
+    for i, (g, kw) in enumerate(zip(grids, kws)):
+        sc = r["scales"][i]
+        cell = O.segment(fields[i])
+        raw = O.label(pos, L, g, cell).tolist()
+        roots = O.maxima(fields[i]).tolist()
+        assert sc["maxima"].tolist() == roots
+        cells, parts = {}, {}
+        for v in cell.ravel().tolist():
+            if v >= 0:
+                cells[v] = cells.get(v, 0) + 1
+        for p in range(npt):
+            if claimed[p] < 0 and raw[p] >= 0:
+                parts[raw[p]] = parts.get(raw[p], 0) + 1
+        nxt = fields[i + 1] if i + 1 < len(grids) else np.zeros_like(fields[i])
+        gn = nxt.shape[0]
+        ppos, pval = O.peaks(fields[i], roots, L) if roots else (np.zeros((0, 3)), np.zeros(0))
+        _, _, l1b, l2b = O._peak_fits(fields[i], roots) if roots else (None, None, [], [])
+        keep = {}
+        for k, rt in enumerate(roots):
+            v = pval[k] + 0.3125 * (2 * l2b[k] - l1b[k]) * (1 - (g / gn) ** 2)  # App. B, 3/5 removed
+            x, y, z = (int(math.floor(ppos[k][a] / (L / gn) + 0.5)) % gn for a in range(3))
+            near = max(nxt[(z + a) % gn, (y + b) % gn, (x + c) % gn]
+                       for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1))
+            p_, c_ = parts.get(rt, 0), cells.get(rt, 0)
+            keep[rt] = (v > near and p_ * g ** 3 >= dens_th * c_ * npt and p_ >= pth)
+            assert sc["particles"][k] == p_ and sc["cells"][k] == c_
+            assert bool(sc["keep"][k]) == keep[rt]
+        for p in range(npt):
+            if claimed[p] < 0 and raw[p] >= 0 and keep[raw[p]]:
+                claimed[p] = i
+                root_of[p] = raw[p]
+    assert r["halo_scale"].tolist() == claimed
+    assert r["halo_root"].tolist() == root_of
+    assert sum(bool(sc["keep"].any()) for sc in r["scales"]) >= 2  # more than one scale keeps groups
+
+
+def test_paper_grid_schedule():
+    # step 1 / the flowchart: N_g = Int(400 k_w + 150)
+    for kw, ng in ((0.1, 190), (0.5, 350), (1.0, 550), (2.5, 1150), (0.0123, 154)):
+        assert O.paper_grid(kw) == ng
+
+
 def test_compact_and_extended_halos_claimed_at_their_scales():
     # blob response at its centre peaks at scale length a* = s / sqrt(6/7):
     # extended s = 4 Mpc/h -> a* = 2.2 cells (dx = 2): claimed at a = 2 cells,
