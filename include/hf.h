@@ -1,8 +1,9 @@
 /*
- * hf.h - C ABI of the MI355X (gfx950) single-scale CWT halo-finding path.
+ * hf.h - C ABI of the MI355X (gfx950) CWT halo-finding path.
  *
- * The path is the per-scale core of CWTHF (Li, Wang & He, arXiv:2501.10622),
- * Sec. 2, identification steps 2-6:
+ * The path is the data-parallel core of CWTHF (Li, Wang & He,
+ * arXiv:2501.10622), Sec. 2, identification steps 2-8 (the self-boundness
+ * check of steps 9-10 is not part of it):
  *
  *   hf_deposit  step 2  cloud-in-cell mass on a periodic n^3 grid, Eq. (1)
  *   hf_cwt      step 3  grid CWT with the Mexican-hat wavelet, Eqs. (2)-(4)
@@ -17,6 +18,7 @@
  *   hf_cross_scale  step 8  maxima that are also maxima across scale
  *   hf_identify steps 2-8   the loop over scales, largest first, that claims
  *                       particles for halos (Sec. 2 and its flowchart)
+ *   hf_identify_grids  the same loop with every scale on its own grid N_g
  *
  * Conventions shared by every call
  * --------------------------------
@@ -28,7 +30,12 @@
  *    (z*n + y)*n + x (int32, so n <= 1024).
  *  - Positions are [np][3] rows (x, y, z) in the units of box_len, FP32 or
  *    FP64 (hf_dtype).  Positions outside [0, box_len) wrap periodically.
- *  - Supported n: n = 2^a 3^b with a >= 1, 8 <= n <= 1024.
+ *  - Supported n: n = 2^a 3^b with a >= 1, 8 <= n <= 1024 wherever the FFT
+ *    transform runs (hf_cwt with SAMPLED or ANALYTIC, the batched and
+ *    multi-scale transforms, the one-call pipelines with those kernels, and
+ *    hf_workspace_size with HF_STAGE_CWT); any 8 <= n <= 1024 for the other
+ *    stages and for the pipelines with HF_KERNEL_STENCIL (the flowchart's
+ *    per-scale grids N_g are arbitrary integers).
  *    frac_bits (B, CIC fraction bits per axis) in [8, 20].
  *  - Workspaces are device buffers of at least hf_workspace_size() bytes,
  *    256-byte aligned.  One workspace may be reused by every stage in turn.
@@ -403,6 +410,49 @@ hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype 
                       float tau, int64_t *rho, int32_t count, const hf_scale_job *scales,
                       const hf_identify_groups *groups, double dens_th, int64_t particle_th, int32_t *halo_scale,
                       int32_t *halo_root, void *ws, size_t ws_bytes);
+
+/* Sec. 2's identification loop on per-scale grids (step 1 and the flowchart:
+ * each scale is gridded afresh, N_g = Int(400 k_w + 150) points per side).
+ * Scale j (scales[] in increasing kw, so the largest scale length comes first)
+ * deposits the np particles on its own n_j^3 grid (any 8 <= n_j <= 1024) into
+ * rho, takes the grid CWT by the paper's truncated stencil (Sec. 2.1; as
+ * hf_cwt_stencil with hf_stencil_half_width(kw, n_j), which is Table 1's
+ * count when n_j = N_g), then its maxima (capacity max_cap) and segmentation.
+ * Then, scale by scale, steps 6-8 as hf_identify does in input order: the
+ * step-8 flags of the scale's maxima against the next scale's field on that
+ * scale's own grid (hf_cross_scale, whose App. B cube-size term corrects for
+ * the two grid spacings; after the last scale the zero grid of its own size),
+ * the particles no earlier scale claimed take their cell's label, the groups'
+ * cell and particle counts and the step-7/8 decision (hf_groups' test with n_j,
+ * dens_th, particle_th), and the kept groups claim their particles.
+ * particle_label [np] receives the scale's filtered labels (-1 unless the
+ * particle is claimed at this scale); halo_scale/halo_root [np] as hf_identify.
+ * All pointers are device pointers.  Errors: HF_ERR_ARG for a null required
+ * pointer, scales not in increasing kw, count outside 1..HF_CWT_BATCH_MAX, a
+ * max_cap above n_j^3, a stencil half-width above HF_STENCIL_MAX_HALF_WIDTH;
+ * HF_ERR_SIZE for an n_j outside [8, 1024] or frac_bits outside [8, 20].
+ * Workspace: hf_identify_grids_ws_size (the largest scale's stage workspace,
+ * its group counters and one byte per maximum of the largest list). */
+typedef struct {
+    double kw;                 /* scale k_w = w box_len / 1000 */
+    int32_t n;                 /* this scale's grid points per side */
+    int64_t *rho;              /* [n^3] int64: CIC density on this grid */
+    float *cwt;                /* [n^3] FP32 grid CWT */
+    int32_t *max_idx;          /* [max_cap] sorted maxima */
+    int64_t max_cap;
+    int64_t *d_count;          /* device int64: number of maxima */
+    int32_t *cell_label;       /* [n^3] */
+    int32_t *particle_label;   /* [np] */
+    uint32_t *group_particles; /* [max_cap] */
+    uint32_t *group_cells;     /* [max_cap] */
+    uint8_t *group_keep;       /* [max_cap] */
+} hf_grid_scale;
+hf_status hf_identify_grids_ws_size(double box_len, int32_t frac_bits, int64_t np, int32_t count,
+                                    const hf_grid_scale *scales, size_t *bytes);
+hf_status hf_identify_grids(hf_ctx *ctx, double box_len, int32_t frac_bits, const void *pos, hf_dtype dtype,
+                            int64_t np, float tau, int32_t count, const hf_grid_scale *scales, double dens_th,
+                            int64_t particle_th, int32_t *halo_scale, int32_t *halo_root, void *ws,
+                            size_t ws_bytes);
 
 /* Serving form of steps 2-6 for `count` (1..HF_CWT_BATCH_MAX) boxes of the same
  * grid size n: per-box deposits, ONE batched transform (hf_cwt_batch) for the

@@ -190,7 +190,7 @@ extern "C" hf_status hf_sync(hf_ctx *ctx) {
 
 extern "C" hf_status hf_workspace_size(const hf_box *box, int64_t np, int stage_mask, size_t *bytes) {
     if (!bytes || np < 0) return HF_ERR_ARG;
-    hf_status s = check_box(box);
+    hf_status s = (stage_mask & HF_STAGE_CWT) ? check_box(box) : check_box_grid(box);
     if (s != HF_OK) return s;
     if (stage_mask & ~(HF_STAGE_ALL | HF_STAGE_GROUPS | HF_STAGE_STENCIL)) return HF_ERR_ARG;
     // deposit + label: the deposit's particle order is kept for the labels in
@@ -217,11 +217,10 @@ extern "C" hf_status hf_workspace_size(const hf_box *box, int64_t np, int stage_
 // Steps 2-6 as hf_find_halos, with the device's scratch array as workspace.
 extern "C" hf_status hf_find_halos_noalloc(hf_ctx *ctx, const hf_box *box, const hf_job *job) {
     if (!ctx || !job) return HF_ERR_ARG;
-    hf_status s = check_box(box);
+    hf_status s = check_box_for(box, job->kernel);
     if (s != HF_OK) return s;
     size_t need = 0;
-    s = hf_workspace_size(box, job->np, HF_STAGE_ALL | (job->kernel == HF_KERNEL_STENCIL ? HF_STAGE_STENCIL : 0),
-                          &need);
+    s = hf_workspace_size(box, job->np, pipeline_stages(job->kernel), &need);
     if (s != HF_OK) return s;
     if (need > HF_NOALLOC_SCRATCH_BYTES) return HF_ERR_WORKSPACE;
     if (!ctx->scratch) return HF_ERR_DEVICE;

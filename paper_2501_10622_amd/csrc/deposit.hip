@@ -130,7 +130,7 @@ extern "C" hf_status hf_deposit(hf_ctx *ctx, const hf_box *box, const void *pos,
                                 int64_t *rho, void *ws, size_t ws_bytes) {
     if (!ctx || !rho || np < 0 || (np > 0 && !pos)) return HF_ERR_ARG;
     if (dtype != HF_F32 && dtype != HF_F64) return HF_ERR_ARG;
-    hf_status s = check_box(box);
+    hf_status s = check_box_grid(box);
     if (s != HF_OK) return s;
     s = check_ws(ws, ws_bytes, deposit_ws_bytes(*box, np));
     if (s != HF_OK) return s;
@@ -159,7 +159,7 @@ extern "C" hf_status hf_label(hf_ctx *ctx, const hf_box *box, const void *pos, h
                               const int32_t *cell_label, int32_t *particle_label) {
     if (!ctx || !cell_label || np < 0 || (np > 0 && (!pos || !particle_label))) return HF_ERR_ARG;
     if (dtype != HF_F32 && dtype != HF_F64) return HF_ERR_ARG;
-    hf_status s = check_box(box);
+    hf_status s = check_box_grid(box);
     if (s != HF_OK) return s;
     if (np == 0) return HF_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;

@@ -510,10 +510,11 @@ hf_status hf::groups_filter(hf_ctx *ctx, const hf_box &box, const int32_t *in, i
 }
 
 hf_status hf::cross_scale_dev(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count,
-                              int64_t cap, const float *c_scale, const float *c_smaller, uint8_t *pass) {
+                              int64_t cap, const float *c_scale, int n_smaller, const float *c_smaller,
+                              uint8_t *pass) {
     if (cap <= 0) return HF_OK;
     HF_LAUNCH(ctx, K_GROUP_CROSS, cross_scale_kernel, dim3(grid_of(ctx, cap, GB)), dim3(GB), 0, ctx->stream, roots,
-              d_count, cap, box.n, c_scale, box.n, c_smaller, pass, ctx->d_status);
+              d_count, cap, box.n, c_scale, n_smaller, c_smaller, pass, ctx->d_status);
     return launch_status();
 }
 
@@ -543,7 +544,7 @@ hf_status hf::claim_take(hf_ctx *ctx, const int32_t *label, int32_t *halo_scale,
 extern "C" hf_status hf_peaks(hf_ctx *ctx, const hf_box *box, const float *cwt, const int32_t *roots, int64_t nroots,
                               double *pos, double *value) {
     if (!ctx) return HF_ERR_ARG;
-    hf_status s = check_box(box);
+    hf_status s = check_box_grid(box);
     if (s != HF_OK) return s;
     if (nroots < 0 || nroots > cells_of(*box)) return HF_ERR_ARG;
     if (nroots == 0) return HF_OK;
@@ -558,7 +559,7 @@ extern "C" hf_status hf_cross_scale(hf_ctx *ctx, const hf_box *box, const int32_
                                     const float *cwt_scale, int32_t n_smaller, const float *cwt_smaller,
                                     uint8_t *pass) {
     if (!ctx) return HF_ERR_ARG;
-    hf_status s = check_box(box);
+    hf_status s = check_box_grid(box);
     if (s != HF_OK) return s;
     if (n_smaller < 1 || n_smaller > 1024) return HF_ERR_SIZE;
     if (nroots < 0 || nroots > cells_of(*box)) return HF_ERR_ARG;
@@ -577,7 +578,7 @@ extern "C" hf_status hf_groups(hf_ctx *ctx, const hf_box *box, int64_t np, const
                                uint8_t *group_keep, int32_t *cell_label_out, int32_t *particle_label_out, void *ws,
                                size_t ws_bytes) {
     if (!ctx || !cell_label) return HF_ERR_ARG;
-    hf_status s = check_box(box);
+    hf_status s = check_box_grid(box);
     if (s != HF_OK) return s;
     const int64_t ncells = cells_of(*box);
     if (np < 0 || np > int64_t(UINT32_MAX) || nroots < 0 || nroots > ncells) return HF_ERR_ARG;

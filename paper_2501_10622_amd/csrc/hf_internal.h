@@ -107,6 +107,27 @@ inline hf_status check_box(const hf_box *box) {
     return HF_OK;
 }
 
+// The stages that use no FFT (deposit, stencil transform, maxima,
+// segmentation, labels, groups, peaks, cross-scale) take any 8 <= n <= 1024:
+// the flowchart's per-scale grids N_g = Int(400 k_w + 150) are arbitrary
+// integers.  Grids their tiled paths cannot cover take the direct ones.
+inline hf_status check_box_grid(const hf_box *box) {
+    if (!box) return HF_ERR_ARG;
+    if (box->n < 8 || box->n > 1024) return HF_ERR_SIZE;
+    if (box->frac_bits < 8 || box->frac_bits > 20) return HF_ERR_SIZE;
+    if (!(box->box_len > 0.0) || !(box->box_len < 1e300)) return HF_ERR_ARG;
+    return HF_OK;
+}
+
+// The one-call pipelines: the FFT transform needs n = 2^a 3^b, the stencil
+// transform any grid; their stage sets (the stencil's workspace replaces the FFT's).
+inline hf_status check_box_for(const hf_box *box, hf_kernel k) {
+    return k == HF_KERNEL_STENCIL ? check_box_grid(box) : check_box(box);
+}
+inline int pipeline_stages(hf_kernel k) {
+    return k == HF_KERNEL_STENCIL ? ((HF_STAGE_ALL & ~HF_STAGE_CWT) | HF_STAGE_STENCIL) : HF_STAGE_ALL;
+}
+
 inline hf_status check_ws(void *ws, size_t ws_bytes, size_t need) {
     if (need == 0) return HF_OK;
     if (!ws || ws_bytes < need) return HF_ERR_WORKSPACE;
@@ -199,10 +220,11 @@ size_t cwt_ws_bytes(const hf_box &box);
 size_t maxima_ws_bytes(const hf_box &box);
 size_t segment_ws_bytes(const hf_box &box);
 size_t groups_ws_bytes(const hf_box &box);
-// Step 8 with the maxima count on the device (cap = the list's capacity);
-// c_smaller null compares with the all-zero grid.
+// Step 8 with the maxima count on the device (cap = the list's capacity); the
+// smaller scale's field is on an n_smaller^3 grid over the same box; c_smaller
+// null compares with the all-zero grid.
 hf_status cross_scale_dev(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count, int64_t cap,
-                          const float *c_scale, const float *c_smaller, uint8_t *pass);
+                          const float *c_scale, int n_smaller, const float *c_smaller, uint8_t *pass);
 // The identification loop's particle bookkeeping (halo_scale / halo_root).
 hf_status claim_init(hf_ctx *ctx, int32_t *halo_scale, int32_t *halo_root, int64_t np);
 // After the decision: labels of claimed particles and of disposed groups

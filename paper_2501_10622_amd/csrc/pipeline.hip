@@ -5,11 +5,10 @@ using namespace hf;
 
 extern "C" hf_status hf_find_halos(hf_ctx *ctx, const hf_box *box, const hf_job *job, void *ws, size_t ws_bytes) {
     if (!ctx || !job) return HF_ERR_ARG;
-    hf_status s = check_box(box);
+    hf_status s = check_box_for(box, job->kernel);
     if (s != HF_OK) return s;
     size_t need = 0;
-    s = hf_workspace_size(box, job->np, HF_STAGE_ALL | (job->kernel == HF_KERNEL_STENCIL ? HF_STAGE_STENCIL : 0),
-                          &need);
+    s = hf_workspace_size(box, job->np, pipeline_stages(job->kernel), &need);
     if (s != HF_OK) return s;
     s = check_ws(ws, ws_bytes, need);
     if (s != HF_OK) return s;
@@ -53,7 +52,7 @@ extern "C" hf_status hf_find_halos(hf_ctx *ctx, const hf_box *box, const hf_job 
 extern "C" hf_status hf_find_halos_filtered(hf_ctx *ctx, const hf_box *box, const hf_job *job,
                                            const hf_group_filter *gf, void *ws, size_t ws_bytes) {
     if (!ctx || !job || !gf) return HF_ERR_ARG;
-    hf_status s = check_box(box);
+    hf_status s = check_box_for(box, job->kernel);
     if (s != HF_OK) return s;
     const int64_t ncells = int64_t(box->n) * box->n * box->n;
     if (!(gf->dens_th >= 0.0) || !(gf->dens_th < 1e300) || gf->particle_th < 0 || job->np > int64_t(UINT32_MAX))
@@ -61,9 +60,7 @@ extern "C" hf_status hf_find_halos_filtered(hf_ctx *ctx, const hf_box *box, cons
     if (job->max_cap > 0 && (!gf->group_particles || !gf->group_cells || !gf->group_keep)) return HF_ERR_ARG;
     if (job->max_cap > ncells) return HF_ERR_ARG;
     size_t need = 0;
-    s = hf_workspace_size(box, job->np,
-                          HF_STAGE_ALL | HF_STAGE_GROUPS | (job->kernel == HF_KERNEL_STENCIL ? HF_STAGE_STENCIL : 0),
-                          &need);
+    s = hf_workspace_size(box, job->np, pipeline_stages(job->kernel) | HF_STAGE_GROUPS, &need);
     if (s != HF_OK) return s;
     s = check_ws(ws, ws_bytes, need);
     if (s != HF_OK) return s;
@@ -302,7 +299,7 @@ extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos
         const hf_identify_groups &gj = groups[j];
         const float *next = j + 1 < count ? scales[j + 1].cwt : nullptr;
         int32_t *lab = order ? lab2 : sj.particle_label;
-        s = cross_scale_dev(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, sj.cwt, next, pass);
+        s = cross_scale_dev(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, sj.cwt, box->n, next, pass);
         if (s == HF_OK)
             s = order ? label_tiles(ctx, *box, np, po, sj.cell_label, sw, nullptr)
                       : hf_label(ctx, box, pos, dtype, np, sj.cell_label, sj.particle_label);
@@ -318,6 +315,109 @@ extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos
             s = claim_filter(ctx, *box, lab, cs, order ? nullptr : halo_root, np, g, sj.max_cap > 0, j);
         if (s == HF_OK && order) s = label_back(ctx, *box, np, po, sj.particle_label, sw, nullptr);
         if (s == HF_OK && order) s = claim_take(ctx, sj.particle_label, halo_scale, halo_root, np, j);
+    }
+    return s;
+}
+
+// Sec. 2's identification loop on per-scale grids (step 1 and the flowchart's
+// N_g): every scale deposits the particles on its own grid and takes the
+// paper's truncated-stencil transform there; then, largest scale first, the
+// flowchart's pair of grids as in hf_identify, in input order, with the
+// cross-scale check between the two scales' grids.
+namespace {
+struct GridsLayout {
+    size_t shared, groups, pass, total;
+};
+
+hf_status grids_layout(double box_len, int32_t frac_bits, int64_t np, int32_t count, const hf_grid_scale *scales,
+                       GridsLayout &L) {
+    if (!scales || count < 1 || count > HF_CWT_BATCH_MAX || np < 0) return HF_ERR_ARG;
+    size_t shared = 0, groups = 0;
+    int64_t cap = 0;
+    for (int j = 0; j < count; ++j) {
+        const hf_box b{scales[j].n, frac_bits, box_len};
+        hf_status s = check_box_grid(&b);
+        if (s != HF_OK) return s;
+        if (scales[j].max_cap < 0) return HF_ERR_ARG;
+        size_t need = 0;
+        s = hf_workspace_size(&b, np, HF_STAGE_DEPOSIT | HF_STAGE_STENCIL | HF_STAGE_MAXIMA | HF_STAGE_SEGMENT,
+                              &need);
+        if (s != HF_OK) return s;
+        shared = need > shared ? need : shared;
+        groups = groups_ws_bytes(b) > groups ? groups_ws_bytes(b) : groups;
+        cap = scales[j].max_cap > cap ? scales[j].max_cap : cap;
+    }
+    L.shared = 0;
+    L.groups = align_up(shared);
+    L.pass = L.groups + align_up(groups);
+    L.total = L.pass + align_up(size_t(cap));
+    return HF_OK;
+}
+}  // namespace
+
+extern "C" hf_status hf_identify_grids_ws_size(double box_len, int32_t frac_bits, int64_t np, int32_t count,
+                                              const hf_grid_scale *scales, size_t *bytes) {
+    if (!bytes) return HF_ERR_ARG;
+    GridsLayout L{};
+    hf_status s = grids_layout(box_len, frac_bits, np, count, scales, L);
+    if (s == HF_OK) *bytes = L.total;
+    return s;
+}
+
+extern "C" hf_status hf_identify_grids(hf_ctx *ctx, double box_len, int32_t frac_bits, const void *pos,
+                                       hf_dtype dtype, int64_t np, float tau, int32_t count,
+                                       const hf_grid_scale *scales, double dens_th, int64_t particle_th,
+                                       int32_t *halo_scale, int32_t *halo_root, void *ws, size_t ws_bytes) {
+    if (!ctx || !scales || count < 1 || count > HF_CWT_BATCH_MAX) return HF_ERR_ARG;
+    if (np < 0 || np > int64_t(UINT32_MAX) || (np > 0 && (!pos || !halo_scale || !halo_root))) return HF_ERR_ARG;
+    if ((dtype != HF_F32 && dtype != HF_F64) || tau != tau) return HF_ERR_ARG;
+    if (!(dens_th >= 0.0) || !(dens_th < 1e300) || particle_th < 0) return HF_ERR_ARG;
+    GridsLayout L{};
+    hf_status s = grids_layout(box_len, frac_bits, np, count, scales, L);
+    if (s != HF_OK) return s;
+    int32_t hw[HF_CWT_BATCH_MAX];
+    for (int j = 0; j < count; ++j) {
+        const hf_grid_scale &sj = scales[j];
+        if (j > 0 && !(sj.kw > scales[j - 1].kw)) return HF_ERR_ARG;  // largest scale first
+        if (!sj.rho || !sj.cwt || !sj.d_count || !sj.cell_label || (sj.max_cap > 0 && !sj.max_idx) ||
+            (np > 0 && !sj.particle_label) || !(sj.kw > 0.0) || !(sj.kw < 1e300))
+            return HF_ERR_ARG;
+        if (sj.max_cap > int64_t(sj.n) * sj.n * sj.n) return HF_ERR_ARG;
+        if (sj.max_cap > 0 && (!sj.group_particles || !sj.group_cells || !sj.group_keep)) return HF_ERR_ARG;
+        hw[j] = stencil_half_width(sj.kw, sj.n);
+        if (hw[j] < 0) return HF_ERR_ARG;
+    }
+    s = check_ws(ws, ws_bytes, L.total);
+    if (s != HF_OK) return s;
+    if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
+    char *w0 = static_cast<char *>(ws);
+    const size_t sb = L.groups;  // the shared stage region
+    // steps 2-5 of every scale on its own grid
+    for (int j = 0; j < count && s == HF_OK; ++j) {
+        const hf_grid_scale &sj = scales[j];
+        const hf_box b{sj.n, frac_bits, box_len};
+        s = hf_deposit(ctx, &b, pos, dtype, np, sj.rho, w0, sb);
+        if (s == HF_OK) s = hf_cwt_stencil(ctx, &b, sj.rho, sj.kw, hw[j], sj.cwt, w0, sb);
+        if (s == HF_OK)
+            s = maxima_segment(ctx, b, sj.cwt, tau, sj.max_idx, sj.max_cap, sj.d_count, sj.cell_label, w0, sb);
+    }
+    if (s != HF_OK) return s;
+    uint8_t *pass = reinterpret_cast<uint8_t *>(w0 + L.pass);
+    s = claim_init(ctx, halo_scale, halo_root, np);
+    for (int j = 0; j < count && s == HF_OK; ++j) {
+        const hf_grid_scale &sj = scales[j];
+        const hf_box b{sj.n, frac_bits, box_len};
+        const GroupCounters g = group_counters_at(b, w0 + L.groups);
+        const bool last = j + 1 == count;
+        s = cross_scale_dev(ctx, b, sj.max_idx, sj.d_count, sj.max_cap, sj.cwt, last ? sj.n : scales[j + 1].n,
+                            last ? nullptr : scales[j + 1].cwt, pass);
+        if (s == HF_OK) s = hf_label(ctx, &b, pos, dtype, np, sj.cell_label, sj.particle_label);
+        if (s == HF_OK) s = groups_count_cells(ctx, b, sj.max_idx, sj.d_count, sj.max_cap, sj.cell_label, g);
+        if (s == HF_OK && sj.max_cap > 0) s = groups_count_particles(ctx, b, sj.particle_label, np, g, halo_scale);
+        if (s == HF_OK)
+            s = groups_decide(ctx, b, sj.max_idx, sj.d_count, sj.max_cap, g, dens_th, np, particle_th, pass,
+                              sj.group_particles, sj.group_cells, sj.group_keep);
+        if (s == HF_OK) s = claim_filter(ctx, b, sj.particle_label, halo_scale, halo_root, np, g, sj.max_cap > 0, j);
     }
     return s;
 }

@@ -883,7 +883,7 @@ extern "C" hf_status hf_maxima(hf_ctx *ctx, const hf_box *box, const float *cwt,
                                int64_t max_cap, int64_t *d_count, void *ws, size_t ws_bytes) {
     if (!ctx || !cwt || !d_count || max_cap < 0 || (max_cap > 0 && !max_idx)) return HF_ERR_ARG;
     if (tau != tau) return HF_ERR_ARG;
-    hf_status s = check_box(box);
+    hf_status s = check_box_grid(box);
     if (s != HF_OK) return s;
     const MaximaLayout L = maxima_layout(box->n);
     s = check_ws(ws, ws_bytes, L.total);
@@ -908,7 +908,7 @@ extern "C" hf_status hf_segment(hf_ctx *ctx, const hf_box *box, const float *cwt
                                 void *ws, size_t ws_bytes) {
     if (!ctx || !cwt || !cell_label) return HF_ERR_ARG;
     if (tau != tau) return HF_ERR_ARG;
-    hf_status s = check_box(box);
+    hf_status s = check_box_grid(box);
     if (s != HF_OK) return s;
     const SegmentLayout L = segment_layout(box->n);
     s = check_ws(ws, ws_bytes, L.total);

@@ -326,7 +326,7 @@ extern "C" hf_status hf_cwt_stencil(hf_ctx *ctx, const hf_box *box, const int64_
     if (!ctx || !rho || !cwt) return HF_ERR_ARG;
     if (!(kw > 0.0) || !std::isfinite(kw)) return HF_ERR_ARG;
     if (half_width < 0 || half_width > HF_STENCIL_MAX_HALF_WIDTH) return HF_ERR_ARG;
-    hf_status s = check_box(box);
+    hf_status s = check_box_grid(box);
     if (s != HF_OK) return s;
     const int n = box->n, h = half_width;
     const StencilLayout L = stencil_layout(n);

@@ -28,7 +28,7 @@ EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_
            "hf_find_halos_filtered", "hf_cwt_scales",
            "hf_find_halos_scales_ws_size", "hf_find_halos_scales", "hf_cross_scale", "hf_peaks",
            "hf_cwt_stencil", "hf_stencil_half_width", "hf_identify_ws_size", "hf_identify",
-           "hf_find_halos_noalloc")
+           "hf_find_halos_noalloc", "hf_identify_grids_ws_size", "hf_identify_grids")
 CWT_BATCH_MAX = 32
 STAGE_ALL = 31
 STAGE_GROUPS = 32
@@ -67,6 +67,14 @@ class ScaleJob(ctypes.Structure):
 
 class IdentifyGroups(ctypes.Structure):
     _fields_ = [("group_particles", ctypes.c_void_p), ("group_cells", ctypes.c_void_p),
+                ("group_keep", ctypes.c_void_p)]
+
+
+class GridScale(ctypes.Structure):
+    _fields_ = [("kw", ctypes.c_double), ("n", ctypes.c_int32), ("rho", ctypes.c_void_p), ("cwt", ctypes.c_void_p),
+                ("max_idx", ctypes.c_void_p), ("max_cap", ctypes.c_int64), ("d_count", ctypes.c_void_p),
+                ("cell_label", ctypes.c_void_p), ("particle_label", ctypes.c_void_p),
+                ("group_particles", ctypes.c_void_p), ("group_cells", ctypes.c_void_p),
                 ("group_keep", ctypes.c_void_p)]
 
 
@@ -123,6 +131,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                                     ctypes.POINTER(ScaleJob), vp, sz]),
             "hf_find_halos": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job), vp, sz]),
             "hf_find_halos_noalloc": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job)]),
+            "hf_identify_grids_ws_size": (ctypes.c_int, [dbl, i32, i64, i32, ctypes.POINTER(GridScale),
+                                                         ctypes.POINTER(sz)]),
+            "hf_identify_grids": (ctypes.c_int, [vp, dbl, i32, vp, i32, i64, flt, i32, ctypes.POINTER(GridScale),
+                                                 dbl, i64, vp, vp, vp, sz]),
             "hf_identify_ws_size": (ctypes.c_int, [bp, i64, i32, ctypes.POINTER(ScaleJob), ctypes.POINTER(sz)]),
             "hf_identify": (ctypes.c_int, [vp, bp, vp, ctypes.c_int, i64, ctypes.c_int, flt, vp, i32,
                                            ctypes.POINTER(ScaleJob), ctypes.POINTER(IdentifyGroups), dbl, i64, vp,
@@ -531,8 +543,8 @@ def job_buffers(n: int, np_: int, device, with_cwt_ws: bool = True, frac_bits: i
     stages = STAGE_ALL if with_cwt_ws else (STAGE_DEPOSIT | STAGE_MAXIMA | STAGE_SEGMENT)
     if with_groups:
         stages |= STAGE_GROUPS
-    if with_stencil:
-        stages |= STAGE_STENCIL
+    if with_stencil:  # the stencil transform's workspace instead of the FFT's (any n)
+        stages = (stages & ~STAGE_CWT) | STAGE_STENCIL
     need = workspace_size(n, 1.0, np_, stages, frac_bits)
     cap = ((n + 1) // 2) ** 3
     extra = {}
@@ -663,6 +675,64 @@ def identify_async(pos: torch.Tensor, box_len: float, n: int, kws, bufs: dict, d
                                       KERNELS[kernel], float(tau), _ptr(bufs["rho"]), count, jobs, groups,
                                       float(dens_th), int(particle_th), _ptr(bufs["halo_scale"]),
                                       _ptr(bufs["halo_root"]), _ptr(bufs["ws"]), bufs["ws"].numel()), "hf_identify")
+
+
+def paper_grid(kw: float) -> int:
+    """The flowchart's grid size for a scale, N_g = Int(400 k_w + 150)."""
+    return int(400.0 * kw + 150.0)
+
+
+def _grid_scales(kws, bufs):
+    return (GridScale * len(kws))(*[GridScale(float(kw), int(bufs["grids"][j]), bufs["rho"][j].data_ptr(),
+                                              bufs["cwt"][j].data_ptr(), bufs["maxima"][j].data_ptr(),
+                                              bufs["maxima"][j].numel(), bufs["count"][j].data_ptr(),
+                                              bufs["cell_label"][j].data_ptr(), bufs["particle_label"][j].data_ptr(),
+                                              bufs["group_particles"][j].data_ptr(),
+                                              bufs["group_cells"][j].data_ptr(), bufs["group_keep"][j].data_ptr())
+                                    for j, kw in enumerate(kws)])
+
+
+def identify_grids_buffers(grids, np_: int, device, box_len: float = 1.0, frac_bits: int = 15) -> dict:
+    """Outputs (one entry per scale, each on its own grid size in ``grids``) and
+    workspace for identify_grids_async."""
+    count = len(grids)
+    caps = [((g + 1) // 2) ** 3 for g in grids]
+    bufs = {
+        "grids": [int(g) for g in grids],
+        "rho": [torch.empty((g, g, g), dtype=torch.int64, device=device) for g in grids],
+        "cwt": [torch.empty((g, g, g), dtype=torch.float32, device=device) for g in grids],
+        "maxima": [torch.empty(c, dtype=torch.int32, device=device) for c in caps],
+        "count": [torch.empty(1, dtype=torch.int64, device=device) for _ in grids],
+        "cell_label": [torch.empty((g, g, g), dtype=torch.int32, device=device) for g in grids],
+        "particle_label": [torch.empty(max(np_, 1), dtype=torch.int32, device=device) for _ in grids],
+        "group_particles": [torch.empty(c, dtype=torch.int32, device=device) for c in caps],
+        "group_cells": [torch.empty(c, dtype=torch.int32, device=device) for c in caps],
+        "group_keep": [torch.empty(c, dtype=torch.uint8, device=device) for c in caps],
+        "halo_scale": torch.empty(max(np_, 1), dtype=torch.int32, device=device),
+        "halo_root": torch.empty(max(np_, 1), dtype=torch.int32, device=device),
+    }
+    out = ctypes.c_size_t()
+    jobs = _grid_scales([0.1 * (j + 1) for j in range(count)], bufs)
+    _check(load_library().hf_identify_grids_ws_size(float(box_len), int(frac_bits), int(np_), count, jobs,
+                                                    ctypes.byref(out)), "hf_identify_grids_ws_size")
+    bufs["ws"] = torch.empty(max(out.value, 256), dtype=torch.uint8, device=device)
+    return bufs
+
+
+def identify_grids_async(pos: torch.Tensor, box_len: float, kws, bufs: dict, dens_th: float = 4.0,
+                         particle_th: int = 15, frac_bits: int = 15, tau: float = 0.0, ctx=None):
+    """Enqueue Sec. 2's identification loop with every scale on its own grid
+    (bufs from identify_grids_buffers, e.g. with grids [paper_grid(kw) ...])."""
+    _require_cuda(pos, "pos")
+    ctx = ctx or context(pos.device.index)
+    count = len(kws)
+    if count != len(bufs["grids"]):
+        raise ValueError("one grid per scale")
+    jobs = _grid_scales(kws, bufs)
+    _check(load_library().hf_identify_grids(ctx.handle, float(box_len), int(frac_bits), _ptr(pos), _dtype_code(pos),
+                                            pos.shape[0], float(tau), count, jobs, float(dens_th), int(particle_th),
+                                            _ptr(bufs["halo_scale"]), _ptr(bufs["halo_root"]), _ptr(bufs["ws"]),
+                                            bufs["ws"].numel()), "hf_identify_grids")
 
 
 def find_halos_filtered_async(pos: torch.Tensor, box_len: float, n: int, kw: float, bufs: dict,
