@@ -38,6 +38,7 @@ __all__ = [
     "gdw_resolution", "paper_grid", "stencil_half_width", "stencil", "stencil_cwt_field", "stencil_cwt", "stencil_cwt_at",
     "neighbour_offsets", "maxima", "is_maximum_at", "parents", "segment", "follow", "ngp_nodes", "label",
     "find_halos", "group_stats", "cross_scale", "peaks", "cube_size_term", "identify", "DepositOverflow",
+    "GRAV", "self_bound",
 ]
 
 
@@ -640,11 +641,75 @@ def cross_scale(c_scale: np.ndarray, c_smaller: np.ndarray, roots) -> np.ndarray
 
 
 # --------------------------------------------------------------------------
+# steps 9-10: the self-boundness check (Sec. 2.3)
+# --------------------------------------------------------------------------
+# Newton's constant in (Mpc/h) (km/s)^2 / (M_sun/h): G M_sun / Mpc from
+# G = 6.67430e-11 m^3 kg^-1 s^-2, M_sun = 1.98841e30 kg, Mpc = 3.0856775814913673e22 m
+# (the factors of h cancel in G M / r with masses in M_sun/h and lengths in Mpc/h).
+GRAV = 6.67430e-11 * 1.98841e30 / 3.0856775814913673e22 / 1.0e6
+
+
+def self_bound(pos, vel, box_len: float, members, ref, grav_mass: float):
+    """The self-boundness check of one group (Sec. 2.3, steps 9-10), FP64.
+
+    ``members`` are the group's particle indices (ascending), ``ref`` a point
+    of the group (its root node) about which positions are unwrapped
+    periodically (minimum image), ``grav_mass`` = G m_p for the equal particle
+    mass m_p, in (Mpc/h) (km/s)^2.  Each round:
+
+      centre c = mean of the remaining members' unwrapped positions (the
+      centre of mass, equal masses), bulk velocity u = mean of their velocities;
+      r_i = |x_i - c|; in the order of increasing (r_i, member position) the
+      shells inside and at r_i act as a point mass at the centre, the shells
+      outside as shells: Phi_i = -G m [(rank_i + 1) / r_i + sum over later j
+      of 1 / r_j] (spherical symmetry); the local escape speed is
+      sqrt(-2 Phi_i), and particle i escapes if |v_i - u|^2 > -2 Phi_i.
+
+    Escaping particles are removed and the round repeats until none escapes.
+    The group is kept unless more than 40% of its particles were removed
+    (decided exactly: 5 removed > 2 N).  Readings: peculiar velocities relative to the remaining
+    members' mean, no Hubble flow; the potential of the remaining members only;
+    a member exactly at the centre (r = 0) is bound.
+
+    Returns the bound flags of the members, the kept flag and the rounds made.
+    """
+    members = np.asarray(members, dtype=np.int64).ravel()
+    n0 = members.size
+    x = np.asarray(pos, dtype=np.float64)[members]
+    v = np.asarray(vel, dtype=np.float64)[members]
+    d = x - np.asarray(ref, dtype=np.float64)
+    half = 0.5 * box_len
+    d = np.where(d >= half, d - box_len, np.where(d < -half, d + box_len, d))  # minimum image
+    alive = np.ones(n0, dtype=bool)
+    rounds = 0
+    while alive.any():
+        rounds += 1
+        idx = np.flatnonzero(alive)
+        c = d[idx].sum(axis=0) / idx.size
+        u = v[idx].sum(axis=0) / idx.size
+        r = np.sqrt(((d[idx] - c) ** 2).sum(axis=1))
+        order = np.lexsort((idx, r))  # by radius, ties by member position
+        rs = r[order]
+        with np.errstate(divide="ignore"):
+            inv = 1.0 / rs
+        outer = np.concatenate([np.cumsum(inv[::-1])[::-1][1:], [0.0]])  # sum over later shells
+        with np.errstate(divide="ignore", invalid="ignore"):
+            phi = -grav_mass * (np.arange(1, idx.size + 1) / rs + outer)
+        speed2 = ((v[idx[order]] - u) ** 2).sum(axis=1)
+        escape = speed2 > -2.0 * phi  # r = 0: -2 phi = inf, bound
+        if not escape.any():
+            break
+        alive[idx[order][escape]] = False
+    removed = n0 - int(alive.sum())
+    return alive, bool(5 * removed <= 2 * n0 and alive.any()), rounds
+
+
+# --------------------------------------------------------------------------
 # the identification loop over scales (Sec. 2 and its flowchart)
 # --------------------------------------------------------------------------
 def identify(pos, box_len: float, n: int, kws, dens_th: float = 4.0, particle_th: int = 15,
              frac_bits: int = 15, tau: float = 0.0, mode: str = "sampled", decide_dtype=np.float64,
-             grids=None) -> dict:
+             grids=None, vel=None, grav_mass: float | None = None) -> dict:
     """Steps 2-8 over the scales ``kws`` (increasing k_w: from the largest
     scale length down), without the self-boundness check of steps 9-10.
 
@@ -667,6 +732,14 @@ def identify(pos, box_len: float, n: int, kws, dens_th: float = 4.0, particle_th
     the density test count cells of its own scale's grid.  Reading: the density
     of a group counts the particles it takes at its scale against the mean of
     all particles.
+
+    With velocities ``vel`` [np][3] (km/s) and ``grav_mass`` = G m_p, steps 9
+    and 10 follow: every group kept by steps 7-8 takes the self-boundness check
+    (``self_bound``) on its particles, and only its bound particles are
+    claimed; a group that fails the check, or whose bound particles number
+    fewer than particle_th (Table 1's minimum particle number of a halo), is
+    discarded and claims none.  Particles it leaves stay free for the next
+    scales.
     """
     kws = [float(k) for k in kws]
     if not kws or any(b <= a for a, b in zip(kws, kws[1:])):
@@ -699,12 +772,25 @@ def identify(pos, box_len: float, n: int, kws, dens_th: float = 4.0, particle_th
         pl = np.where(halo_scale >= 0, -1, pl)  # only particles with no label yet
         ok = cross_scale(c, nxt, roots)
         g = group_stats(cell, pl, roots, ni, np_total, dens_th, particle_th, root_ok=ok)
-        take = g["particle_label"] >= 0
+        plab = g["particle_label"].astype(np.int64)
+        bound_keep = g["keep"].copy()
+        if vel is not None:
+            dxi = box_len / ni
+            for k in np.flatnonzero(g["keep"]):
+                rt = int(roots[k])
+                members = np.flatnonzero(plab == rt)
+                ref = np.array([rt % ni, (rt // ni) % ni, rt // (ni * ni)], dtype=np.float64) * dxi
+                bound, kept, _ = self_bound(pos, vel, box_len, members, ref, grav_mass)
+                if not kept or int(bound.sum()) < particle_th:
+                    bound_keep[k] = False
+                    bound[:] = False
+                plab[members[~bound]] = -1
+        take = plab >= 0
         halo_scale[take] = i
-        halo_root[take] = g["particle_label"][take]
+        halo_root[take] = plab[take]
         per_scale.append({"grid": ni, "cwt": c, "maxima": roots, "cell_label": cell, "cross_scale": ok,
                           "particles": g["particles"], "cells": g["cells"], "keep": g["keep"],
-                          "particle_label": g["particle_label"]})
+                          "bound_keep": bound_keep, "particle_label": plab.astype(np.int32)})
     return {"rho": rhos[sizes[0]], "rhos": [rhos[size] for size in sizes], "grids": sizes, "scales": per_scale,
             "halo_scale": halo_scale, "halo_root": halo_root}
 

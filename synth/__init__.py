@@ -103,9 +103,9 @@ def nfw_radius(gen: torch.Generator, conc: torch.Tensor) -> torch.Tensor:
     return 0.5 * (lo + hi) / conc
 
 
-def make_box(box_len: float, n_particles: int, n_halos: int, dtype: str, seed: int,
-             device="cpu", halo_frac: float = HALO_FRAC) -> torch.Tensor:
-    """Particle positions ``[n_particles, 3]`` (x, y, z) in [0, box_len)."""
+def _draw_box(box_len: float, n_particles: int, n_halos: int, seed: int, device, halo_frac: float):
+    """Unpermuted FP64 positions, halo membership and halo properties, then the
+    permutation, all from one generator stream."""
     device = torch.device(device)
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed))
@@ -119,23 +119,80 @@ def make_box(box_len: float, n_particles: int, n_halos: int, dtype: str, seed: i
     r_vir = (3.0 * counts.to(f64) / (4.0 * math.pi * DELTA_VIR * nbar)) ** (1.0 / 3.0)
 
     pos = torch.empty((n_particles, 3), dtype=f64, device=device)
+    owner = None
     if n_in_halos > 0:
         owner = torch.repeat_interleave(torch.arange(n_halos, device=device), counts)
         r = nfw_radius(gen, conc[owner]) * r_vir[owner]
         d = torch.randn((n_in_halos, 3), generator=gen, dtype=f64, device=device)
         d = d / torch.linalg.vector_norm(d, dim=1, keepdim=True).clamp_min(1e-300)
         pos[:n_in_halos] = centres[owner] + r[:, None] * d
-        del owner, r, d
+        del r, d
     n_uniform = n_particles - n_in_halos
     if n_uniform > 0:
         pos[n_in_halos:] = torch.rand((n_uniform, 3), generator=gen, dtype=f64, device=device) * box_len
     pos = torch.remainder(pos, box_len)
+    perm_gen = gen  # the permutation is the stream's last draw
+    return pos, owner, counts, r_vir, n_in_halos, perm_gen
+
+
+def _finish(pos: torch.Tensor, box_len: float, dtype: str) -> torch.Tensor:
     out = pos.to(_torch_dtype(dtype))
+    top = torch.tensor(box_len, dtype=out.dtype, device=out.device)
+    return torch.where(out >= top, out - top, out)  # values rounded up to L wrap to 0
+
+
+def make_box(box_len: float, n_particles: int, n_halos: int, dtype: str, seed: int,
+             device="cpu", halo_frac: float = HALO_FRAC) -> torch.Tensor:
+    """Particle positions ``[n_particles, 3]`` (x, y, z) in [0, box_len)."""
+    pos, owner, _, _, _, gen = _draw_box(box_len, n_particles, n_halos, seed, device, halo_frac)
+    del owner
+    out = _finish(pos, box_len, dtype)
     del pos
-    top = torch.tensor(box_len, dtype=out.dtype, device=device)
-    out = torch.where(out >= top, out - top, out)  # values rounded up to L wrap to 0
-    perm = torch.randperm(n_particles, generator=gen, device=device)
+    perm = torch.randperm(n_particles, generator=gen, device=out.device)
     return out[perm].contiguous()
+
+
+# Velocity model (for the self-boundness check of steps 9-10).  Units: km/s,
+# Mpc/h, M_sun/h.  G in (Mpc/h) (km/s)^2 / (M_sun/h); the box is at the mean
+# matter density of a flat universe with Omega_m = 0.3 (rho_crit = 2.775e11 h^2
+# M_sun / Mpc^3), which fixes the equal particle mass.
+G_MPC_KMS2_MSUN = 6.67430e-11 * 1.98841e30 / 3.0856775814913673e22 / 1.0e6
+OMEGA_M = 0.3
+RHO_CRIT = 2.775e11
+SIGMA_BULK = 300.0       # km/s per axis: each halo's bulk velocity
+SIGMA_FIELD = 400.0      # km/s per axis: the uniform background
+
+
+def particle_mass(box_len: float, n_particles: int) -> float:
+    """Equal particle mass (M_sun/h) of a box at the mean matter density."""
+    return OMEGA_M * RHO_CRIT * box_len ** 3 / n_particles
+
+
+def make_phase_box(box_len: float, n_particles: int, n_halos: int, dtype: str, seed: int, device="cpu",
+                   halo_frac: float = HALO_FRAC):
+    """Positions exactly as ``make_box`` and velocities [n_particles, 3] (km/s),
+    in the same order, plus the particle mass (M_sun/h).
+
+    A halo particle moves with its halo's bulk velocity (N(0, 300 km/s) per
+    axis) plus an isotropic Gaussian of dispersion V_vir / sqrt(3) per axis,
+    V_vir = sqrt(G M m_p / r_vir) (M its particle number); background particles
+    draw N(0, 400 km/s) per axis.  The velocities come from a generator of
+    their own, so the positions do not depend on whether they are drawn."""
+    pos, owner, counts, r_vir, n_in, gen = _draw_box(box_len, n_particles, n_halos, seed, device, halo_frac)
+    dev = pos.device
+    f64 = torch.float64
+    vgen = torch.Generator(device=dev)
+    vgen.manual_seed(int(seed) * 1000003 + 17)
+    m_p = particle_mass(box_len, n_particles)
+    vel = torch.randn((n_particles, 3), generator=vgen, dtype=f64, device=dev) * SIGMA_FIELD
+    if n_in > 0:
+        bulk = torch.randn((n_halos, 3), generator=vgen, dtype=f64, device=dev) * SIGMA_BULK
+        v_vir = torch.sqrt(G_MPC_KMS2_MSUN * counts.to(f64) * m_p / r_vir)
+        vel[:n_in] = bulk[owner] + vel[:n_in] / SIGMA_FIELD * (v_vir[owner] / math.sqrt(3.0))[:, None]
+    out = _finish(pos, box_len, dtype)
+    del pos
+    perm = torch.randperm(n_particles, generator=gen, device=dev)
+    return out[perm].contiguous(), vel.to(_torch_dtype(dtype))[perm].contiguous(), m_p
 
 
 def smooth_field(n: int, seed: int, device="cpu", half_width: int = 2, passes: int = 2) -> torch.Tensor:
