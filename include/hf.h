@@ -2,8 +2,7 @@
  * hf.h - C ABI of the MI355X (gfx950) CWT halo-finding path.
  *
  * The path is the data-parallel core of CWTHF (Li, Wang & He,
- * arXiv:2501.10622), Sec. 2, identification steps 2-8 (the self-boundness
- * check of steps 9-10 is not part of it):
+ * arXiv:2501.10622), Sec. 2, identification steps 2-10:
  *
  *   hf_deposit  step 2  cloud-in-cell mass on a periodic n^3 grid, Eq. (1)
  *   hf_cwt      step 3  grid CWT with the Mexican-hat wavelet, Eqs. (2)-(4)
@@ -18,7 +17,9 @@
  *   hf_cross_scale  step 8  maxima that are also maxima across scale
  *   hf_identify steps 2-8   the loop over scales, largest first, that claims
  *                       particles for halos (Sec. 2 and its flowchart)
- *   hf_identify_grids  the same loop with every scale on its own grid N_g
+ *   hf_identify_grids  the same loop with every scale on its own grid N_g,
+ *                       with steps 9-10 when velocities are given
+ *   hf_unbind   steps 9-10  the self-boundness check of one scale's groups
  *
  * Conventions shared by every call
  * --------------------------------
@@ -425,14 +426,21 @@ hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype 
  * the particles no earlier scale claimed take their cell's label, the groups'
  * cell and particle counts and the step-7/8 decision (hf_groups' test with n_j,
  * dens_th, particle_th), and the kept groups claim their particles.
+ * With velocities vel [np][3] (km/s, the dtype of pos; NULL skips it) steps
+ * 9 and 10 follow at every scale (hf_unbind with grav_mass = G m_p): the kept
+ * groups' self-boundness check, bound_keep [max_cap] receiving its decision,
+ * and only the bound particles of the groups that pass are claimed; the others
+ * stay free for the later scales.
  * particle_label [np] receives the scale's filtered labels (-1 unless the
  * particle is claimed at this scale); halo_scale/halo_root [np] as hf_identify.
  * All pointers are device pointers.  Errors: HF_ERR_ARG for a null required
  * pointer, scales not in increasing kw, count outside 1..HF_CWT_BATCH_MAX, a
- * max_cap above n_j^3, a stencil half-width above HF_STENCIL_MAX_HALF_WIDTH;
+ * max_cap above n_j^3, a stencil half-width above HF_STENCIL_MAX_HALF_WIDTH,
+ * np above 2^31 - 1, a non-positive grav_mass with velocities;
  * HF_ERR_SIZE for an n_j outside [8, 1024] or frac_bits outside [8, 20].
  * Workspace: hf_identify_grids_ws_size (the largest scale's stage workspace,
- * its group counters and one byte per maximum of the largest list). */
+ * or the check's with velocities, its group counters and one byte per
+ * maximum of the largest list). */
 typedef struct {
     double kw;                 /* scale k_w = w box_len / 1000 */
     int32_t n;                 /* this scale's grid points per side */
@@ -445,14 +453,40 @@ typedef struct {
     int32_t *particle_label;   /* [np] */
     uint32_t *group_particles; /* [max_cap] */
     uint32_t *group_cells;     /* [max_cap] */
-    uint8_t *group_keep;       /* [max_cap] */
+    uint8_t *group_keep;       /* [max_cap] steps 7-8 */
+    uint8_t *bound_keep;       /* [max_cap] steps 9-10 (with velocities; else unused, may be NULL) */
 } hf_grid_scale;
 hf_status hf_identify_grids_ws_size(double box_len, int32_t frac_bits, int64_t np, int32_t count,
-                                    const hf_grid_scale *scales, size_t *bytes);
-hf_status hf_identify_grids(hf_ctx *ctx, double box_len, int32_t frac_bits, const void *pos, hf_dtype dtype,
-                            int64_t np, float tau, int32_t count, const hf_grid_scale *scales, double dens_th,
-                            int64_t particle_th, int32_t *halo_scale, int32_t *halo_root, void *ws,
-                            size_t ws_bytes);
+                                    const hf_grid_scale *scales, int32_t with_velocities, size_t *bytes);
+hf_status hf_identify_grids(hf_ctx *ctx, double box_len, int32_t frac_bits, const void *pos, const void *vel,
+                            hf_dtype dtype, int64_t np, float tau, int32_t count, const hf_grid_scale *scales,
+                            double dens_th, int64_t particle_th, double grav_mass, int32_t *halo_scale,
+                            int32_t *halo_root, void *ws, size_t ws_bytes);
+
+/* Steps 9-10 (Sec. 2.3): the self-boundness check of one scale's groups.  For
+ * every root i with group_keep[i] != 0, its group is the particles whose
+ * particle_label is roots[i] (n^3 grid of box; roots and labels as hf_groups);
+ * repeatedly, with the remaining particles: their centre of mass (positions
+ * unwrapped about the root's node by minimum image) and mean velocity, each
+ * one's radius r, the spherical shell potential
+ *   Phi_i = -grav_mass [ (particles at or inside (r_i, index i)) / r_i
+ *                        + sum over those outside of 1 / r_j ]
+ * and the particles with |v - mean|^2 > -2 Phi_i leave, until none leaves.
+ * bound_keep[i] = 1 iff no more than 40% left (5 removed <= 2 N) and at least
+ * max(1, particle_th) remain.  particle_label (in/out) keeps only the bound
+ * particles of the groups with bound_keep set; every other label becomes -1.
+ * pos, vel [np][3] in dtype (vel in km/s), grav_mass = G m_p in
+ * (Mpc/h)(km/s)^2 (equal particle masses), all in FP64 arithmetic.  Readings:
+ * peculiar velocities, no Hubble flow; a particle at r = 0 is bound.  Errors:
+ * HF_ERR_ARG for a null required pointer, np outside [0, 2^31 - 1], nroots
+ * outside [0, n^3], a non-positive grav_mass or a negative particle_th; a
+ * label >= 0 that is not among the roots, or a root outside [0, n^3), sets
+ * HF_ERR_INPUT (the label becomes -1).  Workspace: hf_unbind_ws_size (a slot
+ * per cell, and 21 bytes per particle). */
+hf_status hf_unbind_ws_size(const hf_box *box, int64_t np, int64_t nroots, size_t *bytes);
+hf_status hf_unbind(hf_ctx *ctx, const hf_box *box, const void *pos, const void *vel, hf_dtype dtype, int64_t np,
+                    const int32_t *roots, int64_t nroots, const uint8_t *group_keep, int32_t *particle_label,
+                    double grav_mass, int64_t particle_th, uint8_t *bound_keep, void *ws, size_t ws_bytes);
 
 /* Serving form of steps 2-6 for `count` (1..HF_CWT_BATCH_MAX) boxes of the same
  * grid size n: per-box deposits, ONE batched transform (hf_cwt_batch) for the

@@ -649,7 +649,7 @@ def cross_scale(c_scale: np.ndarray, c_smaller: np.ndarray, roots) -> np.ndarray
 GRAV = 6.67430e-11 * 1.98841e30 / 3.0856775814913673e22 / 1.0e6
 
 
-def self_bound(pos, vel, box_len: float, members, ref, grav_mass: float):
+def self_bound(pos, vel, box_len: float, members, ref, grav_mass: float, margins: bool = False):
     """The self-boundness check of one group (Sec. 2.3, steps 9-10), FP64.
 
     ``members`` are the group's particle indices (ascending), ``ref`` a point
@@ -671,7 +671,9 @@ def self_bound(pos, vel, box_len: float, members, ref, grav_mass: float):
     members' mean, no Hubble flow; the potential of the remaining members only;
     a member exactly at the centre (r = 0) is bound.
 
-    Returns the bound flags of the members, the kept flag and the rounds made.
+    Returns the bound flags of the members, the kept flag and the rounds made
+    (with ``margins``, also the smallest |(|v - u|^2 + 2 Phi)| / |2 Phi| of
+    any decision made, a diagnostic of how far each one was from a tie).
     """
     members = np.asarray(members, dtype=np.int64).ravel()
     n0 = members.size
@@ -682,6 +684,7 @@ def self_bound(pos, vel, box_len: float, members, ref, grav_mass: float):
     d = np.where(d >= half, d - box_len, np.where(d < -half, d + box_len, d))  # minimum image
     alive = np.ones(n0, dtype=bool)
     rounds = 0
+    margin = np.inf
     while alive.any():
         rounds += 1
         idx = np.flatnonzero(alive)
@@ -697,11 +700,16 @@ def self_bound(pos, vel, box_len: float, members, ref, grav_mass: float):
             phi = -grav_mass * (np.arange(1, idx.size + 1) / rs + outer)
         speed2 = ((v[idx[order]] - u) ** 2).sum(axis=1)
         escape = speed2 > -2.0 * phi  # r = 0: -2 phi = inf, bound
+        if margins:
+            with np.errstate(invalid="ignore", divide="ignore"):
+                rel = np.abs(speed2 + 2.0 * phi) / np.abs(2.0 * phi)
+            margin = min(margin, float(np.nanmin(rel)) if rel.size else np.inf)
         if not escape.any():
             break
         alive[idx[order][escape]] = False
     removed = n0 - int(alive.sum())
-    return alive, bool(5 * removed <= 2 * n0 and alive.any()), rounds
+    kept = bool(5 * removed <= 2 * n0 and alive.any())
+    return (alive, kept, rounds, margin) if margins else (alive, kept, rounds)
 
 
 # --------------------------------------------------------------------------

@@ -11,5 +11,6 @@ from .hf import (  # noqa: F401
     cross_scale, cwt, cwt_batch, cwt_batch_ws_bytes, cwt_scales, cwt_stencil, deposit, find_halos, find_halos_async,
     find_halos_filtered_async, find_halos_group_async, find_halos_noalloc_async, find_halos_scales_async, groups,
     identify_async, identify_buffers, identify_grids_async, identify_grids_buffers, job_buffers, label, load_library,
-    maxima, paper_grid, peaks, scales_buffers, segment, stencil_half_width, status_str, sync, workspace_size,
+    maxima, paper_grid, peaks, scales_buffers, segment, stencil_half_width, status_str, sync, unbind,
+    workspace_size,
 )

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libhf.so")
 OBJDIR = os.path.join(PKG, "_build")
 
-SOURCES = ["api.hip", "deposit.hip", "deposit_tiled.hip", "fft.hip", "segment.hip", "pipeline.hip", "groups.hip", "stencil.hip"]
+SOURCES = ["api.hip", "deposit.hip", "deposit_tiled.hip", "fft.hip", "segment.hip", "pipeline.hip", "groups.hip", "stencil.hip", "unbind.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -47,7 +47,7 @@ const char *hf::kernel_name(int id) {
         "parent", "jump_flags", "jump", "finalize",
         "label_tiles", "label_level1", "label_input", "resolve",
         "groups_clear", "groups_cells", "groups_particles", "groups_decide", "groups_filter", "cross_scale",
-        "peaks", "stencil_x", "stencil_mass", "stencil_y", "stencil_z", "claim",
+        "peaks", "stencil_x", "stencil_mass", "stencil_y", "stencil_z", "claim", "unbind",
     };
     return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }

@@ -20,7 +20,7 @@ enum KernelId {
     K_PARENT, K_FLAGS, K_JUMP, K_FINALIZE,
     K_LABEL_TILES, K_LABEL_LEVEL1, K_LABEL_INPUT, K_RESOLVE,
     K_GROUP_CLEAR, K_GROUP_CELLS, K_GROUP_PARTICLES, K_GROUP_DECIDE, K_GROUP_FILTER, K_GROUP_CROSS, K_PEAKS,
-    K_ST_X, K_ST_MASS, K_ST_Y, K_ST_Z, K_CLAIM,
+    K_ST_X, K_ST_MASS, K_ST_Y, K_ST_Z, K_CLAIM, K_UNBIND,
     K_COUNT
 };
 const char *kernel_name(int id);
@@ -237,6 +237,18 @@ hf_status claim_filter(hf_ctx *ctx, const hf_box &box, int32_t *label, int32_t *
 hf_status claim_take(hf_ctx *ctx, const int32_t *label, int32_t *halo_scale, int32_t *halo_root, int64_t np,
                      int32_t scale);
 size_t stencil_ws_bytes(const hf_box &box);
+// Steps 9-10 for the kept groups (keep[i]) of the roots: afterwards only the
+// bound particles of the groups that pass keep their labels; bound_keep[i]
+// receives the decision.  nroots is the list's capacity; with d_count the
+// list holds min(*d_count, nroots) roots.  Workspace: unbind_ws_bytes(box, np,
+// nroots).
+size_t unbind_ws_bytes(const hf_box &box, int64_t np, int64_t nroots);
+hf_status unbind_dev(hf_ctx *ctx, const hf_box &box, const void *pos, const void *vel, hf_dtype dtype, int64_t np,
+                     const int32_t *roots, int64_t nroots, const uint8_t *keep, int32_t *label, double grav_mass,
+                     int64_t particle_th, uint8_t *bound_keep, void *ws, const int64_t *d_count = nullptr);
+// Particles that scale `scale` claimed and whose label is now -1 are free again.
+hf_status unclaim(hf_ctx *ctx, const int32_t *label, int64_t np, int32_t scale, int32_t *halo_scale,
+                  int32_t *halo_root);
 // The stencil half-width of HF_KERNEL_STENCIL on an n^3 grid: Table 1's
 // count Int(1.5/k_w + 5) is in cells of the flowchart's grid for the scale,
 // N_g = Int(400 k_w + 150), where it spans 10-12 scale lengths; on n cells the

@@ -330,7 +330,7 @@ struct GridsLayout {
 };
 
 hf_status grids_layout(double box_len, int32_t frac_bits, int64_t np, int32_t count, const hf_grid_scale *scales,
-                       GridsLayout &L) {
+                       bool with_vel, GridsLayout &L) {
     if (!scales || count < 1 || count > HF_CWT_BATCH_MAX || np < 0) return HF_ERR_ARG;
     size_t shared = 0, groups = 0;
     int64_t cap = 0;
@@ -344,6 +344,10 @@ hf_status grids_layout(double box_len, int32_t frac_bits, int64_t np, int32_t co
                               &need);
         if (s != HF_OK) return s;
         shared = need > shared ? need : shared;
+        if (with_vel) {  // steps 9-10 reuse the stage region once every scale's stages are done
+            const size_t ub = unbind_ws_bytes(b, np, scales[j].max_cap);
+            shared = ub > shared ? ub : shared;
+        }
         groups = groups_ws_bytes(b) > groups ? groups_ws_bytes(b) : groups;
         cap = scales[j].max_cap > cap ? scales[j].max_cap : cap;
     }
@@ -356,24 +360,27 @@ hf_status grids_layout(double box_len, int32_t frac_bits, int64_t np, int32_t co
 }  // namespace
 
 extern "C" hf_status hf_identify_grids_ws_size(double box_len, int32_t frac_bits, int64_t np, int32_t count,
-                                              const hf_grid_scale *scales, size_t *bytes) {
+                                              const hf_grid_scale *scales, int32_t with_velocities, size_t *bytes) {
     if (!bytes) return HF_ERR_ARG;
     GridsLayout L{};
-    hf_status s = grids_layout(box_len, frac_bits, np, count, scales, L);
+    hf_status s = grids_layout(box_len, frac_bits, np, count, scales, with_velocities != 0, L);
     if (s == HF_OK) *bytes = L.total;
     return s;
 }
 
 extern "C" hf_status hf_identify_grids(hf_ctx *ctx, double box_len, int32_t frac_bits, const void *pos,
-                                       hf_dtype dtype, int64_t np, float tau, int32_t count,
+                                       const void *vel, hf_dtype dtype, int64_t np, float tau, int32_t count,
                                        const hf_grid_scale *scales, double dens_th, int64_t particle_th,
-                                       int32_t *halo_scale, int32_t *halo_root, void *ws, size_t ws_bytes) {
+                                       double grav_mass, int32_t *halo_scale, int32_t *halo_root, void *ws,
+                                       size_t ws_bytes) {
     if (!ctx || !scales || count < 1 || count > HF_CWT_BATCH_MAX) return HF_ERR_ARG;
-    if (np < 0 || np > int64_t(UINT32_MAX) || (np > 0 && (!pos || !halo_scale || !halo_root))) return HF_ERR_ARG;
+    if (np < 0 || np > int64_t(INT32_MAX) || (np > 0 && (!pos || !halo_scale || !halo_root))) return HF_ERR_ARG;
     if ((dtype != HF_F32 && dtype != HF_F64) || tau != tau) return HF_ERR_ARG;
     if (!(dens_th >= 0.0) || !(dens_th < 1e300) || particle_th < 0) return HF_ERR_ARG;
+    const bool with_vel = vel != nullptr;
+    if (with_vel && (!(grav_mass > 0.0) || !(grav_mass < 1e300))) return HF_ERR_ARG;
     GridsLayout L{};
-    hf_status s = grids_layout(box_len, frac_bits, np, count, scales, L);
+    hf_status s = grids_layout(box_len, frac_bits, np, count, scales, with_vel, L);
     if (s != HF_OK) return s;
     int32_t hw[HF_CWT_BATCH_MAX];
     for (int j = 0; j < count; ++j) {
@@ -384,6 +391,7 @@ extern "C" hf_status hf_identify_grids(hf_ctx *ctx, double box_len, int32_t frac
             return HF_ERR_ARG;
         if (sj.max_cap > int64_t(sj.n) * sj.n * sj.n) return HF_ERR_ARG;
         if (sj.max_cap > 0 && (!sj.group_particles || !sj.group_cells || !sj.group_keep)) return HF_ERR_ARG;
+        if (with_vel && sj.max_cap > 0 && !sj.bound_keep) return HF_ERR_ARG;
         hw[j] = stencil_half_width(sj.kw, sj.n);
         if (hw[j] < 0) return HF_ERR_ARG;
     }
@@ -418,6 +426,13 @@ extern "C" hf_status hf_identify_grids(hf_ctx *ctx, double box_len, int32_t frac
             s = groups_decide(ctx, b, sj.max_idx, sj.d_count, sj.max_cap, g, dens_th, np, particle_th, pass,
                               sj.group_particles, sj.group_cells, sj.group_keep);
         if (s == HF_OK) s = claim_filter(ctx, b, sj.particle_label, halo_scale, halo_root, np, g, sj.max_cap > 0, j);
+        // steps 9-10: the kept groups' self-boundness check; the particles it
+        // removes (all of a discarded group's) are free again for later scales
+        if (s == HF_OK && with_vel && sj.max_cap > 0) {
+            s = unbind_dev(ctx, b, pos, vel, dtype, np, sj.max_idx, sj.max_cap, sj.group_keep, sj.particle_label,
+                           grav_mass, particle_th, sj.bound_keep, w0, sj.d_count);
+            if (s == HF_OK) s = unclaim(ctx, sj.particle_label, np, j, halo_scale, halo_root);
+        }
     }
     return s;
 }

@@ -28,7 +28,8 @@ EXPORTS = ("hf_create", "hf_destroy", "hf_status_str", "hf_sync", "hf_workspace_
            "hf_find_halos_filtered", "hf_cwt_scales",
            "hf_find_halos_scales_ws_size", "hf_find_halos_scales", "hf_cross_scale", "hf_peaks",
            "hf_cwt_stencil", "hf_stencil_half_width", "hf_identify_ws_size", "hf_identify",
-           "hf_find_halos_noalloc", "hf_identify_grids_ws_size", "hf_identify_grids")
+           "hf_find_halos_noalloc", "hf_identify_grids_ws_size", "hf_identify_grids", "hf_unbind_ws_size",
+           "hf_unbind")
 CWT_BATCH_MAX = 32
 STAGE_ALL = 31
 STAGE_GROUPS = 32
@@ -75,7 +76,7 @@ class GridScale(ctypes.Structure):
                 ("max_idx", ctypes.c_void_p), ("max_cap", ctypes.c_int64), ("d_count", ctypes.c_void_p),
                 ("cell_label", ctypes.c_void_p), ("particle_label", ctypes.c_void_p),
                 ("group_particles", ctypes.c_void_p), ("group_cells", ctypes.c_void_p),
-                ("group_keep", ctypes.c_void_p)]
+                ("group_keep", ctypes.c_void_p), ("bound_keep", ctypes.c_void_p)]
 
 
 class GroupFilter(ctypes.Structure):
@@ -131,10 +132,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                                     ctypes.POINTER(ScaleJob), vp, sz]),
             "hf_find_halos": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job), vp, sz]),
             "hf_find_halos_noalloc": (ctypes.c_int, [vp, bp, ctypes.POINTER(Job)]),
-            "hf_identify_grids_ws_size": (ctypes.c_int, [dbl, i32, i64, i32, ctypes.POINTER(GridScale),
+            "hf_identify_grids_ws_size": (ctypes.c_int, [dbl, i32, i64, i32, ctypes.POINTER(GridScale), i32,
                                                          ctypes.POINTER(sz)]),
-            "hf_identify_grids": (ctypes.c_int, [vp, dbl, i32, vp, i32, i64, flt, i32, ctypes.POINTER(GridScale),
-                                                 dbl, i64, vp, vp, vp, sz]),
+            "hf_identify_grids": (ctypes.c_int, [vp, dbl, i32, vp, vp, i32, i64, flt, i32, ctypes.POINTER(GridScale),
+                                                 dbl, i64, dbl, vp, vp, vp, sz]),
+            "hf_unbind_ws_size": (ctypes.c_int, [bp, i64, i64, ctypes.POINTER(sz)]),
+            "hf_unbind": (ctypes.c_int, [vp, bp, vp, vp, i32, i64, vp, i64, vp, vp, dbl, i64, vp, vp, sz]),
             "hf_identify_ws_size": (ctypes.c_int, [bp, i64, i32, ctypes.POINTER(ScaleJob), ctypes.POINTER(sz)]),
             "hf_identify": (ctypes.c_int, [vp, bp, vp, ctypes.c_int, i64, ctypes.c_int, flt, vp, i32,
                                            ctypes.POINTER(ScaleJob), ctypes.POINTER(IdentifyGroups), dbl, i64, vp,
@@ -688,13 +691,15 @@ def _grid_scales(kws, bufs):
                                               bufs["maxima"][j].numel(), bufs["count"][j].data_ptr(),
                                               bufs["cell_label"][j].data_ptr(), bufs["particle_label"][j].data_ptr(),
                                               bufs["group_particles"][j].data_ptr(),
-                                              bufs["group_cells"][j].data_ptr(), bufs["group_keep"][j].data_ptr())
+                                              bufs["group_cells"][j].data_ptr(), bufs["group_keep"][j].data_ptr(),
+                                              bufs["bound_keep"][j].data_ptr())
                                     for j, kw in enumerate(kws)])
 
 
-def identify_grids_buffers(grids, np_: int, device, box_len: float = 1.0, frac_bits: int = 15) -> dict:
+def identify_grids_buffers(grids, np_: int, device, box_len: float = 1.0, frac_bits: int = 15,
+                           with_velocities: bool = False) -> dict:
     """Outputs (one entry per scale, each on its own grid size in ``grids``) and
-    workspace for identify_grids_async."""
+    workspace for identify_grids_async (with_velocities: room for steps 9-10)."""
     count = len(grids)
     caps = [((g + 1) // 2) ** 3 for g in grids]
     bufs = {
@@ -708,31 +713,65 @@ def identify_grids_buffers(grids, np_: int, device, box_len: float = 1.0, frac_b
         "group_particles": [torch.empty(c, dtype=torch.int32, device=device) for c in caps],
         "group_cells": [torch.empty(c, dtype=torch.int32, device=device) for c in caps],
         "group_keep": [torch.empty(c, dtype=torch.uint8, device=device) for c in caps],
+        "bound_keep": [torch.empty(c, dtype=torch.uint8, device=device) for c in caps],
         "halo_scale": torch.empty(max(np_, 1), dtype=torch.int32, device=device),
         "halo_root": torch.empty(max(np_, 1), dtype=torch.int32, device=device),
     }
     out = ctypes.c_size_t()
     jobs = _grid_scales([0.1 * (j + 1) for j in range(count)], bufs)
     _check(load_library().hf_identify_grids_ws_size(float(box_len), int(frac_bits), int(np_), count, jobs,
-                                                    ctypes.byref(out)), "hf_identify_grids_ws_size")
+                                                    int(bool(with_velocities)), ctypes.byref(out)),
+           "hf_identify_grids_ws_size")
     bufs["ws"] = torch.empty(max(out.value, 256), dtype=torch.uint8, device=device)
     return bufs
 
 
 def identify_grids_async(pos: torch.Tensor, box_len: float, kws, bufs: dict, dens_th: float = 4.0,
-                         particle_th: int = 15, frac_bits: int = 15, tau: float = 0.0, ctx=None):
+                         particle_th: int = 15, frac_bits: int = 15, tau: float = 0.0, vel=None,
+                         grav_mass: float = 0.0, ctx=None):
     """Enqueue Sec. 2's identification loop with every scale on its own grid
-    (bufs from identify_grids_buffers, e.g. with grids [paper_grid(kw) ...])."""
+    (bufs from identify_grids_buffers, e.g. with grids [paper_grid(kw) ...]);
+    with velocities vel [np, 3] (km/s) and grav_mass = G m_p, steps 9-10 too."""
     _require_cuda(pos, "pos")
+    if vel is not None:
+        _require_cuda(vel, "vel")
+        if vel.dtype != pos.dtype or vel.shape != pos.shape:
+            raise ValueError("vel must match pos in dtype and shape")
     ctx = ctx or context(pos.device.index)
     count = len(kws)
     if count != len(bufs["grids"]):
         raise ValueError("one grid per scale")
     jobs = _grid_scales(kws, bufs)
-    _check(load_library().hf_identify_grids(ctx.handle, float(box_len), int(frac_bits), _ptr(pos), _dtype_code(pos),
-                                            pos.shape[0], float(tau), count, jobs, float(dens_th), int(particle_th),
-                                            _ptr(bufs["halo_scale"]), _ptr(bufs["halo_root"]), _ptr(bufs["ws"]),
-                                            bufs["ws"].numel()), "hf_identify_grids")
+    _check(load_library().hf_identify_grids(ctx.handle, float(box_len), int(frac_bits), _ptr(pos), _ptr(vel),
+                                            _dtype_code(pos), pos.shape[0], float(tau), count, jobs, float(dens_th),
+                                            int(particle_th), float(grav_mass), _ptr(bufs["halo_scale"]),
+                                            _ptr(bufs["halo_root"]), _ptr(bufs["ws"]), bufs["ws"].numel()),
+           "hf_identify_grids")
+
+
+def unbind(pos: torch.Tensor, vel: torch.Tensor, box_len: float, n: int, roots: torch.Tensor,
+           group_keep: torch.Tensor, particle_label: torch.Tensor, grav_mass: float, particle_th: int = 15,
+           frac_bits: int = 15, ctx=None) -> torch.Tensor:
+    """Steps 9-10 on one scale's groups (hf_unbind): particle_label is changed in
+    place to the bound particles' labels; returns the uint8 bound_keep flags."""
+    _require_cuda(pos, "pos")
+    _require_cuda(vel, "vel")
+    if vel.dtype != pos.dtype or vel.shape != pos.shape:
+        raise ValueError("vel must match pos in dtype and shape")
+    if roots.dtype != torch.int32 or particle_label.dtype != torch.int32 or group_keep.dtype != torch.uint8:
+        raise ValueError("roots and particle_label must be int32, group_keep uint8")
+    ctx = ctx or context(pos.device.index)
+    b = box(n, box_len, frac_bits)
+    out = ctypes.c_size_t()
+    _check(load_library().hf_unbind_ws_size(ctypes.byref(b), pos.shape[0], roots.numel(), ctypes.byref(out)),
+           "hf_unbind_ws_size")
+    ws = workspace(out.value, ctx)
+    bound = torch.empty(max(roots.numel(), 1), dtype=torch.uint8, device=pos.device)[: roots.numel()]
+    _check(load_library().hf_unbind(ctx.handle, ctypes.byref(b), _ptr(pos), _ptr(vel), _dtype_code(pos),
+                                    pos.shape[0], _ptr(roots), roots.numel(), _ptr(group_keep),
+                                    _ptr(particle_label), float(grav_mass), int(particle_th), _ptr(bound),
+                                    _ptr(ws), out.value), "hf_unbind")
+    return bound
 
 
 def find_halos_filtered_async(pos: torch.Tensor, box_len: float, n: int, kw: float, bufs: dict,
