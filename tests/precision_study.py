@@ -71,18 +71,19 @@ def main():
     cfg = synth.CONFIGS[args.config]
     n, L = cfg.n, cfg.box_len
     log(f"{args.config}: n={n} np={cfg.n_particles} scales(cells)={cfg.scales_cells}")
-    pos = synth.make_config_box(cfg, device="cpu").numpy()
-    log("positions generated (CPU)")
+    import torch
+    pos = synth.make_config_box(cfg, device="cuda" if torch.cuda.is_available() else "cpu").cpu().numpy()
+    log("positions generated")
     t0 = time.perf_counter()
-    rho64 = O.deposit(pos, L, n)
+    from oracle import cic
+    rho64 = cic.deposit_c(pos, L, n, 15, threads=max(1, min(16, len(os.sched_getaffinity(0)))))
     t_dep = time.perf_counter() - t0
-    log(f"oracle deposit {t_dep:.1f} s")
+    log(f"oracle deposit (C, exact integers) {t_dep:.1f} s")
     with ThreadPoolExecutor(max_workers=len(cfg.kw_list)) as ex:
         futs = [ex.submit(oracle_scale, rho64, pos, L, n, kw) for kw in cfg.kw_list]
         ref = [f.result() for f in futs]
     log("oracle scales done: " + ", ".join(f"{r['seconds']:.0f} s" for r in ref))
 
-    import torch
     import paper_2501_10622_amd as hfm
     dev = torch.device("cuda", 0)
     pos_d = torch.as_tensor(pos, device=dev)
