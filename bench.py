@@ -590,6 +590,80 @@ def identify_bench(pos, box_len: float, n: int, ctx, iters: int = 2) -> dict:
             "checks": {"claimed_equals_kept_group_particles_and_roots": ok}}
 
 
+def identify_grids_bench(ctx, iters: int = 2) -> dict:
+    """The flowchart's own loop (hf_identify_grids): every scale on its own grid
+    N_g = Int(400 k_w + 150), the truncated-stencil transform, then steps 5-8,
+    and, with velocities, the self-boundness check of steps 9-10.  Workload: a
+    phase-space box of L = 250 Mpc/h with 256^3 FP32 particles (20000 NFW halos,
+    the M2 recipe plus the synthetic velocity model), k_w = 0.3, 0.5, 0.8
+    (N_g = 270, 350, 470), dens_th = 4, particle_th = 15: one untimed call,
+    then `iters` timed calls with and without velocities; per scale the maxima,
+    the groups steps 7-8 keep, those the check keeps and the particles claimed,
+    with the invariant that the particles a scale claims are exactly the bound
+    particles of the groups it keeps."""
+    import torch
+    import paper_2501_10622_amd as hfm
+    import synth
+    L, npt, halos, seed = 250.0, 256 ** 3, 20000, 2
+    kws = [0.3, 0.5, 0.8]
+    grids = [hfm.paper_grid(k) for k in kws]
+    pos, vel, m_p = synth.make_phase_box(L, npt, halos, "f32", seed, device="cuda")
+    gm = synth.G_MPC_KMS2_MSUN * m_p
+    bufs = hfm.identify_grids_buffers(grids, npt, pos.device, L, with_velocities=True)
+    out = {"what": "the flowchart's loop on per-scale grids N_g = Int(400 k_w + 150) with the stencil transform, "
+                   "steps 2-10, dens_th = 4, particle_th = 15",
+           "workload": f"L={L:g} Mpc/h, {npt} FP32 particles with velocities, {halos} NFW halos, k_w = "
+                       + ", ".join(f"{k:g}" for k in kws), "grids": grids}
+    for with_vel in (False, True):
+        v = vel if with_vel else None
+
+        def call():
+            hfm.identify_grids_async(pos, L, kws, bufs, 4.0, 15, vel=v, grav_mass=gm, ctx=ctx)
+
+        call()
+        ctx.sync()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(iters):
+            call()
+        stop.record()
+        torch.cuda.synchronize()
+        ctx.sync()
+        ms = start.elapsed_time(stop) / iters
+        ctx.profile(True)
+        ctx.profile_reset()
+        call()
+        ctx.sync()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        hs = bufs["halo_scale"][:npt]
+        per, ok = [], True
+        for i in range(len(kws)):
+            k = int(bufs["count"][i].item())
+            keep = bufs["group_keep"][i][:k].bool()
+            bound = bufs["bound_keep"][i][:k].bool() if with_vel else keep
+            mine = hs == i
+            claimed = int(mine.sum().item())
+            lab = bufs["particle_label"][i][:npt]
+            ok = ok and bool((lab[mine] == bufs["halo_root"][:npt][mine]).all().item())
+            ok = ok and int((lab >= 0).sum().item()) == claimed
+            ok = ok and not bool((bound & ~keep).any().item())
+            per.append({"grid": grids[i], "kw": kws[i], "maxima": k, "kept_steps_7_8": int(keep.sum().item()),
+                        "kept_steps_9_10": int(bound.sum().item()) if with_vel else None,
+                        "particles_claimed": claimed})
+        key = "with_velocities" if with_vel else "without_velocities"
+        out[key] = {"ms_per_call": round(ms, 3), "scales": per,
+                    "particles_claimed": int((hs >= 0).sum().item()),
+                    "kernels_ms_per_call": {kk: round(vv[0], 3) for kk, vv in
+                                            sorted(prof.items(), key=lambda kv: -kv[1][0]) if vv[1]},
+                    "checks": {"claims_are_the_kept_groups_bound_particles": ok}}
+        log(f"identify on per-scale grids {grids} ({key}): {ms:.1f} ms per call, "
+            f"{out[key]['particles_claimed']} of {npt} claimed")
+    del bufs, pos, vel
+    torch.cuda.empty_cache()
+    return out
+
+
 def stencil_bench(rho, c_fft, box_len: float, n: int, kw: float, warmup: int, iters: int, ctx) -> dict:
     """Step 3 by the paper's truncated real-space stencil (hf_cwt_stencil with
     Table 1's half-width) on the step's density: `warmup` untimed calls, then
@@ -950,6 +1024,8 @@ def main():
         out["identify"] = identify_bench(pos, L, n, ctx)
     del pos
     torch.cuda.empty_cache()
+    if not args.no_groups and not multi:
+        out["identify_grids"] = identify_grids_bench(ctx)
     cp = copy_rate()
     out["hbm_copy_measured"] = {"GBps": round(cp["GBps"], 1), "frac_of_peak": round(cp["GBps"] / HBM_PEAK_GBS, 4),
                                 "what": "device copy of 4 GiB (read + write bytes / time), torch copy_"}

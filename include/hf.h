@@ -482,7 +482,7 @@ hf_status hf_identify_grids(hf_ctx *ctx, double box_len, int32_t frac_bits, cons
  * outside [0, n^3], a non-positive grav_mass or a negative particle_th; a
  * label >= 0 that is not among the roots, or a root outside [0, n^3), sets
  * HF_ERR_INPUT (the label becomes -1).  Workspace: hf_unbind_ws_size (a slot
- * per cell, and 21 bytes per particle). */
+ * per cell, and 29 bytes per particle). */
 hf_status hf_unbind_ws_size(const hf_box *box, int64_t np, int64_t nroots, size_t *bytes);
 hf_status hf_unbind(hf_ctx *ctx, const hf_box *box, const void *pos, const void *vel, hf_dtype dtype, int64_t np,
                     const int32_t *roots, int64_t nroots, const uint8_t *group_keep, int32_t *particle_label,

@@ -311,19 +311,24 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
 
 // ---------------------------------------------------------------------------
 // Counting labels per workgroup in an LDS hash table of HT (a power of two)
-// slots of (label, count), keys -1 when empty, linear probing; a label that
-// finds the table full adds to ctr[label] directly.  lds_tally_wave first
+// slots of (label, count), keys -1 when empty, linear probing over at most
+// TALLY_PROBES slots; a label that finds no slot there adds to ctr[label]
+// directly (so a chunk with more labels than the table holds costs a global
+// atomic per extra run, not a scan of the whole table per insert).  lds_tally_wave first
 // merges the lanes that share the first pending lane's label with one ballot
 // round (the commonest case: a run of one label), then adds the other lanes'
 // labels one by one.  Every lane of the wavefront must call it; labels below 0
 // are not counted.  After a barrier, lds_tally_flush adds the table to ctr.
 // ---------------------------------------------------------------------------
+constexpr int TALLY_PROBES = 32;
+
 template <int HT>
 __device__ __forceinline__ void lds_tally_add(int32_t *hkey, uint32_t *hcnt, uint32_t *ctr, int32_t l, uint32_t c) {
     static_assert((HT & (HT - 1)) == 0 && HT >= 2, "power-of-two table");
     constexpr int BITS = __builtin_ctz(unsigned(HT));
     uint32_t h = (uint32_t(l) * 2654435761u) >> (32 - BITS);  // Knuth's multiplicative hash, top bits
-    for (int probe = 0; probe < HT; ++probe) {
+    constexpr int PROBES = HT < TALLY_PROBES ? HT : TALLY_PROBES;
+    for (int probe = 0; probe < PROBES; ++probe) {
         int32_t k = hkey[h];
         if (k == -1) k = atomicCAS(hkey + h, -1, l);  // -1 back: this lane took the slot
         if (k == -1 || k == l) {

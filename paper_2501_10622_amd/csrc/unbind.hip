@@ -31,11 +31,12 @@ namespace {
 
 constexpr int UB_THREADS = 256;
 constexpr int UB_TILE = 1024;          // members per LDS tile of the potential pass
+constexpr int UB_MPT = 4;              // members each thread takes per pass over the tiles
 constexpr int UB_SORT_LDS = 8192;      // runs up to this many members are sorted in LDS
 constexpr int SCAN_GROUPS = 2;         // scan tag of this use
 
 struct UnbindLayout {
-    size_t slot, cnt, start, cursor, partial, pid, rad, spd, alive, total;
+    size_t slot, cnt, start, cursor, partial, pid, rad, inv, spd, alive, total;
 };
 
 UnbindLayout unbind_layout(int n, int64_t np, int64_t nroots) {
@@ -53,6 +54,7 @@ UnbindLayout unbind_layout(int n, int64_t np, int64_t nroots) {
     L.partial = take(sizeof(uint64_t) * SCAN_MAX_GROUPS);
     L.pid = take(sizeof(int32_t) * size_t(np > 0 ? np : 1));
     L.rad = take(sizeof(double) * size_t(np > 0 ? np : 1));
+    L.inv = take(sizeof(double) * size_t(np > 0 ? np : 1));
     L.spd = take(sizeof(double) * size_t(np > 0 ? np : 1));
     L.alive = take(sizeof(uint8_t) * size_t(np > 0 ? np : 1));
     L.total = off;
@@ -212,10 +214,11 @@ __global__ void __launch_bounds__(UB_THREADS)
     ub_group_kernel(const T *__restrict__ pos, const T *__restrict__ vel, int32_t *__restrict__ label,
                     const int32_t *__restrict__ roots, const int64_t *d_count, const uint8_t *__restrict__ keep,
                     const uint32_t *__restrict__ start, int32_t *__restrict__ pid, double *__restrict__ rad,
-                    double *__restrict__ spd, uint8_t *__restrict__ alive, int n, double box_len, double gm,
-                    int64_t particle_th, uint8_t *__restrict__ bound_keep) {
+                    double *__restrict__ inv, double *__restrict__ spd, uint8_t *__restrict__ alive, int n,
+                    double box_len, double gm, int64_t particle_th, uint8_t *__restrict__ bound_keep) {
     __shared__ double red[UB_THREADS / 64];
     __shared__ double tr[UB_TILE];
+    __shared__ double tinv[UB_TILE];
     __shared__ int32_t tid_[UB_TILE];
     __shared__ uint8_t tal[UB_TILE];
     __shared__ int32_t sort_lds[UB_SORT_LDS];
@@ -229,7 +232,7 @@ __global__ void __launch_bounds__(UB_THREADS)
     const uint32_t s0 = start[g];
     const int m0 = int(start[g + 1] - s0);
     int32_t *P = pid + s0;
-    double *R = rad + s0, *S = spd + s0;
+    double *R = rad + s0, *I = inv + s0, *S = spd + s0;
     uint8_t *A = alive + s0;
     block_sort(P, m0, sort_lds, UB_SORT_LDS);
     const uint32_t un = uint32_t(n), r0 = uint32_t(roots[g]);
@@ -269,7 +272,9 @@ __global__ void __launch_bounds__(UB_THREADS)
                 r2 = __dadd_rn(r2, __dmul_rn(e, e));
                 s2 = __dadd_rn(s2, __dmul_rn(w, w));
             }
-            R[k] = __dsqrt_rn(r2);
+            const double r = __dsqrt_rn(r2);
+            R[k] = r;
+            I[k] = __ddiv_rn(1.0, r);  // each member's 1 / r, once per round (inf at r = 0)
             S[k] = s2;
         }
         if (threadIdx.x == 0) s_count[0] = 0u;
@@ -277,33 +282,48 @@ __global__ void __launch_bounds__(UB_THREADS)
         // the shell potential at each remaining member, over LDS tiles of all
         // members; a leaver is marked 2 (still counted this round)
         uint32_t leaving = 0;
-        for (int i0 = 0; i0 < m0; i0 += UB_THREADS) {
-            const int i = i0 + int(threadIdx.x);
-            const bool mine = i < m0 && A[i] != 0;
-            const double ri = mine ? R[i] : 0.0;
-            const int32_t pi = mine ? P[i] : 0;
-            uint32_t inner = 0;
-            double outer = 0.0;
+        for (int i0 = 0; i0 < m0; i0 += UB_THREADS * UB_MPT) {
+            bool mine[UB_MPT];
+            double ri[UB_MPT], outer[UB_MPT];
+            int32_t pi[UB_MPT];
+            uint32_t inner[UB_MPT];
+#pragma unroll
+            for (int q = 0; q < UB_MPT; ++q) {
+                const int i = i0 + q * UB_THREADS + int(threadIdx.x);
+                mine[q] = i < m0 && A[i] != 0;
+                ri[q] = mine[q] ? R[i] : 0.0;
+                pi[q] = mine[q] ? P[i] : 0;
+                inner[q] = 0;
+                outer[q] = 0.0;
+            }
             for (int base = 0; base < m0; base += UB_TILE) {
                 const int tile = m0 - base < UB_TILE ? m0 - base : UB_TILE;
                 __syncthreads();
                 for (int k = threadIdx.x; k < tile; k += UB_THREADS) {
                     tal[k] = A[base + k] != 0;
                     tr[k] = R[base + k];
+                    tinv[k] = I[base + k];
                     tid_[k] = P[base + k];
                 }
                 __syncthreads();
-                if (mine) {
-                    for (int k = 0; k < tile; ++k) {
-                        if (!tal[k]) continue;
-                        const double rj = tr[k];
-                        if (rj < ri || (rj == ri && tid_[k] <= pi)) inner += 1u;
-                        else outer = __dadd_rn(outer, __ddiv_rn(1.0, rj));
+                for (int k = 0; k < tile; ++k) {
+                    if (!tal[k]) continue;
+                    const double rj = tr[k], ij = tinv[k];
+                    const int32_t pj = tid_[k];
+#pragma unroll
+                    for (int q = 0; q < UB_MPT; ++q) {
+                        // at or inside (r_i, i): a point mass at the centre; outside: its own shell
+                        const bool in = rj < ri[q] || (rj == ri[q] && pj <= pi[q]);
+                        inner[q] += in ? 1u : 0u;
+                        if (!in) outer[q] = __dadd_rn(outer[q], ij);
                     }
                 }
             }
-            if (mine) {
-                const double phi = -__dmul_rn(gm, __dadd_rn(__ddiv_rn(double(inner), ri), outer));
+#pragma unroll
+            for (int q = 0; q < UB_MPT; ++q) {
+                if (!mine[q]) continue;
+                const int i = i0 + q * UB_THREADS + int(threadIdx.x);
+                const double phi = -__dmul_rn(gm, __dadd_rn(__ddiv_rn(double(inner[q]), ri[q]), outer[q]));
                 if (S[i] > __dmul_rn(-2.0, phi)) {
                     A[i] = 2;
                     ++leaving;
@@ -364,6 +384,7 @@ hf_status hf::unbind_dev(hf_ctx *ctx, const hf_box &box, const void *pos, const 
     auto *partial = reinterpret_cast<uint64_t *>(w + L.partial);
     auto *pid = reinterpret_cast<int32_t *>(w + L.pid);
     auto *rad = reinterpret_cast<double *>(w + L.rad);
+    auto *inv = reinterpret_cast<double *>(w + L.inv);
     auto *spd = reinterpret_cast<double *>(w + L.spd);
     auto *alive = reinterpret_cast<uint8_t *>(w + L.alive);
     const int64_t ncells = int64_t(box.n) * box.n * box.n;
@@ -382,11 +403,11 @@ hf_status hf::unbind_dev(hf_ctx *ctx, const hf_box &box, const void *pos, const 
     if (dtype == HF_F32)
         HF_LAUNCH(ctx, K_UNBIND, ub_group_kernel<float>, dim3(unsigned(nroots)), dim3(UB_THREADS), 0, st,
                   static_cast<const float *>(pos), static_cast<const float *>(vel), label, roots, d_count, keep,
-                  start, pid, rad, spd, alive, box.n, box.box_len, grav_mass, particle_th, bound_keep);
+                  start, pid, rad, inv, spd, alive, box.n, box.box_len, grav_mass, particle_th, bound_keep);
     else
         HF_LAUNCH(ctx, K_UNBIND, ub_group_kernel<double>, dim3(unsigned(nroots)), dim3(UB_THREADS), 0, st,
                   static_cast<const double *>(pos), static_cast<const double *>(vel), label, roots, d_count, keep,
-                  start, pid, rad, spd, alive, box.n, box.box_len, grav_mass, particle_th, bound_keep);
+                  start, pid, rad, inv, spd, alive, box.n, box.box_len, grav_mass, particle_th, bound_keep);
     return launch_status();
 }
 
