@@ -12,6 +12,15 @@
 //       writes the owned cells once and the skirt sums to a side buffer;
 //   FOLD each tile adds the skirt sums of its lower neighbours to its low faces.
 //
+// Level-1 records are stored replica-major: the scatter chunks of one counter
+// replica (all on one XCD) write only into that replica's region, where the
+// replica's share of every bucket lies back to back, so a chunk's runs land in
+// a few pages instead of one page per bucket across the whole array.  Every
+// other index (the run maps, the level-2 chunks, step 6's level-1 labels) is
+// the bucket-major index the records would have with the buckets contiguous;
+// a per-(bucket, replica) table of segment starts converts it to the storage
+// slot where the records are read.
+//
 // Tiles are long in x so that the fold's face accesses are mostly whole rows.
 // Each partition pass is a histogram pass plus a scatter pass whose writes are
 // staged in LDS so that each workgroup writes one contiguous run per bucket
@@ -42,7 +51,7 @@ constexpr int PART_PER = 8;
 constexpr int CHUNK = PART_THREADS * PART_PER;                          // particles per scatter workgroup
 constexpr int HIST_CHUNKS = 8;                                          // scatter chunks per histogram workgroup
 constexpr int HCHUNK = CHUNK * HIST_CHUNKS;
-constexpr int REPLICAS = 64;   // level-1 counters are replicated to spread atomic traffic
+constexpr int REPLICAS = 16;   // level-1 counters are replicated to spread atomic traffic
 constexpr int MAX_DIGITS = 512;
 constexpr int HIST_THREADS = 512;  // histogram workgroups stay at 512 threads
 constexpr int ACC_THREADS = 512;
@@ -285,6 +294,65 @@ __global__ void __launch_bounds__(MAX_DIGITS) l1_scan_kernel(const uint32_t *__r
     }
 }
 
+// Storage of the replica-major level-1 records, one workgroup per replica r:
+// seg_v[b][r] = the bucket-major index where replica r's share of bucket b
+// starts (cursor1's initial value), seg_p[b][r] = the storage slot where it is
+// kept (the records of the replicas before r, then r's shares of the buckets
+// before b).
+__global__ void __launch_bounds__(MAX_DIGITS) l1_segs_kernel(const uint32_t *__restrict__ count1, int nbuckets,
+                                                             const uint32_t *__restrict__ cursor1,
+                                                             uint32_t *__restrict__ seg_v,
+                                                             uint32_t *__restrict__ seg_p) {
+    __shared__ uint32_t s[MAX_DIGITS], tmp[MAX_DIGITS];
+    const int r = blockIdx.x, t = threadIdx.x;
+    uint32_t before = 0;
+    if (t < nbuckets)
+        for (int q = 0; q < r; ++q) before += count1[q * MAX_DIGITS + t];
+    s[t] = before;
+    __syncthreads();
+    const uint32_t rbase = block_exclusive_scan(s, tmp, nbuckets);
+    s[t] = t < nbuckets ? count1[r * MAX_DIGITS + t] : 0u;
+    __syncthreads();
+    block_exclusive_scan(s, tmp, nbuckets);
+    if (t < nbuckets) {
+        seg_v[t * REPLICAS + r] = cursor1[r * MAX_DIGITS + t];
+        seg_p[t * REPLICAS + r] = rbase + s[t];
+    }
+}
+
+// Storage slot of bucket-major level-1 index i of a bucket whose segment
+// starts sv[] / sp[] (per replica, in LDS) are given: the last replica whose
+// share starts at or before i holds it (an empty share starts where the next
+// one does, so the last of equal starts is the one that holds i).
+__device__ __forceinline__ uint32_t seg_slot(const uint32_t *sv, const uint32_t *sp, uint32_t i) {
+    int r = 0;
+#pragma unroll
+    for (int step = REPLICAS / 2; step > 0; step >>= 1)
+        if (sv[r + step] <= i) r += step;
+    return sp[r] + (i - sv[r]);
+}
+static_assert((REPLICAS & (REPLICAS - 1)) == 0, "the segment search halves a power of two");
+
+// The indices [lo, hi) of one level-2 chunk: usually within one replica's
+// share, whose storage offset then serves every record without a search.
+struct SegRange {
+    bool single;
+    uint32_t shift;  // storage slot - index inside that share
+};
+
+__device__ __forceinline__ SegRange seg_range(const uint32_t *sv, const uint32_t *sp, uint32_t lo, uint32_t hi) {
+    int r = 0;
+#pragma unroll
+    for (int step = REPLICAS / 2; step > 0; step >>= 1)
+        if (sv[r + step] <= lo) r += step;
+    return {r == REPLICAS - 1 || sv[r + 1] >= hi, sp[r] - sv[r]};
+}
+
+__device__ __forceinline__ uint32_t seg_slot(const uint32_t *sv, const uint32_t *sp, const SegRange &g,
+                                             uint32_t i) {
+    return g.single ? i + g.shift : seg_slot(sv, sp, i);
+}
+
 // Persistent: workgroup w takes the logical blocks w, w + G, w + 2G, ... of
 // the replica mapping (G = gridDim.x, a multiple of NUM_XCD, so they all stay
 // on one XCD).  Software-pipelined over two sets of bucket counts, offsets and
@@ -294,10 +362,13 @@ __global__ void __launch_bounds__(MAX_DIGITS) l1_scan_kernel(const uint32_t *__r
 template <typename T>
 __global__ void __launch_bounds__(PART_THREADS) l1_scatter_kernel(const T *__restrict__ pos, int64_t np,
                                                                   FixedPoint<T> fp, Geom g, uint32_t *cursor1,
+                                                                  const uint32_t *__restrict__ seg_v,
+                                                                  const uint32_t *__restrict__ seg_p,
                                                                   Q3 *__restrict__ rec1, RunMaps maps) {
     __shared__ Q3 stage[CHUNK];
     __shared__ uint16_t sbk[CHUNK];
-    __shared__ uint32_t h[2][MAX_DIGITS], off[2][MAX_DIGITS], gbase[2][MAX_DIGITS], tmp[MAX_DIGITS];
+    __shared__ uint32_t h[2][MAX_DIGITS], off[2][MAX_DIGITS], gbase[2][MAX_DIGITS], gshift[2][MAX_DIGITS],
+        tmp[MAX_DIGITS];
     static_assert(PART_PER == LBATCH, "one batch per scatter chunk");
     const uint32_t nchunks = uint32_t((np + CHUNK - 1) / CHUNK);
     const uint32_t logical = replica_grid(nchunks);
@@ -340,9 +411,13 @@ __global__ void __launch_bounds__(PART_THREADS) l1_scatter_kernel(const T *__res
         __syncthreads();
         const uint32_t total = block_exclusive_scan(off[j], tmp, g.nbuckets);
         // the histogram pass counted this chunk under replica (c / HIST_CHUNKS) % REPLICAS
-        uint32_t *mine = cursor1 + ((c / HIST_CHUNKS) % REPLICAS) * MAX_DIGITS;
+        const int rep = int((c / HIST_CHUNKS) % REPLICAS);
+        uint32_t *mine = cursor1 + rep * MAX_DIGITS;
         for (int b = threadIdx.x; b < g.nbuckets; b += blockDim.x)
-            if (h[j][b]) gbase[j][b] = atomicAdd(&mine[b], h[j][b]);
+            if (h[j][b]) {
+                gbase[j][b] = atomicAdd(&mine[b], h[j][b]);
+                gshift[j][b] = seg_p[b * REPLICAS + rep] - seg_v[b * REPLICAS + rep];  // index -> storage slot
+            }
         return total;
     };
     uint32_t total = prepare(chunk, 0);
@@ -369,7 +444,7 @@ __global__ void __launch_bounds__(PART_THREADS) l1_scatter_kernel(const T *__res
         if (nxt >= 0) load_raw(pos, nxt * CHUNK + threadIdx.x, PART_THREADS, np, raw);
         for (uint32_t s = threadIdx.x; s < total; s += PART_THREADS) {
             const int b = sbk[s];
-            rec1[gbase[j][b] + (s - off[j][b])] = stage[s];
+            rec1[gbase[j][b] + gshift[j][b] + (s - off[j][b])] = stage[s];
         }
         if (maps.pos) save_run_table(maps, chunk, g.nbuckets, h[j], off[j], gbase[j], total);
         if (nxt < 0) break;
@@ -392,6 +467,7 @@ struct L2Input {
     int64_t np;
     FixedPoint<T> fp;
     const Q3 *rec1;
+    const uint32_t *seg_v, *seg_p;  // per (bucket, replica): where the level-1 records are kept
     const uint32_t *start1;
     const uint32_t *chunk_first;  // per-bucket chunk prefix for this kernel's chunk size
     int nbuckets;
@@ -426,24 +502,27 @@ __device__ __forceinline__ bool l2_chunk(const L2Input<T, FROM_REC> &in, int &b,
     return true;
 }
 
+// The segment starts of bucket b into LDS (the caller synchronises).
 template <typename T, bool FROM_REC>
-__device__ __forceinline__ bool l2_load(const L2Input<T, FROM_REC> &in, int64_t i, Q3 &q) {
-    if (FROM_REC) {
-        q = in.rec1[i];
-        return true;
+__device__ __forceinline__ void l2_segments(const L2Input<T, FROM_REC> &in, int b, uint32_t *sv, uint32_t *sp) {
+    if (!FROM_REC) return;
+    for (int r = threadIdx.x; r < REPLICAS; r += blockDim.x) {
+        sv[r] = in.seg_v[b * REPLICAS + r];
+        sp[r] = in.seg_p[b * REPLICAS + r];
     }
-    return load_q(in.pos, i, in.fp, q);
 }
 
 template <typename T, bool FROM_REC>
 __global__ void __launch_bounds__(HIST_THREADS) l2_hist_kernel(L2Input<T, FROM_REC> in, Geom g, uint32_t *count2,
                                                                uint32_t *status) {
-    __shared__ uint32_t h[MAX_DIGITS];
+    __shared__ uint32_t h[MAX_DIGITS], sv[REPLICAS], sp[REPLICAS];
     int b;
     int64_t lo, hi;
     if (!l2_chunk(in, b, lo, hi)) return;
     for (int d = threadIdx.x; d < MAX_DIGITS; d += blockDim.x) h[d] = 0u;
+    l2_segments(in, b, sv, sp);
     __syncthreads();
+    const SegRange sg = FROM_REC ? seg_range(sv, sp, uint32_t(lo), uint32_t(hi)) : SegRange{true, 0u};
     bool bad = false;
     for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += HIST_THREADS * LBATCH) {
         Q3 q[LBATCH];
@@ -453,7 +532,7 @@ __global__ void __launch_bounds__(HIST_THREADS) l2_hist_kernel(L2Input<T, FROM_R
             for (int k = 0; k < LBATCH; ++k) {
                 const int64_t i = i0 + k * HIST_THREADS;
                 ok[k] = i < hi;
-                if (ok[k]) q[k] = in.rec1[i];
+                if (ok[k]) q[k] = in.rec1[seg_slot(sv, sp, sg, uint32_t(i))];
             }
         } else {
             load_q_batch(in.pos, i0, HIST_THREADS, hi, in.fp, q, ok, bad);
@@ -476,12 +555,15 @@ __global__ void __launch_bounds__(PART_THREADS) l2_scatter_kernel(L2Input<T, FRO
                                                                   RunMaps maps) {
     __shared__ uint64_t stage[CHUNK];
     __shared__ uint16_t sdig[CHUNK];
-    __shared__ uint32_t h[MAX_DIGITS], off[MAX_DIGITS], gbase[MAX_DIGITS], tmp[MAX_DIGITS];
+    __shared__ uint32_t h[MAX_DIGITS], off[MAX_DIGITS], gbase[MAX_DIGITS], tmp[MAX_DIGITS], sv[REPLICAS],
+        sp[REPLICAS];
     int b;
     int64_t lo, hi;
     if (!l2_chunk(in, b, lo, hi)) return;
     for (int d = threadIdx.x; d < MAX_DIGITS; d += blockDim.x) h[d] = 0u;
+    l2_segments(in, b, sv, sp);
     __syncthreads();
+    const SegRange sg = FROM_REC ? seg_range(sv, sp, uint32_t(lo), uint32_t(hi)) : SegRange{true, 0u};
     uint64_t r[PART_PER];
     int dg[PART_PER];
     uint32_t rank[PART_PER];
@@ -492,7 +574,7 @@ __global__ void __launch_bounds__(PART_THREADS) l2_scatter_kernel(L2Input<T, FRO
         for (int k = 0; k < PART_PER; ++k) {
             const int64_t i = lo + k * PART_THREADS + threadIdx.x;
             ok[k] = i < hi;
-            if (ok[k]) q[k] = in.rec1[i];
+            if (ok[k]) q[k] = in.rec1[seg_slot(sv, sp, sg, uint32_t(i))];
         }
     } else {
         bool bad = false;  // reported by the histogram pass
@@ -1004,8 +1086,8 @@ bool make_geom(const hf_box &box, Geom &out) {
 }
 
 struct DepLayout {
-    size_t count1, start1, cursor1, chunk_first, hchunk_first, count2, start2, cursor2, partial, rec1, rec2, skirt,
-        total;
+    size_t count1, start1, cursor1, seg_v, seg_p, chunk_first, hchunk_first, count2, start2, cursor2, partial, rec1,
+        rec2, skirt, total;
 };
 
 // Deposit workspace; with keep_order the level-2 records and the bucket and
@@ -1022,6 +1104,8 @@ DepLayout dep_layout(const Geom &g, int64_t np, bool keep_order) {
     L.count2 = take(sizeof(uint32_t) * size_t(g.ntiles));
     L.start1 = take(keep_order ? 0 : sizeof(uint32_t) * (MAX_DIGITS + 1));
     L.cursor1 = take(sizeof(uint32_t) * MAX_DIGITS * REPLICAS);
+    L.seg_v = take(sizeof(uint32_t) * MAX_DIGITS * REPLICAS);
+    L.seg_p = take(sizeof(uint32_t) * MAX_DIGITS * REPLICAS);
     L.chunk_first = take(keep_order ? 0 : sizeof(uint32_t) * (MAX_DIGITS + 1));
     L.hchunk_first = take(sizeof(uint32_t) * (MAX_DIGITS + 1));
     L.start2 = take(keep_order ? 0 : sizeof(uint32_t) * (size_t(g.ntiles) + 1));
@@ -1089,6 +1173,8 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
     auto *count2 = reinterpret_cast<uint32_t *>(ws + L.count2);
     auto *start1 = order ? order->start1 : reinterpret_cast<uint32_t *>(ws + L.start1);
     auto *cursor1 = reinterpret_cast<uint32_t *>(ws + L.cursor1);
+    auto *seg_v = reinterpret_cast<uint32_t *>(ws + L.seg_v);
+    auto *seg_p = reinterpret_cast<uint32_t *>(ws + L.seg_p);
     auto *chunk_first = order ? order->chunk_first : reinterpret_cast<uint32_t *>(ws + L.chunk_first);
     auto *hchunk_first = reinterpret_cast<uint32_t *>(ws + L.hchunk_first);
     auto *start2 = order ? order->start2 : reinterpret_cast<uint32_t *>(ws + L.start2);
@@ -1117,13 +1203,15 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
                       fp, g, count1, ctx->d_status);
         HF_LAUNCH(ctx, K_DEP_PREP, l1_scan_kernel, dim3(1), dim3(MAX_DIGITS), 0, st, count1, g.nbuckets, start1,
                   cursor1, chunk_first, hchunk_first, nrec);
+        HF_LAUNCH(ctx, K_DEP_PREP, l1_segs_kernel, dim3(REPLICAS), dim3(MAX_DIGITS), 0, st, count1, g.nbuckets,
+                  cursor1, seg_v, seg_p);
         if (part_blocks)
             HF_LAUNCH(ctx, K_DEP_L1_SCATTER, l1_scatter_kernel<T>,
                       dim3(resident_grid(ctx, reinterpret_cast<const void *>(&l1_scatter_kernel<T>),
                                          replica_grid(part_blocks))),
-                      dim3(PART_THREADS), 0, st, pos, np, fp, g, cursor1, rec1, m1);
-        const L2Input<T, true> hin{pos, np, fp, rec1, start1, hchunk_first, g.nbuckets, HCHUNK};
-        const L2Input<T, true> sin{pos, np, fp, rec1, start1, chunk_first, g.nbuckets, CHUNK};
+                      dim3(PART_THREADS), 0, st, pos, np, fp, g, cursor1, seg_v, seg_p, rec1, m1);
+        const L2Input<T, true> hin{pos, np, fp, rec1, seg_v, seg_p, start1, hchunk_first, g.nbuckets, HCHUNK};
+        const L2Input<T, true> sin{pos, np, fp, rec1, seg_v, seg_p, start1, chunk_first, g.nbuckets, CHUNK};
         HF_LAUNCH(ctx, K_DEP_L2_HIST, (l2_hist_kernel<T, true>), dim3(hist_blocks + unsigned(g.nbuckets)),
                   dim3(HIST_THREADS), 0, st, hin, g, count2, ctx->d_status);
         HF_LAUNCH(ctx, K_DEP_PREP, seg_reduce_kernel<SCAN_TILES>, dim3(scan_groups(tile_scan)), dim3(SCAN_THREADS),
@@ -1133,8 +1221,8 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
         HF_LAUNCH(ctx, K_DEP_L2_SCATTER, (l2_scatter_kernel<T, true>), dim3(part_blocks + unsigned(g.nbuckets)),
                   dim3(PART_THREADS), 0, st, sin, g, cursor2, rec2, m2);
     } else {
-        const L2Input<T, false> hin{pos, np, fp, nullptr, nullptr, nullptr, 1, HCHUNK};
-        const L2Input<T, false> sin{pos, np, fp, nullptr, nullptr, nullptr, 1, CHUNK};
+        const L2Input<T, false> hin{pos, np, fp, nullptr, nullptr, nullptr, nullptr, nullptr, 1, HCHUNK};
+        const L2Input<T, false> sin{pos, np, fp, nullptr, nullptr, nullptr, nullptr, nullptr, 1, CHUNK};
         if (hist_blocks)
             HF_LAUNCH(ctx, K_DEP_L2_HIST, (l2_hist_kernel<T, false>), dim3(hist_blocks), dim3(HIST_THREADS), 0, st,
                       hin, g, count2, ctx->d_status);
