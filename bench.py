@@ -35,7 +35,7 @@ CSRC = os.path.join(ROOT, "paper_2501_10622_amd", "csrc")
 TIMER_SYMBOLS = {
     "zero_grid": ("fill_u64_kernel",), "deposit": ("tile_accum_kernel",), "label": ("label_kernel",),
     "deposit_atomic": ("deposit_atomic_kernel",),
-    "deposit_prep": ("zero_u32_kernel", "l1_scan_kernel", "seg_reduce_kernel<0>", "seg_scan_kernel<0>"),
+    "deposit_prep": ("zero_u32_kernel", "l1_scan_kernel", "l1_segs_kernel", "seg_reduce_kernel<0>", "seg_scan_kernel<0>"),
     "deposit_l1_hist": ("l1_hist_kernel",), "deposit_l1_scatter": ("l1_scatter_kernel",),
     "deposit_l2_hist": ("l2_hist_kernel",), "deposit_l2_scatter": ("l2_scatter_kernel",),
     "deposit_fold": ("skirt_fold_kernel",),
@@ -44,7 +44,7 @@ TIMER_SYMBOLS = {
     "fft_y_inv": ("fft_y_kernel<true>",), "fft_x_inv": ("fft_x_inv_kernel",),
     "maxima_mark": ("max_tile_kernel", "max_direct_kernel"), "maxima_count": ("mask_count_kernel",),
     "maxima_scan": ("seg_reduce_kernel<1>", "seg_scan_kernel<1>"), "maxima_write": ("list_write_kernel",),
-    "parent": ("parent_walk_kernel", "parent_direct_kernel"), "resolve": ("resolve_tile_kernel",), "jump_flags": ("fill_flags_kernel",),
+    "parent": ("parent_resolve_kernel", "parent_direct_kernel"), "jump_flags": ("fill_flags_kernel",),
     "jump": ("bnd_jump_first_kernel", "bnd_jump_kernel", "jump_direct_kernel"), "finalize": ("seg_finalize_kernel", "finalize_direct_kernel"),
     "label_tiles": ("tile_label_kernel",), "label_level1": ("to_level1_kernel",), "label_input": ("to_input_kernel",),
     "groups_clear": ("groups_clear_kernel",), "groups_cells": ("groups_runs_kernel<false>", "groups_tally_kernel<false>"),
@@ -70,7 +70,7 @@ STAGES = {
     "cwt_y_inv": ("fft_y_inv",),
     "cwt_x_inv": ("fft_x_inv",),
     # the one-call pipeline finds the maxima in the segmentation's parent pass
-    "maxima_segment": ("maxima_mark", "maxima_count", "maxima_scan", "maxima_write", "parent", "resolve",
+    "maxima_segment": ("maxima_mark", "maxima_count", "maxima_scan", "maxima_write", "parent",
                        "jump_flags", "jump", "finalize"),
     "label": ("label", "label_tiles", "label_level1", "label_input"),
 }

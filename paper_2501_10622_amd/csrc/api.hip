@@ -45,7 +45,7 @@ const char *hf::kernel_name(int id) {
         "tables_1", "tables_2", "fft_x_fwd", "mass", "fft_y_fwd", "fft_z_mul", "fft_y_inv", "fft_x_inv",
         "maxima_mark", "maxima_count", "maxima_scan", "maxima_write",
         "parent", "jump_flags", "jump", "finalize",
-        "label_tiles", "label_level1", "label_input", "resolve",
+        "label_tiles", "label_level1", "label_input",
         "groups_clear", "groups_cells", "groups_particles", "groups_decide", "groups_filter", "cross_scale",
         "peaks", "stencil_x", "stencil_mass", "stencil_y", "stencil_z", "claim", "unbind",
     };

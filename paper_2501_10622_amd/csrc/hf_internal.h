@@ -18,7 +18,7 @@ enum KernelId {
     K_TABLES_1, K_TABLES_2, K_X_FWD, K_MASS, K_Y_FWD, K_Z_MUL, K_Y_INV, K_X_INV,
     K_MAX_MARK, K_MAX_COUNT, K_MAX_SCAN, K_MAX_WRITE,
     K_PARENT, K_FLAGS, K_JUMP, K_FINALIZE,
-    K_LABEL_TILES, K_LABEL_LEVEL1, K_LABEL_INPUT, K_RESOLVE,
+    K_LABEL_TILES, K_LABEL_LEVEL1, K_LABEL_INPUT,
     K_GROUP_CLEAR, K_GROUP_CELLS, K_GROUP_PARTICLES, K_GROUP_DECIDE, K_GROUP_FILTER, K_GROUP_CROSS, K_PEAKS,
     K_ST_X, K_ST_MASS, K_ST_Y, K_ST_Z, K_CLAIM, K_UNBIND,
     K_COUNT

@@ -8,14 +8,14 @@
 // neighbourhood (itself included); a cell is a maximum iff it is its own
 // parent and its value exceeds tau.
 //
-// Tiled path (n % 32 == 0): one workgroup per 32x8x8 tile holds the tile and a
-// one-cell halo of keys in LDS and forms the 3x3x3 maximum separably (x, y, z).
-// That pass writes every cell's parent index (the maxima mask as well when
-// asked); chains are then resolved on larger 32x16x16 tiles, whose int32
-// pointers alone fit LDS, so fewer cells sit on tile boundaries.
+// Tiled path (n % 32 == 0): one workgroup per 32x16x16 tile holds the tile and
+// a one-cell halo of the field in LDS, forms every cell's parent (the largest
+// key of its 3x3x3 neighbourhood) and the maxima mask, and follows the parent
+// chains inside the tile, so the parents never go to memory.
 //  - maxima: a wavefront covers two 32-cell rows, so its ballot is two aligned
 //    32-bit words of a linear-order bit mask; count / scan / write passes turn
-//    the mask into the sorted index list.
+//    the mask into the sorted index list (hf_maxima alone forms the maxima of
+//    32x8x8 tiles separably, x then y then z).
 //  - segmentation: parent chains are followed inside each 32x16x16 tile by
 //    pointer doubling in LDS, so every cell ends at a root or at the first cell
 //    its chain reaches outside the tile.  Such exit targets are always on a
@@ -204,60 +204,66 @@ __global__ void __launch_bounds__(SEG_THREADS) max_tile_kernel(const float *__re
     if (nan) atomicOr(status, ST_INPUT);
 }
 
-// Parent of every cell: parent[g] = the index of the largest key of g's 3x3x3
-// neighbourhood, or -1 for a root (its own parent) at or below tau.  With a
-// mask, the tile's maxima bits are written as well (the maxima are exactly the
-// cells that are their own parent, above tau).
+// Parents and the chains inside a resolve tile in one pass, one workgroup per
+// RX x RY x RZ tile.  A cell's parent is the index of the largest key of its
+// 3x3x3 neighbourhood, or -1 for a root (its own parent) at or below tau; with
+// a mask the tile's maxima bits are written as well (the maxima are exactly
+// the cells that are their own parent, above tau).
 //
-// One workgroup per WX x 8 x 8 tile (WX = 128 or 64 where n allows, else 32) keeps
-// the tile and a one-cell halo of the field in LDS as 32-bit order-preserving
-// bits (the index half of a key is formed in registers), and each thread walks
-// one z column of the tile: the largest key of each 3x3 halo plane around the
-// column is formed once, and a cell's parent is the largest of the three plane
-// maxima around it.  That is about 11 LDS reads of 4 bytes per cell; the wide
-// tiles read the field in long row pieces.
-template <int WX>
-__global__ void __launch_bounds__(WX * TY) parent_walk_kernel(const float *__restrict__ c, TileGrid tg,
-                                                              uint32_t tau_ord, int32_t *__restrict__ parent,
-                                                              uint32_t *__restrict__ mask, uint32_t *status) {
-    constexpr int THREADS = WX * TY;  // one z column each
-    constexpr int WHX = WX + 2, WCELLS = WHX * HY * HZ;
-    __shared__ uint32_t V[WCELLS];
+// The tile and a one-cell halo of the field sit in LDS as 32-bit
+// order-preserving bits (the index half of a key is formed in registers).
+// Each thread walks one z column: the largest key of each 3x3 halo plane
+// around the column is formed once, and a cell's parent is the largest of the
+// three plane maxima around it (about 10 LDS reads per cell).  The parents
+// then replace the field in LDS as the tile's pointer array, where chains are
+// followed by pointer doubling, so that on exit every cell holds its root (-1
+// for a root at or below tau) or the first cell its chain reaches outside the
+// tile; that goes to ptr and, for the tile's boundary cells, to bnd.  In LDS,
+// loc[e] >= 0 points to local cell loc[e]; loc[e] < 0 is resolved to the
+// value -2 - loc[e].
+constexpr int PR_THREADS = RX * RY;          // one z column each
+constexpr int PR_PER = RCELLS / PR_THREADS;  // RZ cells per thread
+static_assert(RHCELLS >= RCELLS, "the pointer array fits where the field was");
+
+__global__ void __launch_bounds__(PR_THREADS) parent_resolve_kernel(const float *__restrict__ c, TileGrid rg,
+                                                                    uint32_t tau_ord, int32_t *__restrict__ ptr,
+                                                                    int32_t *__restrict__ bnd,
+                                                                    uint32_t *__restrict__ mask, uint32_t *status) {
+    __shared__ uint32_t V[RHCELLS];
+    int32_t *loc = reinterpret_cast<int32_t *>(V);  // after the parents are formed
+    int x0, y0, z0;
     const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int x0 = int(tile % uint32_t(tg.ntx)) * WX;
-    const int y0 = int((tile / uint32_t(tg.ntx)) % uint32_t(tg.nty)) * TY;
-    const int z0 = int(tile / uint32_t(tg.ntx * tg.nty)) * TZ;
-    const int n = tg.n;
+    rtile_origin(rg, int(tile), x0, y0, z0);
+    const int n = rg.n;
     const uint32_t un = uint32_t(n);
     bool nan = false;
     {
         // all loads of the halo tile are issued before any is used
-        constexpr int LOADS = (WCELLS + THREADS - 1) / THREADS;
+        constexpr int LOADS = (RHCELLS + PR_THREADS - 1) / PR_THREADS;
         float v[LOADS];
 #pragma unroll
         for (int i = 0; i < LOADS; ++i) {
-            const int e = threadIdx.x + i * THREADS;
-            const int hx = e % WHX, hy = (e / WHX) % HY, hz = e / (WHX * HY);
-            if (e < WCELLS)
+            const int e = threadIdx.x + i * PR_THREADS;
+            const int hx = e % RHX, hy = (e / RHX) % RHY, hz = e / (RHX * RHY);
+            if (e < RHCELLS)
                 v[i] = c[(wrap(z0 + hz - 1, n) * un + wrap(y0 + hy - 1, n)) * un + wrap(x0 + hx - 1, n)];
         }
 #pragma unroll
         for (int i = 0; i < LOADS; ++i) {
-            const int e = threadIdx.x + i * THREADS;
-            if (e < WCELLS) V[e] = ordered_bits(v[i], nan);
+            const int e = threadIdx.x + i * PR_THREADS;
+            if (e < RHCELLS) V[e] = ordered_bits(v[i], nan);
         }
     }
     __syncthreads();
-    // the thread's column (x, y); a wavefront covers 64 consecutive x of one
-    // row (WX >= 64) or rows y and y + 1 (WX = 32)
-    const int x = threadIdx.x % WX, y = threadIdx.x / WX;
+    // the thread's column (x, y); a wavefront covers rows y and y + 1 of one z,
+    // so its ballot is two aligned 32-bit words of the mask
+    const int x = threadIdx.x % RX, y = threadIdx.x / RX;
     const int lane = threadIdx.x & 63;
-    uint32_t gx[3], gy[3], gyn[3];  // global x / y of the halo columns / rows x - 1 .. x + 1, y - 1 .. y + 1
+    uint32_t gx[3], gyn[3];  // global x of the halo columns x - 1 .. x + 1, and (global y) * n of the rows
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         gx[d] = wrap(x0 + x + d - 1, n);
-        gy[d] = wrap(y0 + y + d - 1, n);
-        gyn[d] = gy[d] * un;  // once per thread; the plane's part of the index is the same for the workgroup
+        gyn[d] = wrap(y0 + y + d - 1, n) * un;
     }
     // largest key of halo plane hz around the column
     auto plane_max = [&](int hz) {
@@ -268,91 +274,66 @@ __global__ void __launch_bounds__(WX * TY) parent_walk_kernel(const float *__res
             const uint32_t row = plane + gyn[dy];
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx)
-                best = kmax(best, (uint64_t(V[(hz * HY + y + dy) * WHX + x + dx]) << 32) | (row + gx[dx]));
+                best = kmax(best, (uint64_t(V[(hz * RHY + y + dy) * RHX + x + dx]) << 32) | (row + gx[dx]));
         }
         return best;
     };
+    int32_t l[PR_PER];
     uint64_t b0 = plane_max(0), b1 = plane_max(1);
 #pragma unroll
-    for (int z = 0; z < TZ; ++z) {
+    for (int z = 0; z < RZ; ++z) {
         const uint64_t b2 = plane_max(z + 2);
         const uint64_t best = kmax(kmax(b0, b1), b2);
-        const uint32_t g = (uint32_t(z0 + z) * un + gy[1]) * un + gx[1];
+        const uint32_t g = (uint32_t(z0 + z) * un + uint32_t(y0 + y)) * un + uint32_t(x0 + x);
         const uint32_t p = uint32_t(best);
         const bool high = uint32_t(best >> 32) > tau_ord;
         if (mask) {
             const unsigned long long bits = __ballot(p == g && high);
             if (lane == 0) {
                 mask[g >> 5] = uint32_t(bits);
-                mask[(g + (WX >= 64 ? 32u : un)) >> 5] = uint32_t(bits >> 32);
+                mask[(g + un) >> 5] = uint32_t(bits >> 32);
             }
         }
-        parent[g] = (p == g && !high) ? -1 : int32_t(p);
+        // local form: a root (above tau: itself; else -1) is resolved, so is
+        // a parent outside the tile; a parent inside is followed
+        l[z] = (p == g) ? (high ? -2 - int32_t(g) : -1) : -2 - int32_t(p);
+        if (p != g) {
+            uint32_t px, py, pz;
+            cell_coords(rg, p, px, py, pz);
+            const int lx = int(px) - x0, ly = int(py) - y0, lz = int(pz) - z0;
+            if (lx >= 0 && lx < RX && ly >= 0 && ly < RY && lz >= 0 && lz < RZ) l[z] = lx + RX * (ly + RY * lz);
+        }
         b0 = b1;
         b1 = b2;
     }
     if (nan) atomicOr(status, ST_INPUT);
-}
-
-// Chains resolved inside a resolve tile, in place: ptr[] holds parents on
-// entry and, on exit, each cell's root (-1 for a root at or below tau) or the
-// first cell its chain reaches outside the tile; bnd[] holds the same for the
-// tile's boundary cells.  In LDS, loc[e] >= 0 points to local cell loc[e];
-// loc[e] < 0 is resolved to the value -2 - loc[e].
-__global__ void __launch_bounds__(RES_THREADS) resolve_tile_kernel(int32_t *__restrict__ ptr, TileGrid rg,
-                                                                   int32_t *__restrict__ bnd) {
-    __shared__ int32_t loc[RCELLS];
-    int x0, y0, z0;
-    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    rtile_origin(rg, int(tile), x0, y0, z0);
-    const uint32_t n = uint32_t(rg.n);
-    int32_t v[RES_PER];
+    __syncthreads();  // every read of the field is done
 #pragma unroll
-    for (int i = 0; i < RES_PER; ++i) {
-        const int e = i * RES_THREADS + threadIdx.x;
-        const int x = e % RX, y = (e / RX) % RY, z = e / (RX * RY);
-        v[i] = ptr[((uint32_t(z0 + z) * n) + uint32_t(y0 + y)) * n + uint32_t(x0 + x)];
-    }
-#pragma unroll
-    for (int i = 0; i < RES_PER; ++i) {
-        const int e = i * RES_THREADS + threadIdx.x;
-        const int x = e % RX, y = (e / RX) % RY, z = e / (RX * RY);
-        const uint32_t g = ((uint32_t(z0 + z) * n) + uint32_t(y0 + y)) * n + uint32_t(x0 + x);
-        const int32_t p = v[i];
-        int32_t l = -2 - p;  // resolved: -1, a root, or a cell outside the tile
-        if (p >= 0 && uint32_t(p) != g) {
-            uint32_t px, py, pz;
-            cell_coords(rg, uint32_t(p), px, py, pz);
-            const int lx = int(px) - x0, ly = int(py) - y0, lz = int(pz) - z0;
-            if (lx >= 0 && lx < RX && ly >= 0 && ly < RY && lz >= 0 && lz < RZ) l = lx + RX * (ly + RY * lz);
-        }
-        loc[e] = l;
-    }
+    for (int z = 0; z < RZ; ++z) loc[threadIdx.x + z * PR_THREADS] = l[z];  // local cell x + RX (y + RY z)
     __syncthreads();
     // pointer doubling inside the tile (chains are at most RCELLS - 1 long)
     bool open = true;
     while (open) {
-        int32_t nv[RES_PER];
+        int32_t nv[PR_PER];
         bool any = false;
 #pragma unroll
-        for (int i = 0; i < RES_PER; ++i) {
-            const int32_t w = loc[i * RES_THREADS + threadIdx.x];
+        for (int i = 0; i < PR_PER; ++i) {
+            const int32_t w = loc[i * PR_THREADS + threadIdx.x];
             nv[i] = w >= 0 ? loc[w] : w;
             any |= nv[i] >= 0;
         }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < RES_PER; ++i) loc[i * RES_THREADS + threadIdx.x] = nv[i];
+        for (int i = 0; i < PR_PER; ++i) loc[i * PR_THREADS + threadIdx.x] = nv[i];
         open = __syncthreads_or(any);
     }
 #pragma unroll
-    for (int i = 0; i < RES_PER; ++i) {
-        const int e = i * RES_THREADS + threadIdx.x;
-        const int x = e % RX, y = (e / RX) % RY, z = e / (RX * RY);
-        const uint32_t g = ((uint32_t(z0 + z) * n) + uint32_t(y0 + y)) * n + uint32_t(x0 + x);
+    for (int i = 0; i < PR_PER; ++i) {
+        const int e = i * PR_THREADS + threadIdx.x;  // (x, y) of this thread, z = i
+        const uint32_t g = ((uint32_t(z0 + i) * un) + uint32_t(y0 + y)) * un + uint32_t(x0 + x);
         const int32_t t = -2 - loc[e];
         ptr[g] = t;
-        const int r = bnd_rank(x, y, z);
+        const int r = bnd_rank(x, y, i);
         if (r >= 0) bnd[int64_t(tile) * NBND + r] = t;
     }
 }
@@ -799,35 +780,24 @@ hf_status mask_to_list(hf_ctx *ctx, const MaximaLayout &L, char *w8, int32_t *ma
     return launch_status();
 }
 
-// Parents (and the maxima mask when given) of a tiled grid.
-hf_status launch_parents(hf_ctx *ctx, int n, const float *cwt, float tau, int32_t *parent, uint32_t *mask) {
-    const uint32_t tau_ord = host_ordered_bits(tau);
-    if (n % 128 == 0) {
-        const TileGrid wg{n, n / 128, n / TY, n / TZ, FastDiv(uint32_t(n))};
-        HF_LAUNCH(ctx, K_PARENT, parent_walk_kernel<128>, dim3(wg.ntx * wg.nty * wg.ntz), dim3(128 * TY), 0,
-                  ctx->stream, cwt, wg, tau_ord, parent, mask, ctx->d_status);
-    } else if (n % 64 == 0) {
-        const TileGrid wg{n, n / 64, n / TY, n / TZ, FastDiv(uint32_t(n))};
-        HF_LAUNCH(ctx, K_PARENT, parent_walk_kernel<64>, dim3(wg.ntx * wg.nty * wg.ntz), dim3(64 * TY), 0,
-                  ctx->stream, cwt, wg, tau_ord, parent, mask, ctx->d_status);
-    } else {
-        const TileGrid tg = tile_grid(n);
-        HF_LAUNCH(ctx, K_PARENT, parent_walk_kernel<TX>, dim3(tg.ntx * tg.nty * tg.ntz), dim3(TX * TY), 0,
-                  ctx->stream, cwt, tg, tau_ord, parent, mask, ctx->d_status);
-    }
+// Parents (and the maxima mask when given) of a tiled grid, with the chains
+// inside each resolve tile followed: ptr and bnd of the segmentation workspace.
+hf_status launch_parent_resolve(hf_ctx *ctx, const SegmentLayout &L, char *w8, int n, const float *cwt, float tau,
+                                uint32_t *mask) {
+    const TileGrid tg = resolve_grid(n);
+    HF_LAUNCH(ctx, K_PARENT, parent_resolve_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(PR_THREADS), 0,
+              ctx->stream, cwt, tg, host_ordered_bits(tau), reinterpret_cast<int32_t *>(w8 + L.ptr),
+              reinterpret_cast<int32_t *>(w8 + L.bnd), mask, ctx->d_status);
     return launch_status();
 }
 
-// After launch_parents has filled ptr with parents: chains resolved per
-// resolve tile, pointer-jumping rounds over the boundary entries, and the final
-// mapping through them.
+// After launch_parent_resolve: pointer-jumping rounds over the boundary
+// entries, and the final mapping through them.
 hf_status segment_finish(hf_ctx *ctx, const SegmentLayout &L, char *w8, int n, int32_t *cell_label) {
     const TileGrid tg = resolve_grid(n);
     auto *flags = reinterpret_cast<uint32_t *>(w8 + L.flags);
     auto *ptr = reinterpret_cast<int32_t *>(w8 + L.ptr);
     auto *bnd = reinterpret_cast<int32_t *>(w8 + L.bnd);
-    HF_LAUNCH(ctx, K_RESOLVE, resolve_tile_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(RES_THREADS), 0, ctx->stream,
-              ptr, tg, bnd);
     uint32_t *list[2], *counts[2];
     for (int b = 0; b < 2; ++b) {
         list[b] = reinterpret_cast<uint32_t *>(w8 + L.list[b]);
@@ -871,8 +841,7 @@ hf_status hf::maxima_segment(hf_ctx *ctx, const hf_box &box, const float *cwt, f
     auto *flags = reinterpret_cast<uint32_t *>(w8 + SL.flags);
     HF_LAUNCH(ctx, K_FLAGS, fill_flags_kernel, dim3((SL.rounds + 2 + 255) / 256), dim3(256), 0, ctx->stream, flags,
               SL.rounds + 2);
-    s = launch_parents(ctx, n, cwt, tau, reinterpret_cast<int32_t *>(w8 + SL.ptr),
-                       reinterpret_cast<uint32_t *>(wm + ML.mask));
+    s = launch_parent_resolve(ctx, SL, w8, n, cwt, tau, reinterpret_cast<uint32_t *>(wm + ML.mask));
     if (s != HF_OK) return s;
     s = mask_to_list(ctx, ML, wm, max_idx, max_cap, d_count);
     if (s != HF_OK) return s;
@@ -920,7 +889,7 @@ extern "C" hf_status hf_segment(hf_ctx *ctx, const hf_box *box, const float *cwt
     HF_LAUNCH(ctx, K_FLAGS, fill_flags_kernel, dim3((L.rounds + 2 + 255) / 256), dim3(256), 0, ctx->stream, flags,
               L.rounds + 2);
     if (tiled(n)) {
-        s = launch_parents(ctx, n, cwt, tau, reinterpret_cast<int32_t *>(w8 + L.ptr), nullptr);
+        s = launch_parent_resolve(ctx, L, w8, n, cwt, tau, nullptr);
         if (s != HF_OK) return s;
         return segment_finish(ctx, L, w8, n, cell_label);
     } else {
