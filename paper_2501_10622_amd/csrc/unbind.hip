@@ -16,10 +16,13 @@
 // the member order -- and with it every floating-point sum -- does not depend
 // on the order the atomics resolved in.  The workgroup then iterates the
 // rounds: FP64 reductions for the centre and mean velocity, each member's
-// radius and speed, and the potential by a pass over all members in
-// LDS-staged tiles (O(N^2) per round: groups hold tens to tens of thousands of
-// particles, and the pass needs no sort by radius).  The ties of equal radii
-// are broken by particle index, the order the definition uses.
+// radius and speed, then the remaining members sorted by (radius, member
+// position) -- chunks of UB_CHUNK sorted in LDS, then merged pairwise in
+// global memory -- so that a member's inner count is its sorted position plus
+// one and its outer sum a suffix sum of 1 / r over the sorted order, formed
+// block by block from the outermost inward (O(N log N) per round).  Member
+// positions follow particle indices, so equal radii are ordered by particle
+// index, the order the definition uses.
 #include <cmath>
 
 #include "hf_internal.h"
@@ -30,13 +33,13 @@ using namespace hf;
 namespace {
 
 constexpr int UB_THREADS = 256;
-constexpr int UB_TILE = 1024;          // members per LDS tile of the potential pass
-constexpr int UB_MPT = 4;              // members each thread takes per pass over the tiles
-constexpr int UB_SORT_LDS = 8192;      // runs up to this many members are sorted in LDS
+constexpr int UB_CHUNK = 4096;           // members sorted by radius per LDS pass
+constexpr int UB_LDS_WORDS = 3 * UB_CHUNK;  // LDS sort buffer: radii (8 B) and member positions (4 B)
+constexpr int UB_SORT_LDS = UB_LDS_WORDS;   // runs of up to this many particle indices are sorted in LDS
 constexpr int SCAN_GROUPS = 2;         // scan tag of this use
 
 struct UnbindLayout {
-    size_t slot, cnt, start, cursor, partial, pid, rad, inv, spd, alive, total;
+    size_t slot, cnt, start, cursor, partial, queue, pid, rad, ord, tmp, spd, alive, total;
 };
 
 UnbindLayout unbind_layout(int n, int64_t np, int64_t nroots) {
@@ -52,9 +55,11 @@ UnbindLayout unbind_layout(int n, int64_t np, int64_t nroots) {
     L.start = take(sizeof(uint32_t) * size_t(nroots + 1));
     L.cursor = take(sizeof(uint32_t) * size_t(nroots > 0 ? nroots : 1));
     L.partial = take(sizeof(uint64_t) * SCAN_MAX_GROUPS);
+    L.queue = take(2 * sizeof(uint32_t));
     L.pid = take(sizeof(int32_t) * size_t(np > 0 ? np : 1));
     L.rad = take(sizeof(double) * size_t(np > 0 ? np : 1));
-    L.inv = take(sizeof(double) * size_t(np > 0 ? np : 1));
+    L.ord = take(sizeof(uint32_t) * size_t(np > 0 ? np : 1));
+    L.tmp = take(sizeof(uint32_t) * size_t(np > 0 ? np : 1));
     L.spd = take(sizeof(double) * size_t(np > 0 ? np : 1));
     L.alive = take(sizeof(uint8_t) * size_t(np > 0 ? np : 1));
     L.total = off;
@@ -74,12 +79,15 @@ unsigned ub_grid(const hf_ctx *ctx, int64_t work) {
     return unsigned(want < 1 ? 1 : (want > cap ? cap : want));
 }
 
-// slot[root_i] = i for every root; cnt[i] = cursor[i] = 0 over the capacity.
+// slot[root_i] = i for every root; cnt[i] = cursor[i] = 0 over the capacity;
+// the group kernel's two work counters to 0.
 __global__ void __launch_bounds__(UB_THREADS) ub_slots_kernel(const int32_t *__restrict__ roots,
                                                               const int64_t *d_count, int64_t cap, int64_t ncells,
                                                               uint32_t *__restrict__ slot, uint32_t *__restrict__ cnt,
-                                                              uint32_t *__restrict__ cur, uint32_t *status) {
+                                                              uint32_t *__restrict__ cur, uint32_t *__restrict__ queue,
+                                                              uint32_t *status) {
     const int64_t nroots = ub_roots(d_count, cap);
+    if (blockIdx.x == 0 && threadIdx.x < 2) queue[threadIdx.x] = 0u;  // the group kernel's work counters
     bool bad = false;
     for (int64_t i = blockIdx.x * int64_t(UB_THREADS) + threadIdx.x; i < cap; i += int64_t(gridDim.x) * UB_THREADS) {
         cnt[i] = 0u;
@@ -208,33 +216,112 @@ __device__ __forceinline__ double unwrap(double d, double box_len) {
     return d;
 }
 
-// One workgroup per root: the kept groups' check, then their labels.
-template <typename T>
-__global__ void __launch_bounds__(UB_THREADS)
-    ub_group_kernel(const T *__restrict__ pos, const T *__restrict__ vel, int32_t *__restrict__ label,
-                    const int32_t *__restrict__ roots, const int64_t *d_count, const uint8_t *__restrict__ keep,
-                    const uint32_t *__restrict__ start, int32_t *__restrict__ pid, double *__restrict__ rad,
-                    double *__restrict__ inv, double *__restrict__ spd, uint8_t *__restrict__ alive, int n,
-                    double box_len, double gm, int64_t particle_th, uint8_t *__restrict__ bound_keep) {
-    __shared__ double red[UB_THREADS / 64];
-    __shared__ double tr[UB_TILE];
-    __shared__ double tinv[UB_TILE];
-    __shared__ int32_t tid_[UB_TILE];
-    __shared__ uint8_t tal[UB_TILE];
-    __shared__ int32_t sort_lds[UB_SORT_LDS];
-    __shared__ uint32_t s_count[2];
-    const uint32_t g = blockIdx.x;
-    if (int64_t(g) >= ub_roots(d_count, int64_t(gridDim.x))) return;  // past the list's count
-    if (!keep[g]) {
-        if (threadIdx.x == 0) bound_keep[g] = 0;
-        return;
+// (R[x], x) < (R[y], y): radius first, then member position.
+__device__ __forceinline__ bool by_radius(const double *R, uint32_t x, uint32_t y) {
+    const double a = R[x], b = R[y];
+    return a < b || (a == b && x < y);
+}
+
+// One merge of sorted runs a[0..na) and b[0..nb) into out by the workgroup:
+// each thread finds where its share of the output starts on the merge path
+// (a binary search), then merges its share in order.
+__device__ void merge_runs(const uint32_t *a, int na, const uint32_t *b, int nb, uint32_t *out, const double *R) {
+    const int total = na + nb;
+    const int per = (total + UB_THREADS - 1) / UB_THREADS;
+    const int o0 = int(threadIdx.x) * per;
+    if (o0 >= total) return;
+    const int o1 = o0 + per < total ? o0 + per : total;
+    int lo = o0 - nb > 0 ? o0 - nb : 0, hi = o0 < na ? o0 : na;
+    while (lo < hi) {  // how many of the first o0 outputs come from a
+        const int i = (lo + hi) >> 1;
+        if (by_radius(R, a[i], b[o0 - i - 1])) lo = i + 1;
+        else hi = i;
     }
+    int i = lo, j = o0 - lo;
+    for (int o = o0; o < o1; ++o) {
+        const bool from_a = j >= nb || (i < na && by_radius(R, a[i], b[j]));
+        out[o] = from_a ? a[i++] : b[j++];
+    }
+}
+
+// Sorts the member positions ord[0..m) by (R, position) with the workgroup:
+// runs of UB_CHUNK in LDS (the all-ascending bitonic network over (radius,
+// position) pairs, places past the run taken as +infinity), then pairwise
+// merges between ord and tmp.  Returns the array that holds the result.
+__device__ uint32_t *sort_by_radius(const double *R, uint32_t *ord, uint32_t *tmp, int m, double *skey,
+                                    uint32_t *sidx) {
+    for (int c0 = 0; c0 < m; c0 += UB_CHUNK) {
+        const int len = m - c0 < UB_CHUNK ? m - c0 : UB_CHUNK;
+        for (int k = threadIdx.x; k < len; k += UB_THREADS) {
+            const uint32_t x = ord[c0 + k];
+            sidx[k] = x;
+            skey[k] = R[x];
+        }
+        __syncthreads();
+        int p2 = 1;
+        while (p2 < len) p2 <<= 1;
+        auto cswap = [&](int lo, int hi) {
+            if (hi >= len) return;  // hi is +infinity: nothing moves
+            const double a = skey[lo], b = skey[hi];
+            const uint32_t x = sidx[lo], y = sidx[hi];
+            if (b < a || (b == a && y < x)) {
+                skey[lo] = b;
+                skey[hi] = a;
+                sidx[lo] = y;
+                sidx[hi] = x;
+            }
+        };
+        for (int size = 2; size <= p2; size <<= 1) {
+            const int half = size >> 1;
+            for (int t = threadIdx.x; t < p2 / 2; t += UB_THREADS) {
+                const int q = t % half, b = (t / half) * size;
+                cswap(b + q, b + size - 1 - q);
+            }
+            __syncthreads();
+            for (int stride = half >> 1; stride > 0; stride >>= 1) {
+                for (int t = threadIdx.x; t < p2 / 2; t += UB_THREADS) {
+                    const int lo = 2 * t - (t & (stride - 1));
+                    cswap(lo, lo + stride);
+                }
+                __syncthreads();
+            }
+        }
+        for (int k = threadIdx.x; k < len; k += UB_THREADS) ord[c0 + k] = sidx[k];
+        __syncthreads();
+    }
+    uint32_t *src = ord, *dst = tmp;
+    for (int w = UB_CHUNK; w < m; w *= 2) {
+        for (int a = 0; a < m; a += 2 * w) {
+            const int na = m - a < w ? m - a : w;
+            const int nb = m - a - na < w ? m - a - na : w;
+            merge_runs(src + a, na, src + a + na, nb, dst + a, R);
+        }
+        __syncthreads();
+        uint32_t *t = src;
+        src = dst;
+        dst = t;
+    }
+    return src;
+}
+
+// The check of kept group g (steps 9-10) by the whole workgroup: its members
+// sorted by particle index, then the rounds, the decision and the labels.
+template <typename T>
+__device__ void check_group(uint32_t g, const T *__restrict__ pos, const T *__restrict__ vel,
+                            int32_t *__restrict__ label, const int32_t *__restrict__ roots,
+                            const uint32_t *__restrict__ start, int32_t *__restrict__ pid, double *__restrict__ rad,
+                            uint32_t *__restrict__ ordb, uint32_t *__restrict__ tmpb, double *__restrict__ spd,
+                            uint8_t *__restrict__ alive, int n, double box_len, double gm, int64_t particle_th,
+                            uint8_t *__restrict__ bound_keep, double *red, double *lds, uint32_t *s_count) {
     const uint32_t s0 = start[g];
     const int m0 = int(start[g + 1] - s0);
     int32_t *P = pid + s0;
-    double *R = rad + s0, *I = inv + s0, *S = spd + s0;
+    double *R = rad + s0, *S = spd + s0;
+    uint32_t *ord = ordb + s0, *tmp = tmpb + s0;
     uint8_t *A = alive + s0;
-    block_sort(P, m0, sort_lds, UB_SORT_LDS);
+    double *skey = lds;                                          // [UB_CHUNK]
+    uint32_t *sidx = reinterpret_cast<uint32_t *>(lds + UB_CHUNK);  // [UB_CHUNK]
+    block_sort(P, m0, reinterpret_cast<int32_t *>(lds), UB_SORT_LDS);
     const uint32_t un = uint32_t(n), r0 = uint32_t(roots[g]);
     const double dx = box_len / double(n);
     const double ref[3] = {__dmul_rn(double(r0 % un), dx), __dmul_rn(double((r0 / un) % un), dx),
@@ -272,61 +359,61 @@ __global__ void __launch_bounds__(UB_THREADS)
                 r2 = __dadd_rn(r2, __dmul_rn(e, e));
                 s2 = __dadd_rn(s2, __dmul_rn(w, w));
             }
-            const double r = __dsqrt_rn(r2);
-            R[k] = r;
-            I[k] = __ddiv_rn(1.0, r);  // each member's 1 / r, once per round (inf at r = 0)
+            R[k] = __dsqrt_rn(r2);
             S[k] = s2;
         }
+        // the remaining members' positions, in order
+        {
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            uint32_t base = 0;
+            for (int k0 = 0; k0 < m0; k0 += UB_THREADS) {
+                const int k = k0 + int(threadIdx.x);
+                const bool live = k < m0 && A[k] != 0;
+                const unsigned long long bits = __ballot(live);
+                if (lane == 0) s_count[2 + wave] = uint32_t(__popcll(bits));
+                __syncthreads();
+                uint32_t before = base;
+                for (int w = 0; w < wave; ++w) before += s_count[2 + w];
+                if (live) ord[before + __popcll(bits & ((1ull << lane) - 1ull))] = uint32_t(k);
+                for (int w = 0; w < UB_THREADS / 64; ++w) base += s_count[2 + w];
+                __syncthreads();
+            }
+        }
+        const uint32_t *srt = sort_by_radius(R, ord, tmp, m, skey, sidx);
         if (threadIdx.x == 0) s_count[0] = 0u;
-        __syncthreads();
-        // the shell potential at each remaining member, over LDS tiles of all
-        // members; a leaver is marked 2 (still counted this round)
+        // the shell potential at each remaining member from its sorted position
+        // p: (p + 1) / r inside, plus the suffix sum of 1 / r of the members
+        // after it, formed block by block from the outermost inward; a leaver
+        // is marked 2 (still counted this round)
         uint32_t leaving = 0;
-        for (int i0 = 0; i0 < m0; i0 += UB_THREADS * UB_MPT) {
-            bool mine[UB_MPT];
-            double ri[UB_MPT], outer[UB_MPT];
-            int32_t pi[UB_MPT];
-            uint32_t inner[UB_MPT];
+        {
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            double carry = 0.0;
+            for (int b = ((m - 1) / UB_THREADS) * UB_THREADS; b >= 0; b -= UB_THREADS) {
+                const int p = b + int(threadIdx.x);
+                const uint32_t x = p < m ? srt[p] : 0u;
+                const double r = p < m ? R[x] : 0.0;
+                const double v = p < m ? __ddiv_rn(1.0, r) : 0.0;  // inf at r = 0
+                double incl = v;  // sum over this lane and the later lanes of the wavefront
 #pragma unroll
-            for (int q = 0; q < UB_MPT; ++q) {
-                const int i = i0 + q * UB_THREADS + int(threadIdx.x);
-                mine[q] = i < m0 && A[i] != 0;
-                ri[q] = mine[q] ? R[i] : 0.0;
-                pi[q] = mine[q] ? P[i] : 0;
-                inner[q] = 0;
-                outer[q] = 0.0;
-            }
-            for (int base = 0; base < m0; base += UB_TILE) {
-                const int tile = m0 - base < UB_TILE ? m0 - base : UB_TILE;
-                __syncthreads();
-                for (int k = threadIdx.x; k < tile; k += UB_THREADS) {
-                    tal[k] = A[base + k] != 0;
-                    tr[k] = R[base + k];
-                    tinv[k] = I[base + k];
-                    tid_[k] = P[base + k];
+                for (int off = 1; off < 64; off <<= 1) {
+                    const double y = __shfl_down(incl, off, 64);
+                    if (lane + off < 64) incl = __dadd_rn(incl, y);
                 }
+                const double after = __shfl_down(incl, 1, 64);
+                if (lane == 0) red[wave] = incl;
                 __syncthreads();
-                for (int k = 0; k < tile; ++k) {
-                    if (!tal[k]) continue;
-                    const double rj = tr[k], ij = tinv[k];
-                    const int32_t pj = tid_[k];
-#pragma unroll
-                    for (int q = 0; q < UB_MPT; ++q) {
-                        // at or inside (r_i, i): a point mass at the centre; outside: its own shell
-                        const bool in = rj < ri[q] || (rj == ri[q] && pj <= pi[q]);
-                        inner[q] += in ? 1u : 0u;
-                        if (!in) outer[q] = __dadd_rn(outer[q], ij);
+                double later = lane < 63 ? after : 0.0;
+                for (int w = wave + 1; w < UB_THREADS / 64; ++w) later = __dadd_rn(later, red[w]);
+                const double outer = __dadd_rn(later, carry);
+                for (int w = 0; w < UB_THREADS / 64; ++w) carry = __dadd_rn(carry, red[w]);
+                __syncthreads();
+                if (p < m) {
+                    const double phi = -__dmul_rn(gm, __dadd_rn(__ddiv_rn(double(p + 1), r), outer));
+                    if (S[x] > __dmul_rn(-2.0, phi)) {
+                        A[x] = 2;
+                        ++leaving;
                     }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < UB_MPT; ++q) {
-                if (!mine[q]) continue;
-                const int i = i0 + q * UB_THREADS + int(threadIdx.x);
-                const double phi = -__dmul_rn(gm, __dadd_rn(__ddiv_rn(double(inner[q]), ri[q]), outer[q]));
-                if (S[i] > __dmul_rn(-2.0, phi)) {
-                    A[i] = 2;
-                    ++leaving;
                 }
             }
         }
@@ -344,6 +431,61 @@ __global__ void __launch_bounds__(UB_THREADS)
     if (threadIdx.x == 0) bound_keep[g] = ok ? 1 : 0;
     for (int k = threadIdx.x; k < m0; k += UB_THREADS)
         if (!ok || !A[k]) label[P[k]] = -1;
+    __syncthreads();  // the workgroup's LDS is free for the next group
+}
+
+// Persistent: each workgroup takes the next UB_BATCH roots from a work
+// counter until the list's count is reached (a grid of one workgroup per root
+// would be mostly workgroups with nothing to do: the capacity is far above the
+// count, and most groups are not kept).  The batch's kept groups are checked
+// one after the other, then their labels.  Two sweeps over the list, each with
+// its own counter: first the groups of at least UB_BIG members, then the rest,
+// so that the longest checks start first and the short ones fill in around
+// them.
+constexpr int UB_BATCH = 64;
+constexpr uint32_t UB_BIG = 2048;
+
+template <typename T>
+__global__ void __launch_bounds__(UB_THREADS)
+    ub_group_kernel(const T *__restrict__ pos, const T *__restrict__ vel, int32_t *__restrict__ label,
+                    const int32_t *__restrict__ roots, const int64_t *d_count, int64_t cap,
+                    const uint8_t *__restrict__ keep, const uint32_t *__restrict__ start, uint32_t *queue,
+                    int32_t *__restrict__ pid, double *__restrict__ rad, uint32_t *__restrict__ ordb,
+                    uint32_t *__restrict__ tmpb, double *__restrict__ spd, uint8_t *__restrict__ alive, int n, double box_len, double gm,
+                    int64_t particle_th, uint8_t *__restrict__ bound_keep) {
+    static_assert(UB_BATCH <= UB_THREADS, "one root per thread of a batch");
+    __shared__ double red[UB_THREADS / 64];
+    __shared__ double lds[UB_LDS_WORDS / 2];         // the sorts' LDS (radii and positions, or particle indices)
+    __shared__ uint32_t s_count[2 + UB_THREADS / 64];  // leavers of a round, then per-wavefront counts
+    __shared__ uint32_t s_next, s_nlist, s_list[UB_BATCH];
+    const int64_t count = ub_roots(d_count, cap);
+    for (int sweep = 0; sweep < 2;) {
+        if (threadIdx.x == 0) {
+            s_next = atomicAdd(queue + sweep, uint32_t(UB_BATCH));
+            s_nlist = 0u;
+        }
+        __syncthreads();
+        const uint32_t g0 = s_next;
+        if (int64_t(g0) >= count) {
+            ++sweep;
+            __syncthreads();  // s_next is read before the next take
+            continue;
+        }
+        if (threadIdx.x < UB_BATCH && int64_t(g0) + threadIdx.x < count) {
+            const uint32_t g = g0 + threadIdx.x;
+            if (!keep[g]) {
+                if (sweep == 0) bound_keep[g] = 0;
+            } else if ((start[g + 1] - start[g] >= UB_BIG) == (sweep == 0)) {
+                s_list[atomicAdd(&s_nlist, 1u)] = g;  // the order of the checks does not matter
+            }
+        }
+        __syncthreads();
+        const uint32_t nl = s_nlist;
+        for (uint32_t q = 0; q < nl; ++q)
+            check_group(s_list[q], pos, vel, label, roots, start, pid, rad, ordb, tmpb, spd, alive, n, box_len, gm,
+                        particle_th, bound_keep, red, lds, s_count);
+        __syncthreads();  // the batch's list is read before the next take rewrites it
+    }
 }
 
 // The identification loop: particles this scale claimed whose label the check
@@ -384,13 +526,15 @@ hf_status hf::unbind_dev(hf_ctx *ctx, const hf_box &box, const void *pos, const 
     auto *partial = reinterpret_cast<uint64_t *>(w + L.partial);
     auto *pid = reinterpret_cast<int32_t *>(w + L.pid);
     auto *rad = reinterpret_cast<double *>(w + L.rad);
-    auto *inv = reinterpret_cast<double *>(w + L.inv);
+    auto *ordb = reinterpret_cast<uint32_t *>(w + L.ord);
+    auto *tmpb = reinterpret_cast<uint32_t *>(w + L.tmp);
     auto *spd = reinterpret_cast<double *>(w + L.spd);
     auto *alive = reinterpret_cast<uint8_t *>(w + L.alive);
     const int64_t ncells = int64_t(box.n) * box.n * box.n;
     hipStream_t st = ctx->stream;
+    auto *queue = reinterpret_cast<uint32_t *>(w + L.queue);
     HF_LAUNCH(ctx, K_UNBIND, ub_slots_kernel, dim3(ub_grid(ctx, nroots)), dim3(UB_THREADS), 0, st, roots, d_count,
-              nroots, ncells, slot, cnt, cur, ctx->d_status);
+              nroots, ncells, slot, cnt, cur, queue, ctx->d_status);
     if (np > 0)
         HF_LAUNCH(ctx, K_UNBIND, ub_count_kernel, dim3(ub_grid(ctx, np)), dim3(UB_THREADS), 0, st, label, np, roots,
                   d_count, nroots, ncells, slot, keep, cnt, ctx->d_status);
@@ -400,14 +544,19 @@ hf_status hf::unbind_dev(hf_ctx *ctx, const hf_box &box, const void *pos, const 
     if (np > 0)
         HF_LAUNCH(ctx, K_UNBIND, ub_gather_kernel, dim3(ub_grid(ctx, np)), dim3(UB_THREADS), 0, st, label, np, slot,
                   start, cur, pid);
+    // a few resident workgroups per CU take the groups from the work counter
+    const int64_t wgs = int64_t(ctx->cus) * 4;
+    const dim3 grid(unsigned(nroots < wgs ? nroots : wgs));
     if (dtype == HF_F32)
-        HF_LAUNCH(ctx, K_UNBIND, ub_group_kernel<float>, dim3(unsigned(nroots)), dim3(UB_THREADS), 0, st,
-                  static_cast<const float *>(pos), static_cast<const float *>(vel), label, roots, d_count, keep,
-                  start, pid, rad, inv, spd, alive, box.n, box.box_len, grav_mass, particle_th, bound_keep);
+        HF_LAUNCH(ctx, K_UNBIND, ub_group_kernel<float>, grid, dim3(UB_THREADS), 0, st,
+                  static_cast<const float *>(pos), static_cast<const float *>(vel), label, roots, d_count, nroots,
+                  keep, start, queue, pid, rad, ordb, tmpb, spd, alive, box.n, box.box_len, grav_mass, particle_th,
+                  bound_keep);
     else
-        HF_LAUNCH(ctx, K_UNBIND, ub_group_kernel<double>, dim3(unsigned(nroots)), dim3(UB_THREADS), 0, st,
-                  static_cast<const double *>(pos), static_cast<const double *>(vel), label, roots, d_count, keep,
-                  start, pid, rad, inv, spd, alive, box.n, box.box_len, grav_mass, particle_th, bound_keep);
+        HF_LAUNCH(ctx, K_UNBIND, ub_group_kernel<double>, grid, dim3(UB_THREADS), 0, st,
+                  static_cast<const double *>(pos), static_cast<const double *>(vel), label, roots, d_count, nroots,
+                  keep, start, queue, pid, rad, ordb, tmpb, spd, alive, box.n, box.box_len, grav_mass, particle_th,
+                  bound_keep);
     return launch_status();
 }
 
