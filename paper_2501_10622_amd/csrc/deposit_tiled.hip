@@ -7,10 +7,13 @@
 //       records = the three fixed-point coordinates q (12 bytes);
 //   L2  partition each bucket by tile (TX x 8 x 8 cells, TX = 64, 32 or 16),
 //       records = cell-in-tile and fraction bits packed into 8 bytes;
-//   ACC one workgroup per tile accumulates its particles' eight CIC weights in
-//       LDS int64 over the tile plus its +x/+y/+z skirt ((TX+1) x 9 x 9 cells),
-//       writes the owned cells once and the skirt sums to a side buffer;
-//   FOLD each tile adds the skirt sums of its lower neighbours to its low faces.
+//   ACC one workgroup per row of tiles along x takes the row's tiles in order:
+//       each tile's particles' eight CIC weights are accumulated in LDS int64
+//       over the tile plus its +x/+y/+z skirt ((TX+1) x 9 x 9 cells), the owned
+//       cells written once, the y and z skirt faces to a side buffer, and the x
+//       face carried in LDS into the next tile of the row;
+//   FOLD each tile adds the y- and z-face sums of its lower neighbours to its
+//       y = 0 and z = 0 cells (whole rows).
 //
 // Level-1 records are stored replica-major: the scatter chunks of one counter
 // replica (all on one XCD) write only into that replica's region, where the
@@ -91,7 +94,7 @@ struct Geom {
     int nbuckets;       // nbx * nby * nbz
     int digits;         // btx * bty * btz tiles per bucket
     int ntiles;         // ntx * nty * ntz
-    int skirt;          // skirt cells per tile: 81 + 17 tx
+    int skirt;          // side-buffer cells per tile (y and z faces): 17 tx
     int bits;           // fraction bits B
     FastDiv cbx, cby, cbz;  // cells per bucket along x, y, z
     FastDiv tbx, tby, tbz;  // tiles per bucket along x, y, z
@@ -675,75 +678,120 @@ __device__ __forceinline__ void accumulate(const uint64_t *__restrict__ rec2, ui
     }
 }
 
-// Skirt cells of a tile, in side-buffer order: the x face (x = tx, y and z in
-// [0, 8]), the y face (y = 8, x < tx, z in [0, 8]), the z face (z = 8, x < tx, y < 8).
+// Skirt cells of a tile, in side-buffer order: the y face (y = 8, x < tx, z in
+// [0, 8]), then the z face (z = 8, x < tx, y < 8).  The x face (x = tx) is not
+// stored: it is carried to the next tile of the row in LDS.
 __device__ __forceinline__ void skirt_cell(int tx, int s, int &x, int &y, int &z) {
-    const int fx = AYZ * AYZ, fy = tx * AYZ;
-    if (s < fx) {
-        x = tx;
-        y = s % AYZ;
-        z = s / AYZ;
-    } else if (s < fx + fy) {
-        const int j = s - fx;
-        x = j % tx;
+    const int fy = tx * AYZ;
+    if (s < fy) {
+        x = s % tx;
         y = TYZ;
-        z = j / tx;
+        z = s / tx;
     } else {
-        const int j = s - fx - fy;
+        const int j = s - fy;
         x = j % tx;
         y = j / tx;
         z = TYZ;
     }
 }
 
-__device__ __forceinline__ int skirt_index(int tx, int x, int y, int z) {
-    const int fx = AYZ * AYZ, fy = tx * AYZ;
-    if (x == tx) return z * AYZ + y;
-    if (y == TYZ) return fx + z * tx + x;
-    return fx + fy + y * tx + x;
+// Level-2 slot (bucket, tile in bucket) of the tile at tile coordinates (tx, ty, tz).
+__device__ __forceinline__ int tile_slot(const Geom &g, int tx, int ty, int tz) {
+    const int bx = tx / g.btx, by = ty / g.bty, bz = tz / g.btz;
+    const int ux = tx - bx * g.btx, uy = ty - by * g.bty, uz = tz - bz * g.btz;
+    return ((bz * g.nby + by) * g.nbx + bx) * g.digits + (uz * g.bty + uy) * g.btx + ux;
 }
 
-// One workgroup per tile, in level-2 (bucket, tile-in-bucket) order.
+// One workgroup per row of tiles along x (fixed tile y and z), the tiles in
+// order: each tile's particles are accumulated in LDS over the tile plus its
+// +x/+y/+z skirt; the owned cells go to the grid, the y and z faces to the
+// side buffer, and the x face (x = tx, all y and z in [0, 8]) stays in LDS as
+// the x = 0 plane of the next tile, so no x face is ever folded through memory.
+// The last tile's x face belongs to the first tile of the row (periodic): it
+// is added to that tile's cells and side-buffer entries at the end.
 __global__ void __launch_bounds__(ACC_THREADS) tile_accum_kernel(const uint64_t *__restrict__ rec2,
                                                                  const uint32_t *__restrict__ start2, Geom g,
                                                                  unsigned long long *__restrict__ rho,
                                                                  unsigned long long *__restrict__ skirt,
                                                                  uint32_t *status) {
     __shared__ unsigned long long acc[MAX_ACC_CELLS];
-    const int slot = blockIdx.x;
-    const int b = slot / g.digits, d = slot % g.digits;
-    int tx, ty, tz;
-    tile_coords(g, b, d, tx, ty, tz);
+    int ty, tz;
+    if (g.btx == g.ntx) {
+        // rows of a bucket are whole rows: bucket-major row order, so each row's
+        // records are one run of the level-2 order and neighbouring workgroups
+        // read neighbouring runs
+        const int rows = g.bty * g.btz, b = int(blockIdx.x) / rows, r = int(blockIdx.x) % rows;
+        ty = ((b / g.nbx) % g.nby) * g.bty + r % g.bty;
+        tz = (b / (g.nbx * g.nby)) * g.btz + r / g.bty;
+    } else {
+        ty = int(blockIdx.x) % g.nty;
+        tz = int(blockIdx.x) / g.nty;
+    }
     const int ax = g.tx + 1;
     const int ncells = ax * AYZ * AYZ;
-    for (int c = threadIdx.x; c < ncells; c += ACC_THREADS) acc[c] = 0ull;
-    __syncthreads();
-    const uint32_t lo = start2[slot], hi = start2[slot + 1];
-    bool overflow = false;
-    // fewer than 2^(63 - 3B) particles cannot carry any cell of this tile past 2^63 - 1
-    if (uint64_t(hi - lo) < (1ull << (63 - 3 * g.bits)))
-        accumulate<false>(rec2, lo, hi, g.bits, ax, acc, overflow);
-    else
-        accumulate<true>(rec2, lo, hi, g.bits, ax, acc, overflow);
-    __syncthreads();
     const size_t n = size_t(g.n);
-    const size_t gx0 = size_t(tx) * g.tx, gy0 = size_t(ty) * TYZ, gz0 = size_t(tz) * TYZ;
+    const size_t gy0 = size_t(ty) * TYZ, gz0 = size_t(tz) * TYZ;
     const int owned = g.tx * TYZ * TYZ;
-    for (int c = threadIdx.x; c < owned; c += ACC_THREADS) {
-        const int x = c & (g.tx - 1), y = (c >> g.ltx) & (TYZ - 1), z = c >> (g.ltx + 3);
-        rho[((gz0 + z) * n + gy0 + y) * n + gx0 + x] = acc[(z * AYZ + y) * ax + x];
+    constexpr int FACE = AYZ * AYZ;  // cells of the x face
+    bool overflow = false;
+    uint32_t prev = 0;  // particles of the previous tile, whose x face is carried in
+    for (int tx = 0; tx < g.ntx; ++tx) {
+        unsigned long long carried = 0ull;
+        if (tx > 0 && threadIdx.x < FACE) carried = acc[threadIdx.x * ax + g.tx];  // (z, y) = (k / 9, k % 9)
+        __syncthreads();
+        for (int c = threadIdx.x; c < ncells; c += ACC_THREADS) acc[c] = 0ull;
+        __syncthreads();
+        if (tx > 0 && threadIdx.x < FACE) acc[threadIdx.x * ax] = carried;
+        __syncthreads();
+        const int slot = tile_slot(g, tx, ty, tz);
+        const uint32_t lo = start2[slot], hi = start2[slot + 1];
+        // fewer than 2^(63 - 3B) particles (with those carried in) cannot carry
+        // any cell of this tile past 2^63 - 1
+        if (uint64_t(hi - lo) + prev < (1ull << (63 - 3 * g.bits)))
+            accumulate<false>(rec2, lo, hi, g.bits, ax, acc, overflow);
+        else
+            accumulate<true>(rec2, lo, hi, g.bits, ax, acc, overflow);
+        prev = hi - lo;
+        __syncthreads();
+        const size_t gx0 = size_t(tx) * g.tx;
+        for (int c = threadIdx.x; c < owned; c += ACC_THREADS) {
+            const int x = c & (g.tx - 1), y = (c >> g.ltx) & (TYZ - 1), z = c >> (g.ltx + 3);
+            rho[((gz0 + z) * n + gy0 + y) * n + gx0 + x] = acc[(z * AYZ + y) * ax + x];
+        }
+        const size_t tglob = (size_t(tz) * g.nty + ty) * g.ntx + tx;
+        for (int k = threadIdx.x; k < g.skirt; k += ACC_THREADS) {
+            int x, y, z;
+            skirt_cell(g.tx, k, x, y, z);
+            skirt[tglob * g.skirt + k] = acc[(z * AYZ + y) * ax + x];
+        }
     }
-    const size_t tglob = (size_t(tz) * g.nty + ty) * g.ntx + tx;
-    for (int k = threadIdx.x; k < g.skirt; k += ACC_THREADS) {
-        int x, y, z;
-        skirt_cell(g.tx, k, x, y, z);
-        skirt[tglob * g.skirt + k] = acc[(z * AYZ + y) * ax + x];
+    // the last x face onto the row's first tile (x = 0 there): its owned cells
+    // in the grid, its y = 8 and z = 8 cells in the side buffer, all written by
+    // this workgroup above (the barrier's workgroup-scope ordering makes them
+    // visible here; a device-scope fence would write the L2 back)
+    __syncthreads();
+    if (threadIdx.x < FACE) {
+        const int y = threadIdx.x % AYZ, z = threadIdx.x / AYZ;
+        const unsigned long long w = acc[threadIdx.x * ax + g.tx];
+        unsigned long long *at;
+        if (y < TYZ && z < TYZ) {
+            at = rho + ((gz0 + z) * n + gy0 + y) * n;
+        } else {
+            const size_t t0 = (size_t(tz) * g.nty + ty) * g.ntx;
+            at = skirt + t0 * g.skirt + (y == TYZ ? z * g.tx : g.tx * AYZ + y * g.tx);
+        }
+        const unsigned long long v = *at, t = v + w;
+        // both parts are below 2^63 unless already reported; the sum must be too
+        if (t < v || (t >> 63)) overflow = true;
+        *at = t;
     }
     if (overflow) atomicOr(status, ST_OVERFLOW);
 }
 
-// One workgroup per tile: its low-face cells gather the skirt sums that lower
-// neighbours computed for them.
+// One workgroup per tile: its y = 0 and z = 0 cells (the z = 0 plane, then the
+// y = 0 row of each plane z = 1..7: 15 tx cells, all in whole rows) gather the
+// y- and z-face sums that the lower neighbours in y and z computed for them
+// (the x faces were carried along the rows already).
 __global__ void __launch_bounds__(ACC_THREADS) skirt_fold_kernel(const unsigned long long *__restrict__ skirt, Geom g,
                                                                  unsigned long long *__restrict__ rho,
                                                                  uint32_t *status) {
@@ -751,62 +799,41 @@ __global__ void __launch_bounds__(ACC_THREADS) skirt_fold_kernel(const unsigned 
     const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
     const size_t n = size_t(g.n);
     const size_t gx0 = size_t(tx) * g.tx, gy0 = size_t(ty) * TYZ, gz0 = size_t(tz) * TYZ;
+    const int sy = ty == 0 ? g.nty - 1 : ty - 1, sz = tz == 0 ? g.ntz - 1 : tz - 1;
+    const size_t below_y = (size_t(tz) * g.nty + sy) * g.ntx + tx;   // tile - y
+    const size_t below_z = (size_t(sz) * g.nty + ty) * g.ntx + tx;   // tile - z
+    const size_t below_yz = (size_t(sz) * g.nty + sy) * g.ntx + tx;  // tile - y - z
+    const int yface = g.tx * AYZ;  // start of the z face in a tile's side-buffer entries
     bool overflow = false;
-    // Face cells of a tx x 8 x 8 tile, enumerated directly: the z = 0 plane
-    // (8 tx cells), then for z = 1..7 the y = 0 row (tx cells) and the x = 0
-    // cells of rows y = 1..7 -- 15 tx + 49 cells in all.
-    const int nface = 15 * g.tx + 49;
-    constexpr int FB = (15 * MAX_TX + 49 + ACC_THREADS - 1) / ACC_THREADS;
-    unsigned long long v[FB], add_lo[FB], add_hi[FB];
-    size_t at[FB];
-#pragma unroll
-    for (int i = 0; i < FB; ++i) {
-        const int k = threadIdx.x + i * ACC_THREADS;
-        add_lo[i] = add_hi[i] = 0ull;
-        at[i] = 0;
-        if (k >= nface) continue;
+    const int nface = 15 * g.tx;
+    for (int k = threadIdx.x; k < nface; k += ACC_THREADS) {
         int x, y, z;
         if (k < 8 * g.tx) {
             z = 0;
             y = k >> g.ltx;
             x = k & (g.tx - 1);
         } else {
-            const int j = k - 8 * g.tx, row = g.tx + 7;
-            z = 1 + j / row;
-            const int r = j - (z - 1) * row;
-            if (r < g.tx) {
-                y = 0;
-                x = r;
-            } else {
-                y = r - g.tx + 1;
-                x = 0;
-            }
+            const int j = k - 8 * g.tx;
+            z = 1 + (j >> g.ltx);
+            y = 0;
+            x = j & (g.tx - 1);
         }
-        const int zmask = (x == 0 ? 1 : 0) | (y == 0 ? 2 : 0) | (z == 0 ? 4 : 0);
-        at[i] = ((gz0 + z) * n + gy0 + y) * n + gx0 + x;
-        v[i] = rho[at[i]];
-        for (int dm = zmask; dm; dm = (dm - 1) & zmask) {  // nonzero subsets of the zero axes
-            const int dx = dm & 1, dy = (dm >> 1) & 1, dz = (dm >> 2) & 1;
-            const int sx = tx - dx < 0 ? g.ntx - 1 : tx - dx;
-            const int sy = ty - dy < 0 ? g.nty - 1 : ty - dy;
-            const int sz = tz - dz < 0 ? g.ntz - 1 : tz - dz;
-            const size_t src = (size_t(sz) * g.nty + sy) * g.ntx + sx;
-            const unsigned long long w =
-                skirt[src * g.skirt + skirt_index(g.tx, x + g.tx * dx, y + TYZ * dy, z + TYZ * dz)];
-            const unsigned long long t = add_lo[i] + w;
-            add_hi[i] += t < w;
-            add_lo[i] = t;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < FB; ++i) {
-        const int k = threadIdx.x + i * ACC_THREADS;
-        if (k >= nface) continue;
+        const size_t at = ((gz0 + z) * n + gy0 + y) * n + gx0 + x;
+        const unsigned long long v = rho[at];
+        unsigned long long lo = 0ull, hi = 0ull;
+        auto add = [&](unsigned long long w) {
+            const unsigned long long s = lo + w;
+            hi += s < w;
+            lo = s;
+        };
+        if (z == 0) add(skirt[below_z * g.skirt + yface + y * g.tx + x]);            // (x, y, 8) of tile - z
+        if (y == 0) add(skirt[below_y * g.skirt + z * g.tx + x]);                    // (x, 8, z) of tile - y
+        if (y == 0 && z == 0) add(skirt[below_yz * g.skirt + TYZ * g.tx + x]);       // (x, 8, 8) of tile - y - z
         // every part is below 2^63 unless already reported; the total must be too
-        const unsigned long long t = add_lo[i] + v[i];
-        const unsigned long long hi = add_hi[i] + (t < v[i]);
-        if (hi != 0 || (t >> 63)) overflow = true;
-        rho[at[i]] = t;
+        const unsigned long long s = lo + v;
+        hi += s < v;
+        if (hi != 0 || (s >> 63)) overflow = true;
+        rho[at] = s;
     }
     if (overflow) atomicOr(status, ST_OVERFLOW);
 }
@@ -1043,32 +1070,38 @@ bool make_geom(const hf_box &box, Geom &out) {
     g.ntx = box.n / g.tx;
     g.nty = g.ntz = box.n / TYZ;
     g.ntiles = g.ntx * g.nty * g.ntz;
-    g.skirt = AYZ * AYZ + g.tx * AYZ + g.tx * TYZ;
-    // fewest buckets, then the most cube-like bucket
+    g.skirt = g.tx * AYZ + g.tx * TYZ;  // y and z faces
+    // buckets of whole rows of tiles along x where that fits (the accumulation
+    // walks each row in order), then the fewest buckets, then the most
+    // cube-like bucket
     long best_nb = -1;
     double best_shape = 0.0;
-    for (int bx = 1; bx <= g.ntx; ++bx) {
-        if (g.ntx % bx) continue;
-        for (int by = 1; by <= g.nty; ++by) {
-            if (g.nty % by) continue;
-            for (int bz = 1; bz <= g.ntz; ++bz) {
-                if (g.ntz % bz || long(bx) * by * bz > MAX_DIGITS) continue;
-                const long nb = long(g.ntx / bx) * (g.nty / by) * (g.ntz / bz);
-                if (nb > MAX_DIGITS) continue;
-                const double ex = double(bx) * g.tx, ey = double(by) * TYZ, ez = double(bz) * TYZ;
-                const double hi = ex > ey ? (ex > ez ? ex : ez) : (ey > ez ? ey : ez);
-                const double lo = ex < ey ? (ex < ez ? ex : ez) : (ey < ez ? ey : ez);
-                const double shape = hi / lo;
-                if (best_nb < 0 || nb < best_nb || (nb == best_nb && shape < best_shape)) {
-                    best_nb = nb;
-                    best_shape = shape;
-                    g.btx = bx;
-                    g.bty = by;
-                    g.btz = bz;
+    auto search = [&](int bx_from) {
+        for (int bx = bx_from; bx <= g.ntx; ++bx) {
+            if (g.ntx % bx) continue;
+            for (int by = 1; by <= g.nty; ++by) {
+                if (g.nty % by) continue;
+                for (int bz = 1; bz <= g.ntz; ++bz) {
+                    if (g.ntz % bz || long(bx) * by * bz > MAX_DIGITS) continue;
+                    const long nb = long(g.ntx / bx) * (g.nty / by) * (g.ntz / bz);
+                    if (nb > MAX_DIGITS) continue;
+                    const double ex = double(bx) * g.tx, ey = double(by) * TYZ, ez = double(bz) * TYZ;
+                    const double hi = ex > ey ? (ex > ez ? ex : ez) : (ey > ez ? ey : ez);
+                    const double lo = ex < ey ? (ex < ez ? ex : ez) : (ey < ez ? ey : ez);
+                    const double shape = hi / lo;
+                    if (best_nb < 0 || nb < best_nb || (nb == best_nb && shape < best_shape)) {
+                        best_nb = nb;
+                        best_shape = shape;
+                        g.btx = bx;
+                        g.bty = by;
+                        g.btz = bz;
+                    }
                 }
             }
         }
-    }
+    };
+    search(g.ntx);               // whole rows
+    if (best_nb < 0) search(1);  // else any shape
     if (best_nb < 0) return false;
     g.nbx = g.ntx / g.btx;
     g.nby = g.nty / g.bty;
@@ -1234,7 +1267,7 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
             HF_LAUNCH(ctx, K_DEP_L2_SCATTER, (l2_scatter_kernel<T, false>), dim3(part_blocks), dim3(PART_THREADS),
                       0, st, sin, g, cursor2, rec2, RunMaps{});
     }
-    HF_LAUNCH(ctx, K_DEPOSIT, tile_accum_kernel, dim3(g.ntiles), dim3(ACC_THREADS), 0, st, rec2, start2, g, rho,
+    HF_LAUNCH(ctx, K_DEPOSIT, tile_accum_kernel, dim3(g.nty * g.ntz), dim3(ACC_THREADS), 0, st, rec2, start2, g, rho,
               skirt, ctx->d_status);
     HF_LAUNCH(ctx, K_DEP_FOLD, skirt_fold_kernel, dim3(g.ntiles), dim3(ACC_THREADS), 0, st, skirt, g, rho,
               ctx->d_status);
