@@ -640,22 +640,32 @@ __device__ __forceinline__ void lds_add(unsigned long long *acc, int c, unsigned
     }
 }
 
+constexpr int ACC_RB = 8;  // records per thread loaded together
+
+// The records lo + threadIdx.x + k * ACC_THREADS (k < ACC_RB) below hi of a tile.
+__device__ __forceinline__ void load_records(const uint64_t *__restrict__ rec2, uint32_t i0, uint32_t hi,
+                                             uint64_t (&rr)[ACC_RB]) {
+#pragma unroll
+    for (int k = 0; k < ACC_RB; ++k) {
+        const uint32_t i = i0 + k * ACC_THREADS;
+        rr[k] = i < hi ? rec2[i] : 0ull;
+    }
+}
+
+// Adds the CIC weights of records [lo, hi) of a tile into acc; rr holds the
+// first batch (load_records at lo + threadIdx.x) on entry.
 template <bool CHECKED>
 __device__ __forceinline__ void accumulate(const uint64_t *__restrict__ rec2, uint32_t lo, uint32_t hi, int bits,
-                                           int ax, unsigned long long *acc, bool &overflow) {
+                                           int ax, unsigned long long *acc, bool &overflow,
+                                           uint64_t (&rr)[ACC_RB]) {
     const int sx = 6 + bits, sy = 3 + bits;
     const uint64_t fmask = (1ull << bits) - 1ull;
     const uint64_t mx = (1ull << sx) - 1ull, my = (1ull << sy) - 1ull;
     const uint64_t one = 1ull << bits;
     const int plane = ax * AYZ;
-    constexpr int RB = 8;  // records per thread loaded together
+    constexpr int RB = ACC_RB;
     for (uint32_t i0 = lo + threadIdx.x; i0 < hi; i0 += ACC_THREADS * RB) {
-        uint64_t rr[RB];
-#pragma unroll
-        for (int k = 0; k < RB; ++k) {
-            const uint32_t i = i0 + k * ACC_THREADS;
-            rr[k] = i < hi ? rec2[i] : 0ull;
-        }
+        if (i0 != lo + threadIdx.x) load_records(rec2, i0, hi, rr);
 #pragma unroll
         for (int k = 0; k < RB; ++k) {
         if (i0 + k * ACC_THREADS >= hi) break;
@@ -735,6 +745,11 @@ __global__ void __launch_bounds__(ACC_THREADS) tile_accum_kernel(const uint64_t 
     constexpr int FACE = AYZ * AYZ;  // cells of the x face
     bool overflow = false;
     uint32_t prev = 0;  // particles of the previous tile, whose x face is carried in
+    // each tile's first batch of records is loaded before the previous tile
+    // is written out, so that its latency hides behind the stores
+    uint32_t lo = start2[tile_slot(g, 0, ty, tz)], hi = start2[tile_slot(g, 0, ty, tz) + 1];
+    uint64_t rr[ACC_RB];
+    load_records(rec2, lo + threadIdx.x, hi, rr);
     for (int tx = 0; tx < g.ntx; ++tx) {
         unsigned long long carried = 0ull;
         if (tx > 0 && threadIdx.x < FACE) carried = acc[threadIdx.x * ax + g.tx];  // (z, y) = (k / 9, k % 9)
@@ -743,15 +758,19 @@ __global__ void __launch_bounds__(ACC_THREADS) tile_accum_kernel(const uint64_t 
         __syncthreads();
         if (tx > 0 && threadIdx.x < FACE) acc[threadIdx.x * ax] = carried;
         __syncthreads();
-        const int slot = tile_slot(g, tx, ty, tz);
-        const uint32_t lo = start2[slot], hi = start2[slot + 1];
         // fewer than 2^(63 - 3B) particles (with those carried in) cannot carry
         // any cell of this tile past 2^63 - 1
         if (uint64_t(hi - lo) + prev < (1ull << (63 - 3 * g.bits)))
-            accumulate<false>(rec2, lo, hi, g.bits, ax, acc, overflow);
+            accumulate<false>(rec2, lo, hi, g.bits, ax, acc, overflow, rr);
         else
-            accumulate<true>(rec2, lo, hi, g.bits, ax, acc, overflow);
+            accumulate<true>(rec2, lo, hi, g.bits, ax, acc, overflow, rr);
         prev = hi - lo;
+        if (tx + 1 < g.ntx) {
+            const int next = tile_slot(g, tx + 1, ty, tz);
+            lo = start2[next];
+            hi = start2[next + 1];
+            load_records(rec2, lo + threadIdx.x, hi, rr);
+        }
         __syncthreads();
         const size_t gx0 = size_t(tx) * g.tx;
         for (int c = threadIdx.x; c < owned; c += ACC_THREADS) {
