@@ -1139,12 +1139,51 @@ bool make_geom(const hf_box &box, Geom &out) {
 
 struct DepLayout {
     size_t count1, start1, cursor1, seg_v, seg_p, chunk_first, hchunk_first, count2, start2, cursor2, partial, rec1,
-        rec2, skirt, total;
+        rec2, skirt, pad, total;
 };
+
+// Grid the binned form runs on for an n^3 box: n itself when its tiles fit
+// (n a multiple of 16), else the next multiple of 16 above n.  On the larger
+// grid the particles (cells 0..n-1) fill the low corner, their upper CIC
+// corners reach cell n at most, and a last pass folds the planes at n onto
+// the planes at 0 along each axis and keeps the n^3 cells.
+int padded_n(int n) { return n % 16 == 0 ? n : (n + 1 + 15) / 16 * 16; }
+
+hf_box padded_box(const hf_box &box) {
+    hf_box b = box;
+    b.n = padded_n(box.n);
+    return b;
+}
+
+// rho[x, y, z] of the n^3 grid = the sum over the cells of the padded grid
+// (side np) that coincide with it periodically: x and x + n where x = 0, and
+// the same in y and z.  Exact, with the 2^63 check.
+__global__ void crop_fold_kernel(const unsigned long long *__restrict__ pad, int npad, int n,
+                                 unsigned long long *__restrict__ rho, uint32_t *status) {
+    const int64_t cells = int64_t(n) * n * n;
+    const size_t sp = size_t(npad);
+    bool overflow = false;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < cells; i += int64_t(gridDim.x) * blockDim.x) {
+        const int x = int(i % n), y = int((i / n) % n), z = int(i / (int64_t(n) * n));
+        unsigned long long lo = 0ull, hi = 0ull;
+        for (int dz = 0; dz <= (z == 0); ++dz)
+            for (int dy = 0; dy <= (y == 0); ++dy)
+                for (int dx = 0; dx <= (x == 0); ++dx) {
+                    const unsigned long long w =
+                        pad[(size_t(z + dz * n) * sp + size_t(y + dy * n)) * sp + size_t(x + dx * n)];
+                    const unsigned long long t = lo + w;
+                    hi += t < w;
+                    lo = t;
+                }
+        if (hi != 0 || (lo >> 63)) overflow = true;
+        rho[i] = lo;
+    }
+    if (overflow) atomicOr(status, ST_OVERFLOW);
+}
 
 // Deposit workspace; with keep_order the level-2 records and the bucket and
 // tile offsets live in the ParticleOrder region instead.
-DepLayout dep_layout(const Geom &g, int64_t np, bool keep_order) {
+DepLayout dep_layout(const Geom &g, int64_t np, bool keep_order, bool padded = false) {
     DepLayout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -1166,6 +1205,7 @@ DepLayout dep_layout(const Geom &g, int64_t np, bool keep_order) {
     L.rec1 = take(g.nbuckets > 1 ? sizeof(Q3) * size_t(np) : 0);
     L.rec2 = take(keep_order ? 0 : sizeof(uint64_t) * size_t(np));
     L.skirt = take(sizeof(unsigned long long) * size_t(g.skirt) * size_t(g.ntiles));
+    L.pad = take(padded ? sizeof(unsigned long long) * size_t(g.n) * size_t(g.n) * size_t(g.n) : 0);
     L.total = off;
     return L;
 }
@@ -1215,12 +1255,14 @@ unsigned resident_grid(const hf_ctx *ctx, const void *kernel, unsigned blocks) {
 }
 
 template <typename T>
-hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, unsigned long long *rho,
+hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, unsigned long long *rho_out,
                     char *ws, const ParticleOrder *order) {
-    Geom g;
-    if (!make_geom(box, g)) return HF_ERR_SIZE;
-    if (order && g.nbuckets < 2) return HF_ERR_ARG;  // no level-1 records to keep
-    const DepLayout L = dep_layout(g, np, order != nullptr);
+    Geom g;  // on the padded grid where n is not a multiple of 16; the fixed point is the box's own
+    const bool padded = padded_n(box.n) != box.n;
+    if (!make_geom(padded_box(box), g)) return HF_ERR_SIZE;
+    if (order && (g.nbuckets < 2 || padded)) return HF_ERR_ARG;  // no level-1 records to keep
+    const DepLayout L = dep_layout(g, np, order != nullptr, padded);
+    auto *rho = padded ? reinterpret_cast<unsigned long long *>(ws + L.pad) : rho_out;
     auto *count1 = reinterpret_cast<uint32_t *>(ws + L.count1);
     auto *count2 = reinterpret_cast<uint32_t *>(ws + L.count2);
     auto *start1 = order ? order->start1 : reinterpret_cast<uint32_t *>(ws + L.start1);
@@ -1290,6 +1332,12 @@ hf_status run_tiled(hf_ctx *ctx, const hf_box &box, const T *pos, int64_t np, un
               skirt, ctx->d_status);
     HF_LAUNCH(ctx, K_DEP_FOLD, skirt_fold_kernel, dim3(g.ntiles), dim3(ACC_THREADS), 0, st, skirt, g, rho,
               ctx->d_status);
+    if (padded) {
+        const int64_t cells = int64_t(box.n) * box.n * box.n;
+        const int64_t want = (cells + 255) / 256, cap = int64_t(ctx->cus) * 16;
+        HF_LAUNCH(ctx, K_DEP_FOLD, crop_fold_kernel, dim3(unsigned(want < cap ? want : cap)), dim3(256), 0, st, rho,
+                  g.n, box.n, rho_out, ctx->d_status);
+    }
     return launch_status();
 }
 
@@ -1299,12 +1347,13 @@ bool hf::deposit_tiled_supported(const hf_box &box, int64_t np) {
     // packed tile records hold 12 + 3B <= 63 bits; counts are uint32
     if (box.frac_bits > 17 || np >= (int64_t(1) << 32)) return false;
     Geom g;
-    return make_geom(box, g);
+    return make_geom(padded_box(box), g);
 }
 
 size_t hf::deposit_tiled_ws_bytes(const hf_box &box, int64_t np, bool keep_order) {
     Geom g;
-    return make_geom(box, g) ? dep_layout(g, np, keep_order).total : 0;
+    const bool padded = padded_n(box.n) != box.n;
+    return make_geom(padded_box(box), g) ? dep_layout(g, np, keep_order, padded).total : 0;
 }
 
 hf_status hf::deposit_tiled(hf_ctx *ctx, const hf_box &box, const void *pos, hf_dtype dtype, int64_t np,

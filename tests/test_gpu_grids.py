@@ -35,7 +35,7 @@ def hfm():
 
 
 @pytest.mark.parametrize("n,L,np_,a,seed", [
-    (75, 75.0, 300000, 1.5, 91),     # odd: direct deposit and segmentation
+    (75, 75.0, 300000, 1.5, 91),     # odd: deposit binned on 80^3 and folded, direct segmentation
     (101, 90.0, 500000, 2.0, 92),    # prime
     (80, 80.0, 400000, 2.5, 93),     # binned deposit with 16-cell tiles, not 2^a 3^b
     (160, 150.0, 2000000, 2.0, 94),  # binned deposit, tiled segmentation, not 2^a 3^b

@@ -41,6 +41,13 @@ def hfm():
     (256, 250.0, 256 ** 3, 20000, "f32", 15, 2),   # the 256^3 FP32 configuration
     (512, 500.0, 3000000, 5000, "f32", 15, 8),
     (432, 432.0, 400000, 100, "f32", 15, 9),        # 16-wide tiles, 162 buckets
+    # n not a multiple of 16: binned on the next multiple of 16 above n, then
+    # the planes at n folded onto the planes at 0
+    (9, 9.0, 5000, 4, "f64", 15, 10),               # padded to 16
+    (47, 47.0, 100000, 40, "f32", 15, 11),          # padded to 48: the fold plane is the grid's last
+    (101, 90.0, 500000, 200, "f32", 16, 12),        # prime, padded to 112
+    (270, 250.0, 2000000, 2000, "f32", 15, 13),     # N_g = Int(400 * 0.3 + 150), padded to 272
+    (350, 250.0, 1500000, 1500, "f64", 15, 14),     # N_g for k_w = 0.5, padded to 352
 ])
 def test_deposit_bit_exact(n, L, np_, halos, dtype, bits, seed):
     pos = small_box(n, L, np_, halos, dtype, seed)
@@ -48,6 +55,28 @@ def test_deposit_bit_exact(n, L, np_, halos, dtype, bits, seed):
     got = hfm().deposit(cuda(pos), L, n, bits)
     hfm().sync()
     np.testing.assert_array_equal(got.cpu().numpy(), O.deposit(pos, L, n, bits))
+
+
+@pytest.mark.parametrize("n", [9, 47, 75, 270])
+def test_deposit_last_cells_fold_onto_the_first(n):
+    # particles in the last cell along one, two and three axes: their upper
+    # corners land on plane n of the padded grid and must reach plane 0
+    L = float(n)
+    rng = np.random.default_rng(n)
+    e = L - 0.3 - 0.5 * rng.random((600, 3))          # inside the last cell
+    mid = L * rng.random((600, 3))
+    pos = np.concatenate([
+        np.column_stack([e[:100, 0], mid[:100, 1], mid[:100, 2]]),
+        np.column_stack([mid[100:200, 0], e[100:200, 1], e[100:200, 2]]),
+        e[200:400],                                    # the far corner cell
+        np.column_stack([e[400:, 0], e[400:, 1], mid[400:, 2]]),
+    ]).astype(np.float64)
+    print(f"deposit last-cell fold n={n}", flush=True)
+    got = hfm().deposit(cuda(pos), L, n, 15)
+    hfm().sync()
+    want = O.deposit(pos, L, n, 15)
+    np.testing.assert_array_equal(got.cpu().numpy(), want)
+    assert want[0, 0, 0] > 0 and want[:, :, 0].sum() > 0
 
 
 def test_deposit_wraps_outside_box_and_edge_cases():
