@@ -8,7 +8,7 @@
 // neighbourhood (itself included); a cell is a maximum iff it is its own
 // parent and its value exceeds tau.
 //
-// Tiled path (n % 32 == 0): one workgroup per 32x16x16 tile holds the tile and
+// Tiled path: one workgroup per 32x16x16 tile holds the tile and
 // a one-cell halo of the field in LDS, forms every cell's parent (the largest
 // key of its 3x3x3 neighbourhood) and the maxima mask, and follows the parent
 // chains inside the tile, so the parents never go to memory.
@@ -26,7 +26,11 @@
 //    one workgroup per tile, loads the resolved entries of the one-cell shell
 //    around the tile (every exit target lies in it) into LDS and maps each
 //    cell of the tile through them.
-// Other sizes use direct per-cell kernels with the same results.
+// Any n: where n is not a multiple of a tile's extent, the last tile along
+// that axis is short (its cells past n are absent); a short tile's far-edge
+// cells take the boundary ranks of a full tile's far edge.  The separable
+// maxima pass of hf_maxima alone needs n % 32 == 0; other sizes use a direct
+// per-cell pass with the same results.
 #include "hf_internal.h"
 #include "scan.h"
 
@@ -104,15 +108,32 @@ __device__ __forceinline__ int bnd_rank(int x, int y, int z) {
     return -1;
 }
 
-// Where the compact boundary array keeps cell g (rg: the resolve-tile grid),
-// or -1 if g is interior to its tile.
+// Extent along one axis of the resolve tile starting at `origin`: R, or less
+// for the last tile where n is not a multiple of R.
+__device__ __forceinline__ int tile_extent(int origin, int R, int n) { return n - origin < R ? n - origin : R; }
+
+// Rank among its tile's boundary cells of local cell (x, y, z) of a tile of
+// extents (wx, wy, wz), or -1: a coordinate on a short tile's far edge counts
+// as the full tile's far edge, which keeps the ranks distinct.
+__device__ __forceinline__ int bnd_rank_in(int x, int y, int z, int wx, int wy, int wz) {
+    return bnd_rank(x == wx - 1 ? RX - 1 : x, y == wy - 1 ? RY - 1 : y, z == wz - 1 ? RZ - 1 : z);
+}
+
+// Where the compact boundary array keeps cell (x, y, z) (rg: the resolve-tile
+// grid), or -1 if it is interior to its tile.
+__device__ __forceinline__ int64_t bnd_slot_at(const TileGrid &rg, uint32_t x, uint32_t y, uint32_t z) {
+    const int tx = int(x / RX), ty = int(y / RY), tz = int(z / RZ);
+    const int r = bnd_rank_in(int(x) - tx * RX, int(y) - ty * RY, int(z) - tz * RZ, tile_extent(tx * RX, RX, rg.n),
+                              tile_extent(ty * RY, RY, rg.n), tile_extent(tz * RZ, RZ, rg.n));
+    if (r < 0) return -1;
+    const int64_t tile = (int64_t(tz) * rg.nty + ty) * rg.ntx + tx;
+    return tile * NBND + r;
+}
+
 __device__ __forceinline__ int64_t bnd_slot(const TileGrid &rg, int32_t g) {
     uint32_t x, y, z;
     cell_coords(rg, uint32_t(g), x, y, z);
-    const int r = bnd_rank(int(x % RX), int(y % RY), int(z % RZ));
-    if (r < 0) return -1;
-    const int64_t tile = (int64_t(z / RZ) * rg.nty + y / RY) * rg.ntx + x / RX;
-    return tile * NBND + r;
+    return bnd_slot_at(rg, x, y, z);
 }
 
 // Loads the keys of the tile at (x0, y0, z0) plus a one-cell periodic halo and
@@ -236,6 +257,10 @@ __global__ void __launch_bounds__(PR_THREADS) parent_resolve_kernel(const float 
     rtile_origin(rg, int(tile), x0, y0, z0);
     const int n = rg.n;
     const uint32_t un = uint32_t(n);
+    // a tile at the far end of an axis is short where n is not a multiple of
+    // the tile: its cells past n are absent (never pointed to, never written)
+    const int wx = tile_extent(x0, RX, n), wy = tile_extent(y0, RY, n), wz = tile_extent(z0, RZ, n);
+    const bool full = wx == RX && wy == RY && wz == RZ;
     bool nan = false;
     {
         // all loads of the halo tile are issued before any is used
@@ -284,20 +309,26 @@ __global__ void __launch_bounds__(PR_THREADS) parent_resolve_kernel(const float 
     for (int z = 0; z < RZ; ++z) {
         const uint64_t b2 = plane_max(z + 2);
         const uint64_t best = kmax(kmax(b0, b1), b2);
+        const bool real = x < wx && y < wy && z < wz;
         const uint32_t g = (uint32_t(z0 + z) * un + uint32_t(y0 + y)) * un + uint32_t(x0 + x);
         const uint32_t p = uint32_t(best);
         const bool high = uint32_t(best >> 32) > tau_ord;
         if (mask) {
-            const unsigned long long bits = __ballot(p == g && high);
-            if (lane == 0) {
-                mask[g >> 5] = uint32_t(bits);
-                mask[(g + un) >> 5] = uint32_t(bits >> 32);
+            if (full && un % 32u == 0u) {  // the wavefront's two rows are two aligned mask words
+                const unsigned long long bits = __ballot(p == g && high);
+                if (lane == 0) {
+                    mask[g >> 5] = uint32_t(bits);
+                    mask[(g + un) >> 5] = uint32_t(bits >> 32);
+                }
+            } else if (real && p == g && high) {  // rows straddle words: the mask was cleared first
+                atomicOr(&mask[g >> 5], 1u << (g & 31u));
             }
         }
         // local form: a root (above tau: itself; else -1) is resolved, so is
         // a parent outside the tile; a parent inside is followed
         l[z] = (p == g) ? (high ? -2 - int32_t(g) : -1) : -2 - int32_t(p);
-        if (p != g) {
+        if (!real) l[z] = -1;  // absent
+        if (real && p != g) {
             uint32_t px, py, pz;
             cell_coords(rg, p, px, py, pz);
             const int lx = int(px) - x0, ly = int(py) - y0, lz = int(pz) - z0;
@@ -327,15 +358,28 @@ __global__ void __launch_bounds__(PR_THREADS) parent_resolve_kernel(const float 
         for (int i = 0; i < PR_PER; ++i) loc[i * PR_THREADS + threadIdx.x] = nv[i];
         open = __syncthreads_or(any);
     }
+    if (!full) {
+        // a short tile leaves some of its boundary slots unused: they hold -1
+        // (final), so that the jump rounds, which visit every slot, read no
+        // stale entry
+        for (int k = threadIdx.x; k < NBND; k += PR_THREADS) bnd[int64_t(tile) * NBND + k] = -1;
+        __syncthreads();
+    }
 #pragma unroll
     for (int i = 0; i < PR_PER; ++i) {
         const int e = i * PR_THREADS + threadIdx.x;  // (x, y) of this thread, z = i
+        if (x >= wx || y >= wy || i >= wz) continue;
         const uint32_t g = ((uint32_t(z0 + i) * un) + uint32_t(y0 + y)) * un + uint32_t(x0 + x);
         const int32_t t = -2 - loc[e];
         ptr[g] = t;
-        const int r = bnd_rank(x, y, i);
+        const int r = bnd_rank_in(x, y, i, wx, wy, wz);
         if (r >= 0) bnd[int64_t(tile) * NBND + r] = t;
     }
+}
+
+__global__ void zero_words_kernel(uint32_t *w, int64_t count) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < count; i += int64_t(gridDim.x) * blockDim.x)
+        w[i] = 0u;
 }
 
 __global__ void fill_flags_kernel(uint32_t *flags, int count) {
@@ -473,49 +517,52 @@ __global__ void __launch_bounds__(RES_THREADS) seg_finalize_kernel(const int32_t
     rtile_origin(rg, int(tile), x0, y0, z0);
     const int n = rg.n;
     const uint32_t un = uint32_t(n);
+    const int wx = tile_extent(x0, RX, n), wy = tile_extent(y0, RY, n), wz = tile_extent(z0, RZ, n);
     // this tile's pointers and the shell's entries, all loads issued before any is used
     int32_t t[RES_PER];
 #pragma unroll
     for (int i = 0; i < RES_PER; ++i) {
         const int e = i * RES_THREADS + threadIdx.x;
         const int x = e % RX, y = (e / RX) % RY, z = e / (RX * RY);
-        t[i] = ptr[((uint32_t(z0 + z) * un) + uint32_t(y0 + y)) * un + uint32_t(x0 + x)];
+        t[i] = 0;
+        if (x < wx && y < wy && z < wz) t[i] = ptr[((uint32_t(z0 + z) * un) + uint32_t(y0 + y)) * un + uint32_t(x0 + x)];
     }
-    // the shell's cells, enumerated: the two z planes, then per inner plane the
-    // two y rows and the two x ends of the rows between them
-    constexpr int ZPLANE = RHX * RHY, RING = 2 * RHX + 2 * (RHY - 2);
-    constexpr int NSHELL = 2 * ZPLANE + (RHZ - 2) * RING;  // RHCELLS - RCELLS
-    constexpr int LOADS = (NSHELL + RES_THREADS - 1) / RES_THREADS;
+    // the one-cell shell around the tile's (wx, wy, wz) cells, enumerated: the
+    // two z planes, then per inner plane the two y rows and the two x ends of
+    // the rows between them; shell cell (hx, hy, hz) sits at LDS place
+    // (hz RHY + hy) RHX + hx, with the tile's cells at 1..wx, 1..wy, 1..wz
+    const int ex = wx + 2, ey = wy + 2, ez = wz + 2;
+    const int zplane = ex * ey, ring = 2 * ex + 2 * (ey - 2);
+    const int nshell = 2 * zplane + (ez - 2) * ring;
+    constexpr int LOADS = (RHCELLS - RCELLS + RES_THREADS - 1) / RES_THREADS;
     int32_t v[LOADS];
     int at[LOADS];
 #pragma unroll
     for (int i = 0; i < LOADS; ++i) {
         const int k = threadIdx.x + i * RES_THREADS;
         at[i] = -1;
-        if (k >= NSHELL) continue;
+        if (k >= nshell) continue;
         int hx, hy, hz;
-        if (k < 2 * ZPLANE) {
-            hz = k < ZPLANE ? 0 : RHZ - 1;
-            const int j = k % ZPLANE;
-            hy = j / RHX;
-            hx = j % RHX;
+        if (k < 2 * zplane) {
+            hz = k < zplane ? 0 : ez - 1;
+            const int j = k % zplane;
+            hy = j / ex;
+            hx = j % ex;
         } else {
-            const int j = k - 2 * ZPLANE;
-            hz = 1 + j / RING;
-            const int r = j % RING;
-            if (r < 2 * RHX) {
-                hy = r < RHX ? 0 : RHY - 1;
-                hx = r % RHX;
+            const int j = k - 2 * zplane;
+            hz = 1 + j / ring;
+            const int r = j % ring;
+            if (r < 2 * ex) {
+                hy = r < ex ? 0 : ey - 1;
+                hx = r % ex;
             } else {
-                const int q = r - 2 * RHX;
+                const int q = r - 2 * ex;
                 hy = 1 + q / 2;
-                hx = (q & 1) ? RHX - 1 : 0;
+                hx = (q & 1) ? ex - 1 : 0;
             }
         }
         const uint32_t gx = wrap(x0 + hx - 1, n), gy = wrap(y0 + hy - 1, n), gz = wrap(z0 + hz - 1, n);
-        const int r = bnd_rank(int(gx % RX), int(gy % RY), int(gz % RZ));  // on its tile's boundary
-        const int64_t nt = (int64_t(gz / RZ) * rg.nty + gy / RY) * rg.ntx + gx / RX;
-        v[i] = bnd[nt * NBND + r];
+        v[i] = bnd[bnd_slot_at(rg, gx, gy, gz)];  // on its tile's boundary
         at[i] = (hz * RHY + hy) * RHX + hx;
     }
 #pragma unroll
@@ -526,6 +573,7 @@ __global__ void __launch_bounds__(RES_THREADS) seg_finalize_kernel(const int32_t
     for (int i = 0; i < RES_PER; ++i) {
         const int e = i * RES_THREADS + threadIdx.x;
         const int x = e % RX, y = (e / RX) % RY, z = e / (RX * RY);
+        if (x >= wx || y >= wy || z >= wz) continue;
         const uint32_t g = ((uint32_t(z0 + z) * un) + uint32_t(y0 + y)) * un + uint32_t(x0 + x);
         int32_t r = t[i];
         if (r >= 0) {
@@ -534,7 +582,7 @@ __global__ void __launch_bounds__(RES_THREADS) seg_finalize_kernel(const int32_t
             // shell coordinates of the target, periodic
             const int hx = int(wrap(int(px) - x0 + 1, n)), hy = int(wrap(int(py) - y0 + 1, n)),
                       hz = int(wrap(int(pz) - z0 + 1, n));
-            const bool inside = hx >= 1 && hx <= RX && hy >= 1 && hy <= RY && hz >= 1 && hz <= RZ;
+            const bool inside = hx >= 1 && hx <= wx && hy >= 1 && hy <= wy && hz >= 1 && hz <= wz;
             if (!inside) r = shell[(hz * RHY + hy) * RHX + hx];
         }
         label[g] = r;
@@ -588,42 +636,6 @@ __global__ void __launch_bounds__(256) max_direct_kernel(const float *__restrict
     if (nan) atomicOr(status, ST_INPUT);
 }
 
-__global__ void __launch_bounds__(256) parent_direct_kernel(const float *__restrict__ c, int n,
-                                                            int32_t *__restrict__ parent, uint32_t *status) {
-    const uint32_t cells = uint32_t(n) * n * n;
-    bool nan = false;
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cells; j += gridDim.x * blockDim.x) {
-        const int x = int(j % uint32_t(n)), y = int((j / uint32_t(n)) % uint32_t(n)), z = int(j / (uint32_t(n) * n));
-        const uint64_t me = cell_key(c[j], j, nan);
-        const uint64_t nb = neighbour_max(c, n, x, y, z, nan);
-        parent[j] = int32_t(uint32_t(kmax(nb, me)));
-    }
-    if (nan) atomicOr(status, ST_INPUT);
-}
-
-__global__ void __launch_bounds__(256) jump_direct_kernel(int32_t *__restrict__ ptr, uint32_t cells, uint32_t *flags,
-                                                          int round) {
-    if (flags[round] == 0u) return;
-    bool changed = false;
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cells; j += gridDim.x * blockDim.x) {
-        const int32_t p = ptr[j];
-        const int32_t pp = ptr[p];
-        if (pp != p) {
-            ptr[j] = pp;
-            changed = true;
-        }
-    }
-    if (__any(changed) && (threadIdx.x & 63) == 0) flags[round + 1] = 1u;
-}
-
-__global__ void __launch_bounds__(256) finalize_direct_kernel(int32_t *__restrict__ ptr, const float *__restrict__ c,
-                                                              uint32_t cells, float tau) {
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cells; j += gridDim.x * blockDim.x) {
-        const int32_t r = ptr[j];
-        ptr[j] = c[r] > tau ? r : -1;
-    }
-}
-
 // ------------------------------------------------------------------ mask -> sorted list
 constexpr int LIST_CHUNK_WORDS = 128;  // 4096 cells per chunk
 
@@ -672,7 +684,11 @@ bool tiled(int n) { return n % TX == 0; }  // TY, TZ, RY and RZ (8 or 16) divide
 
 TileGrid tile_grid(int n) { return TileGrid{n, n / TX, n / TY, n / TZ, FastDiv(uint32_t(n))}; }
 
-TileGrid resolve_grid(int n) { return TileGrid{n, n / RX, n / RY, n / RZ, FastDiv(uint32_t(n))}; }
+// Resolve tiles over any n: the last tile along an axis is short where n is
+// not a multiple of the tile.
+TileGrid resolve_grid(int n) {
+    return TileGrid{n, (n + RX - 1) / RX, (n + RY - 1) / RY, (n + RZ - 1) / RZ, FastDiv(uint32_t(n))};
+}
 
 int rounds_for(uint64_t count) {
     int k = 0;
@@ -724,7 +740,7 @@ SegmentLayout segment_layout(int n) {
     const uint64_t cells = uint64_t(n) * n * n;
     size_t off = 0;
     L.flags = off;
-    if (tiled(n)) {
+    {
         const TileGrid rg = resolve_grid(n);
         L.nbnd = int64_t(rg.ntx) * rg.nty * rg.ntz * NBND;
         L.rounds = rounds_for(uint64_t(L.nbnd));
@@ -743,9 +759,6 @@ SegmentLayout segment_layout(int n) {
             L.counts[b] = off;
             off = align_up(off + sizeof(uint32_t) * size_t(L.jump_grid));
         }
-    } else {
-        L.rounds = rounds_for(cells);
-        off = align_up(off + sizeof(uint32_t) * (L.rounds + 2));
     }
     L.total = off;
     return L;
@@ -824,11 +837,6 @@ size_t hf::maxima_segment_ws_bytes(const hf_box &box) {
 hf_status hf::maxima_segment(hf_ctx *ctx, const hf_box &box, const float *cwt, float tau, int32_t *max_idx,
                              int64_t max_cap, int64_t *d_count, int32_t *cell_label, void *ws, size_t ws_bytes) {
     const int n = box.n;
-    if (!tiled(n)) {
-        hf_status s = hf_maxima(ctx, &box, cwt, tau, max_idx, max_cap, d_count, ws, ws_bytes);
-        if (s != HF_OK) return s;
-        return hf_segment(ctx, &box, cwt, tau, cell_label, ws, ws_bytes);
-    }
     if (!ctx || !cwt || !d_count || !cell_label || max_cap < 0 || (max_cap > 0 && !max_idx) || tau != tau)
         return HF_ERR_ARG;
     const SegmentLayout SL = segment_layout(n);
@@ -841,7 +849,11 @@ hf_status hf::maxima_segment(hf_ctx *ctx, const hf_box &box, const float *cwt, f
     auto *flags = reinterpret_cast<uint32_t *>(w8 + SL.flags);
     HF_LAUNCH(ctx, K_FLAGS, fill_flags_kernel, dim3((SL.rounds + 2 + 255) / 256), dim3(256), 0, ctx->stream, flags,
               SL.rounds + 2);
-    s = launch_parent_resolve(ctx, SL, w8, n, cwt, tau, reinterpret_cast<uint32_t *>(wm + ML.mask));
+    auto *mask = reinterpret_cast<uint32_t *>(wm + ML.mask);
+    if (n % 32 != 0)  // rows straddle mask words: the maxima are set bit by bit into a cleared mask
+        HF_LAUNCH(ctx, K_FLAGS, zero_words_kernel, dim3(stride_grid(ML.words)), dim3(256), 0, ctx->stream, mask,
+                  ML.words);
+    s = launch_parent_resolve(ctx, SL, w8, n, cwt, tau, mask);
     if (s != HF_OK) return s;
     s = mask_to_list(ctx, ML, wm, max_idx, max_cap, d_count);
     if (s != HF_OK) return s;
@@ -888,19 +900,7 @@ extern "C" hf_status hf_segment(hf_ctx *ctx, const hf_box *box, const float *cwt
     const int n = box->n;
     HF_LAUNCH(ctx, K_FLAGS, fill_flags_kernel, dim3((L.rounds + 2 + 255) / 256), dim3(256), 0, ctx->stream, flags,
               L.rounds + 2);
-    if (tiled(n)) {
-        s = launch_parent_resolve(ctx, L, w8, n, cwt, tau, nullptr);
-        if (s != HF_OK) return s;
-        return segment_finish(ctx, L, w8, n, cell_label);
-    } else {
-        const uint32_t cells = uint32_t(n) * n * n;
-        const int g = stride_grid(cells);
-        HF_LAUNCH(ctx, K_PARENT, parent_direct_kernel, dim3(g), dim3(256), 0, ctx->stream, cwt, n, cell_label,
-                  ctx->d_status);
-        for (int r = 0; r < L.rounds; ++r)
-            HF_LAUNCH(ctx, K_JUMP, jump_direct_kernel, dim3(g), dim3(256), 0, ctx->stream, cell_label, cells, flags, r);
-        HF_LAUNCH(ctx, K_FINALIZE, finalize_direct_kernel, dim3(g), dim3(256), 0, ctx->stream, cell_label, cwt, cells,
-                  tau);
-    }
-    return launch_status();
+    s = launch_parent_resolve(ctx, L, w8, n, cwt, tau, nullptr);
+    if (s != HF_OK) return s;
+    return segment_finish(ctx, L, w8, n, cell_label);
 }

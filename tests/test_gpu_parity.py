@@ -207,6 +207,11 @@ def _oracle_field32(n, L, a, seed, quantise=None):
     (64, 100.0, 2.0, 1, None, 0.0),
     (96, 96.0, 1.5, 6, None, 0.0),
     (256, 250.0, 2.0, 2, None, 0.0),
+    # sizes that leave short resolve tiles: one cell wide (33), odd (47), both
+    # axes short by different amounts (75)
+    (33, 33.0, 1.0, 7, 0.5, 0.0),
+    (47, 47.0, 1.5, 8, None, 0.0),
+    (75, 70.0, 2.0, 9, None, 0.0),
 ])
 def test_maxima_segment_label_stage_isolated(n, L, a, seed, quant, tau):
     pos, c32 = _oracle_field32(n, L, a, seed, quant)
