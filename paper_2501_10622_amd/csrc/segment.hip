@@ -120,20 +120,25 @@ __device__ __forceinline__ int bnd_rank_in(int x, int y, int z, int wx, int wy, 
 }
 
 // Where the compact boundary array keeps cell (x, y, z) (rg: the resolve-tile
-// grid), or -1 if it is interior to its tile.
+// grid), or -1 if it is interior to its tile.  FULL: n is a multiple of every
+// tile extent, so no tile is short.
+template <bool FULL>
 __device__ __forceinline__ int64_t bnd_slot_at(const TileGrid &rg, uint32_t x, uint32_t y, uint32_t z) {
     const int tx = int(x / RX), ty = int(y / RY), tz = int(z / RZ);
-    const int r = bnd_rank_in(int(x) - tx * RX, int(y) - ty * RY, int(z) - tz * RZ, tile_extent(tx * RX, RX, rg.n),
-                              tile_extent(ty * RY, RY, rg.n), tile_extent(tz * RZ, RZ, rg.n));
+    const int lx = int(x) - tx * RX, ly = int(y) - ty * RY, lz = int(z) - tz * RZ;
+    const int r = FULL ? bnd_rank(lx, ly, lz)
+                       : bnd_rank_in(lx, ly, lz, tile_extent(tx * RX, RX, rg.n), tile_extent(ty * RY, RY, rg.n),
+                                     tile_extent(tz * RZ, RZ, rg.n));
     if (r < 0) return -1;
     const int64_t tile = (int64_t(tz) * rg.nty + ty) * rg.ntx + tx;
     return tile * NBND + r;
 }
 
+template <bool FULL>
 __device__ __forceinline__ int64_t bnd_slot(const TileGrid &rg, int32_t g) {
     uint32_t x, y, z;
     cell_coords(rg, uint32_t(g), x, y, z);
-    return bnd_slot_at(rg, x, y, z);
+    return bnd_slot_at<FULL>(rg, x, y, z);
 }
 
 // Loads the keys of the tile at (x0, y0, z0) plus a one-cell periodic halo and
@@ -246,6 +251,7 @@ constexpr int PR_THREADS = RX * RY;          // one z column each
 constexpr int PR_PER = RCELLS / PR_THREADS;  // RZ cells per thread
 static_assert(RHCELLS >= RCELLS, "the pointer array fits where the field was");
 
+template <bool FULL>
 __global__ void __launch_bounds__(PR_THREADS) parent_resolve_kernel(const float *__restrict__ c, TileGrid rg,
                                                                     uint32_t tau_ord, int32_t *__restrict__ ptr,
                                                                     int32_t *__restrict__ bnd,
@@ -259,8 +265,9 @@ __global__ void __launch_bounds__(PR_THREADS) parent_resolve_kernel(const float 
     const uint32_t un = uint32_t(n);
     // a tile at the far end of an axis is short where n is not a multiple of
     // the tile: its cells past n are absent (never pointed to, never written)
-    const int wx = tile_extent(x0, RX, n), wy = tile_extent(y0, RY, n), wz = tile_extent(z0, RZ, n);
-    const bool full = wx == RX && wy == RY && wz == RZ;
+    const int wx = FULL ? RX : tile_extent(x0, RX, n), wy = FULL ? RY : tile_extent(y0, RY, n),
+              wz = FULL ? RZ : tile_extent(z0, RZ, n);
+    const bool full = FULL || (wx == RX && wy == RY && wz == RZ);
     bool nan = false;
     {
         // all loads of the halo tile are issued before any is used
@@ -314,7 +321,7 @@ __global__ void __launch_bounds__(PR_THREADS) parent_resolve_kernel(const float 
         const uint32_t p = uint32_t(best);
         const bool high = uint32_t(best >> 32) > tau_ord;
         if (mask) {
-            if (full && un % 32u == 0u) {  // the wavefront's two rows are two aligned mask words
+            if (FULL) {  // the wavefront's two rows are two aligned mask words
                 const unsigned long long bits = __ballot(p == g && high);
                 if (lane == 0) {
                     mask[g >> 5] = uint32_t(bits);
@@ -412,6 +419,7 @@ __device__ __forceinline__ void append_active(bool again, uint32_t k, uint32_t *
     }
 }
 
+template <bool FULL>
 __global__ void __launch_bounds__(256) bnd_jump_first_kernel(int32_t *__restrict__ bnd, int64_t count, TileGrid tg,
                                                              uint32_t *__restrict__ list, int64_t cap,
                                                              uint32_t *__restrict__ counts, uint32_t *flags) {
@@ -432,7 +440,7 @@ __global__ void __launch_bounds__(256) bnd_jump_first_kernel(int32_t *__restrict
         for (int i = 0; i < BATCH; ++i) {
             const int64_t k = k0 + int64_t(i) * blockDim.x;
             // -1 (a root at or below tau) and interior targets (roots) are final
-            s[i] = k < count && p[i] >= 0 ? bnd_slot(tg, p[i]) : -1;
+            s[i] = k < count && p[i] >= 0 ? bnd_slot<FULL>(tg, p[i]) : -1;
             q[i] = s[i] >= 0 ? bnd[s[i]] : p[i];
         }
 #pragma unroll
@@ -441,7 +449,7 @@ __global__ void __launch_bounds__(256) bnd_jump_first_kernel(int32_t *__restrict
             bool again = false;
             if (k < count && q[i] != p[i]) {
                 bnd[k] = q[i];
-                again = q[i] >= 0 && bnd_slot(tg, q[i]) >= 0;
+                again = q[i] >= 0 && bnd_slot<FULL>(tg, q[i]) >= 0;
             }
             append_active(again, uint32_t(k), mine, &lcount);
         }
@@ -455,6 +463,7 @@ __global__ void __launch_bounds__(256) bnd_jump_first_kernel(int32_t *__restrict
 
 // Round r >= 1: list_in / counts_in hold round r - 1's active entries, the
 // entries still active after this round go to list_out / counts_out.
+template <bool FULL>
 __global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd, const uint32_t *__restrict__ list_in,
                                                        const uint32_t *__restrict__ counts_in,
                                                        uint32_t *__restrict__ list_out,
@@ -482,7 +491,7 @@ __global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd
         }
 #pragma unroll
         for (int i = 0; i < BATCH; ++i) {
-            const int64_t sl = p[i] >= 0 ? bnd_slot(tg, p[i]) : -1;
+            const int64_t sl = p[i] >= 0 ? bnd_slot<FULL>(tg, p[i]) : -1;
             q[i] = sl >= 0 ? bnd[sl] : p[i];
         }
 #pragma unroll
@@ -491,7 +500,7 @@ __global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd
             bool again = false;
             if (j < count && q[i] != p[i]) {
                 bnd[k[i]] = q[i];
-                again = q[i] >= 0 && bnd_slot(tg, q[i]) >= 0;
+                again = q[i] >= 0 && bnd_slot<FULL>(tg, q[i]) >= 0;
             }
             append_active(again, k[i], mine, &lcount);
         }
@@ -508,6 +517,7 @@ __global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd
 // tiles; every exit target of the tile lies in the shell), then every cell of
 // the tile maps its pointer: -1 stays -1, a target inside the tile is a root
 // above tau, a target in the shell takes the shell's entry.
+template <bool FULL>
 __global__ void __launch_bounds__(RES_THREADS) seg_finalize_kernel(const int32_t *__restrict__ ptr,
                                                                    const int32_t *__restrict__ bnd, TileGrid rg,
                                                                    int32_t *__restrict__ label) {
@@ -517,7 +527,8 @@ __global__ void __launch_bounds__(RES_THREADS) seg_finalize_kernel(const int32_t
     rtile_origin(rg, int(tile), x0, y0, z0);
     const int n = rg.n;
     const uint32_t un = uint32_t(n);
-    const int wx = tile_extent(x0, RX, n), wy = tile_extent(y0, RY, n), wz = tile_extent(z0, RZ, n);
+    const int wx = FULL ? RX : tile_extent(x0, RX, n), wy = FULL ? RY : tile_extent(y0, RY, n),
+              wz = FULL ? RZ : tile_extent(z0, RZ, n);
     // this tile's pointers and the shell's entries, all loads issued before any is used
     int32_t t[RES_PER];
 #pragma unroll
@@ -562,7 +573,7 @@ __global__ void __launch_bounds__(RES_THREADS) seg_finalize_kernel(const int32_t
             }
         }
         const uint32_t gx = wrap(x0 + hx - 1, n), gy = wrap(y0 + hy - 1, n), gz = wrap(z0 + hz - 1, n);
-        v[i] = bnd[bnd_slot_at(rg, gx, gy, gz)];  // on its tile's boundary
+        v[i] = bnd[bnd_slot_at<FULL>(rg, gx, gy, gz)];  // on its tile's boundary
         at[i] = (hz * RHY + hy) * RHX + hx;
     }
 #pragma unroll
@@ -684,6 +695,9 @@ bool tiled(int n) { return n % TX == 0; }  // TY, TZ, RY and RZ (8 or 16) divide
 
 TileGrid tile_grid(int n) { return TileGrid{n, n / TX, n / TY, n / TZ, FastDiv(uint32_t(n))}; }
 
+// True where every resolve tile is whole (n a multiple of 32, hence of 16).
+bool all_full(int n) { return n % RX == 0 && n % RY == 0 && n % RZ == 0; }
+
 // Resolve tiles over any n: the last tile along an axis is short where n is
 // not a multiple of the tile.
 TileGrid resolve_grid(int n) {
@@ -798,9 +812,15 @@ hf_status mask_to_list(hf_ctx *ctx, const MaximaLayout &L, char *w8, int32_t *ma
 hf_status launch_parent_resolve(hf_ctx *ctx, const SegmentLayout &L, char *w8, int n, const float *cwt, float tau,
                                 uint32_t *mask) {
     const TileGrid tg = resolve_grid(n);
-    HF_LAUNCH(ctx, K_PARENT, parent_resolve_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(PR_THREADS), 0,
-              ctx->stream, cwt, tg, host_ordered_bits(tau), reinterpret_cast<int32_t *>(w8 + L.ptr),
-              reinterpret_cast<int32_t *>(w8 + L.bnd), mask, ctx->d_status);
+    const dim3 grid(tg.ntx * tg.nty * tg.ntz);
+    auto *ptr = reinterpret_cast<int32_t *>(w8 + L.ptr);
+    auto *bnd = reinterpret_cast<int32_t *>(w8 + L.bnd);
+    if (all_full(n))
+        HF_LAUNCH(ctx, K_PARENT, parent_resolve_kernel<true>, grid, dim3(PR_THREADS), 0, ctx->stream, cwt, tg,
+                  host_ordered_bits(tau), ptr, bnd, mask, ctx->d_status);
+    else
+        HF_LAUNCH(ctx, K_PARENT, parent_resolve_kernel<false>, grid, dim3(PR_THREADS), 0, ctx->stream, cwt, tg,
+                  host_ordered_bits(tau), ptr, bnd, mask, ctx->d_status);
     return launch_status();
 }
 
@@ -816,13 +836,28 @@ hf_status segment_finish(hf_ctx *ctx, const SegmentLayout &L, char *w8, int n, i
         list[b] = reinterpret_cast<uint32_t *>(w8 + L.list[b]);
         counts[b] = reinterpret_cast<uint32_t *>(w8 + L.counts[b]);
     }
-    HF_LAUNCH(ctx, K_JUMP, bnd_jump_first_kernel, dim3(L.jump_grid), dim3(256), 0, ctx->stream, bnd, L.nbnd, tg,
-              list[0], L.list_cap, counts[0], flags);
-    for (int r = 1; r < L.rounds; ++r)
-        HF_LAUNCH(ctx, K_JUMP, bnd_jump_kernel, dim3(L.jump_grid), dim3(256), 0, ctx->stream, bnd, list[(r - 1) & 1],
-                  counts[(r - 1) & 1], list[r & 1], counts[r & 1], L.list_cap, tg, flags, r);
-    HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel, dim3(tg.ntx * tg.nty * tg.ntz), dim3(RES_THREADS), 0,
-              ctx->stream, ptr, bnd, tg, cell_label);
+    const bool full = all_full(n);
+    if (full)
+        HF_LAUNCH(ctx, K_JUMP, bnd_jump_first_kernel<true>, dim3(L.jump_grid), dim3(256), 0, ctx->stream, bnd,
+                  L.nbnd, tg, list[0], L.list_cap, counts[0], flags);
+    else
+        HF_LAUNCH(ctx, K_JUMP, bnd_jump_first_kernel<false>, dim3(L.jump_grid), dim3(256), 0, ctx->stream, bnd,
+                  L.nbnd, tg, list[0], L.list_cap, counts[0], flags);
+    for (int r = 1; r < L.rounds; ++r) {
+        if (full)
+            HF_LAUNCH(ctx, K_JUMP, bnd_jump_kernel<true>, dim3(L.jump_grid), dim3(256), 0, ctx->stream, bnd,
+                      list[(r - 1) & 1], counts[(r - 1) & 1], list[r & 1], counts[r & 1], L.list_cap, tg, flags, r);
+        else
+            HF_LAUNCH(ctx, K_JUMP, bnd_jump_kernel<false>, dim3(L.jump_grid), dim3(256), 0, ctx->stream, bnd,
+                      list[(r - 1) & 1], counts[(r - 1) & 1], list[r & 1], counts[r & 1], L.list_cap, tg, flags, r);
+    }
+    const dim3 grid(tg.ntx * tg.nty * tg.ntz);
+    if (full)
+        HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel<true>, grid, dim3(RES_THREADS), 0, ctx->stream, ptr, bnd, tg,
+                  cell_label);
+    else
+        HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel<false>, grid, dim3(RES_THREADS), 0, ctx->stream, ptr, bnd, tg,
+                  cell_label);
     return launch_status();
 }
 
