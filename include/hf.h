@@ -222,7 +222,11 @@ hf_status hf_label(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dty
  * treated as -1).  Labels >= 0 that are not among the roots give undefined
  * statistics for themselves (never a memory fault).
  * Workspace: HF_STAGE_GROUPS (8 bytes per cell; only the roots' entries are
- * touched). */
+ * touched).  The size hf_workspace_size reports for HF_STAGE_GROUPS alone
+ * adds 4 bytes per particle and n^3/8 bytes, for a partitioned count and a
+ * keep bitmap (much faster on labels in input order); a workspace of the
+ * counters' size alone (np == 0 in the query) is accepted and counts with one
+ * global atomic per labelled particle.  Either way the results are the same. */
 hf_status hf_groups(hf_ctx *ctx, const hf_box *box, int64_t np, const int32_t *roots, int64_t nroots,
                     const int32_t *cell_label, const int32_t *particle_label, double dens_th,
                     int64_t particle_th, const uint8_t *root_ok, uint32_t *group_particles, uint32_t *group_cells,

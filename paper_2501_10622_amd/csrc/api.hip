@@ -210,6 +210,8 @@ extern "C" hf_status hf_workspace_size(const hf_box *box, int64_t np, int stage_
     // order (hf_find_halos_filtered): then they get a region of their own
     const bool groups_apart = order && (stage_mask & HF_STAGE_GROUPS);
     if ((stage_mask & HF_STAGE_GROUPS) && !groups_apart) take(groups_ws_bytes(*box));
+    // hf_groups on its own (its stage alone): room for its partitioned count
+    if (stage_mask == HF_STAGE_GROUPS) take(groups_ws_bytes(*box) + groups_part_ws_bytes(*box, np));
     *bytes = (order ? particle_order_bytes(*box, np) : 0) + (groups_apart ? groups_ws_bytes(*box) : 0) + need;
     return HF_OK;
 }

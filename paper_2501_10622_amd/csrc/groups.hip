@@ -435,6 +435,219 @@ __global__ void __launch_bounds__(GB) peaks_kernel(const int32_t *__restrict__ r
     if (bad) atomicOr(status, ST_INPUT);
 }
 
+// ---------------------------------------------------------------------------
+// hf_groups on labels in input order, where neighbouring particles rarely
+// share a group.  The particle labels are first partitioned by label >> shift
+// into GP_BUCKETS ranges of cell indices (a histogram, a scan and a scatter
+// staged in LDS, one run per bucket and workgroup); a chunk of the partitioned
+// labels then holds a few thousand distinct roots at most, and is counted in
+// an LDS table (lds_tally), each root's count added to its counter once per
+// chunk.  The keep flags of the decision go to a bitmap of one bit per cell
+// (n^3 / 8 bytes) and a summary of one bit per 512 cells (one line of the
+// bitmap; 256 KB at 1024^3, which stays in the L2): the label filters read the
+// summary first, and the bitmap only for labels whose 512-cell block holds a
+// kept root, so the particles' scattered lookups mostly stay in the cache.
+// The counts are exact integer sums, so the order the atomics resolve in
+// changes nothing.
+// ---------------------------------------------------------------------------
+constexpr int GP_BUCKETS = 256;
+constexpr int GP_THREADS = 1024;
+constexpr int GP_PER = 8;
+constexpr int GP_CHUNK = GP_THREADS * GP_PER;  // labels per scatter workgroup
+constexpr int GP_HCHUNK = 8 * GP_CHUNK;        // labels per histogram workgroup
+constexpr int GP_CCHUNK = 2 * GP_CHUNK;        // partitioned labels per counting workgroup
+constexpr int GP_HT = 8192;                    // LDS tally slots of the counting pass
+
+struct GroupPart {
+    uint32_t *count;   // [GP_BUCKETS + 1]: labels per bucket, then the total at [GP_BUCKETS]
+    uint32_t *cursor;  // [GP_BUCKETS]
+    int32_t *sorted;   // [np]
+    uint32_t *bits;    // [words] keep bitmap, then [words / 16 rounded up] its summary
+    int64_t words;     // of the bitmap and its summary together
+    uint32_t *summary;
+    int shift;
+};
+
+constexpr int GP_BLOCK_LOG = 9;  // cells per summary bit: 512, one 64-byte line of the bitmap
+
+__device__ __forceinline__ bool gp_label_ok(int32_t l, int64_t ncells, bool &bad) {
+    if (l >= ncells || l < -1) {
+        bad = true;
+        return false;
+    }
+    return l >= 0;
+}
+
+__global__ void __launch_bounds__(512) gp_hist_kernel(const int32_t *__restrict__ label, int64_t np, int64_t ncells,
+                                                      int shift, uint32_t *__restrict__ count, uint32_t *status) {
+    __shared__ uint32_t h[GP_BUCKETS];
+    for (int b = threadIdx.x; b < GP_BUCKETS; b += blockDim.x) h[b] = 0u;
+    __syncthreads();
+    bool bad = false;
+    const int64_t c0 = int64_t(blockIdx.x) * GP_HCHUNK;
+    const int64_t c1 = c0 + GP_HCHUNK < np ? c0 + GP_HCHUNK : np;
+    for (int64_t i0 = c0 + threadIdx.x; i0 < c1; i0 += int64_t(blockDim.x) * 8) {
+        int32_t l[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t i = i0 + int64_t(k) * blockDim.x;
+            l[k] = i < c1 ? label[i] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (gp_label_ok(l[k], ncells, bad)) atomicAdd(&h[uint32_t(l[k]) >> shift], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < GP_BUCKETS; b += blockDim.x)
+        if (h[b]) atomicAdd(&count[b], h[b]);
+    if (bad) atomicOr(status, ST_INPUT);
+}
+
+// cursor = exclusive scan of the bucket counts; count[GP_BUCKETS] = the total.
+__global__ void __launch_bounds__(GP_BUCKETS) gp_scan_kernel(uint32_t *__restrict__ count,
+                                                             uint32_t *__restrict__ cursor) {
+    __shared__ uint32_t tot[GP_BUCKETS / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint32_t x = count[t];
+    uint32_t inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) tot[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int w = 0; w < GP_BUCKETS / 64; ++w) {
+        before += w < wave ? tot[w] : 0u;
+        all += tot[w];
+    }
+    cursor[t] = before + inc - x;
+    if (t == 0) count[GP_BUCKETS] = all;
+}
+
+__global__ void __launch_bounds__(GP_THREADS) gp_scatter_kernel(const int32_t *__restrict__ label, int64_t np,
+                                                                int64_t ncells, int shift, uint32_t *cursor,
+                                                                int32_t *__restrict__ sorted) {
+    __shared__ int32_t stage[GP_CHUNK];
+    __shared__ uint32_t h[GP_BUCKETS], off[GP_BUCKETS], gbase[GP_BUCKETS], tot[GP_BUCKETS / 64];
+    const int t = threadIdx.x;
+    if (t < GP_BUCKETS) h[t] = 0u;
+    __syncthreads();
+    const int64_t c0 = int64_t(blockIdx.x) * GP_CHUNK;
+    int32_t l[GP_PER];
+    uint32_t rank[GP_PER];
+    bool bad = false;  // reported by the histogram pass
+#pragma unroll
+    for (int k = 0; k < GP_PER; ++k) {
+        const int64_t i = c0 + int64_t(k) * GP_THREADS + t;
+        l[k] = i < np ? label[i] : -1;
+        if (!gp_label_ok(l[k], ncells, bad)) l[k] = -1;
+    }
+#pragma unroll
+    for (int k = 0; k < GP_PER; ++k)
+        if (l[k] >= 0) rank[k] = atomicAdd(&h[uint32_t(l[k]) >> shift], 1u);
+    __syncthreads();
+    if (t < GP_BUCKETS) {  // exclusive scan of the chunk's bucket counts, and the runs' places
+        const int lane = t & 63, wave = t >> 6;
+        const uint32_t x = h[t];
+        uint32_t inc = x;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        if (lane == 63) tot[wave] = inc;
+        off[t] = inc - x;
+        if (x) gbase[t] = atomicAdd(&cursor[t], x);
+    }
+    __syncthreads();
+    if (t < GP_BUCKETS) {
+        uint32_t before = 0;
+        for (int w = 0; w < (t >> 6); ++w) before += tot[w];
+        off[t] += before;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < GP_PER; ++k)
+        if (l[k] >= 0) stage[off[uint32_t(l[k]) >> shift] + rank[k]] = l[k];
+    __syncthreads();
+    const uint32_t total = off[GP_BUCKETS - 1] + h[GP_BUCKETS - 1];
+    for (uint32_t s = t; s < total; s += GP_THREADS) {
+        const int32_t v = stage[s];
+        const uint32_t b = uint32_t(v) >> shift;
+        sorted[gbase[b] + (s - off[b])] = v;
+    }
+}
+
+__global__ void __launch_bounds__(GP_THREADS) gp_count_kernel(const int32_t *__restrict__ sorted,
+                                                              const uint32_t *__restrict__ count,
+                                                              uint32_t *__restrict__ parts) {
+    __shared__ int32_t hkey[GP_HT];
+    __shared__ uint32_t hcnt[GP_HT];
+    const uint32_t total = count[GP_BUCKETS];
+    const int64_t c0 = int64_t(blockIdx.x) * GP_CCHUNK;
+    if (c0 >= int64_t(total)) return;  // the same for the whole workgroup
+    lds_tally_init<GP_HT>(hkey, hcnt);
+    __syncthreads();
+    for (int k = 0; k < GP_CCHUNK / GP_THREADS; ++k) {
+        const int64_t i = c0 + int64_t(k) * GP_THREADS + threadIdx.x;
+        const int32_t l = i < int64_t(total) ? sorted[i] : -1;
+        lds_tally_wave<GP_HT>(hkey, hcnt, parts, l);
+    }
+    __syncthreads();
+    lds_tally_flush<GP_HT>(hkey, hcnt, parts);
+}
+
+__global__ void __launch_bounds__(GB) gp_zero_kernel(uint32_t *__restrict__ w, int64_t count) {
+    for (int64_t i = blockIdx.x * int64_t(GB) + threadIdx.x; i < count; i += int64_t(gridDim.x) * GB) w[i] = 0u;
+}
+
+// Bit r of the bitmap for every kept root r (decided in the same pass's keep flags).
+__global__ void __launch_bounds__(GB) gp_bits_kernel(const int32_t *__restrict__ roots, int64_t nroots,
+                                                     int64_t ncells, const uint8_t *__restrict__ keep,
+                                                     uint32_t *__restrict__ bits, uint32_t *__restrict__ summary) {
+    for (int64_t i = blockIdx.x * int64_t(GB) + threadIdx.x; i < nroots; i += int64_t(gridDim.x) * GB) {
+        const int32_t r = roots[i];
+        if (r >= 0 && r < ncells && keep[i]) {
+            const uint32_t u = uint32_t(r), blk = u >> GP_BLOCK_LOG;
+            atomicOr(&bits[u >> 5], 1u << (u & 31u));
+            atomicOr(&summary[blk >> 5], 1u << (blk & 31u));
+        }
+    }
+}
+
+__device__ __forceinline__ bool gp_kept(const uint32_t *__restrict__ bits, const uint32_t *__restrict__ summary,
+                                        uint32_t l) {
+    const uint32_t blk = l >> GP_BLOCK_LOG;
+    if (!((summary[blk >> 5] >> (blk & 31u)) & 1u)) return false;
+    return (bits[l >> 5] >> (l & 31u)) & 1u;
+}
+
+__global__ void __launch_bounds__(GB) gp_filter_kernel(const int32_t *in, int32_t *out, int64_t count,
+                                                       int64_t ncells, const uint32_t *__restrict__ bits,
+                                                       const uint32_t *__restrict__ summary, uint32_t *status) {
+    bool bad = false;
+    const int64_t stride = int64_t(gridDim.x) * GB;
+    for (int64_t i0 = blockIdx.x * int64_t(GB) + threadIdx.x; i0 < count; i0 += stride * GPER) {
+        int32_t l[GPER];
+#pragma unroll
+        for (int k = 0; k < GPER; ++k) {
+            const int64_t i = i0 + k * stride;
+            l[k] = i < count ? in[i] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < GPER; ++k) {
+            const int64_t i = i0 + k * stride;
+            if (i >= count) continue;
+            int32_t v = -1;
+            if (gp_label_ok(l[k], ncells, bad) && gp_kept(bits, summary, uint32_t(l[k]))) v = l[k];
+            out[i] = v;
+        }
+    }
+    if (bad) atomicOr(status, ST_INPUT);
+}
+
 unsigned grid_of(const hf_ctx *ctx, int64_t work, int64_t per_block) {
     const int64_t want = (work + per_block - 1) / per_block;
     const int64_t cap = int64_t(ctx->cus) * 32;
@@ -443,7 +656,41 @@ unsigned grid_of(const hf_ctx *ctx, int64_t work, int64_t per_block) {
 
 int64_t cells_of(const hf_box &box) { return int64_t(box.n) * box.n * box.n; }
 
+// The partition scratch of hf_groups, after the counters.
+size_t part_layout(const hf_box &box, int64_t np, size_t base, void *ws, GroupPart *out) {
+    const int64_t ncells = cells_of(box);
+    const int64_t fine = (ncells + 31) / 32, coarse = ((ncells >> GP_BLOCK_LOG) + 1 + 31) / 32;
+    const int64_t words = fine + coarse;
+    size_t off = base;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    const size_t c = take(sizeof(uint32_t) * (GP_BUCKETS + 1));
+    const size_t cur = take(sizeof(uint32_t) * GP_BUCKETS);
+    const size_t so = take(sizeof(int32_t) * size_t(np > 0 ? np : 1));
+    const size_t bi = take(sizeof(uint32_t) * size_t(words));
+    if (out && ws) {
+        char *w = static_cast<char *>(ws);
+        int bitsneeded = 0;
+        while ((int64_t(1) << bitsneeded) < ncells) ++bitsneeded;
+        out->count = reinterpret_cast<uint32_t *>(w + c);
+        out->cursor = reinterpret_cast<uint32_t *>(w + cur);
+        out->sorted = reinterpret_cast<int32_t *>(w + so);
+        out->bits = reinterpret_cast<uint32_t *>(w + bi);
+        out->summary = out->bits + fine;
+        out->words = words;
+        out->shift = bitsneeded > 8 ? bitsneeded - 8 : 0;  // label >> shift < GP_BUCKETS
+    }
+    return off - base;
+}
+
 }  // namespace
+
+size_t hf::groups_part_ws_bytes(const hf_box &box, int64_t np) {
+    return part_layout(box, np, 0, nullptr, nullptr);
+}
 
 size_t hf::groups_ws_bytes(const hf_box &box) { return 2 * align_up(size_t(cells_of(box)) * sizeof(uint32_t)); }
 
@@ -589,13 +836,51 @@ extern "C" hf_status hf_groups(hf_ctx *ctx, const hf_box *box, int64_t np, const
     if (s != HF_OK) return s;
     if (hipSetDevice(ctx->device) != hipSuccess) return HF_ERR_DEVICE;
     const GroupCounters g = group_counters_at(*box, ws);
+    // with room for the partition scratch (the size hf_workspace_size gives for
+    // HF_STAGE_GROUPS alone), the particles are partitioned before they are
+    // counted and the filters read a keep bitmap; else one global atomic per
+    // labelled particle and the keep flags in the counters
+    const size_t base = groups_ws_bytes(*box);
+    GroupPart gp{};
+    const bool part = ws_bytes >= base + groups_part_ws_bytes(*box, np);
+    if (part) part_layout(*box, np, base, ws, &gp);
+    hipStream_t st = ctx->stream;
+    if (part) {
+        HF_LAUNCH(ctx, K_GROUP_CLEAR, gp_zero_kernel, dim3(grid_of(ctx, gp.words, GB)), dim3(GB), 0, st, gp.bits,
+                  gp.words);
+        HF_LAUNCH(ctx, K_GROUP_CLEAR, gp_zero_kernel, dim3(1), dim3(GB), 0, st, gp.count, int64_t(GP_BUCKETS + 1));
+    }
     if (nroots > 0) {
         s = groups_count_cells(ctx, *box, roots, nullptr, nroots, cell_label, g);
-        if (s == HF_OK) s = groups_count_particles(ctx, *box, particle_label, np, g);
+        if (s == HF_OK && part && np > 0) {
+            HF_LAUNCH(ctx, K_GROUP_PARTICLES, gp_hist_kernel, dim3(unsigned((np + GP_HCHUNK - 1) / GP_HCHUNK)),
+                      dim3(512), 0, st, particle_label, np, ncells, gp.shift, gp.count, ctx->d_status);
+            HF_LAUNCH(ctx, K_GROUP_PARTICLES, gp_scan_kernel, dim3(1), dim3(GP_BUCKETS), 0, st, gp.count, gp.cursor);
+            const dim3 chunks(unsigned((np + GP_CHUNK - 1) / GP_CHUNK));
+            HF_LAUNCH(ctx, K_GROUP_PARTICLES, gp_scatter_kernel, chunks, dim3(GP_THREADS), 0, st, particle_label, np,
+                      ncells, gp.shift, gp.cursor, gp.sorted);
+            HF_LAUNCH(ctx, K_GROUP_PARTICLES, gp_count_kernel, dim3(unsigned((np + GP_CCHUNK - 1) / GP_CCHUNK)),
+                      dim3(GP_THREADS), 0, st, gp.sorted, gp.count, g.parts);
+            s = launch_status();
+        } else if (s == HF_OK) {
+            s = groups_count_particles(ctx, *box, particle_label, np, g);
+        }
         if (s == HF_OK)
             s = groups_decide(ctx, *box, roots, nullptr, nroots, g, dens_th, np, particle_th, root_ok,
                               group_particles, group_cells, group_keep);
         if (s != HF_OK) return s;
+        if (part)
+            HF_LAUNCH(ctx, K_GROUP_DECIDE, gp_bits_kernel, dim3(grid_of(ctx, nroots, GB)), dim3(GB), 0, st, roots,
+                      nroots, ncells, group_keep, gp.bits, gp.summary);
+    }
+    if (part) {
+        if (cell_label_out)
+            HF_LAUNCH(ctx, K_GROUP_FILTER, gp_filter_kernel, dim3(grid_of(ctx, ncells, GB * GPER)), dim3(GB), 0, st,
+                      cell_label, cell_label_out, ncells, ncells, gp.bits, gp.summary, ctx->d_status);
+        if (particle_label_out && np > 0)
+            HF_LAUNCH(ctx, K_GROUP_FILTER, gp_filter_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0, st,
+                      particle_label, particle_label_out, np, ncells, gp.bits, gp.summary, ctx->d_status);
+        return launch_status();
     }
     s = groups_filter(ctx, *box, cell_label, cell_label_out, ncells, g, nroots > 0);
     if (s == HF_OK) s = groups_filter(ctx, *box, particle_label, particle_label_out, np, g, nroots > 0);

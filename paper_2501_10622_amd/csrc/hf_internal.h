@@ -220,6 +220,10 @@ size_t cwt_ws_bytes(const hf_box &box);
 size_t maxima_ws_bytes(const hf_box &box);
 size_t segment_ws_bytes(const hf_box &box);
 size_t groups_ws_bytes(const hf_box &box);
+// hf_groups' partition scratch beyond the counters (labels partitioned by
+// range, a keep bitmap), for the workspace hf_workspace_size gives for
+// HF_STAGE_GROUPS alone.
+size_t groups_part_ws_bytes(const hf_box &box, int64_t np);
 // Step 8 with the maxima count on the device (cap = the list's capacity); the
 // smaller scale's field is on an n_smaller^3 grid over the same box; c_smaller
 // null compares with the all-zero grid.

@@ -472,7 +472,7 @@ def groups(cell_label: torch.Tensor, particle_label: torch.Tensor, roots: torch.
         "particle_label": torch.empty_like(particle_label) if filter_particles else None,
     }
     b = box(n, 1.0)
-    need = workspace_size(n, 1.0, 0, STAGE_GROUPS)
+    need = workspace_size(n, 1.0, int(particle_label.numel()), STAGE_GROUPS)  # with the partitioned count's room
     ws = workspace(need, ctx)
     if root_ok is not None and (root_ok.dtype != torch.uint8 or root_ok.numel() != nroots):
         raise ValueError("root_ok must be uint8 with one flag per root")

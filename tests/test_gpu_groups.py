@@ -120,9 +120,13 @@ def test_no_groups_and_no_particles():
     assert_same(run_gpu(cl2, np.zeros(0, np.int32), roots, 0, 4.0, 0), want)
 
 
-def test_in_place_outputs_and_repeat_calls():
+@pytest.mark.parametrize("sized_for", [0, 30000])
+def test_in_place_outputs_and_repeat_calls(sized_for):
     # the C ABI allows the label outputs to be the inputs; the workspace keeps
-    # the first call's counters and must not leak them into the second
+    # the first call's counters and must not leak them into the second.  A
+    # workspace sized for no particles holds only the counters (one global
+    # atomic per particle); one sized for the call also holds the partitioned
+    # count and the keep bitmap.
     from paper_2501_10622_amd import hf
     import ctypes
     n = 32
@@ -135,7 +139,7 @@ def test_in_place_outputs_and_repeat_calls():
     gk = torch.empty(len(roots), dtype=torch.uint8, device="cuda")
     ctx = hfm().context(0)
     b = hf.box(n, 1.0)
-    need = hf.workspace_size(n, 1.0, 0, hf.STAGE_GROUPS)
+    need = hf.workspace_size(n, 1.0, sized_for, hf.STAGE_GROUPS)
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     p = hf._ptr
     for want in (want1, want2):
