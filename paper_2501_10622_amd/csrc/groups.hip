@@ -455,7 +455,7 @@ constexpr int GP_THREADS = 1024;
 constexpr int GP_PER = 8;
 constexpr int GP_CHUNK = GP_THREADS * GP_PER;  // labels per scatter workgroup
 constexpr int GP_HCHUNK = 8 * GP_CHUNK;        // labels per histogram workgroup
-constexpr int GP_CCHUNK = 2 * GP_CHUNK;        // partitioned labels per counting workgroup
+constexpr int GP_CCHUNK = 32 * GP_CHUNK;       // partitioned labels per counting workgroup (few flushes per root)
 constexpr int GP_HT = 8192;                    // LDS tally slots of the counting pass
 
 struct GroupPart {
@@ -590,10 +590,16 @@ __global__ void __launch_bounds__(GP_THREADS) gp_count_kernel(const int32_t *__r
     if (c0 >= int64_t(total)) return;  // the same for the whole workgroup
     lds_tally_init<GP_HT>(hkey, hcnt);
     __syncthreads();
-    for (int k = 0; k < GP_CCHUNK / GP_THREADS; ++k) {
-        const int64_t i = c0 + int64_t(k) * GP_THREADS + threadIdx.x;
-        const int32_t l = i < int64_t(total) ? sorted[i] : -1;
-        lds_tally_wave<GP_HT>(hkey, hcnt, parts, l);
+    const int64_t c1 = c0 + GP_CCHUNK < int64_t(total) ? c0 + GP_CCHUNK : int64_t(total);
+    for (int64_t b0 = c0; b0 < c1; b0 += int64_t(GP_THREADS) * 8) {  // the same trip count on every lane
+        int32_t l[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t i = b0 + int64_t(k) * GP_THREADS + threadIdx.x;
+            l[k] = i < c1 ? sorted[i] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) lds_tally_wave<GP_HT>(hkey, hcnt, parts, l[k]);
     }
     __syncthreads();
     lds_tally_flush<GP_HT>(hkey, hcnt, parts);
