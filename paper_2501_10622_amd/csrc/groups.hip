@@ -462,13 +462,16 @@ struct GroupPart {
     uint32_t *count;   // [GP_BUCKETS + 1]: labels per bucket, then the total at [GP_BUCKETS]
     uint32_t *cursor;  // [GP_BUCKETS]
     int32_t *sorted;   // [np]
-    uint32_t *bits;    // [words] keep bitmap, then [words / 16 rounded up] its summary
+    uint32_t *bits;    // keep bitmap, one bit per cell, then its summary
     int64_t words;     // of the bitmap and its summary together
-    uint32_t *summary;
+    uint32_t *summary;  // [swords]: one bit per 2^blog cells, set where the block holds a kept root
+    int64_t swords;
+    int blog;
     int shift;
 };
 
-constexpr int GP_BLOCK_LOG = 9;  // cells per summary bit: 512, one 64-byte line of the bitmap
+constexpr int GP_BLOCK_LOG = 9;  // fewest cells per summary bit (log 2): 512, one 64-byte line of the bitmap
+constexpr int GP_SUMMARY_LOG = 20;  // most summary bits (log 2): 128 KB, to sit in one workgroup's LDS
 
 __device__ __forceinline__ bool gp_label_ok(int32_t l, int64_t ncells, bool &bad) {
     if (l >= ncells || l < -1) {
@@ -612,43 +615,94 @@ __global__ void __launch_bounds__(GB) gp_zero_kernel(uint32_t *__restrict__ w, i
 // Bit r of the bitmap for every kept root r (decided in the same pass's keep flags).
 __global__ void __launch_bounds__(GB) gp_bits_kernel(const int32_t *__restrict__ roots, int64_t nroots,
                                                      int64_t ncells, const uint8_t *__restrict__ keep,
-                                                     uint32_t *__restrict__ bits, uint32_t *__restrict__ summary) {
+                                                     uint32_t *__restrict__ bits, uint32_t *__restrict__ summary,
+                                                     int blog) {
     for (int64_t i = blockIdx.x * int64_t(GB) + threadIdx.x; i < nroots; i += int64_t(gridDim.x) * GB) {
         const int32_t r = roots[i];
         if (r >= 0 && r < ncells && keep[i]) {
-            const uint32_t u = uint32_t(r), blk = u >> GP_BLOCK_LOG;
+            const uint32_t u = uint32_t(r), blk = u >> blog;
             atomicOr(&bits[u >> 5], 1u << (u & 31u));
             atomicOr(&summary[blk >> 5], 1u << (blk & 31u));
         }
     }
 }
 
-__device__ __forceinline__ bool gp_kept(const uint32_t *__restrict__ bits, const uint32_t *__restrict__ summary,
-                                        uint32_t l) {
-    const uint32_t blk = l >> GP_BLOCK_LOG;
-    if (!((summary[blk >> 5] >> (blk & 31u)) & 1u)) return false;
-    return (bits[l >> 5] >> (l & 31u)) & 1u;
-}
-
+// Labels stream through once (non-temporal, so the bitmap and its summary keep
+// the cache); the lookups go in phases so every lane has all its loads of one
+// kind in flight at once: the labels, then the summary words, then the bitmap
+// words of those whose 512-cell block holds a kept root.
 __global__ void __launch_bounds__(GB) gp_filter_kernel(const int32_t *in, int32_t *out, int64_t count,
                                                        int64_t ncells, const uint32_t *__restrict__ bits,
-                                                       const uint32_t *__restrict__ summary, uint32_t *status) {
+                                                       const uint32_t *__restrict__ summary, int blog,
+                                                       uint32_t *status) {
+    constexpr int P = 2 * GPER;
     bool bad = false;
     const int64_t stride = int64_t(gridDim.x) * GB;
-    for (int64_t i0 = blockIdx.x * int64_t(GB) + threadIdx.x; i0 < count; i0 += stride * GPER) {
-        int32_t l[GPER];
+    for (int64_t i0 = blockIdx.x * int64_t(GB) + threadIdx.x; i0 < count; i0 += stride * P) {
+        int32_t l[P];
+        uint32_t w[P];
 #pragma unroll
-        for (int k = 0; k < GPER; ++k) {
+        for (int k = 0; k < P; ++k) {
             const int64_t i = i0 + k * stride;
-            l[k] = i < count ? in[i] : -1;
+            l[k] = i < count ? __builtin_nontemporal_load(in + i) : -1;
         }
 #pragma unroll
-        for (int k = 0; k < GPER; ++k) {
+        for (int k = 0; k < P; ++k) {
+            if (!gp_label_ok(l[k], ncells, bad)) l[k] = -1;
+            const uint32_t blk = uint32_t(l[k] < 0 ? 0 : l[k]) >> blog;
+            w[k] = summary[blk >> 5] >> (blk & 31u);
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const uint32_t u = uint32_t(l[k]);
+            w[k] = (l[k] >= 0 && (w[k] & 1u)) ? bits[u >> 5] >> (u & 31u) : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
             const int64_t i = i0 + k * stride;
-            if (i >= count) continue;
-            int32_t v = -1;
-            if (gp_label_ok(l[k], ncells, bad) && gp_kept(bits, summary, uint32_t(l[k]))) v = l[k];
-            out[i] = v;
+            if (i < count) __builtin_nontemporal_store((w[k] & 1u) ? l[k] : -1, out + i);
+        }
+    }
+    if (bad) atomicOr(status, ST_INPUT);
+}
+
+// The same filter for labels in no spatial order (particles in input order):
+// there neighbouring lanes look up unrelated summary words, which the vector
+// cache serves one line at a time, so each workgroup first copies the summary
+// (at most 128 KB) into LDS and looks it up there.
+constexpr int GP_FP = 16;  // labels per thread per sweep of the LDS filter
+__global__ void __launch_bounds__(GP_THREADS) gp_filter_lds_kernel(const int32_t *in, int32_t *out, int64_t count,
+                                                                   int64_t ncells, const uint32_t *__restrict__ bits,
+                                                                   const uint32_t *__restrict__ summary,
+                                                                   int swords, int blog, uint32_t *status) {
+    extern __shared__ uint32_t gp_lsum[];
+    for (int i = threadIdx.x; i < swords; i += GP_THREADS) gp_lsum[i] = summary[i];
+    __syncthreads();
+    bool bad = false;
+    const int64_t stride = int64_t(gridDim.x) * GP_THREADS;
+    for (int64_t i0 = blockIdx.x * int64_t(GP_THREADS) + threadIdx.x; i0 < count; i0 += stride * GP_FP) {
+        int32_t l[GP_FP];
+        uint32_t w[GP_FP];
+#pragma unroll
+        for (int k = 0; k < GP_FP; ++k) {
+            const int64_t i = i0 + k * stride;
+            l[k] = i < count ? __builtin_nontemporal_load(in + i) : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < GP_FP; ++k) {
+            if (!gp_label_ok(l[k], ncells, bad)) l[k] = -1;
+            const uint32_t blk = uint32_t(l[k] < 0 ? 0 : l[k]) >> blog;
+            w[k] = gp_lsum[blk >> 5] >> (blk & 31u);
+        }
+#pragma unroll
+        for (int k = 0; k < GP_FP; ++k) {
+            const uint32_t u = uint32_t(l[k]);
+            w[k] = (l[k] >= 0 && (w[k] & 1u)) ? bits[u >> 5] >> (u & 31u) : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < GP_FP; ++k) {
+            const int64_t i = i0 + k * stride;
+            if (i < count) __builtin_nontemporal_store((w[k] & 1u) ? l[k] : -1, out + i);
         }
     }
     if (bad) atomicOr(status, ST_INPUT);
@@ -665,7 +719,10 @@ int64_t cells_of(const hf_box &box) { return int64_t(box.n) * box.n * box.n; }
 // The partition scratch of hf_groups, after the counters.
 size_t part_layout(const hf_box &box, int64_t np, size_t base, void *ws, GroupPart *out) {
     const int64_t ncells = cells_of(box);
-    const int64_t fine = (ncells + 31) / 32, coarse = ((ncells >> GP_BLOCK_LOG) + 1 + 31) / 32;
+    int bitsneeded = 0;
+    while ((int64_t(1) << bitsneeded) < ncells) ++bitsneeded;
+    const int blog = bitsneeded - GP_SUMMARY_LOG > GP_BLOCK_LOG ? bitsneeded - GP_SUMMARY_LOG : GP_BLOCK_LOG;
+    const int64_t fine = (ncells + 31) / 32, coarse = ncells > 0 ? (((ncells - 1) >> blog) >> 5) + 1 : 1;
     const int64_t words = fine + coarse;
     size_t off = base;
     auto take = [&](size_t bytes) {
@@ -679,14 +736,14 @@ size_t part_layout(const hf_box &box, int64_t np, size_t base, void *ws, GroupPa
     const size_t bi = take(sizeof(uint32_t) * size_t(words));
     if (out && ws) {
         char *w = static_cast<char *>(ws);
-        int bitsneeded = 0;
-        while ((int64_t(1) << bitsneeded) < ncells) ++bitsneeded;
         out->count = reinterpret_cast<uint32_t *>(w + c);
         out->cursor = reinterpret_cast<uint32_t *>(w + cur);
         out->sorted = reinterpret_cast<int32_t *>(w + so);
         out->bits = reinterpret_cast<uint32_t *>(w + bi);
         out->summary = out->bits + fine;
         out->words = words;
+        out->swords = coarse;
+        out->blog = blog;
         out->shift = bitsneeded > 8 ? bitsneeded - 8 : 0;  // label >> shift < GP_BUCKETS
     }
     return off - base;
@@ -877,15 +934,30 @@ extern "C" hf_status hf_groups(hf_ctx *ctx, const hf_box *box, int64_t np, const
         if (s != HF_OK) return s;
         if (part)
             HF_LAUNCH(ctx, K_GROUP_DECIDE, gp_bits_kernel, dim3(grid_of(ctx, nroots, GB)), dim3(GB), 0, st, roots,
-                      nroots, ncells, group_keep, gp.bits, gp.summary);
+                      nroots, ncells, group_keep, gp.bits, gp.summary, gp.blog);
     }
     if (part) {
         if (cell_label_out)
-            HF_LAUNCH(ctx, K_GROUP_FILTER, gp_filter_kernel, dim3(grid_of(ctx, ncells, GB * GPER)), dim3(GB), 0, st,
-                      cell_label, cell_label_out, ncells, ncells, gp.bits, gp.summary, ctx->d_status);
-        if (particle_label_out && np > 0)
-            HF_LAUNCH(ctx, K_GROUP_FILTER, gp_filter_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0, st,
-                      particle_label, particle_label_out, np, ncells, gp.bits, gp.summary, ctx->d_status);
+            HF_LAUNCH(ctx, K_GROUP_FILTER, gp_filter_kernel, dim3(grid_of(ctx, ncells, GB * 2 * GPER)), dim3(GB), 0, st,
+                      cell_label, cell_label_out, ncells, ncells, gp.bits, gp.summary, gp.blog, ctx->d_status);
+        if (particle_label_out && np > 0) {
+            const size_t lds = sizeof(uint32_t) * size_t(gp.swords);
+            const void *f = reinterpret_cast<const void *>(&gp_filter_lds_kernel);
+            const hf_status before = launch_status();  // the attribute call below may leave its own error
+            if (before != HF_OK) return before;
+            if (lds <= 65536 || hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) == hipSuccess) {
+                const int64_t want = (np + int64_t(GP_THREADS) * GP_FP - 1) / (int64_t(GP_THREADS) * GP_FP);
+                const unsigned grid = unsigned(want < int64_t(ctx->cus) * 2 ? want : int64_t(ctx->cus) * 2);
+                HF_LAUNCH(ctx, K_GROUP_FILTER, gp_filter_lds_kernel, dim3(grid), dim3(GP_THREADS), lds, st,
+                          particle_label, particle_label_out, np, ncells, gp.bits, gp.summary, int(gp.swords), gp.blog,
+                          ctx->d_status);
+            } else {
+                (void)hipGetLastError();  // no room for the summary in LDS: look it up through the cache
+                HF_LAUNCH(ctx, K_GROUP_FILTER, gp_filter_kernel, dim3(grid_of(ctx, np, GB * 2 * GPER)), dim3(GB), 0,
+                          st, particle_label, particle_label_out, np, ncells, gp.bits, gp.summary, gp.blog,
+                          ctx->d_status);
+            }
+        }
         return launch_status();
     }
     s = groups_filter(ctx, *box, cell_label, cell_label_out, ncells, g, nroots > 0);

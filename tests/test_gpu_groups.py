@@ -280,3 +280,33 @@ def test_cell_counts_on_unaligned_labels(offset):
     hfm().sync()
     np.testing.assert_array_equal(out["cells"].cpu().numpy().astype(np.int64), want["cells"])
     np.testing.assert_array_equal(out["keep"].cpu().numpy().astype(bool), want["keep"])
+
+
+def test_grid_above_half_a_billion_cells():
+    # Above 2^29 cells the keep summary holds one bit per 1024 cells (at most
+    # 2^20 bits, so that it fits a workgroup's LDS); roots spread over the whole
+    # label range reach its last words.  Runs of up to 48 cells after each root
+    # carry its label; particles pick groups with log-uniform weights.
+    n = 816
+    ncell = n ** 3
+    assert ncell > 2 ** 29
+    rng = np.random.default_rng(816)
+    ngroups, np_ = 200_000, 3_000_000
+    roots = np.sort(rng.choice(ncell, size=ngroups, replace=False)).astype(np.int64)
+    roots[-1] = ncell - 1
+    roots = np.unique(roots)
+    gap = np.diff(np.append(roots, ncell))
+    run = np.minimum(rng.integers(1, 49, size=len(roots)), gap)
+    cl = np.full(ncell, -1, dtype=np.int32)
+    starts = np.repeat(roots, run)
+    offs = np.arange(int(run.sum())) - np.repeat(np.cumsum(run) - run, run)
+    cl[starts + offs] = starts.astype(np.int32)
+    weight = run * np.exp(rng.uniform(np.log(0.25), np.log(16.0), size=len(roots)))
+    pl = roots[rng.choice(len(roots), size=np_, p=weight / weight.sum())].astype(np.int32)
+    pl = np.where(rng.random(np_) < 0.1, -1, pl).astype(np.int32)
+    roots = roots.astype(np.int32)
+    cl = cl.reshape(n, n, n)
+    print(f"groups n={n} groups={len(roots)} np={np_}", flush=True)
+    want = O.group_stats(cl, pl, roots, n, np_, 4.0, 15)
+    assert 0 < want["keep"].sum() < len(roots) and roots[want["keep"]].max() >= ncell - ncell // 64
+    assert_same(run_gpu(cl, pl, roots, np_, 4.0, 15), want)
