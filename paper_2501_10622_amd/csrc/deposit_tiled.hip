@@ -995,10 +995,14 @@ __device__ void slot_dest(const uint16_t *off_s, int ndest, uint32_t *mark, uint
 // takes the value at its staging position.  Rejected elements get -1.  With
 // FILTER, a label l >= 0 whose keep[l] is 0 becomes -1 (the group filter of
 // step 7; labels of a chunk's runs are few, so these reads stay in cache).
-template <bool FILTER>
+// With CLAIM, the elements' labels also claim them as ClaimOut describes;
+// with TCLAIM, the source slots' claim state is tested and advanced as
+// TileClaim describes (FILTER is then on).
+template <bool FILTER, bool CLAIM = false, bool TCLAIM = false>
 __device__ void chunk_gather(const RunMaps &m, int64_t chunk, int ndest, int64_t e0, int64_t e1,
                              const int32_t *__restrict__ src, int32_t *__restrict__ dst,
-                             const uint32_t *__restrict__ keep) {
+                             const uint32_t *__restrict__ keep, const ClaimOut &claim = ClaimOut{},
+                             const TileClaim &tc = TileClaim{}) {
     __shared__ uint32_t base_s[MAX_DIGITS];
     __shared__ uint16_t off_s[OFF_STRIDE];
     __shared__ int32_t val[CHUNK];
@@ -1020,8 +1024,16 @@ __device__ void chunk_gather(const RunMaps &m, int64_t chunk, int ndest, int64_t
         const uint32_t s = k * PART_THREADS + threadIdx.x;
         if (s < total) {
             const int d = dd[k];
-            v[k] = src[base_s[d] + (s - off_s[d])];
-            if (FILTER && v[k] >= 0 && !keep[v[k]]) v[k] = -1;
+            const uint32_t at = base_s[d] + (s - off_s[d]);
+            v[k] = src[at];
+            if (TCLAIM) {
+                const bool open = tc.first || tc.cs[at] < 0;
+                if (!open || !tc.any || (v[k] >= 0 && !keep[v[k]])) v[k] = -1;
+                if (tc.first) tc.cs[at] = v[k] >= 0 ? tc.scale : -1;
+                else if (v[k] >= 0) tc.cs[at] = tc.scale;
+            } else if (FILTER && v[k] >= 0 && !keep[v[k]]) {
+                v[k] = -1;
+            }
         }
     }
 #pragma unroll
@@ -1033,20 +1045,27 @@ __device__ void chunk_gather(const RunMaps &m, int64_t chunk, int ndest, int64_t
 #pragma unroll
     for (int k = 0; k < PART_PER; ++k) {
         const int64_t e = e0 + k * PART_THREADS + threadIdx.x;
-        if (e < e1) dst[e] = p[k] < total ? val[p[k]] : -1;
+        if (e >= e1) continue;
+        const int32_t l = p[k] < total ? val[p[k]] : -1;
+        dst[e] = l;
+        if (CLAIM && (claim.first || l >= 0)) {
+            claim.halo_scale[e] = l >= 0 ? claim.scale : -1;
+            claim.halo_root[e] = l;
+        }
     }
 }
 
 // Pass 2, level-1 order: lab1[j] = lab2[level-2 slot of record j], one
 // workgroup per level-2 scatter chunk (CHUNK records of one bucket); with
-// FILTER, labels of disposed groups (keep[label] == 0) become -1.
-template <bool FILTER>
+// FILTER, labels of disposed groups (keep[label] == 0) become -1; with
+// TCLAIM, also those of particles claimed before, and the rest claim theirs.
+template <bool FILTER, bool TCLAIM>
 __global__ void __launch_bounds__(PART_THREADS) to_level1_kernel(RunMaps m2, const uint32_t *__restrict__ start1,
                                                                  const uint32_t *__restrict__ chunk_first,
                                                                  int nbuckets, int digits,
                                                                  const int32_t *__restrict__ lab2,
                                                                  int32_t *__restrict__ lab1,
-                                                                 const uint32_t *__restrict__ keep) {
+                                                                 const uint32_t *__restrict__ keep, TileClaim tc) {
     const uint32_t w = xcd_remap(blockIdx.x, gridDim.x);  // as the level-2 scatter placed them
     if (w >= chunk_first[nbuckets]) return;
     int L = 0, R = nbuckets - 1;  // last b with chunk_first[b] <= w
@@ -1059,21 +1078,22 @@ __global__ void __launch_bounds__(PART_THREADS) to_level1_kernel(RunMaps m2, con
     const int64_t lo = int64_t(start1[b]) + int64_t(w - chunk_first[b]) * CHUNK;
     const int64_t end = start1[b + 1];
     const int64_t hi = lo + CHUNK < end ? lo + CHUNK : end;
-    chunk_gather<FILTER>(m2, w, digits, lo, hi, lab2, lab1, keep);
+    chunk_gather<FILTER, false, TCLAIM>(m2, w, digits, lo, hi, lab2, lab1, keep, ClaimOut{}, tc);
 }
 
 // Pass 3, input order: particle i -> lab1[level-1 slot of i], one workgroup
-// per level-1 scatter chunk.
+// per level-1 scatter chunk; with CLAIM the labels also claim their particles.
+template <bool CLAIM>
 __global__ void __launch_bounds__(PART_THREADS) to_input_kernel(RunMaps m1, int64_t np, int nbuckets,
                                                                 const int32_t *__restrict__ lab1,
-                                                                int32_t *__restrict__ out) {
+                                                                int32_t *__restrict__ out, ClaimOut claim) {
     // the level-1 scatter's chunk order: each XCD reads the runs of the counter
     // replicas it wrote, in the order it wrote them, so runs sharing lines meet in one L2
     const int64_t chunk = replica_chunk(blockIdx.x, unsigned((np + CHUNK - 1) / CHUNK));
     if (chunk < 0) return;
     const int64_t e0 = chunk * CHUNK;
     const int64_t e1 = e0 + CHUNK < np ? e0 + CHUNK : np;
-    chunk_gather<false>(m1, chunk, nbuckets, e0, e1, lab1, out, nullptr);
+    chunk_gather<false, CLAIM>(m1, chunk, nbuckets, e0, e1, lab1, out, nullptr, claim);
 }
 
 // ---------------------------------------------------------------- host side
@@ -1412,7 +1432,8 @@ hf_status hf::label_tiles(hf_ctx *ctx, const hf_box &box, int64_t np, const Part
 }
 
 hf_status hf::label_back(hf_ctx *ctx, const hf_box &box, int64_t np, const ParticleOrder &order,
-                         int32_t *particle_label, void *scratch, const uint32_t *keep) {
+                         int32_t *particle_label, void *scratch, const uint32_t *keep, const ClaimOut *claim,
+                         const TileClaim *tile_claim) {
     if (np <= 0) return HF_OK;
     Geom g;
     if (!make_geom(box, g)) return HF_ERR_SIZE;
@@ -1423,16 +1444,25 @@ hf_status hf::label_back(hf_ctx *ctx, const hf_box &box, int64_t np, const Parti
     RunMaps m1, m2;
     __builtin_memcpy(&m1, order.maps[0], sizeof(m1));
     __builtin_memcpy(&m2, order.maps[1], sizeof(m2));
-    if (keep)
-        HF_LAUNCH(ctx, K_LABEL_LEVEL1, to_level1_kernel<true>, dim3(blocks + unsigned(g.nbuckets)),
+    if (tile_claim && !keep) return HF_ERR_ARG;
+    if (tile_claim)
+        HF_LAUNCH(ctx, K_LABEL_LEVEL1, (to_level1_kernel<true, true>), dim3(blocks + unsigned(g.nbuckets)),
                   dim3(PART_THREADS), 0, ctx->stream, m2, order.start1, order.chunk_first, g.nbuckets, g.digits, lab2,
-                  lab1, keep);
+                  lab1, keep, *tile_claim);
+    else if (keep)
+        HF_LAUNCH(ctx, K_LABEL_LEVEL1, (to_level1_kernel<true, false>), dim3(blocks + unsigned(g.nbuckets)),
+                  dim3(PART_THREADS), 0, ctx->stream, m2, order.start1, order.chunk_first, g.nbuckets, g.digits, lab2,
+                  lab1, keep, TileClaim{});
     else
-        HF_LAUNCH(ctx, K_LABEL_LEVEL1, to_level1_kernel<false>, dim3(blocks + unsigned(g.nbuckets)),
+        HF_LAUNCH(ctx, K_LABEL_LEVEL1, (to_level1_kernel<false, false>), dim3(blocks + unsigned(g.nbuckets)),
                   dim3(PART_THREADS), 0, ctx->stream, m2, order.start1, order.chunk_first, g.nbuckets, g.digits, lab2,
-                  lab1, nullptr);
-    HF_LAUNCH(ctx, K_LABEL_INPUT, to_input_kernel, dim3(replica_grid(blocks)), dim3(PART_THREADS), 0, ctx->stream,
-              m1, np, g.nbuckets, lab1, particle_label);
+                  lab1, nullptr, TileClaim{});
+    if (claim)
+        HF_LAUNCH(ctx, K_LABEL_INPUT, to_input_kernel<true>, dim3(replica_grid(blocks)), dim3(PART_THREADS), 0,
+                  ctx->stream, m1, np, g.nbuckets, lab1, particle_label, *claim);
+    else
+        HF_LAUNCH(ctx, K_LABEL_INPUT, to_input_kernel<false>, dim3(replica_grid(blocks)), dim3(PART_THREADS), 0,
+                  ctx->stream, m1, np, g.nbuckets, lab1, particle_label, ClaimOut{});
     return launch_status();
 }
 

@@ -383,29 +383,6 @@ __global__ void __launch_bounds__(GB) claim_filter_kernel(int32_t *__restrict__ 
     if (bad) atomicOr(status, ST_INPUT);
 }
 
-// A scale's filtered labels in input order claim their particles.
-__global__ void __launch_bounds__(GB) claim_take_kernel(const int32_t *__restrict__ label,
-                                                        int32_t *__restrict__ halo_scale,
-                                                        int32_t *__restrict__ halo_root, int64_t np, int32_t scale) {
-    const int64_t stride = int64_t(gridDim.x) * GB;
-    for (int64_t i0 = blockIdx.x * int64_t(GB) + threadIdx.x; i0 < np; i0 += stride * GPER) {
-        int32_t l[GPER];
-#pragma unroll
-        for (int k = 0; k < GPER; ++k) {
-            const int64_t i = i0 + k * stride;
-            l[k] = i < np ? label[i] : -1;
-        }
-#pragma unroll
-        for (int k = 0; k < GPER; ++k) {
-            const int64_t i = i0 + k * stride;
-            if (l[k] >= 0) {
-                halo_scale[i] = scale;
-                halo_root[i] = l[k];
-            }
-        }
-    }
-}
-
 // Step 4's correction of grid maxima (App. B): each maximum's corrected
 // position (wrapped into [0, L)) and value, from peak_fit.
 __global__ void __launch_bounds__(GB) peaks_kernel(const int32_t *__restrict__ roots, int64_t nroots, int n,
@@ -783,7 +760,15 @@ hf_status hf::groups_count_particles_tiled(hf_ctx *ctx, const hf_box &box, const
                                            int64_t np, const GroupCounters &g) {
     if (np <= 0) return HF_OK;
     const dim3 grid(unsigned((np + GCHUNK - 1) / GCHUNK));
-    if (reinterpret_cast<uintptr_t>(label) % sizeof(int4) == 0 && reinterpret_cast<uintptr_t>(mask) % sizeof(int4) == 0)
+    const bool aligned = reinterpret_cast<uintptr_t>(label) % sizeof(int4) == 0 &&
+                         reinterpret_cast<uintptr_t>(mask) % sizeof(int4) == 0;
+    if (!mask && aligned)
+        HF_LAUNCH(ctx, K_GROUP_PARTICLES, groups_runs_kernel<false>, grid, dim3(GB), 0, ctx->stream, label, nullptr,
+                  np, cells_of(box), g.parts, ctx->d_status);
+    else if (!mask)
+        HF_LAUNCH(ctx, K_GROUP_PARTICLES, groups_tally_kernel<false>, grid, dim3(GB), 0, ctx->stream, label, nullptr,
+                  np, cells_of(box), g.parts, ctx->d_status);
+    else if (aligned)
         HF_LAUNCH(ctx, K_GROUP_PARTICLES, groups_runs_kernel<true>, grid, dim3(GB), 0, ctx->stream, label, mask, np,
                   cells_of(box), g.parts, ctx->d_status);
     else
@@ -840,14 +825,6 @@ hf_status hf::claim_filter(hf_ctx *ctx, const hf_box &box, int32_t *label, int32
     if (np <= 0) return HF_OK;
     HF_LAUNCH(ctx, K_CLAIM, claim_filter_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0, ctx->stream, label,
               halo_scale, halo_root, np, cells_of(box), g.cells, any_roots ? 1 : 0, scale, ctx->d_status);
-    return launch_status();
-}
-
-hf_status hf::claim_take(hf_ctx *ctx, const int32_t *label, int32_t *halo_scale, int32_t *halo_root, int64_t np,
-                         int32_t scale) {
-    if (np <= 0) return HF_OK;
-    HF_LAUNCH(ctx, K_CLAIM, claim_take_kernel, dim3(grid_of(ctx, np, GB * GPER)), dim3(GB), 0, ctx->stream, label,
-              halo_scale, halo_root, np, scale);
     return launch_status();
 }
 

@@ -193,7 +193,7 @@ hf_status groups_count_cells(hf_ctx *ctx, const hf_box &box, const int32_t *root
 hf_status groups_count_particles(hf_ctx *ctx, const hf_box &box, const int32_t *particle_label, int64_t np,
                                  const GroupCounters &g, const int32_t *skip = nullptr);
 // The same count over labels in the deposit's tile order (LDS tables; entries
-// whose mask is >= 0 skipped).
+// whose mask is >= 0 skipped; mask may be null).
 hf_status groups_count_particles_tiled(hf_ctx *ctx, const hf_box &box, const int32_t *label, const int32_t *mask,
                                        int64_t np, const GroupCounters &g);
 // Decides every group and writes the per-group outputs; then, where given,
@@ -205,14 +205,38 @@ hf_status groups_decide(hf_ctx *ctx, const hf_box &box, const int32_t *roots, co
 hf_status groups_filter(hf_ctx *ctx, const hf_box &box, const int32_t *in, int32_t *out, int64_t count,
                         const GroupCounters &g, bool any_roots);
 
+// Where the pass back to input order also claims particles for a scale of the
+// identification loop: a label l >= 0 sets halo_scale = scale and
+// halo_root = l; with first, every particle is written (-1 and -1 where
+// l < 0), so that the two arrays need no clearing before the first scale.
+struct ClaimOut {
+    int32_t *halo_scale;
+    int32_t *halo_root;
+    int32_t scale;
+    int32_t first;
+};
+// The same loop's claim state in the deposit's tile order (cs, one entry per
+// level-2 slot: the scale that claimed the particle, or -1), tested and
+// advanced by the pass to level-1 order: a label survives only where cs is
+// -1, its group is kept and the scale has maxima (any), and then claims its
+// slot.  With first, cs is not read but written for every slot.
+struct TileClaim {
+    int32_t *cs;
+    int32_t scale;
+    int32_t first;
+    int32_t any;
+};
+
 // Step 6 through a kept particle order in its two halves: the tile pass
 // (counting each label's particles into parts when given) and the two passes
 // back to input order (labels of groups whose keep flag is 0 become -1 when
-// keep is given).  label_from_order is the two in turn.
+// keep is given; the particles claimed when claim is given).
+// label_from_order is the two in turn.
 hf_status label_tiles(hf_ctx *ctx, const hf_box &box, int64_t np, const ParticleOrder &order,
                       const int32_t *cell_label, void *scratch, uint32_t *parts);
 hf_status label_back(hf_ctx *ctx, const hf_box &box, int64_t np, const ParticleOrder &order,
-                     int32_t *particle_label, void *scratch, const uint32_t *keep);
+                     int32_t *particle_label, void *scratch, const uint32_t *keep, const ClaimOut *claim = nullptr,
+                     const TileClaim *tile_claim = nullptr);
 
 // Workspace requirements of each stage (defined next to each stage).
 size_t deposit_ws_bytes(const hf_box &box, int64_t np);
@@ -236,10 +260,6 @@ hf_status claim_init(hf_ctx *ctx, int32_t *halo_scale, int32_t *halo_root, int64
 // may be null).
 hf_status claim_filter(hf_ctx *ctx, const hf_box &box, int32_t *label, int32_t *halo_scale, int32_t *halo_root,
                        int64_t np, const GroupCounters &g, bool any_roots, int32_t scale);
-// Filtered labels (input order) claim their particles: halo_scale = scale,
-// halo_root = the label, where the label is >= 0.
-hf_status claim_take(hf_ctx *ctx, const int32_t *label, int32_t *halo_scale, int32_t *halo_root, int64_t np,
-                     int32_t scale);
 size_t stencil_ws_bytes(const hf_box &box);
 // Steps 9-10 for the kept groups (keep[i]) of the roots: afterwards only the
 // bound particles of the groups that pass keep their labels; bound_keep[i]

@@ -231,11 +231,12 @@ extern "C" hf_status hf_identify_ws_size(const hf_box *box, int64_t np, int32_t 
 // (largest first) the flowchart's pair of grids: the cross-scale flags of this
 // scale's maxima against the next scale's field (the zero grid after the last),
 // the groups' statistics over the particles not yet claimed, the step-7/8
-// decision, and one pass that filters the labels and claims the kept groups'
-// particles.  Where the deposit keeps its particle order, labels, counts and
-// claims run in that (tile) order, whose neighbouring particles share groups;
-// each scale's filtered labels come back to input order once and claim their
-// particles there too.
+// decision, and the filter of the labels with the claims of the kept groups'
+// particles.  Where the deposit keeps its particle order, labels and counts
+// run in that (tile) order, whose neighbouring particles share groups, and
+// the filter and the claims ride on the two passes that bring each scale's
+// labels back to input order (the claim state is kept in tile order for the
+// counts; the first scale writes the claim arrays outright).
 extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos, hf_dtype dtype, int64_t np,
                                  hf_kernel kernel, float tau, int64_t *rho, int32_t count, const hf_scale_job *scales,
                                  const hf_identify_groups *groups, double dens_th, int64_t particle_th,
@@ -292,8 +293,9 @@ extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos
     // order is kept (the masks of the counts and the claims there)
     int32_t *cs = order ? reinterpret_cast<int32_t *>(w0 + L.claim) : halo_scale;
     int32_t *lab2 = reinterpret_cast<int32_t *>(sw);  // tile-order labels (label scratch)
-    s = claim_init(ctx, halo_scale, halo_root, np);
-    if (s == HF_OK && order) s = claim_init(ctx, cs, nullptr, np);
+    // in tile order the first scale writes both claim arrays outright (nothing
+    // is claimed before it), so neither is cleared first
+    if (!order) s = claim_init(ctx, halo_scale, halo_root, np);
     for (int j = 0; j < count && s == HF_OK; ++j) {
         const hf_scale_job &sj = scales[j];
         const hf_identify_groups &gj = groups[j];
@@ -306,15 +308,19 @@ extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos
         if (s == HF_OK) s = groups_count_cells(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, sj.cell_label, g);
         // particles already claimed are not counted
         if (s == HF_OK && sj.max_cap > 0)
-            s = order ? groups_count_particles_tiled(ctx, *box, lab, cs, np, g)
+            s = order ? groups_count_particles_tiled(ctx, *box, lab, j > 0 ? cs : nullptr, np, g)
                       : groups_count_particles(ctx, *box, lab, np, g, cs);
         if (s == HF_OK)
             s = groups_decide(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, g, dens_th, np, particle_th, pass,
                               gj.group_particles, gj.group_cells, gj.group_keep);
-        if (s == HF_OK)
-            s = claim_filter(ctx, *box, lab, cs, order ? nullptr : halo_root, np, g, sj.max_cap > 0, j);
-        if (s == HF_OK && order) s = label_back(ctx, *box, np, po, sj.particle_label, sw, nullptr);
-        if (s == HF_OK && order) s = claim_take(ctx, sj.particle_label, halo_scale, halo_root, np, j);
+        if (s == HF_OK && !order)
+            s = claim_filter(ctx, *box, lab, cs, halo_root, np, g, sj.max_cap > 0, j);
+        if (s == HF_OK && order) {
+            // the filter and the claims ride on the two passes back to input order
+            const TileClaim tc{cs, j, j == 0 ? 1 : 0, sj.max_cap > 0 ? 1 : 0};
+            const ClaimOut claim{halo_scale, halo_root, j, j == 0 ? 1 : 0};
+            s = label_back(ctx, *box, np, po, sj.particle_label, sw, g.cells, &claim, &tc);
+        }
     }
     return s;
 }

@@ -117,6 +117,9 @@ def test_equals_composition_of_entry_points(n, L, np_, halos, scales):
     dens_th, pth = 2.0, 15
     print(f"identify composition n={n} scales={len(kws)}", flush=True)
     bufs = hfm().identify_buffers(n, np_, len(kws), "cuda")
+    # the claim outputs need no clearing: the loop writes every particle's entry
+    bufs["halo_scale"].fill_(3)
+    bufs["halo_root"].fill_(7)
     hfm().identify_async(pos, L, n, kws, bufs, dens_th, pth)
     hfm().sync()
     sb = hfm().scales_buffers(n, np_, len(kws), "cuda")
