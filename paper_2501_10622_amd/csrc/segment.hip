@@ -311,38 +311,96 @@ __global__ void __launch_bounds__(PR_THREADS) parent_resolve_kernel(const float 
         return best;
     };
     int32_t l[PR_PER];
-    uint64_t b0 = plane_max(0), b1 = plane_max(1);
+    // a tile whose halo does not wrap around the periodic box: there a cell's
+    // neighbours, taken in (dz, dy, dx) order, come in increasing global index,
+    // so the largest key is the last largest value met in that order (32-bit
+    // compares and a neighbour code 0..26, no index per neighbour)
+    const bool interior = FULL && x0 > 0 && x0 + RX < n && y0 > 0 && y0 + RY < n && z0 > 0 && z0 + RZ < n;
+    if (interior) {
+        auto plane_arg = [&](int hz, uint32_t &bv, uint32_t &bc) {
+            bv = V[(hz * RHY + y) * RHX + x];
+            bc = 0u;
 #pragma unroll
-    for (int z = 0; z < RZ; ++z) {
-        const uint64_t b2 = plane_max(z + 2);
-        const uint64_t best = kmax(kmax(b0, b1), b2);
-        const bool real = x < wx && y < wy && z < wz;
-        const uint32_t g = (uint32_t(z0 + z) * un + uint32_t(y0 + y)) * un + uint32_t(x0 + x);
-        const uint32_t p = uint32_t(best);
-        const bool high = uint32_t(best >> 32) > tau_ord;
-        if (mask) {
-            if (FULL) {  // the wavefront's two rows are two aligned mask words
-                const unsigned long long bits = __ballot(p == g && high);
+            for (int k = 1; k < 9; ++k) {
+                const uint32_t v = V[(hz * RHY + y + k / 3) * RHX + x + k % 3];
+                const bool up = v >= bv;
+                bv = up ? v : bv;
+                bc = up ? uint32_t(k) : bc;
+            }
+        };
+        uint32_t v0, c0, v1, c1;
+        plane_arg(0, v0, c0);
+        plane_arg(1, v1, c1);
+        const uint32_t gb = (uint32_t(z0) * un + uint32_t(y0 + y)) * un + uint32_t(x0 + x);
+#pragma unroll
+        for (int z = 0; z < RZ; ++z) {
+            uint32_t v2, c2;
+            plane_arg(z + 2, v2, c2);
+            uint32_t bv = v0, bc = c0;
+            if (v1 >= bv) {
+                bv = v1;
+                bc = c1 + 9u;
+            }
+            if (v2 >= bv) {
+                bv = v2;
+                bc = c2 + 18u;
+            }
+            const uint32_t g = gb + uint32_t(z) * un * un;
+            const bool self = bc == 13u;  // (dz, dy, dx) = (1, 1, 1)
+            const bool high = bv > tau_ord;
+            if (mask) {  // the wavefront's two rows are two aligned mask words
+                const unsigned long long bits = __ballot(self && high);
                 if (lane == 0) {
                     mask[g >> 5] = uint32_t(bits);
                     mask[(g + un) >> 5] = uint32_t(bits >> 32);
                 }
-            } else if (real && p == g && high) {  // rows straddle words: the mask was cleared first
-                atomicOr(&mask[g >> 5], 1u << (g & 31u));
             }
+            const int lx = x + int(bc % 3u) - 1, ly = y + int((bc / 3u) % 3u) - 1, lz = z + int(bc / 9u) - 1;
+            if (self)
+                l[z] = high ? -2 - int32_t(g) : -1;
+            else if (lx >= 0 && lx < RX && ly >= 0 && ly < RY && lz >= 0 && lz < RZ)
+                l[z] = lx + RX * (ly + RY * lz);
+            else
+                l[z] = -2 - int32_t((uint32_t(z0 + lz) * un + uint32_t(y0 + ly)) * un + uint32_t(x0 + lx));
+            v0 = v1;
+            c0 = c1;
+            v1 = v2;
+            c1 = c2;
         }
-        // local form: a root (above tau: itself; else -1) is resolved, so is
-        // a parent outside the tile; a parent inside is followed
-        l[z] = (p == g) ? (high ? -2 - int32_t(g) : -1) : -2 - int32_t(p);
-        if (!real) l[z] = -1;  // absent
-        if (real && p != g) {
-            uint32_t px, py, pz;
-            cell_coords(rg, p, px, py, pz);
-            const int lx = int(px) - x0, ly = int(py) - y0, lz = int(pz) - z0;
-            if (lx >= 0 && lx < RX && ly >= 0 && ly < RY && lz >= 0 && lz < RZ) l[z] = lx + RX * (ly + RY * lz);
+    } else {
+        uint64_t b0 = plane_max(0), b1 = plane_max(1);
+#pragma unroll
+        for (int z = 0; z < RZ; ++z) {
+            const uint64_t b2 = plane_max(z + 2);
+            const uint64_t best = kmax(kmax(b0, b1), b2);
+            const bool real = x < wx && y < wy && z < wz;
+            const uint32_t g = (uint32_t(z0 + z) * un + uint32_t(y0 + y)) * un + uint32_t(x0 + x);
+            const uint32_t p = uint32_t(best);
+            const bool high = uint32_t(best >> 32) > tau_ord;
+            if (mask) {
+                if (FULL) {  // the wavefront's two rows are two aligned mask words
+                    const unsigned long long bits = __ballot(p == g && high);
+                    if (lane == 0) {
+                        mask[g >> 5] = uint32_t(bits);
+                        mask[(g + un) >> 5] = uint32_t(bits >> 32);
+                    }
+                } else if (real && p == g && high) {  // rows straddle words: the mask was cleared first
+                    atomicOr(&mask[g >> 5], 1u << (g & 31u));
+                }
+            }
+            // local form: a root (above tau: itself; else -1) is resolved, so is
+            // a parent outside the tile; a parent inside is followed
+            l[z] = (p == g) ? (high ? -2 - int32_t(g) : -1) : -2 - int32_t(p);
+            if (!real) l[z] = -1;  // absent
+            if (real && p != g) {
+                uint32_t px, py, pz;
+                cell_coords(rg, p, px, py, pz);
+                const int lx = int(px) - x0, ly = int(py) - y0, lz = int(pz) - z0;
+                if (lx >= 0 && lx < RX && ly >= 0 && ly < RY && lz >= 0 && lz < RZ) l[z] = lx + RX * (ly + RY * lz);
+            }
+            b0 = b1;
+            b1 = b2;
         }
-        b0 = b1;
-        b1 = b2;
     }
     if (nan) atomicOr(status, ST_INPUT);
     __syncthreads();  // every read of the field is done

@@ -207,6 +207,7 @@ def _oracle_field32(n, L, a, seed, quantise=None):
     (64, 100.0, 2.0, 1, None, 0.0),
     (96, 96.0, 1.5, 6, None, 0.0),
     (256, 250.0, 2.0, 2, None, 0.0),
+    (128, 128.0, 1.0, 10, 0.5, 0.0),  # engineered ties, most tiles clear of the periodic faces
     # sizes that leave short resolve tiles: one cell wide (33), odd (47), both
     # axes short by different amounts (75)
     (33, 33.0, 1.0, 7, 0.5, 0.0),
