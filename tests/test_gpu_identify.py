@@ -109,6 +109,9 @@ def test_matches_oracle_loop(case):
 
 @pytest.mark.parametrize("n,L,np_,halos,scales", [
     (128, 125.0, 128 ** 3, 1200, (4.0, 2.0, 1.0)),
+    # every scale claims particles: the later scales' counts and filters skip
+    # the particles claimed before them (tile-order claim state)
+    (128, 125.0, 128 ** 3, 1200, (1.5, 1.25, 1.0)),
     (96, 96.0, 500000, 300, (3.0, 2.5, 2.0, 1.5, 1.0)),
 ])
 def test_equals_composition_of_entry_points(n, L, np_, halos, scales):
@@ -145,6 +148,8 @@ def test_equals_composition_of_entry_points(n, L, np_, halos, scales):
     assert torch.equal(bufs["halo_scale"][:np_], claimed)
     assert torch.equal(bufs["halo_root"][:np_], root)
     assert int((claimed >= 0).sum()) > 0
+    if scales == (1.5, 1.25, 1.0):
+        assert all(int((claimed == i).sum()) > 0 for i in range(len(kws)))
 
 
 def test_scale_order_and_arguments_checked():
