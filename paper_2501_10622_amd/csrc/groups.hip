@@ -607,7 +607,7 @@ __global__ void __launch_bounds__(GB) gp_bits_kernel(const int32_t *__restrict__
 // Labels stream through once (non-temporal, so the bitmap and its summary keep
 // the cache); the lookups go in phases so every lane has all its loads of one
 // kind in flight at once: the labels, then the summary words, then the bitmap
-// words of those whose 512-cell block holds a kept root.
+// words of those whose summary block (2^blog cells) holds a kept root.
 __global__ void __launch_bounds__(GB) gp_filter_kernel(const int32_t *in, int32_t *out, int64_t count,
                                                        int64_t ncells, const uint32_t *__restrict__ bits,
                                                        const uint32_t *__restrict__ summary, int blog,
