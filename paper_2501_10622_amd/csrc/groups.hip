@@ -740,20 +740,12 @@ GroupCounters hf::group_counters_at(const hf_box &box, void *region) {
                          reinterpret_cast<uint32_t *>(base + align_up(size_t(cells_of(box)) * sizeof(uint32_t)))};
 }
 
-hf_status hf::groups_clear(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count,
-                           int64_t cap, const GroupCounters &g) {
-    if (cap <= 0) return HF_OK;
-    HF_LAUNCH(ctx, K_GROUP_CLEAR, groups_clear_kernel, dim3(grid_of(ctx, cap, GB)), dim3(GB), 0, ctx->stream, roots,
-              d_count, cap, cells_of(box), g, ctx->d_status);
-    return launch_status();
-}
-
 hf_status hf::groups_count_cells(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count,
                                  int64_t cap, const int32_t *cell_label, const GroupCounters &g) {
     const int64_t ncells = cells_of(box);
     if (cap <= 0) return HF_OK;
-    hf_status s = groups_clear(ctx, box, roots, d_count, cap, g);
-    if (s != HF_OK) return s;
+    HF_LAUNCH(ctx, K_GROUP_CLEAR, groups_clear_kernel, dim3(grid_of(ctx, cap, GB)), dim3(GB), 0, ctx->stream, roots,
+              d_count, cap, ncells, g, ctx->d_status);
     const dim3 grid(unsigned((ncells + GCHUNK - 1) / GCHUNK));
     if (reinterpret_cast<uintptr_t>(cell_label) % sizeof(int4) == 0)
         HF_LAUNCH(ctx, K_GROUP_CELLS, groups_runs_kernel<false>, grid, dim3(GB), 0, ctx->stream, cell_label, nullptr,

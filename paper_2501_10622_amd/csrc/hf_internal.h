@@ -171,17 +171,11 @@ size_t label_scratch_bytes(int64_t np);
 hf_status label_from_order(hf_ctx *ctx, const hf_box &box, int64_t np, const ParticleOrder &order,
                            const int32_t *cell_label, int32_t *particle_label, void *scratch);
 
-struct GroupCounters;
-
-// Steps 4 and 5 with one pass over the field (the parents give the maxima mask
-// too); workspace maxima_segment_ws_bytes(box).  With cells_into and a maxima
-// list (max_cap > 0), the listed maxima's group counters are cleared and the
-// pass that writes the cell labels also counts every group's cells into
-// cells_into->cells (step 5's volumes, as groups_count_cells would).
+// Steps 4 and 5 in one pass over the field where the grid is tiled (n % 32 ==
+// 0), else hf_maxima then hf_segment; workspace maxima_segment_ws_bytes(box).
 size_t maxima_segment_ws_bytes(const hf_box &box);
 hf_status maxima_segment(hf_ctx *ctx, const hf_box &box, const float *cwt, float tau, int32_t *max_idx,
-                         int64_t max_cap, int64_t *d_count, int32_t *cell_label, void *ws, size_t ws_bytes,
-                         const GroupCounters *cells_into = nullptr);
+                         int64_t max_cap, int64_t *d_count, int32_t *cell_label, void *ws, size_t ws_bytes);
 
 // Group statistics (steps 5 and 7): per-root counters in two n^3 uint32 arrays
 // indexed by the root's cell (only the listed roots' entries are touched);
@@ -192,10 +186,7 @@ struct GroupCounters {
 };
 GroupCounters group_counters_at(const hf_box &box, void *region);
 // Clears the counters of roots[0, min(*d_count, cap)) (all cap with d_count
-// null).
-hf_status groups_clear(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count, int64_t cap,
-                       const GroupCounters &g);
-// Clears them as groups_clear and counts every group's cells.
+// null) and counts every group's cells.
 hf_status groups_count_cells(hf_ctx *ctx, const hf_box &box, const int32_t *roots, const int64_t *d_count,
                              int64_t cap, const int32_t *cell_label, const GroupCounters &g);
 // Counts particle labels in input order (one atomic per labelled particle).

@@ -91,14 +91,13 @@ extern "C" hf_status hf_find_halos_filtered(hf_ctx *ctx, const hf_box *box, cons
     if (s != HF_OK) return s;
     s = hf_cwt(ctx, box, job->rho, job->kw, job->kernel, job->cwt, sw, sb);
     if (s != HF_OK) return s;
-    // in tile order the counters have a region of their own, so the
-    // segmentation's last pass counts the group volumes as it writes the labels
     s = maxima_segment(ctx, *box, job->cwt, job->tau, job->max_idx, job->max_cap, job->d_count, job->cell_label, sw,
-                       sb, order ? &g : nullptr);
+                       sb);
     if (s != HF_OK) return s;
     const int64_t cap = job->max_cap;
     if (order) {
-        s = label_tiles(ctx, *box, job->np, po, job->cell_label, sw, cap > 0 ? g.parts : nullptr);
+        s = groups_count_cells(ctx, *box, job->max_idx, job->d_count, cap, job->cell_label, g);
+        if (s == HF_OK) s = label_tiles(ctx, *box, job->np, po, job->cell_label, sw, cap > 0 ? g.parts : nullptr);
         if (s == HF_OK)
             s = groups_decide(ctx, *box, job->max_idx, job->d_count, cap, g, gf->dens_th, job->np, gf->particle_th,
                               nullptr, gf->group_particles, gf->group_cells, gf->group_keep);
@@ -228,11 +227,10 @@ extern "C" hf_status hf_identify_ws_size(const hf_box *box, int64_t np, int32_t 
 }
 
 // Sec. 2's identification loop at one grid: one deposit and one forward
-// transform, every scale's field, then scale by scale (largest first) its
-// maxima and segmentation (the groups' volumes counted as the labels are
-// written) and the flowchart's pair of grids: the cross-scale flags of this
+// transform, every scale's field, maxima and segmentation, then scale by scale
+// (largest first) the flowchart's pair of grids: the cross-scale flags of this
 // scale's maxima against the next scale's field (the zero grid after the last),
-// the groups' particle numbers over the particles not yet claimed, the step-7/8
+// the groups' statistics over the particles not yet claimed, the step-7/8
 // decision, and the filter of the labels with the claims of the kept groups'
 // particles.  Where the deposit keeps its particle order, labels and counts
 // run in that (tile) order, whose neighbouring particles share groups, and
@@ -284,6 +282,10 @@ extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos
         s = hf_deposit(ctx, box, pos, dtype, np, rho, sw, sb);
     }
     if (s == HF_OK) s = hf_cwt_scales(ctx, box, rho, count, kws, kernel, cwts, sw, sb);
+    for (int j = 0; j < count && s == HF_OK; ++j) {
+        const hf_scale_job &sj = scales[j];
+        s = maxima_segment(ctx, *box, sj.cwt, tau, sj.max_idx, sj.max_cap, sj.d_count, sj.cell_label, sw, sb);
+    }
     if (s != HF_OK) return s;
     const GroupCounters g = group_counters_at(*box, w0 + L.groups);
     uint8_t *pass = reinterpret_cast<uint8_t *>(w0 + L.pass);
@@ -299,14 +301,11 @@ extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos
         const hf_identify_groups &gj = groups[j];
         const float *next = j + 1 < count ? scales[j + 1].cwt : nullptr;
         int32_t *lab = order ? lab2 : sj.particle_label;
-        // steps 4-5 of this scale, with its groups' volumes counted as the labels
-        // are written (the cross-scale check needs only the next scale's field)
-        s = maxima_segment(ctx, *box, sj.cwt, tau, sj.max_idx, sj.max_cap, sj.d_count, sj.cell_label, sw, sb, &g);
-        if (s == HF_OK)
-            s = cross_scale_dev(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, sj.cwt, box->n, next, pass);
+        s = cross_scale_dev(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, sj.cwt, box->n, next, pass);
         if (s == HF_OK)
             s = order ? label_tiles(ctx, *box, np, po, sj.cell_label, sw, nullptr)
                       : hf_label(ctx, box, pos, dtype, np, sj.cell_label, sj.particle_label);
+        if (s == HF_OK) s = groups_count_cells(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, sj.cell_label, g);
         // particles already claimed are not counted
         if (s == HF_OK && sj.max_cap > 0)
             s = order ? groups_count_particles_tiled(ctx, *box, lab, j > 0 ? cs : nullptr, np, g)

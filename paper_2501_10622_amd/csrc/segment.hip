@@ -574,19 +574,12 @@ __global__ void __launch_bounds__(256) bnd_jump_kernel(int32_t *__restrict__ bnd
 // one-cell shell around the tile go to LDS (they belong to the neighbouring
 // tiles; every exit target of the tile lies in the shell), then every cell of
 // the tile maps its pointer: -1 stays -1, a target inside the tile is a root
-// above tau, a target in the shell takes the shell's entry.  With COUNT the
-// labels are also tallied in LDS and each group's cells added to cells[root]
-// once per tile (step 5's volumes).
-constexpr int FIN_HT = 1024;  // tally slots: a tile holds at most a few hundred groups
-template <bool FULL, bool COUNT>
+// above tau, a target in the shell takes the shell's entry.
+template <bool FULL>
 __global__ void __launch_bounds__(RES_THREADS) seg_finalize_kernel(const int32_t *__restrict__ ptr,
                                                                    const int32_t *__restrict__ bnd, TileGrid rg,
-                                                                   int32_t *__restrict__ label,
-                                                                   uint32_t *__restrict__ cells) {
-    __shared__ __align__(16) int32_t shell[RHCELLS];
-    __shared__ int32_t hkey[COUNT ? FIN_HT : 1];
-    __shared__ uint32_t hcnt[COUNT ? FIN_HT : 1];
-    if (COUNT) lds_tally_init<FIN_HT>(hkey, hcnt);  // ordered before use by the barrier below
+                                                                   int32_t *__restrict__ label) {
+    __shared__ int32_t shell[RHCELLS];
     int x0, y0, z0;
     const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
     rtile_origin(rg, int(tile), x0, y0, z0);
@@ -649,48 +642,19 @@ __global__ void __launch_bounds__(RES_THREADS) seg_finalize_kernel(const int32_t
     for (int i = 0; i < RES_PER; ++i) {
         const int e = i * RES_THREADS + threadIdx.x;
         const int x = e % RX, y = (e / RX) % RY, z = e / (RX * RY);
-        int32_t r = -1;
-        if (x < wx && y < wy && z < wz) {
-            const uint32_t g = ((uint32_t(z0 + z) * un) + uint32_t(y0 + y)) * un + uint32_t(x0 + x);
-            r = t[i];
-            if (r >= 0) {
-                uint32_t px, py, pz;
-                cell_coords(rg, uint32_t(r), px, py, pz);
-                // shell coordinates of the target, periodic
-                const int hx = int(wrap(int(px) - x0 + 1, n)), hy = int(wrap(int(py) - y0 + 1, n)),
-                          hz = int(wrap(int(pz) - z0 + 1, n));
-                const bool inside = hx >= 1 && hx <= wx && hy >= 1 && hy <= wy && hz >= 1 && hz <= wz;
-                if (!inside) r = shell[(hz * RHY + hy) * RHX + hx];
-            }
-            label[g] = r;
+        if (x >= wx || y >= wy || z >= wz) continue;
+        const uint32_t g = ((uint32_t(z0 + z) * un) + uint32_t(y0 + y)) * un + uint32_t(x0 + x);
+        int32_t r = t[i];
+        if (r >= 0) {
+            uint32_t px, py, pz;
+            cell_coords(rg, uint32_t(r), px, py, pz);
+            // shell coordinates of the target, periodic
+            const int hx = int(wrap(int(px) - x0 + 1, n)), hy = int(wrap(int(py) - y0 + 1, n)),
+                      hz = int(wrap(int(pz) - z0 + 1, n));
+            const bool inside = hx >= 1 && hx <= wx && hy >= 1 && hy <= wy && hz >= 1 && hz <= wz;
+            if (!inside) r = shell[(hz * RHY + hy) * RHX + hx];
         }
-        t[i] = r;
-    }
-    if (COUNT) {
-        // the tile's labels go to LDS in place of the shell (absent cells -1),
-        // then each thread adds the runs of 8 consecutive cells of a row
-        static_assert(RCELLS == 8 * RES_THREADS && RX % 8 == 0, "8 cells of one row per thread");
-        __syncthreads();  // every read of the shell is done
-#pragma unroll
-        for (int i = 0; i < RES_PER; ++i) shell[i * RES_THREADS + threadIdx.x] = t[i];
-        __syncthreads();
-        const int4 *row = reinterpret_cast<const int4 *>(shell + 8 * threadIdx.x);
-        const int4 a0 = row[0], a1 = row[1];
-        const int32_t v[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-        int32_t run = -1;
-        uint32_t len = 0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            if (v[q] != run) {
-                if (run >= 0) lds_tally_add<FIN_HT>(hkey, hcnt, cells, run, len);
-                run = v[q];
-                len = 0;
-            }
-            ++len;
-        }
-        if (run >= 0) lds_tally_add<FIN_HT>(hkey, hcnt, cells, run, len);
-        __syncthreads();
-        lds_tally_flush<FIN_HT>(hkey, hcnt, cells);
+        label[g] = r;
     }
 }
 
@@ -920,8 +884,7 @@ hf_status launch_parent_resolve(hf_ctx *ctx, const SegmentLayout &L, char *w8, i
 
 // After launch_parent_resolve: pointer-jumping rounds over the boundary
 // entries, and the final mapping through them.
-hf_status segment_finish(hf_ctx *ctx, const SegmentLayout &L, char *w8, int n, int32_t *cell_label,
-                         uint32_t *cells = nullptr) {
+hf_status segment_finish(hf_ctx *ctx, const SegmentLayout &L, char *w8, int n, int32_t *cell_label) {
     const TileGrid tg = resolve_grid(n);
     auto *flags = reinterpret_cast<uint32_t *>(w8 + L.flags);
     auto *ptr = reinterpret_cast<int32_t *>(w8 + L.ptr);
@@ -947,18 +910,12 @@ hf_status segment_finish(hf_ctx *ctx, const SegmentLayout &L, char *w8, int n, i
                       list[(r - 1) & 1], counts[(r - 1) & 1], list[r & 1], counts[r & 1], L.list_cap, tg, flags, r);
     }
     const dim3 grid(tg.ntx * tg.nty * tg.ntz);
-    if (full && cells)
-        HF_LAUNCH(ctx, K_FINALIZE, (seg_finalize_kernel<true, true>), grid, dim3(RES_THREADS), 0, ctx->stream, ptr,
-                  bnd, tg, cell_label, cells);
-    else if (full)
-        HF_LAUNCH(ctx, K_FINALIZE, (seg_finalize_kernel<true, false>), grid, dim3(RES_THREADS), 0, ctx->stream, ptr,
-                  bnd, tg, cell_label, nullptr);
-    else if (cells)
-        HF_LAUNCH(ctx, K_FINALIZE, (seg_finalize_kernel<false, true>), grid, dim3(RES_THREADS), 0, ctx->stream, ptr,
-                  bnd, tg, cell_label, cells);
+    if (full)
+        HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel<true>, grid, dim3(RES_THREADS), 0, ctx->stream, ptr, bnd, tg,
+                  cell_label);
     else
-        HF_LAUNCH(ctx, K_FINALIZE, (seg_finalize_kernel<false, false>), grid, dim3(RES_THREADS), 0, ctx->stream, ptr,
-                  bnd, tg, cell_label, nullptr);
+        HF_LAUNCH(ctx, K_FINALIZE, seg_finalize_kernel<false>, grid, dim3(RES_THREADS), 0, ctx->stream, ptr, bnd, tg,
+                  cell_label);
     return launch_status();
 }
 
@@ -971,8 +928,7 @@ size_t hf::maxima_segment_ws_bytes(const hf_box &box) {
 // Steps 4 and 5 together: on tiled grids one pass over the field yields both
 // the parents and the maxima mask.  Same results as hf_maxima then hf_segment.
 hf_status hf::maxima_segment(hf_ctx *ctx, const hf_box &box, const float *cwt, float tau, int32_t *max_idx,
-                             int64_t max_cap, int64_t *d_count, int32_t *cell_label, void *ws, size_t ws_bytes,
-                             const GroupCounters *cells_into) {
+                             int64_t max_cap, int64_t *d_count, int32_t *cell_label, void *ws, size_t ws_bytes) {
     const int n = box.n;
     if (!ctx || !cwt || !d_count || !cell_label || max_cap < 0 || (max_cap > 0 && !max_idx) || tau != tau)
         return HF_ERR_ARG;
@@ -994,10 +950,7 @@ hf_status hf::maxima_segment(hf_ctx *ctx, const hf_box &box, const float *cwt, f
     if (s != HF_OK) return s;
     s = mask_to_list(ctx, ML, wm, max_idx, max_cap, d_count);
     if (s != HF_OK) return s;
-    const bool count = cells_into && max_cap > 0;
-    if (count) s = groups_clear(ctx, box, max_idx, d_count, max_cap, *cells_into);
-    if (s != HF_OK) return s;
-    return segment_finish(ctx, SL, w8, n, cell_label, count ? cells_into->cells : nullptr);
+    return segment_finish(ctx, SL, w8, n, cell_label);
 }
 
 extern "C" hf_status hf_maxima(hf_ctx *ctx, const hf_box *box, const float *cwt, float tau, int32_t *max_idx,
