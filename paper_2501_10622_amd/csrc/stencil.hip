@@ -26,8 +26,10 @@ namespace {
 
 constexpr int ST_THREADS = 256;
 constexpr int ST_LANES = 64;          // x columns of a y- or z-pass tile (one wavefront row)
-constexpr int ST_GROUPS = ST_THREADS / ST_LANES;
-constexpr int ST_T = 32;              // outputs along the pass axis per tile (32 measured faster than 48, 64, 128)
+constexpr int ST_GROUPS = 8;          // wavefront rows of a y- or z-pass workgroup
+constexpr int ST_AX_THREADS = ST_LANES * ST_GROUPS;
+constexpr int ST_K = 8;               // outputs per thread along the pass axis
+constexpr int ST_T = ST_GROUPS * ST_K;  // outputs along the pass axis per tile
 constexpr int ST_X_CELLS = 4096;      // line-buffer cells per x-pass workgroup (whole rows)
 
 struct StencilLayout {
@@ -222,19 +224,32 @@ __global__ void __launch_bounds__(1024)
 
 // y (ZPASS false, axis stride n) and z (ZPASS true, axis stride n^2) passes.
 // A tile is ST_LANES x columns by ST_T outputs along the axis at one value of
-// the third coordinate; it reads ST_T + 2h lines of both inputs into LDS.
-// Tiles that neighbour along the axis (and share halo lines) are consecutive
-// logical blocks, which xcd_remap keeps on one XCD.
+// the third coordinate; it reads ST_T + 2 hp lines of both inputs into LDS,
+// hp = h rounded up to ST_K (taps past h weigh 0), with one spare line at each
+// end that the last tap's window refill may read but no output uses.  Tiles that neighbour along
+// the axis (and share halo lines) are consecutive logical blocks, which
+// xcd_remap keeps on one XCD.
+//
+// Each thread makes ST_K consecutive outputs along the axis.  For tap d they
+// need the inputs at k + d and k - d (k < ST_K): two windows of ST_K values per
+// input, kept in registers, that move by one line per tap, so a tap costs two
+// LDS reads per input instead of 2 ST_K.  The tap loop is unrolled by ST_K,
+// which turns each window's rotation into fixed register names.  Every output
+// adds its taps in the same order as a plain loop over d would.
+
+__host__ __device__ inline int stencil_pad(int h) { return (h + ST_K - 1) / ST_K * ST_K; }
+
 template <bool ZPASS>
-__global__ void __launch_bounds__(ST_THREADS)
+__global__ void __launch_bounds__(ST_AX_THREADS)
     stencil_axis_kernel(const float *__restrict__ in0, const float *__restrict__ in1, float *__restrict__ out0,
                         float *__restrict__ out1, const double *__restrict__ scalars, int n, int h, int tiles_x,
                         int tiles_t, double wdx) {
     extern __shared__ float sm[];
-    const int R = ST_T + 2 * h;
-    float *wa = sm, *wb = sm + (h + 1);
-    float *b0 = sm + 2 * (h + 1);
-    float *b1 = b0 + R * ST_LANES;
+    const int hp = stencil_pad(h);
+    const int R = ST_T + 2 * hp;  // lines read (the spare lines are not loaded)
+    float *wa = sm, *wb = sm + (hp + 1);
+    float *b0 = sm + 2 * (hp + 1) + ST_LANES;  // line -1 is spare, so is line R
+    float *b1 = b0 + (R + 2) * ST_LANES;
     const uint32_t lt = xcd_remap(blockIdx.x, gridDim.x);
     const int tt = int(lt % uint32_t(tiles_t));
     const uint32_t rest = lt / uint32_t(tiles_t);
@@ -249,8 +264,9 @@ __global__ void __launch_bounds__(ST_THREADS)
         return ZPASS ? (size_t(t) * sn + size_t(o)) * sn + size_t(x) : (size_t(o) * sn + size_t(t)) * sn + size_t(x);
     };
     stencil_weights(wa, wb, h, wdx);
+    for (int d = h + 1 + int(threadIdx.x); d <= hp; d += ST_AX_THREADS) wa[d] = wb[d] = 0.0f;
     if (x < n) {
-        constexpr int UB = 4 * LOAD_BATCH;  // 2 UB loads in flight per lane (all of a tile's lines at h <= 16)
+        constexpr int UB = 4 * LOAD_BATCH;  // 2 UB loads in flight per lane
         for (int rb = grp; rb < R; rb += ST_GROUPS * UB) {
             float v0[UB], v1[UB];
 #pragma unroll
@@ -258,7 +274,7 @@ __global__ void __launch_bounds__(ST_THREADS)
                 const int r = rb + u * ST_GROUPS;
                 v0[u] = v1[u] = 0.0f;
                 if (r < R) {
-                    const size_t e = at(wrapq(t0 - h + r, n));
+                    const size_t e = at(wrapq(t0 - hp + r, n));
                     v0[u] = in0[e];
                     v1[u] = in1[e];
                 }
@@ -275,36 +291,72 @@ __global__ void __launch_bounds__(ST_THREADS)
     }
     __syncthreads();
     if (x >= n) return;
+    const int k0 = grp * ST_K;
+    // line j of these is the input at axis offset t0 + k0 + j
+    const float *c0 = b0 + (k0 + hp) * ST_LANES + lane;
+    const float *c1 = b1 + (k0 + hp) * ST_LANES + lane;
     const float a0 = wa[0];
+    float acc0[ST_K], acc1[ST_K], acc2[ST_K];  // y: G, A*fB, B*fA;  z: A*S, B*G
+#pragma unroll
+    for (int k = 0; k < ST_K; ++k) {
+        acc0[k] = ZPASS ? a0 * c1[k * ST_LANES] : a0 * c0[k * ST_LANES];
+        acc1[k] = ZPASS ? 0.0f : a0 * c1[k * ST_LANES];
+        acc2[k] = 0.0f;
+    }
+    if (hp > 0) {
+        // windows for d = 1: up[j % ST_K] = line j (j = d .. d + ST_K - 1),
+        // lo[j % ST_K] = line j (j = -d .. ST_K - 1 - d)
+        float up0[ST_K], lo0[ST_K], up1[ST_K], lo1[ST_K];
+#pragma unroll
+        for (int j = 1; j <= ST_K; ++j) {
+            up0[j % ST_K] = c0[j * ST_LANES];
+            up1[j % ST_K] = c1[j * ST_LANES];
+        }
+#pragma unroll
+        for (int j = -1; j < ST_K - 1; ++j) {
+            lo0[(j + ST_K) % ST_K] = c0[j * ST_LANES];
+            lo1[(j + ST_K) % ST_K] = c1[j * ST_LANES];
+        }
+        for (int d8 = 0; d8 < hp; d8 += ST_K) {
+#pragma unroll
+            for (int s = 0; s < ST_K; ++s) {
+                const int d = d8 + s + 1;
+                const float wad = wa[d], wbd = wb[d];
+#pragma unroll
+                for (int k = 0; k < ST_K; ++k) {
+                    const float s0 = up0[(k + s + 1) % ST_K] + lo0[(k - s - 1 + 2 * ST_K) % ST_K];
+                    const float s1 = up1[(k + s + 1) % ST_K] + lo1[(k - s - 1 + 2 * ST_K) % ST_K];
+                    if (!ZPASS) {
+                        acc0[k] = fmaf(wad, s0, acc0[k]);
+                        acc1[k] = fmaf(wad, s1, acc1[k]);
+                        acc2[k] = fmaf(wbd, s0, acc2[k]);
+                    } else {
+                        acc0[k] = fmaf(wad, s1, acc0[k]);
+                        acc2[k] = fmaf(wbd, s0, acc2[k]);
+                    }
+                }
+                // move both windows one line outwards (after the last tap this
+                // reads a spare line or the neighbouring group's, unused)
+                up0[(s + 1) % ST_K] = c0[(d + ST_K) * ST_LANES];
+                up1[(s + 1) % ST_K] = c1[(d + ST_K) * ST_LANES];
+                lo0[(ST_K - 2 - s + ST_K) % ST_K] = c0[(-d - 1) * ST_LANES];
+                lo1[(ST_K - 2 - s + ST_K) % ST_K] = c1[(-d - 1) * ST_LANES];
+            }
+        }
+    }
     const double factor = ZPASS ? scalars[0] : 0.0;
-    for (int k = grp; k < ST_T; k += ST_GROUPS) {
-        const int t = t0 + k;
+#pragma unroll
+    for (int k = 0; k < ST_K; ++k) {
+        const int t = t0 + k0 + k;
         if (t >= n) break;
-        const float *c0 = b0 + (k + h) * ST_LANES + lane;
-        const float *c1 = b1 + (k + h) * ST_LANES + lane;
         const size_t e = at(t);
         if (!ZPASS) {
             // in0 = fA, in1 = fB: G = A*fA, S = 6 G - A*fB - B*fA
-            float g = a0 * c0[0], ab = a0 * c1[0], ba = 0.0f;
-            for (int d = 1; d <= h; ++d) {
-                const float s0 = c0[d * ST_LANES] + c0[-d * ST_LANES];
-                const float s1 = c1[d * ST_LANES] + c1[-d * ST_LANES];
-                g = fmaf(wa[d], s0, g);
-                ab = fmaf(wa[d], s1, ab);
-                ba = fmaf(wb[d], s0, ba);
-            }
-            out0[e] = g;
-            out1[e] = 6.0f * g - ab - ba;
+            out0[e] = acc0[k];
+            out1[e] = 6.0f * acc0[k] - acc1[k] - acc2[k];
         } else {
             // in0 = G, in1 = S: C = (P / mean) (A*S - B*G)
-            float as = a0 * c1[0], bg = 0.0f;
-            for (int d = 1; d <= h; ++d) {
-                const float s0 = c0[d * ST_LANES] + c0[-d * ST_LANES];
-                const float s1 = c1[d * ST_LANES] + c1[-d * ST_LANES];
-                as = fmaf(wa[d], s1, as);
-                bg = fmaf(wb[d], s0, bg);
-            }
-            out0[e] = float(double(as - bg) * factor);
+            out0[e] = float(double(acc0[k] - acc2[k]) * factor);
         }
     }
 }
@@ -345,7 +397,8 @@ extern "C" hf_status hf_cwt_stencil(hf_ctx *ctx, const hf_box *box, const int64_
     float *g1 = reinterpret_cast<float *>(b + L.g1);
     float *g2 = reinterpret_cast<float *>(b + L.g2);
     const size_t x_shm = sizeof(float) * (2 * size_t(h + 1) + size_t(L.xrows) * size_t(n + 2 * h));
-    const size_t a_shm = sizeof(float) * (2 * size_t(h + 1) + 2 * size_t(ST_T + 2 * h) * ST_LANES);
+    const size_t a_shm =
+        sizeof(float) * (2 * size_t(stencil_pad(h) + 1) + ST_LANES + 2 * size_t(ST_T + 2 * stencil_pad(h) + 2) * ST_LANES);
     auto allow = [](const void *f, size_t bytes) {
         return bytes <= 65536 ||
                hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)) == hipSuccess;
@@ -364,10 +417,10 @@ extern "C" hf_status hf_cwt_stencil(hf_ctx *ctx, const hf_box *box, const int64_
     HF_LAUNCH(ctx, K_ST_MASS, stencil_mass_kernel, dim3(1), dim3(1024), 0, st, mass, L.xblocks, n, pref, scalars,
               ctx->d_status);
     // y pass: (fA, fB) -> (G -> g1, S -> g2)
-    HF_LAUNCH(ctx, K_ST_Y, stencil_axis_kernel<false>, dim3(tiles), dim3(ST_THREADS), a_shm, st, g0, cwt, g1, g2,
+    HF_LAUNCH(ctx, K_ST_Y, stencil_axis_kernel<false>, dim3(tiles), dim3(ST_AX_THREADS), a_shm, st, g0, cwt, g1, g2,
               scalars, n, h, tiles_x, tiles_t, wdx);
     // z pass: (G, S) -> C
-    HF_LAUNCH(ctx, K_ST_Z, stencil_axis_kernel<true>, dim3(tiles), dim3(ST_THREADS), a_shm, st, g1, g2, cwt, nullptr,
+    HF_LAUNCH(ctx, K_ST_Z, stencil_axis_kernel<true>, dim3(tiles), dim3(ST_AX_THREADS), a_shm, st, g1, g2, cwt, nullptr,
               scalars, n, h, tiles_x, tiles_t, wdx);
     return launch_status();
 }
