@@ -30,7 +30,19 @@ constexpr int ST_GROUPS = 8;          // wavefront rows of a y- or z-pass workgr
 constexpr int ST_AX_THREADS = ST_LANES * ST_GROUPS;
 constexpr int ST_K = 8;               // outputs per thread along the pass axis
 constexpr int ST_T = ST_GROUPS * ST_K;  // outputs along the pass axis per tile
-constexpr int ST_X_CELLS = 4096;      // line-buffer cells per x-pass workgroup (whole rows)
+
+__host__ __device__ inline int stencil_pad(int h) { return (h + ST_K - 1) / ST_K * ST_K; }
+
+// An x-pass row buffer holds slots q = 0 .. n + 2 hp - 1 (input x = q - hp,
+// periodic) as ST_K rows of blocks: slot q at (q mod ST_K) LB + q / ST_K + 1,
+// so a lane that owns the outputs of one block reads every window element at
+// an address one above its left neighbour's.  Block 0 and the last block are
+// spare (read by window refills that no output uses), and LB = 8 mod 64 keeps
+// the staging writes of 64 consecutive slots on 64 distinct banks.
+__host__ __device__ inline int xrow_blocks(int n, int hp) {
+    const int nb = (n + ST_K - 1) / ST_K + 2 * hp / ST_K + 2;
+    return nb + (72 - nb % 64) % 64;
+}
 
 struct StencilLayout {
     size_t scalars, mass, g0, g1, g2, total;
@@ -40,9 +52,13 @@ struct StencilLayout {
 
 StencilLayout stencil_layout(int n) {
     StencilLayout L{};
-    // about ST_X_CELLS cells of line buffer per workgroup at the widest stencil
+    // rows enough for about two output blocks per thread, and at most 64 KB of
+    // row buffers at the widest stencil
     const int64_t rows = int64_t(n) * n;
-    const int64_t per = ST_X_CELLS / (n + 2 * HF_STENCIL_MAX_HALF_WIDTH);
+    const int64_t lanes = (n + ST_K - 1) / ST_K;
+    const int64_t row_floats = int64_t(ST_K) * xrow_blocks(n, stencil_pad(HF_STENCIL_MAX_HALF_WIDTH));
+    int64_t per = (2 * ST_THREADS + lanes - 1) / lanes;
+    if (per > 16384 / row_floats) per = 16384 / row_floats;
     L.xrows = int(per < 1 ? 1 : (per < rows ? per : rows));
     L.xblocks = (rows + L.xrows - 1) / L.xrows;
     const size_t grid = sizeof(float) * size_t(n) * size_t(n) * size_t(n);
@@ -108,22 +124,29 @@ __device__ __forceinline__ void block_mass(unsigned long long lo, unsigned long 
 }
 
 // x pass: xrows whole rows per workgroup; row r of the grid (r = z n + y) is
-// read once with h cells of periodic halo on either side.
+// read once with hp cells of periodic halo on either side into a row buffer
+// (xrow_blocks).  Each thread then makes the ST_K outputs of one block of a
+// row from two register windows that move one slot per tap, as the y and z
+// passes do (taps past h weigh 0), and every output adds its taps in the
+// order of a plain loop over d.
 __global__ void __launch_bounds__(ST_THREADS)
     stencil_x_kernel(const int64_t *__restrict__ rho, float *__restrict__ fa, float *__restrict__ fb,
                      Mass128 *__restrict__ mass, int n, int h, int xrows, double wdx, uint32_t *status) {
     extern __shared__ float sm[];
-    float *wa = sm, *wb = sm + (h + 1);
-    float *buf = sm + 2 * (h + 1);
+    const int hp = stencil_pad(h);
+    float *wa = sm, *wb = sm + (hp + 1);
+    float *buf = sm + 2 * (hp + 1);
+    const int LB = xrow_blocks(n, hp), RF = ST_K * LB;
     const int tid = threadIdx.x;
-    const int W = n + 2 * h;
+    const int W = n + 2 * hp;
     const int64_t nrows = int64_t(n) * n;
     const int64_t row0 = int64_t(blockIdx.x) * xrows;
     const int rows = int(nrows - row0 < xrows ? nrows - row0 : xrows);
     stencil_weights(wa, wb, h, wdx);
+    for (int d = h + 1 + tid; d <= hp; d += ST_THREADS) wa[d] = wb[d] = 0.0f;
     unsigned long long lo = 0, hi = 0;
     bool neg = false;
-    // the rows' line buffers as one run of rows * W slots, LOAD_BATCH loads in flight per thread
+    // the rows' slots as one run of rows * W, LOAD_BATCH loads in flight per thread
     const int slots = rows * W;
     for (int s0 = tid; s0 < slots; s0 += ST_THREADS * LOAD_BATCH) {
         int64_t v[LOAD_BATCH];
@@ -132,40 +155,73 @@ __global__ void __launch_bounds__(ST_THREADS)
             const int sl = s0 + u * ST_THREADS;
             v[u] = 0;
             if (sl < slots) {
-                const int r = sl / W, i = sl - r * W;
-                v[u] = rho[(row0 + r) * n + wrapq(i - h, n)];
+                const int r = sl / W, q = sl - r * W;
+                v[u] = rho[(row0 + r) * n + wrapq(q - hp, n)];
             }
         }
 #pragma unroll
         for (int u = 0; u < LOAD_BATCH; ++u) {
             const int sl = s0 + u * ST_THREADS;
             if (sl < slots) {
-                const int i = sl % W;
-                if (i >= h && i < h + n) {  // each cell counted once, from its own slot
+                const int r = sl / W, q = sl - r * W;
+                if (q >= hp && q < hp + n) {  // each cell counted once, from its own slot
                     neg |= v[u] < 0;
                     add128(lo, hi, static_cast<unsigned long long>(v[u]));
                 }
-                buf[sl] = float(v[u]);
+                buf[r * RF + (q % ST_K) * LB + q / ST_K + 1] = float(v[u]);
             }
         }
     }
     if (neg) atomicOr(status, ST_INPUT);
-    block_mass(lo, hi, mass + blockIdx.x);  // its barrier also publishes the line buffers
+    block_mass(lo, hi, mass + blockIdx.x);  // its barrier also publishes the row buffers
     const float a0 = wa[0];
-    for (int r = 0; r < rows; ++r) {
-        const float *line = buf + r * W + h;
-        float *oa = fa + (row0 + r) * n;
-        float *ob = fb + (row0 + r) * n;
-        for (int x = tid; x < n; x += ST_THREADS) {
-            const float *c = line + x;
-            float sa = a0 * c[0], sb = 0.0f;  // B(0) = 0
-            for (int d = 1; d <= h; ++d) {
-                const float s = c[d] + c[-d];
-                sa = fmaf(wa[d], s, sa);
-                sb = fmaf(wb[d], s, sb);
+    const int lanes = (n + ST_K - 1) / ST_K;
+    for (int w = tid; w < rows * lanes; w += ST_THREADS) {
+        const int r = w / lanes, l = w - r * lanes;
+        // slot qb + j (qb = ST_K l + hp, j >= -ST_K) at ((j + ST_K) mod ST_K) LB + qk + (j + ST_K) / ST_K
+        const float *row = buf + r * RF;
+        const int qk = l + hp / ST_K;  // qb / ST_K
+        float sa[ST_K], sb[ST_K];
+#pragma unroll
+        for (int k = 0; k < ST_K; ++k) {
+            sa[k] = a0 * row[k * LB + qk + 1];
+            sb[k] = 0.0f;  // B(0) = 0
+        }
+        if (hp > 0) {
+            // windows for d = 1: up[j % ST_K] = slot qb + j (j = 1 .. ST_K),
+            // lo[(j + ST_K) % ST_K] = slot qb + j (j = -1 .. ST_K - 2)
+            float up[ST_K], dn[ST_K];
+#pragma unroll
+            for (int j = 1; j <= ST_K; ++j) up[j % ST_K] = row[(j % ST_K) * LB + qk + 1 + j / ST_K];
+#pragma unroll
+            for (int j = -1; j < ST_K - 1; ++j)
+                dn[(j + ST_K) % ST_K] = row[((j + ST_K) % ST_K) * LB + qk + (j + ST_K) / ST_K];
+            for (int b8 = 0; b8 < hp / ST_K; ++b8) {
+#pragma unroll
+                for (int s = 0; s < ST_K; ++s) {
+                    const int d = b8 * ST_K + s + 1;
+                    const float wad = wa[d], wbd = wb[d];
+#pragma unroll
+                    for (int k = 0; k < ST_K; ++k) {
+                        const float v = up[(k + s + 1) % ST_K] + dn[(k - s - 1 + 2 * ST_K) % ST_K];
+                        sa[k] = fmaf(wad, v, sa[k]);
+                        sb[k] = fmaf(wbd, v, sb[k]);
+                    }
+                    // slot qb + d + ST_K into up, slot qb - d - 1 into dn
+                    up[(s + 1) % ST_K] = row[((s + 1) % ST_K) * LB + qk + b8 + 2 + (s + 1) / ST_K];
+                    dn[(2 * ST_K - s - 2) % ST_K] =
+                        row[((2 * ST_K - s - 2) % ST_K) * LB + qk - b8 - (s == ST_K - 1 ? 1 : 0)];
+                }
             }
-            oa[x] = sa;
-            ob[x] = sb;
+        }
+        float *oa = fa + (row0 + r) * n, *ob = fb + (row0 + r) * n;
+#pragma unroll
+        for (int k = 0; k < ST_K; ++k) {
+            const int x = ST_K * l + k;
+            if (x < n) {
+                oa[x] = sa[k];
+                ob[x] = sb[k];
+            }
         }
     }
 }
@@ -236,8 +292,6 @@ __global__ void __launch_bounds__(1024)
 // LDS reads per input instead of 2 ST_K.  The tap loop is unrolled by ST_K,
 // which turns each window's rotation into fixed register names.  Every output
 // adds its taps in the same order as a plain loop over d would.
-
-__host__ __device__ inline int stencil_pad(int h) { return (h + ST_K - 1) / ST_K * ST_K; }
 
 template <bool ZPASS>
 __global__ void __launch_bounds__(ST_AX_THREADS)
@@ -396,7 +450,8 @@ extern "C" hf_status hf_cwt_stencil(hf_ctx *ctx, const hf_box *box, const int64_
     float *g0 = reinterpret_cast<float *>(b + L.g0);
     float *g1 = reinterpret_cast<float *>(b + L.g1);
     float *g2 = reinterpret_cast<float *>(b + L.g2);
-    const size_t x_shm = sizeof(float) * (2 * size_t(h + 1) + size_t(L.xrows) * size_t(n + 2 * h));
+    const size_t x_shm =
+        sizeof(float) * (2 * size_t(stencil_pad(h) + 1) + size_t(L.xrows) * ST_K * size_t(xrow_blocks(n, stencil_pad(h))));
     const size_t a_shm =
         sizeof(float) * (2 * size_t(stencil_pad(h) + 1) + ST_LANES + 2 * size_t(ST_T + 2 * stencil_pad(h) + 2) * ST_LANES);
     auto allow = [](const void *f, size_t bytes) {
