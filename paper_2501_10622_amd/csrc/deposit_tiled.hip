@@ -1027,10 +1027,10 @@ __device__ void chunk_gather(const RunMaps &m, int64_t chunk, int ndest, int64_t
             const uint32_t at = base_s[d] + (s - off_s[d]);
             v[k] = src[at];
             if (TCLAIM) {
-                const bool open = tc.first || tc.cs[at] < 0;
+                const bool open = tc.first || tc.cs[at] == 0;
                 if (!open || !tc.any || (v[k] >= 0 && !keep[v[k]])) v[k] = -1;
-                if (tc.first) tc.cs[at] = v[k] >= 0 ? tc.scale : -1;
-                else if (v[k] >= 0) tc.cs[at] = tc.scale;
+                if (tc.first) tc.cs[at] = v[k] >= 0 ? 1 : 0;
+                else if (v[k] >= 0) tc.cs[at] = 1;
             } else if (FILTER && v[k] >= 0 && !keep[v[k]]) {
                 v[k] = -1;
             }

@@ -40,13 +40,13 @@ __global__ void __launch_bounds__(GB) groups_clear_kernel(const int32_t *__restr
 // contiguous range of GCHUNK cells (a few grid rows, a few hundred labels) in
 // an LDS table and adds it to the counters once.  With MASKED the same count
 // runs over `count` labels of particles in the deposit's tile order (spatially
-// coherent, like cells), skipping those whose mask entry is >= 0.
+// coherent, like cells), skipping those whose mask byte is nonzero.
 constexpr int GCHUNK = 16384;
 constexpr int CELL_HT = 1024;
 
 template <bool MASKED>
 __global__ void __launch_bounds__(GB) groups_tally_kernel(const int32_t *__restrict__ label,
-                                                          const int32_t *__restrict__ mask, int64_t count,
+                                                          const uint8_t *__restrict__ mask, int64_t count,
                                                           int64_t ncells, uint32_t *__restrict__ cells,
                                                           uint32_t *status) {
     __shared__ int32_t hkey[CELL_HT];
@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(GB) groups_tally_kernel(const int32_t *__restr
         for (int k = 0; k < GPER; ++k) {
             const int64_t i = base + k * GB + threadIdx.x;
             l[k] = i < c1 ? label[i] : -1;
-            if (MASKED && i < c1 && mask[i] >= 0) l[k] = -1;
+            if (MASKED && i < c1 && mask[i]) l[k] = -1;
         }
 #pragma unroll
         for (int k = 0; k < GPER; ++k) {
@@ -82,12 +82,14 @@ __global__ void __launch_bounds__(GB) groups_tally_kernel(const int32_t *__restr
 // vector load per four) and adds each run of equal labels to the LDS table
 // once, so a basin a few cells wide costs one insert per run instead of one
 // per cell.  With MASKED, the same over particle labels in the deposit's tile
-// order, skipping those whose mask entry is >= 0.  Both arrays 16-byte aligned.
+// order, skipping those whose mask byte is nonzero.  Both arrays 16-byte
+// aligned.
 constexpr int CELL_RUN = 16;
+static_assert(CELL_RUN == 16, "one 16-byte load of mask bytes per run of labels");
 
 template <bool MASKED>
 __global__ void __launch_bounds__(GB) groups_runs_kernel(const int32_t *__restrict__ cell_label,
-                                                         const int32_t *__restrict__ mask, int64_t count,
+                                                         const uint8_t *__restrict__ mask, int64_t count,
                                                          int64_t ncells, uint32_t *__restrict__ cells,
                                                          uint32_t *status) {
     __shared__ int32_t hkey[CELL_HT];
@@ -101,7 +103,14 @@ __global__ void __launch_bounds__(GB) groups_runs_kernel(const int32_t *__restri
         int32_t v[CELL_RUN];
         if (b + CELL_RUN <= c1) {
             const int4 *p = reinterpret_cast<const int4 *>(cell_label + b);
-            const int4 *pm = MASKED ? reinterpret_cast<const int4 *>(mask + b) : nullptr;
+            uint32_t mw[CELL_RUN / 4] = {};  // the CELL_RUN mask bytes, four per word
+            if (MASKED) {
+                const uint4 m = *reinterpret_cast<const uint4 *>(mask + b);
+                mw[0] = m.x;
+                mw[1] = m.y;
+                mw[2] = m.z;
+                mw[3] = m.w;
+            }
 #pragma unroll
             for (int q = 0; q < CELL_RUN / 4; ++q) {
                 const int4 w = p[q];
@@ -110,18 +119,16 @@ __global__ void __launch_bounds__(GB) groups_runs_kernel(const int32_t *__restri
                 v[4 * q + 2] = w.z;
                 v[4 * q + 3] = w.w;
                 if (MASKED) {
-                    const int4 m = pm[q];
-                    if (m.x >= 0) v[4 * q] = -1;
-                    if (m.y >= 0) v[4 * q + 1] = -1;
-                    if (m.z >= 0) v[4 * q + 2] = -1;
-                    if (m.w >= 0) v[4 * q + 3] = -1;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if ((mw[q] >> (8 * e)) & 0xffu) v[4 * q + e] = -1;
                 }
             }
         } else {
 #pragma unroll
             for (int q = 0; q < CELL_RUN; ++q) {
                 v[q] = b + q < c1 ? cell_label[b + q] : -1;
-                if (MASKED && b + q < c1 && mask[b + q] >= 0) v[q] = -1;
+                if (MASKED && b + q < c1 && mask[b + q]) v[q] = -1;
             }
         }
         int32_t run = -1;
@@ -756,7 +763,7 @@ hf_status hf::groups_count_cells(hf_ctx *ctx, const hf_box &box, const int32_t *
     return launch_status();
 }
 
-hf_status hf::groups_count_particles_tiled(hf_ctx *ctx, const hf_box &box, const int32_t *label, const int32_t *mask,
+hf_status hf::groups_count_particles_tiled(hf_ctx *ctx, const hf_box &box, const int32_t *label, const uint8_t *mask,
                                            int64_t np, const GroupCounters &g) {
     if (np <= 0) return HF_OK;
     const dim3 grid(unsigned((np + GCHUNK - 1) / GCHUNK));

@@ -193,8 +193,8 @@ hf_status groups_count_cells(hf_ctx *ctx, const hf_box &box, const int32_t *root
 hf_status groups_count_particles(hf_ctx *ctx, const hf_box &box, const int32_t *particle_label, int64_t np,
                                  const GroupCounters &g, const int32_t *skip = nullptr);
 // The same count over labels in the deposit's tile order (LDS tables; entries
-// whose mask is >= 0 skipped; mask may be null).
-hf_status groups_count_particles_tiled(hf_ctx *ctx, const hf_box &box, const int32_t *label, const int32_t *mask,
+// whose mask byte is nonzero skipped; mask may be null).
+hf_status groups_count_particles_tiled(hf_ctx *ctx, const hf_box &box, const int32_t *label, const uint8_t *mask,
                                        int64_t np, const GroupCounters &g);
 // Decides every group and writes the per-group outputs; then, where given,
 // the filtered cell labels.
@@ -215,14 +215,13 @@ struct ClaimOut {
     int32_t scale;
     int32_t first;
 };
-// The same loop's claim state in the deposit's tile order (cs, one entry per
-// level-2 slot: the scale that claimed the particle, or -1), tested and
-// advanced by the pass to level-1 order: a label survives only where cs is
-// -1, its group is kept and the scale has maxima (any), and then claims its
+// The same loop's claim state in the deposit's tile order (cs, one byte per
+// level-2 slot: 1 once an earlier scale claimed the particle, else 0), tested
+// and advanced by the pass to level-1 order: a label survives only where cs
+// is 0, its group is kept and the scale has maxima (any), and then claims its
 // slot.  With first, cs is not read but written for every slot.
 struct TileClaim {
-    int32_t *cs;
-    int32_t scale;
+    uint8_t *cs;
     int32_t first;
     int32_t any;
 };

@@ -212,7 +212,7 @@ hf_status identify_layout(const hf_box *box, int64_t np, int32_t count, const hf
     L.pass = L.groups + groups_ws_bytes(*box);
     L.claim = L.pass + align_up(size_t(cap));
     const bool order = particle_order_supported(*box, np);
-    L.total = L.claim + (order ? align_up(sizeof(int32_t) * size_t(np)) : 0);
+    L.total = L.claim + (order ? align_up(size_t(np)) : 0);  // one claim byte per particle, tile order
     return HF_OK;
 }
 }  // namespace
@@ -289,9 +289,9 @@ extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos
     if (s != HF_OK) return s;
     const GroupCounters g = group_counters_at(*box, w0 + L.groups);
     uint8_t *pass = reinterpret_cast<uint8_t *>(w0 + L.pass);
-    // which scale claimed each particle, also kept in tile order where the
-    // order is kept (the masks of the counts and the claims there)
-    int32_t *cs = order ? reinterpret_cast<int32_t *>(w0 + L.claim) : halo_scale;
+    // whether a particle is claimed: in tile order one byte per particle (the
+    // masks of the counts and the claims there), else halo_scale itself
+    uint8_t *cs8 = order ? reinterpret_cast<uint8_t *>(w0 + L.claim) : nullptr;
     int32_t *lab2 = reinterpret_cast<int32_t *>(sw);  // tile-order labels (label scratch)
     // in tile order the first scale writes both claim arrays outright (nothing
     // is claimed before it), so neither is cleared first
@@ -308,16 +308,16 @@ extern "C" hf_status hf_identify(hf_ctx *ctx, const hf_box *box, const void *pos
         if (s == HF_OK) s = groups_count_cells(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, sj.cell_label, g);
         // particles already claimed are not counted
         if (s == HF_OK && sj.max_cap > 0)
-            s = order ? groups_count_particles_tiled(ctx, *box, lab, j > 0 ? cs : nullptr, np, g)
-                      : groups_count_particles(ctx, *box, lab, np, g, cs);
+            s = order ? groups_count_particles_tiled(ctx, *box, lab, j > 0 ? cs8 : nullptr, np, g)
+                      : groups_count_particles(ctx, *box, lab, np, g, halo_scale);
         if (s == HF_OK)
             s = groups_decide(ctx, *box, sj.max_idx, sj.d_count, sj.max_cap, g, dens_th, np, particle_th, pass,
                               gj.group_particles, gj.group_cells, gj.group_keep);
         if (s == HF_OK && !order)
-            s = claim_filter(ctx, *box, lab, cs, halo_root, np, g, sj.max_cap > 0, j);
+            s = claim_filter(ctx, *box, lab, halo_scale, halo_root, np, g, sj.max_cap > 0, j);
         if (s == HF_OK && order) {
             // the filter and the claims ride on the two passes back to input order
-            const TileClaim tc{cs, j, j == 0 ? 1 : 0, sj.max_cap > 0 ? 1 : 0};
+            const TileClaim tc{cs8, j == 0 ? 1 : 0, sj.max_cap > 0 ? 1 : 0};
             const ClaimOut claim{halo_scale, halo_root, j, j == 0 ? 1 : 0};
             s = label_back(ctx, *box, np, po, sj.particle_label, sw, g.cells, &claim, &tc);
         }
