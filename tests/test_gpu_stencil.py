@@ -137,6 +137,26 @@ def test_full_size_sampled_cells():
     assert np.max(np.abs(got - want)) <= CWT_RTOL * peak
 
 
+@pytest.mark.parametrize("h", [33, 64])
+def test_wide_stencils_on_sampled_cells(h):
+    # half-widths whose y- and z-pass tiles need more than 64 KB of LDS (and the
+    # widest one accepted), on a box they wrap around several times
+    n, L, kw = 64, 64.0, 0.02
+    pos = small_box(n, L, 100000, 60, "f32", 66)
+    rho = hfm().deposit(cuda(pos), L, n)
+    c = hfm().cwt_stencil(rho, L, kw, h)
+    hfm().sync()
+    print(f"stencil n={n} h={h}", flush=True)
+    top = torch.topk(c.view(-1), 16).indices.cpu().numpy()
+    rnd = np.random.default_rng(h).integers(0, n ** 3, size=16)
+    cells = np.concatenate([top, rnd])
+    got = c.view(-1)[torch.as_tensor(cells, device="cuda")].cpu().numpy().astype(np.float64)
+    want = O.stencil_cwt_at(rho.cpu().numpy(), L, kw, h, cells)
+    peak = np.abs(want[:16]).max()
+    assert peak > 0.0
+    assert np.max(np.abs(got - want)) <= CWT_RTOL * peak
+
+
 def test_stencil_kernel_in_the_transform_and_the_pipeline():
     # HF_KERNEL_STENCIL: hf_cwt and hf_find_halos take the paper's truncated
     # stencil with Table 1's extent (k_w = 0.02: ceil(80 * 32 / 158) = 17, a = 1.6 cells)
